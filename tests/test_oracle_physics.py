@@ -1,0 +1,306 @@
+"""Pins of the oracle's physics against what the paper and mathematics fix.
+
+Each test checks an oracle function against something other than itself:
+quadrature of the paper's integral definitions (mpmath), library routines
+(numpy, scipy), closed-form limits, printed numbers, symmetries.
+"""
+import math
+
+import mpmath as mp
+import numpy as np
+import pytest
+from scipy import special
+
+from oracle import oracle as O
+
+ALPHA = 1.0 / 137.035999084
+RE = 2.8179403262e-15
+RC = 3.8615926796e-13
+
+
+def test_gauss_legendre_matches_numpy():
+    for n in (2, 5, 8, 16):
+        x, w = O.gauss_legendre(n)
+        xr, wr = np.polynomial.legendre.leggauss(n)
+        np.testing.assert_allclose(x, xr, rtol=0, atol=2e-16)
+        np.testing.assert_allclose(w, wr, rtol=2e-14, atol=0)
+        assert abs(w.sum() - 2.0) < 4e-15
+
+
+@pytest.mark.parametrize("z", [-0.36, -0.3, -0.1, -1e-3, -4.5e-4, -1e-7, -1e-12, 0.5, 2.0, 10.0])
+def test_lambert_w0_matches_scipy(z):
+    # eq:lambert-W uses the principal branch
+    ref = special.lambertw(z, 0).real
+    w = O.lambert_w0(z)
+    assert abs(w - ref) <= 4e-16 * max(1.0, abs(ref)) + 1e-17
+    assert abs(w * math.exp(w) - z) <= 1e-15 * max(1.0, abs(z))
+
+
+@pytest.mark.parametrize("Z", [6, 29, 79, 100])
+def test_coulomb_correction_truncation(Z):
+    # Sec. II.B.3: four terms suffice; exact series a^2 sum 1/(nu (nu^2 + a^2))
+    a2 = mp.mpf(ALPHA * Z) ** 2
+    exact = a2 * mp.nsum(lambda nu: 1 / (nu * (nu * nu + a2)), [1, mp.inf])
+    fc = O.fc(Z)
+    tol = {79: 1e-5, 100: 5e-5}.get(Z, 1e-7)
+    assert abs(fc / float(exact) - 1) < tol
+    # Z = 29 and 79 values quoted in the readings of the paper's formula
+    if Z == 29:
+        assert abs(fc - 0.0518404) < 5e-7
+    if Z == 79:
+        assert abs(fc - 0.3127970) < 5e-7
+
+
+# ---------------------------------------------------------------- I1, I2
+def _I12_quad(d, L):
+    """eq:defphi1, eq:defphi2 with 1 - F_e = L^2 u^2/(1 + L^2 u^2) (eq:app_FT_V)."""
+    mp.mp.dps = 30
+    d = mp.mpf(d); L = mp.mpf(L)
+    S = lambda u: (L * L * u * u / (1 + L * L * u * u)) ** 2
+    pts = sorted(set([d] + [x for x in [1 / L, 10 / L, mp.mpf("0.1"), mp.mpf("0.5")] if d < x < 1]
+                     + [mp.mpf(1)]))
+    i1 = mp.quad(lambda u: (u - d) ** 2 / u ** 3 * S(u), pts)
+    i2 = mp.quad(lambda u: (u ** 3 - 6 * d * d * u * mp.log(u / d) + 3 * d * d * u - 4 * d ** 3)
+                 / u ** 4 * S(u), pts)
+    return float(i1), float(i2)
+
+
+CASES = [(1e-4, 44.6), (0.01, 365.0), (0.3, 31.9), (1e-6, 4e4), (0.5, 1e6), (0.999, 100.0),
+         (0.9, 1e6), (0.05, 365.0), (1e-9, 1e6), (0.2, 3.0), (0.5, 2e5), (3e-3, 1e6),
+         (0.25, 70.8), (1e-2, 1e6)]
+
+
+@pytest.mark.parametrize("d,L", CASES)
+def test_I12_against_quadrature_of_definition(d, L):
+    I1, I2 = O.I12(d, L)
+    r1, r2 = _I12_quad(d, L)
+    # I1 + 1 and I2 + 5/6 enter the cross sections: absolute accuracy matters
+    assert abs(I1 - r1) < 2e-15 * max(1.0, abs(r1))
+    assert abs(I2 - r2) < 2e-15 * max(1.0, abs(r2))
+
+
+def _printed_I1(d, L):
+    """eq:deriv_I1 as printed."""
+    return (L * d * (math.atan(d * L) - math.atan(L)) - L * L / 2 * (1 - d) ** 2 / (1 + L * L)
+            + 0.5 * math.log((1 + L * L) / (1 + L * L * d * d)))
+
+
+def _printed_I2(d, L):
+    """eq:deriv_I2 as printed (2 I2 = ...)."""
+    v = (4 * L ** 3 * d ** 3 * (math.atan(L * d) - math.atan(L))
+         + (1 + 3 * L * L * d * d) * math.log((1 + L * L) / (1 + L * L * d * d))
+         + 6 * L ** 4 * d * d / (1 + L * L) * math.log(d)
+         + L * L * (d - 1) * (d + 1 - 4 * L * L * d * d) / (1 + L * L))
+    return 0.5 * v
+
+
+@pytest.mark.parametrize("d,L", [(1e-4, 44.6), (1e-3, 100.0), (0.01, 50.0), (0.05, 31.9), (0.2, 3.0)])
+def test_I12_matches_printed_closed_form_where_it_is_stable(d, L):
+    # the printed forms cancel catastrophically for L*delta >> 1; at small
+    # L*delta they are accurate and must agree with the stable rewriting
+    I1, I2 = O.I12(d, L)
+    assert abs(I1 - _printed_I1(d, L)) < 1e-12 * max(1, abs(I1))
+    assert abs(I2 - _printed_I2(d, L)) < 1e-11 * max(1, abs(I2))
+
+
+@pytest.mark.parametrize("d", [1e-3, 0.01, 0.1, 0.5, 0.9])
+def test_I12_unscreened_limit(d):
+    # F_e = 0 in eq:defphi1/2: I1 -> -ln d - 3/2 + 2d - d^2/2,
+    # I2 -> -(1 + 3 d^2) ln d - 4/3 + 4 d^3/3 (checked against quadrature too)
+    I1, I2 = O.I12(d, 1e12)
+    e1 = -math.log(d) - 1.5 + 2 * d - d * d / 2
+    e2 = -(1 + 3 * d * d) * math.log(d) - 4.0 / 3.0 + 4.0 / 3.0 * d ** 3
+    mp.mp.dps = 30
+    q2 = mp.quad(lambda u: (u ** 3 - 6 * d * d * u * mp.log(u / d) + 3 * d * d * u - 4 * d ** 3)
+                 / u ** 4, [d, 1])
+    assert abs(e2 - float(q2)) < 1e-14
+    assert abs(I1 - e1) < 1e-12 * max(1, abs(e1))
+    assert abs(I2 - e2) < 1e-12 * max(1, abs(e2))
+
+
+@pytest.mark.parametrize("L", [10.0, 44.6, 365.0, 1e4, 1e6])
+def test_I12_fully_screened_limit(L):
+    # eq:inte: delta -> 0 gives I1 = I2 = I_R (eq:IRE with q_R = q)
+    IR = 0.5 * (math.log1p(L * L) - L * L / (1 + L * L))
+    I1, I2 = O.I12(1e-13 / L, L)
+    assert abs(I1 - IR) < 1e-9 * IR
+    assert abs(I2 - IR) < 1e-9 * IR
+
+
+def test_I12_zero_at_delta_one():
+    for L in (10.0, 1e3, 1e6):
+        I1, I2 = O.I12(1.0, L)
+        assert I1 == 0.0 and abs(I2) < 1e-15
+
+
+# ---------------------------------------------------------------- screening
+def _I_tfd_quad(etf, ed, Ltf, Ld):
+    """eq:inte with 1 - F_e = u^2 [etf Ltf^2/(1+Ltf^2 u^2) + ed Ld^2/(1+Ld^2 u^2)]
+    (eq:app_FT_V_TFD in eq:app_FT_FF_V)."""
+    mp.mp.dps = 30
+    f = lambda u: u ** 3 * (etf * Ltf ** 2 / (1 + Ltf ** 2 * u * u) + ed * Ld ** 2 / (1 + Ld ** 2 * u * u)) ** 2
+    pts = sorted(set([0, 1 / max(Ltf, Ld), 1 / min(Ltf, Ld), 1]))
+    return float(mp.quad(f, [p for p in pts if p <= 1]))
+
+
+@pytest.mark.parametrize("etf,ed,Ltf,Ld", [(1, 0, 44.6, 365.0), (0.5, 0.5, 44.6, 365.0),
+                                          (0.1, 0.9, 31.9, 5e5), (0.9, 0.1, 31.9, 412.0),
+                                          (0.3, 0.7, 44.6, 44.6 * 1.00001), (0.3, 0.7, 44.6, 44.6 * 1.01)])
+def test_I_tfd_against_quadrature(etf, ed, Ltf, Ld):
+    a = O.I_tfd(etf, ed, Ltf, Ld)
+    ref = _I_tfd_quad(etf, ed, Ltf, Ld)
+    tol = 1e-8 if abs(Ld / Ltf - 1) < 1e-4 else 1e-13
+    assert abs(a / ref - 1) < tol
+
+
+@pytest.mark.parametrize("a", [1.8, 3.298314172107152, 3.76, 6.0, 13.3])
+def test_reduced_length_solves_reduit(a):
+    # eq:reduit: 2a(x+1) = (x+1) ln(x+1) - x, x = L_R^2; independent Newton solve
+    L = O.L_reduced(a)
+    x = L * L
+    assert abs(2 * a * (x + 1) - ((x + 1) * math.log1p(x) - x)) < 1e-13 * (x + 1) * (2 * a)
+    y = math.exp(1 + 2 * a)
+    for _ in range(60):
+        g = y * (math.log(y) - 1 - 2 * a) + 1
+        y -= g / (math.log(y) - 2 * a)
+    assert abs(math.sqrt(y - 1) / L - 1) < 1e-13
+
+
+@pytest.mark.parametrize("Z", [13, 29, 79])
+def test_reduced_length_limits(Z):
+    # Z* = 0: reduced potential = TF potential (Sec. II.B.2, exact coincidence);
+    # Z* = Z: reduced = Debye
+    ni = 8.5e28
+    s0 = O.screening(Z, 0.0, ni, 100.0)
+    Ltf = 1.0 / (Z ** (1.0 / 3.0) * ALPHA)
+    assert abs(s0["Ltf"] / Ltf - 1) < 1e-15
+    assert abs(s0["Lr"] / s0["Ltf"] - 1) < 1e-13
+    s1 = O.screening(Z, float(Z), ni, 5000.0)
+    assert abs(s1["Lr"] / s1["Ld"] - 1) < 1e-13
+
+
+def test_debye_numbers_printed_in_paper():
+    # Sec. II.B: solid-density Cu, r_i = 1.4e-10 m; L_D exceeds r_i only
+    # above ~27 keV (fully ionised, Z* = 29)
+    s = O.screening(29, 29.0, 8.5e28, 100.0)
+    ri_m = s["ri"] * RC
+    assert abs(ri_m - 1.4e-10) < 0.02e-10
+    below = O.screening(29, 29.0, 8.5e28, 26.0e3)
+    above = O.screening(29, 29.0, 8.5e28, 27.5e3)
+    assert below["branch"] == 2.0 and above["branch"] == 1.0
+    # Debye length formula eq:LDH when unclamped
+    T = 27.5e3
+    LD = math.sqrt(8.8541878128e-12 * T / (1.602176634e-19 * 8.5e28 * 29 * 30)) / RC
+    assert abs(above["Ld"] / LD - 1) < 1e-14
+
+
+# ---------------------------------------------------------------- cross sections
+def _nr_quad(Z, g1, k, etd, Ltf, Ld):
+    """eq:csnr with the transform eq:app_FT_V_TFD, integrated by mpmath,
+    kinematic bounds p1 -+ p2 (reading), no Elwert factor."""
+    mp.mp.dps = 30
+    g1 = mp.mpf(g1); k = mp.mpf(k)
+    p1 = mp.sqrt(g1 * g1 - 1); g2 = g1 - k; p2 = mp.sqrt(g2 * g2 - 1)
+    V = lambda u: Z / (2 * mp.pi ** 2) * ((1 - etd) * Ltf ** 2 / (1 + Ltf ** 2 * u * u)
+                                          + etd * Ld ** 2 / (1 + Ld ** 2 * u * u))
+    I = mp.quad(lambda u: V(u) ** 2 * u ** 3, [p1 - p2, p1 + p2])
+    return float(64 * mp.pi ** 4 * RE * RE * ALPHA / (3 * k * p1 * p1) * I)
+
+
+@pytest.mark.parametrize("g1,kf,etd,Ld", [(1.2, 0.3, 0.0, 365.0), (1.2, 0.3, 0.4, 365.0),
+                                          (1.9, 0.01, 0.7, 5e3), (1.05, 0.9, 1.0, 200.0),
+                                          (1.5, 0.5, 0.3, 44.0)])
+def test_nr_cross_section_against_quadrature(g1, kf, etd, Ld):
+    Z = 29
+    Ltf = 1.0 / (Z ** (1.0 / 3.0) * ALPHA)
+    k = kf * (g1 - 1)
+    v = O.dsdk_nr(Z, g1, k, etd, Ltf, Ld, elwert=False)
+    ref = _nr_quad(Z, g1, k, etd, Ltf, Ld)
+    tol = 1e-8 if abs(Ld / Ltf - 1) < 1e-4 else 1e-12
+    assert abs(v / ref - 1) < tol
+
+
+def test_nr_unscreened_born_and_elwert():
+    # point Coulomb: 16 Z^2 r_e^2 alpha/(3 k p1^2) ln((p1+p2)/(p1-p2)), times f_E
+    Z, g1, k = 29, 1.3, 0.2
+    p1 = math.sqrt(g1 * g1 - 1); g2 = g1 - k; p2 = math.sqrt(g2 * g2 - 1)
+    born = 16 * Z * Z * RE * RE * ALPHA / (3 * k * p1 * p1) * math.log((p1 + p2) / (p1 - p2))
+    v = O.dsdk_nr(Z, g1, k, 0.0, 1e12, 1e12, elwert=False)
+    assert abs(v / born - 1) < 1e-9
+    b1, b2 = p1 / g1, p2 / g2
+    c = 2 * math.pi * Z * ALPHA
+    fe = b1 / b2 * (1 - math.exp(-c / b1)) / (1 - math.exp(-c / b2))
+    assert abs(O.dsdk_nr(Z, g1, k, 0.0, 1e12, 1e12, elwert=True) / (born * fe) - 1) < 1e-9
+
+
+def test_relativistic_cross_section_composition():
+    # eq:csre, eq:csur with the quadrature of eq:defphi1/2
+    Z, g1, k, L = 29, 10.0, 3.0, 70.78
+    g2 = g1 - k; d = k / (2 * g1 * g2)
+    I1, I2 = _I12_quad(d, L)
+    r = g2 / g1
+    ref = 4 * Z * Z * RE * RE * ALPHA / k * ((1 + r * r) * (I1 + 1) - 2.0 / 3.0 * r * (I2 + 5.0 / 6.0))
+    assert abs(O.dsdk_rel(Z, g1, k, L) / ref - 1) < 1e-13
+    fc = O.fc(Z)
+    ref_u = 4 * Z * Z * RE * RE * ALPHA / k * ((1 + r * r) * (I1 + 1 - fc)
+                                                - 2.0 / 3.0 * r * (I2 + 5.0 / 6.0 - fc))
+    assert abs(O.dsdk_rel(Z, g1, k, L, coulomb=True) / ref_u - 1) < 1e-13
+
+
+@pytest.mark.parametrize("k", [2.5, 10.0, 195.7, 2e4])
+def test_bethe_heitler_symmetry(k):
+    # Sec. II.C: plateau symmetric about g+ = k/2
+    for L in (31.9, 1e3, 1e6):
+        for gp in (1.0 + 1e-3, 1.3, 0.25 * k, 0.49 * k):
+            if gp >= k - 1:
+                continue
+            a = O.dsdgp_bh(79, k, gp, L)
+            b = O.dsdgp_bh(79, k, k - gp, L)
+            # k - g+ rounds the argument by ulp(k): allow for it
+            assert abs(a / b - 1) < 1e-13 + 1e-15 * k
+
+
+def test_trident_total_and_threshold():
+    Z = 79
+    assert O.sigma_trident(Z, 3.0) == 0.0
+    assert O.sigma_trident(Z, 2.5) == 0.0
+    g1 = 200.0
+    ref = 5.22 * Z * Z * math.log((g1 + 4.50) / 6.89) ** 3 * 1e-34
+    assert abs(O.sigma_trident(Z, g1) / ref - 1) < 1e-15
+
+
+def test_trident_spectrum_limits():
+    # d sigma/d gp = a b/(a + b) is bounded by min(a, b) and tends to the
+    # non-relativistic form near threshold and to the relativistic one far above
+    Z, g1 = 29, 400.0
+    zra2 = (Z * RE * ALPHA) ** 2
+    x = 1 / g1; x2 = x * x; q = x2 / (1 - x2); lg = math.log(1 / x2)
+    C = 4 * q * lg - 4 / 3 * x2 + x2 * x2 / 6
+    Cz = 3 * q * (1 - q * lg) - 13 / 5 * x2 + 7 / 4 * x2 ** 2 - 9 / 10 * x2 ** 3 + x2 ** 4 / 5
+    Cr = -1.5 * q * (1 - q * lg) + 0.8 * x2 - x2 ** 2 / 8 - x2 ** 3 / 20 + x2 ** 4 / 40
+    br = math.log(g1 * g1) - 161 / 60 + C + Cr + Cz
+    for gp in (2.0 + 1e-6, 2.05, 20.0, 150.0, 390.0):
+        a = zra2 / 32 * br * gp ** 3
+        b = 56 / (9 * math.pi) * zra2 * math.log(gp) * math.log(g1 / gp) / gp
+        v = O.dsdgp_trident(Z, g1, gp)
+        assert v <= min(a, b) * (1 + 1e-14)
+        assert abs(v / (a * b / (a + b)) - 1) < 1e-13
+    # NR bracket positive at the threshold g1 = 3 (reading of the Trident support)
+    x = 1 / 3.0; x2 = x * x; q = x2 / (1 - x2); lg = math.log(1 / x2)
+    C = 4 * q * lg - 4 / 3 * x2 + x2 * x2 / 6
+    Cz = 3 * q * (1 - q * lg) - 13 / 5 * x2 + 7 / 4 * x2 ** 2 - 9 / 10 * x2 ** 3 + x2 ** 4 / 5
+    Cr = -1.5 * q * (1 - q * lg) + 0.8 * x2 - x2 ** 2 / 8 - x2 ** 3 / 20 + x2 ** 4 / 40
+    assert 0.40 < math.log(9) - 161 / 60 + C + Cr + Cz < 0.44
+
+
+def test_split_shape_support_and_symmetry():
+    for gpair in (4.5, 10.0, 1000.0):
+        for gplus in np.linspace(1.0, gpair - 1.0, 57):
+            v = O.split_shape(gpair, gplus)
+            gm = gpair - gplus
+            assert v >= 0.0
+            if (gplus - 1) * (gm - 1) < 1 - 1e-12:
+                assert v == 0.0
+            assert abs(v - O.split_shape(gpair, gm)) <= 1e-12 * max(1.0, v)
+    for gplus in np.linspace(1.0, 3.0, 11):
+        assert O.split_shape(4.0, gplus) == 0.0
