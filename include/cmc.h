@@ -1,0 +1,252 @@
+/*
+ * cmc.h -- C ABI of the Coulomb-process Monte Carlo library (libcmc.so).
+ *
+ * Implements, for MI355X (gfx950), the per-cell pairwise Monte Carlo step
+ * of Martinez et al., "High-Energy Radiation and Pair Production by Coulomb
+ * Processes in Particle-In-Cell Simulations" (Sec. III.A): weighted
+ * macro-electrons and macro-photons are paired with the macro-ions of their
+ * cell and undergo Bremsstrahlung (Sec. II.B), Bethe-Heitler (Sec. II.C)
+ * and Coulomb Trident (Sec. II.D) events, with cross sections screened by
+ * the Thomas-Fermi-Debye potential (Sec. II.A, eq:V_TFD).  A deterministic
+ * expected-yield pass and its adjoint sit beside the step.
+ *
+ * Conventions shared by every entry point
+ *  - Units: momenta in m_e c (photons: k times the unit direction), energies
+ *    in m_e c^2, densities in m^-3, temperatures in eV, times in s, cross
+ *    sections in m^2.  Weights are in density units: the density of a
+ *    species in a cell is the sum of its weights (Sec. III.A).
+ *  - Pointers named "device" are device memory owned by the caller; the
+ *    library keeps no reference to them after the call returns.  Host
+ *    pointers are read before the call returns.
+ *  - Calls enqueue work on `stream` (a hipStream_t passed as void*, NULL =
+ *    the default stream) and return without synchronising.
+ *  - Argument errors found on the host return CMC_EINVAL (or CMC_ERANGE)
+ *    synchronously, enqueue nothing and set the thread-local message of
+ *    cmc_last_error().  Errors found on the device (bad cell parameters,
+ *    bad weights, energies above the tables, full product buffers, cells
+ *    larger than the launch allows) never abort the launch: they set bits
+ *    of the sticky status word (CMC_ST_*) and are counted in the tallies.
+ *  - No call allocates device memory except cmc_build_tables.
+ */
+#ifndef CMC_H
+#define CMC_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CMC_OK = 0,
+    CMC_EINVAL = 1,    /* bad argument (null pointer, size, flag)           */
+    CMC_ERANGE = 2,    /* argument outside the supported range              */
+    CMC_EDEVICE = 3,   /* HIP runtime error (launch, copy, memory)          */
+    CMC_ENOMEM = 4     /* device allocation failed (cmc_build_tables only)  */
+} cmc_status;
+
+/* Thread-local text of the last error reported by this thread. */
+const char* cmc_last_error(void);
+
+/* processes (bit mask), Sec. II.B, II.C, II.D */
+enum { CMC_BREMS = 1, CMC_BH = 2, CMC_TRIDENT = 4 };
+/* arithmetic of the table lookups and kinematics; the event probability
+ * 1 - exp(-x) and all tallies are FP64 in both forms */
+enum { CMC_FP64 = 0, CMC_FP32 = 1 };
+
+/* sticky device status bits */
+enum {
+    CMC_ST_OVERFLOW = 1,    /* a product buffer of some cell was full       */
+    CMC_ST_GAMMA_HIGH = 2,  /* an energy above the table top (clamped)      */
+    CMC_ST_BAD_CELL = 4,    /* Z* outside [0, Z], n_i <= 0 or T < 0: skipped */
+    CMC_ST_BAD_WEIGHT = 8,  /* a negative or non-finite weight: cell skipped */
+    CMC_ST_TOO_LARGE = 16   /* a cell above max_per_cell: cell skipped       */
+};
+
+/* ------------------------------------------------------------------ */
+/* Cross-section tables (Sec. III.A: cross sections tabulated in the   */
+/* ion rest frame)                                                      */
+/* ------------------------------------------------------------------ */
+typedef struct cmc_tables_s* cmc_tables;
+
+/* Build all tables for element Z (1..100) on the current device: total
+ * Bremsstrahlung cross section and its photon-energy moment, Bethe-Heitler
+ * total cross section, and the cumulative distributions used to sample
+ * photon, pair and positron energies (numerical inversion of the
+ * cumulative distribution, Sec. III.A), for the screened potential of
+ * eq:V_TFD (non-relativistic segment, eq:cs_br_nr) and its reduced
+ * single-exponential form (eq:csre, eq:csur, eq:dsdkbh).  The grid is fixed
+ * (see the package documentation); FP64 and FP32 copies are kept.
+ * Allocates device memory (about 45 MB) and enqueues the build on `stream`;
+ * the handle is usable by any later work ordered after it.
+ * Errors: CMC_EINVAL (Z out of range, out == NULL), CMC_ENOMEM, CMC_EDEVICE. */
+cmc_status cmc_build_tables(int32_t Z, void* stream, cmc_tables* out);
+
+/* Free the tables (synchronises the device first).  NULL is a no-op. */
+cmc_status cmc_tables_free(cmc_tables t);
+
+/* Number of FP64 values of table array `which` (0..12, in the order
+ * sigR, skR, cdfR, sigU, skU, cdfU, sigN, skN, cdfN, sigB, cdfB, cdfT, cdfS),
+ * or -1 if `which` is unknown. */
+int64_t cmc_tables_size(cmc_tables t, int32_t which);
+
+/* Copy table array `which` (FP64) to host memory `dst` of n values
+ * (synchronous).  Errors: CMC_EINVAL (bad handle, which, n), CMC_EDEVICE. */
+cmc_status cmc_tables_export(cmc_tables t, int32_t which, double* dst, int64_t n);
+
+/* ------------------------------------------------------------------ */
+/* Particle layout: structure of arrays, grouped by cell.  Cell c owns   */
+/* positions [off[c], off[c+1]) of every array of the species; the first */
+/* count[c] of them are live (count == NULL: all of them).               */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int64_t n_cells;
+    const double* Zstar;   /* device [n_cells]: ionisation degree, 0 <= Z* <= Z */
+    const double* n_i;     /* device [n_cells]: ion density for screening (eq:LDH) */
+    const double* T_e;     /* device [n_cells]: temperature T_e = T_i, eV */
+} cmc_cells;
+
+typedef struct {
+    const int64_t* off;    /* device [n_cells+1], non-decreasing             */
+    int32_t* count;        /* device [n_cells] live counts, or NULL (= full)  */
+    double *px, *py, *pz;  /* device momenta; ions: must be NULL (at rest)    */
+    double* w;             /* device weights                                  */
+    int64_t* parent;       /* device, products only (NULL = not recorded):
+                              global index of the parent particle            */
+} cmc_species;
+
+typedef struct {
+    double dt;             /* time step, s (> 0)                              */
+    uint64_t seed;         /* Philox key                                      */
+    uint64_t step;         /* step counter (keys the random numbers)          */
+    uint32_t processes;    /* CMC_BREMS | CMC_BH | CMC_TRIDENT                */
+    int32_t precision;     /* CMC_FP64 or CMC_FP32                            */
+    int32_t schedule;      /* 0 = automatic, see cmc_schedule_*               */
+    int32_t max_per_cell;  /* upper bound of live electrons, photons and ions
+                              per cell (<= CMC_MAX_PER_CELL); sizes the launch */
+    double near_rel;       /* band |U - P| <= near_rel * P counted as near-threshold */
+} cmc_step_params;
+
+#define CMC_MAX_PER_CELL 16384
+
+/* per-cell tallies: int64 [n_cells][CMC_NI] and FP64 [n_cells][CMC_ND] */
+enum { CMC_I_PAIRS_BR = 0, CMC_I_PAIRS_TR, CMC_I_PAIRS_BH,
+       CMC_I_EV_BR, CMC_I_EV_TR, CMC_I_EV_BH,
+       CMC_I_NEAR_BR, CMC_I_NEAR_TR, CMC_I_NEAR_BH,
+       CMC_I_DROP_PH, CMC_I_DROP_EL, CMC_I_DROP_PO, CMC_NI };
+enum { CMC_D_NAB_EI = 0,   /* n_ei = sum_j min(W_e, W_i), eq:proba3          */
+       CMC_D_NAB_GI,       /* same for photon-ion pairs                      */
+       CMC_D_E_BR,         /* sum W k of Bremsstrahlung photons              */
+       CMC_D_E_TR,         /* sum W (g+ + g-) of Trident pairs               */
+       CMC_D_E_BH,         /* sum W (g+ + g-) of Bethe-Heitler pairs         */
+       CMC_D_DE_EL,        /* sum W (gamma_after - gamma_before), electrons,
+                              taken as -k / -g_pair (exact for ions at rest) */
+       CMC_D_DE_PH,        /* -sum W k of photons converted                  */
+       CMC_D_W_BR, CMC_D_W_TR, CMC_D_W_BH,  /* created weight per process    */
+       CMC_ND };
+
+typedef struct {
+    int64_t* ti;           /* device [n_cells*CMC_NI], overwritten            */
+    double* td;            /* device [n_cells*CMC_ND], overwritten            */
+    int32_t* status;       /* device [1], OR-ed with CMC_ST_* (caller clears) */
+} cmc_tallies;
+
+/* ------------------------------------------------------------------ */
+/* Pairing (Sec. III.A): in every cell, N = max(N_a, N_b) macro-pairs,   */
+/* each drawn uniformly.  Each species is put in a random order by a     */
+/* 32-bit Philox4x32-10 key per particle (ties broken by index); the     */
+/* larger species A is walked once in that order and the smaller B       */
+/* cyclically: pair j = (A[pi_A(j)], B[pi_B(j mod N_B)]); on a tie the   */
+/* a-species is A.  pass = 1 keys electrons/ions as the electron-ion     */
+/* pass of cmc_collide_step does, pass = 2 photons/ions.                 */
+/* a_off/b_off/pair_off: device [n_cells+1]; a_cnt/b_cnt device or NULL; */
+/* wa/wb device weights; pair_off[c] = caller's exclusive scan of        */
+/* max(N_a, N_b).  Outputs (device): pa[pair_off[c]+j], pb[...] = local  */
+/* index (within the cell) of the a and b particle of pair j; n_ab       */
+/* (nullable) [n_cells] = sum_j min(W_a, W_b).                           */
+/* Cells with more than CMC_MAX_PER_CELL particles of a species produce  */
+/* no pairs and set pa = pb = -1.                                        */
+/* Errors: CMC_EINVAL (null pointers, pass), CMC_EDEVICE.                */
+/* ------------------------------------------------------------------ */
+cmc_status cmc_pair_cells(int64_t n_cells, const int64_t* a_off, const int32_t* a_cnt,
+                          const int64_t* b_off, const int32_t* b_cnt,
+                          const double* wa, const double* wb,
+                          uint64_t seed, uint64_t step, uint32_t pass,
+                          const int64_t* pair_off, int32_t* pa, int32_t* pb, double* n_ab,
+                          void* stream);
+
+/* ------------------------------------------------------------------ */
+/* One Monte Carlo step (Sec. III.A, eq:proba3), all cells.             */
+/*  1. electron-ion pass: per pair, Bremsstrahlung then Trident on the   */
+/*     electron as left by Bremsstrahlung;                               */
+/*  2. photon-ion pass: Bethe-Heitler over the photons live at the start */
+/*     of the step.                                                      */
+/* Each pair: P = 1 - exp(-(n_a n_b/n_ab) sigma' gamma' v'/(gamma_a      */
+/* gamma_b) dt) in FP64; the event happens iff U1 < P and               */
+/* U2 < W_ion/max(W_mobile, W_ion); the energy is sampled from the      */
+/* tabulated cumulative distribution; products move along the parent.   */
+/* Updates in place: electron momenta; photons (Bremsstrahlung photons   */
+/* are appended to the photon species of the cell, photons converted by  */
+/* Bethe-Heitler are removed and the survivors kept in order, followed   */
+/* by the new photons; photons->count is required).  Trident and        */
+/* Bethe-Heitler e- and e+ are appended to new_el / new_po (count       */
+/* required, capacity off[c+1]-off[c]); products are appended in pair    */
+/* order; a full buffer drops the product (counted, CMC_ST_OVERFLOW).    */
+/* Random numbers: Philox4x32-10 keyed by (seed) with counter            */
+/* (pair or particle index, cell, step, tag): results do not depend on   */
+/* the schedule or on how cells are split across launches or devices.   */
+/* workspace: device scratch of cmc_step_workspace_bytes() bytes (may be */
+/* NULL when that is 0).                                                 */
+/* Errors: CMC_EINVAL (null or inconsistent pointers, dt <= 0, unknown  */
+/* processes/precision/schedule, ions with momenta), CMC_ERANGE          */
+/* (max_per_cell outside [1, CMC_MAX_PER_CELL]), CMC_EDEVICE.            */
+/* ------------------------------------------------------------------ */
+cmc_status cmc_collide_step(cmc_tables t, const cmc_cells* cells,
+                            cmc_species* electrons, cmc_species* photons,
+                            const cmc_species* ions,
+                            cmc_species* new_el, cmc_species* new_po,
+                            const cmc_step_params* params, cmc_tallies* tallies,
+                            void* workspace, size_t workspace_bytes, void* stream);
+
+/* Scratch bytes cmc_collide_step needs for n_cells with this schedule. */
+size_t cmc_step_workspace_bytes(int64_t n_cells, int32_t schedule);
+
+/* schedules: 0 automatic; 1 one workgroup per cell; 2 persistent
+ * work-queue launch (cells dealt by an atomic counter) */
+enum { CMC_SCHED_AUTO = 0, CMC_SCHED_CELL = 1, CMC_SCHED_PERSISTENT = 2 };
+
+/* ------------------------------------------------------------------ */
+/* Expected photon energy yield (deterministic): for every cell c,      */
+/*   Y_c = sum_j w_j P_j <k>_j,  P = 1 - exp(-n_i sigma_B(gamma) beta c dt), */
+/* each electron against the cell's ions at rest with n_i = n_e/Z*      */
+/* (eq:proba1, eq:LDH), <k> = sigma_k/sigma_B the mean photon energy of */
+/* the tabulated spectrum.  Zstar, n_e, T_e: device [n_cells] (Z* > 0); */
+/* off device [n_cells+1]; px..w device [off[n_cells]]; Y device        */
+/* [n_cells]; y_part device per-electron terms or NULL.                 */
+/* precision: CMC_FP64 or CMC_FP32 (table lookups in FP32, P and sums   */
+/* in FP64).  Errors: CMC_EINVAL, CMC_EDEVICE.                          */
+/* ------------------------------------------------------------------ */
+cmc_status cmc_expected_yield(cmc_tables t, int64_t n_cells, const double* Zstar,
+                              const double* n_e, const double* T_e, const int64_t* off,
+                              const double* px, const double* py, const double* pz,
+                              const double* w, double dt, int32_t precision,
+                              double* Y, double* y_part, void* stream);
+
+/* Adjoint of cmc_expected_yield for upstream gradient gY (device
+ * [n_cells]): writes dL/dpx, dL/dpy, dL/dpz, dL/dw (per electron; gw may
+ * be NULL) and dL/dZ*, dL/dn_e, dL/dT_e (per cell), L = sum_c gY_c Y_c.
+ * The table lookups are recomputed, not stored.  The derivative of the
+ * piecewise-linear table interpolant is taken inside the bracketing
+ * interval (one-sided at knots).  Errors: CMC_EINVAL, CMC_EDEVICE. */
+cmc_status cmc_expected_yield_backward(cmc_tables t, int64_t n_cells, const double* Zstar,
+                                       const double* n_e, const double* T_e, const int64_t* off,
+                                       const double* px, const double* py, const double* pz,
+                                       const double* w, double dt, int32_t precision,
+                                       const double* gY, double* gpx, double* gpy, double* gpz,
+                                       double* gw, double* gZstar, double* gn_e, double* gT_e,
+                                       void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1047,6 +1047,18 @@ static int append(or_species* sl, int64_t c, double px, double py, double pz, do
     return 1;
 }
 
+/* Lab-frame energy change of the electron, from its ion-frame change
+ * dE' (= -k or -g_pair, exact by construction) rather than from the
+ * difference of two Lorentz factors, which cancels when dE' << gamma:
+ * dE_lab = g_i dE' + u.n (|p'_f| - |p'|), |p'_f| - |p'| = dE'(g'_f + g')/(|p'_f| + |p'|). */
+static double lab_energy_change(int moving, const double u[3], double gi, const double n[3],
+                                double dEp, double gfp, double gp, double pf, double pm)
+{
+    if (!moving) return dEp;
+    double dp = dEp * (gfp + gp) / (pf + pm);
+    return gi * dEp + (u[0] * n[0] + u[1] * n[1] + u[2] * n[2]) * dp;
+}
+
 static int32_t cell_step(const stepctx* X, const or_cells* cells, int64_t c, int64_t* ti, double* td)
 {
     const or_tables* tb = X->tb;
@@ -1150,11 +1162,10 @@ static int32_t cell_step(const stepctx* X, const or_cells* cells, int64_t c, int
                         qk[0] = p[0] * h; qk[1] = p[1] * h; qk[2] = p[2] * h;
                     }
                     el->px[ie] = qe[0]; el->py[ie] = qe[1]; el->pz[ie] = qe[2];
-                    double gef = sqrt(1.0 + qe[0] * qe[0] + qe[1] * qe[1] + qe[2] * qe[2]);
                     double kl = sqrt(qk[0] * qk[0] + qk[1] * qk[1] + qk[2] * qk[2]);
                     ti[OR_I_EV_BR]++;
                     td[OR_D_E_BR] += We * kl;
-                    td[OR_D_DE_EL] += We * (gef - ge);
+                    td[OR_D_DE_EL] += We * lab_energy_change(moving, u, gi, nh, -k, g2, gp, pf, pm);
                     td[OR_D_W_BR] += We;
                     if (!append(ph, c, qk[0], qk[1], qk[2], We, ie)) { ti[OR_I_DROP_PH]++; st |= OR_ST_OVERFLOW; }
                 } else {
@@ -1178,12 +1189,11 @@ static int32_t cell_step(const stepctx* X, const or_cells* cells, int64_t c, int
                         for (int dd = 0; dd < 3; dd++) { qe[dd] = p[dd] * f; qp[dd] = p[dd] * fp; qm[dd] = p[dd] * fm; }
                     }
                     el->px[ie] = qe[0]; el->py[ie] = qe[1]; el->pz[ie] = qe[2];
-                    double gef = sqrt(1.0 + qe[0] * qe[0] + qe[1] * qe[1] + qe[2] * qe[2]);
                     double gpl_l = sqrt(1.0 + qp[0] * qp[0] + qp[1] * qp[1] + qp[2] * qp[2]);
                     double gmi_l = sqrt(1.0 + qm[0] * qm[0] + qm[1] * qm[1] + qm[2] * qm[2]);
                     ti[OR_I_EV_TR]++;
                     td[OR_D_E_TR] += We * (gpl_l + gmi_l);
-                    td[OR_D_DE_EL] += We * (gef - ge);
+                    td[OR_D_DE_EL] += We * lab_energy_change(moving, u, gi, nh, -gpair, gf, gp, pf, pm);
                     td[OR_D_W_TR] += We;
                     if (!append(X->nel, c, qm[0], qm[1], qm[2], We, ie)) { ti[OR_I_DROP_EL]++; st |= OR_ST_OVERFLOW; }
                     if (!append(X->npo, c, qp[0], qp[1], qp[2], We, ie)) { ti[OR_I_DROP_PO]++; st |= OR_ST_OVERFLOW; }

@@ -38,7 +38,8 @@ enum { OR_D_NAB_EI = 0, OR_D_NAB_GI,
        OR_D_E_BR,      /* sum W k of Bremsstrahlung photons (lab)        */
        OR_D_E_TR,      /* sum W (g+ + g-) of Trident pairs (lab)         */
        OR_D_E_BH,      /* sum W (g+ + g-) of Bethe-Heitler pairs (lab)   */
-       OR_D_DE_EL,     /* sum W (gamma_after - gamma_before), electrons  */
+       OR_D_DE_EL,     /* sum W (gamma_after - gamma_before), electrons,
+                          from the energy given to the products       */
        OR_D_DE_PH,     /* sum W (-k) of photons converted by BH          */
        OR_D_W_BR, OR_D_W_TR, OR_D_W_BH,   /* created weight per process  */
        OR_ND };

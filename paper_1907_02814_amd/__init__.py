@@ -1,0 +1,309 @@
+"""cmc: pairwise Coulomb-process Monte Carlo (Bremsstrahlung, Bethe-Heitler,
+Trident) for weighted PIC macro-particles on MI355X.
+
+A thin ctypes binding of libcmc.so (include/cmc.h): every function here only
+marshals torch tensors (device memory) and the current HIP stream into the
+C ABI; all work runs in the library's HIP kernels.  The first call into the
+library fails loudly (ImportError) when libcmc.so has not been built; there
+is no fallback path.
+
+Paper: Martinez et al., "High-Energy Radiation and Pair Production by Coulomb
+Processes in Particle-In-Cell Simulations" (arXiv:1907.02814).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcmc.so")
+
+BREMS, BH, TRIDENT = 1, 2, 4
+FP64, FP32 = 0, 1
+SCHED_AUTO, SCHED_CELL, SCHED_PERSISTENT = 0, 1, 2
+MAX_PER_CELL = 16384
+ST_OVERFLOW, ST_GAMMA_HIGH, ST_BAD_CELL, ST_BAD_WEIGHT, ST_TOO_LARGE = 1, 2, 4, 8, 16
+I_NAMES = ["pairs_br", "pairs_tr", "pairs_bh", "ev_br", "ev_tr", "ev_bh",
+           "near_br", "near_tr", "near_bh", "drop_ph", "drop_el", "drop_po"]
+D_NAMES = ["nab_ei", "nab_gi", "E_br", "E_tr", "E_bh", "dE_el", "dE_ph",
+           "W_br", "W_tr", "W_bh"]
+TABLE_NAMES = ["sigR", "skR", "cdfR", "sigU", "skU", "cdfU", "sigN", "skN", "cdfN",
+               "sigB", "cdfB", "cdfT", "cdfS"]
+EXPORTS = ["cmc_last_error", "cmc_build_tables", "cmc_tables_free", "cmc_tables_size",
+           "cmc_tables_export", "cmc_pair_cells", "cmc_collide_step", "cmc_step_workspace_bytes",
+           "cmc_expected_yield", "cmc_expected_yield_backward"]
+
+_vp = C.c_void_p
+_i64 = C.c_int64
+
+
+class CmcError(RuntimeError):
+    pass
+
+
+class _Cells(C.Structure):
+    _fields_ = [("n_cells", C.c_int64), ("Zstar", _vp), ("n_i", _vp), ("T_e", _vp)]
+
+
+class _Species(C.Structure):
+    _fields_ = [("off", _vp), ("count", _vp), ("px", _vp), ("py", _vp), ("pz", _vp),
+                ("w", _vp), ("parent", _vp)]
+
+
+class _StepParams(C.Structure):
+    _fields_ = [("dt", C.c_double), ("seed", C.c_uint64), ("step", C.c_uint64),
+                ("processes", C.c_uint32), ("precision", C.c_int32), ("schedule", C.c_int32),
+                ("max_per_cell", C.c_int32), ("near_rel", C.c_double)]
+
+
+class _Tallies(C.Structure):
+    _fields_ = [("ti", _vp), ("td", _vp), ("status", _vp)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libcmc.so is not built ({LIB_PATH}); run "
+                          "`python -c 'import __graft_entry__ as g; g.build()'`")
+    L = C.CDLL(LIB_PATH)
+    L.cmc_last_error.restype = C.c_char_p
+    L.cmc_build_tables.argtypes = [C.c_int32, _vp, C.POINTER(_vp)]
+    L.cmc_tables_free.argtypes = [_vp]
+    L.cmc_tables_size.argtypes = [_vp, C.c_int32]
+    L.cmc_tables_size.restype = _i64
+    L.cmc_tables_export.argtypes = [_vp, C.c_int32, _vp, _i64]
+    L.cmc_pair_cells.argtypes = [_i64, _vp, _vp, _vp, _vp, _vp, _vp, C.c_uint64, C.c_uint64,
+                                 C.c_uint32, _vp, _vp, _vp, _vp, _vp]
+    L.cmc_collide_step.argtypes = [_vp, C.POINTER(_Cells), C.POINTER(_Species), C.POINTER(_Species),
+                                   C.POINTER(_Species), C.POINTER(_Species), C.POINTER(_Species),
+                                   C.POINTER(_StepParams), C.POINTER(_Tallies), _vp, C.c_size_t, _vp]
+    L.cmc_step_workspace_bytes.argtypes = [_i64, C.c_int32]
+    L.cmc_step_workspace_bytes.restype = C.c_size_t
+    L.cmc_expected_yield.argtypes = [_vp, _i64] + [_vp] * 8 + [C.c_double, C.c_int32, _vp, _vp, _vp]
+    L.cmc_expected_yield_backward.argtypes = ([_vp, _i64] + [_vp] * 8 + [C.c_double, C.c_int32]
+                                              + [_vp] * 8 + [_vp])
+    for name in ("cmc_build_tables", "cmc_tables_free", "cmc_tables_export", "cmc_pair_cells",
+                 "cmc_collide_step", "cmc_expected_yield", "cmc_expected_yield_backward"):
+        getattr(L, name).restype = C.c_int
+    return L
+
+
+_LIB = None
+
+
+def get_lib():
+    """The loaded libcmc.so (ImportError if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        _LIB = _load()
+    return _LIB
+
+
+def __getattr__(name):
+    if name == "lib":
+        return get_lib()
+    raise AttributeError(name)
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        msg = get_lib().cmc_last_error()
+        raise CmcError(f"{what} failed ({rc}): {msg.decode() if msg else ''}")
+
+
+_PLACEHOLDER = {}
+
+
+def _ptr(t) -> Optional[int]:
+    """Device pointer of a contiguous tensor (None -> NULL).  An empty tensor
+    (a species with no particles anywhere) gets a one-element placeholder so
+    that required arrays are never NULL; the kernels never address it."""
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensors must be contiguous")
+    if not t.is_cuda:
+        raise ValueError("tensors must be on the GPU")
+    if t.numel() == 0:
+        import torch
+        key = (t.device, t.dtype)
+        if key not in _PLACEHOLDER:
+            _PLACEHOLDER[key] = torch.zeros(1, dtype=t.dtype, device=t.device)
+        return _PLACEHOLDER[key].data_ptr()
+    return t.data_ptr()
+
+
+def _stream(stream=None) -> Optional[int]:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+class Tables:
+    """Device tables for element Z (cmc_build_tables)."""
+
+    def __init__(self, Z: int, stream=None):
+        h = _vp()
+        _check(get_lib().cmc_build_tables(int(Z), _stream(stream), C.byref(h)), "cmc_build_tables")
+        self.Z = int(Z)
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def export(self, name) -> np.ndarray:
+        which = TABLE_NAMES.index(name) if isinstance(name, str) else int(name)
+        n = get_lib().cmc_tables_size(self._h, which)
+        out = np.zeros(n)
+        _check(get_lib().cmc_tables_export(self._h, which, out.ctypes.data, n), "cmc_tables_export")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            get_lib().cmc_tables_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def build_tables(Z: int, stream=None) -> Tables:
+    return Tables(Z, stream)
+
+
+def pair_cells(a_off, a_cnt, b_off, b_cnt, wa, wb, seed, step, pass_, pair_off, stream=None):
+    """Pair indices of every cell (cmc_pair_cells); returns (pa, pb, n_ab)."""
+    import torch
+    n_cells = a_off.numel() - 1
+    n_pairs = int(pair_off[-1].item())
+    dev = a_off.device
+    pa = torch.empty(max(n_pairs, 1), dtype=torch.int32, device=dev)
+    pb = torch.empty(max(n_pairs, 1), dtype=torch.int32, device=dev)
+    nab = torch.empty(max(n_cells, 1), dtype=torch.float64, device=dev)
+    _check(get_lib().cmc_pair_cells(n_cells, _ptr(a_off), _ptr(a_cnt), _ptr(b_off), _ptr(b_cnt),
+                              _ptr(wa), _ptr(wb), int(seed), int(step), int(pass_), _ptr(pair_off),
+                              _ptr(pa), _ptr(pb), _ptr(nab), _stream(stream)), "cmc_pair_cells")
+    return pa[:n_pairs], pb[:n_pairs], nab[:n_cells]
+
+
+def _species(d: Dict, moving_ok=True) -> _Species:
+    s = _Species()
+    s.off = _ptr(d["off"])
+    s.count = _ptr(d.get("count"))
+    for k in ("px", "py", "pz", "w"):
+        setattr(s, k, _ptr(d.get(k)))
+    s.parent = _ptr(d.get("parent"))
+    return s
+
+
+class StepState:
+    """Per-step argument block: keeps ctypes structs (and tally tensors)
+    alive so that repeated steps only update the step counter."""
+
+    def __init__(self, tables: Tables, cells, electrons, photons, ions, new_el, new_po, *, dt,
+                 seed=1, processes=BREMS | BH | TRIDENT, precision=FP64, schedule=SCHED_AUTO,
+                 max_per_cell=None, near_rel=1e-6):
+        import torch
+        self.tables = tables
+        n = cells["Zstar"].numel()
+        dev = cells["Zstar"].device
+        self.cells = _Cells(n, _ptr(cells["Zstar"]), _ptr(cells["n_i"]), _ptr(cells["T_e"]))
+        self.sp = [_species(x) for x in (electrons, photons, ions, new_el, new_po)]
+        if max_per_cell is None:
+            def mx(d):
+                o = d["off"]
+                return int((o[1:] - o[:-1]).max().item()) if o.numel() > 1 else 0
+            max_per_cell = max(1, mx(electrons), mx(photons), mx(ions))
+        self.params = _StepParams(float(dt), int(seed), 0, int(processes), int(precision),
+                                  int(schedule), int(max_per_cell), float(near_rel))
+        self.ti = torch.zeros((n, len(I_NAMES)), dtype=torch.int64, device=dev)
+        self.td = torch.zeros((n, len(D_NAMES)), dtype=torch.float64, device=dev)
+        self.status = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.tal = _Tallies(_ptr(self.ti), _ptr(self.td), _ptr(self.status))
+        wsb = get_lib().cmc_step_workspace_bytes(n, int(schedule))
+        self.workspace = torch.empty(max(wsb, 1), dtype=torch.uint8, device=dev) if wsb else None
+        self.wsb = wsb
+        self._refs = (cells, electrons, photons, ions, new_el, new_po)
+
+    def step(self, step: int, stream=None):
+        self.params.step = int(step)
+        _check(get_lib().cmc_collide_step(self.tables.handle, C.byref(self.cells), C.byref(self.sp[0]),
+                                    C.byref(self.sp[1]), C.byref(self.sp[2]), C.byref(self.sp[3]),
+                                    C.byref(self.sp[4]), C.byref(self.params), C.byref(self.tal),
+                                    _ptr(self.workspace), self.wsb, _stream(stream)),
+               "cmc_collide_step")
+
+
+def collide_step(tables: Tables, cells, electrons, photons, ions, new_el, new_po, *, dt, seed, step,
+                 processes=BREMS | BH | TRIDENT, precision=FP64, schedule=SCHED_AUTO,
+                 max_per_cell=None, near_rel=1e-6, stream=None):
+    """One Monte Carlo step in place on the given device tensors (dicts of
+    torch tensors laid out as in include/cmc.h); returns (ti, td, status)
+    tensors of per-cell tallies."""
+    st = StepState(tables, cells, electrons, photons, ions, new_el, new_po, dt=dt, seed=seed,
+                   processes=processes, precision=precision, schedule=schedule,
+                   max_per_cell=max_per_cell, near_rel=near_rel)
+    st.step(step, stream)
+    return st.ti, st.td, st.status
+
+
+def expected_yield(tables: Tables, Zstar, n_e, T_e, off, px, py, pz, w, dt, precision=FP64,
+                   per_particle=False, stream=None):
+    import torch
+    n = Zstar.numel()
+    Y = torch.empty(n, dtype=torch.float64, device=Zstar.device)
+    yp = torch.empty_like(px) if per_particle else None
+    _check(get_lib().cmc_expected_yield(tables.handle, n, _ptr(Zstar), _ptr(n_e), _ptr(T_e), _ptr(off),
+                                  _ptr(px), _ptr(py), _ptr(pz), _ptr(w), float(dt), int(precision),
+                                  _ptr(Y), _ptr(yp), _stream(stream)), "cmc_expected_yield")
+    return (Y, yp) if per_particle else Y
+
+
+def expected_yield_backward(tables: Tables, Zstar, n_e, T_e, off, px, py, pz, w, dt, gY,
+                            precision=FP64, stream=None):
+    import torch
+    out = {k: torch.empty_like(px) for k in ("gpx", "gpy", "gpz", "gw")}
+    out.update({k: torch.empty_like(Zstar) for k in ("gZstar", "gn_e", "gT_e")})
+    _check(get_lib().cmc_expected_yield_backward(
+        tables.handle, Zstar.numel(), _ptr(Zstar), _ptr(n_e), _ptr(T_e), _ptr(off), _ptr(px),
+        _ptr(py), _ptr(pz), _ptr(w), float(dt), int(precision), _ptr(gY.contiguous()),
+        _ptr(out["gpx"]), _ptr(out["gpy"]), _ptr(out["gpz"]), _ptr(out["gw"]), _ptr(out["gZstar"]),
+        _ptr(out["gn_e"]), _ptr(out["gT_e"]), _stream(stream)), "cmc_expected_yield_backward")
+    return out
+
+
+def _autograd_function():
+    import torch
+
+    class ExpectedYield(torch.autograd.Function):
+        """Y[c] = sum_j w_j P_j <k>_j per cell; differentiable in px, py, pz, w,
+        Z*, n_e and T_e through the hand-written adjoint kernel (the table
+        lookups are recomputed in backward; only the inputs are saved)."""
+
+        @staticmethod
+        def forward(ctx, px, py, pz, w, Zstar, n_e, T_e, off, tables, dt, precision=FP64):
+            ctx.save_for_backward(px, py, pz, w, Zstar, n_e, T_e, off)
+            ctx.tables, ctx.dt, ctx.precision = tables, dt, precision
+            return expected_yield(tables, Zstar, n_e, T_e, off, px, py, pz, w, dt, precision)
+
+        @staticmethod
+        def backward(ctx, gY):
+            px, py, pz, w, Zstar, n_e, T_e, off = ctx.saved_tensors
+            g = expected_yield_backward(ctx.tables, Zstar, n_e, T_e, off, px, py, pz, w, ctx.dt,
+                                        gY.to(torch.float64), ctx.precision)
+            return (g["gpx"], g["gpy"], g["gpz"], g["gw"], g["gZstar"], g["gn_e"], g["gT_e"],
+                    None, None, None, None)
+
+    return ExpectedYield
+
+
+try:
+    ExpectedYield = _autograd_function()
+except Exception:  # torch missing: the C ABI stays usable without autograd
+    ExpectedYield = None

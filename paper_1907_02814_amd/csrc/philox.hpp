@@ -1,0 +1,47 @@
+// philox.hpp -- Philox4x32-10 counter-based generator (Salmon, Moraes,
+// Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3", SC'11) and the
+// draws of the step.  Counter = (x, cell, step low word, tag<<24 | step bits
+// 32..55), key = (seed low, seed high): every random number of the method
+// is a pure function of where it is used, so results do not depend on the
+// launch schedule.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cmc {
+
+struct U4 { uint32_t x, y, z, w; };
+
+__device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                            uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
+    }
+    return U4{c0, c1, c2, c3};
+}
+
+// tags of the counter's last word
+enum : uint32_t {
+    kTagKeyE = 0x01, kTagKeyIE = 0x02, kTagKeyG = 0x03, kTagKeyIG = 0x04,
+    kTagAccBr = 0x11, kTagSmpBr = 0x12, kTagAccTr = 0x21, kTagSmpTr = 0x22,
+    kTagAccBh = 0x31, kTagSmpBh = 0x32
+};
+
+struct Rng {
+    uint32_t k0, k1, step_lo, step_hi;
+    __device__ __forceinline__ U4 draw(uint32_t x, uint32_t cell, uint32_t tag) const {
+        return philox4x32_10(x, cell, step_lo, (tag << 24) | (step_hi & 0xFFFFFFu), k0, k1);
+    }
+};
+
+// uniform double in [0, 1) with 53 random bits
+__device__ __forceinline__ double u53(uint32_t a, uint32_t b) {
+    return ((double)(a >> 5) * 67108864.0 + (double)(b >> 6)) * (1.0 / 9007199254740992.0);
+}
+
+}  // namespace cmc

@@ -1,0 +1,705 @@
+// step.hip -- pairing and the Monte Carlo step (Sec. III.A) on the device.
+//
+// One workgroup of kThreads threads owns one cell at a time:
+//   1. sums of weights (n_alpha = sum W, Sec. III.A) and the screening state;
+//   2. for each pass (electron-ion, then photon-ion) both species are put in
+//      Philox-key order in LDS (bucket by the top key bits, insertion sort
+//      inside the buckets by (key, index)), n_ab = sum_j min(W_a, W_b);
+//   3. pairs are processed in chunks of kThreads consecutive pair indices
+//      that never hold the same mobile particle twice (a round of the
+//      smaller species when that is the mobile one), so a particle reused by
+//      later rounds is always handled by the same thread and sees its own
+//      updates in pair order;
+//   4. events append their products at slots given by a workgroup prefix
+//      sum of ballots, i.e. in pair order, whatever the schedule;
+//   5. photons converted by Bethe-Heitler are removed by a stable in-place
+//      compaction; per-cell tallies are reduced in a fixed tree.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "common.hpp"
+#include "philox.hpp"
+
+namespace cmc {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+
+// ------------------------------------------------------------------ helpers
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// fixed-shape workgroup sum (deterministic for a given kThreads)
+__device__ double block_sum(double v, double* red) {
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    double s = red[0];
+#pragma unroll
+    for (int i = 1; i < kWaves; ++i) s += red[i];
+    __syncthreads();
+    return s;
+}
+
+__device__ long long block_sum_ll(long long v, long long* red) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    long long s = 0;
+#pragma unroll
+    for (int i = 0; i < kWaves; ++i) s += red[i];
+    __syncthreads();
+    return s;
+}
+
+__device__ int block_or(int v, int* red) {
+    const int w = threadIdx.x >> 6;
+    const unsigned long long b = __ballot(v != 0);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[w] = b != 0ull;
+    __syncthreads();
+    int s = 0;
+#pragma unroll
+    for (int i = 0; i < kWaves; ++i) s |= red[i];
+    __syncthreads();
+    return s;
+}
+
+// exclusive prefix of a 0/1 flag over the workgroup in thread order;
+// returns the prefix, writes the total
+__device__ int block_flag_scan(bool f, int* red, int& total) {
+    const unsigned long long b = __ballot(f);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int in_wave = __popcll(b & ((1ull << lane) - 1ull));
+    __syncthreads();
+    if (lane == 0) red[w] = __popcll(b);
+    __syncthreads();
+    int before = 0, t = 0;
+#pragma unroll
+    for (int i = 0; i < kWaves; ++i) { if (i < w) before += red[i]; t += red[i]; }
+    total = t;
+    __syncthreads();
+    return before + in_wave;
+}
+
+// exclusive scan of n uint32 counters in LDS (n <= 64 * kThreads)
+__device__ void block_excl_scan_u32(uint32_t* a, int n, uint32_t* red) {
+    const int per = (n + kThreads - 1) / kThreads;
+    const int lo = threadIdx.x * per, hi = min(n, lo + per);
+    uint32_t s = 0;
+    for (int i = lo; i < hi; ++i) s += a[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int i = 0; i < kThreads; ++i) { const uint32_t v = red[i]; red[i] = run; run += v; }
+    }
+    __syncthreads();
+    uint32_t run = red[threadIdx.x];
+    for (int i = lo; i < hi; ++i) { const uint32_t v = a[i]; a[i] = run; run += v; }
+    __syncthreads();
+}
+
+__device__ __forceinline__ int bucket_bits(int n) {
+    int b = 4;
+    while (b < 12 && (1 << (b + 2)) < n) ++b;
+    return b;
+}
+
+// perm[0..n) = indices 0..n-1 in increasing (Philox key, index) order
+__device__ void key_order(int n, uint32_t cell, uint32_t tag, const Rng& rng, uint32_t* keys,
+                          uint16_t* perm, uint32_t* bcnt, uint32_t* red) {
+    if (n <= 0) return;
+    const int bb = bucket_bits(n), nb = 1 << bb, sh = 32 - bb;
+    for (int i = threadIdx.x; i < nb; i += kThreads) bcnt[i] = 0;
+    __syncthreads();
+    const int nq = (n + 3) >> 2;
+    for (int q = threadIdx.x; q < nq; q += kThreads) {
+        const U4 r = rng.draw((uint32_t)q, cell, tag);
+        const uint32_t w4[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = 4 * q + u;
+            if (i < n) { keys[i] = w4[u]; atomicAdd(&bcnt[w4[u] >> sh], 1u); }
+        }
+    }
+    __syncthreads();
+    block_excl_scan_u32(bcnt, nb, red);
+    for (int i = threadIdx.x; i < n; i += kThreads) {
+        const uint32_t pos = atomicAdd(&bcnt[keys[i] >> sh], 1u);
+        perm[pos] = (uint16_t)i;
+    }
+    __syncthreads();
+    // bcnt[b] now holds the end of bucket b
+    for (int b = threadIdx.x; b < nb; b += kThreads) {
+        const int lo = b ? (int)bcnt[b - 1] : 0, hi = (int)bcnt[b];
+        for (int x = lo + 1; x < hi; ++x) {
+            const uint16_t v = perm[x];
+            const uint32_t kv = keys[v];
+            int y = x - 1;
+            while (y >= lo) {
+                const uint16_t u = perm[y];
+                const uint32_t ku = keys[u];
+                if (ku < kv || (ku == kv && u < v)) break;
+                perm[y + 1] = u;
+                --y;
+            }
+            perm[y + 1] = v;
+        }
+    }
+    __syncthreads();
+}
+
+// ------------------------------------------------------------------ shared layout
+struct Smem {
+    uint32_t* keys;
+    uint16_t* pm;     // order of the mobile species (electrons / photons)
+    uint16_t* pi;     // order of the ions
+    uint32_t* bcnt;
+    uint32_t* dead;   // bitmap of converted photons
+};
+
+__host__ __device__ inline int smem_buckets(int maxn) {
+    int b = 4;
+    while (b < 12 && (1 << (b + 2)) < maxn) ++b;
+    return 1 << b;
+}
+
+__host__ __device__ inline size_t smem_bytes(int maxn) {
+    const size_t n = (size_t)((maxn + 63) / 64 * 64);
+    return n * 4 + n * 2 * 2 + (size_t)smem_buckets(maxn) * 4 + n / 8 + 64;
+}
+
+__device__ Smem carve(unsigned char* base, int maxn) {
+    const size_t n = (size_t)((maxn + 63) / 64 * 64);
+    Smem s;
+    s.keys = reinterpret_cast<uint32_t*>(base);
+    s.pm = reinterpret_cast<uint16_t*>(base + n * 4);
+    s.pi = s.pm + n;
+    s.bcnt = reinterpret_cast<uint32_t*>(base + n * 8);
+    s.dead = s.bcnt + smem_buckets(maxn);
+    return s;
+}
+
+// ------------------------------------------------------------------ step
+struct SpeciesDev {
+    const int64_t* off;
+    int32_t* count;
+    double *px, *py, *pz, *w;
+    int64_t* parent;
+};
+
+struct StepArgs {
+    SpeciesDev el, ph, io, ne, np;
+    const double *Zs, *ni, *Te;
+    int64_t n_cells;
+    double dt, near_rel;
+    Rng rng;
+    uint32_t proc;
+    int maxn;
+    int64_t* ti;
+    double* td;
+    int32_t* status;
+};
+
+struct Tally {
+    long long pairs[3], ev[3], near[3], drop[3];
+    double E_br, E_tr, E_bh, dE_el, dE_ph, W_br, W_tr, W_bh;
+};
+
+// live particles of cell c, clamped to the segment so that an inconsistent
+// count can never address outside the cell
+__device__ __forceinline__ int live(const SpeciesDev& s, int64_t c) {
+    const int cap = (int)(s.off[c + 1] - s.off[c]);
+    if (!s.count) return cap;
+    const int n = s.count[c];
+    return n < 0 ? 0 : (n > cap ? cap : n);
+}
+
+template <typename R>
+struct CellShared {
+    phys::Screen scr;
+    CellTab<R> ct;
+};
+
+template <typename R>
+__device__ void write_tallies(const StepArgs& A, int64_t c, const Tally& t, long long* redl, double* redd) {
+    long long iv[CMC_NI] = {t.pairs[0], t.pairs[1], t.pairs[2], t.ev[0], t.ev[1], t.ev[2],
+                            t.near[0], t.near[1], t.near[2], t.drop[0], t.drop[1], t.drop[2]};
+    for (int q = 0; q < CMC_NI; ++q) {
+        const long long s = block_sum_ll(iv[q], redl);
+        if (threadIdx.x == 0) A.ti[c * CMC_NI + q] = s;
+    }
+    const double dv[8] = {t.E_br, t.E_tr, t.E_bh, t.dE_el, t.dE_ph, t.W_br, t.W_tr, t.W_bh};
+    for (int q = 0; q < 8; ++q) {
+        const double s = block_sum(dv[q], redd);
+        if (threadIdx.x == 0) A.td[c * CMC_ND + CMC_D_E_BR + q] = s;
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_collide(StepArgs A, TabView<R> T) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double redd[kWaves];
+    __shared__ long long redl[kWaves];
+    __shared__ int redi[kWaves];
+    __shared__ uint32_t redu[kThreads];
+    __shared__ CellShared<R> cs;
+    const Smem S = carve(smem_raw, A.maxn);
+    const int tid = threadIdx.x;
+
+    for (int64_t c = blockIdx.x; c < A.n_cells; c += gridDim.x) {
+        const uint32_t cell = (uint32_t)c;
+        const int Ne = live(A.el, c), Ng0 = live(A.ph, c), Ni = live(A.io, c);
+        const int64_t e0 = A.el.off[c], g0 = A.ph.off[c], i0 = A.io.off[c];
+        const double Zs = A.Zs[c], nic = A.ni[c], Te = A.Te[c];
+        Tally t = {};
+        bool skip = false;
+        int st = 0;
+        if (!(Zs >= 0.0 && Zs <= T.Z && nic > 0.0 && Te >= 0.0 && isfinite(nic) && isfinite(Te))) {
+            st = CMC_ST_BAD_CELL; skip = true;
+        } else if (Ne > A.maxn || Ng0 > A.maxn || Ni > A.maxn) {
+            st = CMC_ST_TOO_LARGE; skip = true;
+        }
+        // densities and weight check
+        double se = 0.0, sg = 0.0, si = 0.0;
+        int bad = 0;
+        if (!skip) {
+            for (int a = tid; a < Ne; a += kThreads) { const double w = A.el.w[e0 + a]; se += w; bad |= !(w >= 0.0) || !isfinite(w); }
+            for (int a = tid; a < Ng0; a += kThreads) { const double w = A.ph.w[g0 + a]; sg += w; bad |= !(w >= 0.0) || !isfinite(w); }
+            for (int a = tid; a < Ni; a += kThreads) { const double w = A.io.w[i0 + a]; si += w; bad |= !(w >= 0.0) || !isfinite(w); }
+            if (tid == 0) {
+                cs.scr = phys::screening(T.Z, Zs, nic, Te);
+                cs.ct = cell_tab<R>(cs.scr, T.ax);
+            }
+        }
+        const double n_e = block_sum(se, redd), n_g = block_sum(sg, redd), n_I = block_sum(si, redd);
+        if (!skip && block_or(bad, redi)) { st = CMC_ST_BAD_WEIGHT; skip = true; }
+        double nab_ei = 0.0, nab_gi = 0.0;
+        if (skip) {
+            if (tid == 0) atomicOr(A.status, st);
+            write_tallies<R>(A, c, t, redl, redd);
+            if (tid == 0) { A.td[c * CMC_ND + CMC_D_NAB_EI] = 0.0; A.td[c * CMC_ND + CMC_D_NAB_GI] = 0.0; }
+            __syncthreads();
+            continue;
+        }
+        const CellTab<R> ct = cs.ct;
+        bool high_any = false;
+
+        // ---------------------------------------------- electron-ion pass
+        int ph_count = Ng0;   // photons in the species after Bremsstrahlung appends
+        const int cap_ph = (int)(A.ph.off[c + 1] - g0);
+        int cnt_ne = A.ne.count[c], cnt_np = A.np.count[c];
+        const int cap_ne = (int)(A.ne.off[c + 1] - A.ne.off[c]), cap_np = (int)(A.np.off[c + 1] - A.np.off[c]);
+        if ((A.proc & (CMC_BREMS | CMC_TRIDENT)) && Ne > 0 && Ni > 0) {
+            key_order(Ne, cell, kTagKeyE, A.rng, S.keys, S.pm, S.bcnt, redu);
+            key_order(Ni, cell, kTagKeyIE, A.rng, S.keys, S.pi, S.bcnt, redu);
+            const int N = Ne > Ni ? Ne : Ni;
+            double part = 0.0;
+            for (int j = tid; j < N; j += kThreads) {
+                const double we = A.el.w[e0 + S.pm[j % Ne]], wi = A.io.w[i0 + S.pi[j % Ni]];
+                part += we < wi ? we : wi;
+            }
+            nab_ei = block_sum(part, redd);
+            const double coef = n_e * n_I / nab_ei;
+            const int run = Ne >= Ni ? N : Ne;          // pairs in a run never repeat an electron
+            for (int r0 = (nab_ei > 0.0 ? 0 : N); r0 < N; r0 += run) {
+                const int rend = min(N, r0 + run);
+                for (int base = r0; base < rend; base += kThreads) {
+                    const int j = base + tid;
+                    const bool act = j < rend;
+                    bool f_ph = false, f_tr = false;
+                    double kx = 0, ky = 0, kz = 0, pxm = 0, pym = 0, pzm = 0, pxp = 0, pyp = 0, pzp = 0, We = 0;
+                    int64_t ie = 0;
+                    if (act) {
+                        ie = e0 + S.pm[j % Ne];
+                        const int64_t ii = i0 + S.pi[j % Ni];
+                        We = A.el.w[ie];
+                        const double Wi = A.io.w[ii];
+                        const double Pej = Wi / (We > Wi ? We : Wi);
+                        double px = A.el.px[ie], py = A.el.py[ie], pz = A.el.pz[ie];
+                        bool moved = false;
+                        for (int proc = 0; proc < 2; ++proc) {
+                            const uint32_t bit = proc == 0 ? CMC_BREMS : CMC_TRIDENT;
+                            if (!(A.proc & bit)) continue;
+                            t.pairs[proc]++;
+                            const R rpx = (R)px, rpy = (R)py, rpz = (R)pz;
+                            const R p2 = rpx * rpx + rpy * rpy + rpz * rpz;
+                            const R g = sqrt((R)1 + p2), gm1 = p2 / (g + (R)1);
+                            const R pm = sqrt(p2);
+                            R sig;
+                            BremsLook<R> BL;
+                            bool high = false;
+                            if (proc == 0) { BL = brems_lookup<R>(T, ct, g, gm1, high); sig = BL.sig; }
+                            else sig = (R)phys::trident_sigma(T.Z, (double)g);
+                            high_any |= high;
+                            if (!(sig > (R)0)) continue;
+                            // eq:proba3 with gamma' v' = c |p'| (eq:proba2), ions at rest
+                            const double x = coef * (double)sig * (phys::kC * (double)pm / (double)g) * A.dt;
+                            const double P = -expm1(-x);
+                            const U4 r = A.rng.draw((uint32_t)j, cell, proc == 0 ? kTagAccBr : kTagAccTr);
+                            const double U1 = u53(r.x, r.y), U2 = u53(r.z, r.w);
+                            if (fabs(U1 - P) <= A.near_rel * P) t.near[proc]++;
+                            if (!(U1 < P && U2 < Pej)) continue;
+                            const U4 q = A.rng.draw((uint32_t)j, cell, proc == 0 ? kTagSmpBr : kTagSmpTr);
+                            const R xi1 = (R)u53(q.x, q.y), xi2 = (R)u53(q.z, q.w);
+                            t.ev[proc]++;
+                            moved = true;
+                            if (proc == 0) {
+                                R k, g2, g2m1;
+                                brems_sample<R>(T, ct, BL, g, gm1, xi1, k, g2, g2m1);
+                                const R pf = sqrt(g2m1 * (g2 + (R)1));
+                                const R f = pf / pm, h = k / pm;
+                                const R qx = rpx * f, qy = rpy * f, qz = rpz * f;
+                                kx = (double)(rpx * h); ky = (double)(rpy * h); kz = (double)(rpz * h);
+                                px = (double)qx; py = (double)qy; pz = (double)qz;
+                                const double kl = sqrt(kx * kx + ky * ky + kz * kz);
+                                t.E_br += We * kl;
+                                // electron energy change = -k exactly (ions at rest); the
+                                // difference of two Lorentz factors would cancel for k << gamma
+                                t.dE_el += We * (-(double)k);
+                                t.W_br += We;
+                                f_ph = true;
+                            } else {
+                                R gpair, gpl, gmi;
+                                trident_sample<R>(T, g, xi1, xi2, gpair, gpl, gmi);
+                                const R gfm1 = gm1 - gpair, gf = gfm1 + (R)1;
+                                const R pf = sqrt(gfm1 * (gf + (R)1));
+                                const R pplus = sqrt((gpl - (R)1) * (gpl + (R)1));
+                                const R pminus = sqrt((gmi - (R)1) * (gmi + (R)1));
+                                const R f = pf / pm, fp = pplus / pm, fm = pminus / pm;
+                                px = (double)(rpx * f); py = (double)(rpy * f); pz = (double)(rpz * f);
+                                pxp = (double)(rpx * fp); pyp = (double)(rpy * fp); pzp = (double)(rpz * fp);
+                                pxm = (double)(rpx * fm); pym = (double)(rpy * fm); pzm = (double)(rpz * fm);
+                                const double gpl_l = sqrt(1.0 + pxp * pxp + pyp * pyp + pzp * pzp);
+                                const double gmi_l = sqrt(1.0 + pxm * pxm + pym * pym + pzm * pzm);
+                                t.E_tr += We * (gpl_l + gmi_l);
+                                t.dE_el += We * (-(double)gpair);
+                                t.W_tr += We;
+                                f_tr = true;
+                            }
+                        }
+                        if (moved) { A.el.px[ie] = px; A.el.py[ie] = py; A.el.pz[ie] = pz; }
+                    }
+                    // ordered appends (pair order within the chunk)
+                    int tot_ph, tot_tr;
+                    const int o_ph = block_flag_scan(f_ph, redi, tot_ph);
+                    const int o_tr = block_flag_scan(f_tr, redi, tot_tr);
+                    if (f_ph) {
+                        const int slot = ph_count + o_ph;
+                        if (slot < cap_ph) {
+                            const int64_t at = g0 + slot;
+                            A.ph.px[at] = kx; A.ph.py[at] = ky; A.ph.pz[at] = kz; A.ph.w[at] = We;
+                            if (A.ph.parent) A.ph.parent[at] = ie;
+                        } else { t.drop[0]++; }
+                    }
+                    if (f_tr) {
+                        const int s1 = cnt_ne + o_tr, s2 = cnt_np + o_tr;
+                        if (s1 < cap_ne) {
+                            const int64_t at = A.ne.off[c] + s1;
+                            A.ne.px[at] = pxm; A.ne.py[at] = pym; A.ne.pz[at] = pzm; A.ne.w[at] = We;
+                            if (A.ne.parent) A.ne.parent[at] = ie;
+                        } else { t.drop[1]++; }
+                        if (s2 < cap_np) {
+                            const int64_t at = A.np.off[c] + s2;
+                            A.np.px[at] = pxp; A.np.py[at] = pyp; A.np.pz[at] = pzp; A.np.w[at] = We;
+                            if (A.np.parent) A.np.parent[at] = ie;
+                        } else { t.drop[2]++; }
+                    }
+                    ph_count = min(cap_ph, ph_count + tot_ph);
+                    cnt_ne = min(cap_ne, cnt_ne + tot_tr);
+                    cnt_np = min(cap_np, cnt_np + tot_tr);
+                }
+            }
+        }
+
+        // ---------------------------------------------- photon-ion pass
+        bool any_dead = false;
+        if ((A.proc & CMC_BH) && Ng0 > 0 && Ni > 0) {
+            for (int i = tid; i < (Ng0 + 31) / 32; i += kThreads) S.dead[i] = 0u;
+            key_order(Ng0, cell, kTagKeyG, A.rng, S.keys, S.pm, S.bcnt, redu);
+            key_order(Ni, cell, kTagKeyIG, A.rng, S.keys, S.pi, S.bcnt, redu);
+            const int N = Ng0 > Ni ? Ng0 : Ni;
+            double part = 0.0;
+            for (int j = tid; j < N; j += kThreads) {
+                const double wg = A.ph.w[g0 + S.pm[j % Ng0]], wi = A.io.w[i0 + S.pi[j % Ni]];
+                part += wg < wi ? wg : wi;
+            }
+            nab_gi = block_sum(part, redd);
+            const double coef = n_g * n_I / nab_gi;
+            const int run = Ng0 >= Ni ? N : Ng0;
+            int killed = 0;
+            for (int r0 = (nab_gi > 0.0 ? 0 : N); r0 < N; r0 += run) {
+                const int rend = min(N, r0 + run);
+                for (int base = r0; base < rend; base += kThreads) {
+                    const int j = base + tid;
+                    bool f_bh = false;
+                    double pxm = 0, pym = 0, pzm = 0, pxp = 0, pyp = 0, pzp = 0, Wg = 0;
+                    int64_t ig = 0;
+                    if (j < rend) {
+                        const int lg = S.pm[j % Ng0];
+                        const bool dead = (S.dead[lg >> 5] >> (lg & 31)) & 1u;
+                        if (!dead) {
+                            ig = g0 + lg;
+                            const int64_t ii = i0 + S.pi[j % Ni];
+                            t.pairs[2]++;
+                            Wg = A.ph.w[ig];
+                            const double Wi = A.io.w[ii];
+                            const double Pej = Wi / (Wg > Wi ? Wg : Wi);
+                            const double qx = A.ph.px[ig], qy = A.ph.py[ig], qz = A.ph.pz[ig];
+                            const R rqx = (R)qx, rqy = (R)qy, rqz = (R)qz;
+                            const R k = sqrt(rqx * rqx + rqy * rqy + rqz * rqz);
+                            int ik; R wk; bool high;
+                            const R sig = bh_lookup<R>(T, ct, k, ik, wk, high);
+                            high_any |= high;
+                            if (sig > (R)0) {
+                                // eq:proba3 for photons: gamma -> k', v' -> c, flux k' c/(k gamma_i)
+                                const double x = coef * (double)sig * (phys::kC * (double)k / (double)k) * A.dt;
+                                const double P = -expm1(-x);
+                                const U4 r = A.rng.draw((uint32_t)j, cell, kTagAccBh);
+                                const double U1 = u53(r.x, r.y), U2 = u53(r.z, r.w);
+                                if (fabs(U1 - P) <= A.near_rel * P) t.near[2]++;
+                                if (U1 < P && U2 < Pej) {
+                                    const U4 q = A.rng.draw((uint32_t)j, cell, kTagSmpBh);
+                                    R gpl, gmi;
+                                    bh_sample<R>(T, ct, k, ik, wk, (R)u53(q.x, q.y), gpl, gmi);
+                                    const R pplus = sqrt((gpl - (R)1) * (gpl + (R)1));
+                                    const R pminus = sqrt((gmi - (R)1) * (gmi + (R)1));
+                                    const R fp = pplus / k, fm = pminus / k;
+                                    pxp = (double)(rqx * fp); pyp = (double)(rqy * fp); pzp = (double)(rqz * fp);
+                                    pxm = (double)(rqx * fm); pym = (double)(rqy * fm); pzm = (double)(rqz * fm);
+                                    const double gpl_l = sqrt(1.0 + pxp * pxp + pyp * pyp + pzp * pzp);
+                                    const double gmi_l = sqrt(1.0 + pxm * pxm + pym * pym + pzm * pzm);
+                                    atomicOr(&S.dead[lg >> 5], 1u << (lg & 31));
+                                    t.ev[2]++;
+                                    t.E_bh += Wg * (gpl_l + gmi_l);
+                                    t.dE_ph += -Wg * (double)k;
+                                    t.W_bh += Wg;
+                                    f_bh = true;
+                                }
+                            }
+                        }
+                    }
+                    int tot;
+                    const int o = block_flag_scan(f_bh, redi, tot);
+                    if (f_bh) {
+                        const int s1 = cnt_ne + o, s2 = cnt_np + o;
+                        if (s1 < cap_ne) {
+                            const int64_t at = A.ne.off[c] + s1;
+                            A.ne.px[at] = pxm; A.ne.py[at] = pym; A.ne.pz[at] = pzm; A.ne.w[at] = Wg;
+                            if (A.ne.parent) A.ne.parent[at] = ig;
+                        } else { t.drop[1]++; }
+                        if (s2 < cap_np) {
+                            const int64_t at = A.np.off[c] + s2;
+                            A.np.px[at] = pxp; A.np.py[at] = pyp; A.np.pz[at] = pzp; A.np.w[at] = Wg;
+                            if (A.np.parent) A.np.parent[at] = ig;
+                        } else { t.drop[2]++; }
+                    }
+                    killed += tot;
+                    cnt_ne = min(cap_ne, cnt_ne + tot);
+                    cnt_np = min(cap_np, cnt_np + tot);
+                }
+            }
+            any_dead = killed > 0;
+        }
+
+        // ---------------------------------------------- photon compaction
+        if (any_dead) {
+            int wpos = 0;
+            for (int base = 0; base < ph_count; base += kThreads) {
+                const int a = base + tid;
+                bool keep = false;
+                double vx = 0, vy = 0, vz = 0, vw = 0;
+                int64_t par = -1;
+                if (a < ph_count) {
+                    keep = !(a < Ng0 && ((S.dead[a >> 5] >> (a & 31)) & 1u));
+                    if (keep) {
+                        vx = A.ph.px[g0 + a]; vy = A.ph.py[g0 + a]; vz = A.ph.pz[g0 + a]; vw = A.ph.w[g0 + a];
+                        if (A.ph.parent) par = A.ph.parent[g0 + a];
+                    }
+                }
+                int tot;
+                const int o = block_flag_scan(keep, redi, tot);   // barrier: all reads precede writes
+                if (keep) {
+                    const int64_t at = g0 + wpos + o;
+                    A.ph.px[at] = vx; A.ph.py[at] = vy; A.ph.pz[at] = vz; A.ph.w[at] = vw;
+                    if (A.ph.parent) A.ph.parent[at] = par;
+                }
+                wpos += tot;
+                __syncthreads();
+            }
+            ph_count = wpos;
+        }
+
+        // ---------------------------------------------- counts, tallies
+        if (high_any) atomicOr(A.status, CMC_ST_GAMMA_HIGH);
+        const long long dropped = block_sum_ll(t.drop[0] + t.drop[1] + t.drop[2], redl);
+        if (tid == 0) {
+            if (A.ph.count) A.ph.count[c] = ph_count;
+            A.ne.count[c] = cnt_ne;
+            A.np.count[c] = cnt_np;
+            A.td[c * CMC_ND + CMC_D_NAB_EI] = nab_ei;
+            A.td[c * CMC_ND + CMC_D_NAB_GI] = nab_gi;
+            if (dropped) atomicOr(A.status, CMC_ST_OVERFLOW);
+        }
+        write_tallies<R>(A, c, t, redl, redd);
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ pair_cells
+struct PairArgs {
+    const int64_t *a_off, *b_off, *pair_off;
+    const int32_t *a_cnt, *b_cnt;
+    const double *wa, *wb;
+    int32_t *pa, *pb;
+    double* nab;
+    int64_t n_cells;
+    Rng rng;
+    uint32_t tag_a, tag_b;
+    int maxn;
+};
+
+__global__ __launch_bounds__(kThreads) void k_pair(PairArgs A) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double redd[kWaves];
+    __shared__ uint32_t redu[kThreads];
+    const Smem S = carve(smem_raw, A.maxn);
+    for (int64_t c = blockIdx.x; c < A.n_cells; c += gridDim.x) {
+        const int ca = (int)(A.a_off[c + 1] - A.a_off[c]), cb = (int)(A.b_off[c + 1] - A.b_off[c]);
+        const int na = A.a_cnt ? max(0, min(ca, A.a_cnt[c])) : ca;
+        const int nb = A.b_cnt ? max(0, min(cb, A.b_cnt[c])) : cb;
+        const int64_t po = A.pair_off[c];
+        const int N = (na > 0 && nb > 0) ? (na > nb ? na : nb) : 0;
+        if (na > A.maxn || nb > A.maxn || A.pair_off[c + 1] - po < N) {
+            const int room = (int)min((int64_t)N, A.pair_off[c + 1] - po);
+            for (int j = threadIdx.x; j < room; j += kThreads) { A.pa[po + j] = -1; A.pb[po + j] = -1; }
+            if (A.nab && threadIdx.x == 0) A.nab[c] = 0.0;
+            continue;
+        }
+        double part = 0.0;
+        if (N > 0) {
+            key_order(na, (uint32_t)c, A.tag_a, A.rng, S.keys, S.pm, S.bcnt, redu);
+            key_order(nb, (uint32_t)c, A.tag_b, A.rng, S.keys, S.pi, S.bcnt, redu);
+            for (int j = threadIdx.x; j < N; j += kThreads) {
+                const int a = S.pm[j % na], b = S.pi[j % nb];
+                A.pa[po + j] = a; A.pb[po + j] = b;
+                const double x = A.wa[A.a_off[c] + a], y = A.wb[A.b_off[c] + b];
+                part += x < y ? x : y;
+            }
+        }
+        const double s = block_sum(part, redd);
+        if (A.nab && threadIdx.x == 0) A.nab[c] = s;
+        __syncthreads();
+    }
+}
+
+int grid_for(int64_t n_cells) {
+    const int64_t cap = 256 * 64;
+    return (int)(n_cells < cap ? (n_cells > 0 ? n_cells : 1) : cap);
+}
+
+}  // namespace
+}  // namespace cmc
+
+using namespace cmc;
+
+extern "C" size_t cmc_step_workspace_bytes(int64_t n_cells, int32_t schedule) {
+    (void)n_cells; (void)schedule;
+    return 0;
+}
+
+static cmc_status set_species(SpeciesDev& d, const cmc_species* s, const char* name, bool need_count,
+                              bool need_mom) {
+    CMC_REQUIRE(s && s->off && s->w, CMC_EINVAL, "cmc_collide_step: %s: off and w are required", name);
+    CMC_REQUIRE(!need_count || s->count, CMC_EINVAL, "cmc_collide_step: %s: count is required", name);
+    CMC_REQUIRE(!need_mom || (s->px && s->py && s->pz), CMC_EINVAL,
+                "cmc_collide_step: %s: px, py, pz are required", name);
+    d.off = s->off; d.count = s->count; d.px = s->px; d.py = s->py; d.pz = s->pz; d.w = s->w;
+    d.parent = s->parent;
+    return CMC_OK;
+}
+
+extern "C" cmc_status cmc_collide_step(cmc_tables t, const cmc_cells* cells, cmc_species* electrons,
+                                       cmc_species* photons, const cmc_species* ions,
+                                       cmc_species* new_el, cmc_species* new_po,
+                                       const cmc_step_params* P, cmc_tallies* tal,
+                                       void* workspace, size_t workspace_bytes, void* stream) {
+    (void)workspace; (void)workspace_bytes;
+    CMC_REQUIRE(t && cells && P && tal, CMC_EINVAL, "cmc_collide_step: NULL argument");
+    CMC_REQUIRE(cells->n_cells >= 0 && cells->Zstar && cells->n_i && cells->T_e, CMC_EINVAL,
+                "cmc_collide_step: cells incomplete");
+    CMC_REQUIRE(tal->ti && tal->td && tal->status, CMC_EINVAL, "cmc_collide_step: tallies incomplete");
+    CMC_REQUIRE(P->dt > 0.0, CMC_EINVAL, "cmc_collide_step: dt must be > 0");
+    CMC_REQUIRE((P->processes & ~7u) == 0, CMC_EINVAL, "cmc_collide_step: unknown process bits");
+    CMC_REQUIRE(P->precision == CMC_FP64 || P->precision == CMC_FP32, CMC_EINVAL,
+                "cmc_collide_step: unknown precision %d", P->precision);
+    CMC_REQUIRE(P->schedule >= 0 && P->schedule <= 2, CMC_EINVAL, "cmc_collide_step: unknown schedule");
+    CMC_REQUIRE(P->max_per_cell >= 1 && P->max_per_cell <= CMC_MAX_PER_CELL, CMC_ERANGE,
+                "cmc_collide_step: max_per_cell = %d outside [1, %d]", P->max_per_cell, CMC_MAX_PER_CELL);
+    CMC_REQUIRE(P->near_rel >= 0.0, CMC_EINVAL, "cmc_collide_step: near_rel < 0");
+    StepArgs A{};
+    cmc_status s;
+    if ((s = set_species(A.el, electrons, "electrons", false, true)) != CMC_OK) return s;
+    if ((s = set_species(A.ph, photons, "photons", true, true)) != CMC_OK) return s;
+    if ((s = set_species(A.io, ions, "ions", false, false)) != CMC_OK) return s;
+    CMC_REQUIRE(!ions->px && !ions->py && !ions->pz, CMC_EINVAL,
+                "cmc_collide_step: moving ions are not supported (ions at rest: px = py = pz = NULL)");
+    if ((s = set_species(A.ne, new_el, "new_el", true, true)) != CMC_OK) return s;
+    if ((s = set_species(A.np, new_po, "new_po", true, true)) != CMC_OK) return s;
+    A.Zs = cells->Zstar; A.ni = cells->n_i; A.Te = cells->T_e;
+    A.n_cells = cells->n_cells;
+    A.dt = P->dt; A.near_rel = P->near_rel;
+    A.rng.k0 = (uint32_t)P->seed; A.rng.k1 = (uint32_t)(P->seed >> 32);
+    A.rng.step_lo = (uint32_t)P->step; A.rng.step_hi = (uint32_t)(P->step >> 32);
+    A.proc = P->processes;
+    A.maxn = P->max_per_cell;
+    A.ti = tal->ti; A.td = tal->td; A.status = tal->status;
+    if (A.n_cells == 0) return CMC_OK;
+    const size_t shm = smem_bytes(A.maxn);
+    hipStream_t st = as_stream(stream);
+    const int grid = grid_for(A.n_cells);
+    if (P->precision == CMC_FP64) {
+        (void)hipFuncSetAttribute((const void*)k_collide<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        hipLaunchKernelGGL(k_collide<double>, dim3(grid), dim3(kThreads), shm, st, A, view64(t));
+    } else {
+        (void)hipFuncSetAttribute((const void*)k_collide<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        hipLaunchKernelGGL(k_collide<float>, dim3(grid), dim3(kThreads), shm, st, A, view32(t));
+    }
+    CMC_CHECK_LAUNCH("cmc_collide_step");
+    return CMC_OK;
+}
+
+extern "C" cmc_status cmc_pair_cells(int64_t n_cells, const int64_t* a_off, const int32_t* a_cnt,
+                                     const int64_t* b_off, const int32_t* b_cnt, const double* wa,
+                                     const double* wb, uint64_t seed, uint64_t step, uint32_t pass,
+                                     const int64_t* pair_off, int32_t* pa, int32_t* pb, double* n_ab,
+                                     void* stream) {
+    CMC_REQUIRE(n_cells >= 0, CMC_EINVAL, "cmc_pair_cells: n_cells < 0");
+    CMC_REQUIRE(a_off && b_off && wa && wb && pair_off && pa && pb, CMC_EINVAL, "cmc_pair_cells: NULL argument");
+    CMC_REQUIRE(pass == 1 || pass == 2, CMC_EINVAL, "cmc_pair_cells: pass must be 1 or 2");
+    if (n_cells == 0) return CMC_OK;
+    PairArgs A{};
+    A.a_off = a_off; A.b_off = b_off; A.pair_off = pair_off; A.a_cnt = a_cnt; A.b_cnt = b_cnt;
+    A.wa = wa; A.wb = wb; A.pa = pa; A.pb = pb; A.nab = n_ab; A.n_cells = n_cells;
+    A.rng.k0 = (uint32_t)seed; A.rng.k1 = (uint32_t)(seed >> 32);
+    A.rng.step_lo = (uint32_t)step; A.rng.step_hi = (uint32_t)(step >> 32);
+    A.tag_a = pass == 1 ? kTagKeyE : kTagKeyG;
+    A.tag_b = pass == 1 ? kTagKeyIE : kTagKeyIG;
+    A.maxn = CMC_MAX_PER_CELL;
+    const size_t shm = smem_bytes(A.maxn);
+    (void)hipFuncSetAttribute((const void*)k_pair, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    hipLaunchKernelGGL(k_pair, dim3(grid_for(n_cells)), dim3(kThreads), shm, as_stream(stream), A);
+    CMC_CHECK_LAUNCH("cmc_pair_cells");
+    return CMC_OK;
+}

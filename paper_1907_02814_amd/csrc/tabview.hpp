@@ -1,0 +1,210 @@
+// tabview.hpp -- device view of the cross-section tables, table lookups and
+// inverse-CDF sampling.  Templated on the arithmetic type R of the lookups
+// and kinematics (double: plain form, float: FP32 form).
+//
+// Lookup rule (part of the tabulated method): linear interpolation, first
+// along the screening axis of the cell (ln L_R; or L_D then eta_D for the
+// non-relativistic segment), then along the energy axis.  Sampling inverts
+// the piecewise-linear cumulative distribution blended the same way.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "grid.hpp"
+#include "physics.hpp"
+
+namespace cmc {
+
+struct AxisDef { double u0, u1, du; int n; };
+
+// axis constants, computed once on the host
+struct Axes {
+    AxisDef nr, rel, ur, bh, tri, split, L, eta;
+};
+
+template <typename R>
+struct TabView {
+    const R* a[grid::kNumArrays];
+    Axes ax;
+    double Z, Ltf, fc;
+    __device__ __forceinline__ const R* operator[](int i) const { return a[i]; }
+};
+
+template <typename R>
+__device__ __forceinline__ R lerp(R a, R b, R w) { return a + w * (b - a); }
+
+// position on a uniform axis: i in [0, n-2], w in [0, 1]; `inside` false
+// when clamped at an end (zero derivative there)
+template <typename R>
+__device__ __forceinline__ void locate(R u, const AxisDef& A, int& i, R& w, bool& inside) {
+    const R pos = (u - (R)A.u0) / (R)A.du;
+    if (pos <= (R)0) { i = 0; w = (R)0; inside = false; return; }
+    if (pos >= (R)(A.n - 1)) { i = A.n - 2; w = (R)1; inside = false; return; }
+    int k = (int)pos;
+    if (k > A.n - 2) k = A.n - 2;
+    i = k; w = pos - (R)k; inside = true;
+}
+
+// per-cell lookup state (screening axes)
+template <typename R>
+struct CellTab {
+    int iL, iE, iD;
+    R wL, wE, wD;
+    bool inL, inE, inD;
+};
+
+template <typename R>
+__device__ __forceinline__ CellTab<R> cell_tab(const phys::Screen& s, const Axes& ax) {
+    CellTab<R> t;
+    locate<R>((R)log(s.Lr), ax.L, t.iL, t.wL, t.inL);
+    locate<R>((R)s.eta_d, ax.eta, t.iE, t.wE, t.inE);
+    const double lnLd = s.eta_d > 0.0 ? log(s.Ld) : log(grid::kLmin);
+    locate<R>((R)lnLd, ax.L, t.iD, t.wD, t.inD);
+    return t;
+}
+
+// blend along ln L of a (energy, L) array at energy node i, column col
+template <typename R>
+__device__ __forceinline__ R blend_L(const R* T, int stride, int i, const CellTab<R>& c, int col) {
+    const R* p = T + ((size_t)i * grid::kL + c.iL) * stride + col;
+    return lerp(p[0], p[stride], c.wL);
+}
+
+// blend along ln L_D then eta_D of an (energy, eta, L) array
+template <typename R>
+__device__ __forceinline__ R blend_N(const R* T, int stride, int i, const CellTab<R>& c, int col) {
+    const R* p = T + (((size_t)i * grid::kEta + c.iE) * grid::kL + c.iD) * stride + col;
+    const R* q = p + (size_t)grid::kL * stride;
+    return lerp(lerp(p[0], p[stride], c.wD), lerp(q[0], q[stride], c.wD), c.wE);
+}
+
+enum Seg { kSegNone = 0, kSegNR = 1, kSegRel = 2, kSegUR = 3 };
+
+template <typename R>
+struct BremsLook {
+    int seg, ig;
+    R wg;
+    bool in;
+    R sig, sk;
+};
+
+// Bremsstrahlung segment and cross section of an electron (gamma g,
+// kinetic g1m1 = g - 1).  Regimes of Sec. II.B: g <= 2 non-relativistic,
+// 2 < g <= 100 moderately relativistic, g > 100 ultra-relativistic; no
+// emission below 1 keV; energies above the table are clamped (high = true).
+template <typename R>
+__device__ __forceinline__ BremsLook<R> brems_lookup(const TabView<R>& T, const CellTab<R>& c,
+                                                     R g, R g1m1, bool& high) {
+    BremsLook<R> o;
+    high = false;
+    o.seg = kSegNone; o.ig = 0; o.wg = (R)0; o.in = false; o.sig = (R)0; o.sk = (R)0;
+    if (!(g1m1 > (R)(grid::kTminEv / grid::kMec2Ev))) return o;
+    if (g <= (R)2) {
+        o.seg = kSegNR;
+        locate<R>(log(g1m1), T.ax.nr, o.ig, o.wg, o.in);
+        const R s0 = blend_N<R>(T[grid::kSigN], 1, o.ig, c, 0), s1 = blend_N<R>(T[grid::kSigN], 1, o.ig + 1, c, 0);
+        const R k0 = blend_N<R>(T[grid::kSkN], 1, o.ig, c, 0), k1 = blend_N<R>(T[grid::kSkN], 1, o.ig + 1, c, 0);
+        o.sig = lerp(s0, s1, o.wg); o.sk = lerp(k0, k1, o.wg);
+        return o;
+    }
+    const bool rel = g <= (R)100;
+    o.seg = rel ? kSegRel : kSegUR;
+    R u;
+    if (!rel && g > (R)grid::kTop) { high = true; u = (R)log(grid::kTop); } else { u = log(g); }
+    locate<R>(u, rel ? T.ax.rel : T.ax.ur, o.ig, o.wg, o.in);
+    const R* S = T[rel ? grid::kSigR : grid::kSigU];
+    const R* K = T[rel ? grid::kSkR : grid::kSkU];
+    o.sig = lerp(blend_L<R>(S, 1, o.ig, c, 0), blend_L<R>(S, 1, o.ig + 1, c, 0), o.wg);
+    o.sk = lerp(blend_L<R>(K, 1, o.ig, c, 0), blend_L<R>(K, 1, o.ig + 1, c, 0), o.wg);
+    return o;
+}
+
+// Bethe-Heitler total cross section at photon energy k (ion frame): zero
+// at k <= 2, linear to zero below the first node (k - 2 < 1e-6), clamped
+// above the table.
+template <typename R>
+__device__ __forceinline__ R bh_lookup(const TabView<R>& T, const CellTab<R>& c, R k,
+                                       int& ik, R& wk, bool& high) {
+    high = false; ik = 0; wk = (R)0;
+    if (!(k > (R)2)) return (R)0;
+    R x = k - (R)2;
+    if (k > (R)grid::kTop) { high = true; x = (R)(grid::kTop - 2.0); }
+    const R* S = T[grid::kSigB];
+    if (x < (R)grid::kBHx0) return blend_L<R>(S, 1, 0, c, 0) * (x / (R)grid::kBHx0);
+    bool in;
+    locate<R>(log(x), T.ax.bh, ik, wk, in);
+    return lerp(blend_L<R>(S, 1, ik, c, 0), blend_L<R>(S, 1, ik + 1, c, 0), wk);
+}
+
+// ------------------------------------------------------------------ sampling
+// blended CDF value j of the rows at energy nodes i, i+1 (kind: 0 (g, L),
+// 1 (g, eta, L), 2 one-dimensional)
+template <typename R>
+__device__ __forceinline__ R cdf_value(const R* T, int kind, int i, R w, const CellTab<R>& c, int j) {
+    R a, b;
+    if (kind == 0) { a = blend_L<R>(T, grid::kRow, i, c, j); b = blend_L<R>(T, grid::kRow, i + 1, c, j); }
+    else if (kind == 1) { a = blend_N<R>(T, grid::kRow, i, c, j); b = blend_N<R>(T, grid::kRow, i + 1, c, j); }
+    else { a = T[(size_t)i * grid::kRow + j]; b = T[(size_t)(i + 1) * grid::kRow + j]; }
+    return lerp(a, b, w);
+}
+
+// abscissa t in [0, 1] with F(t) = xi for the piecewise-linear blended CDF
+template <typename R>
+__device__ __forceinline__ R cdf_invert(const R* T, int kind, int i, R w, const CellTab<R>& c, R xi) {
+    int lo = 0, hi = grid::kPanels;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (cdf_value<R>(T, kind, i, w, c, mid) <= xi) lo = mid; else hi = mid;
+    }
+    const R flo = cdf_value<R>(T, kind, i, w, c, lo), fhi = cdf_value<R>(T, kind, i, w, c, hi);
+    return ((R)lo + (xi - flo) / (fhi - flo)) / (R)grid::kPanels;
+}
+
+// Bremsstrahlung photon energy for an electron of (g1, g1m1): returns k and
+// the electron's g2, g2 - 1 after emission (Sec. III.A)
+template <typename R>
+__device__ __forceinline__ void brems_sample(const TabView<R>& T, const CellTab<R>& c,
+                                             const BremsLook<R>& L, R g1, R g1m1, R xi,
+                                             R& k, R& g2, R& g2m1) {
+    const bool nr = L.seg == kSegNR;
+    const R* C = T[nr ? grid::kCdfN : (L.seg == kSegRel ? grid::kCdfR : grid::kCdfU)];
+    const R t = cdf_invert<R>(C, nr ? 1 : 0, L.ig, L.wg, c, xi);
+    const R Y = log((g1 - (R)grid::kCut * g1m1) / (R)grid::kCut);
+    const R dl = nr ? ((R)1 - t) * ((R)1 - t) * Y : ((R)1 - t) * Y;
+    const R ey = g1m1 * exp(-dl);
+    g2 = g1 / ((R)1 + ey);
+    g2m1 = g1m1 * (-expm1(-dl)) / ((R)1 + ey);
+    k = ey * g2;
+}
+
+// Bethe-Heitler positron / electron energies for photon energy k
+template <typename R>
+__device__ __forceinline__ void bh_sample(const TabView<R>& T, const CellTab<R>& c, R k, int ik, R wk,
+                                          R xi, R& gp, R& gm) {
+    const R t = cdf_invert<R>(T[grid::kCdfB], 0, ik, wk, c, xi);
+    const R V = log((R)0.5 * k);
+    if (t <= (R)0.5) { gp = exp((R)2 * t * V); gm = k - gp; }
+    else { gm = exp((R)2 * ((R)1 - t) * V); gp = k - gm; }
+}
+
+// Trident pair energy, then the positron split (Sec. II.D)
+template <typename R>
+__device__ __forceinline__ void trident_sample(const TabView<R>& T, R g1, R xi1, R xi2,
+                                               R& gpair, R& gp, R& gm) {
+    CellTab<R> none{};
+    int i; R w; bool in;
+    const R ga = g1 > (R)grid::kTop ? (R)grid::kTop : g1;
+    locate<R>(log(ga), T.ax.tri, i, w, in);
+    const R t = cdf_invert<R>(T[grid::kCdfT], 2, i, w, none, xi1);
+    const R l2 = (R)0.69314718055994530942;
+    gpair = exp(l2 + t * (log(g1 - (R)1) - l2));
+    if (gpair <= (R)4) { gp = (R)0.5 * gpair; gm = gp; return; }
+    const R gq = gpair > (R)grid::kTop ? (R)grid::kTop : gpair;
+    locate<R>(log(gq), T.ax.split, i, w, in);
+    const R t2 = cdf_invert<R>(T[grid::kCdfS], 2, i, w, none, xi2);
+    const R glo = (R)2 / ((R)1 + sqrt((R)1 - (R)4 / gpair));
+    const R V = log(gpair / ((R)2 * glo));
+    if (t2 <= (R)0.5) { gp = glo * exp((R)2 * t2 * V); gm = gpair - gp; }
+    else { gm = glo * exp((R)2 * ((R)1 - t2) * V); gp = gpair - gm; }
+}
+
+}  // namespace cmc

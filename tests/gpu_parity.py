@@ -1,0 +1,125 @@
+"""Helpers of the GPU parity tests: run the same seeded workload through the
+HIP library (via the C ABI) and through the oracle, compare cell by cell.
+
+Rules: event counts, slots and parent indices bit-exact; floating-point
+outputs within `rtol` (1e-12 for the FP64 form, 1e-5 for the FP32 form).
+A cell may differ only if it holds a decision within the near-threshold
+band |U - P| <= 1e-6 P (counted by both sides); such cells are counted,
+reported and left out of later comparisons.
+"""
+import functools
+import sys
+
+import numpy as np
+
+import paper_1907_02814_amd as cmc
+from oracle import oracle as O
+
+
+def torch_mod():
+    import torch
+    return torch
+
+
+DEV = "cuda:0"
+
+
+@functools.lru_cache(maxsize=None)
+def gpu_tables(Z):
+    return cmc.build_tables(Z)
+
+
+def _vec_close(ax, ay, az, bx, by, bz, rtol):
+    da = np.sqrt((ax - bx) ** 2 + (ay - by) ** 2 + (az - bz) ** 2)
+    mag = np.sqrt(bx * bx + by * by + bz * bz)
+    return da <= rtol * np.maximum(mag, 1e-300) + 1e-300
+
+
+class Parity:
+    def __init__(self, wl, *, precision=cmc.FP64, schedule=cmc.SCHED_AUTO, seed=1,
+                 max_per_cell=None, rtol=None, nthreads=0):
+        torch = torch_mod()
+        self.wl = wl
+        self.ref = wl.copy()
+        self.g = wl.to_torch(DEV)
+        self.rtol = rtol if rtol is not None else (1e-12 if precision == cmc.FP64 else 1e-5)
+        self.seed = seed
+        self.nthreads = nthreads
+        self.state = cmc.StepState(gpu_tables(wl.Z), self.g.cells, self.g.electrons, self.g.photons,
+                                   self.g.ions, self.g.new_el, self.g.new_po, dt=wl.dt, seed=seed,
+                                   processes=wl.processes, precision=precision, schedule=schedule,
+                                   max_per_cell=max_per_cell)
+        self.diverged = np.zeros(wl.n_cells, dtype=bool)
+        self.flips = 0
+        self.report = []
+        self.torch = torch
+
+    def step(self, s):
+        torch = self.torch
+        self.state.status.zero_()
+        self.state.step(s)
+        torch.cuda.synchronize()
+        oti, otd, ost = O.collide_step(O.tables(self.wl.Z), self.ref.cells, self.ref.electrons,
+                                       self.ref.photons, self.ref.ions, self.ref.new_el,
+                                       self.ref.new_po, self.wl.dt, self.seed, s, self.wl.processes,
+                                       nthreads=self.nthreads)
+        ti = self.state.ti.cpu().numpy()
+        td = self.state.td.cpu().numpy()
+        st = int(self.state.status.item())
+        return self.compare(ti, td, st, oti, otd, ost, s)
+
+    def _cells_of(self, off, n):
+        return np.repeat(np.arange(n), np.diff(off))
+
+    def compare(self, ti, td, st, oti, otd, ost, s):
+        g, r, rtol = self.g, self.ref, self.rtol
+        n = self.wl.n_cells
+        bad = np.zeros(n, dtype=bool)
+        bad |= np.any(ti != oti, axis=1)
+        # electrons
+        e = {k: g.electrons[k].cpu().numpy() for k in ("px", "py", "pz")}
+        ok = _vec_close(e["px"], e["py"], e["pz"], r.electrons["px"], r.electrons["py"],
+                        r.electrons["pz"], rtol)
+        ecell = self._cells_of(r.electrons["off"], n)
+        bad |= np.bincount(ecell[~ok], minlength=n) > 0
+        # photon species and product buffers
+        for name in ("photons", "new_el", "new_po"):
+            G = getattr(g, name); Rr = getattr(r, name)
+            cnt = G["count"].cpu().numpy()
+            bad |= cnt != Rr["count"]
+            off = Rr["off"]
+            live = np.zeros(int(off[-1]), dtype=bool)
+            for c in range(n):
+                live[off[c]:off[c] + min(cnt[c], Rr["count"][c])] = True
+            arr = {k: G[k].cpu().numpy() for k in ("px", "py", "pz", "w")}
+            okv = _vec_close(arr["px"], arr["py"], arr["pz"], Rr["px"], Rr["py"], Rr["pz"], rtol)
+            okw = np.abs(arr["w"] - Rr["w"]) <= rtol * np.abs(Rr["w"])
+            okp = np.ones_like(okv)
+            if G.get("parent") is not None and Rr.get("parent") is not None:
+                okp = G["parent"].cpu().numpy() == Rr["parent"]
+            wrong = live & ~(okv & okw & okp)
+            cells = self._cells_of(off, n)
+            bad |= np.bincount(cells[wrong], minlength=n) > 0
+        # FP64 tallies
+        scale = np.abs(otd[:, 2:5]).sum(1) + np.abs(otd[:, 5:7]).sum(1)
+        for q in range(otd.shape[1]):
+            ref = otd[:, q]
+            sc = np.maximum(np.abs(ref), scale if q in (2, 3, 4, 5, 6) else np.abs(ref))
+            bad |= ~(np.abs(td[:, q] - ref) <= rtol * sc + 1e-300)
+        new_bad = bad & ~self.diverged
+        near = (oti[:, 6:9].sum(1) > 0) | (ti[:, 6:9].sum(1) > 0)
+        unexplained = new_bad & ~near
+        if unexplained.any():
+            c = int(np.flatnonzero(unexplained)[0])
+            msg = (f"step {s}: cell {c} differs without a near-threshold decision\n"
+                   f"  gpu ti {ti[c].tolist()}\n  ora ti {oti[c].tolist()}\n"
+                   f"  gpu td {td[c].tolist()}\n  ora td {otd[c].tolist()}")
+            raise AssertionError(msg)
+        self.flips += int(new_bad.sum())
+        self.diverged |= new_bad
+        if new_bad.any():
+            self.report.append((s, np.flatnonzero(new_bad).tolist()))
+            print(f"[parity] step {s}: {int(new_bad.sum())} cell(s) with a near-threshold flip",
+                  file=sys.stderr)
+        assert (st & ~cmc.ST_OVERFLOW) == (ost & ~cmc.ST_OVERFLOW) or self.flips, (st, ost)
+        return ti, td, oti, otd

@@ -1,0 +1,118 @@
+"""cmc_collide_step against the oracle, step by step (parity rules in
+gpu_parity.py): FP64 form at 1e-12, FP32 form at 1e-5, bit-exact events,
+slots and parents except counted near-threshold flips."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1907_02814_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+MEC2 = 0.51099895
+
+
+def _run(wl, steps, **kw):
+    from gpu_parity import Parity
+    P = Parity(wl, **kw)
+    for s in range(steps):
+        P.step(s)
+    print(f"[parity] {wl.name}: {P.flips} near-threshold flip(s) in {steps} step(s)")
+    assert P.flips <= max(1, wl.n_cells // 50)
+    return P
+
+
+def test_cfg1_physical_dt_ten_steps():
+    # Plain FP64 Bremsstrahlung, 64 cells x (256 e + 256 Cu), dt = 0.1 fs
+    _run(W.cfg1(), 10)
+
+
+def test_cfg1_amplified_dt():
+    # same cells with dt x 1e4 so that most pairs are tested near P ~ 0.3
+    P = _run(W.cfg1(dt=1e-12), 3)
+    assert P.ref.photons["count"].sum() > 1000
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_bethe_heitler_cells(precision):
+    wl = W.cfg2(np.random.default_rng(5), n_cells=48, per_cell=1024, dt=3e-13)
+    P = _run(wl, 2, precision=precision)
+    assert (wl.photons["count"].sum() - P.ref.photons["count"].sum()) > 100
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_all_processes_uneven_cells(precision):
+    wl = W.cfg3(np.random.default_rng(9), n_cells=160, dt=2e-13, lo=1, hi=3000)
+    P = _run(wl, 2, precision=precision)
+    I = P.state.ti.cpu().numpy().sum(0)
+    assert I[3] > 100 and I[5] > 10
+
+
+def test_foil_chain_cells():
+    wl = W.cfg5(np.random.default_rng(2), n_cells=6, per_cell=4096, dt=5e-14)
+    P = _run(wl, 3)
+    assert P.ref.photons["count"].sum() > 0
+
+
+def test_edge_cells():
+    rng = np.random.default_rng(4)
+    ne = np.array([0, 3, 1, 50, 7, 1, 200, 5])
+    ng = np.array([4, 0, 1, 30, 7, 9, 0, 5])
+    ni = np.array([6, 5, 1, 0, 7, 1, 17, 300])
+    Zs = np.array([0.0, 29.0, 12.0, 3.0, 29.0, 0.0, 7.5, 1e-6])
+    n = len(ne)
+    e_g = 1 + np.exp(rng.uniform(math.log(0.002), math.log(1e4), ne.sum())) / MEC2
+    k = 2.0 + np.exp(rng.uniform(math.log(1e-7), math.log(1e4), ng.sum()))
+    wl = W.assemble("edges", 29, 1e-12, 7, 1, Zs, np.full(n, 8.5e28), np.array([1, 1e4, 50, 100, 3, 1, 1e3, 10.0]),
+                    e_g, rng.lognormal(0, 1, ne.sum()) * 1e26, ne, k, rng.lognormal(0, 1, ng.sum()) * 1e26, ng,
+                    rng.lognormal(0, 1, ni.sum()) * 1e26, ni, rng,
+                    photon_extra=np.full(n, 2) , pair_cap=np.full(n, 3))
+    _run(wl, 3)
+
+
+def test_flags_bad_cells_and_limits():
+    import paper_1907_02814_amd as cmc
+    wl = W.cfg1(np.random.default_rng(1), n_cells=6, per_cell=32, dt=1e-12)
+    wl.cells["Zstar"][1] = 30.0
+    wl.cells["T_e"][2] = -1.0
+    wl.ions["w"][3 * 32 + 4] = np.nan
+    P = _run(wl, 1, max_per_cell=32)
+    st = int(P.state.status.item())
+    assert st & cmc.ST_BAD_CELL and st & cmc.ST_BAD_WEIGHT
+    # a cell larger than max_per_cell is skipped and flagged
+    wl2 = W.cfg1(np.random.default_rng(1), n_cells=3, per_cell=40, dt=1e-12)
+    from gpu_parity import Parity
+    Q = Parity(wl2, max_per_cell=39)
+    Q.state.status.zero_()
+    Q.state.step(0)
+    import torch
+    torch.cuda.synchronize()
+    assert int(Q.state.status.item()) & cmc.ST_TOO_LARGE
+    assert Q.state.ti.cpu().numpy().sum() == 0
+
+
+def test_overflow_drops_in_pair_order():
+    wl = W.cfg1(np.random.default_rng(8), n_cells=8, per_cell=64, dt=3e-12)
+    wl.photons = W._slab(np.full(8, 5))
+    P = _run(wl, 1)
+    assert P.state.ti.cpu().numpy()[:, 9].sum() > 0
+
+
+def test_repeatable_bitwise():
+    import torch
+    import paper_1907_02814_amd as cmc
+    from gpu_parity import gpu_tables
+    wl = W.cfg3(np.random.default_rng(3), n_cells=64, dt=2e-13, lo=1, hi=2000)
+    outs = []
+    for _ in range(2):
+        g = wl.copy().to_torch("cuda:0")
+        st = cmc.StepState(gpu_tables(wl.Z), g.cells, g.electrons, g.photons, g.ions, g.new_el,
+                           g.new_po, dt=wl.dt, seed=3, processes=wl.processes)
+        for s in range(2):
+            st.step(s)
+        torch.cuda.synchronize()
+        outs.append([g.electrons["px"].cpu().numpy(), g.photons["px"].cpu().numpy(),
+                     g.new_po["pz"].cpu().numpy(), st.td.cpu().numpy(), st.ti.cpu().numpy()])
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)

@@ -177,14 +177,18 @@ def test_energy_and_weight_conservation_per_event(proc, dt, need):
     I = {n: ti[:, i] for i, n in enumerate(O.I_NAMES)}
     assert I["ev_br"].sum() >= need[0] and I["ev_bh"].sum() >= need[1] and I["ev_tr"].sum() >= need[2]
     scale = max(np.abs(D["E_br"]).max(), np.abs(D["E_tr"]).max(), np.abs(D["E_bh"]).max())
-    # electron energy lost = photon energy + pair energy (ions at rest)
-    np.testing.assert_allclose(D["E_br"] + D["E_tr"] + D["dE_el"], 0.0, atol=1e-12 * scale)
+    # electron energy lost = photon energy + pair energy (ions at rest), per cell
+    np.testing.assert_allclose(D["E_br"] + D["E_tr"] + D["dE_el"], 0.0,
+                               atol=1e-13 * (D["E_br"] + D["E_tr"]).max())
+    assert np.all(np.abs(D["E_br"] + D["E_tr"] + D["dE_el"]) <= 1e-13 * (D["E_br"] + D["E_tr"]) + 1e-300)
     # photon energy converted = pair energy
     np.testing.assert_allclose(D["E_bh"] + D["dE_ph"], 0.0, atol=1e-12 * scale)
     g1 = np.sqrt(1 + wl.electrons["px"] ** 2 + wl.electrons["py"] ** 2 + wl.electrons["pz"] ** 2)
     We = wl.electrons["w"]
-    np.testing.assert_allclose((We * (g1 - g0)).reshape(n_cells, ne).sum(1), D["dE_el"], rtol=1e-10,
-                               atol=1e-12 * scale)
+    # the same change from the momenta: the difference of two Lorentz factors
+    # carries a rounding error of a few ulp of gamma per electron
+    slack = (We * g0).reshape(n_cells, ne).sum(1) * 1e-14
+    assert np.all(np.abs((We * (g1 - g0)).reshape(n_cells, ne).sum(1) - D["dE_el"]) <= slack)
     assert np.all(g1 >= 1.0)
     # e+ weight equals e- weight, products counted exactly
     ne_cnt, np_cnt = wl.new_el["count"], wl.new_po["count"]
