@@ -786,15 +786,19 @@ static double cdf_at(const cdfsel* c, int j)
     }
 }
 
-static double cdf_invert(const cdfsel* c, double xi)
+/* Returns t and, in *ct, 1 - t evaluated from F_hi - xi, which keeps its
+ * relative precision near the top of the row (the spectrum tip, where the
+ * product's gamma - 1 is small). */
+static double cdf_invert(const cdfsel* c, double xi, double* ct)
 {
     int lo = 0, hi = M_CDF;
     while (hi - lo > 1) {
         int mid = (lo + hi) / 2;
         if (cdf_at(c, mid) <= xi) lo = mid; else hi = mid;
     }
-    double Flo = cdf_at(c, lo), Fhi = cdf_at(c, hi);
-    return (lo + (xi - Flo) / (Fhi - Flo)) / M_CDF;
+    double Flo = cdf_at(c, lo), Fhi = cdf_at(c, hi), d = Fhi - Flo;
+    *ct = ((M_CDF - hi) + (Fhi - xi) / d) / M_CDF;
+    return (lo + (xi - Flo) / d) / M_CDF;
 }
 
 /* Bremsstrahlung photon energy, Sec. III.A: t from the blended CDF, then
@@ -806,43 +810,48 @@ static void brems_sample(const or_tables* tb, const cellstate* s, const brems_lo
     c.s = s; c.i = L->ig; c.w = L->wg;
     if (L->seg == SEG_NR) { c.T = tb->cN; c.kind = 1; }
     else { c.T = L->seg == SEG_R ? tb->cR : tb->cU; c.kind = 0; }
-    double t = cdf_invert(&c, xi);
-    double ga = g1, gam1 = g1m1;
-    double Y = brems_yrange(ga, gam1);
-    double dl = L->seg == SEG_NR ? (1.0 - t) * (1.0 - t) * Y : (1.0 - t) * Y;
-    brems_kin(ga, gam1, dl, k, g2, g2m1);
+    double ct;
+    cdf_invert(&c, xi, &ct);
+    double Y = brems_yrange(g1, g1m1);
+    double dl = L->seg == SEG_NR ? ct * ct * Y : ct * Y;
+    brems_kin(g1, g1m1, dl, k, g2, g2m1);
 }
 
 static void bh_sample(const or_tables* tb, const cellstate* s, double k, int ik, double wk,
                       double xi, double* gp, double* gm)
 {
     cdfsel c; c.T = tb->cB; c.kind = 0; c.i = ik; c.w = wk; c.s = s;
-    double t = cdf_invert(&c, xi);
+    double ct, t = cdf_invert(&c, xi, &ct);
     double V = log(0.5 * k);
     if (t <= 0.5) { *gp = exp(2.0 * t * V); *gm = k - *gp; }
-    else          { *gm = exp(2.0 * (1.0 - t) * V); *gp = k - *gm; }
+    else          { *gm = exp(2.0 * ct * V); *gp = k - *gm; }
 }
 
-static void trident_sample(const or_tables* tb, double g1, double xi1, double xi2,
-                           double* gpair, double* gp, double* gm)
+/* Trident: pair energy on [2, g1 - 1] in ln g_pair, then the positron
+ * split; *gfm1 = g1 - 1 - g_pair, the electron's kinetic energy left,
+ * from the complement of the abscissa (no cancellation at the tip). */
+static void trident_sample(const or_tables* tb, double g1, double g1m1, double xi1, double xi2,
+                           double* gpair, double* gp, double* gm, double* gfm1)
 {
     cdfsel c; c.s = NULL; c.kind = 2;
     int in;
     double ga = g1 > GMAX ? GMAX : g1;
     c.T = tb->cT;
     axis_pos(log(ga), log(3.0), log(GMAX), N_T, &c.i, &c.w, &in);
-    double t = cdf_invert(&c, xi1);
-    *gpair = exp(log(2.0) + t * (log(g1 - 1.0) - log(2.0)));
+    double ct, t = cdf_invert(&c, xi1, &ct);
+    double Lg = log(g1m1) - log(2.0);
+    *gpair = exp(log(2.0) + t * Lg);
+    *gfm1 = -g1m1 * expm1(-ct * Lg);
     if (*gpair <= 4.0) { *gp = 0.5 * (*gpair); *gm = *gp; return; }
     double gq = *gpair > GMAX ? GMAX : *gpair;
     c.T = tb->cS;
     axis_pos(log(gq), log(4.0), log(GMAX), N_S, &c.i, &c.w, &in);
-    double t2 = cdf_invert(&c, xi2);
+    double ct2, t2 = cdf_invert(&c, xi2, &ct2);
     double q = 1.0 - 4.0 / (*gpair);
     double glo = 2.0 / (1.0 + sqrt(q));
     double V = log(*gpair / (2.0 * glo));
     if (t2 <= 0.5) { *gp = glo * exp(2.0 * t2 * V); *gm = *gpair - *gp; }
-    else           { *gm = glo * exp(2.0 * (1.0 - t2) * V); *gp = *gpair - *gm; }
+    else           { *gm = glo * exp(2.0 * ct2 * V); *gp = *gpair - *gm; }
 }
 
 /* process ids of or_lookup / or_sample: 1 Brems, 2 BH, 4 Trident */
@@ -884,8 +893,8 @@ int or_sample(const or_tables* t, double Zs, double ni, double T, double e1, int
         bh_sample(t, &s, e1, ik, wk, xi1, &out[0], &out[1]);
     } else if (process == OR_TRIDENT) {
         if (!(e1 > 3.0)) return 1;
-        double gpair, gp, gm;
-        trident_sample(t, e1, xi1, xi2, &gpair, &gp, &gm);
+        double gpair, gp, gm, gfm1;
+        trident_sample(t, e1, (e1 * e1 - 1.0) / (e1 + 1.0), xi1, xi2, &gpair, &gp, &gm, &gfm1);
         out[0] = gp; out[1] = gm;
     } else return 1;
     return 0;
@@ -1171,9 +1180,9 @@ static int32_t cell_step(const stepctx* X, const or_cells* cells, int64_t c, int
                 } else {
                     /* Trident: pair energy, then the positron split; the pair
                      * travels along the electron, which loses g_pair (reading) */
-                    double gpair, gpl, gmi;
-                    trident_sample(tb, gp, xi1, xi2, &gpair, &gpl, &gmi);
-                    double gfm1 = gpm1 - gpair, gf = gfm1 + 1.0;
+                    double gpair, gpl, gmi, gfm1;
+                    trident_sample(tb, gp, gpm1, xi1, xi2, &gpair, &gpl, &gmi, &gfm1);
+                    double gf = gfm1 + 1.0;
                     double pf = sqrt(gfm1 * (gf + 1.0));
                     double pplus = sqrt((gpl - 1.0) * (gpl + 1.0)), pminus = sqrt((gmi - 1.0) * (gmi + 1.0));
                     double qe[3], qp[3], qm[3];

@@ -352,39 +352,41 @@ __global__ __launch_bounds__(kThreads) void k_collide(StepArgs A, TabView<R> T) 
                             if (fabs(U1 - P) <= A.near_rel * P) t.near[proc]++;
                             if (!(U1 < P && U2 < Pej)) continue;
                             const U4 q = A.rng.draw((uint32_t)j, cell, proc == 0 ? kTagSmpBr : kTagSmpTr);
-                            const R xi1 = (R)u53(q.x, q.y), xi2 = (R)u53(q.z, q.w);
+                            const double xi1 = u53(q.x, q.y), xi2 = u53(q.z, q.w);
                             t.ev[proc]++;
                             moved = true;
+                            // event kinematics in FP64 from the stored momentum
+                            const double p2d = px * px + py * py + pz * pz;
+                            const double gd = sqrt(1.0 + p2d), gm1d = p2d / (gd + 1.0), pmd = sqrt(p2d);
                             if (proc == 0) {
-                                R k, g2, g2m1;
-                                brems_sample<R>(T, ct, BL, g, gm1, xi1, k, g2, g2m1);
-                                const R pf = sqrt(g2m1 * (g2 + (R)1));
-                                const R f = pf / pm, h = k / pm;
-                                const R qx = rpx * f, qy = rpy * f, qz = rpz * f;
-                                kx = (double)(rpx * h); ky = (double)(rpy * h); kz = (double)(rpz * h);
-                                px = (double)qx; py = (double)qy; pz = (double)qz;
+                                double k, g2, g2m1;
+                                brems_sample<R>(T, ct, BL, gd, gm1d, xi1, k, g2, g2m1);
+                                const double pf = sqrt(g2m1 * (g2 + 1.0));
+                                const double f = pf / pmd, h = k / pmd;
+                                kx = px * h; ky = py * h; kz = pz * h;
+                                px *= f; py *= f; pz *= f;
                                 const double kl = sqrt(kx * kx + ky * ky + kz * kz);
                                 t.E_br += We * kl;
                                 // electron energy change = -k exactly (ions at rest); the
                                 // difference of two Lorentz factors would cancel for k << gamma
-                                t.dE_el += We * (-(double)k);
+                                t.dE_el += We * (-k);
                                 t.W_br += We;
                                 f_ph = true;
                             } else {
-                                R gpair, gpl, gmi;
-                                trident_sample<R>(T, g, xi1, xi2, gpair, gpl, gmi);
-                                const R gfm1 = gm1 - gpair, gf = gfm1 + (R)1;
-                                const R pf = sqrt(gfm1 * (gf + (R)1));
-                                const R pplus = sqrt((gpl - (R)1) * (gpl + (R)1));
-                                const R pminus = sqrt((gmi - (R)1) * (gmi + (R)1));
-                                const R f = pf / pm, fp = pplus / pm, fm = pminus / pm;
-                                px = (double)(rpx * f); py = (double)(rpy * f); pz = (double)(rpz * f);
-                                pxp = (double)(rpx * fp); pyp = (double)(rpy * fp); pzp = (double)(rpz * fp);
-                                pxm = (double)(rpx * fm); pym = (double)(rpy * fm); pzm = (double)(rpz * fm);
+                                double gpair, gpl, gmi, gfm1;
+                                trident_sample<R>(T, gd, gm1d, xi1, xi2, gpair, gpl, gmi, gfm1);
+                                const double gf = gfm1 + 1.0;
+                                const double pf = sqrt(gfm1 * (gf + 1.0));
+                                const double pplus = sqrt((gpl - 1.0) * (gpl + 1.0));
+                                const double pminus = sqrt((gmi - 1.0) * (gmi + 1.0));
+                                const double f = pf / pmd, fp = pplus / pmd, fm = pminus / pmd;
+                                pxp = px * fp; pyp = py * fp; pzp = pz * fp;
+                                pxm = px * fm; pym = py * fm; pzm = pz * fm;
+                                px *= f; py *= f; pz *= f;
                                 const double gpl_l = sqrt(1.0 + pxp * pxp + pyp * pyp + pzp * pzp);
                                 const double gmi_l = sqrt(1.0 + pxm * pxm + pym * pym + pzm * pzm);
                                 t.E_tr += We * (gpl_l + gmi_l);
-                                t.dE_el += We * (-(double)gpair);
+                                t.dE_el += We * (-gpair);
                                 t.W_tr += We;
                                 f_tr = true;
                             }
@@ -471,19 +473,20 @@ __global__ __launch_bounds__(kThreads) void k_collide(StepArgs A, TabView<R> T) 
                                 if (fabs(U1 - P) <= A.near_rel * P) t.near[2]++;
                                 if (U1 < P && U2 < Pej) {
                                     const U4 q = A.rng.draw((uint32_t)j, cell, kTagSmpBh);
-                                    R gpl, gmi;
-                                    bh_sample<R>(T, ct, k, ik, wk, (R)u53(q.x, q.y), gpl, gmi);
-                                    const R pplus = sqrt((gpl - (R)1) * (gpl + (R)1));
-                                    const R pminus = sqrt((gmi - (R)1) * (gmi + (R)1));
-                                    const R fp = pplus / k, fm = pminus / k;
-                                    pxp = (double)(rqx * fp); pyp = (double)(rqy * fp); pzp = (double)(rqz * fp);
-                                    pxm = (double)(rqx * fm); pym = (double)(rqy * fm); pzm = (double)(rqz * fm);
+                                    const double kd = sqrt(qx * qx + qy * qy + qz * qz);
+                                    double gpl, gmi;
+                                    bh_sample<R>(T, ct, kd, ik, wk, u53(q.x, q.y), gpl, gmi);
+                                    const double pplus = sqrt((gpl - 1.0) * (gpl + 1.0));
+                                    const double pminus = sqrt((gmi - 1.0) * (gmi + 1.0));
+                                    const double fp = pplus / kd, fm = pminus / kd;
+                                    pxp = qx * fp; pyp = qy * fp; pzp = qz * fp;
+                                    pxm = qx * fm; pym = qy * fm; pzm = qz * fm;
                                     const double gpl_l = sqrt(1.0 + pxp * pxp + pyp * pyp + pzp * pzp);
                                     const double gmi_l = sqrt(1.0 + pxm * pxm + pym * pym + pzm * pzm);
                                     atomicOr(&S.dead[lg >> 5], 1u << (lg & 31));
                                     t.ev[2]++;
                                     t.E_bh += Wg * (gpl_l + gmi_l);
-                                    t.dE_ph += -Wg * (double)k;
+                                    t.dE_ph += -Wg * kd;
                                     t.W_bh += Wg;
                                     f_bh = true;
                                 }

@@ -148,63 +148,87 @@ __device__ __forceinline__ R cdf_value(const R* T, int kind, int i, R w, const C
 }
 
 // abscissa t in [0, 1] with F(t) = xi for the piecewise-linear blended CDF
+// (values blended in R, xi and the result in FP64); ct = 1 - t is formed
+// from F_hi - xi so that it keeps its relative precision near the top of the
+// row (the spectrum tip, where a product's gamma - 1 is small)
 template <typename R>
-__device__ __forceinline__ R cdf_invert(const R* T, int kind, int i, R w, const CellTab<R>& c, R xi) {
+__device__ __forceinline__ double cdf_invert(const R* T, int kind, int i, R w, const CellTab<R>& c,
+                                             double xi, double& ct) {
     int lo = 0, hi = grid::kPanels;
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
-        if (cdf_value<R>(T, kind, i, w, c, mid) <= xi) lo = mid; else hi = mid;
+        if ((double)cdf_value<R>(T, kind, i, w, c, mid) <= xi) lo = mid; else hi = mid;
     }
-    const R flo = cdf_value<R>(T, kind, i, w, c, lo), fhi = cdf_value<R>(T, kind, i, w, c, hi);
-    return ((R)lo + (xi - flo) / (fhi - flo)) / (R)grid::kPanels;
+    const double flo = (double)cdf_value<R>(T, kind, i, w, c, lo);
+    const double fhi = (double)cdf_value<R>(T, kind, i, w, c, hi);
+    const double d = fhi - flo;
+    ct = ((double)(grid::kPanels - hi) + (fhi - xi) / d) / grid::kPanels;
+    return ((double)lo + (xi - flo) / d) / grid::kPanels;
 }
 
-// Bremsstrahlung photon energy for an electron of (g1, g1m1): returns k and
-// the electron's g2, g2 - 1 after emission (Sec. III.A)
+// Sampling: the row abscissa is found from the blended CDF (table values
+// in R), and the energies follow from it in FP64 (events are rare; near a
+// threshold gamma - 1 << 1 and FP32 would lose the product momenta).
+
+// Bremsstrahlung photon energy k and the electron's g2, g2 - 1 for an
+// electron (g1, g1m1) (Sec. III.A: k' sampled on (10^-7, 1) of the kinetic
+// energy by inversion of the cumulative distribution, g'_ef = g'_e - k').
+// Rows are in y = ln(k/g2); y_hi - y = (1-t) Y, or (1-t)^2 Y on the
+// non-relativistic segment (square-root tip).
 template <typename R>
 __device__ __forceinline__ void brems_sample(const TabView<R>& T, const CellTab<R>& c,
-                                             const BremsLook<R>& L, R g1, R g1m1, R xi,
-                                             R& k, R& g2, R& g2m1) {
+                                             const BremsLook<R>& L, double g1, double g1m1, double xi,
+                                             double& k, double& g2, double& g2m1) {
     const bool nr = L.seg == kSegNR;
     const R* C = T[nr ? grid::kCdfN : (L.seg == kSegRel ? grid::kCdfR : grid::kCdfU)];
-    const R t = cdf_invert<R>(C, nr ? 1 : 0, L.ig, L.wg, c, xi);
-    const R Y = log((g1 - (R)grid::kCut * g1m1) / (R)grid::kCut);
-    const R dl = nr ? ((R)1 - t) * ((R)1 - t) * Y : ((R)1 - t) * Y;
-    const R ey = g1m1 * exp(-dl);
-    g2 = g1 / ((R)1 + ey);
-    g2m1 = g1m1 * (-expm1(-dl)) / ((R)1 + ey);
+    double ct;
+    cdf_invert<R>(C, nr ? 1 : 0, L.ig, L.wg, c, xi, ct);
+    const double Y = log((g1 - grid::kCut * g1m1) / grid::kCut);
+    const double dl = nr ? ct * ct * Y : ct * Y;
+    const double ey = g1m1 * exp(-dl);
+    g2 = g1 / (1.0 + ey);
+    g2m1 = g1m1 * (-expm1(-dl)) / (1.0 + ey);
     k = ey * g2;
 }
 
-// Bethe-Heitler positron / electron energies for photon energy k
+// Bethe-Heitler positron / electron energies for photon energy k (row in
+// ln g+ over the lower half, mirrored)
 template <typename R>
-__device__ __forceinline__ void bh_sample(const TabView<R>& T, const CellTab<R>& c, R k, int ik, R wk,
-                                          R xi, R& gp, R& gm) {
-    const R t = cdf_invert<R>(T[grid::kCdfB], 0, ik, wk, c, xi);
-    const R V = log((R)0.5 * k);
-    if (t <= (R)0.5) { gp = exp((R)2 * t * V); gm = k - gp; }
-    else { gm = exp((R)2 * ((R)1 - t) * V); gp = k - gm; }
+__device__ __forceinline__ void bh_sample(const TabView<R>& T, const CellTab<R>& c, double k, int ik,
+                                          R wk, double xi, double& gp, double& gm) {
+    double ct;
+    const double t = cdf_invert<R>(T[grid::kCdfB], 0, ik, wk, c, xi, ct);
+    const double V = log(0.5 * k);
+    if (t <= 0.5) { gp = exp(2.0 * t * V); gm = k - gp; }
+    else { gm = exp(2.0 * ct * V); gp = k - gm; }
 }
 
-// Trident pair energy, then the positron split (Sec. II.D)
+// Trident (Sec. II.D): pair energy from the g1 row (ln g_pair on
+// [2, g1 - 1]), then the positron split from the g_pair row; gfm1 = the
+// electron's kinetic energy left, g1 - 1 - g_pair, from the complement.
 template <typename R>
-__device__ __forceinline__ void trident_sample(const TabView<R>& T, R g1, R xi1, R xi2,
-                                               R& gpair, R& gp, R& gm) {
+__device__ __forceinline__ void trident_sample(const TabView<R>& T, double g1, double g1m1, double xi1,
+                                               double xi2, double& gpair, double& gp, double& gm,
+                                               double& gfm1) {
     CellTab<R> none{};
     int i; R w; bool in;
-    const R ga = g1 > (R)grid::kTop ? (R)grid::kTop : g1;
-    locate<R>(log(ga), T.ax.tri, i, w, in);
-    const R t = cdf_invert<R>(T[grid::kCdfT], 2, i, w, none, xi1);
-    const R l2 = (R)0.69314718055994530942;
-    gpair = exp(l2 + t * (log(g1 - (R)1) - l2));
-    if (gpair <= (R)4) { gp = (R)0.5 * gpair; gm = gp; return; }
-    const R gq = gpair > (R)grid::kTop ? (R)grid::kTop : gpair;
-    locate<R>(log(gq), T.ax.split, i, w, in);
-    const R t2 = cdf_invert<R>(T[grid::kCdfS], 2, i, w, none, xi2);
-    const R glo = (R)2 / ((R)1 + sqrt((R)1 - (R)4 / gpair));
-    const R V = log(gpair / ((R)2 * glo));
-    if (t2 <= (R)0.5) { gp = glo * exp((R)2 * t2 * V); gm = gpair - gp; }
-    else { gm = glo * exp((R)2 * ((R)1 - t2) * V); gp = gpair - gm; }
+    const double ga = g1 > grid::kTop ? grid::kTop : g1;
+    locate<R>((R)log(ga), T.ax.tri, i, w, in);
+    double ct;
+    const double t = cdf_invert<R>(T[grid::kCdfT], 2, i, w, none, xi1, ct);
+    const double l2 = 0.69314718055994530942;
+    const double Lg = log(g1m1) - l2;
+    gpair = exp(l2 + t * Lg);
+    gfm1 = -g1m1 * expm1(-ct * Lg);
+    if (gpair <= 4.0) { gp = 0.5 * gpair; gm = gp; return; }
+    const double gq = gpair > grid::kTop ? grid::kTop : gpair;
+    locate<R>((R)log(gq), T.ax.split, i, w, in);
+    double ct2;
+    const double t2 = cdf_invert<R>(T[grid::kCdfS], 2, i, w, none, xi2, ct2);
+    const double glo = 2.0 / (1.0 + sqrt(1.0 - 4.0 / gpair));
+    const double V = log(gpair / (2.0 * glo));
+    if (t2 <= 0.5) { gp = glo * exp(2.0 * t2 * V); gm = gpair - gp; }
+    else { gm = glo * exp(2.0 * ct2 * V); gp = gpair - gm; }
 }
 
 }  // namespace cmc

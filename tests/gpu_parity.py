@@ -13,6 +13,7 @@ import sys
 import numpy as np
 
 import paper_1907_02814_amd as cmc
+from paper_1907_02814_amd import D_NAMES
 from oracle import oracle as O
 
 
@@ -29,10 +30,11 @@ def gpu_tables(Z):
     return cmc.build_tables(Z)
 
 
-def _vec_close(ax, ay, az, bx, by, bz, rtol):
+def _vec_rel(ax, ay, az, bx, by, bz):
+    """|a - b|/|b| per particle (0 where both vanish)."""
     da = np.sqrt((ax - bx) ** 2 + (ay - by) ** 2 + (az - bz) ** 2)
     mag = np.sqrt(bx * bx + by * by + bz * bz)
-    return da <= rtol * np.maximum(mag, 1e-300) + 1e-300
+    return np.where(da == 0, 0.0, da / np.maximum(mag, 1e-300))
 
 
 class Parity:
@@ -53,6 +55,7 @@ class Parity:
         self.flips = 0
         self.report = []
         self.torch = torch
+        self.errors = {}
 
     def step(self, s):
         torch = self.torch
@@ -71,47 +74,64 @@ class Parity:
     def _cells_of(self, off, n):
         return np.repeat(np.arange(n), np.diff(off))
 
+    def _note(self, key, err):
+        if err.size:
+            self.errors[key] = max(self.errors.get(key, 0.0), float(np.max(err)))
+
     def compare(self, ti, td, st, oti, otd, ost, s):
         g, r, rtol = self.g, self.ref, self.rtol
         n = self.wl.n_cells
         bad = np.zeros(n, dtype=bool)
-        bad |= np.any(ti != oti, axis=1)
-        # electrons
+        why = {}
+
+        def flag(mask, name):
+            nonlocal bad
+            for c in np.flatnonzero(mask & ~bad):
+                why.setdefault(int(c), name)
+            bad |= mask
+
+        flag(np.any(ti != oti, axis=1), "ti")
+        keep = ~self.diverged
+        # electrons: per-particle relative error of the momentum vector
         e = {k: g.electrons[k].cpu().numpy() for k in ("px", "py", "pz")}
-        ok = _vec_close(e["px"], e["py"], e["pz"], r.electrons["px"], r.electrons["py"],
-                        r.electrons["pz"], rtol)
         ecell = self._cells_of(r.electrons["off"], n)
-        bad |= np.bincount(ecell[~ok], minlength=n) > 0
+        err = _vec_rel(e["px"], e["py"], e["pz"], r.electrons["px"], r.electrons["py"], r.electrons["pz"])
+        self._note("electron p", err[keep[ecell]])
+        flag(np.bincount(ecell[err > rtol], minlength=n) > 0, "electrons")
         # photon species and product buffers
         for name in ("photons", "new_el", "new_po"):
             G = getattr(g, name); Rr = getattr(r, name)
             cnt = G["count"].cpu().numpy()
-            bad |= cnt != Rr["count"]
+            flag(cnt != Rr["count"], name + " count")
             off = Rr["off"]
             live = np.zeros(int(off[-1]), dtype=bool)
             for c in range(n):
                 live[off[c]:off[c] + min(cnt[c], Rr["count"][c])] = True
-            arr = {k: G[k].cpu().numpy() for k in ("px", "py", "pz", "w")}
-            okv = _vec_close(arr["px"], arr["py"], arr["pz"], Rr["px"], Rr["py"], Rr["pz"], rtol)
-            okw = np.abs(arr["w"] - Rr["w"]) <= rtol * np.abs(Rr["w"])
-            okp = np.ones_like(okv)
-            if G.get("parent") is not None and Rr.get("parent") is not None:
-                okp = G["parent"].cpu().numpy() == Rr["parent"]
-            wrong = live & ~(okv & okw & okp)
             cells = self._cells_of(off, n)
-            bad |= np.bincount(cells[wrong], minlength=n) > 0
+            arr = {k: G[k].cpu().numpy() for k in ("px", "py", "pz", "w")}
+            errv = _vec_rel(arr["px"], arr["py"], arr["pz"], Rr["px"], Rr["py"], Rr["pz"])
+            errw = np.abs(arr["w"] - Rr["w"]) / np.maximum(np.abs(Rr["w"]), 1e-300)
+            sel = live & keep[cells]
+            self._note(name + " p", errv[sel]); self._note(name + " w", errw[sel])
+            wrong = live & ((errv > rtol) | (errw > rtol))
+            if G.get("parent") is not None and Rr.get("parent") is not None:
+                wrong |= live & (G["parent"].cpu().numpy() != Rr["parent"])
+            flag(np.bincount(cells[wrong], minlength=n) > 0, name)
         # FP64 tallies
         scale = np.abs(otd[:, 2:5]).sum(1) + np.abs(otd[:, 5:7]).sum(1)
         for q in range(otd.shape[1]):
             ref = otd[:, q]
             sc = np.maximum(np.abs(ref), scale if q in (2, 3, 4, 5, 6) else np.abs(ref))
-            bad |= ~(np.abs(td[:, q] - ref) <= rtol * sc + 1e-300)
+            errq = np.abs(td[:, q] - ref) / np.maximum(sc, 1e-300)
+            self._note("tally " + D_NAMES[q], errq[keep])
+            flag(errq > rtol, "tally " + D_NAMES[q])
         new_bad = bad & ~self.diverged
         near = (oti[:, 6:9].sum(1) > 0) | (ti[:, 6:9].sum(1) > 0)
         unexplained = new_bad & ~near
         if unexplained.any():
             c = int(np.flatnonzero(unexplained)[0])
-            msg = (f"step {s}: cell {c} differs without a near-threshold decision\n"
+            msg = (f"step {s}: cell {c} differs ({why.get(c)}) without a near-threshold decision\n"
+                   f"  errors so far {self.errors}\n"
                    f"  gpu ti {ti[c].tolist()}\n  ora ti {oti[c].tolist()}\n"
                    f"  gpu td {td[c].tolist()}\n  ora td {otd[c].tolist()}")
             raise AssertionError(msg)

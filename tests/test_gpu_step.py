@@ -18,7 +18,8 @@ def _run(wl, steps, **kw):
     P = Parity(wl, **kw)
     for s in range(steps):
         P.step(s)
-    print(f"[parity] {wl.name}: {P.flips} near-threshold flip(s) in {steps} step(s)")
+    print(f"[parity] {wl.name}: {P.flips} near-threshold flip(s) in {steps} step(s); "
+          f"max relative error per output: " + ", ".join(f"{k} {v:.1e}" for k, v in P.errors.items()))
     assert P.flips <= max(1, wl.n_cells // 50)
     return P
 
