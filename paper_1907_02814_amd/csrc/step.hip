@@ -229,7 +229,8 @@ __device__ __forceinline__ int live(const SpeciesDev& s, int64_t c) {
 template <typename R>
 struct CellShared {
     phys::Screen scr;
-    CellTab<R> ct;
+    CellTab<R> ct;          // lookup state of the per-pair path
+    CellTab<double> ct64;   // lookup state of the (rare) event branch
 };
 
 template <typename R>
@@ -247,8 +248,11 @@ __device__ void write_tallies(const StepArgs& A, int64_t c, const Tally& t, long
     }
 }
 
+// R is the arithmetic of the per-pair path (table interpolation of the
+// cross sections, gamma, beta); events sample their energies from the FP64
+// tables T64 in FP64 in both forms.
 template <typename R>
-__global__ __launch_bounds__(kThreads) void k_collide(StepArgs A, TabView<R> T) {
+__global__ __launch_bounds__(kThreads) void k_collide(StepArgs A, TabView<R> T, TabView<double> T64) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double redd[kWaves];
     __shared__ long long redl[kWaves];
@@ -281,6 +285,7 @@ __global__ __launch_bounds__(kThreads) void k_collide(StepArgs A, TabView<R> T) 
             if (tid == 0) {
                 cs.scr = phys::screening(T.Z, Zs, nic, Te);
                 cs.ct = cell_tab<R>(cs.scr, T.ax);
+                cs.ct64 = cell_tab<double>(cs.scr, T.ax);
             }
         }
         const double n_e = block_sum(se, redd), n_g = block_sum(sg, redd), n_I = block_sum(si, redd);
@@ -294,6 +299,7 @@ __global__ __launch_bounds__(kThreads) void k_collide(StepArgs A, TabView<R> T) 
             continue;
         }
         const CellTab<R> ct = cs.ct;
+        const CellTab<double> ct64 = cs.ct64;
         bool high_any = false;
 
         // ---------------------------------------------- electron-ion pass
@@ -359,8 +365,10 @@ __global__ __launch_bounds__(kThreads) void k_collide(StepArgs A, TabView<R> T) 
                             const double p2d = px * px + py * py + pz * pz;
                             const double gd = sqrt(1.0 + p2d), gm1d = p2d / (gd + 1.0), pmd = sqrt(p2d);
                             if (proc == 0) {
+                                bool hi2;
+                                const BremsLook<double> BLd = brems_lookup<double>(T64, ct64, gd, gm1d, hi2);
                                 double k, g2, g2m1;
-                                brems_sample<R>(T, ct, BL, gd, gm1d, xi1, k, g2, g2m1);
+                                brems_sample<double>(T64, ct64, BLd, gd, gm1d, xi1, k, g2, g2m1);
                                 const double pf = sqrt(g2m1 * (g2 + 1.0));
                                 const double f = pf / pmd, h = k / pmd;
                                 kx = px * h; ky = py * h; kz = pz * h;
@@ -374,7 +382,7 @@ __global__ __launch_bounds__(kThreads) void k_collide(StepArgs A, TabView<R> T) 
                                 f_ph = true;
                             } else {
                                 double gpair, gpl, gmi, gfm1;
-                                trident_sample<R>(T, gd, gm1d, xi1, xi2, gpair, gpl, gmi, gfm1);
+                                trident_sample<double>(T64, gd, gm1d, xi1, xi2, gpair, gpl, gmi, gfm1);
                                 const double gf = gfm1 + 1.0;
                                 const double pf = sqrt(gfm1 * (gf + 1.0));
                                 const double pplus = sqrt((gpl - 1.0) * (gpl + 1.0));
@@ -475,7 +483,9 @@ __global__ __launch_bounds__(kThreads) void k_collide(StepArgs A, TabView<R> T) 
                                     const U4 q = A.rng.draw((uint32_t)j, cell, kTagSmpBh);
                                     const double kd = sqrt(qx * qx + qy * qy + qz * qz);
                                     double gpl, gmi;
-                                    bh_sample<R>(T, ct, kd, ik, wk, u53(q.x, q.y), gpl, gmi);
+                                    int ikd; double wkd; bool hi2;
+                                    bh_lookup<double>(T64, ct64, kd, ikd, wkd, hi2);
+                                    bh_sample<double>(T64, ct64, kd, ikd, wkd, u53(q.x, q.y), gpl, gmi);
                                     const double pplus = sqrt((gpl - 1.0) * (gpl + 1.0));
                                     const double pminus = sqrt((gmi - 1.0) * (gmi + 1.0));
                                     const double fp = pplus / kd, fm = pminus / kd;
@@ -674,10 +684,10 @@ extern "C" cmc_status cmc_collide_step(cmc_tables t, const cmc_cells* cells, cmc
     const int grid = grid_for(A.n_cells);
     if (P->precision == CMC_FP64) {
         (void)hipFuncSetAttribute((const void*)k_collide<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-        hipLaunchKernelGGL(k_collide<double>, dim3(grid), dim3(kThreads), shm, st, A, view64(t));
+        hipLaunchKernelGGL(k_collide<double>, dim3(grid), dim3(kThreads), shm, st, A, view64(t), view64(t));
     } else {
         (void)hipFuncSetAttribute((const void*)k_collide<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-        hipLaunchKernelGGL(k_collide<float>, dim3(grid), dim3(kThreads), shm, st, A, view32(t));
+        hipLaunchKernelGGL(k_collide<float>, dim3(grid), dim3(kThreads), shm, st, A, view32(t), view64(t));
     }
     CMC_CHECK_LAUNCH("cmc_collide_step");
     return CMC_OK;
