@@ -16,6 +16,7 @@
 //      compaction; per-cell tallies are reduced in a fixed tree.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "common.hpp"
@@ -92,20 +93,31 @@ __device__ int block_flag_scan(bool f, int* red, int& total) {
     return before + in_wave;
 }
 
-// exclusive scan of n uint32 counters in LDS (n <= 64 * kThreads)
+// inclusive prefix sum of a uint32 over the workgroup (thread order)
+__device__ __forceinline__ uint32_t block_incl_scan_u32(uint32_t v, uint32_t* red) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t u = __shfl_up(v, o, 64);
+        if (lane >= o) v += u;
+    }
+    if (lane == 63) red[w] = v;
+    __syncthreads();
+    uint32_t before = 0;
+#pragma unroll
+    for (int i = 0; i < kWaves; ++i) if (i < w) before += red[i];
+    __syncthreads();
+    return v + before;
+}
+
+// exclusive scan of n uint32 counters in LDS (n <= 64 * kThreads), in place
 __device__ void block_excl_scan_u32(uint32_t* a, int n, uint32_t* red) {
     const int per = (n + kThreads - 1) / kThreads;
     const int lo = threadIdx.x * per, hi = min(n, lo + per);
     uint32_t s = 0;
     for (int i = lo; i < hi; ++i) s += a[i];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t run = 0;
-        for (int i = 0; i < kThreads; ++i) { const uint32_t v = red[i]; red[i] = run; run += v; }
-    }
-    __syncthreads();
-    uint32_t run = red[threadIdx.x];
+    const uint32_t incl = block_incl_scan_u32(s, red);
+    uint32_t run = incl - s;
     for (int i = lo; i < hi; ++i) { const uint32_t v = a[i]; a[i] = run; run += v; }
     __syncthreads();
 }
@@ -210,15 +222,16 @@ struct StepArgs {
     int64_t* ti;
     double* td;
     int32_t* status;
+    const int32_t* only_slow;   // non-NULL: process only cells flagged for the sequential path
 };
 
+// per-thread tallies (scalars: no dynamically indexed local arrays)
 struct Tally {
-    long long pairs[3], ev[3], near[3], drop[3];
+    long long pairs_br, pairs_tr, pairs_bh, ev_br, ev_tr, ev_bh, near_br, near_tr, near_bh;
+    long long drop_ph, drop_el, drop_po;
     double E_br, E_tr, E_bh, dE_el, dE_ph, W_br, W_tr, W_bh;
 };
 
-// live particles of cell c, clamped to the segment so that an inconsistent
-// count can never address outside the cell
 __device__ __forceinline__ int live(const SpeciesDev& s, int64_t c) {
     const int cap = (int)(s.off[c + 1] - s.off[c]);
     if (!s.count) return cap;
@@ -233,19 +246,45 @@ struct CellShared {
     CellTab<double> ct64;   // lookup state of the (rare) event branch
 };
 
-template <typename R>
-__device__ void write_tallies(const StepArgs& A, int64_t c, const Tally& t, long long* redl, double* redd) {
-    long long iv[CMC_NI] = {t.pairs[0], t.pairs[1], t.pairs[2], t.ev[0], t.ev[1], t.ev[2],
-                            t.near[0], t.near[1], t.near[2], t.drop[0], t.drop[1], t.drop[2]};
-    for (int q = 0; q < CMC_NI; ++q) {
-        const long long s = block_sum_ll(iv[q], redl);
-        if (threadIdx.x == 0) A.ti[c * CMC_NI + q] = s;
+// all tallies of the cell reduced in one pass: wave butterflies, then the
+// waves' partials summed in wave order by one thread (fixed shape)
+__device__ void write_tallies(const StepArgs& A, int64_t c, const Tally& t, double nab_ei,
+                              double nab_gi, long long* redl, double* redd) {
+    long long iv[CMC_NI] = {t.pairs_br, t.pairs_tr, t.pairs_bh, t.ev_br, t.ev_tr, t.ev_bh,
+                            t.near_br, t.near_tr, t.near_bh, t.drop_ph, t.drop_el, t.drop_po};
+    double dv[8] = {t.E_br, t.E_tr, t.E_bh, t.dE_el, t.dE_ph, t.W_br, t.W_tr, t.W_bh};
+#pragma unroll
+    for (int q = 0; q < CMC_NI; ++q)
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) iv[q] += __shfl_xor(iv[q], o, 64);
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) dv[q] += __shfl_xor(dv[q], o, 64);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int q = 0; q < CMC_NI; ++q) redl[w * CMC_NI + q] = iv[q];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) redd[w * 8 + q] = dv[q];
     }
-    const double dv[8] = {t.E_br, t.E_tr, t.E_bh, t.dE_el, t.dE_ph, t.W_br, t.W_tr, t.W_bh};
-    for (int q = 0; q < 8; ++q) {
-        const double s = block_sum(dv[q], redd);
-        if (threadIdx.x == 0) A.td[c * CMC_ND + CMC_D_E_BR + q] = s;
+    __syncthreads();
+    const int q = threadIdx.x;
+    if (q < CMC_NI) {
+        long long s = 0;
+        for (int i = 0; i < kWaves; ++i) s += redl[i * CMC_NI + q];
+        A.ti[c * CMC_NI + q] = s;
+    } else if (q < CMC_NI + 8) {
+        const int r = q - CMC_NI;
+        double s = redd[r];
+        for (int i = 1; i < kWaves; ++i) s += redd[i * 8 + r];
+        A.td[c * CMC_ND + CMC_D_E_BR + r] = s;
+    } else if (q == CMC_NI + 8) {
+        A.td[c * CMC_ND + CMC_D_NAB_EI] = nab_ei;
+        A.td[c * CMC_ND + CMC_D_NAB_GI] = nab_gi;
     }
+    __syncthreads();
 }
 
 // R is the arithmetic of the per-pair path (table interpolation of the
@@ -254,15 +293,16 @@ __device__ void write_tallies(const StepArgs& A, int64_t c, const Tally& t, long
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_collide(StepArgs A, TabView<R> T, TabView<double> T64) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ double redd[kWaves];
-    __shared__ long long redl[kWaves];
+    __shared__ double redd[kWaves * 8];
+    __shared__ long long redl[kWaves * CMC_NI];
     __shared__ int redi[kWaves];
-    __shared__ uint32_t redu[kThreads];
+    __shared__ uint32_t redu[kWaves];
     __shared__ CellShared<R> cs;
     const Smem S = carve(smem_raw, A.maxn);
     const int tid = threadIdx.x;
 
     for (int64_t c = blockIdx.x; c < A.n_cells; c += gridDim.x) {
+        if (A.only_slow && !(A.only_slow[c] & 1)) continue;
         const uint32_t cell = (uint32_t)c;
         const int Ne = live(A.el, c), Ng0 = live(A.ph, c), Ni = live(A.io, c);
         const int64_t e0 = A.el.off[c], g0 = A.ph.off[c], i0 = A.io.off[c];
@@ -293,9 +333,7 @@ __global__ __launch_bounds__(kThreads) void k_collide(StepArgs A, TabView<R> T, 
         double nab_ei = 0.0, nab_gi = 0.0;
         if (skip) {
             if (tid == 0) atomicOr(A.status, st);
-            write_tallies<R>(A, c, t, redl, redd);
-            if (tid == 0) { A.td[c * CMC_ND + CMC_D_NAB_EI] = 0.0; A.td[c * CMC_ND + CMC_D_NAB_GI] = 0.0; }
-            __syncthreads();
+            write_tallies(A, c, t, 0.0, 0.0, redl, redd);
             continue;
         }
         const CellTab<R> ct = cs.ct;
@@ -338,7 +376,7 @@ __global__ __launch_bounds__(kThreads) void k_collide(StepArgs A, TabView<R> T, 
                         for (int proc = 0; proc < 2; ++proc) {
                             const uint32_t bit = proc == 0 ? CMC_BREMS : CMC_TRIDENT;
                             if (!(A.proc & bit)) continue;
-                            t.pairs[proc]++;
+                            if (proc == 0) t.pairs_br++; else t.pairs_tr++;
                             const R rpx = (R)px, rpy = (R)py, rpz = (R)pz;
                             const R p2 = rpx * rpx + rpy * rpy + rpz * rpz;
                             const R g = sqrt((R)1 + p2), gm1 = p2 / (g + (R)1);
@@ -355,18 +393,18 @@ __global__ __launch_bounds__(kThreads) void k_collide(StepArgs A, TabView<R> T, 
                             const double P = -expm1(-x);
                             const U4 r = A.rng.draw((uint32_t)j, cell, proc == 0 ? kTagAccBr : kTagAccTr);
                             const double U1 = u53(r.x, r.y), U2 = u53(r.z, r.w);
-                            if (fabs(U1 - P) <= A.near_rel * P) t.near[proc]++;
+                            if (fabs(U1 - P) <= A.near_rel * P) { if (proc == 0) t.near_br++; else t.near_tr++; }
                             if (!(U1 < P && U2 < Pej)) continue;
                             const U4 q = A.rng.draw((uint32_t)j, cell, proc == 0 ? kTagSmpBr : kTagSmpTr);
                             const double xi1 = u53(q.x, q.y), xi2 = u53(q.z, q.w);
-                            t.ev[proc]++;
+                            if (proc == 0) t.ev_br++; else t.ev_tr++;
                             moved = true;
                             // event kinematics in FP64 from the stored momentum
                             const double p2d = px * px + py * py + pz * pz;
                             const double gd = sqrt(1.0 + p2d), gm1d = p2d / (gd + 1.0), pmd = sqrt(p2d);
                             if (proc == 0) {
                                 bool hi2;
-                                const BremsLook<double> BLd = brems_lookup<double>(T64, ct64, gd, gm1d, hi2);
+                                const BremsLook<double> BLd = brems_lookup<double, false>(T64, ct64, gd, gm1d, hi2);
                                 double k, g2, g2m1;
                                 brems_sample<double>(T64, ct64, BLd, gd, gm1d, xi1, k, g2, g2m1);
                                 const double pf = sqrt(g2m1 * (g2 + 1.0));
@@ -411,7 +449,7 @@ __global__ __launch_bounds__(kThreads) void k_collide(StepArgs A, TabView<R> T, 
                             const int64_t at = g0 + slot;
                             A.ph.px[at] = kx; A.ph.py[at] = ky; A.ph.pz[at] = kz; A.ph.w[at] = We;
                             if (A.ph.parent) A.ph.parent[at] = ie;
-                        } else { t.drop[0]++; }
+                        } else { t.drop_ph++; }
                     }
                     if (f_tr) {
                         const int s1 = cnt_ne + o_tr, s2 = cnt_np + o_tr;
@@ -419,12 +457,12 @@ __global__ __launch_bounds__(kThreads) void k_collide(StepArgs A, TabView<R> T, 
                             const int64_t at = A.ne.off[c] + s1;
                             A.ne.px[at] = pxm; A.ne.py[at] = pym; A.ne.pz[at] = pzm; A.ne.w[at] = We;
                             if (A.ne.parent) A.ne.parent[at] = ie;
-                        } else { t.drop[1]++; }
+                        } else { t.drop_el++; }
                         if (s2 < cap_np) {
                             const int64_t at = A.np.off[c] + s2;
                             A.np.px[at] = pxp; A.np.py[at] = pyp; A.np.pz[at] = pzp; A.np.w[at] = We;
                             if (A.np.parent) A.np.parent[at] = ie;
-                        } else { t.drop[2]++; }
+                        } else { t.drop_po++; }
                     }
                     ph_count = min(cap_ph, ph_count + tot_ph);
                     cnt_ne = min(cap_ne, cnt_ne + tot_tr);
@@ -462,7 +500,7 @@ __global__ __launch_bounds__(kThreads) void k_collide(StepArgs A, TabView<R> T, 
                         if (!dead) {
                             ig = g0 + lg;
                             const int64_t ii = i0 + S.pi[j % Ni];
-                            t.pairs[2]++;
+                            t.pairs_bh++;
                             Wg = A.ph.w[ig];
                             const double Wi = A.io.w[ii];
                             const double Pej = Wi / (Wg > Wi ? Wg : Wi);
@@ -478,7 +516,7 @@ __global__ __launch_bounds__(kThreads) void k_collide(StepArgs A, TabView<R> T, 
                                 const double P = -expm1(-x);
                                 const U4 r = A.rng.draw((uint32_t)j, cell, kTagAccBh);
                                 const double U1 = u53(r.x, r.y), U2 = u53(r.z, r.w);
-                                if (fabs(U1 - P) <= A.near_rel * P) t.near[2]++;
+                                if (fabs(U1 - P) <= A.near_rel * P) t.near_bh++;
                                 if (U1 < P && U2 < Pej) {
                                     const U4 q = A.rng.draw((uint32_t)j, cell, kTagSmpBh);
                                     const double kd = sqrt(qx * qx + qy * qy + qz * qz);
@@ -494,7 +532,7 @@ __global__ __launch_bounds__(kThreads) void k_collide(StepArgs A, TabView<R> T, 
                                     const double gpl_l = sqrt(1.0 + pxp * pxp + pyp * pyp + pzp * pzp);
                                     const double gmi_l = sqrt(1.0 + pxm * pxm + pym * pym + pzm * pzm);
                                     atomicOr(&S.dead[lg >> 5], 1u << (lg & 31));
-                                    t.ev[2]++;
+                                    t.ev_bh++;
                                     t.E_bh += Wg * (gpl_l + gmi_l);
                                     t.dE_ph += -Wg * kd;
                                     t.W_bh += Wg;
@@ -511,12 +549,12 @@ __global__ __launch_bounds__(kThreads) void k_collide(StepArgs A, TabView<R> T, 
                             const int64_t at = A.ne.off[c] + s1;
                             A.ne.px[at] = pxm; A.ne.py[at] = pym; A.ne.pz[at] = pzm; A.ne.w[at] = Wg;
                             if (A.ne.parent) A.ne.parent[at] = ig;
-                        } else { t.drop[1]++; }
+                        } else { t.drop_el++; }
                         if (s2 < cap_np) {
                             const int64_t at = A.np.off[c] + s2;
                             A.np.px[at] = pxp; A.np.py[at] = pyp; A.np.pz[at] = pzp; A.np.w[at] = Wg;
                             if (A.np.parent) A.np.parent[at] = ig;
-                        } else { t.drop[2]++; }
+                        } else { t.drop_po++; }
                     }
                     killed += tot;
                     cnt_ne = min(cap_ne, cnt_ne + tot);
@@ -556,16 +594,479 @@ __global__ __launch_bounds__(kThreads) void k_collide(StepArgs A, TabView<R> T, 
 
         // ---------------------------------------------- counts, tallies
         if (high_any) atomicOr(A.status, CMC_ST_GAMMA_HIGH);
-        const long long dropped = block_sum_ll(t.drop[0] + t.drop[1] + t.drop[2], redl);
+        if (t.drop_ph + t.drop_el + t.drop_po) atomicOr(A.status, CMC_ST_OVERFLOW);
         if (tid == 0) {
             if (A.ph.count) A.ph.count[c] = ph_count;
             A.ne.count[c] = cnt_ne;
             A.np.count[c] = cnt_np;
-            A.td[c * CMC_ND + CMC_D_NAB_EI] = nab_ei;
-            A.td[c * CMC_ND + CMC_D_NAB_GI] = nab_gi;
-            if (dropped) atomicOr(A.status, CMC_ST_OVERFLOW);
         }
-        write_tallies<R>(A, c, t, redl, redd);
+        write_tallies(A, c, t, nab_ei, nab_gi, redl, redd);
+    }
+}
+
+
+// ------------------------------------------------------------------ fast path
+// The step is split in three launches.  k_decide tests every pair of a cell
+// with the particles as they are at the start of the step (loads in storage
+// order, ion weights staged in LDS) and records the events; this is exact
+// whenever no particle reused by a later pair of the same pass changes
+// before that pair, i.e. when every event falls on the last pair of its
+// mobile particle.  k_events then samples the events of such cells in pair
+// order and writes the products.  Cells where that does not hold (or that
+// hold more than kEvCap events) are flagged and run by k_collide, the
+// sequential per-cell kernel above.
+constexpr int kEvCap = 64;
+enum : int32_t { kFlagSlow = 1, kFlagSkip = 2 };
+enum : uint32_t { kEvBr = 1, kEvTrPending = 2, kEvTr = 4, kEvBh = 8 };
+
+struct CellState {
+    CellTab<double> d;
+    CellTab<float> f;
+    int32_t status;                  // CMC_ST_BAD_CELL or 0
+};
+
+struct Work {
+    CellState* cs;
+    int32_t* flags;
+    int32_t* nev;
+    double* dens;                    // n_e, n_gamma, n_ion per cell
+    uint64_t* ev;                    // [n_cells][kEvCap] event records
+};
+
+__host__ __device__ inline size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+__host__ __device__ inline size_t work_bytes(int64_t n) {
+    return align256(sizeof(CellState) * n) + align256(4 * n) + align256(4 * n) + align256(24 * n) +
+           align256(8 * (size_t)n * kEvCap);
+}
+
+inline Work carve_work(void* base, int64_t n) {
+    unsigned char* p = static_cast<unsigned char*>(base);
+    Work w;
+    w.cs = reinterpret_cast<CellState*>(p); p += align256(sizeof(CellState) * n);
+    w.flags = reinterpret_cast<int32_t*>(p); p += align256(4 * n);
+    w.nev = reinterpret_cast<int32_t*>(p); p += align256(4 * n);
+    w.dens = reinterpret_cast<double*>(p); p += align256(24 * n);
+    w.ev = reinterpret_cast<uint64_t*>(p);
+    return w;
+}
+
+__device__ __forceinline__ uint64_t ev_pack(int pass, int j, int mi, int ii, uint32_t kind) {
+    return (uint64_t)(uint32_t)j | ((uint64_t)(uint32_t)mi << 16) | ((uint64_t)(uint32_t)ii << 32) |
+           ((uint64_t)(kind | (uint32_t)pass << 7) << 48);
+}
+__device__ __forceinline__ int ev_j(uint64_t r) { return (int)(r & 0xFFFF); }
+__device__ __forceinline__ int ev_m(uint64_t r) { return (int)((r >> 16) & 0xFFFF); }
+__device__ __forceinline__ int ev_i(uint64_t r) { return (int)((r >> 32) & 0xFFFF); }
+__device__ __forceinline__ uint32_t ev_kind(uint64_t r) { return (uint32_t)(r >> 48) & 0x7F; }
+__device__ __forceinline__ int ev_pass(uint64_t r) { return (int)((r >> 55) & 1); }
+__device__ __forceinline__ uint32_t ev_key(uint64_t r) { return ((uint32_t)ev_pass(r) << 16) | (uint32_t)ev_j(r); }
+
+__global__ void k_cell_state(const double* Zs, const double* ni, const double* Te, int64_t n, double Z,
+                             Axes ax, CellState* out) {
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
+        const double z = Zs[c], d = ni[c], t = Te[c];
+        CellState s = {};
+        if (!(z >= 0.0 && z <= Z && d > 0.0 && t >= 0.0 && isfinite(d) && isfinite(t))) {
+            s.status = CMC_ST_BAD_CELL;
+        } else {
+            const phys::Screen sc = phys::screening(Z, z, d, t);
+            s.d = cell_tab<double>(sc, ax);
+            s.f = cell_tab<float>(sc, ax);
+        }
+        out[c] = s;
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ const CellTab<R>& pick(const CellState& s);
+template <>
+__device__ __forceinline__ const CellTab<double>& pick<double>(const CellState& s) { return s.d; }
+template <>
+__device__ __forceinline__ const CellTab<float>& pick<float>(const CellState& s) { return s.f; }
+
+// LDS of k_decide: keys/inverse (u32), two orders (u16), ion weights (f64)
+__host__ __device__ inline size_t decide_smem_bytes(int maxn) {
+    const size_t n = (size_t)((maxn + 63) / 64 * 64);
+    return n * 4 + n * 2 * 2 + n * 8 + (size_t)smem_buckets(maxn) * 4 + 64;
+}
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_decide(StepArgs A, TabView<R> T, Work W) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double redd[kWaves];
+    __shared__ long long redl[kWaves * CMC_NI];
+    __shared__ double redd8[kWaves * 8];
+    __shared__ int redi[kWaves];
+    __shared__ uint32_t redu[kWaves];
+    __shared__ int evcount, conflict;
+    const size_t nn = (size_t)((A.maxn + 63) / 64 * 64);
+    uint32_t* keys = reinterpret_cast<uint32_t*>(smem_raw);
+    uint16_t* inv = reinterpret_cast<uint16_t*>(smem_raw);           // reuses the key space
+    uint16_t* pm = reinterpret_cast<uint16_t*>(smem_raw + nn * 4);
+    uint16_t* pi = pm + nn;
+    double* wion = reinterpret_cast<double*>(smem_raw + nn * 8);
+    uint32_t* bcnt = reinterpret_cast<uint32_t*>(smem_raw + nn * 16);
+    const int tid = threadIdx.x;
+
+    for (int64_t c = blockIdx.x; c < A.n_cells; c += gridDim.x) {
+        const uint32_t cell = (uint32_t)c;
+        const int Ne = live(A.el, c), Ng0 = live(A.ph, c), Ni = live(A.io, c);
+        const int64_t e0 = A.el.off[c], g0 = A.ph.off[c], i0 = A.io.off[c];
+        int st = W.cs[c].status;
+        if (!st && (Ne > A.maxn || Ng0 > A.maxn || Ni > A.maxn)) st = CMC_ST_TOO_LARGE;
+        double se = 0.0, sg = 0.0, si = 0.0;
+        int bad = 0;
+        if (!st) {
+            for (int a = tid; a < Ne; a += kThreads) { const double w = A.el.w[e0 + a]; se += w; bad |= !(w >= 0.0) || !isfinite(w); }
+            for (int a = tid; a < Ng0; a += kThreads) { const double w = A.ph.w[g0 + a]; sg += w; bad |= !(w >= 0.0) || !isfinite(w); }
+            for (int a = tid; a < Ni; a += kThreads) { const double w = A.io.w[i0 + a]; wion[a] = w; si += w; bad |= !(w >= 0.0) || !isfinite(w); }
+        }
+        if (tid == 0) { evcount = 0; conflict = 0; }
+        const double n_e = block_sum(se, redd), n_g = block_sum(sg, redd), n_I = block_sum(si, redd);
+        if (!st && block_or(bad, redi)) st = CMC_ST_BAD_WEIGHT;
+        int c_pairs_br = 0, c_pairs_tr = 0, c_pairs_bh = 0, c_near_br = 0, c_near_tr = 0, c_near_bh = 0;
+        int c_high = 0;
+        double nab_ei = 0.0, nab_gi = 0.0;
+        if (!st) {
+            const CellTab<R> ct = pick<R>(W.cs[c]);
+            // ------------------------------ electron-ion pass
+            if ((A.proc & (CMC_BREMS | CMC_TRIDENT)) && Ne > 0 && Ni > 0) {
+                key_order(Ne, cell, kTagKeyE, A.rng, keys, pm, bcnt, redu);
+                key_order(Ni, cell, kTagKeyIE, A.rng, keys, pi, bcnt, redu);
+                const int N = Ne > Ni ? Ne : Ni;
+                const bool mobA = Ne >= Ni;
+                if (mobA) {
+                    for (int q = tid; q < Ne; q += kThreads) inv[pm[q]] = (uint16_t)q;
+                    __syncthreads();
+                }
+                // pairs as (j, electron, ion): mobile-first in storage order
+                // when each electron pairs once, else by pair index
+                const int npass = mobA ? Ne : N;
+                double part = 0.0;
+                for (int q = tid; q < npass; q += kThreads) {
+                    const int j = mobA ? (int)inv[q] : q;
+                    const int me = mobA ? q : (int)pm[q % Ne];
+                    const double we = A.el.w[e0 + me], wi = wion[pi[j % Ni]];
+                    part += we < wi ? we : wi;
+                }
+                nab_ei = block_sum(part, redd);
+                if (nab_ei > 0.0) {
+                    const double coef = n_e * n_I / nab_ei;
+                    for (int q = tid; q < npass; q += kThreads) {
+                        const int j = mobA ? (int)inv[q] : q;
+                        const int me = mobA ? q : (int)pm[q % Ne];
+                        const int ii = pi[j % Ni];
+                        const bool reused = !mobA && j + Ne < N;
+                        const int64_t ie = e0 + me;
+                        const double We = A.el.w[ie], Wi = wion[ii];
+                        const double Pej = Wi / (We > Wi ? We : Wi);
+                        const R rpx = (R)A.el.px[ie], rpy = (R)A.el.py[ie], rpz = (R)A.el.pz[ie];
+                        const R p2 = rpx * rpx + rpy * rpy + rpz * rpz;
+                        const R g = sqrt((R)1 + p2), gm1 = p2 / (g + (R)1), pmag = sqrt(p2);
+                        uint32_t kind = 0;
+                        if (A.proc & CMC_BREMS) {
+                            c_pairs_br++;
+                            bool high;
+                            const BremsLook<R> BL = brems_lookup<R, false>(T, ct, g, gm1, high);
+                            c_high |= high;
+                            if (BL.sig > (R)0) {
+                                const double x = coef * (double)BL.sig * (phys::kC * (double)pmag / (double)g) * A.dt;
+                                const double P = -expm1(-x);
+                                const U4 r = A.rng.draw((uint32_t)j, cell, kTagAccBr);
+                                const double U1 = u53(r.x, r.y), U2 = u53(r.z, r.w);
+                                if (fabs(U1 - P) <= A.near_rel * P) c_near_br++;
+                                if (U1 < P && U2 < Pej) kind = kEvBr | ((A.proc & CMC_TRIDENT) ? kEvTrPending : 0u);
+                            }
+                        }
+                        if (A.proc & CMC_TRIDENT) {
+                            c_pairs_tr++;
+                            if (!kind) {
+                                const R sig = (R)phys::trident_sigma(T.Z, (double)g);
+                                if (sig > (R)0) {
+                                    const double x = coef * (double)sig * (phys::kC * (double)pmag / (double)g) * A.dt;
+                                    const double P = -expm1(-x);
+                                    const U4 r = A.rng.draw((uint32_t)j, cell, kTagAccTr);
+                                    const double U1 = u53(r.x, r.y), U2 = u53(r.z, r.w);
+                                    if (fabs(U1 - P) <= A.near_rel * P) c_near_tr++;
+                                    if (U1 < P && U2 < Pej) kind = kEvTr;
+                                }
+                            }
+                        }
+                        if (kind) {
+                            const int k = atomicAdd(&evcount, 1);
+                            if (k < kEvCap) W.ev[c * kEvCap + k] = ev_pack(0, j, me, ii, kind);
+                            if (reused) conflict = 1;
+                        }
+                    }
+                }
+            }
+            // ------------------------------ photon-ion pass
+            if ((A.proc & CMC_BH) && Ng0 > 0 && Ni > 0) {
+                key_order(Ng0, cell, kTagKeyG, A.rng, keys, pm, bcnt, redu);
+                key_order(Ni, cell, kTagKeyIG, A.rng, keys, pi, bcnt, redu);
+                const int N = Ng0 > Ni ? Ng0 : Ni;
+                const bool mobA = Ng0 >= Ni;
+                if (mobA) {
+                    for (int q = tid; q < Ng0; q += kThreads) inv[pm[q]] = (uint16_t)q;
+                    __syncthreads();
+                }
+                const int npass = mobA ? Ng0 : N;
+                double part = 0.0;
+                for (int q = tid; q < npass; q += kThreads) {
+                    const int j = mobA ? (int)inv[q] : q;
+                    const int mg = mobA ? q : (int)pm[q % Ng0];
+                    const double wg = A.ph.w[g0 + mg], wi = wion[pi[j % Ni]];
+                    part += wg < wi ? wg : wi;
+                }
+                nab_gi = block_sum(part, redd);
+                if (nab_gi > 0.0) {
+                    const double coef = n_g * n_I / nab_gi;
+                    for (int q = tid; q < npass; q += kThreads) {
+                        const int j = mobA ? (int)inv[q] : q;
+                        const int mg = mobA ? q : (int)pm[q % Ng0];
+                        const int ii = pi[j % Ni];
+                        const bool reused = !mobA && j + Ng0 < N;
+                        const int64_t ig = g0 + mg;
+                        c_pairs_bh++;
+                        const double Wg = A.ph.w[ig], Wi = wion[ii];
+                        const double Pej = Wi / (Wg > Wi ? Wg : Wi);
+                        const R rqx = (R)A.ph.px[ig], rqy = (R)A.ph.py[ig], rqz = (R)A.ph.pz[ig];
+                        const R k = sqrt(rqx * rqx + rqy * rqy + rqz * rqz);
+                        int ik; R wk; bool high;
+                        const R sig = bh_lookup<R>(T, ct, k, ik, wk, high);
+                        c_high |= high;
+                        if (sig > (R)0) {
+                            const double x = coef * (double)sig * (phys::kC * (double)k / (double)k) * A.dt;
+                            const double P = -expm1(-x);
+                            const U4 r = A.rng.draw((uint32_t)j, cell, kTagAccBh);
+                            const double U1 = u53(r.x, r.y), U2 = u53(r.z, r.w);
+                            if (fabs(U1 - P) <= A.near_rel * P) c_near_bh++;
+                            if (U1 < P && U2 < Pej) {
+                                const int kk = atomicAdd(&evcount, 1);
+                                if (kk < kEvCap) W.ev[c * kEvCap + kk] = ev_pack(1, j, mg, ii, kEvBh);
+                                if (reused) conflict = 1;
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        const bool high_any = block_or(c_high, redi);
+        Tally t = {};
+        t.pairs_br = c_pairs_br; t.pairs_tr = c_pairs_tr; t.pairs_bh = c_pairs_bh;
+        t.near_br = c_near_br; t.near_tr = c_near_tr; t.near_bh = c_near_bh;
+        if (tid == 0) {
+            if (st) atomicOr(A.status, st);
+            if (high_any) atomicOr(A.status, CMC_ST_GAMMA_HIGH);
+            const int n = evcount;
+            W.flags[c] = st ? kFlagSkip : ((conflict || n > kEvCap) ? kFlagSlow : 0);
+            W.nev[c] = n < kEvCap ? n : kEvCap;
+            W.dens[c * 3 + 0] = n_e; W.dens[c * 3 + 1] = n_g; W.dens[c * 3 + 2] = n_I;
+        }
+        write_tallies(A, c, t, nab_ei, nab_gi, redl, redd8);
+    }
+}
+
+// one wavefront per cell with events: sample, write products in pair order
+template <typename R>
+__global__ __launch_bounds__(64) void k_events(StepArgs A, TabView<R> T, TabView<double> T64, Work W) {
+    __shared__ uint64_t rec[kEvCap];
+    __shared__ uint32_t killed[CMC_MAX_PER_CELL / 32];
+    const int lane = threadIdx.x;
+    for (int64_t c = blockIdx.x; c < A.n_cells; c += gridDim.x) {
+        const int n = W.nev[c];
+        if (W.flags[c] != 0 || n == 0) continue;
+        const uint32_t cell = (uint32_t)c;
+        // events in (pass, pair index) order
+        const uint64_t mine = lane < n ? W.ev[c * kEvCap + lane] : ~0ull;
+        const uint32_t key = lane < n ? ev_key(mine) : 0xFFFFFFFFu;
+        int rank = 0;
+        for (int l = 0; l < n; ++l) {
+            const uint32_t kl = __shfl(key, l, 64);
+            rank += kl < key;
+        }
+        if (lane < n) rec[rank] = mine;
+        __syncthreads();
+        const uint64_t r = lane < n ? rec[lane] : 0ull;
+        const bool live_ev = lane < n;
+        const int pass = live_ev ? ev_pass(r) : 2;
+        const uint32_t kind = live_ev ? ev_kind(r) : 0u;
+        const int j = ev_j(r), mi = ev_m(r), ii = ev_i(r);
+        const CellTab<double> ct64 = W.cs[c].d;
+        const int64_t e0 = A.el.off[c], g0 = A.ph.off[c], i0 = A.io.off[c];
+        const int Ng0 = live(A.ph, c);
+        const int cap_ph = (int)(A.ph.off[c + 1] - g0);
+        const int cap_ne = (int)(A.ne.off[c + 1] - A.ne.off[c]), cap_np = (int)(A.np.off[c + 1] - A.np.off[c]);
+        const int cnt_ne0 = A.ne.count[c], cnt_np0 = A.np.count[c];
+        const double n_e = W.dens[c * 3 + 0], n_g = W.dens[c * 3 + 1], n_I = W.dens[c * 3 + 2];
+        Tally t = {};
+        bool f_ph = false, f_tr = false, f_bh = false;
+        double kx = 0, ky = 0, kz = 0, pxm = 0, pym = 0, pzm = 0, pxp = 0, pyp = 0, pzp = 0, Wm = 0;
+        int64_t par = 0;
+        if (pass == 0) {
+            const int64_t ie = e0 + mi;
+            par = ie;
+            double px = A.el.px[ie], py = A.el.py[ie], pz = A.el.pz[ie];
+            Wm = A.el.w[ie];
+            if (kind & kEvBr) {
+                const U4 q = A.rng.draw((uint32_t)j, cell, kTagSmpBr);
+                const double p2d = px * px + py * py + pz * pz;
+                const double gd = sqrt(1.0 + p2d), gm1d = p2d / (gd + 1.0), pmd = sqrt(p2d);
+                bool hi2;
+                const BremsLook<double> BLd = brems_lookup<double, false>(T64, ct64, gd, gm1d, hi2);
+                double k, g2, g2m1;
+                brems_sample<double>(T64, ct64, BLd, gd, gm1d, u53(q.x, q.y), k, g2, g2m1);
+                const double pf = sqrt(g2m1 * (g2 + 1.0));
+                const double f = pf / pmd, h = k / pmd;
+                kx = px * h; ky = py * h; kz = pz * h;
+                px *= f; py *= f; pz *= f;
+                t.ev_br++;
+                t.E_br += Wm * sqrt(kx * kx + ky * ky + kz * kz);
+                t.dE_el += Wm * (-k);
+                t.W_br += Wm;
+                f_ph = true;
+            }
+            bool tr = (kind & kEvTr) != 0;
+            if (kind & kEvTrPending) {
+                // Trident on the electron left by Bremsstrahlung (same pair)
+                const double Wi = A.io.w[i0 + ii];
+                const double Pej = Wi / (Wm > Wi ? Wm : Wi);
+                const R rpx = (R)px, rpy = (R)py, rpz = (R)pz;
+                const R p2 = rpx * rpx + rpy * rpy + rpz * rpz;
+                const R g = sqrt((R)1 + p2), pmag = sqrt(p2);
+                const R sig = (R)phys::trident_sigma(T.Z, (double)g);
+                const double nab = A.td[c * CMC_ND + CMC_D_NAB_EI];
+                if (sig > (R)0) {
+                    const double x = (n_e * n_I / nab) * (double)sig * (phys::kC * (double)pmag / (double)g) * A.dt;
+                    const double P = -expm1(-x);
+                    const U4 q = A.rng.draw((uint32_t)j, cell, kTagAccTr);
+                    const double U1 = u53(q.x, q.y), U2 = u53(q.z, q.w);
+                    if (fabs(U1 - P) <= A.near_rel * P) t.near_tr++;
+                    tr = U1 < P && U2 < Pej;
+                }
+            }
+            if (tr) {
+                const U4 q = A.rng.draw((uint32_t)j, cell, kTagSmpTr);
+                const double p2d = px * px + py * py + pz * pz;
+                const double gd = sqrt(1.0 + p2d), gm1d = p2d / (gd + 1.0), pmd = sqrt(p2d);
+                double gpair, gpl, gmi, gfm1;
+                trident_sample<double>(T64, gd, gm1d, u53(q.x, q.y), u53(q.z, q.w), gpair, gpl, gmi, gfm1);
+                const double gf = gfm1 + 1.0;
+                const double pf = sqrt(gfm1 * (gf + 1.0));
+                const double pplus = sqrt((gpl - 1.0) * (gpl + 1.0)), pminus = sqrt((gmi - 1.0) * (gmi + 1.0));
+                const double f = pf / pmd, fp = pplus / pmd, fm = pminus / pmd;
+                pxp = px * fp; pyp = py * fp; pzp = pz * fp;
+                pxm = px * fm; pym = py * fm; pzm = pz * fm;
+                px *= f; py *= f; pz *= f;
+                t.ev_tr++;
+                t.E_tr += Wm * (sqrt(1.0 + pxp * pxp + pyp * pyp + pzp * pzp) + sqrt(1.0 + pxm * pxm + pym * pym + pzm * pzm));
+                t.dE_el += Wm * (-gpair);
+                t.W_tr += Wm;
+                f_tr = true;
+            }
+            if (f_ph || f_tr) { A.el.px[ie] = px; A.el.py[ie] = py; A.el.pz[ie] = pz; }
+        } else if (pass == 1) {
+            const int64_t ig = g0 + mi;
+            par = ig;
+            const double qx = A.ph.px[ig], qy = A.ph.py[ig], qz = A.ph.pz[ig];
+            Wm = A.ph.w[ig];
+            const double kd = sqrt(qx * qx + qy * qy + qz * qz);
+            const U4 q = A.rng.draw((uint32_t)j, cell, kTagSmpBh);
+            int ikd; double wkd; bool hi2;
+            bh_lookup<double>(T64, ct64, kd, ikd, wkd, hi2);
+            double gpl, gmi;
+            bh_sample<double>(T64, ct64, kd, ikd, wkd, u53(q.x, q.y), gpl, gmi);
+            const double pplus = sqrt((gpl - 1.0) * (gpl + 1.0)), pminus = sqrt((gmi - 1.0) * (gmi + 1.0));
+            const double fp = pplus / kd, fm = pminus / kd;
+            pxp = qx * fp; pyp = qy * fp; pzp = qz * fp;
+            pxm = qx * fm; pym = qy * fm; pzm = qz * fm;
+            t.ev_bh++;
+            t.E_bh += Wm * (sqrt(1.0 + pxp * pxp + pyp * pyp + pzp * pzp) + sqrt(1.0 + pxm * pxm + pym * pym + pzm * pzm));
+            t.dE_ph += -Wm * kd;
+            t.W_bh += Wm;
+            f_bh = true;
+        }
+        // slots in (pass, pair) order: lanes are already in that order
+        const unsigned long long b_ph = __ballot(f_ph), b_tr = __ballot(f_tr), b_bh = __ballot(f_bh);
+        const unsigned long long below = (1ull << lane) - 1ull;
+        const int n_ph = __popcll(b_ph), n_tr = __popcll(b_tr), n_bh = __popcll(b_bh);
+        if (f_ph) {
+            const int slot = Ng0 + __popcll(b_ph & below);
+            if (slot < cap_ph) {
+                const int64_t at = g0 + slot;
+                A.ph.px[at] = kx; A.ph.py[at] = ky; A.ph.pz[at] = kz; A.ph.w[at] = Wm;
+                if (A.ph.parent) A.ph.parent[at] = par;
+            } else t.drop_ph++;
+        }
+        if (f_tr || f_bh) {
+            const int o = f_tr ? __popcll(b_tr & below) : n_tr + __popcll(b_bh & below);
+            if (cnt_ne0 + o < cap_ne) {
+                const int64_t at = A.ne.off[c] + cnt_ne0 + o;
+                A.ne.px[at] = pxm; A.ne.py[at] = pym; A.ne.pz[at] = pzm; A.ne.w[at] = Wm;
+                if (A.ne.parent) A.ne.parent[at] = par;
+            } else t.drop_el++;
+            if (cnt_np0 + o < cap_np) {
+                const int64_t at = A.np.off[c] + cnt_np0 + o;
+                A.np.px[at] = pxp; A.np.py[at] = pyp; A.np.pz[at] = pzp; A.np.w[at] = Wm;
+                if (A.np.parent) A.np.parent[at] = par;
+            } else t.drop_po++;
+        }
+        int ph_count = min(cap_ph, Ng0 + n_ph);
+        // remove converted photons (stable, in place)
+        if (n_bh) {
+            for (int i = lane; i < (Ng0 + 31) / 32; i += 64) killed[i] = 0u;
+            __syncthreads();
+            if (f_bh) atomicOr(&killed[mi >> 5], 1u << (mi & 31));
+            __syncthreads();
+            int wpos = 0;
+            for (int base = 0; base < ph_count; base += 64) {
+                const int a = base + lane;
+                bool keep = false;
+                double vx = 0, vy = 0, vz = 0, vw = 0;
+                int64_t pp = -1;
+                if (a < ph_count) {
+                    keep = !(a < Ng0 && ((killed[a >> 5] >> (a & 31)) & 1u));
+                    if (keep) {
+                        vx = A.ph.px[g0 + a]; vy = A.ph.py[g0 + a]; vz = A.ph.pz[g0 + a]; vw = A.ph.w[g0 + a];
+                        if (A.ph.parent) pp = A.ph.parent[g0 + a];
+                    }
+                }
+                const unsigned long long bk = __ballot(keep);
+                __syncthreads();
+                if (keep) {
+                    const int64_t at = g0 + wpos + __popcll(bk & below);
+                    A.ph.px[at] = vx; A.ph.py[at] = vy; A.ph.pz[at] = vz; A.ph.w[at] = vw;
+                    if (A.ph.parent) A.ph.parent[at] = pp;
+                }
+                wpos += __popcll(bk);
+                __syncthreads();
+            }
+            ph_count = wpos;
+        }
+        // tallies of the events (the pair counts were written by k_decide)
+        long long iv[7] = {t.ev_br, t.ev_tr, t.ev_bh, t.near_tr, t.drop_ph, t.drop_el, t.drop_po};
+        double dv[8] = {t.E_br, t.E_tr, t.E_bh, t.dE_el, t.dE_ph, t.W_br, t.W_tr, t.W_bh};
+#pragma unroll
+        for (int q = 0; q < 7; ++q)
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) iv[q] += __shfl_xor(iv[q], o, 64);
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) dv[q] += __shfl_xor(dv[q], o, 64);
+        if (lane == 0) {
+            int64_t* ti = A.ti + c * CMC_NI;
+            ti[CMC_I_EV_BR] = iv[0]; ti[CMC_I_EV_TR] = iv[1]; ti[CMC_I_EV_BH] = iv[2];
+            ti[CMC_I_NEAR_TR] += iv[3];
+            ti[CMC_I_DROP_PH] = iv[4]; ti[CMC_I_DROP_EL] = iv[5]; ti[CMC_I_DROP_PO] = iv[6];
+            double* td = A.td + c * CMC_ND + CMC_D_E_BR;
+            for (int q = 0; q < 8; ++q) td[q] = dv[q];
+            if (A.ph.count) A.ph.count[c] = ph_count;
+            A.ne.count[c] = min(cap_ne, cnt_ne0 + n_tr + n_bh);
+            A.np.count[c] = min(cap_np, cnt_np0 + n_tr + n_bh);
+            if (iv[4] + iv[5] + iv[6]) atomicOr(A.status, CMC_ST_OVERFLOW);
+        }
         __syncthreads();
     }
 }
@@ -586,7 +1087,7 @@ struct PairArgs {
 __global__ __launch_bounds__(kThreads) void k_pair(PairArgs A) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double redd[kWaves];
-    __shared__ uint32_t redu[kThreads];
+    __shared__ uint32_t redu[kWaves];
     const Smem S = carve(smem_raw, A.maxn);
     for (int64_t c = blockIdx.x; c < A.n_cells; c += gridDim.x) {
         const int ca = (int)(A.a_off[c + 1] - A.a_off[c]), cb = (int)(A.b_off[c + 1] - A.b_off[c]);
@@ -628,8 +1129,8 @@ int grid_for(int64_t n_cells) {
 using namespace cmc;
 
 extern "C" size_t cmc_step_workspace_bytes(int64_t n_cells, int32_t schedule) {
-    (void)n_cells; (void)schedule;
-    return 0;
+    if (n_cells <= 0 || schedule == CMC_SCHED_CELL) return 0;
+    return work_bytes(n_cells);
 }
 
 static cmc_status set_species(SpeciesDev& d, const cmc_species* s, const char* name, bool need_count,
@@ -679,17 +1180,50 @@ extern "C" cmc_status cmc_collide_step(cmc_tables t, const cmc_cells* cells, cmc
     A.maxn = P->max_per_cell;
     A.ti = tal->ti; A.td = tal->td; A.status = tal->status;
     if (A.n_cells == 0) return CMC_OK;
-    const size_t shm = smem_bytes(A.maxn);
     hipStream_t st = as_stream(stream);
+    const size_t shm = smem_bytes(A.maxn);
     const int grid = grid_for(A.n_cells);
-    if (P->precision == CMC_FP64) {
+    const bool fp64 = P->precision == CMC_FP64;
+    if (P->schedule == CMC_SCHED_CELL) {
+        // one sequential workgroup per cell for every cell
+        A.only_slow = nullptr;
+        if (fp64) {
+            (void)hipFuncSetAttribute((const void*)k_collide<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+            hipLaunchKernelGGL(k_collide<double>, dim3(grid), dim3(kThreads), shm, st, A, view64(t), view64(t));
+        } else {
+            (void)hipFuncSetAttribute((const void*)k_collide<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+            hipLaunchKernelGGL(k_collide<float>, dim3(grid), dim3(kThreads), shm, st, A, view32(t), view64(t));
+        }
+        CMC_CHECK_LAUNCH("cmc_collide_step");
+        return CMC_OK;
+    }
+    const size_t need = work_bytes(A.n_cells);
+    CMC_REQUIRE(workspace != nullptr && workspace_bytes >= need, CMC_EINVAL,
+                "cmc_collide_step: workspace of %zu bytes required (got %zu)", need, workspace_bytes);
+    const Work W = carve_work(workspace, A.n_cells);
+    A.only_slow = W.flags;
+    const size_t dshm = decide_smem_bytes(A.maxn);
+    hipLaunchKernelGGL(k_cell_state, dim3((unsigned)std::min<int64_t>((A.n_cells + 255) / 256, 4096)), dim3(256), 0, st,
+                       A.Zs, A.ni, A.Te, A.n_cells, (double)t->Z, t->ax, W.cs);
+    CMC_CHECK_LAUNCH("cmc_collide_step: k_cell_state");
+    if (fp64) {
+        (void)hipFuncSetAttribute((const void*)k_decide<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dshm);
+        hipLaunchKernelGGL(k_decide<double>, dim3(grid), dim3(kThreads), dshm, st, A, view64(t), W);
+        CMC_CHECK_LAUNCH("cmc_collide_step: k_decide");
+        hipLaunchKernelGGL(k_events<double>, dim3(grid), dim3(64), 0, st, A, view64(t), view64(t), W);
+        CMC_CHECK_LAUNCH("cmc_collide_step: k_events");
         (void)hipFuncSetAttribute((const void*)k_collide<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
         hipLaunchKernelGGL(k_collide<double>, dim3(grid), dim3(kThreads), shm, st, A, view64(t), view64(t));
     } else {
+        (void)hipFuncSetAttribute((const void*)k_decide<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dshm);
+        hipLaunchKernelGGL(k_decide<float>, dim3(grid), dim3(kThreads), dshm, st, A, view32(t), W);
+        CMC_CHECK_LAUNCH("cmc_collide_step: k_decide");
+        hipLaunchKernelGGL(k_events<float>, dim3(grid), dim3(64), 0, st, A, view32(t), view64(t), W);
+        CMC_CHECK_LAUNCH("cmc_collide_step: k_events");
         (void)hipFuncSetAttribute((const void*)k_collide<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
         hipLaunchKernelGGL(k_collide<float>, dim3(grid), dim3(kThreads), shm, st, A, view32(t), view64(t));
     }
-    CMC_CHECK_LAUNCH("cmc_collide_step");
+    CMC_CHECK_LAUNCH("cmc_collide_step: k_collide");
     return CMC_OK;
 }
 

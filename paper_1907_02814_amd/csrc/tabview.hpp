@@ -91,7 +91,7 @@ struct BremsLook {
 // kinetic g1m1 = g - 1).  Regimes of Sec. II.B: g <= 2 non-relativistic,
 // 2 < g <= 100 moderately relativistic, g > 100 ultra-relativistic; no
 // emission below 1 keV; energies above the table are clamped (high = true).
-template <typename R>
+template <typename R, bool kMoment = true>
 __device__ __forceinline__ BremsLook<R> brems_lookup(const TabView<R>& T, const CellTab<R>& c,
                                                      R g, R g1m1, bool& high) {
     BremsLook<R> o;
@@ -102,8 +102,11 @@ __device__ __forceinline__ BremsLook<R> brems_lookup(const TabView<R>& T, const 
         o.seg = kSegNR;
         locate<R>(log(g1m1), T.ax.nr, o.ig, o.wg, o.in);
         const R s0 = blend_N<R>(T[grid::kSigN], 1, o.ig, c, 0), s1 = blend_N<R>(T[grid::kSigN], 1, o.ig + 1, c, 0);
-        const R k0 = blend_N<R>(T[grid::kSkN], 1, o.ig, c, 0), k1 = blend_N<R>(T[grid::kSkN], 1, o.ig + 1, c, 0);
-        o.sig = lerp(s0, s1, o.wg); o.sk = lerp(k0, k1, o.wg);
+        o.sig = lerp(s0, s1, o.wg);
+        if (kMoment) {
+            const R k0 = blend_N<R>(T[grid::kSkN], 1, o.ig, c, 0), k1 = blend_N<R>(T[grid::kSkN], 1, o.ig + 1, c, 0);
+            o.sk = lerp(k0, k1, o.wg);
+        }
         return o;
     }
     const bool rel = g <= (R)100;
@@ -112,9 +115,11 @@ __device__ __forceinline__ BremsLook<R> brems_lookup(const TabView<R>& T, const 
     if (!rel && g > (R)grid::kTop) { high = true; u = (R)log(grid::kTop); } else { u = log(g); }
     locate<R>(u, rel ? T.ax.rel : T.ax.ur, o.ig, o.wg, o.in);
     const R* S = T[rel ? grid::kSigR : grid::kSigU];
-    const R* K = T[rel ? grid::kSkR : grid::kSkU];
     o.sig = lerp(blend_L<R>(S, 1, o.ig, c, 0), blend_L<R>(S, 1, o.ig + 1, c, 0), o.wg);
-    o.sk = lerp(blend_L<R>(K, 1, o.ig, c, 0), blend_L<R>(K, 1, o.ig + 1, c, 0), o.wg);
+    if (kMoment) {
+        const R* K = T[rel ? grid::kSkR : grid::kSkU];
+        o.sk = lerp(blend_L<R>(K, 1, o.ig, c, 0), blend_L<R>(K, 1, o.ig + 1, c, 0), o.wg);
+    }
     return o;
 }
 
