@@ -124,7 +124,8 @@ typedef struct {
     int32_t schedule;      /* 0 = automatic, see cmc_schedule_*               */
     int32_t max_per_cell;  /* upper bound of live electrons, photons and ions
                               per cell (<= CMC_MAX_PER_CELL); sizes the launch */
-    double near_rel;       /* band |U - P| <= near_rel * P counted as near-threshold */
+    double near_rel;       /* band |U - P| <= near_rel * P counted as near-threshold,
+                              in [0, 1] (default 1e-6)                        */
 } cmc_step_params;
 
 #define CMC_MAX_PER_CELL 16384
@@ -198,7 +199,8 @@ cmc_status cmc_pair_cells(int64_t n_cells, const int64_t* a_off, const int32_t* 
 /* workspace: device scratch of cmc_step_workspace_bytes() bytes (may be */
 /* NULL when that is 0).                                                 */
 /* Errors: CMC_EINVAL (null or inconsistent pointers, dt <= 0, unknown  */
-/* processes/precision/schedule, ions with momenta), CMC_ERANGE          */
+/* processes/precision/schedule, near_rel outside [0, 1], ions with     */
+/* momenta), CMC_ERANGE                                                  */
 /* (max_per_cell outside [1, CMC_MAX_PER_CELL]), CMC_EDEVICE.            */
 /* ------------------------------------------------------------------ */
 cmc_status cmc_collide_step(cmc_tables t, const cmc_cells* cells,
@@ -211,9 +213,23 @@ cmc_status cmc_collide_step(cmc_tables t, const cmc_cells* cells,
 /* Scratch bytes cmc_collide_step needs for n_cells with this schedule. */
 size_t cmc_step_workspace_bytes(int64_t n_cells, int32_t schedule);
 
-/* schedules: 0 automatic; 1 one workgroup per cell; 2 persistent
- * work-queue launch (cells dealt by an atomic counter) */
-enum { CMC_SCHED_AUTO = 0, CMC_SCHED_CELL = 1, CMC_SCHED_PERSISTENT = 2 };
+/* Schedules (every schedule gives the same decisions and products):
+ *  CMC_SCHED_CELL   one workgroup per cell tests the pairs in order (the
+ *                   sequential reference schedule; no workspace);
+ *  CMC_SCHED_GROUP  all pairs of a cell are tested at once from the state
+ *                   at the start of the step by one workgroup per cell,
+ *                   events are then applied in pair order; cells where a
+ *                   particle used by a later pair changes (or with many
+ *                   events, or too many particles for LDS) fall back to
+ *                   the sequential kernel;
+ *  CMC_SCHED_WAVE   the same with one wavefront per cell (cells above
+ *                   1024 particles of a species take the fallback);
+ *  CMC_SCHED_AUTO   GROUP or WAVE, whichever is faster on the first step of
+ *                   a launch shape (device, n_cells, max_per_cell,
+ *                   processes, precision): that first call times both and
+ *                   waits for the timing; under stream capture an untimed
+ *                   shape uses GROUP. */
+enum { CMC_SCHED_AUTO = 0, CMC_SCHED_CELL = 1, CMC_SCHED_GROUP = 2, CMC_SCHED_WAVE = 3 };
 
 /* ------------------------------------------------------------------ */
 /* Expected photon energy yield (deterministic): for every cell c,      */

@@ -18,6 +18,10 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <algorithm>
 
 #include "common.hpp"
 #include "philox.hpp"
@@ -222,7 +226,8 @@ struct StepArgs {
     int64_t* ti;
     double* td;
     int32_t* status;
-    const int32_t* only_slow;   // non-NULL: process only cells flagged for the sequential path
+    const int32_t* list;        // non-NULL: process only the cells list[0 .. *list_n)
+    const int32_t* list_n;
 };
 
 // per-thread tallies (scalars: no dynamically indexed local arrays)
@@ -301,8 +306,9 @@ __global__ __launch_bounds__(kThreads) void k_collide(StepArgs A, TabView<R> T, 
     const Smem S = carve(smem_raw, A.maxn);
     const int tid = threadIdx.x;
 
-    for (int64_t c = blockIdx.x; c < A.n_cells; c += gridDim.x) {
-        if (A.only_slow && !(A.only_slow[c] & 1)) continue;
+    const int64_t n_items = A.list ? (int64_t)*A.list_n : A.n_cells;
+    for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+        const int64_t c = A.list ? (int64_t)A.list[item] : item;
         const uint32_t cell = (uint32_t)c;
         const int Ne = live(A.el, c), Ng0 = live(A.ph, c), Ni = live(A.io, c);
         const int64_t e0 = A.el.off[c], g0 = A.ph.off[c], i0 = A.io.off[c];
@@ -512,7 +518,7 @@ __global__ __launch_bounds__(kThreads) void k_collide(StepArgs A, TabView<R> T, 
                             high_any |= high;
                             if (sig > (R)0) {
                                 // eq:proba3 for photons: gamma -> k', v' -> c, flux k' c/(k gamma_i)
-                                const double x = coef * (double)sig * (phys::kC * (double)k / (double)k) * A.dt;
+                                const double x = coef * (double)sig * phys::kC * A.dt;
                                 const double P = -expm1(-x);
                                 const U4 r = A.rng.draw((uint32_t)j, cell, kTagAccBh);
                                 const double U1 = u53(r.x, r.y), U2 = u53(r.z, r.w);
@@ -606,17 +612,19 @@ __global__ __launch_bounds__(kThreads) void k_collide(StepArgs A, TabView<R> T, 
 
 
 // ------------------------------------------------------------------ fast path
-// The step is split in three launches.  k_decide tests every pair of a cell
-// with the particles as they are at the start of the step (loads in storage
-// order, ion weights staged in LDS) and records the events; this is exact
-// whenever no particle reused by a later pair of the same pass changes
-// before that pair, i.e. when every event falls on the last pair of its
-// mobile particle.  k_events then samples the events of such cells in pair
-// order and writes the products.  Cells where that does not hold (or that
-// hold more than kEvCap events) are flagged and run by k_collide, the
-// sequential per-cell kernel above.
-constexpr int kEvCap = 64;
-enum : int32_t { kFlagSlow = 1, kFlagSkip = 2 };
+// The step is split in launches.  k_cell_state computes the screening
+// state of every cell and clears its tallies.  k_pass (one launch per pass)
+// tests every pair of a cell with the particles as they are at the start of
+// the step; this is exact whenever no particle used by a later pair of the
+// same pass changes before that pair, i.e. when every event falls on the
+// last pair of its particle.  Tests the bound on P cannot settle are listed
+// per cell; k_events settles them and applies the events of the cell in
+// pair order.  Cells where the start-of-step reading does not hold (an event
+// on a particle used again, more open pairs than kCandCap, more particles
+// than the pass kernel's LDS) are listed for k_collide, the sequential
+// per-cell kernel above, which redoes the whole cell.
+constexpr int kCandCap = 64;     // open pairs per cell (both passes)
+enum : int32_t { kFlagSlow = 1 };
 enum : uint32_t { kEvBr = 1, kEvTrPending = 2, kEvTr = 4, kEvBh = 8 };
 
 struct CellState {
@@ -627,17 +635,21 @@ struct CellState {
 
 struct Work {
     CellState* cs;
-    int32_t* flags;
-    int32_t* nev;
+    int32_t* flags;                  // kFlagSlow: the sequential kernel runs the cell
+    int32_t* ncand;                  // open pairs pushed per cell
     double* dens;                    // n_e, n_gamma, n_ion per cell
-    uint64_t* ev;                    // [n_cells][kEvCap] event records
+    double* coef;                    // n_a n_b / n_ab per cell and pass
+    int32_t* counters;               // [0] cells with open pairs, [1] cells for the sequential kernel
+    int32_t* list_ev;                // cells with open pairs (event kernel)
+    int32_t* list_slow;              // cells the sequential kernel runs
+    uint64_t* cand;                  // [n_cells][kCandCap] open pairs
 };
 
 __host__ __device__ inline size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
 __host__ __device__ inline size_t work_bytes(int64_t n) {
     return align256(sizeof(CellState) * n) + align256(4 * n) + align256(4 * n) + align256(24 * n) +
-           align256(8 * (size_t)n * kEvCap);
+           align256(16 * n) + align256(16) + 2 * align256(4 * n) + align256(8 * (size_t)n * kCandCap);
 }
 
 inline Work carve_work(void* base, int64_t n) {
@@ -645,9 +657,13 @@ inline Work carve_work(void* base, int64_t n) {
     Work w;
     w.cs = reinterpret_cast<CellState*>(p); p += align256(sizeof(CellState) * n);
     w.flags = reinterpret_cast<int32_t*>(p); p += align256(4 * n);
-    w.nev = reinterpret_cast<int32_t*>(p); p += align256(4 * n);
+    w.ncand = reinterpret_cast<int32_t*>(p); p += align256(4 * n);
     w.dens = reinterpret_cast<double*>(p); p += align256(24 * n);
-    w.ev = reinterpret_cast<uint64_t*>(p);
+    w.coef = reinterpret_cast<double*>(p); p += align256(16 * n);
+    w.counters = reinterpret_cast<int32_t*>(p); p += align256(16);
+    w.list_ev = reinterpret_cast<int32_t*>(p); p += align256(4 * n);
+    w.list_slow = reinterpret_cast<int32_t*>(p); p += align256(4 * n);
+    w.cand = reinterpret_cast<uint64_t*>(p);
     return w;
 }
 
@@ -662,19 +678,27 @@ __device__ __forceinline__ uint32_t ev_kind(uint64_t r) { return (uint32_t)(r >>
 __device__ __forceinline__ int ev_pass(uint64_t r) { return (int)((r >> 55) & 1); }
 __device__ __forceinline__ uint32_t ev_key(uint64_t r) { return ((uint32_t)ev_pass(r) << 16) | (uint32_t)ev_j(r); }
 
+// screening state of every cell; clears the cell's tallies and work
+// counters and the list counters of the step
 __global__ void k_cell_state(const double* Zs, const double* ni, const double* Te, int64_t n, double Z,
-                             Axes ax, CellState* out) {
+                             Axes ax, Work W, int64_t* ti, double* td, int32_t* status) {
+    if (blockIdx.x == 0 && threadIdx.x < 4) W.counters[threadIdx.x] = 0;
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
         const double z = Zs[c], d = ni[c], t = Te[c];
         CellState s = {};
+        W.flags[c] = 0;
+        W.ncand[c] = 0;
+        for (int q = 0; q < CMC_NI; ++q) ti[c * CMC_NI + q] = 0;
+        for (int q = 0; q < CMC_ND; ++q) td[c * CMC_ND + q] = 0.0;
         if (!(z >= 0.0 && z <= Z && d > 0.0 && t >= 0.0 && isfinite(d) && isfinite(t))) {
             s.status = CMC_ST_BAD_CELL;
+            atomicOr(status, CMC_ST_BAD_CELL);
         } else {
             const phys::Screen sc = phys::screening(Z, z, d, t);
             s.d = cell_tab<double>(sc, ax);
             s.f = cell_tab<float>(sc, ax);
         }
-        out[c] = s;
+        W.cs[c] = s;
     }
 }
 
@@ -685,222 +709,538 @@ __device__ __forceinline__ const CellTab<double>& pick<double>(const CellState& 
 template <>
 __device__ __forceinline__ const CellTab<float>& pick<float>(const CellState& s) { return s.f; }
 
-// LDS of k_decide: keys/inverse (u32), two orders (u16), ion weights (f64)
-__host__ __device__ inline size_t decide_smem_bytes(int maxn) {
-    const size_t n = (size_t)((maxn + 63) / 64 * 64);
-    return n * 4 + n * 2 * 2 + n * 8 + (size_t)smem_buckets(maxn) * 4 + 64;
-}
+// ------------------------------------------------------------------ teams
+// A team runs one cell: the whole workgroup (kT = 256) or one wavefront
+// (kT = 64: four cells per workgroup and no workgroup barrier at all).
+template <int kT>
+struct Team {
+    static_assert(kT == 64 || kT == 256, "team of one wavefront or one workgroup");
+    static __device__ __forceinline__ int tid() { return kT == 64 ? (int)(threadIdx.x & 63u) : (int)threadIdx.x; }
+    static __device__ __forceinline__ void sync() {
+        if constexpr (kT == 64) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        } else {
+            __syncthreads();
+        }
+    }
+};
 
-template <typename R>
-__global__ __launch_bounds__(kThreads) void k_decide(StepArgs A, TabView<R> T, Work W) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ double redd[kWaves];
-    __shared__ long long redl[kWaves * CMC_NI];
-    __shared__ double redd8[kWaves * 8];
-    __shared__ int redi[kWaves];
-    __shared__ uint32_t redu[kWaves];
-    __shared__ int evcount, conflict;
-    const size_t nn = (size_t)((A.maxn + 63) / 64 * 64);
-    uint32_t* keys = reinterpret_cast<uint32_t*>(smem_raw);
-    uint16_t* inv = reinterpret_cast<uint16_t*>(smem_raw);           // reuses the key space
-    uint16_t* pm = reinterpret_cast<uint16_t*>(smem_raw + nn * 4);
-    uint16_t* pi = pm + nn;
-    double* wion = reinterpret_cast<double*>(smem_raw + nn * 8);
-    uint32_t* bcnt = reinterpret_cast<uint32_t*>(smem_raw + nn * 16);
-    const int tid = threadIdx.x;
-
-    for (int64_t c = blockIdx.x; c < A.n_cells; c += gridDim.x) {
-        const uint32_t cell = (uint32_t)c;
-        const int Ne = live(A.el, c), Ng0 = live(A.ph, c), Ni = live(A.io, c);
-        const int64_t e0 = A.el.off[c], g0 = A.ph.off[c], i0 = A.io.off[c];
-        int st = W.cs[c].status;
-        if (!st && (Ne > A.maxn || Ng0 > A.maxn || Ni > A.maxn)) st = CMC_ST_TOO_LARGE;
-        double se = 0.0, sg = 0.0, si = 0.0;
-        int bad = 0;
-        if (!st) {
-            for (int a = tid; a < Ne; a += kThreads) { const double w = A.el.w[e0 + a]; se += w; bad |= !(w >= 0.0) || !isfinite(w); }
-            for (int a = tid; a < Ng0; a += kThreads) { const double w = A.ph.w[g0 + a]; sg += w; bad |= !(w >= 0.0) || !isfinite(w); }
-            for (int a = tid; a < Ni; a += kThreads) { const double w = A.io.w[i0 + a]; wion[a] = w; si += w; bad |= !(w >= 0.0) || !isfinite(w); }
-        }
-        if (tid == 0) { evcount = 0; conflict = 0; }
-        const double n_e = block_sum(se, redd), n_g = block_sum(sg, redd), n_I = block_sum(si, redd);
-        if (!st && block_or(bad, redi)) st = CMC_ST_BAD_WEIGHT;
-        int c_pairs_br = 0, c_pairs_tr = 0, c_pairs_bh = 0, c_near_br = 0, c_near_tr = 0, c_near_bh = 0;
-        int c_high = 0;
-        double nab_ei = 0.0, nab_gi = 0.0;
-        if (!st) {
-            const CellTab<R> ct = pick<R>(W.cs[c]);
-            // ------------------------------ electron-ion pass
-            if ((A.proc & (CMC_BREMS | CMC_TRIDENT)) && Ne > 0 && Ni > 0) {
-                key_order(Ne, cell, kTagKeyE, A.rng, keys, pm, bcnt, redu);
-                key_order(Ni, cell, kTagKeyIE, A.rng, keys, pi, bcnt, redu);
-                const int N = Ne > Ni ? Ne : Ni;
-                const bool mobA = Ne >= Ni;
-                if (mobA) {
-                    for (int q = tid; q < Ne; q += kThreads) inv[pm[q]] = (uint16_t)q;
-                    __syncthreads();
-                }
-                // pairs as (j, electron, ion): mobile-first in storage order
-                // when each electron pairs once, else by pair index
-                const int npass = mobA ? Ne : N;
-                double part = 0.0;
-                for (int q = tid; q < npass; q += kThreads) {
-                    const int j = mobA ? (int)inv[q] : q;
-                    const int me = mobA ? q : (int)pm[q % Ne];
-                    const double we = A.el.w[e0 + me], wi = wion[pi[j % Ni]];
-                    part += we < wi ? we : wi;
-                }
-                nab_ei = block_sum(part, redd);
-                if (nab_ei > 0.0) {
-                    const double coef = n_e * n_I / nab_ei;
-                    for (int q = tid; q < npass; q += kThreads) {
-                        const int j = mobA ? (int)inv[q] : q;
-                        const int me = mobA ? q : (int)pm[q % Ne];
-                        const int ii = pi[j % Ni];
-                        const bool reused = !mobA && j + Ne < N;
-                        const int64_t ie = e0 + me;
-                        const double We = A.el.w[ie], Wi = wion[ii];
-                        const double Pej = Wi / (We > Wi ? We : Wi);
-                        const R rpx = (R)A.el.px[ie], rpy = (R)A.el.py[ie], rpz = (R)A.el.pz[ie];
-                        const R p2 = rpx * rpx + rpy * rpy + rpz * rpz;
-                        const R g = sqrt((R)1 + p2), gm1 = p2 / (g + (R)1), pmag = sqrt(p2);
-                        uint32_t kind = 0;
-                        if (A.proc & CMC_BREMS) {
-                            c_pairs_br++;
-                            bool high;
-                            const BremsLook<R> BL = brems_lookup<R, false>(T, ct, g, gm1, high);
-                            c_high |= high;
-                            if (BL.sig > (R)0) {
-                                const double x = coef * (double)BL.sig * (phys::kC * (double)pmag / (double)g) * A.dt;
-                                const double P = -expm1(-x);
-                                const U4 r = A.rng.draw((uint32_t)j, cell, kTagAccBr);
-                                const double U1 = u53(r.x, r.y), U2 = u53(r.z, r.w);
-                                if (fabs(U1 - P) <= A.near_rel * P) c_near_br++;
-                                if (U1 < P && U2 < Pej) kind = kEvBr | ((A.proc & CMC_TRIDENT) ? kEvTrPending : 0u);
-                            }
-                        }
-                        if (A.proc & CMC_TRIDENT) {
-                            c_pairs_tr++;
-                            if (!kind) {
-                                const R sig = (R)phys::trident_sigma(T.Z, (double)g);
-                                if (sig > (R)0) {
-                                    const double x = coef * (double)sig * (phys::kC * (double)pmag / (double)g) * A.dt;
-                                    const double P = -expm1(-x);
-                                    const U4 r = A.rng.draw((uint32_t)j, cell, kTagAccTr);
-                                    const double U1 = u53(r.x, r.y), U2 = u53(r.z, r.w);
-                                    if (fabs(U1 - P) <= A.near_rel * P) c_near_tr++;
-                                    if (U1 < P && U2 < Pej) kind = kEvTr;
-                                }
-                            }
-                        }
-                        if (kind) {
-                            const int k = atomicAdd(&evcount, 1);
-                            if (k < kEvCap) W.ev[c * kEvCap + k] = ev_pack(0, j, me, ii, kind);
-                            if (reused) conflict = 1;
-                        }
-                    }
-                }
-            }
-            // ------------------------------ photon-ion pass
-            if ((A.proc & CMC_BH) && Ng0 > 0 && Ni > 0) {
-                key_order(Ng0, cell, kTagKeyG, A.rng, keys, pm, bcnt, redu);
-                key_order(Ni, cell, kTagKeyIG, A.rng, keys, pi, bcnt, redu);
-                const int N = Ng0 > Ni ? Ng0 : Ni;
-                const bool mobA = Ng0 >= Ni;
-                if (mobA) {
-                    for (int q = tid; q < Ng0; q += kThreads) inv[pm[q]] = (uint16_t)q;
-                    __syncthreads();
-                }
-                const int npass = mobA ? Ng0 : N;
-                double part = 0.0;
-                for (int q = tid; q < npass; q += kThreads) {
-                    const int j = mobA ? (int)inv[q] : q;
-                    const int mg = mobA ? q : (int)pm[q % Ng0];
-                    const double wg = A.ph.w[g0 + mg], wi = wion[pi[j % Ni]];
-                    part += wg < wi ? wg : wi;
-                }
-                nab_gi = block_sum(part, redd);
-                if (nab_gi > 0.0) {
-                    const double coef = n_g * n_I / nab_gi;
-                    for (int q = tid; q < npass; q += kThreads) {
-                        const int j = mobA ? (int)inv[q] : q;
-                        const int mg = mobA ? q : (int)pm[q % Ng0];
-                        const int ii = pi[j % Ni];
-                        const bool reused = !mobA && j + Ng0 < N;
-                        const int64_t ig = g0 + mg;
-                        c_pairs_bh++;
-                        const double Wg = A.ph.w[ig], Wi = wion[ii];
-                        const double Pej = Wi / (Wg > Wi ? Wg : Wi);
-                        const R rqx = (R)A.ph.px[ig], rqy = (R)A.ph.py[ig], rqz = (R)A.ph.pz[ig];
-                        const R k = sqrt(rqx * rqx + rqy * rqy + rqz * rqz);
-                        int ik; R wk; bool high;
-                        const R sig = bh_lookup<R>(T, ct, k, ik, wk, high);
-                        c_high |= high;
-                        if (sig > (R)0) {
-                            const double x = coef * (double)sig * (phys::kC * (double)k / (double)k) * A.dt;
-                            const double P = -expm1(-x);
-                            const U4 r = A.rng.draw((uint32_t)j, cell, kTagAccBh);
-                            const double U1 = u53(r.x, r.y), U2 = u53(r.z, r.w);
-                            if (fabs(U1 - P) <= A.near_rel * P) c_near_bh++;
-                            if (U1 < P && U2 < Pej) {
-                                const int kk = atomicAdd(&evcount, 1);
-                                if (kk < kEvCap) W.ev[c * kEvCap + kk] = ev_pack(1, j, mg, ii, kEvBh);
-                                if (reused) conflict = 1;
-                            }
-                        }
-                    }
-                }
-            }
-        }
-        const bool high_any = block_or(c_high, redi);
-        Tally t = {};
-        t.pairs_br = c_pairs_br; t.pairs_tr = c_pairs_tr; t.pairs_bh = c_pairs_bh;
-        t.near_br = c_near_br; t.near_tr = c_near_tr; t.near_bh = c_near_bh;
-        if (tid == 0) {
-            if (st) atomicOr(A.status, st);
-            if (high_any) atomicOr(A.status, CMC_ST_GAMMA_HIGH);
-            const int n = evcount;
-            W.flags[c] = st ? kFlagSkip : ((conflict || n > kEvCap) ? kFlagSlow : 0);
-            W.nev[c] = n < kEvCap ? n : kEvCap;
-            W.dens[c * 3 + 0] = n_e; W.dens[c * 3 + 1] = n_g; W.dens[c * 3 + 2] = n_I;
-        }
-        write_tallies(A, c, t, nab_ei, nab_gi, redl, redd8);
+// inclusive prefix sum over the team in thread order
+template <int kT>
+__device__ __forceinline__ uint32_t team_incl_scan(uint32_t v, uint32_t* red) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t u = __shfl_up(v, o, 64);
+        if (lane >= o) v += u;
+    }
+    if constexpr (kT == 64) {
+        return v;
+    } else {
+        const int w = threadIdx.x >> 6;
+        if (lane == 63) red[w] = v;
+        __syncthreads();
+        uint32_t before = 0;
+        for (int i = 0; i < w; ++i) before += red[i];
+        __syncthreads();
+        return v + before;
     }
 }
 
-// one wavefront per cell with events: sample, write products in pair order
+// exclusive scan of n counters in LDS, in place
+template <int kT>
+__device__ void team_excl_scan(uint32_t* a, int n, uint32_t* red) {
+    const int t = Team<kT>::tid();
+    const int per = (n + kT - 1) / kT;
+    const int lo = t * per, hi = min(n, lo + per);
+    uint32_t s = 0;
+    for (int i = lo; i < hi; ++i) s += a[i];
+    uint32_t run = team_incl_scan<kT>(s, red) - s;
+    for (int i = lo; i < hi; ++i) { const uint32_t v = a[i]; a[i] = run; run += v; }
+    Team<kT>::sync();
+}
+
+template <int kT>
+__device__ __forceinline__ int team_sum_i(int v, int* red) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if constexpr (kT == 64) {
+        return v;
+    } else {
+        const int w = threadIdx.x >> 6;
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) red[w] = v;
+        __syncthreads();
+        const int s = red[0] + red[1] + red[2] + red[3];
+        __syncthreads();
+        return s;
+    }
+}
+
+template <int kT>
+__device__ __forceinline__ bool team_any(bool v, int* red) {
+    if constexpr (kT == 64) return __ballot(v) != 0ull;
+    else return block_or(v, red) != 0;
+}
+
+// Sum of f(i) over i in [0, n) in one fixed order whatever the team size:
+// as 256 threads striding by 256, each wavefront's partials reduced by an
+// xor butterfly and the four wavefront totals added in order.  The two team
+// shapes therefore give bit-identical densities and n_ab.
+template <int kT, typename F>
+__device__ __forceinline__ double canon_sum(int n, F f, double* red) {
+    if constexpr (kT == 256) {
+        double s = 0.0;
+        for (int i = threadIdx.x; i < n; i += 256) s += f(i);
+        return block_sum(s, red);
+    } else {
+        const int l = threadIdx.x & 63;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        for (int b = l; b < n; b += 256) {
+            a0 += f(b);
+            if (b + 64 < n) a1 += f(b + 64);
+            if (b + 128 < n) a2 += f(b + 128);
+            if (b + 192 < n) a3 += f(b + 192);
+        }
+        return ((wave_sum(a0) + wave_sum(a1)) + wave_sum(a2)) + wave_sum(a3);
+    }
+}
+
+// Densities n = sum of W of the three species and the weight check, with
+// one team reduction (same order as canon_sum for each sum).
+struct Dens { double e, g, i; bool bad; };
+
+template <int kT>
+__device__ __forceinline__ Dens team_densities(const double* we, int Ne, const double* wg, int Ng,
+                                               const double* wi, int Ni, double* red3, int* redi) {
+    int bad = 0;
+    const auto chk = [&bad](double v) { bad |= !(v >= 0.0) || !isfinite(v); return v; };
+    Dens d;
+    if constexpr (kT == 256) {
+        double se = 0.0, sg = 0.0, si = 0.0;
+        for (int a = threadIdx.x; a < Ne; a += 256) se += chk(we[a]);
+        for (int a = threadIdx.x; a < Ng; a += 256) sg += chk(wg[a]);
+        for (int a = threadIdx.x; a < Ni; a += 256) si += chk(wi[a]);
+        se = wave_sum(se); sg = wave_sum(sg); si = wave_sum(si);
+        const bool wbad = __ballot(bad != 0) != 0ull;
+        const int w = threadIdx.x >> 6;
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) { red3[w * 3] = se; red3[w * 3 + 1] = sg; red3[w * 3 + 2] = si; redi[w] = wbad; }
+        __syncthreads();
+        d.e = ((red3[0] + red3[3]) + red3[6]) + red3[9];
+        d.g = ((red3[1] + red3[4]) + red3[7]) + red3[10];
+        d.i = ((red3[2] + red3[5]) + red3[8]) + red3[11];
+        d.bad = (redi[0] | redi[1] | redi[2] | redi[3]) != 0;
+        __syncthreads();
+    } else {
+        const int l = threadIdx.x & 63;
+        const auto sum4 = [&](const double* w, int n) {
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+            for (int b = l; b < n; b += 256) {
+                a0 += chk(w[b]);
+                if (b + 64 < n) a1 += chk(w[b + 64]);
+                if (b + 128 < n) a2 += chk(w[b + 128]);
+                if (b + 192 < n) a3 += chk(w[b + 192]);
+            }
+            return ((wave_sum(a0) + wave_sum(a1)) + wave_sum(a2)) + wave_sum(a3);
+        };
+        d.e = sum4(we, Ne); d.g = sum4(wg, Ng); d.i = sum4(wi, Ni);
+        d.bad = __ballot(bad != 0) != 0ull;
+    }
+    return d;
+}
+
+// sum of a packed counter word and OR of a flag over the team
+template <int kT>
+__device__ __forceinline__ void team_tail(uint64_t& packed, bool& any, uint64_t* redq, int* redi) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) packed += __shfl_xor(packed, o, 64);
+    const bool wany = __ballot(any) != 0ull;
+    if constexpr (kT == 64) {
+        any = wany;
+    } else {
+        const int w = threadIdx.x >> 6;
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) { redq[w] = packed; redi[w] = wany; }
+        __syncthreads();
+        packed = redq[0] + redq[1] + redq[2] + redq[3];
+        any = (redi[0] | redi[1] | redi[2] | redi[3]) != 0;
+    }
+}
+
+// Buckets of the rank sort: the power of two at or above n (at most 4096),
+// so that a bucket holds one or two keys on average.
+__host__ __device__ inline int rank_bucket_bits(int n) {
+    int b = 4;
+    while (b < 12 && (1 << b) < n) ++b;
+    return b;
+}
+
+// Order of n particles by (Philox key, index).  The keys are counted into
+// buckets by their top bits, scattered into bucket order (key and index
+// side by side), and each one's rank is its bucket's start plus the number
+// of bucket members before it; no result depends on the order of the LDS
+// atomics.  The keys are drawn twice (count, scatter) instead of being
+// stored.  inverse: out[i] = rank of i; else out[rank] = i.
+template <int kT>
+__device__ void rank_order(int n, uint32_t cell, uint32_t tag, const Rng& rng, uint32_t* sk,
+                           uint16_t* tmp, uint32_t* hist, uint16_t* out, bool inverse, uint32_t* red) {
+    const int t = Team<kT>::tid();
+    const int bb = rank_bucket_bits(n), nb = 1 << bb, sh = 32 - bb;
+    for (int b = t; b < nb; b += kT) hist[b] = 0u;
+    Team<kT>::sync();
+    const int nq = (n + 3) >> 2;
+    for (int q = t; q < nq; q += kT) {
+        const U4 r = rng.draw((uint32_t)q, cell, tag);
+        const uint32_t w4[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (4 * q + u < n) atomicAdd(&hist[w4[u] >> sh], 1u);
+    }
+    Team<kT>::sync();
+    team_excl_scan<kT>(hist, nb, red);
+    for (int q = t; q < nq; q += kT) {
+        const U4 r = rng.draw((uint32_t)q, cell, tag);
+        const uint32_t w4[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = 4 * q + u;
+            if (i < n) {
+                const uint32_t pos = atomicAdd(&hist[w4[u] >> sh], 1u);
+                sk[pos] = w4[u];
+                tmp[pos] = (uint16_t)i;
+            }
+        }
+    }
+    Team<kT>::sync();
+    // hist[b] is now the end of bucket b
+    for (int p = t; p < n; p += kT) {
+        const uint32_t k = sk[p];
+        const int i = tmp[p];
+        const int b = (int)(k >> sh);
+        const int lo = b ? (int)hist[b - 1] : 0, hi = (int)hist[b];
+        int r = lo;
+        for (int m = lo; m < hi; ++m) {
+            const uint32_t km = sk[m];
+            r += (km < k) | ((km == k) & ((int)tmp[m] < i));
+        }
+        if (inverse) out[i] = (uint16_t)r; else out[r] = (uint16_t)i;
+    }
+    Team<kT>::sync();
+}
+
+// j mod n for j < 2^14 from a float reciprocal (quotient off by at most one)
+__device__ __forceinline__ int mod_small(int j, int n, float rn) {
+    int r = j - (int)((float)j * rn) * n;
+    r += r < 0 ? n : 0;
+    r -= r >= n ? n : 0;
+    return r;
+}
+
+// per-team LDS of the pass kernel
+constexpr int kSliceMax = 168;   // >= kSliceBrems, kSliceBH
+
+__host__ __device__ inline size_t team_bytes(int cap, int rbytes) {
+    const size_t n = (size_t)((cap + 63) / 64 * 64);
+    return n * 10 + ((size_t)4 << rank_bucket_bits(cap)) + (size_t)kSliceMax * rbytes + 16;
+}
+
+struct TeamMem {
+    uint32_t* keys;   // keys in bucket order
+    uint16_t* tmp;    // particle of each bucket slot
+    uint32_t* hist;
+    uint16_t* ordM;   // mobile species: rank of each particle, or particle of each rank
+    uint16_t* ordI;   // ions: particle of each rank
+    unsigned char* slice;
+};
+
+__device__ __forceinline__ TeamMem carve_team(unsigned char* p, int cap, int rbytes) {
+    const size_t n = (size_t)((cap + 63) / 64 * 64);
+    TeamMem m;
+    m.keys = reinterpret_cast<uint32_t*>(p); p += n * 4;
+    m.tmp = reinterpret_cast<uint16_t*>(p); p += n * 2;
+    m.hist = reinterpret_cast<uint32_t*>(p); p += (size_t)4 << rank_bucket_bits(cap);
+    m.ordM = reinterpret_cast<uint16_t*>(p); p += n * 2;
+    m.ordI = reinterpret_cast<uint16_t*>(p); p += n * 2;
+    m.slice = p;
+    return m;
+}
+
+template <typename R>
+struct Elec { R g, gm1; double vrel; };
+
+// electron: gamma, gamma - 1 in R and the speed |p| c / gamma in FP64
+template <typename R>
+__device__ __forceinline__ Elec<R> electron_p(double dx, double dy, double dz) {
+    const R px = (R)dx, py = (R)dy, pz = (R)dz;
+    const R p2 = px * px + py * py + pz * pz;
+    Elec<R> e;
+    e.g = sqrt((R)1 + p2);
+    e.gm1 = p2 / (e.g + (R)1);
+    const R pmag = sqrt(p2);
+    e.vrel = phys::kC * (double)pmag / (double)e.g;
+    return e;
+}
+
+template <typename R>
+__device__ __forceinline__ R photon_k(double px, double py, double pz) {
+    const R qx = (R)px, qy = (R)py, qz = (R)pz;
+    return sqrt(qx * qx + qy * qy + qz * qz);
+}
+
+// one test settled with P = -expm1(-x) in FP64: the near-threshold count,
+// then the event iff U1 < P and U2 < P_ej
+__device__ __forceinline__ bool settle(double x, const U4& r, double rej, double near_rel, double Pej, int& near) {
+    const double U1 = u53(r.x, r.y);
+    if (!(U1 <= rej * x)) return false;
+    const double P = -expm1(-x);
+    if (fabs(U1 - P) <= near_rel * P) near++;
+    return U1 < P && u53(r.z, r.w) < Pej;
+}
+
+// flag a cell for the sequential kernel; it is listed once
+__device__ __forceinline__ void mark_slow(const Work& W, int64_t c) {
+    if (!(atomicOr(&W.flags[c], kFlagSlow) & kFlagSlow)) W.list_slow[atomicAdd(&W.counters[1], 1)] = (int32_t)c;
+}
+
+// a pair the bound on P left open, for the event kernel (the cell is listed
+// with its first one; beyond kCandCap the cell goes to the sequential kernel)
+__device__ __forceinline__ void push_cand(const Work& W, int64_t c, uint64_t rec) {
+    const int k = atomicAdd(&W.ncand[c], 1);
+    if (k == 0) W.list_ev[atomicAdd(&W.counters[0], 1)] = (int32_t)c;
+    if (k < kCandCap) W.cand[c * kCandCap + k] = rec;
+    else mark_slow(W, c);
+}
+
+// One pass of pair tests over all cells from the particles as they are at
+// the start of the step: kPass 0 electron-ion (Bremsstrahlung, then Trident
+// when Bremsstrahlung is not accepted), kPass 1 photon-ion (Bethe-Heitler).
+// A test is settled here when U1 > 2 (1 + near_rel) x: then P <= x < U1 and
+// |U1 - P| > near_rel P hold for the computed values, so the pair has no
+// event and no near-threshold count whatever P is.  The rare other pairs are
+// listed and settled with P by the event kernel.
+template <typename R, int kT, int kPass>
+__global__ __launch_bounds__(256) void k_pass(StepArgs A, TabView<R> T, Work W, int cap) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double redd[kWaves];
+    __shared__ double red3[kWaves * 3];
+    __shared__ uint32_t redu[kWaves];
+    __shared__ int redi[kWaves];
+    constexpr int kTeams = 256 / kT;
+    const int team = kT == 64 ? (int)(threadIdx.x >> 6) : 0;
+    const int t = Team<kT>::tid();
+    const size_t tstride = (team_bytes(cap, (int)sizeof(R)) + 15) / 16 * 16;
+    const TeamMem M = carve_team(smem_raw + tstride * team, cap, (int)sizeof(R));
+    R* slice = reinterpret_cast<R*>(M.slice);
+    const double rej = 2.0 * (1.0 + A.near_rel);
+
+    for (int64_t c = (int64_t)blockIdx.x * kTeams + team; c < A.n_cells; c += (int64_t)gridDim.x * kTeams) {
+        const uint32_t cell = (uint32_t)c;
+        if (W.cs[c].status) continue;                       // invalid cell (flagged by k_cell_state)
+        const int Ne = live(A.el, c), Ng = live(A.ph, c), Ni = live(A.io, c);
+        if (Ne > A.maxn || Ng > A.maxn || Ni > A.maxn) {
+            if (t == 0) atomicOr(A.status, CMC_ST_TOO_LARGE);
+            continue;
+        }
+        const bool ei = (A.proc & (CMC_BREMS | CMC_TRIDENT)) && Ne > 0 && Ni > 0;
+        const bool gi = (A.proc & CMC_BH) && Ng > 0 && Ni > 0;
+        // cells beyond the team's LDS go to the sequential kernel whole
+        if ((ei && (Ne > cap || Ni > cap)) || (gi && (Ng > cap || Ni > cap))) {
+            if (t == 0) mark_slow(W, c);
+            continue;
+        }
+        const int64_t e0 = A.el.off[c], g0 = A.ph.off[c], i0 = A.io.off[c];
+        const Dens d = team_densities<kT>(A.el.w + e0, Ne, A.ph.w + g0, Ng, A.io.w + i0, Ni, red3, redi);
+        if (d.bad) {
+            if (t == 0) atomicOr(A.status, CMC_ST_BAD_WEIGHT);
+            continue;
+        }
+        if (t == 0 && kPass == 0) { W.dens[c * 3 + 0] = d.e; W.dens[c * 3 + 1] = d.g; W.dens[c * 3 + 2] = d.i; }
+        if (!(kPass == 0 ? ei : gi)) continue;
+        const CellTab<R> ct = pick<R>(W.cs[c]);
+        const double* wion = A.io.w + i0;
+        const int Nm = kPass == 0 ? Ne : Ng;
+        const int64_t m0 = kPass == 0 ? e0 : g0;
+        const SpeciesDev& S = kPass == 0 ? A.el : A.ph;
+        if (kPass == 0) {
+            if (A.proc & CMC_BREMS)
+                for (int i = t; i < kSliceBrems; i += kT) slice[i] = slice_node_brems<R>(T, ct, i);
+        } else {
+            for (int i = t; i < kSliceBH; i += kT) slice[i] = slice_node_bh<R>(T, ct, i);
+        }
+        const bool mobA = Nm >= Ni;
+        const int N = mobA ? Nm : Ni;
+        // when every mobile particle pairs once the pair loop walks them in
+        // storage order: its first momenta are loaded before the sort
+        double qx = 0.0, qy = 0.0, qz = 0.0;
+        if (mobA && t < N) { qx = S.px[m0 + t]; qy = S.py[m0 + t]; qz = S.pz[m0 + t]; }
+        rank_order<kT>(Nm, cell, kPass == 0 ? kTagKeyE : kTagKeyG, A.rng, M.keys, M.tmp, M.hist, M.ordM, mobA, redu);
+        rank_order<kT>(Ni, cell, kPass == 0 ? kTagKeyIE : kTagKeyIG, A.rng, M.keys, M.tmp, M.hist, M.ordI, false, redu);
+        const float rNm = 1.0f / (float)Nm, rNi = 1.0f / (float)Ni;
+        const double* wm = S.w + m0;
+        const double nab = canon_sum<kT>(N, [&](int q) {
+            const int j = mobA ? (int)M.ordM[q] : q;
+            const int mi = mobA ? q : (int)M.ordM[mod_small(j, Nm, rNm)];
+            const double a = wm[mi], b = wion[M.ordI[mod_small(j, Ni, rNi)]];
+            return a < b ? a : b;
+        }, redd);
+        int high = 0;
+        if (nab > 0.0) {
+            const double coef = (kPass == 0 ? d.e : d.g) * d.i / nab;
+            for (int q = t; q < N; q += kT) {
+                const int j = mobA ? (int)M.ordM[q] : q;
+                const int mi = mobA ? q : (int)M.ordM[mod_small(j, Nm, rNm)];
+                double cx = qx, cy = qy, cz = qz;
+                if (mobA) {
+                    if (q + kT < N) { qx = S.px[m0 + q + kT]; qy = S.py[m0 + q + kT]; qz = S.pz[m0 + q + kT]; }
+                } else {
+                    cx = S.px[m0 + mi]; cy = S.py[m0 + mi]; cz = S.pz[m0 + mi];
+                }
+                uint32_t bits = 0;
+                if (kPass == 0) {
+                    const Elec<R> e = electron_p<R>(cx, cy, cz);
+                    if (A.proc & CMC_BREMS) {
+                        bool hi;
+                        const R sig = brems_sig_slice<R>(T, slice, e.g, e.gm1, hi);
+                        high |= hi;
+                        if (sig > (R)0) {
+                            const double x = coef * (double)sig * e.vrel * A.dt;
+                            const U4 r = A.rng.draw((uint32_t)j, cell, kTagAccBr);
+                            if (u53(r.x, r.y) <= rej * x) bits = 1u;
+                        }
+                    }
+                    if ((A.proc & CMC_TRIDENT) && !bits) {
+                        const R sig = (R)phys::trident_sigma(T.Z, (double)e.g);
+                        if (sig > (R)0) {
+                            const double x = coef * (double)sig * e.vrel * A.dt;
+                            const U4 r = A.rng.draw((uint32_t)j, cell, kTagAccTr);
+                            if (u53(r.x, r.y) <= rej * x) bits = 2u;
+                        }
+                    }
+                } else {
+                    const R k = photon_k<R>(cx, cy, cz);
+                    bool hi;
+                    const R sig = bh_sig_slice<R>(T, slice, k, hi);
+                    high |= hi;
+                    if (sig > (R)0) {
+                        const double x = coef * (double)sig * phys::kC * A.dt;
+                        const U4 r = A.rng.draw((uint32_t)j, cell, kTagAccBh);
+                        if (u53(r.x, r.y) <= rej * x) bits = 1u;
+                    }
+                }
+                if (bits) push_cand(W, c, ev_pack(kPass, j, mi, M.ordI[mod_small(j, Ni, rNi)], bits));
+            }
+            if (t == 0) W.coef[c * 2 + kPass] = coef;
+        }
+        if (t == 0) {
+            if (kPass == 0) {
+                A.ti[c * CMC_NI + CMC_I_PAIRS_BR] = (nab > 0.0 && (A.proc & CMC_BREMS)) ? N : 0;
+                A.ti[c * CMC_NI + CMC_I_PAIRS_TR] = (nab > 0.0 && (A.proc & CMC_TRIDENT)) ? N : 0;
+                A.td[c * CMC_ND + CMC_D_NAB_EI] = nab;
+            } else {
+                A.ti[c * CMC_NI + CMC_I_PAIRS_BH] = nab > 0.0 ? N : 0;
+                A.td[c * CMC_ND + CMC_D_NAB_GI] = nab;
+            }
+        }
+        if (team_any<kT>(high != 0, redi) && t == 0) atomicOr(A.status, CMC_ST_GAMMA_HIGH);
+        Team<kT>::sync();   // LDS of this cell is free
+    }
+}
+
+// One wavefront per cell with open pairs: settle them with P (same
+// arithmetic as the pass kernels, lookups from the full tables give the same
+// values as the slices), then apply the events in (pass, pair) order:
+// sample the energies, write the products, drop converted photons.
 template <typename R>
 __global__ __launch_bounds__(64) void k_events(StepArgs A, TabView<R> T, TabView<double> T64, Work W) {
-    __shared__ uint64_t rec[kEvCap];
+    __shared__ uint64_t rec[kCandCap];
     __shared__ uint32_t killed[CMC_MAX_PER_CELL / 32];
     const int lane = threadIdx.x;
-    for (int64_t c = blockIdx.x; c < A.n_cells; c += gridDim.x) {
-        const int n = W.nev[c];
-        if (W.flags[c] != 0 || n == 0) continue;
+    const int n_items = W.counters[0];
+    const double rej = 2.0 * (1.0 + A.near_rel);
+    for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
+        const int64_t c = W.list_ev[item];
+        if (W.flags[c] & kFlagSlow) continue;
         const uint32_t cell = (uint32_t)c;
-        // events in (pass, pair index) order
-        const uint64_t mine = lane < n ? W.ev[c * kEvCap + lane] : ~0ull;
-        const uint32_t key = lane < n ? ev_key(mine) : 0xFFFFFFFFu;
-        int rank = 0;
-        for (int l = 0; l < n; ++l) {
-            const uint32_t kl = __shfl(key, l, 64);
-            rank += kl < key;
+        const int nc = min(W.ncand[c], kCandCap);
+        const int64_t e0 = A.el.off[c], g0 = A.ph.off[c], i0 = A.io.off[c];
+        const int Ne = live(A.el, c), Ng0 = live(A.ph, c), Ni = live(A.io, c);
+        // ---- settle the open pairs
+        uint32_t kind = 0;
+        uint64_t mine = 0;
+        int near_br = 0, near_tr = 0, near_bh = 0;
+        bool reused = false;
+        if (lane < nc) {
+            mine = W.cand[c * kCandCap + lane];
+            const int pass = ev_pass(mine), j = ev_j(mine), mi = ev_m(mine), ii = ev_i(mine);
+            const uint32_t bits = ev_kind(mine);
+            const CellTab<R> ct = pick<R>(W.cs[c]);
+            const double coef = W.coef[c * 2 + pass];
+            const double Wi = A.io.w[i0 + ii];
+            if (pass == 0) {
+                const int64_t ie = e0 + mi;
+                const Elec<R> e = electron_p<R>(A.el.px[ie], A.el.py[ie], A.el.pz[ie]);
+                const double We = A.el.w[ie];
+                const double Pej = Wi / (We > Wi ? We : Wi);
+                if (bits & 1u) {
+                    bool hi;
+                    const R sig = brems_lookup<R, false>(T, ct, e.g, e.gm1, hi).sig;
+                    const double x = coef * (double)sig * e.vrel * A.dt;
+                    if (settle(x, A.rng.draw((uint32_t)j, cell, kTagAccBr), rej, A.near_rel, Pej, near_br))
+                        kind = kEvBr | ((A.proc & CMC_TRIDENT) ? kEvTrPending : 0u);
+                }
+                if ((A.proc & CMC_TRIDENT) && !kind) {
+                    const R sig = (R)phys::trident_sigma(T.Z, (double)e.g);
+                    if (sig > (R)0) {
+                        const double x = coef * (double)sig * e.vrel * A.dt;
+                        if (settle(x, A.rng.draw((uint32_t)j, cell, kTagAccTr), rej, A.near_rel, Pej, near_tr))
+                            kind = kEvTr;
+                    }
+                }
+                reused = Ne < Ni && j + Ne < Ni;   // the electron pairs again later
+            } else {
+                const R k = photon_k<R>(A.ph.px[g0 + mi], A.ph.py[g0 + mi], A.ph.pz[g0 + mi]);
+                int ik; R wk; bool hi;
+                const R sig = bh_lookup<R>(T, ct, k, ik, wk, hi);
+                const double x = coef * (double)sig * phys::kC * A.dt;
+                const double Wg = A.ph.w[g0 + mi];
+                const double Pej = Wi / (Wg > Wi ? Wg : Wi);
+                if (settle(x, A.rng.draw((uint32_t)j, cell, kTagAccBh), rej, A.near_rel, Pej, near_bh))
+                    kind = kEvBh;
+                reused = Ng0 < Ni && j + Ng0 < Ni;
+            }
         }
-        if (lane < n) rec[rank] = mine;
+        // an event on a particle used by a later pair of its pass: the
+        // sequential kernel redoes the cell
+        if (__ballot(kind != 0 && reused) != 0ull) {
+            if (lane == 0) mark_slow(W, c);
+            continue;
+        }
+        // ---- events in (pass, pair index) order
+        const unsigned long long evb = __ballot(kind != 0);
+        const int n = __popcll(evb);
+        const uint32_t key = kind ? ev_key(mine) : 0xFFFFFFFFu;
+        int rank = 0;
+        for (int l = 0; l < 64; ++l) {
+            if (!((evb >> l) & 1ull)) continue;
+            rank += __shfl(key, l, 64) < key;
+        }
+        __syncthreads();
+        if (kind) rec[rank] = (mine & ~(0x7Full << 48)) | ((uint64_t)kind << 48);
         __syncthreads();
         const uint64_t r = lane < n ? rec[lane] : 0ull;
         const bool live_ev = lane < n;
         const int pass = live_ev ? ev_pass(r) : 2;
-        const uint32_t kind = live_ev ? ev_kind(r) : 0u;
+        const uint32_t evk = live_ev ? ev_kind(r) : 0u;
         const int j = ev_j(r), mi = ev_m(r), ii = ev_i(r);
         const CellTab<double> ct64 = W.cs[c].d;
-        const int64_t e0 = A.el.off[c], g0 = A.ph.off[c], i0 = A.io.off[c];
-        const int Ng0 = live(A.ph, c);
         const int cap_ph = (int)(A.ph.off[c + 1] - g0);
         const int cap_ne = (int)(A.ne.off[c + 1] - A.ne.off[c]), cap_np = (int)(A.np.off[c + 1] - A.np.off[c]);
         const int cnt_ne0 = A.ne.count[c], cnt_np0 = A.np.count[c];
-        const double n_e = W.dens[c * 3 + 0], n_g = W.dens[c * 3 + 1], n_I = W.dens[c * 3 + 2];
         Tally t = {};
+        t.near_br = near_br; t.near_tr = near_tr; t.near_bh = near_bh;
         bool f_ph = false, f_tr = false, f_bh = false;
         double kx = 0, ky = 0, kz = 0, pxm = 0, pym = 0, pzm = 0, pxp = 0, pyp = 0, pzp = 0, Wm = 0;
         int64_t par = 0;
@@ -909,7 +1249,7 @@ __global__ __launch_bounds__(64) void k_events(StepArgs A, TabView<R> T, TabView
             par = ie;
             double px = A.el.px[ie], py = A.el.py[ie], pz = A.el.pz[ie];
             Wm = A.el.w[ie];
-            if (kind & kEvBr) {
+            if (evk & kEvBr) {
                 const U4 q = A.rng.draw((uint32_t)j, cell, kTagSmpBr);
                 const double p2d = px * px + py * py + pz * pz;
                 const double gd = sqrt(1.0 + p2d), gm1d = p2d / (gd + 1.0), pmd = sqrt(p2d);
@@ -927,18 +1267,15 @@ __global__ __launch_bounds__(64) void k_events(StepArgs A, TabView<R> T, TabView
                 t.W_br += Wm;
                 f_ph = true;
             }
-            bool tr = (kind & kEvTr) != 0;
-            if (kind & kEvTrPending) {
+            bool tr = (evk & kEvTr) != 0;
+            if (evk & kEvTrPending) {
                 // Trident on the electron left by Bremsstrahlung (same pair)
                 const double Wi = A.io.w[i0 + ii];
                 const double Pej = Wi / (Wm > Wi ? Wm : Wi);
-                const R rpx = (R)px, rpy = (R)py, rpz = (R)pz;
-                const R p2 = rpx * rpx + rpy * rpy + rpz * rpz;
-                const R g = sqrt((R)1 + p2), pmag = sqrt(p2);
-                const R sig = (R)phys::trident_sigma(T.Z, (double)g);
-                const double nab = A.td[c * CMC_ND + CMC_D_NAB_EI];
+                const Elec<R> e = electron_p<R>(px, py, pz);
+                const R sig = (R)phys::trident_sigma(T.Z, (double)e.g);
                 if (sig > (R)0) {
-                    const double x = (n_e * n_I / nab) * (double)sig * (phys::kC * (double)pmag / (double)g) * A.dt;
+                    const double x = W.coef[c * 2] * (double)sig * e.vrel * A.dt;
                     const double P = -expm1(-x);
                     const U4 q = A.rng.draw((uint32_t)j, cell, kTagAccTr);
                     const double U1 = u53(q.x, q.y), U2 = u53(q.z, q.w);
@@ -1019,8 +1356,12 @@ __global__ __launch_bounds__(64) void k_events(StepArgs A, TabView<R> T, TabView
             __syncthreads();
             if (f_bh) atomicOr(&killed[mi >> 5], 1u << (mi & 31));
             __syncthreads();
-            int wpos = 0;
-            for (int base = 0; base < ph_count; base += 64) {
+            // photons before the first converted one stay where they are
+            int first = f_bh ? mi : 0x7FFFFFFF;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) first = min(first, __shfl_xor(first, o, 64));
+            int wpos = first & ~63;
+            for (int base = wpos; base < ph_count; base += 64) {
                 const int a = base + lane;
                 bool keep = false;
                 double vx = 0, vy = 0, vz = 0, vw = 0;
@@ -1044,11 +1385,11 @@ __global__ __launch_bounds__(64) void k_events(StepArgs A, TabView<R> T, TabView
             }
             ph_count = wpos;
         }
-        // tallies of the events (the pair counts were written by k_decide)
-        long long iv[7] = {t.ev_br, t.ev_tr, t.ev_bh, t.near_tr, t.drop_ph, t.drop_el, t.drop_po};
+        // tallies of the events (the pair counts were written by the passes)
+        long long iv[9] = {t.ev_br, t.ev_tr, t.ev_bh, t.near_br, t.near_tr, t.near_bh, t.drop_ph, t.drop_el, t.drop_po};
         double dv[8] = {t.E_br, t.E_tr, t.E_bh, t.dE_el, t.dE_ph, t.W_br, t.W_tr, t.W_bh};
 #pragma unroll
-        for (int q = 0; q < 7; ++q)
+        for (int q = 0; q < 9; ++q)
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) iv[q] += __shfl_xor(iv[q], o, 64);
 #pragma unroll
@@ -1058,14 +1399,14 @@ __global__ __launch_bounds__(64) void k_events(StepArgs A, TabView<R> T, TabView
         if (lane == 0) {
             int64_t* ti = A.ti + c * CMC_NI;
             ti[CMC_I_EV_BR] = iv[0]; ti[CMC_I_EV_TR] = iv[1]; ti[CMC_I_EV_BH] = iv[2];
-            ti[CMC_I_NEAR_TR] += iv[3];
-            ti[CMC_I_DROP_PH] = iv[4]; ti[CMC_I_DROP_EL] = iv[5]; ti[CMC_I_DROP_PO] = iv[6];
+            ti[CMC_I_NEAR_BR] = iv[3]; ti[CMC_I_NEAR_TR] = iv[4]; ti[CMC_I_NEAR_BH] = iv[5];
+            ti[CMC_I_DROP_PH] = iv[6]; ti[CMC_I_DROP_EL] = iv[7]; ti[CMC_I_DROP_PO] = iv[8];
             double* td = A.td + c * CMC_ND + CMC_D_E_BR;
             for (int q = 0; q < 8; ++q) td[q] = dv[q];
             if (A.ph.count) A.ph.count[c] = ph_count;
             A.ne.count[c] = min(cap_ne, cnt_ne0 + n_tr + n_bh);
             A.np.count[c] = min(cap_np, cnt_np0 + n_tr + n_bh);
-            if (iv[4] + iv[5] + iv[6]) atomicOr(A.status, CMC_ST_OVERFLOW);
+            if (iv[6] + iv[7] + iv[8]) atomicOr(A.status, CMC_ST_OVERFLOW);
         }
         __syncthreads();
     }
@@ -1128,6 +1469,111 @@ int grid_for(int64_t n_cells) {
 
 using namespace cmc;
 
+// ------------------------------------------------------------------ decision launch
+// LDS of one team: the whole cell must fit (cap particles per species);
+// wavefront teams are limited to kWaveCap so that several workgroups of
+// four teams share a compute unit.
+constexpr int kWaveCap = 1024;
+constexpr size_t kLdsMax = 160 * 1024;
+
+static int team_cap(int team, int maxn, bool fp64) {
+    const int rb = fp64 ? 8 : 4;
+    int cap = team == 64 ? std::min(maxn, kWaveCap) : maxn;
+    const size_t static_lds = 256;
+    while (cap > 64 && (size_t)(256 / team) * ((team_bytes(cap, rb) + 15) / 16 * 16) + static_lds > kLdsMax)
+        cap -= 64;
+    return cap;
+}
+
+template <typename R, int kT>
+static void launch_pass_t(const StepArgs& A, const TabView<R>& T, const Work& W, int cap, size_t dshm,
+                          unsigned grid, hipStream_t st) {
+    if (A.proc & (CMC_BREMS | CMC_TRIDENT)) {
+        (void)hipFuncSetAttribute((const void*)k_pass<R, kT, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dshm);
+        hipLaunchKernelGGL((k_pass<R, kT, 0>), dim3(grid), dim3(256), dshm, st, A, T, W, cap);
+    }
+    if (A.proc & CMC_BH) {
+        (void)hipFuncSetAttribute((const void*)k_pass<R, kT, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dshm);
+        hipLaunchKernelGGL((k_pass<R, kT, 1>), dim3(grid), dim3(256), dshm, st, A, T, W, cap);
+    }
+}
+
+// the pass kernels with teams of `team` threads
+static cmc_status launch_passes(const StepArgs& A, const cmc_tables_s* t, const Work& W, bool fp64, int team,
+                                hipStream_t st) {
+    const int cap = team_cap(team, A.maxn, fp64);
+    const size_t per = (team_bytes(cap, fp64 ? 8 : 4) + 15) / 16 * 16;
+    const size_t dshm = per * (size_t)(256 / team);
+    const int64_t units = team == 64 ? (A.n_cells + 3) / 4 : A.n_cells;
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(units, 256 * 64));
+    if (fp64) {
+        if (team == 64) launch_pass_t<double, 64>(A, view64(t), W, cap, dshm, grid, st);
+        else launch_pass_t<double, 256>(A, view64(t), W, cap, dshm, grid, st);
+    } else {
+        if (team == 64) launch_pass_t<float, 64>(A, view32(t), W, cap, dshm, grid, st);
+        else launch_pass_t<float, 256>(A, view32(t), W, cap, dshm, grid, st);
+    }
+    CMC_CHECK_LAUNCH("cmc_collide_step: k_pass");
+    return CMC_OK;
+}
+
+// Autotuner of the pass kernels' team shape: on the first step of a launch
+// shape (device, cells, max_per_cell, processes, precision) both shapes are
+// timed on that step's own cells (the pass kernels leave the particles
+// untouched; the cell state is cleared again afterwards) and the faster one
+// is kept for the process.  The host waits for the timing once per shape.
+struct TuneKey {
+    int dev;
+    int64_t n_cells;
+    int maxn, proc, precision;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(dev, n_cells, maxn, proc, precision) < std::tie(o.dev, o.n_cells, o.maxn, o.proc, o.precision);
+    }
+};
+static std::mutex g_tune_mu;
+static std::map<TuneKey, int> g_tune;
+
+static bool tune_lookup(const TuneKey& k, int& team) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tune.find(k);
+    if (it == g_tune.end()) return false;
+    team = it->second;
+    return true;
+}
+
+static void tune_store(const TuneKey& k, int team) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune[k] = team;
+}
+
+static cmc_status tune_passes(const StepArgs& A, const cmc_tables_s* t, const Work& W, bool fp64, hipStream_t st,
+                              int& best) {
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) { set_error("cmc_collide_step: hipEventCreate failed"); return CMC_EDEVICE; }
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        set_error("cmc_collide_step: hipEventCreate failed");
+        return CMC_EDEVICE;
+    }
+    float best_ms = 0.0f;
+    best = 256;
+    cmc_status rc = CMC_OK;
+    for (int team : {256, 64}) {
+        if ((rc = launch_passes(A, t, W, fp64, team, st)) != CMC_OK) break;   // warm-up
+        (void)hipEventRecord(e0, st);
+        for (int r = 0; r < 3 && rc == CMC_OK; ++r) rc = launch_passes(A, t, W, fp64, team, st);
+        (void)hipEventRecord(e1, st);
+        if (rc != CMC_OK) break;
+        if (hipEventSynchronize(e1) != hipSuccess) { set_error("cmc_collide_step: timing failed"); rc = CMC_EDEVICE; break; }
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (team == 256 || ms < best_ms) { best_ms = ms; best = team; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
+}
+
 extern "C" size_t cmc_step_workspace_bytes(int64_t n_cells, int32_t schedule) {
     if (n_cells <= 0 || schedule == CMC_SCHED_CELL) return 0;
     return work_bytes(n_cells);
@@ -1158,10 +1604,10 @@ extern "C" cmc_status cmc_collide_step(cmc_tables t, const cmc_cells* cells, cmc
     CMC_REQUIRE((P->processes & ~7u) == 0, CMC_EINVAL, "cmc_collide_step: unknown process bits");
     CMC_REQUIRE(P->precision == CMC_FP64 || P->precision == CMC_FP32, CMC_EINVAL,
                 "cmc_collide_step: unknown precision %d", P->precision);
-    CMC_REQUIRE(P->schedule >= 0 && P->schedule <= 2, CMC_EINVAL, "cmc_collide_step: unknown schedule");
+    CMC_REQUIRE(P->schedule >= 0 && P->schedule <= 3, CMC_EINVAL, "cmc_collide_step: unknown schedule");
     CMC_REQUIRE(P->max_per_cell >= 1 && P->max_per_cell <= CMC_MAX_PER_CELL, CMC_ERANGE,
                 "cmc_collide_step: max_per_cell = %d outside [1, %d]", P->max_per_cell, CMC_MAX_PER_CELL);
-    CMC_REQUIRE(P->near_rel >= 0.0, CMC_EINVAL, "cmc_collide_step: near_rel < 0");
+    CMC_REQUIRE(P->near_rel >= 0.0 && P->near_rel <= 1.0, CMC_EINVAL, "cmc_collide_step: near_rel outside [0, 1]");
     StepArgs A{};
     cmc_status s;
     if ((s = set_species(A.el, electrons, "electrons", false, true)) != CMC_OK) return s;
@@ -1186,7 +1632,7 @@ extern "C" cmc_status cmc_collide_step(cmc_tables t, const cmc_cells* cells, cmc
     const bool fp64 = P->precision == CMC_FP64;
     if (P->schedule == CMC_SCHED_CELL) {
         // one sequential workgroup per cell for every cell
-        A.only_slow = nullptr;
+        A.list = nullptr; A.list_n = nullptr;
         if (fp64) {
             (void)hipFuncSetAttribute((const void*)k_collide<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
             hipLaunchKernelGGL(k_collide<double>, dim3(grid), dim3(kThreads), shm, st, A, view64(t), view64(t));
@@ -1201,27 +1647,48 @@ extern "C" cmc_status cmc_collide_step(cmc_tables t, const cmc_cells* cells, cmc
     CMC_REQUIRE(workspace != nullptr && workspace_bytes >= need, CMC_EINVAL,
                 "cmc_collide_step: workspace of %zu bytes required (got %zu)", need, workspace_bytes);
     const Work W = carve_work(workspace, A.n_cells);
-    A.only_slow = W.flags;
-    const size_t dshm = decide_smem_bytes(A.maxn);
-    hipLaunchKernelGGL(k_cell_state, dim3((unsigned)std::min<int64_t>((A.n_cells + 255) / 256, 4096)), dim3(256), 0, st,
-                       A.Zs, A.ni, A.Te, A.n_cells, (double)t->Z, t->ax, W.cs);
+    const auto cell_state = [&]() {
+        hipLaunchKernelGGL(k_cell_state, dim3((unsigned)std::min<int64_t>((A.n_cells + 63) / 64, 4096)), dim3(64),
+                           0, st, A.Zs, A.ni, A.Te, A.n_cells, (double)t->Z, t->ax, W, A.ti, A.td, A.status);
+    };
+    cell_state();
     CMC_CHECK_LAUNCH("cmc_collide_step: k_cell_state");
+    int team = P->schedule == CMC_SCHED_WAVE ? 64 : 256;
+    if (P->schedule == CMC_SCHED_AUTO) {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        const TuneKey key{dev, A.n_cells, A.maxn, (int)A.proc, P->precision};
+        if (!tune_lookup(key, team)) {
+            hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+            (void)hipStreamIsCapturing(st, &cap);
+            if (cap == hipStreamCaptureStatusNone) {
+                cmc_status s2 = tune_passes(A, t, W, fp64, st, team);
+                if (s2 != CMC_OK) return s2;
+                tune_store(key, team);
+                cell_state();   // the timing runs filled the cell lists
+                CMC_CHECK_LAUNCH("cmc_collide_step: k_cell_state");
+            } else {
+                team = 256;     // no timing under graph capture: workgroup teams
+            }
+        }
+    }
+    cmc_status s1 = launch_passes(A, t, W, fp64, team, st);
+    if (s1 != CMC_OK) return s1;
+    // open pairs and events of the listed cells, then the sequential kernel
+    // on its list (both lists are short: small grids)
+    A.list = W.list_slow; A.list_n = W.counters + 1;
+    const unsigned gev = (unsigned)std::min<int64_t>(A.n_cells, 512);
+    const unsigned gslow = (unsigned)std::min<int64_t>(A.n_cells, 256);
     if (fp64) {
-        (void)hipFuncSetAttribute((const void*)k_decide<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dshm);
-        hipLaunchKernelGGL(k_decide<double>, dim3(grid), dim3(kThreads), dshm, st, A, view64(t), W);
-        CMC_CHECK_LAUNCH("cmc_collide_step: k_decide");
-        hipLaunchKernelGGL(k_events<double>, dim3(grid), dim3(64), 0, st, A, view64(t), view64(t), W);
+        hipLaunchKernelGGL(k_events<double>, dim3(gev), dim3(64), 0, st, A, view64(t), view64(t), W);
         CMC_CHECK_LAUNCH("cmc_collide_step: k_events");
         (void)hipFuncSetAttribute((const void*)k_collide<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-        hipLaunchKernelGGL(k_collide<double>, dim3(grid), dim3(kThreads), shm, st, A, view64(t), view64(t));
+        hipLaunchKernelGGL(k_collide<double>, dim3(gslow), dim3(kThreads), shm, st, A, view64(t), view64(t));
     } else {
-        (void)hipFuncSetAttribute((const void*)k_decide<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dshm);
-        hipLaunchKernelGGL(k_decide<float>, dim3(grid), dim3(kThreads), dshm, st, A, view32(t), W);
-        CMC_CHECK_LAUNCH("cmc_collide_step: k_decide");
-        hipLaunchKernelGGL(k_events<float>, dim3(grid), dim3(64), 0, st, A, view32(t), view64(t), W);
+        hipLaunchKernelGGL(k_events<float>, dim3(gev), dim3(64), 0, st, A, view32(t), view64(t), W);
         CMC_CHECK_LAUNCH("cmc_collide_step: k_events");
         (void)hipFuncSetAttribute((const void*)k_collide<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-        hipLaunchKernelGGL(k_collide<float>, dim3(grid), dim3(kThreads), shm, st, A, view32(t), view64(t));
+        hipLaunchKernelGGL(k_collide<float>, dim3(gslow), dim3(kThreads), shm, st, A, view32(t), view64(t));
     }
     CMC_CHECK_LAUNCH("cmc_collide_step: k_collide");
     return CMC_OK;

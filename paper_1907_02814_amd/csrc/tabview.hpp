@@ -140,6 +140,59 @@ __device__ __forceinline__ R bh_lookup(const TabView<R>& T, const CellTab<R>& c,
     return lerp(blend_L<R>(S, 1, ik, c, 0), blend_L<R>(S, 1, ik + 1, c, 0), wk);
 }
 
+// ------------------------------------------------------------------ per-cell slices
+// The screening blend of a cross-section array at every energy node of one
+// cell, staged once per cell: a lookup then only interpolates the slice
+// along energy.  Same operations in the same order as brems_lookup and
+// bh_lookup, so the results are identical.
+constexpr int kSliceBrems = grid::kNR + grid::kRel + grid::kUR;   // NR | rel | UR nodes
+constexpr int kSliceBH = grid::kBH;
+
+template <typename R>
+__device__ __forceinline__ R slice_node_brems(const TabView<R>& T, const CellTab<R>& c, int i) {
+    if (i < grid::kNR) return blend_N<R>(T[grid::kSigN], 1, i, c, 0);
+    i -= grid::kNR;
+    if (i < grid::kRel) return blend_L<R>(T[grid::kSigR], 1, i, c, 0);
+    return blend_L<R>(T[grid::kSigU], 1, i - grid::kRel, c, 0);
+}
+
+template <typename R>
+__device__ __forceinline__ R slice_node_bh(const TabView<R>& T, const CellTab<R>& c, int i) {
+    return blend_L<R>(T[grid::kSigB], 1, i, c, 0);
+}
+
+// Bremsstrahlung sigma of an electron from the cell's slice (regimes and
+// clamping as brems_lookup)
+template <typename R>
+__device__ __forceinline__ R brems_sig_slice(const TabView<R>& T, const R* sl, R g, R g1m1, bool& high) {
+    high = false;
+    if (!(g1m1 > (R)(grid::kTminEv / grid::kMec2Ev))) return (R)0;
+    int ig; R wg; bool in;
+    if (g <= (R)2) {
+        locate<R>(log(g1m1), T.ax.nr, ig, wg, in);
+        return lerp(sl[ig], sl[ig + 1], wg);
+    }
+    const bool rel = g <= (R)100;
+    R u;
+    if (!rel && g > (R)grid::kTop) { high = true; u = (R)log(grid::kTop); } else { u = log(g); }
+    locate<R>(u, rel ? T.ax.rel : T.ax.ur, ig, wg, in);
+    const R* s = sl + (rel ? grid::kNR : grid::kNR + grid::kRel);
+    return lerp(s[ig], s[ig + 1], wg);
+}
+
+// Bethe-Heitler sigma of a photon from the cell's slice (as bh_lookup)
+template <typename R>
+__device__ __forceinline__ R bh_sig_slice(const TabView<R>& T, const R* sl, R k, bool& high) {
+    high = false;
+    if (!(k > (R)2)) return (R)0;
+    R x = k - (R)2;
+    if (k > (R)grid::kTop) { high = true; x = (R)(grid::kTop - 2.0); }
+    if (x < (R)grid::kBHx0) return sl[0] * (x / (R)grid::kBHx0);
+    int ik; R wk; bool in;
+    locate<R>(log(x), T.ax.bh, ik, wk, in);
+    return lerp(sl[ik], sl[ik + 1], wk);
+}
+
 // ------------------------------------------------------------------ sampling
 // blended CDF value j of the rows at energy nodes i, i+1 (kind: 0 (g, L),
 // 1 (g, eta, L), 2 one-dimensional)
