@@ -2,13 +2,20 @@
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg2]
 
-Prints one JSON line: pair evaluations per second of the timed steps (all
-processes' pair tests, summed), the FP32 form against the plain FP64 form on
-the same cells, the HBM roofline of the step kernel (algorithmic bytes per
-launch over the kernel time measured with HIP events on the launch stream)
-and the FP64 CPU oracle timed on a bounded sample of the same workload.
+Prints one JSON line: pair evaluations per second over the K timed steps
+(the pair tests of all processes, summed; inputs resident in HBM), the FP32
+form against the plain FP64 form on the same cells, the HBM roofline of the
+pair-test kernel (algorithmic bytes per launch over its duration measured
+with HIP events recorded on its own stream around every launch) and the FP64
+CPU oracle timed on a bounded sample of the same workload.
+
+python bench.py --copy-calibration runs only a device-to-device copy of
+known size: the counter runs that measure the kernel's HBM traffic read the
+same counters on it to scale them.
 """
 import argparse
+import ctypes
+import hashlib
 import json
 import os
 import sys
@@ -21,6 +28,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "pair evaluations/sec + % HBM peak; FP32-batched vs FP64-plain at 1e-5 rel err"
+COUNTERS = os.path.join(ROOT, "profiles", "k_pass_bh_cfg2_counters.txt")
+COPY_BYTES = 1 << 30
 
 WORKLOADS = {
     "cfg2": ("Bethe-Heitler pairs, FP32 tables + FP64 tallies: 4096 cells x (1024 photons + "
@@ -33,65 +42,123 @@ WORKLOADS = {
 }
 
 
+def source_digest():
+    """SHA-256 of the HIP sources: stored counter figures are used only
+    while the kernels they were taken on are unchanged."""
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1907_02814_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp")):
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
 def algorithmic_bytes(wl):
-    """One read of every live record per pass (mobile: px, py, pz, w = 32 B;
-    ion: w = 8 B) + per-cell parameters (24 B) and tallies (12*8 + 10*8 B)."""
+    """Bytes the pair tests of one step must move: one read of every live
+    record per pass (mobile px, py, pz, w = 32 B; ion w = 8 B) and the
+    per-cell tallies the passes write (pairs and n_ab: 16 B per pass)."""
     ne = int(np.diff(wl.electrons["off"]).sum())
     ng = int(wl.photons["count"].sum())
     ni = int(np.diff(wl.ions["off"]).sum())
-    n = wl.n_cells
-    passes_i = 0
     b = 0
     if wl.processes & 5:
-        b += 32 * ne; passes_i += 1
+        b += 32 * ne + 8 * ni + 16 * wl.n_cells
     if wl.processes & 2:
-        b += 32 * ng; passes_i += 1
-    b += 8 * ni * passes_i
-    b += n * (24 + 12 * 8 + 10 * 8)
+        b += 32 * ng + 8 * ni + 16 * wl.n_cells
     return b
 
 
-def pair_evals(ti):
-    return int(ti[:, 0:3].sum())
+def step_bytes(wl):
+    """Whole-step algorithmic bytes: the passes plus the cell parameters
+    (24 B) and the full tally rows (12 * 8 + 10 * 8 B) per cell."""
+    return algorithmic_bytes(wl) + wl.n_cells * (24 + 12 * 8 + 10 * 8)
 
 
-def run_gpu(wl, precision, steps, warmup, seed=1):
+class HipEvents:
+    """Raw hipEvent_t handles (the library records them on its launch
+    stream; torch's events only see torch's current stream)."""
+
+    def __init__(self):
+        self.lib = ctypes.CDLL("libamdhip64.so")
+        self.lib.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        self.lib.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
+        self.lib.hipEventDestroy.argtypes = [ctypes.c_void_p]
+
+    def create(self, n):
+        out = []
+        for _ in range(n):
+            e = ctypes.c_void_p()
+            rc = self.lib.hipEventCreate(ctypes.byref(e))
+            if rc != 0:
+                raise RuntimeError(f"hipEventCreate failed ({rc})")
+            out.append(e.value)
+        return out
+
+    def elapsed_ms(self, a, b):
+        ms = ctypes.c_float()
+        rc = self.lib.hipEventElapsedTime(ctypes.byref(ms), ctypes.c_void_p(a), ctypes.c_void_p(b))
+        if rc != 0:
+            raise RuntimeError(f"hipEventElapsedTime failed ({rc})")
+        return float(ms.value)
+
+    def destroy(self, evs):
+        for e in evs:
+            self.lib.hipEventDestroy(ctypes.c_void_p(e))
+
+
+def run_gpu(wl, precision, steps, warmup, schedule, seed=1):
     import torch
     import paper_1907_02814_amd as cmc
     dev = torch.device("cuda:0")
     g = wl.copy().to_torch(dev)
     tab = cmc.build_tables(wl.Z)
     st = cmc.StepState(tab, g.cells, g.electrons, g.photons, g.ions, g.new_el, g.new_po, dt=wl.dt,
-                       seed=seed, processes=wl.processes, precision=precision)
+                       seed=seed, processes=wl.processes, precision=precision, schedule=schedule)
     stream = torch.cuda.current_stream()
+    H = HipEvents()
+    evs = H.create(2 * steps)
     for s in range(warmup):
-        st.step(s)
+        st.step(s, stream)
     torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
-    evals = 0
     t0 = time.perf_counter()
     for i in range(steps):
-        ev[i][0].record(stream)
-        st.step(warmup + i)
-        ev[i][1].record(stream)
+        st.step(warmup + i, stream, events=(evs[2 * i], evs[2 * i + 1]))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kms = [a.elapsed_time(b) for a, b in ev]
-    # pair evaluations of the timed steps: replay the tallies of each step
-    # would need a sync per step; the last step's tallies times the step count
-    # is exact only for stationary cells, so count them step by step in a
-    # second, untimed pass over the same steps
+    pass_ms = [H.elapsed_ms(evs[2 * i], evs[2 * i + 1]) for i in range(steps)]
+    H.destroy(evs)
+    status = int(st.status.item())
+    # pair evaluations of the timed steps, counted step by step in a second,
+    # untimed run of the same steps from the same state
     g2 = wl.copy().to_torch(dev)
     st2 = cmc.StepState(tab, g2.cells, g2.electrons, g2.photons, g2.ions, g2.new_el, g2.new_po,
-                        dt=wl.dt, seed=seed, processes=wl.processes, precision=precision)
+                        dt=wl.dt, seed=seed, processes=wl.processes, precision=precision, schedule=schedule)
     for s in range(warmup):
         st2.step(s)
+    evals = 0
     for i in range(steps):
         st2.step(warmup + i)
         evals += int(st2.ti[:, 0:3].sum().item())
-    status = int(st.status.item())
-    return {"wall_s": wall, "kernel_ms": kms, "evals": evals, "status": status,
+    return {"wall_s": wall, "pass_ms": pass_ms, "evals": evals, "status": status,
             "events": st.ti[:, 3:6].sum(0).tolist()}
+
+
+def stored_traffic(kernel_ms_unused=None):
+    """HBM bytes per launch of the pass kernel from the stored counter runs
+    (FETCH_SIZE + WRITE_SIZE, each scaled by the same counter on a copy of
+    known size), or None when absent or taken on other kernel sources."""
+    try:
+        with open(COUNTERS) as fh:
+            kv = dict(l.split(":", 1) for l in fh if ":" in l and not l.startswith("#"))
+        kv = {k.strip(): v.strip() for k, v in kv.items()}
+        if kv.get("source_sha256") != source_digest():
+            return None
+        fetch = float(kv["pass FETCH_SIZE KiB/dispatch"]) * float(kv["copy read scale"])
+        write = float(kv["pass WRITE_SIZE KiB/dispatch"]) * float(kv["copy write scale"])
+        return (fetch + write) * 1024.0
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(wl, budget_s=12.0, seed=1):
@@ -115,48 +182,72 @@ def cpu_baseline(wl, budget_s=12.0, seed=1):
                       f"{evals} pair evaluations in {el:.2f} s (FP64, OpenMP over cells)"}
 
 
+def copy_calibration():
+    import torch
+    a = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device="cuda:0").uniform_()
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": COPY_BYTES, "dispatches": 3}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="cfg2", choices=sorted(WORKLOADS))
+    ap.add_argument("--schedule", default="auto", choices=["auto", "group", "wave", "cell"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 plain comparison")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a device copy of known size (counter calibration)")
     a = ap.parse_args()
     if a.gpus != 1:
-        print("bench.py: this build runs on one GPU; --gpus must be 1 (the step shards by cells "
-              "with no exchange, see DESIGN.md)", file=sys.stderr)
+        print("bench.py: one GPU only (--gpus 1); cells are independent within a step, so the "
+              "path shards by contiguous cell ranges with no exchange, but this build runs and "
+              "measures one GPU's share", file=sys.stderr)
         sys.exit(2)
-    import torch
+    if a.copy_calibration:
+        copy_calibration()
+        return
     import paper_1907_02814_amd as cmc
     from paper_1907_02814_amd import workloads as W
+    sched = {"auto": cmc.SCHED_AUTO, "group": cmc.SCHED_GROUP, "wave": cmc.SCHED_WAVE,
+             "cell": cmc.SCHED_CELL}[a.schedule]
     print(f"[bench] generating {a.workload}", file=sys.stderr, flush=True)
     wl = getattr(W, a.workload)()
-    fp32 = run_gpu(wl, cmc.FP32, a.steps, a.warmup)
-    print(f"[bench] fp32 done: {fp32['wall_s']*1e3/a.steps:.3f} ms/step", file=sys.stderr, flush=True)
-    fp64 = None if a.no_fp64 else run_gpu(wl, cmc.FP64, a.steps, a.warmup)
+    fp32 = run_gpu(wl, cmc.FP32, a.steps, a.warmup, sched)
+    print(f"[bench] fp32 done: {fp32['wall_s'] * 1e3 / a.steps:.3f} ms/step", file=sys.stderr, flush=True)
+    fp64 = None if a.no_fp64 else run_gpu(wl, cmc.FP64, a.steps, a.warmup, sched)
     if fp64:
-        print(f"[bench] fp64 done: {fp64['wall_s']*1e3/a.steps:.3f} ms/step", file=sys.stderr, flush=True)
-    kavg = float(np.mean(fp32["kernel_ms"]))
+        print(f"[bench] fp64 done: {fp64['wall_s'] * 1e3 / a.steps:.3f} ms/step", file=sys.stderr, flush=True)
+    kavg = float(np.mean(fp32["pass_ms"]))
     alg = algorithmic_bytes(wl)
     achieved = alg / (kavg * 1e-3) / 1e9
     ms = fp32["wall_s"] * 1e3 / a.steps
     value = fp32["evals"] / fp32["wall_s"]
+    traffic = stored_traffic() if a.workload == "cfg2" and a.schedule == "auto" else None
+    kname = {1: "k_pass<float,*,0>", 2: "k_pass<float,*,1>"}.get(
+        (1 if wl.processes & 5 else 0) + (2 if wl.processes & 2 else 0), "k_pass<float,*,0> + k_pass<float,*,1>")
     out = {
         "metric": METRIC, "value": value, "unit": "pair-evals/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "fp32 lookups + fp64 probability/tallies",
         "data": "synthetic",
         "config": {"workload": f"{a.workload}: {WORKLOADS[a.workload]}", "cells": wl.n_cells,
-                   "pairs_per_step": fp32["evals"] // a.steps, "parallelism": "single GPU, cells"},
+                   "pairs_per_step": fp32["evals"] // a.steps, "schedule": a.schedule,
+                   "parallelism": "single GPU, cells"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_collide<float>", "kernel_ms": kavg, "alg_bytes_per_launch": alg},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": kname, "kernel_ms": kavg, "alg_bytes_per_launch": alg},
+        "step_hbm_frac": step_bytes(wl) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "status": fp32["status"],
     }
     if fp64:
         v64 = fp64["evals"] / fp64["wall_s"]
-        k64 = float(np.mean(fp64["kernel_ms"]))
+        k64 = float(np.mean(fp64["pass_ms"]))
         out["fp64_plain"] = {"value": v64, "ms_per_step": fp64["wall_s"] * 1e3 / a.steps,
                              "kernel_ms": k64, "hbm_frac": alg / (k64 * 1e-3) / 1e9 / HBM_PEAK_GBS}
         out["fp32_speedup_vs_fp64"] = value / v64

@@ -126,6 +126,10 @@ typedef struct {
                               per cell (<= CMC_MAX_PER_CELL); sizes the launch */
     double near_rel;       /* band |U - P| <= near_rel * P counted as near-threshold,
                               in [0, 1] (default 1e-6)                        */
+    void* pass_events[2];  /* optional hipEvent_t pair (NULL: none), recorded on
+                              the stream just before and just after the pair-test
+                              kernels of the step, to time them; ignored by
+                              CMC_SCHED_CELL                                  */
 } cmc_step_params;
 
 #define CMC_MAX_PER_CELL 16384

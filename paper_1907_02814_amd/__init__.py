@@ -56,7 +56,7 @@ class _Species(C.Structure):
 class _StepParams(C.Structure):
     _fields_ = [("dt", C.c_double), ("seed", C.c_uint64), ("step", C.c_uint64),
                 ("processes", C.c_uint32), ("precision", C.c_int32), ("schedule", C.c_int32),
-                ("max_per_cell", C.c_int32), ("near_rel", C.c_double)]
+                ("max_per_cell", C.c_int32), ("near_rel", C.c_double), ("pass_events", _vp * 2)]
 
 
 class _Tallies(C.Structure):
@@ -231,8 +231,12 @@ class StepState:
         self.wsb = wsb
         self._refs = (cells, electrons, photons, ions, new_el, new_po)
 
-    def step(self, step: int, stream=None):
+    def step(self, step: int, stream=None, events=None):
+        """One step; `events` = optional pair of raw hipEvent_t handles
+        recorded around the pair-test kernels."""
         self.params.step = int(step)
+        self.params.pass_events[0] = events[0] if events else None
+        self.params.pass_events[1] = events[1] if events else None
         _check(get_lib().cmc_collide_step(self.tables.handle, C.byref(self.cells), C.byref(self.sp[0]),
                                     C.byref(self.sp[1]), C.byref(self.sp[2]), C.byref(self.sp[3]),
                                     C.byref(self.sp[4]), C.byref(self.params), C.byref(self.tal),

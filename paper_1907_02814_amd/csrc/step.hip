@@ -1672,8 +1672,10 @@ extern "C" cmc_status cmc_collide_step(cmc_tables t, const cmc_cells* cells, cmc
             }
         }
     }
+    if (P->pass_events[0]) (void)hipEventRecord(static_cast<hipEvent_t>(P->pass_events[0]), st);
     cmc_status s1 = launch_passes(A, t, W, fp64, team, st);
     if (s1 != CMC_OK) return s1;
+    if (P->pass_events[1]) (void)hipEventRecord(static_cast<hipEvent_t>(P->pass_events[1]), st);
     // open pairs and events of the listed cells, then the sequential kernel
     // on its list (both lists are short: small grids)
     A.list = W.list_slow; A.list_n = W.counters + 1;
