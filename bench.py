@@ -175,7 +175,7 @@ def cpu_baseline(wl, budget_s=12.0, seed=1):
         evals += int(ti[:, 0:3].sum())
         steps += 1
         el = time.perf_counter() - t0
-        if el > budget_s or steps >= 50:
+        if el > budget_s or steps >= 1000:
             break
     return {"value": evals / el, "unit": "pair-evals/s", "cores": cores, "kind": "oracle",
             "sample": f"{steps} step(s) of all {wl.n_cells} cells of the same workload, "

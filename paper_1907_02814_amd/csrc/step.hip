@@ -251,6 +251,28 @@ struct CellShared {
     CellTab<double> ct64;   // lookup state of the (rare) event branch
 };
 
+template <typename R>
+struct Elec { R g, gm1; double vrel; };
+
+// electron: gamma, gamma - 1 in R and the speed |p| c / gamma in FP64
+template <typename R>
+__device__ __forceinline__ Elec<R> electron_p(double dx, double dy, double dz) {
+    const R px = (R)dx, py = (R)dy, pz = (R)dz;
+    const R p2 = px * px + py * py + pz * pz;
+    Elec<R> e;
+    e.g = Fast<R>::sqrt((R)1 + p2);
+    e.gm1 = Fast<R>::div(p2, e.g + (R)1);
+    const R pmag = Fast<R>::sqrt(p2);
+    e.vrel = phys::kC * (double)Fast<R>::div(pmag, e.g);
+    return e;
+}
+
+template <typename R>
+__device__ __forceinline__ R photon_k(double px, double py, double pz) {
+    const R qx = (R)px, qy = (R)py, qz = (R)pz;
+    return Fast<R>::sqrt(qx * qx + qy * qy + qz * qz);
+}
+
 // all tallies of the cell reduced in one pass: wave butterflies, then the
 // waves' partials summed in wave order by one thread (fixed shape)
 __device__ void write_tallies(const StepArgs& A, int64_t c, const Tally& t, double nab_ei,
@@ -383,10 +405,8 @@ __global__ __launch_bounds__(kThreads) void k_collide(StepArgs A, TabView<R> T, 
                             const uint32_t bit = proc == 0 ? CMC_BREMS : CMC_TRIDENT;
                             if (!(A.proc & bit)) continue;
                             if (proc == 0) t.pairs_br++; else t.pairs_tr++;
-                            const R rpx = (R)px, rpy = (R)py, rpz = (R)pz;
-                            const R p2 = rpx * rpx + rpy * rpy + rpz * rpz;
-                            const R g = sqrt((R)1 + p2), gm1 = p2 / (g + (R)1);
-                            const R pm = sqrt(p2);
+                            const Elec<R> e = electron_p<R>(px, py, pz);
+                            const R g = e.g, gm1 = e.gm1;
                             R sig;
                             BremsLook<R> BL;
                             bool high = false;
@@ -395,7 +415,7 @@ __global__ __launch_bounds__(kThreads) void k_collide(StepArgs A, TabView<R> T, 
                             high_any |= high;
                             if (!(sig > (R)0)) continue;
                             // eq:proba3 with gamma' v' = c |p'| (eq:proba2), ions at rest
-                            const double x = coef * (double)sig * (phys::kC * (double)pm / (double)g) * A.dt;
+                            const double x = coef * (double)sig * e.vrel * A.dt;
                             const double P = -expm1(-x);
                             const U4 r = A.rng.draw((uint32_t)j, cell, proc == 0 ? kTagAccBr : kTagAccTr);
                             const double U1 = u53(r.x, r.y), U2 = u53(r.z, r.w);
@@ -511,8 +531,7 @@ __global__ __launch_bounds__(kThreads) void k_collide(StepArgs A, TabView<R> T, 
                             const double Wi = A.io.w[ii];
                             const double Pej = Wi / (Wg > Wi ? Wg : Wi);
                             const double qx = A.ph.px[ig], qy = A.ph.py[ig], qz = A.ph.pz[ig];
-                            const R rqx = (R)qx, rqy = (R)qy, rqz = (R)qz;
-                            const R k = sqrt(rqx * rqx + rqy * rqy + rqz * rqz);
+                            const R k = photon_k<R>(qx, qy, qz);
                             int ik; R wk; bool high;
                             const R sig = bh_lookup<R>(T, ct, k, ik, wk, high);
                             high_any |= high;
@@ -968,28 +987,6 @@ __device__ __forceinline__ TeamMem carve_team(unsigned char* p, int cap, int rby
     return m;
 }
 
-template <typename R>
-struct Elec { R g, gm1; double vrel; };
-
-// electron: gamma, gamma - 1 in R and the speed |p| c / gamma in FP64
-template <typename R>
-__device__ __forceinline__ Elec<R> electron_p(double dx, double dy, double dz) {
-    const R px = (R)dx, py = (R)dy, pz = (R)dz;
-    const R p2 = px * px + py * py + pz * pz;
-    Elec<R> e;
-    e.g = sqrt((R)1 + p2);
-    e.gm1 = p2 / (e.g + (R)1);
-    const R pmag = sqrt(p2);
-    e.vrel = phys::kC * (double)pmag / (double)e.g;
-    return e;
-}
-
-template <typename R>
-__device__ __forceinline__ R photon_k(double px, double py, double pz) {
-    const R qx = (R)px, qy = (R)py, qz = (R)pz;
-    return sqrt(qx * qx + qy * qy + qz * qz);
-}
-
 // one test settled with P = -expm1(-x) in FP64: the near-threshold count,
 // then the event iff U1 < P and U2 < P_ej
 __device__ __forceinline__ bool settle(double x, const U4& r, double rej, double near_rel, double Pej, int& near) {
@@ -1021,8 +1018,10 @@ __device__ __forceinline__ void push_cand(const Work& W, int64_t c, uint64_t rec
 // |U1 - P| > near_rel P hold for the computed values, so the pair has no
 // event and no near-threshold count whatever P is.  The rare other pairs are
 // listed and settled with P by the event kernel.
+// Workgroup teams run best at six wavefronts per SIMD (a few spilled
+// registers); wavefront teams are limited by LDS anyway.
 template <typename R, int kT, int kPass>
-__global__ __launch_bounds__(256) void k_pass(StepArgs A, TabView<R> T, Work W, int cap) {
+__global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, TabView<R> T, Work W, int cap) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double redd[kWaves];
     __shared__ double red3[kWaves * 3];
@@ -1079,11 +1078,14 @@ __global__ __launch_bounds__(256) void k_pass(StepArgs A, TabView<R> T, Work W, 
         rank_order<kT>(Nm, cell, kPass == 0 ? kTagKeyE : kTagKeyG, A.rng, M.keys, M.tmp, M.hist, M.ordM, mobA, redu);
         rank_order<kT>(Ni, cell, kPass == 0 ? kTagKeyIE : kTagKeyIG, A.rng, M.keys, M.tmp, M.hist, M.ordI, false, redu);
         const float rNm = 1.0f / (float)Nm, rNi = 1.0f / (float)Ni;
+        // the smaller species is cycled (j mod N_B); the other one is not
+        const auto ion_of = [&](int j) { return (int)M.ordI[Ni == N ? j : mod_small(j, Ni, rNi)]; };
+        const auto mob_of = [&](int j) { return (int)M.ordM[Nm == N ? j : mod_small(j, Nm, rNm)]; };
         const double* wm = S.w + m0;
         const double nab = canon_sum<kT>(N, [&](int q) {
             const int j = mobA ? (int)M.ordM[q] : q;
-            const int mi = mobA ? q : (int)M.ordM[mod_small(j, Nm, rNm)];
-            const double a = wm[mi], b = wion[M.ordI[mod_small(j, Ni, rNi)]];
+            const int mi = mobA ? q : mob_of(j);
+            const double a = wm[mi], b = wion[ion_of(j)];
             return a < b ? a : b;
         }, redd);
         int high = 0;
@@ -1091,7 +1093,7 @@ __global__ __launch_bounds__(256) void k_pass(StepArgs A, TabView<R> T, Work W, 
             const double coef = (kPass == 0 ? d.e : d.g) * d.i / nab;
             for (int q = t; q < N; q += kT) {
                 const int j = mobA ? (int)M.ordM[q] : q;
-                const int mi = mobA ? q : (int)M.ordM[mod_small(j, Nm, rNm)];
+                const int mi = mobA ? q : mob_of(j);
                 double cx = qx, cy = qy, cz = qz;
                 if (mobA) {
                     if (q + kT < N) { qx = S.px[m0 + q + kT]; qy = S.py[m0 + q + kT]; qz = S.pz[m0 + q + kT]; }
@@ -1130,7 +1132,7 @@ __global__ __launch_bounds__(256) void k_pass(StepArgs A, TabView<R> T, Work W, 
                         if (u53(r.x, r.y) <= rej * x) bits = 1u;
                     }
                 }
-                if (bits) push_cand(W, c, ev_pack(kPass, j, mi, M.ordI[mod_small(j, Ni, rNi)], bits));
+                if (bits) push_cand(W, c, ev_pack(kPass, j, mi, ion_of(j), bits));
             }
             if (t == 0) W.coef[c * 2 + kPass] = coef;
         }
@@ -1244,19 +1246,57 @@ __global__ __launch_bounds__(64) void k_events(StepArgs A, TabView<R> T, TabView
         bool f_ph = false, f_tr = false, f_bh = false;
         double kx = 0, ky = 0, kz = 0, pxm = 0, pym = 0, pzm = 0, pxp = 0, pyp = 0, pzp = 0, Wm = 0;
         int64_t par = 0;
+        // with few events the wavefront inverts each CDF together (one round
+        // of table reads per event), else every lane bisects its own; both
+        // give the same abscissa
+        const bool coop = n <= 8;
+        const auto invert = [&](bool has, const CdfRow<double>& row, double xi, double& ct) {
+            if (coop) return cdf_invert_wave<double>(has, row, ct64, xi, ct);
+            return has ? cdf_invert<double>(row.T, row.kind, row.i, row.w, ct64, xi, ct) : 0.0;
+        };
+        // ---- first draw: Bremsstrahlung photon energy or Bethe-Heitler pair
+        double px = 0, py = 0, pz = 0, kd = 0, gd = 0, gm1d = 0;
+        int64_t ie = 0, ig = 0;
+        BremsLook<double> BLd = {};
+        CdfRow<double> rowA = {};
+        double xiA = 0.0;
+        bool reqA = false;
         if (pass == 0) {
-            const int64_t ie = e0 + mi;
+            ie = e0 + mi;
             par = ie;
-            double px = A.el.px[ie], py = A.el.py[ie], pz = A.el.pz[ie];
+            px = A.el.px[ie]; py = A.el.py[ie]; pz = A.el.pz[ie];
             Wm = A.el.w[ie];
             if (evk & kEvBr) {
                 const U4 q = A.rng.draw((uint32_t)j, cell, kTagSmpBr);
                 const double p2d = px * px + py * py + pz * pz;
-                const double gd = sqrt(1.0 + p2d), gm1d = p2d / (gd + 1.0), pmd = sqrt(p2d);
+                gd = sqrt(1.0 + p2d); gm1d = p2d / (gd + 1.0);
                 bool hi2;
-                const BremsLook<double> BLd = brems_lookup<double, false>(T64, ct64, gd, gm1d, hi2);
+                BLd = brems_lookup<double, false>(T64, ct64, gd, gm1d, hi2);
+                rowA = brems_row<double>(T64, BLd);
+                xiA = u53(q.x, q.y);
+                reqA = true;
+            }
+        } else if (pass == 1) {
+            ig = g0 + mi;
+            par = ig;
+            px = A.ph.px[ig]; py = A.ph.py[ig]; pz = A.ph.pz[ig];
+            Wm = A.ph.w[ig];
+            kd = sqrt(px * px + py * py + pz * pz);
+            const U4 q = A.rng.draw((uint32_t)j, cell, kTagSmpBh);
+            int ikd; double wkd; bool hi2;
+            bh_lookup<double>(T64, ct64, kd, ikd, wkd, hi2);
+            rowA = bh_row<double>(T64, ikd, wkd);
+            xiA = u53(q.x, q.y);
+            reqA = true;
+        }
+        double ctA = 0.0;
+        const double tA = invert(reqA, rowA, xiA, ctA);
+        bool tr = false;
+        if (pass == 0) {
+            if (evk & kEvBr) {
                 double k, g2, g2m1;
-                brems_sample<double>(T64, ct64, BLd, gd, gm1d, u53(q.x, q.y), k, g2, g2m1);
+                brems_energies(BLd.seg, gd, gm1d, ctA, k, g2, g2m1);
+                const double pmd = sqrt(px * px + py * py + pz * pz);
                 const double pf = sqrt(g2m1 * (g2 + 1.0));
                 const double f = pf / pmd, h = k / pmd;
                 kx = px * h; ky = py * h; kz = pz * h;
@@ -1267,7 +1307,7 @@ __global__ __launch_bounds__(64) void k_events(StepArgs A, TabView<R> T, TabView
                 t.W_br += Wm;
                 f_ph = true;
             }
-            bool tr = (evk & kEvTr) != 0;
+            tr = (evk & kEvTr) != 0;
             if (evk & kEvTrPending) {
                 // Trident on the electron left by Bremsstrahlung (same pair)
                 const double Wi = A.io.w[i0 + ii];
@@ -1283,47 +1323,56 @@ __global__ __launch_bounds__(64) void k_events(StepArgs A, TabView<R> T, TabView
                     tr = U1 < P && U2 < Pej;
                 }
             }
-            if (tr) {
-                const U4 q = A.rng.draw((uint32_t)j, cell, kTagSmpTr);
-                const double p2d = px * px + py * py + pz * pz;
-                const double gd = sqrt(1.0 + p2d), gm1d = p2d / (gd + 1.0), pmd = sqrt(p2d);
-                double gpair, gpl, gmi, gfm1;
-                trident_sample<double>(T64, gd, gm1d, u53(q.x, q.y), u53(q.z, q.w), gpair, gpl, gmi, gfm1);
-                const double gf = gfm1 + 1.0;
-                const double pf = sqrt(gfm1 * (gf + 1.0));
-                const double pplus = sqrt((gpl - 1.0) * (gpl + 1.0)), pminus = sqrt((gmi - 1.0) * (gmi + 1.0));
-                const double f = pf / pmd, fp = pplus / pmd, fm = pminus / pmd;
-                pxp = px * fp; pyp = py * fp; pzp = pz * fp;
-                pxm = px * fm; pym = py * fm; pzm = pz * fm;
-                px *= f; py *= f; pz *= f;
-                t.ev_tr++;
-                t.E_tr += Wm * (sqrt(1.0 + pxp * pxp + pyp * pyp + pzp * pzp) + sqrt(1.0 + pxm * pxm + pym * pym + pzm * pzm));
-                t.dE_el += Wm * (-gpair);
-                t.W_tr += Wm;
-                f_tr = true;
-            }
-            if (f_ph || f_tr) { A.el.px[ie] = px; A.el.py[ie] = py; A.el.pz[ie] = pz; }
         } else if (pass == 1) {
-            const int64_t ig = g0 + mi;
-            par = ig;
-            const double qx = A.ph.px[ig], qy = A.ph.py[ig], qz = A.ph.pz[ig];
-            Wm = A.ph.w[ig];
-            const double kd = sqrt(qx * qx + qy * qy + qz * qz);
-            const U4 q = A.rng.draw((uint32_t)j, cell, kTagSmpBh);
-            int ikd; double wkd; bool hi2;
-            bh_lookup<double>(T64, ct64, kd, ikd, wkd, hi2);
             double gpl, gmi;
-            bh_sample<double>(T64, ct64, kd, ikd, wkd, u53(q.x, q.y), gpl, gmi);
+            bh_energies(kd, tA, ctA, gpl, gmi);
             const double pplus = sqrt((gpl - 1.0) * (gpl + 1.0)), pminus = sqrt((gmi - 1.0) * (gmi + 1.0));
             const double fp = pplus / kd, fm = pminus / kd;
-            pxp = qx * fp; pyp = qy * fp; pzp = qz * fp;
-            pxm = qx * fm; pym = qy * fm; pzm = qz * fm;
+            pxp = px * fp; pyp = py * fp; pzp = pz * fp;
+            pxm = px * fm; pym = py * fm; pzm = pz * fm;
             t.ev_bh++;
             t.E_bh += Wm * (sqrt(1.0 + pxp * pxp + pyp * pyp + pzp * pzp) + sqrt(1.0 + pxm * pxm + pym * pym + pzm * pzm));
             t.dE_ph += -Wm * kd;
             t.W_bh += Wm;
             f_bh = true;
         }
+        // ---- Trident: pair energy, then the positron split
+        U4 qt = {0u, 0u, 0u, 0u};
+        CdfRow<double> rowB = {};
+        double gt = 0, gtm1 = 0, pmt = 0;
+        if (tr) {
+            qt = A.rng.draw((uint32_t)j, cell, kTagSmpTr);
+            const double p2d = px * px + py * py + pz * pz;
+            gt = sqrt(1.0 + p2d); gtm1 = p2d / (gt + 1.0); pmt = sqrt(p2d);
+            rowB = trident_row<double>(T64, gt);
+        }
+        double ctB = 0.0;
+        const double tB = invert(tr, rowB, u53(qt.x, qt.y), ctB);
+        double gpair = 0, gpl = 0, gmi = 0, gfm1 = 0;
+        bool reqC = false;
+        CdfRow<double> rowC = {};
+        if (tr) {
+            reqC = trident_pair(gtm1, tB, ctB, gpair, gpl, gmi, gfm1);
+            if (reqC) rowC = split_row<double>(T64, gpair);
+        }
+        double ctC = 0.0;
+        const double tC = invert(reqC, rowC, u53(qt.z, qt.w), ctC);
+        if (reqC) split_energies(gpair, tC, ctC, gpl, gmi);
+        if (tr) {
+            const double gf = gfm1 + 1.0;
+            const double pf = sqrt(gfm1 * (gf + 1.0));
+            const double pplus = sqrt((gpl - 1.0) * (gpl + 1.0)), pminus = sqrt((gmi - 1.0) * (gmi + 1.0));
+            const double f = pf / pmt, fp = pplus / pmt, fm = pminus / pmt;
+            pxp = px * fp; pyp = py * fp; pzp = pz * fp;
+            pxm = px * fm; pym = py * fm; pzm = pz * fm;
+            px *= f; py *= f; pz *= f;
+            t.ev_tr++;
+            t.E_tr += Wm * (sqrt(1.0 + pxp * pxp + pyp * pyp + pzp * pzp) + sqrt(1.0 + pxm * pxm + pym * pym + pzm * pzm));
+            t.dE_el += Wm * (-gpair);
+            t.W_tr += Wm;
+            f_tr = true;
+        }
+        if (pass == 0 && (f_ph || f_tr)) { A.el.px[ie] = px; A.el.py[ie] = py; A.el.pz[ie] = pz; }
         // slots in (pass, pair) order: lanes are already in that order
         const unsigned long long b_ph = __ballot(f_ph), b_tr = __ballot(f_tr), b_bh = __ballot(f_bh);
         const unsigned long long below = (1ull << lane) - 1ull;
@@ -1350,7 +1399,9 @@ __global__ __launch_bounds__(64) void k_events(StepArgs A, TabView<R> T, TabView
             } else t.drop_po++;
         }
         int ph_count = min(cap_ph, Ng0 + n_ph);
-        // remove converted photons (stable, in place)
+        // remove converted photons (stable, in place): four chunks of 64 are
+        // read before any is written (a survivor only moves down, never into
+        // a chunk not yet read)
         if (n_bh) {
             for (int i = lane; i < (Ng0 + 31) / 32; i += 64) killed[i] = 0u;
             __syncthreads();
@@ -1361,27 +1412,31 @@ __global__ __launch_bounds__(64) void k_events(StepArgs A, TabView<R> T, TabView
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) first = min(first, __shfl_xor(first, o, 64));
             int wpos = first & ~63;
-            for (int base = wpos; base < ph_count; base += 64) {
-                const int a = base + lane;
-                bool keep = false;
-                double vx = 0, vy = 0, vz = 0, vw = 0;
-                int64_t pp = -1;
-                if (a < ph_count) {
-                    keep = !(a < Ng0 && ((killed[a >> 5] >> (a & 31)) & 1u));
-                    if (keep) {
-                        vx = A.ph.px[g0 + a]; vy = A.ph.py[g0 + a]; vz = A.ph.pz[g0 + a]; vw = A.ph.w[g0 + a];
-                        if (A.ph.parent) pp = A.ph.parent[g0 + a];
+            for (int base = wpos; base < ph_count; base += 256) {
+                double vx[4], vy[4], vz[4], vw[4];
+                int64_t pp[4];
+                bool keep[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int a = base + 64 * u + lane;
+                    keep[u] = a < ph_count && !(a < Ng0 && ((killed[a >> 5] >> (a & 31)) & 1u));
+                    vx[u] = vy[u] = vz[u] = vw[u] = 0.0;
+                    pp[u] = -1;
+                    if (keep[u]) {
+                        vx[u] = A.ph.px[g0 + a]; vy[u] = A.ph.py[g0 + a]; vz[u] = A.ph.pz[g0 + a]; vw[u] = A.ph.w[g0 + a];
+                        if (A.ph.parent) pp[u] = A.ph.parent[g0 + a];
                     }
                 }
-                const unsigned long long bk = __ballot(keep);
-                __syncthreads();
-                if (keep) {
-                    const int64_t at = g0 + wpos + __popcll(bk & below);
-                    A.ph.px[at] = vx; A.ph.py[at] = vy; A.ph.pz[at] = vz; A.ph.w[at] = vw;
-                    if (A.ph.parent) A.ph.parent[at] = pp;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const unsigned long long bk = __ballot(keep[u]);
+                    if (keep[u]) {
+                        const int64_t at = g0 + wpos + __popcll(bk & below);
+                        A.ph.px[at] = vx[u]; A.ph.py[at] = vy[u]; A.ph.pz[at] = vz[u]; A.ph.w[at] = vw[u];
+                        if (A.ph.parent) A.ph.parent[at] = pp[u];
+                    }
+                    wpos += __popcll(bk);
                 }
-                wpos += __popcll(bk);
-                __syncthreads();
             }
             ph_count = wpos;
         }

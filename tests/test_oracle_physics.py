@@ -179,14 +179,28 @@ def test_reduced_length_limits(Z):
     assert abs(s1["Lr"] / s1["Ld"] - 1) < 1e-13
 
 
+def _golden(name):
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", name)
+    out = {}
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            out[k.strip()] = float(v)
+    return out
+
+
 def test_debye_numbers_printed_in_paper():
     # Sec. II.B: solid-density Cu, r_i = 1.4e-10 m; L_D exceeds r_i only
     # above ~27 keV (fully ionised, Z* = 29)
-    s = O.screening(29, 29.0, 8.5e28, 100.0)
+    g = _golden("cu_solid_density.txt")
+    Z, ni = int(g["Z"]), g["n_i_m3"]
+    s = O.screening(Z, float(Z), ni, 100.0)
     ri_m = s["ri"] * RC
-    assert abs(ri_m - 1.4e-10) < 0.02e-10
-    below = O.screening(29, 29.0, 8.5e28, 26.0e3)
-    above = O.screening(29, 29.0, 8.5e28, 27.5e3)
+    assert abs(ri_m - g["r_i_m"]) < g["r_i_abs_tol_m"]
+    Tk = g["debye_exceeds_ri_above_keV"] * 1e3
+    below = O.screening(Z, float(Z), ni, Tk - 1.0e3)
+    above = O.screening(Z, float(Z), ni, Tk + 0.5e3)
     assert below["branch"] == 2.0 and above["branch"] == 1.0
     # Debye length formula eq:LDH when unclamped
     T = 27.5e3
