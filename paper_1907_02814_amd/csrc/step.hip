@@ -656,7 +656,6 @@ struct Work {
     CellState* cs;
     int32_t* flags;                  // kFlagSlow: the sequential kernel runs the cell
     int32_t* ncand;                  // open pairs pushed per cell
-    double* dens;                    // n_e, n_gamma, n_ion per cell
     double* coef;                    // n_a n_b / n_ab per cell and pass
     int32_t* counters;               // [0] cells with open pairs, [1] cells for the sequential kernel
     int32_t* list_ev;                // cells with open pairs (event kernel)
@@ -667,7 +666,7 @@ struct Work {
 __host__ __device__ inline size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
 __host__ __device__ inline size_t work_bytes(int64_t n) {
-    return align256(sizeof(CellState) * n) + align256(4 * n) + align256(4 * n) + align256(24 * n) +
+    return align256(sizeof(CellState) * n) + align256(4 * n) + align256(4 * n) +
            align256(16 * n) + align256(16) + 2 * align256(4 * n) + align256(8 * (size_t)n * kCandCap);
 }
 
@@ -677,7 +676,6 @@ inline Work carve_work(void* base, int64_t n) {
     w.cs = reinterpret_cast<CellState*>(p); p += align256(sizeof(CellState) * n);
     w.flags = reinterpret_cast<int32_t*>(p); p += align256(4 * n);
     w.ncand = reinterpret_cast<int32_t*>(p); p += align256(4 * n);
-    w.dens = reinterpret_cast<double*>(p); p += align256(24 * n);
     w.coef = reinterpret_cast<double*>(p); p += align256(16 * n);
     w.counters = reinterpret_cast<int32_t*>(p); p += align256(16);
     w.list_ev = reinterpret_cast<int32_t*>(p); p += align256(4 * n);
@@ -782,110 +780,62 @@ __device__ void team_excl_scan(uint32_t* a, int n, uint32_t* red) {
 }
 
 template <int kT>
-__device__ __forceinline__ int team_sum_i(int v, int* red) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    if constexpr (kT == 64) {
-        return v;
-    } else {
-        const int w = threadIdx.x >> 6;
-        __syncthreads();
-        if ((threadIdx.x & 63) == 0) red[w] = v;
-        __syncthreads();
-        const int s = red[0] + red[1] + red[2] + red[3];
-        __syncthreads();
-        return s;
-    }
-}
-
-template <int kT>
 __device__ __forceinline__ bool team_any(bool v, int* red) {
     if constexpr (kT == 64) return __ballot(v) != 0ull;
     else return block_or(v, red) != 0;
 }
 
-// Sum of f(i) over i in [0, n) in one fixed order whatever the team size:
-// as 256 threads striding by 256, each wavefront's partials reduced by an
-// xor butterfly and the four wavefront totals added in order.  The two team
-// shapes therefore give bit-identical densities and n_ab.
+// Sums over i in [0, n) in one fixed order whatever the team size: as 256
+// threads striding by 256, each wavefront's partials reduced by an xor
+// butterfly and the four wavefront totals added in order (team_reduce4).
+// The two team shapes therefore give bit-identical densities and n_ab.
+// canon_part2 is the per-thread part before the cross-wavefront step
+// (wavefront teams: the team total); it walks once and accumulates two sums.
 template <int kT, typename F>
-__device__ __forceinline__ double canon_sum(int n, F f, double* red) {
+__device__ __forceinline__ void canon_part2(int n, F f, double& s1, double& s2) {
     if constexpr (kT == 256) {
-        double s = 0.0;
-        for (int i = threadIdx.x; i < n; i += 256) s += f(i);
-        return block_sum(s, red);
+        double a = 0.0, b = 0.0;
+        for (int q = threadIdx.x; q < n; q += 256) f(q, a, b);
+        s1 = wave_sum(a); s2 = wave_sum(b);
     } else {
         const int l = threadIdx.x & 63;
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        for (int b = l; b < n; b += 256) {
-            a0 += f(b);
-            if (b + 64 < n) a1 += f(b + 64);
-            if (b + 128 < n) a2 += f(b + 128);
-            if (b + 192 < n) a3 += f(b + 192);
-        }
-        return ((wave_sum(a0) + wave_sum(a1)) + wave_sum(a2)) + wave_sum(a3);
-    }
-}
-
-// Densities n = sum of W of the three species and the weight check, with
-// one team reduction (same order as canon_sum for each sum).
-struct Dens { double e, g, i; bool bad; };
-
-template <int kT>
-__device__ __forceinline__ Dens team_densities(const double* we, int Ne, const double* wg, int Ng,
-                                               const double* wi, int Ni, double* red3, int* redi) {
-    int bad = 0;
-    const auto chk = [&bad](double v) { bad |= !(v >= 0.0) || !isfinite(v); return v; };
-    Dens d;
-    if constexpr (kT == 256) {
-        double se = 0.0, sg = 0.0, si = 0.0;
-        for (int a = threadIdx.x; a < Ne; a += 256) se += chk(we[a]);
-        for (int a = threadIdx.x; a < Ng; a += 256) sg += chk(wg[a]);
-        for (int a = threadIdx.x; a < Ni; a += 256) si += chk(wi[a]);
-        se = wave_sum(se); sg = wave_sum(sg); si = wave_sum(si);
-        const bool wbad = __ballot(bad != 0) != 0ull;
-        const int w = threadIdx.x >> 6;
-        __syncthreads();
-        if ((threadIdx.x & 63) == 0) { red3[w * 3] = se; red3[w * 3 + 1] = sg; red3[w * 3 + 2] = si; redi[w] = wbad; }
-        __syncthreads();
-        d.e = ((red3[0] + red3[3]) + red3[6]) + red3[9];
-        d.g = ((red3[1] + red3[4]) + red3[7]) + red3[10];
-        d.i = ((red3[2] + red3[5]) + red3[8]) + red3[11];
-        d.bad = (redi[0] | redi[1] | redi[2] | redi[3]) != 0;
-        __syncthreads();
-    } else {
-        const int l = threadIdx.x & 63;
-        const auto sum4 = [&](const double* w, int n) {
-            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-            for (int b = l; b < n; b += 256) {
-                a0 += chk(w[b]);
-                if (b + 64 < n) a1 += chk(w[b + 64]);
-                if (b + 128 < n) a2 += chk(w[b + 128]);
-                if (b + 192 < n) a3 += chk(w[b + 192]);
-            }
-            return ((wave_sum(a0) + wave_sum(a1)) + wave_sum(a2)) + wave_sum(a3);
-        };
-        d.e = sum4(we, Ne); d.g = sum4(wg, Ng); d.i = sum4(wi, Ni);
-        d.bad = __ballot(bad != 0) != 0ull;
-    }
-    return d;
-}
-
-// sum of a packed counter word and OR of a flag over the team
-template <int kT>
-__device__ __forceinline__ void team_tail(uint64_t& packed, bool& any, uint64_t* redq, int* redi) {
+        double a[4] = {0.0, 0.0, 0.0, 0.0}, b[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int q = l; q < n; q += 256) {
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) packed += __shfl_xor(packed, o, 64);
-    const bool wany = __ballot(any) != 0ull;
+            for (int r = 0; r < 4; ++r)
+                if (q + 64 * r < n) f(q + 64 * r, a[r], b[r]);
+        }
+        s1 = ((wave_sum(a[0]) + wave_sum(a[1])) + wave_sum(a[2])) + wave_sum(a[3]);
+        s2 = ((wave_sum(b[0]) + wave_sum(b[1])) + wave_sum(b[2])) + wave_sum(b[3]);
+    }
+}
+
+template <int kT, typename F>
+__device__ __forceinline__ double canon_part(int n, F f) {
+    double s1, s2;
+    canon_part2<kT>(n, [&](int q, double& a, double& b) { a += f(q); }, s1, s2);
+    return s1;
+}
+
+// the cross-wavefront step of four canonical sums and an OR, one round
+template <int kT>
+__device__ __forceinline__ void team_reduce4(double (&v)[4], bool& flag, double* red4, int* redi) {
+    const bool wf = __ballot(flag) != 0ull;
     if constexpr (kT == 64) {
-        any = wany;
+        flag = wf;
     } else {
         const int w = threadIdx.x >> 6;
         __syncthreads();
-        if ((threadIdx.x & 63) == 0) { redq[w] = packed; redi[w] = wany; }
+        if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) red4[w * 4 + k] = v[k];
+            redi[w] = wf;
+        }
         __syncthreads();
-        packed = redq[0] + redq[1] + redq[2] + redq[3];
-        any = (redi[0] | redi[1] | redi[2] | redi[3]) != 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = ((red4[k] + red4[4 + k]) + red4[8 + k]) + red4[12 + k];
+        flag = (redi[0] | redi[1] | redi[2] | redi[3]) != 0;
+        __syncthreads();
     }
 }
 
@@ -1023,8 +973,7 @@ __device__ __forceinline__ void push_cand(const Work& W, int64_t c, uint64_t rec
 template <typename R, int kT, int kPass>
 __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, TabView<R> T, Work W, int cap) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ double redd[kWaves];
-    __shared__ double red3[kWaves * 3];
+    __shared__ double red4[kWaves * 4];
     __shared__ uint32_t redu[kWaves];
     __shared__ int redi[kWaves];
     constexpr int kTeams = 256 / kT;
@@ -1051,46 +1000,66 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
             continue;
         }
         const int64_t e0 = A.el.off[c], g0 = A.ph.off[c], i0 = A.io.off[c];
-        const Dens d = team_densities<kT>(A.el.w + e0, Ne, A.ph.w + g0, Ng, A.io.w + i0, Ni, red3, redi);
-        if (d.bad) {
-            if (t == 0) atomicOr(A.status, CMC_ST_BAD_WEIGHT);
-            continue;
-        }
-        if (t == 0 && kPass == 0) { W.dens[c * 3 + 0] = d.e; W.dens[c * 3 + 1] = d.g; W.dens[c * 3 + 2] = d.i; }
-        if (!(kPass == 0 ? ei : gi)) continue;
-        const CellTab<R> ct = pick<R>(W.cs[c]);
-        const double* wion = A.io.w + i0;
-        const int Nm = kPass == 0 ? Ne : Ng;
+        const bool active = kPass == 0 ? ei : gi;
+        const int Nm = kPass == 0 ? Ne : Ng, No = kPass == 0 ? Ng : Ne;
         const int64_t m0 = kPass == 0 ? e0 : g0;
         const SpeciesDev& S = kPass == 0 ? A.el : A.ph;
-        if (kPass == 0) {
-            if (A.proc & CMC_BREMS)
-                for (int i = t; i < kSliceBrems; i += kT) slice[i] = slice_node_brems<R>(T, ct, i);
-        } else {
-            for (int i = t; i < kSliceBH; i += kT) slice[i] = slice_node_bh<R>(T, ct, i);
-        }
+        const double* wm = S.w + m0;
+        const double* wo = kPass == 0 ? A.ph.w + g0 : A.el.w + e0;
+        const double* wion = A.io.w + i0;
         const bool mobA = Nm >= Ni;
         const int N = mobA ? Nm : Ni;
         // when every mobile particle pairs once the pair loop walks them in
         // storage order: its first momenta are loaded before the sort
         double qx = 0.0, qy = 0.0, qz = 0.0;
-        if (mobA && t < N) { qx = S.px[m0 + t]; qy = S.py[m0 + t]; qz = S.pz[m0 + t]; }
-        rank_order<kT>(Nm, cell, kPass == 0 ? kTagKeyE : kTagKeyG, A.rng, M.keys, M.tmp, M.hist, M.ordM, mobA, redu);
-        rank_order<kT>(Ni, cell, kPass == 0 ? kTagKeyIE : kTagKeyIG, A.rng, M.keys, M.tmp, M.hist, M.ordI, false, redu);
+        if (active) {
+            if (mobA && t < N) { qx = S.px[m0 + t]; qy = S.py[m0 + t]; qz = S.pz[m0 + t]; }
+            const CellTab<R> ct = pick<R>(W.cs[c]);
+            if (kPass == 0) {
+                if (A.proc & CMC_BREMS)
+                    for (int i = t; i < kSliceBrems; i += kT) slice[i] = slice_node_brems<R>(T, ct, i);
+            } else {
+                for (int i = t; i < kSliceBH; i += kT) slice[i] = slice_node_bh<R>(T, ct, i);
+            }
+            rank_order<kT>(Nm, cell, kPass == 0 ? kTagKeyE : kTagKeyG, A.rng, M.keys, M.tmp, M.hist, M.ordM, mobA, redu);
+            rank_order<kT>(Ni, cell, kPass == 0 ? kTagKeyIE : kTagKeyIG, A.rng, M.keys, M.tmp, M.hist, M.ordI, false, redu);
+        }
         const float rNm = 1.0f / (float)Nm, rNi = 1.0f / (float)Ni;
         // the smaller species is cycled (j mod N_B); the other one is not
         const auto ion_of = [&](int j) { return (int)M.ordI[Ni == N ? j : mod_small(j, Ni, rNi)]; };
         const auto mob_of = [&](int j) { return (int)M.ordM[Nm == N ? j : mod_small(j, Nm, rNm)]; };
-        const double* wm = S.w + m0;
-        const double nab = canon_sum<kT>(N, [&](int q) {
-            const int j = mobA ? (int)M.ordM[q] : q;
-            const int mi = mobA ? q : mob_of(j);
-            const double a = wm[mi], b = wion[ion_of(j)];
-            return a < b ? a : b;
-        }, redd);
+        // the weights, read once: the densities n = sum W of the three
+        // species, n_ab = sum_j min(W_a, W_b) and the weight check (when
+        // every mobile particle pairs once, its density and n_ab share the walk)
+        int bad = 0;
+        const auto chk = [&bad](double v) { bad |= !(v >= 0.0) || !isfinite(v); return v; };
+        double v4[4];   // n_mobile, n_ab, n_ion, n_other
+        v4[2] = canon_part<kT>(Ni, [&](int q) { return chk(wion[q]); });
+        if (active && mobA) {
+            canon_part2<kT>(N, [&](int q, double& a, double& b) {
+                const double u = chk(wm[q]), v = wion[ion_of((int)M.ordM[q])];
+                a += u;
+                b += u < v ? u : v;
+            }, v4[0], v4[1]);
+        } else {
+            v4[0] = canon_part<kT>(Nm, [&](int q) { return chk(wm[q]); });
+            v4[1] = !active ? 0.0 : canon_part<kT>(N, [&](int j) {
+                const double u = wm[mob_of(j)], v = wion[ion_of(j)];
+                return u < v ? u : v;
+            });
+        }
+        v4[3] = canon_part<kT>(No, [&](int q) { return chk(wo[q]); });
+        bool badw = bad != 0;
+        team_reduce4<kT>(v4, badw, red4, redi);
+        if (badw) {
+            if (t == 0) atomicOr(A.status, CMC_ST_BAD_WEIGHT);
+            continue;
+        }
+        if (!active) continue;
+        const double nab = v4[1];
         int high = 0;
         if (nab > 0.0) {
-            const double coef = (kPass == 0 ? d.e : d.g) * d.i / nab;
+            const double coef = v4[0] * v4[2] / nab;
             for (int q = t; q < N; q += kT) {
                 const int j = mobA ? (int)M.ordM[q] : q;
                 const int mi = mobA ? q : mob_of(j);
