@@ -130,6 +130,10 @@ typedef struct {
                               the stream just before and just after the pair-test
                               kernels of the step, to time them; ignored by
                               CMC_SCHED_CELL                                  */
+    uint64_t* step_counter;/* optional device [1] (NULL: use `step`): the step
+                              number is read from it on the device and it is
+                              incremented by the step, so that a step captured
+                              in a HIP graph runs the next step on each replay */
 } cmc_step_params;
 
 #define CMC_MAX_PER_CELL 16384

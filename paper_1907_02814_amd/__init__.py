@@ -56,7 +56,8 @@ class _Species(C.Structure):
 class _StepParams(C.Structure):
     _fields_ = [("dt", C.c_double), ("seed", C.c_uint64), ("step", C.c_uint64),
                 ("processes", C.c_uint32), ("precision", C.c_int32), ("schedule", C.c_int32),
-                ("max_per_cell", C.c_int32), ("near_rel", C.c_double), ("pass_events", _vp * 2)]
+                ("max_per_cell", C.c_int32), ("near_rel", C.c_double), ("pass_events", _vp * 2),
+                ("step_counter", _vp)]
 
 
 class _Tallies(C.Structure):
@@ -230,6 +231,30 @@ class StepState:
         self.workspace = torch.empty(max(wsb, 1), dtype=torch.uint8, device=dev) if wsb else None
         self.wsb = wsb
         self._refs = (cells, electrons, photons, ions, new_el, new_po)
+        self.counter = None
+
+    def use_counter(self, counter):
+        """Read the step number from `counter` (a one-element int64 device
+        tensor) on the device; every step then advances it (None: back to
+        the host step number)."""
+        self.counter = counter
+        self.params.step_counter = _ptr(counter) if counter is not None else None
+
+    def graph(self, step0: int):
+        """Capture one step in a HIP graph (torch.cuda.CUDAGraph) whose
+        replays run steps step0, step0 + 1, ... (the step number lives in
+        device memory).  Run the launch shape eagerly once before, so that
+        the team shape is already tuned.  Returns (graph, counter)."""
+        import torch
+        counter = torch.tensor([int(step0)], dtype=torch.int64, device=self.ti.device)
+        self.use_counter(counter)
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.graph(g, stream=side):
+            self.step(0)
+        torch.cuda.current_stream().wait_stream(side)
+        return g, counter
 
     def step(self, step: int, stream=None, events=None):
         """One step; `events` = optional pair of raw hipEvent_t handles

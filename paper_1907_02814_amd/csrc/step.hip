@@ -228,7 +228,19 @@ struct StepArgs {
     int32_t* status;
     const int32_t* list;        // non-NULL: process only the cells list[0 .. *list_n)
     const int32_t* list_n;
+    const uint64_t* step_dev;   // non-NULL: the step number is read from device memory
 };
+
+// the generator of the step (step from device memory when it is there)
+__device__ __forceinline__ Rng step_rng(const StepArgs& A) {
+    Rng r = A.rng;
+    if (A.step_dev) {
+        const uint64_t s = *A.step_dev;
+        r.step_lo = (uint32_t)s;
+        r.step_hi = (uint32_t)(s >> 32);
+    }
+    return r;
+}
 
 // per-thread tallies (scalars: no dynamically indexed local arrays)
 struct Tally {
@@ -327,6 +339,7 @@ __global__ __launch_bounds__(kThreads) void k_collide(StepArgs A, TabView<R> T, 
     __shared__ CellShared<R> cs;
     const Smem S = carve(smem_raw, A.maxn);
     const int tid = threadIdx.x;
+    const Rng rng = step_rng(A);
 
     const int64_t n_items = A.list ? (int64_t)*A.list_n : A.n_cells;
     for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
@@ -374,8 +387,8 @@ __global__ __launch_bounds__(kThreads) void k_collide(StepArgs A, TabView<R> T, 
         int cnt_ne = A.ne.count[c], cnt_np = A.np.count[c];
         const int cap_ne = (int)(A.ne.off[c + 1] - A.ne.off[c]), cap_np = (int)(A.np.off[c + 1] - A.np.off[c]);
         if ((A.proc & (CMC_BREMS | CMC_TRIDENT)) && Ne > 0 && Ni > 0) {
-            key_order(Ne, cell, kTagKeyE, A.rng, S.keys, S.pm, S.bcnt, redu);
-            key_order(Ni, cell, kTagKeyIE, A.rng, S.keys, S.pi, S.bcnt, redu);
+            key_order(Ne, cell, kTagKeyE, rng, S.keys, S.pm, S.bcnt, redu);
+            key_order(Ni, cell, kTagKeyIE, rng, S.keys, S.pi, S.bcnt, redu);
             const int N = Ne > Ni ? Ne : Ni;
             double part = 0.0;
             for (int j = tid; j < N; j += kThreads) {
@@ -417,11 +430,11 @@ __global__ __launch_bounds__(kThreads) void k_collide(StepArgs A, TabView<R> T, 
                             // eq:proba3 with gamma' v' = c |p'| (eq:proba2), ions at rest
                             const double x = coef * (double)sig * e.vrel * A.dt;
                             const double P = -expm1(-x);
-                            const U4 r = A.rng.draw((uint32_t)j, cell, proc == 0 ? kTagAccBr : kTagAccTr);
+                            const U4 r = rng.draw((uint32_t)j, cell, proc == 0 ? kTagAccBr : kTagAccTr);
                             const double U1 = u53(r.x, r.y), U2 = u53(r.z, r.w);
                             if (fabs(U1 - P) <= A.near_rel * P) { if (proc == 0) t.near_br++; else t.near_tr++; }
                             if (!(U1 < P && U2 < Pej)) continue;
-                            const U4 q = A.rng.draw((uint32_t)j, cell, proc == 0 ? kTagSmpBr : kTagSmpTr);
+                            const U4 q = rng.draw((uint32_t)j, cell, proc == 0 ? kTagSmpBr : kTagSmpTr);
                             const double xi1 = u53(q.x, q.y), xi2 = u53(q.z, q.w);
                             if (proc == 0) t.ev_br++; else t.ev_tr++;
                             moved = true;
@@ -501,8 +514,8 @@ __global__ __launch_bounds__(kThreads) void k_collide(StepArgs A, TabView<R> T, 
         bool any_dead = false;
         if ((A.proc & CMC_BH) && Ng0 > 0 && Ni > 0) {
             for (int i = tid; i < (Ng0 + 31) / 32; i += kThreads) S.dead[i] = 0u;
-            key_order(Ng0, cell, kTagKeyG, A.rng, S.keys, S.pm, S.bcnt, redu);
-            key_order(Ni, cell, kTagKeyIG, A.rng, S.keys, S.pi, S.bcnt, redu);
+            key_order(Ng0, cell, kTagKeyG, rng, S.keys, S.pm, S.bcnt, redu);
+            key_order(Ni, cell, kTagKeyIG, rng, S.keys, S.pi, S.bcnt, redu);
             const int N = Ng0 > Ni ? Ng0 : Ni;
             double part = 0.0;
             for (int j = tid; j < N; j += kThreads) {
@@ -539,11 +552,11 @@ __global__ __launch_bounds__(kThreads) void k_collide(StepArgs A, TabView<R> T, 
                                 // eq:proba3 for photons: gamma -> k', v' -> c, flux k' c/(k gamma_i)
                                 const double x = coef * (double)sig * phys::kC * A.dt;
                                 const double P = -expm1(-x);
-                                const U4 r = A.rng.draw((uint32_t)j, cell, kTagAccBh);
+                                const U4 r = rng.draw((uint32_t)j, cell, kTagAccBh);
                                 const double U1 = u53(r.x, r.y), U2 = u53(r.z, r.w);
                                 if (fabs(U1 - P) <= A.near_rel * P) t.near_bh++;
                                 if (U1 < P && U2 < Pej) {
-                                    const U4 q = A.rng.draw((uint32_t)j, cell, kTagSmpBh);
+                                    const U4 q = rng.draw((uint32_t)j, cell, kTagSmpBh);
                                     const double kd = sqrt(qx * qx + qy * qy + qz * qz);
                                     double gpl, gmi;
                                     int ikd; double wkd; bool hi2;
@@ -657,6 +670,7 @@ struct Work {
     int32_t* flags;                  // kFlagSlow: the sequential kernel runs the cell
     int32_t* ncand;                  // open pairs pushed per cell
     double* coef;                    // n_a n_b / n_ab per cell and pass
+    uint64_t* step;                  // step number of the current step
     int32_t* counters;               // [0] cells with open pairs, [1] cells for the sequential kernel
     int32_t* list_ev;                // cells with open pairs (event kernel)
     int32_t* list_slow;              // cells the sequential kernel runs
@@ -667,7 +681,7 @@ __host__ __device__ inline size_t align256(size_t b) { return (b + 255) / 256 * 
 
 __host__ __device__ inline size_t work_bytes(int64_t n) {
     return align256(sizeof(CellState) * n) + align256(4 * n) + align256(4 * n) +
-           align256(16 * n) + align256(16) + 2 * align256(4 * n) + align256(8 * (size_t)n * kCandCap);
+           align256(16 * n) + align256(8) + align256(16) + 2 * align256(4 * n) + align256(8 * (size_t)n * kCandCap);
 }
 
 inline Work carve_work(void* base, int64_t n) {
@@ -677,6 +691,7 @@ inline Work carve_work(void* base, int64_t n) {
     w.flags = reinterpret_cast<int32_t*>(p); p += align256(4 * n);
     w.ncand = reinterpret_cast<int32_t*>(p); p += align256(4 * n);
     w.coef = reinterpret_cast<double*>(p); p += align256(16 * n);
+    w.step = reinterpret_cast<uint64_t*>(p); p += align256(8);
     w.counters = reinterpret_cast<int32_t*>(p); p += align256(16);
     w.list_ev = reinterpret_cast<int32_t*>(p); p += align256(4 * n);
     w.list_slow = reinterpret_cast<int32_t*>(p); p += align256(4 * n);
@@ -697,8 +712,17 @@ __device__ __forceinline__ uint32_t ev_key(uint64_t r) { return ((uint32_t)ev_pa
 
 // screening state of every cell; clears the cell's tallies and work
 // counters and the list counters of the step
+// The step number: from the device counter when there is one (which then
+// advances, so that a captured graph runs the next step on every replay),
+// else from the host.
 __global__ void k_cell_state(const double* Zs, const double* ni, const double* Te, int64_t n, double Z,
-                             Axes ax, Work W, int64_t* ti, double* td, int32_t* status) {
+                             Axes ax, Work W, int64_t* ti, double* td, int32_t* status, uint64_t* counter,
+                             uint64_t host_step, int advance) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const uint64_t st = counter ? *counter : host_step;
+        W.step[0] = st;
+        if (counter && advance) *counter = st + 1;
+    }
     if (blockIdx.x == 0 && threadIdx.x < 4) W.counters[threadIdx.x] = 0;
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
         const double z = Zs[c], d = ni[c], t = Te[c];
@@ -983,6 +1007,7 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
     const TeamMem M = carve_team(smem_raw + tstride * team, cap, (int)sizeof(R));
     R* slice = reinterpret_cast<R*>(M.slice);
     const double rej = 2.0 * (1.0 + A.near_rel);
+    const Rng rng = step_rng(A);
 
     for (int64_t c = (int64_t)blockIdx.x * kTeams + team; c < A.n_cells; c += (int64_t)gridDim.x * kTeams) {
         const uint32_t cell = (uint32_t)c;
@@ -1021,8 +1046,8 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
             } else {
                 for (int i = t; i < kSliceBH; i += kT) slice[i] = slice_node_bh<R>(T, ct, i);
             }
-            rank_order<kT>(Nm, cell, kPass == 0 ? kTagKeyE : kTagKeyG, A.rng, M.keys, M.tmp, M.hist, M.ordM, mobA, redu);
-            rank_order<kT>(Ni, cell, kPass == 0 ? kTagKeyIE : kTagKeyIG, A.rng, M.keys, M.tmp, M.hist, M.ordI, false, redu);
+            rank_order<kT>(Nm, cell, kPass == 0 ? kTagKeyE : kTagKeyG, rng, M.keys, M.tmp, M.hist, M.ordM, mobA, redu);
+            rank_order<kT>(Ni, cell, kPass == 0 ? kTagKeyIE : kTagKeyIG, rng, M.keys, M.tmp, M.hist, M.ordI, false, redu);
         }
         const float rNm = 1.0f / (float)Nm, rNi = 1.0f / (float)Ni;
         // the smaller species is cycled (j mod N_B); the other one is not
@@ -1078,7 +1103,7 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
                         high |= hi;
                         if (sig > (R)0) {
                             const double x = coef * (double)sig * e.vrel * A.dt;
-                            const U4 r = A.rng.draw((uint32_t)j, cell, kTagAccBr);
+                            const U4 r = rng.draw((uint32_t)j, cell, kTagAccBr);
                             if (u53(r.x, r.y) <= rej * x) bits = 1u;
                         }
                     }
@@ -1086,7 +1111,7 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
                         const R sig = (R)phys::trident_sigma(T.Z, (double)e.g);
                         if (sig > (R)0) {
                             const double x = coef * (double)sig * e.vrel * A.dt;
-                            const U4 r = A.rng.draw((uint32_t)j, cell, kTagAccTr);
+                            const U4 r = rng.draw((uint32_t)j, cell, kTagAccTr);
                             if (u53(r.x, r.y) <= rej * x) bits = 2u;
                         }
                     }
@@ -1097,7 +1122,7 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
                     high |= hi;
                     if (sig > (R)0) {
                         const double x = coef * (double)sig * phys::kC * A.dt;
-                        const U4 r = A.rng.draw((uint32_t)j, cell, kTagAccBh);
+                        const U4 r = rng.draw((uint32_t)j, cell, kTagAccBh);
                         if (u53(r.x, r.y) <= rej * x) bits = 1u;
                     }
                 }
@@ -1131,6 +1156,7 @@ __global__ __launch_bounds__(64) void k_events(StepArgs A, TabView<R> T, TabView
     const int lane = threadIdx.x;
     const int n_items = W.counters[0];
     const double rej = 2.0 * (1.0 + A.near_rel);
+    const Rng rng = step_rng(A);
     for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
         const int64_t c = W.list_ev[item];
         if (W.flags[c] & kFlagSlow) continue;
@@ -1159,14 +1185,14 @@ __global__ __launch_bounds__(64) void k_events(StepArgs A, TabView<R> T, TabView
                     bool hi;
                     const R sig = brems_lookup<R, false>(T, ct, e.g, e.gm1, hi).sig;
                     const double x = coef * (double)sig * e.vrel * A.dt;
-                    if (settle(x, A.rng.draw((uint32_t)j, cell, kTagAccBr), rej, A.near_rel, Pej, near_br))
+                    if (settle(x, rng.draw((uint32_t)j, cell, kTagAccBr), rej, A.near_rel, Pej, near_br))
                         kind = kEvBr | ((A.proc & CMC_TRIDENT) ? kEvTrPending : 0u);
                 }
                 if ((A.proc & CMC_TRIDENT) && !kind) {
                     const R sig = (R)phys::trident_sigma(T.Z, (double)e.g);
                     if (sig > (R)0) {
                         const double x = coef * (double)sig * e.vrel * A.dt;
-                        if (settle(x, A.rng.draw((uint32_t)j, cell, kTagAccTr), rej, A.near_rel, Pej, near_tr))
+                        if (settle(x, rng.draw((uint32_t)j, cell, kTagAccTr), rej, A.near_rel, Pej, near_tr))
                             kind = kEvTr;
                     }
                 }
@@ -1178,7 +1204,7 @@ __global__ __launch_bounds__(64) void k_events(StepArgs A, TabView<R> T, TabView
                 const double x = coef * (double)sig * phys::kC * A.dt;
                 const double Wg = A.ph.w[g0 + mi];
                 const double Pej = Wi / (Wg > Wi ? Wg : Wi);
-                if (settle(x, A.rng.draw((uint32_t)j, cell, kTagAccBh), rej, A.near_rel, Pej, near_bh))
+                if (settle(x, rng.draw((uint32_t)j, cell, kTagAccBh), rej, A.near_rel, Pej, near_bh))
                     kind = kEvBh;
                 reused = Ng0 < Ni && j + Ng0 < Ni;
             }
@@ -1236,7 +1262,7 @@ __global__ __launch_bounds__(64) void k_events(StepArgs A, TabView<R> T, TabView
             px = A.el.px[ie]; py = A.el.py[ie]; pz = A.el.pz[ie];
             Wm = A.el.w[ie];
             if (evk & kEvBr) {
-                const U4 q = A.rng.draw((uint32_t)j, cell, kTagSmpBr);
+                const U4 q = rng.draw((uint32_t)j, cell, kTagSmpBr);
                 const double p2d = px * px + py * py + pz * pz;
                 gd = sqrt(1.0 + p2d); gm1d = p2d / (gd + 1.0);
                 bool hi2;
@@ -1251,7 +1277,7 @@ __global__ __launch_bounds__(64) void k_events(StepArgs A, TabView<R> T, TabView
             px = A.ph.px[ig]; py = A.ph.py[ig]; pz = A.ph.pz[ig];
             Wm = A.ph.w[ig];
             kd = sqrt(px * px + py * py + pz * pz);
-            const U4 q = A.rng.draw((uint32_t)j, cell, kTagSmpBh);
+            const U4 q = rng.draw((uint32_t)j, cell, kTagSmpBh);
             int ikd; double wkd; bool hi2;
             bh_lookup<double>(T64, ct64, kd, ikd, wkd, hi2);
             rowA = bh_row<double>(T64, ikd, wkd);
@@ -1286,7 +1312,7 @@ __global__ __launch_bounds__(64) void k_events(StepArgs A, TabView<R> T, TabView
                 if (sig > (R)0) {
                     const double x = W.coef[c * 2] * (double)sig * e.vrel * A.dt;
                     const double P = -expm1(-x);
-                    const U4 q = A.rng.draw((uint32_t)j, cell, kTagAccTr);
+                    const U4 q = rng.draw((uint32_t)j, cell, kTagAccTr);
                     const double U1 = u53(q.x, q.y), U2 = u53(q.z, q.w);
                     if (fabs(U1 - P) <= A.near_rel * P) t.near_tr++;
                     tr = U1 < P && U2 < Pej;
@@ -1310,7 +1336,7 @@ __global__ __launch_bounds__(64) void k_events(StepArgs A, TabView<R> T, TabView
         CdfRow<double> rowB = {};
         double gt = 0, gtm1 = 0, pmt = 0;
         if (tr) {
-            qt = A.rng.draw((uint32_t)j, cell, kTagSmpTr);
+            qt = rng.draw((uint32_t)j, cell, kTagSmpTr);
             const double p2d = px * px + py * py + pz * pz;
             gt = sqrt(1.0 + p2d); gtm1 = p2d / (gt + 1.0); pmt = sqrt(p2d);
             rowB = trident_row<double>(T64, gt);
@@ -1483,6 +1509,10 @@ __global__ __launch_bounds__(kThreads) void k_pair(PairArgs A) {
     }
 }
 
+__global__ void k_step_bump(uint64_t* counter) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *counter += 1;
+}
+
 int grid_for(int64_t n_cells) {
     const int64_t cap = 256 * 64;
     return (int)(n_cells < cap ? (n_cells > 0 ? n_cells : 1) : cap);
@@ -1509,15 +1539,24 @@ static int team_cap(int team, int maxn, bool fp64) {
     return cap;
 }
 
+// dynamic LDS above the default needs the function attribute; it is set
+// outside stream capture (a captured step reuses what an eager step set)
+static void lds_attr(const void* fn, size_t bytes, hipStream_t st) {
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    (void)hipStreamIsCapturing(st, &cap);
+    if (cap == hipStreamCaptureStatusNone)
+        (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
 template <typename R, int kT>
 static void launch_pass_t(const StepArgs& A, const TabView<R>& T, const Work& W, int cap, size_t dshm,
                           unsigned grid, hipStream_t st) {
     if (A.proc & (CMC_BREMS | CMC_TRIDENT)) {
-        (void)hipFuncSetAttribute((const void*)k_pass<R, kT, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dshm);
+        lds_attr((const void*)k_pass<R, kT, 0>, dshm, st);
         hipLaunchKernelGGL((k_pass<R, kT, 0>), dim3(grid), dim3(256), dshm, st, A, T, W, cap);
     }
     if (A.proc & CMC_BH) {
-        (void)hipFuncSetAttribute((const void*)k_pass<R, kT, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dshm);
+        lds_attr((const void*)k_pass<R, kT, 1>, dshm, st);
         hipLaunchKernelGGL((k_pass<R, kT, 1>), dim3(grid), dim3(256), dshm, st, A, T, W, cap);
     }
 }
@@ -1657,44 +1696,55 @@ extern "C" cmc_status cmc_collide_step(cmc_tables t, const cmc_cells* cells, cmc
     if (P->schedule == CMC_SCHED_CELL) {
         // one sequential workgroup per cell for every cell
         A.list = nullptr; A.list_n = nullptr;
+        A.step_dev = P->step_counter;
         if (fp64) {
-            (void)hipFuncSetAttribute((const void*)k_collide<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+            lds_attr((const void*)k_collide<double>, shm, st);
             hipLaunchKernelGGL(k_collide<double>, dim3(grid), dim3(kThreads), shm, st, A, view64(t), view64(t));
         } else {
-            (void)hipFuncSetAttribute((const void*)k_collide<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+            lds_attr((const void*)k_collide<float>, shm, st);
             hipLaunchKernelGGL(k_collide<float>, dim3(grid), dim3(kThreads), shm, st, A, view32(t), view64(t));
         }
         CMC_CHECK_LAUNCH("cmc_collide_step");
+        if (P->step_counter) {
+            hipLaunchKernelGGL(k_step_bump, dim3(1), dim3(64), 0, st, P->step_counter);
+            CMC_CHECK_LAUNCH("cmc_collide_step: step counter");
+        }
         return CMC_OK;
     }
     const size_t need = work_bytes(A.n_cells);
     CMC_REQUIRE(workspace != nullptr && workspace_bytes >= need, CMC_EINVAL,
                 "cmc_collide_step: workspace of %zu bytes required (got %zu)", need, workspace_bytes);
     const Work W = carve_work(workspace, A.n_cells);
-    const auto cell_state = [&]() {
+    A.step_dev = W.step;
+    const auto cell_state = [&](int advance) {
         hipLaunchKernelGGL(k_cell_state, dim3((unsigned)std::min<int64_t>((A.n_cells + 63) / 64, 4096)), dim3(64),
-                           0, st, A.Zs, A.ni, A.Te, A.n_cells, (double)t->Z, t->ax, W, A.ti, A.td, A.status);
+                           0, st, A.Zs, A.ni, A.Te, A.n_cells, (double)t->Z, t->ax, W, A.ti, A.td, A.status,
+                           P->step_counter, P->step, advance);
     };
-    cell_state();
-    CMC_CHECK_LAUNCH("cmc_collide_step: k_cell_state");
     int team = P->schedule == CMC_SCHED_WAVE ? 64 : 256;
-    if (P->schedule == CMC_SCHED_AUTO) {
+    bool tuned = P->schedule != CMC_SCHED_AUTO;
+    TuneKey key{};
+    if (!tuned) {
         int dev = 0;
         (void)hipGetDevice(&dev);
-        const TuneKey key{dev, A.n_cells, A.maxn, (int)A.proc, P->precision};
-        if (!tune_lookup(key, team)) {
-            hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-            (void)hipStreamIsCapturing(st, &cap);
-            if (cap == hipStreamCaptureStatusNone) {
-                cmc_status s2 = tune_passes(A, t, W, fp64, st, team);
-                if (s2 != CMC_OK) return s2;
-                tune_store(key, team);
-                cell_state();   // the timing runs filled the cell lists
-                CMC_CHECK_LAUNCH("cmc_collide_step: k_cell_state");
-            } else {
-                team = 256;     // no timing under graph capture: workgroup teams
-            }
+        key = TuneKey{dev, A.n_cells, A.maxn, (int)A.proc, P->precision};
+        tuned = tune_lookup(key, team);
+    }
+    // the counter advances once, in the last cell-state launch of the step
+    cell_state(tuned ? 1 : 0);
+    CMC_CHECK_LAUNCH("cmc_collide_step: k_cell_state");
+    if (!tuned) {
+        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+        (void)hipStreamIsCapturing(st, &cap);
+        if (cap == hipStreamCaptureStatusNone) {
+            cmc_status s2 = tune_passes(A, t, W, fp64, st, team);
+            if (s2 != CMC_OK) return s2;
+            tune_store(key, team);
+        } else {
+            team = 256;         // no timing under graph capture: workgroup teams
         }
+        cell_state(1);          // the timing runs filled the cell lists
+        CMC_CHECK_LAUNCH("cmc_collide_step: k_cell_state");
     }
     if (P->pass_events[0]) (void)hipEventRecord(static_cast<hipEvent_t>(P->pass_events[0]), st);
     cmc_status s1 = launch_passes(A, t, W, fp64, team, st);
@@ -1708,12 +1758,12 @@ extern "C" cmc_status cmc_collide_step(cmc_tables t, const cmc_cells* cells, cmc
     if (fp64) {
         hipLaunchKernelGGL(k_events<double>, dim3(gev), dim3(64), 0, st, A, view64(t), view64(t), W);
         CMC_CHECK_LAUNCH("cmc_collide_step: k_events");
-        (void)hipFuncSetAttribute((const void*)k_collide<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        lds_attr((const void*)k_collide<double>, shm, st);
         hipLaunchKernelGGL(k_collide<double>, dim3(gslow), dim3(kThreads), shm, st, A, view64(t), view64(t));
     } else {
         hipLaunchKernelGGL(k_events<float>, dim3(gev), dim3(64), 0, st, A, view32(t), view64(t), W);
         CMC_CHECK_LAUNCH("cmc_collide_step: k_events");
-        (void)hipFuncSetAttribute((const void*)k_collide<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        lds_attr((const void*)k_collide<float>, shm, st);
         hipLaunchKernelGGL(k_collide<float>, dim3(gslow), dim3(kThreads), shm, st, A, view32(t), view64(t));
     }
     CMC_CHECK_LAUNCH("cmc_collide_step: k_collide");

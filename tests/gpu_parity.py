@@ -143,3 +143,47 @@ class Parity:
                   file=sys.stderr)
         assert (st & ~cmc.ST_OVERFLOW) == (ost & ~cmc.ST_OVERFLOW) or self.flips, (st, ost)
         return ti, td, oti, otd
+
+
+
+def compare_sampled_cells(g, st, ref, sample, oti, otd, rtol):
+    """GPU outputs (torch dict workload `g`, StepState `st`) of the cells
+    `sample` against the oracle's (oti, otd, and the arrays of ref =
+    wl.subset(sample), run from the same state: same global cell ids, hence
+    the same random numbers).  Cells with a near-threshold decision on either
+    side are left out; returns their number.  Raises on any other
+    difference: integer tallies and counts bit-exact, floating point within
+    rtol."""
+    ti = st.ti.cpu().numpy()[sample]
+    td = st.td.cpu().numpy()[sample]
+    skip = (oti[:, 6:9].sum(1) > 0) | (ti[:, 6:9].sum(1) > 0)
+    keep = ~skip
+    if not np.array_equal(ti[keep], oti[keep]):
+        c = int(np.flatnonzero(np.any(ti != oti, axis=1) & keep)[0])
+        raise AssertionError(f"integer tallies of cell {sample[c]}: {ti[c].tolist()} vs {oti[c].tolist()}")
+    scale = np.abs(otd[:, 2:5]).sum(1, keepdims=True) + np.abs(otd[:, 5:7]).sum(1, keepdims=True)
+    sc = np.maximum(np.maximum(np.abs(otd), scale), 1e-300)
+    err = np.abs(td - otd) / sc
+    if keep.any() and err[keep].max() > rtol:
+        raise AssertionError(f"FP tallies differ by {err[keep].max():.3g}")
+    for name in ("electrons", "photons", "new_el", "new_po"):
+        G = getattr(g, name)
+        Rr = getattr(ref, name)
+        off_g = G["off"].cpu().numpy()
+        arr = {k: G[k].cpu().numpy() for k in ("px", "py", "pz", "w")}
+        cnt = G["count"].cpu().numpy() if G.get("count") is not None else np.diff(off_g)
+        rcnt = Rr["count"] if Rr.get("count") is not None else np.diff(Rr["off"])
+        for li, c in enumerate(sample):
+            if skip[li]:
+                continue
+            n = int(cnt[c])
+            if n != int(rcnt[li]):
+                raise AssertionError(f"{name} count differs in cell {c}: {n} vs {rcnt[li]}")
+            a0, r0 = int(off_g[c]), int(Rr["off"][li])
+            ga = [arr[k][a0:a0 + n] for k in ("px", "py", "pz", "w")]
+            ra = [Rr[k][r0:r0 + n] for k in ("px", "py", "pz", "w")]
+            ev = _vec_rel(ga[0], ga[1], ga[2], ra[0], ra[1], ra[2])
+            ew = np.abs(ga[3] - ra[3]) / np.maximum(np.abs(ra[3]), 1e-300)
+            if n and (ev.max() > rtol or ew.max() > rtol):
+                raise AssertionError(f"{name} of cell {c} differ: p {ev.max():.3g} w {ew.max():.3g}")
+    return int(skip.sum())

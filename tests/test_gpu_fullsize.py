@@ -1,0 +1,60 @@
+"""Parity at the benchmark sizes, in the launch configuration bench.py times
+(automatic schedule): cfg2 in full (4096 cells x (1024 photons + 1024 Au
+ions), FP32 form) against the oracle; foil-chain cells at their full size
+(4096 electrons + 4096 Au ions, all processes); cfg3 in full (16384 uneven
+cells, all processes) on the GPU against the oracle on a sample of its
+cells (the random numbers are keyed by the global cell index)."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1907_02814_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def test_cfg2_full_size_fp32():
+    import paper_1907_02814_amd as cmc
+    from gpu_parity import Parity
+    wl = W.cfg2()
+    P = Parity(wl, precision=cmc.FP32)
+    for s in range(2):
+        P.step(s)
+    print(f"[parity] cfg2 full: {P.flips} flip(s); " + ", ".join(f"{k} {v:.1e}" for k, v in P.errors.items()))
+    assert P.flips <= 2
+    assert P.state.ti.cpu().numpy()[:, 2].sum() > 4_000_000
+
+
+def test_foil_cells_full_size_fp32():
+    import paper_1907_02814_amd as cmc
+    from gpu_parity import Parity
+    wl = W.cfg5(np.random.default_rng(1005), n_cells=192)
+    P = Parity(wl, precision=cmc.FP32)
+    for s in range(2):
+        P.step(s)
+    print(f"[parity] cfg5 cells: {P.flips} flip(s); " + ", ".join(f"{k} {v:.1e}" for k, v in P.errors.items()))
+    assert P.flips <= 2
+    assert P.ref.photons["count"].sum() > 0
+
+
+def test_cfg3_full_sampled_cells():
+    import torch
+    import paper_1907_02814_amd as cmc
+    from gpu_parity import compare_sampled_cells, gpu_tables
+    wl = W.cfg3()
+    g = wl.copy().to_torch("cuda:0")
+    st = cmc.StepState(gpu_tables(wl.Z), g.cells, g.electrons, g.photons, g.ions, g.new_el, g.new_po,
+                       dt=wl.dt, seed=1, processes=wl.processes, precision=cmc.FP32)
+    st.step(0)
+    torch.cuda.synchronize()
+    sample = np.sort(np.random.default_rng(5).choice(wl.n_cells, 256, replace=False))
+    # the largest cells too
+    big = np.argsort(np.diff(wl.electrons["off"]) + np.diff(wl.ions["off"]))[-8:]
+    sample = np.unique(np.concatenate([sample, big]))
+    ref = wl.subset(sample)
+    oti, otd, ost = O.collide_step(O.tables(wl.Z), ref.cells, ref.electrons, ref.photons, ref.ions,
+                                   ref.new_el, ref.new_po, wl.dt, 1, 0, wl.processes)
+    flips = compare_sampled_cells(g, st, ref, sample, oti, otd, 1e-5)
+    print(f"[parity] cfg3 full, {len(sample)} sampled cells: {flips} with a near-threshold decision")
+    assert flips <= 2
+    assert oti[:, 0:3].sum() > 1e5
