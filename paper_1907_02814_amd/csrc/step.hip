@@ -326,319 +326,336 @@ __device__ void write_tallies(const StepArgs& A, int64_t c, const Tally& t, doub
     __syncthreads();
 }
 
-// R is the arithmetic of the per-pair path (table interpolation of the
-// cross sections, gamma, beta); events sample their energies from the FP64
-// tables T64 in FP64 in both forms.
 template <typename R>
-__global__ __launch_bounds__(kThreads) void k_collide(StepArgs A, TabView<R> T, TabView<double> T64) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ double redd[kWaves * 8];
-    __shared__ long long redl[kWaves * CMC_NI];
-    __shared__ int redi[kWaves];
-    __shared__ uint32_t redu[kWaves];
-    __shared__ CellShared<R> cs;
-    const Smem S = carve(smem_raw, A.maxn);
+struct CollideShared {   // static LDS of the sequential per-cell step
+    double redd[kWaves * 8];
+    long long redl[kWaves * CMC_NI];
+    int redi[kWaves];
+    uint32_t redu[kWaves];
+    CellShared<R> cs;
+};
+
+// The whole step of one cell, pairs in order (the sequential semantics of
+// the method), by a workgroup of kThreads.  R is the arithmetic of the
+// per-pair path (table interpolation of the cross sections, gamma, beta);
+// events sample their energies from the FP64 tables T64 in FP64 in both
+// forms.
+template <typename R>
+__device__ __forceinline__ void collide_cell(const StepArgs& A, const TabView<R>& T, const TabView<double>& T64, const Rng& rng,
+                             int64_t c, const Smem& S, CollideShared<R>& sh) {
+    double* redd = sh.redd;
+    long long* redl = sh.redl;
+    int* redi = sh.redi;
+    uint32_t* redu = sh.redu;
+    CellShared<R>& cs = sh.cs;
     const int tid = threadIdx.x;
-    const Rng rng = step_rng(A);
-
-    const int64_t n_items = A.list ? (int64_t)*A.list_n : A.n_cells;
-    for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
-        const int64_t c = A.list ? (int64_t)A.list[item] : item;
-        const uint32_t cell = (uint32_t)c;
-        const int Ne = live(A.el, c), Ng0 = live(A.ph, c), Ni = live(A.io, c);
-        const int64_t e0 = A.el.off[c], g0 = A.ph.off[c], i0 = A.io.off[c];
-        const double Zs = A.Zs[c], nic = A.ni[c], Te = A.Te[c];
-        Tally t = {};
-        bool skip = false;
-        int st = 0;
-        if (!(Zs >= 0.0 && Zs <= T.Z && nic > 0.0 && Te >= 0.0 && isfinite(nic) && isfinite(Te))) {
-            st = CMC_ST_BAD_CELL; skip = true;
-        } else if (Ne > A.maxn || Ng0 > A.maxn || Ni > A.maxn) {
-            st = CMC_ST_TOO_LARGE; skip = true;
+    const uint32_t cell = (uint32_t)c;
+    const int Ne = live(A.el, c), Ng0 = live(A.ph, c), Ni = live(A.io, c);
+    const int64_t e0 = A.el.off[c], g0 = A.ph.off[c], i0 = A.io.off[c];
+    const double Zs = A.Zs[c], nic = A.ni[c], Te = A.Te[c];
+    Tally t = {};
+    bool skip = false;
+    int st = 0;
+    if (!(Zs >= 0.0 && Zs <= T.Z && nic > 0.0 && Te >= 0.0 && isfinite(nic) && isfinite(Te))) {
+        st = CMC_ST_BAD_CELL; skip = true;
+    } else if (Ne > A.maxn || Ng0 > A.maxn || Ni > A.maxn) {
+        st = CMC_ST_TOO_LARGE; skip = true;
+    }
+    // densities and weight check
+    double se = 0.0, sg = 0.0, si = 0.0;
+    int bad = 0;
+    if (!skip) {
+        for (int a = tid; a < Ne; a += kThreads) { const double w = A.el.w[e0 + a]; se += w; bad |= !(w >= 0.0) || !isfinite(w); }
+        for (int a = tid; a < Ng0; a += kThreads) { const double w = A.ph.w[g0 + a]; sg += w; bad |= !(w >= 0.0) || !isfinite(w); }
+        for (int a = tid; a < Ni; a += kThreads) { const double w = A.io.w[i0 + a]; si += w; bad |= !(w >= 0.0) || !isfinite(w); }
+        if (tid == 0) {
+            cs.scr = phys::screening(T.Z, Zs, nic, Te);
+            cs.ct = cell_tab<R>(cs.scr, T.ax);
+            cs.ct64 = cell_tab<double>(cs.scr, T.ax);
         }
-        // densities and weight check
-        double se = 0.0, sg = 0.0, si = 0.0;
-        int bad = 0;
-        if (!skip) {
-            for (int a = tid; a < Ne; a += kThreads) { const double w = A.el.w[e0 + a]; se += w; bad |= !(w >= 0.0) || !isfinite(w); }
-            for (int a = tid; a < Ng0; a += kThreads) { const double w = A.ph.w[g0 + a]; sg += w; bad |= !(w >= 0.0) || !isfinite(w); }
-            for (int a = tid; a < Ni; a += kThreads) { const double w = A.io.w[i0 + a]; si += w; bad |= !(w >= 0.0) || !isfinite(w); }
-            if (tid == 0) {
-                cs.scr = phys::screening(T.Z, Zs, nic, Te);
-                cs.ct = cell_tab<R>(cs.scr, T.ax);
-                cs.ct64 = cell_tab<double>(cs.scr, T.ax);
+    }
+    const double n_e = block_sum(se, redd), n_g = block_sum(sg, redd), n_I = block_sum(si, redd);
+    if (!skip && block_or(bad, redi)) { st = CMC_ST_BAD_WEIGHT; skip = true; }
+    double nab_ei = 0.0, nab_gi = 0.0;
+    if (skip) {
+        if (tid == 0) atomicOr(A.status, st);
+        write_tallies(A, c, t, 0.0, 0.0, redl, redd);
+        return;
+    }
+    const CellTab<R> ct = cs.ct;
+    const CellTab<double> ct64 = cs.ct64;
+    bool high_any = false;
+
+    // ---------------------------------------------- electron-ion pass
+    int ph_count = Ng0;   // photons in the species after Bremsstrahlung appends
+    const int cap_ph = (int)(A.ph.off[c + 1] - g0);
+    int cnt_ne = A.ne.count[c], cnt_np = A.np.count[c];
+    const int cap_ne = (int)(A.ne.off[c + 1] - A.ne.off[c]), cap_np = (int)(A.np.off[c + 1] - A.np.off[c]);
+    if ((A.proc & (CMC_BREMS | CMC_TRIDENT)) && Ne > 0 && Ni > 0) {
+        key_order(Ne, cell, kTagKeyE, rng, S.keys, S.pm, S.bcnt, redu);
+        key_order(Ni, cell, kTagKeyIE, rng, S.keys, S.pi, S.bcnt, redu);
+        const int N = Ne > Ni ? Ne : Ni;
+        double part = 0.0;
+        for (int j = tid; j < N; j += kThreads) {
+            const double we = A.el.w[e0 + S.pm[j % Ne]], wi = A.io.w[i0 + S.pi[j % Ni]];
+            part += we < wi ? we : wi;
+        }
+        nab_ei = block_sum(part, redd);
+        const double coef = n_e * n_I / nab_ei;
+        const int run = Ne >= Ni ? N : Ne;          // pairs in a run never repeat an electron
+        for (int r0 = (nab_ei > 0.0 ? 0 : N); r0 < N; r0 += run) {
+            const int rend = min(N, r0 + run);
+            for (int base = r0; base < rend; base += kThreads) {
+                const int j = base + tid;
+                const bool act = j < rend;
+                bool f_ph = false, f_tr = false;
+                double kx = 0, ky = 0, kz = 0, pxm = 0, pym = 0, pzm = 0, pxp = 0, pyp = 0, pzp = 0, We = 0;
+                int64_t ie = 0;
+                if (act) {
+                    ie = e0 + S.pm[j % Ne];
+                    const int64_t ii = i0 + S.pi[j % Ni];
+                    We = A.el.w[ie];
+                    const double Wi = A.io.w[ii];
+                    const double Pej = Wi / (We > Wi ? We : Wi);
+                    double px = A.el.px[ie], py = A.el.py[ie], pz = A.el.pz[ie];
+                    bool moved = false;
+                    for (int proc = 0; proc < 2; ++proc) {
+                        const uint32_t bit = proc == 0 ? CMC_BREMS : CMC_TRIDENT;
+                        if (!(A.proc & bit)) continue;
+                        if (proc == 0) t.pairs_br++; else t.pairs_tr++;
+                        const Elec<R> e = electron_p<R>(px, py, pz);
+                        const R g = e.g, gm1 = e.gm1;
+                        R sig;
+                        BremsLook<R> BL;
+                        bool high = false;
+                        if (proc == 0) { BL = brems_lookup<R>(T, ct, g, gm1, high); sig = BL.sig; }
+                        else sig = (R)phys::trident_sigma(T.Z, (double)g);
+                        high_any |= high;
+                        if (!(sig > (R)0)) continue;
+                        // eq:proba3 with gamma' v' = c |p'| (eq:proba2), ions at rest
+                        const double x = coef * (double)sig * e.vrel * A.dt;
+                        const double P = -expm1(-x);
+                        const U4 r = rng.draw((uint32_t)j, cell, proc == 0 ? kTagAccBr : kTagAccTr);
+                        const double U1 = u53(r.x, r.y), U2 = u53(r.z, r.w);
+                        if (fabs(U1 - P) <= A.near_rel * P) { if (proc == 0) t.near_br++; else t.near_tr++; }
+                        if (!(U1 < P && U2 < Pej)) continue;
+                        const U4 q = rng.draw((uint32_t)j, cell, proc == 0 ? kTagSmpBr : kTagSmpTr);
+                        const double xi1 = u53(q.x, q.y), xi2 = u53(q.z, q.w);
+                        if (proc == 0) t.ev_br++; else t.ev_tr++;
+                        moved = true;
+                        // event kinematics in FP64 from the stored momentum
+                        const double p2d = px * px + py * py + pz * pz;
+                        const double gd = sqrt(1.0 + p2d), gm1d = p2d / (gd + 1.0), pmd = sqrt(p2d);
+                        if (proc == 0) {
+                            bool hi2;
+                            const BremsLook<double> BLd = brems_lookup<double, false>(T64, ct64, gd, gm1d, hi2);
+                            double k, g2, g2m1;
+                            brems_sample<double>(T64, ct64, BLd, gd, gm1d, xi1, k, g2, g2m1);
+                            const double pf = sqrt(g2m1 * (g2 + 1.0));
+                            const double f = pf / pmd, h = k / pmd;
+                            kx = px * h; ky = py * h; kz = pz * h;
+                            px *= f; py *= f; pz *= f;
+                            const double kl = sqrt(kx * kx + ky * ky + kz * kz);
+                            t.E_br += We * kl;
+                            // electron energy change = -k exactly (ions at rest); the
+                            // difference of two Lorentz factors would cancel for k << gamma
+                            t.dE_el += We * (-k);
+                            t.W_br += We;
+                            f_ph = true;
+                        } else {
+                            double gpair, gpl, gmi, gfm1;
+                            trident_sample<double>(T64, gd, gm1d, xi1, xi2, gpair, gpl, gmi, gfm1);
+                            const double gf = gfm1 + 1.0;
+                            const double pf = sqrt(gfm1 * (gf + 1.0));
+                            const double pplus = sqrt((gpl - 1.0) * (gpl + 1.0));
+                            const double pminus = sqrt((gmi - 1.0) * (gmi + 1.0));
+                            const double f = pf / pmd, fp = pplus / pmd, fm = pminus / pmd;
+                            pxp = px * fp; pyp = py * fp; pzp = pz * fp;
+                            pxm = px * fm; pym = py * fm; pzm = pz * fm;
+                            px *= f; py *= f; pz *= f;
+                            const double gpl_l = sqrt(1.0 + pxp * pxp + pyp * pyp + pzp * pzp);
+                            const double gmi_l = sqrt(1.0 + pxm * pxm + pym * pym + pzm * pzm);
+                            t.E_tr += We * (gpl_l + gmi_l);
+                            t.dE_el += We * (-gpair);
+                            t.W_tr += We;
+                            f_tr = true;
+                        }
+                    }
+                    if (moved) { A.el.px[ie] = px; A.el.py[ie] = py; A.el.pz[ie] = pz; }
+                }
+                // ordered appends (pair order within the chunk)
+                int tot_ph, tot_tr;
+                const int o_ph = block_flag_scan(f_ph, redi, tot_ph);
+                const int o_tr = block_flag_scan(f_tr, redi, tot_tr);
+                if (f_ph) {
+                    const int slot = ph_count + o_ph;
+                    if (slot < cap_ph) {
+                        const int64_t at = g0 + slot;
+                        A.ph.px[at] = kx; A.ph.py[at] = ky; A.ph.pz[at] = kz; A.ph.w[at] = We;
+                        if (A.ph.parent) A.ph.parent[at] = ie;
+                    } else { t.drop_ph++; }
+                }
+                if (f_tr) {
+                    const int s1 = cnt_ne + o_tr, s2 = cnt_np + o_tr;
+                    if (s1 < cap_ne) {
+                        const int64_t at = A.ne.off[c] + s1;
+                        A.ne.px[at] = pxm; A.ne.py[at] = pym; A.ne.pz[at] = pzm; A.ne.w[at] = We;
+                        if (A.ne.parent) A.ne.parent[at] = ie;
+                    } else { t.drop_el++; }
+                    if (s2 < cap_np) {
+                        const int64_t at = A.np.off[c] + s2;
+                        A.np.px[at] = pxp; A.np.py[at] = pyp; A.np.pz[at] = pzp; A.np.w[at] = We;
+                        if (A.np.parent) A.np.parent[at] = ie;
+                    } else { t.drop_po++; }
+                }
+                ph_count = min(cap_ph, ph_count + tot_ph);
+                cnt_ne = min(cap_ne, cnt_ne + tot_tr);
+                cnt_np = min(cap_np, cnt_np + tot_tr);
             }
         }
-        const double n_e = block_sum(se, redd), n_g = block_sum(sg, redd), n_I = block_sum(si, redd);
-        if (!skip && block_or(bad, redi)) { st = CMC_ST_BAD_WEIGHT; skip = true; }
-        double nab_ei = 0.0, nab_gi = 0.0;
-        if (skip) {
-            if (tid == 0) atomicOr(A.status, st);
-            write_tallies(A, c, t, 0.0, 0.0, redl, redd);
-            continue;
-        }
-        const CellTab<R> ct = cs.ct;
-        const CellTab<double> ct64 = cs.ct64;
-        bool high_any = false;
+    }
 
-        // ---------------------------------------------- electron-ion pass
-        int ph_count = Ng0;   // photons in the species after Bremsstrahlung appends
-        const int cap_ph = (int)(A.ph.off[c + 1] - g0);
-        int cnt_ne = A.ne.count[c], cnt_np = A.np.count[c];
-        const int cap_ne = (int)(A.ne.off[c + 1] - A.ne.off[c]), cap_np = (int)(A.np.off[c + 1] - A.np.off[c]);
-        if ((A.proc & (CMC_BREMS | CMC_TRIDENT)) && Ne > 0 && Ni > 0) {
-            key_order(Ne, cell, kTagKeyE, rng, S.keys, S.pm, S.bcnt, redu);
-            key_order(Ni, cell, kTagKeyIE, rng, S.keys, S.pi, S.bcnt, redu);
-            const int N = Ne > Ni ? Ne : Ni;
-            double part = 0.0;
-            for (int j = tid; j < N; j += kThreads) {
-                const double we = A.el.w[e0 + S.pm[j % Ne]], wi = A.io.w[i0 + S.pi[j % Ni]];
-                part += we < wi ? we : wi;
-            }
-            nab_ei = block_sum(part, redd);
-            const double coef = n_e * n_I / nab_ei;
-            const int run = Ne >= Ni ? N : Ne;          // pairs in a run never repeat an electron
-            for (int r0 = (nab_ei > 0.0 ? 0 : N); r0 < N; r0 += run) {
-                const int rend = min(N, r0 + run);
-                for (int base = r0; base < rend; base += kThreads) {
-                    const int j = base + tid;
-                    const bool act = j < rend;
-                    bool f_ph = false, f_tr = false;
-                    double kx = 0, ky = 0, kz = 0, pxm = 0, pym = 0, pzm = 0, pxp = 0, pyp = 0, pzp = 0, We = 0;
-                    int64_t ie = 0;
-                    if (act) {
-                        ie = e0 + S.pm[j % Ne];
+    // ---------------------------------------------- photon-ion pass
+    bool any_dead = false;
+    if ((A.proc & CMC_BH) && Ng0 > 0 && Ni > 0) {
+        for (int i = tid; i < (Ng0 + 31) / 32; i += kThreads) S.dead[i] = 0u;
+        key_order(Ng0, cell, kTagKeyG, rng, S.keys, S.pm, S.bcnt, redu);
+        key_order(Ni, cell, kTagKeyIG, rng, S.keys, S.pi, S.bcnt, redu);
+        const int N = Ng0 > Ni ? Ng0 : Ni;
+        double part = 0.0;
+        for (int j = tid; j < N; j += kThreads) {
+            const double wg = A.ph.w[g0 + S.pm[j % Ng0]], wi = A.io.w[i0 + S.pi[j % Ni]];
+            part += wg < wi ? wg : wi;
+        }
+        nab_gi = block_sum(part, redd);
+        const double coef = n_g * n_I / nab_gi;
+        const int run = Ng0 >= Ni ? N : Ng0;
+        int killed = 0;
+        for (int r0 = (nab_gi > 0.0 ? 0 : N); r0 < N; r0 += run) {
+            const int rend = min(N, r0 + run);
+            for (int base = r0; base < rend; base += kThreads) {
+                const int j = base + tid;
+                bool f_bh = false;
+                double pxm = 0, pym = 0, pzm = 0, pxp = 0, pyp = 0, pzp = 0, Wg = 0;
+                int64_t ig = 0;
+                if (j < rend) {
+                    const int lg = S.pm[j % Ng0];
+                    const bool dead = (S.dead[lg >> 5] >> (lg & 31)) & 1u;
+                    if (!dead) {
+                        ig = g0 + lg;
                         const int64_t ii = i0 + S.pi[j % Ni];
-                        We = A.el.w[ie];
+                        t.pairs_bh++;
+                        Wg = A.ph.w[ig];
                         const double Wi = A.io.w[ii];
-                        const double Pej = Wi / (We > Wi ? We : Wi);
-                        double px = A.el.px[ie], py = A.el.py[ie], pz = A.el.pz[ie];
-                        bool moved = false;
-                        for (int proc = 0; proc < 2; ++proc) {
-                            const uint32_t bit = proc == 0 ? CMC_BREMS : CMC_TRIDENT;
-                            if (!(A.proc & bit)) continue;
-                            if (proc == 0) t.pairs_br++; else t.pairs_tr++;
-                            const Elec<R> e = electron_p<R>(px, py, pz);
-                            const R g = e.g, gm1 = e.gm1;
-                            R sig;
-                            BremsLook<R> BL;
-                            bool high = false;
-                            if (proc == 0) { BL = brems_lookup<R>(T, ct, g, gm1, high); sig = BL.sig; }
-                            else sig = (R)phys::trident_sigma(T.Z, (double)g);
-                            high_any |= high;
-                            if (!(sig > (R)0)) continue;
-                            // eq:proba3 with gamma' v' = c |p'| (eq:proba2), ions at rest
-                            const double x = coef * (double)sig * e.vrel * A.dt;
+                        const double Pej = Wi / (Wg > Wi ? Wg : Wi);
+                        const double qx = A.ph.px[ig], qy = A.ph.py[ig], qz = A.ph.pz[ig];
+                        const R k = photon_k<R>(qx, qy, qz);
+                        int ik; R wk; bool high;
+                        const R sig = bh_lookup<R>(T, ct, k, ik, wk, high);
+                        high_any |= high;
+                        if (sig > (R)0) {
+                            // eq:proba3 for photons: gamma -> k', v' -> c, flux k' c/(k gamma_i)
+                            const double x = coef * (double)sig * phys::kC * A.dt;
                             const double P = -expm1(-x);
-                            const U4 r = rng.draw((uint32_t)j, cell, proc == 0 ? kTagAccBr : kTagAccTr);
+                            const U4 r = rng.draw((uint32_t)j, cell, kTagAccBh);
                             const double U1 = u53(r.x, r.y), U2 = u53(r.z, r.w);
-                            if (fabs(U1 - P) <= A.near_rel * P) { if (proc == 0) t.near_br++; else t.near_tr++; }
-                            if (!(U1 < P && U2 < Pej)) continue;
-                            const U4 q = rng.draw((uint32_t)j, cell, proc == 0 ? kTagSmpBr : kTagSmpTr);
-                            const double xi1 = u53(q.x, q.y), xi2 = u53(q.z, q.w);
-                            if (proc == 0) t.ev_br++; else t.ev_tr++;
-                            moved = true;
-                            // event kinematics in FP64 from the stored momentum
-                            const double p2d = px * px + py * py + pz * pz;
-                            const double gd = sqrt(1.0 + p2d), gm1d = p2d / (gd + 1.0), pmd = sqrt(p2d);
-                            if (proc == 0) {
-                                bool hi2;
-                                const BremsLook<double> BLd = brems_lookup<double, false>(T64, ct64, gd, gm1d, hi2);
-                                double k, g2, g2m1;
-                                brems_sample<double>(T64, ct64, BLd, gd, gm1d, xi1, k, g2, g2m1);
-                                const double pf = sqrt(g2m1 * (g2 + 1.0));
-                                const double f = pf / pmd, h = k / pmd;
-                                kx = px * h; ky = py * h; kz = pz * h;
-                                px *= f; py *= f; pz *= f;
-                                const double kl = sqrt(kx * kx + ky * ky + kz * kz);
-                                t.E_br += We * kl;
-                                // electron energy change = -k exactly (ions at rest); the
-                                // difference of two Lorentz factors would cancel for k << gamma
-                                t.dE_el += We * (-k);
-                                t.W_br += We;
-                                f_ph = true;
-                            } else {
-                                double gpair, gpl, gmi, gfm1;
-                                trident_sample<double>(T64, gd, gm1d, xi1, xi2, gpair, gpl, gmi, gfm1);
-                                const double gf = gfm1 + 1.0;
-                                const double pf = sqrt(gfm1 * (gf + 1.0));
+                            if (fabs(U1 - P) <= A.near_rel * P) t.near_bh++;
+                            if (U1 < P && U2 < Pej) {
+                                const U4 q = rng.draw((uint32_t)j, cell, kTagSmpBh);
+                                const double kd = sqrt(qx * qx + qy * qy + qz * qz);
+                                double gpl, gmi;
+                                int ikd; double wkd; bool hi2;
+                                bh_lookup<double>(T64, ct64, kd, ikd, wkd, hi2);
+                                bh_sample<double>(T64, ct64, kd, ikd, wkd, u53(q.x, q.y), gpl, gmi);
                                 const double pplus = sqrt((gpl - 1.0) * (gpl + 1.0));
                                 const double pminus = sqrt((gmi - 1.0) * (gmi + 1.0));
-                                const double f = pf / pmd, fp = pplus / pmd, fm = pminus / pmd;
-                                pxp = px * fp; pyp = py * fp; pzp = pz * fp;
-                                pxm = px * fm; pym = py * fm; pzm = pz * fm;
-                                px *= f; py *= f; pz *= f;
+                                const double fp = pplus / kd, fm = pminus / kd;
+                                pxp = qx * fp; pyp = qy * fp; pzp = qz * fp;
+                                pxm = qx * fm; pym = qy * fm; pzm = qz * fm;
                                 const double gpl_l = sqrt(1.0 + pxp * pxp + pyp * pyp + pzp * pzp);
                                 const double gmi_l = sqrt(1.0 + pxm * pxm + pym * pym + pzm * pzm);
-                                t.E_tr += We * (gpl_l + gmi_l);
-                                t.dE_el += We * (-gpair);
-                                t.W_tr += We;
-                                f_tr = true;
+                                atomicOr(&S.dead[lg >> 5], 1u << (lg & 31));
+                                t.ev_bh++;
+                                t.E_bh += Wg * (gpl_l + gmi_l);
+                                t.dE_ph += -Wg * kd;
+                                t.W_bh += Wg;
+                                f_bh = true;
                             }
                         }
-                        if (moved) { A.el.px[ie] = px; A.el.py[ie] = py; A.el.pz[ie] = pz; }
-                    }
-                    // ordered appends (pair order within the chunk)
-                    int tot_ph, tot_tr;
-                    const int o_ph = block_flag_scan(f_ph, redi, tot_ph);
-                    const int o_tr = block_flag_scan(f_tr, redi, tot_tr);
-                    if (f_ph) {
-                        const int slot = ph_count + o_ph;
-                        if (slot < cap_ph) {
-                            const int64_t at = g0 + slot;
-                            A.ph.px[at] = kx; A.ph.py[at] = ky; A.ph.pz[at] = kz; A.ph.w[at] = We;
-                            if (A.ph.parent) A.ph.parent[at] = ie;
-                        } else { t.drop_ph++; }
-                    }
-                    if (f_tr) {
-                        const int s1 = cnt_ne + o_tr, s2 = cnt_np + o_tr;
-                        if (s1 < cap_ne) {
-                            const int64_t at = A.ne.off[c] + s1;
-                            A.ne.px[at] = pxm; A.ne.py[at] = pym; A.ne.pz[at] = pzm; A.ne.w[at] = We;
-                            if (A.ne.parent) A.ne.parent[at] = ie;
-                        } else { t.drop_el++; }
-                        if (s2 < cap_np) {
-                            const int64_t at = A.np.off[c] + s2;
-                            A.np.px[at] = pxp; A.np.py[at] = pyp; A.np.pz[at] = pzp; A.np.w[at] = We;
-                            if (A.np.parent) A.np.parent[at] = ie;
-                        } else { t.drop_po++; }
-                    }
-                    ph_count = min(cap_ph, ph_count + tot_ph);
-                    cnt_ne = min(cap_ne, cnt_ne + tot_tr);
-                    cnt_np = min(cap_np, cnt_np + tot_tr);
-                }
-            }
-        }
-
-        // ---------------------------------------------- photon-ion pass
-        bool any_dead = false;
-        if ((A.proc & CMC_BH) && Ng0 > 0 && Ni > 0) {
-            for (int i = tid; i < (Ng0 + 31) / 32; i += kThreads) S.dead[i] = 0u;
-            key_order(Ng0, cell, kTagKeyG, rng, S.keys, S.pm, S.bcnt, redu);
-            key_order(Ni, cell, kTagKeyIG, rng, S.keys, S.pi, S.bcnt, redu);
-            const int N = Ng0 > Ni ? Ng0 : Ni;
-            double part = 0.0;
-            for (int j = tid; j < N; j += kThreads) {
-                const double wg = A.ph.w[g0 + S.pm[j % Ng0]], wi = A.io.w[i0 + S.pi[j % Ni]];
-                part += wg < wi ? wg : wi;
-            }
-            nab_gi = block_sum(part, redd);
-            const double coef = n_g * n_I / nab_gi;
-            const int run = Ng0 >= Ni ? N : Ng0;
-            int killed = 0;
-            for (int r0 = (nab_gi > 0.0 ? 0 : N); r0 < N; r0 += run) {
-                const int rend = min(N, r0 + run);
-                for (int base = r0; base < rend; base += kThreads) {
-                    const int j = base + tid;
-                    bool f_bh = false;
-                    double pxm = 0, pym = 0, pzm = 0, pxp = 0, pyp = 0, pzp = 0, Wg = 0;
-                    int64_t ig = 0;
-                    if (j < rend) {
-                        const int lg = S.pm[j % Ng0];
-                        const bool dead = (S.dead[lg >> 5] >> (lg & 31)) & 1u;
-                        if (!dead) {
-                            ig = g0 + lg;
-                            const int64_t ii = i0 + S.pi[j % Ni];
-                            t.pairs_bh++;
-                            Wg = A.ph.w[ig];
-                            const double Wi = A.io.w[ii];
-                            const double Pej = Wi / (Wg > Wi ? Wg : Wi);
-                            const double qx = A.ph.px[ig], qy = A.ph.py[ig], qz = A.ph.pz[ig];
-                            const R k = photon_k<R>(qx, qy, qz);
-                            int ik; R wk; bool high;
-                            const R sig = bh_lookup<R>(T, ct, k, ik, wk, high);
-                            high_any |= high;
-                            if (sig > (R)0) {
-                                // eq:proba3 for photons: gamma -> k', v' -> c, flux k' c/(k gamma_i)
-                                const double x = coef * (double)sig * phys::kC * A.dt;
-                                const double P = -expm1(-x);
-                                const U4 r = rng.draw((uint32_t)j, cell, kTagAccBh);
-                                const double U1 = u53(r.x, r.y), U2 = u53(r.z, r.w);
-                                if (fabs(U1 - P) <= A.near_rel * P) t.near_bh++;
-                                if (U1 < P && U2 < Pej) {
-                                    const U4 q = rng.draw((uint32_t)j, cell, kTagSmpBh);
-                                    const double kd = sqrt(qx * qx + qy * qy + qz * qz);
-                                    double gpl, gmi;
-                                    int ikd; double wkd; bool hi2;
-                                    bh_lookup<double>(T64, ct64, kd, ikd, wkd, hi2);
-                                    bh_sample<double>(T64, ct64, kd, ikd, wkd, u53(q.x, q.y), gpl, gmi);
-                                    const double pplus = sqrt((gpl - 1.0) * (gpl + 1.0));
-                                    const double pminus = sqrt((gmi - 1.0) * (gmi + 1.0));
-                                    const double fp = pplus / kd, fm = pminus / kd;
-                                    pxp = qx * fp; pyp = qy * fp; pzp = qz * fp;
-                                    pxm = qx * fm; pym = qy * fm; pzm = qz * fm;
-                                    const double gpl_l = sqrt(1.0 + pxp * pxp + pyp * pyp + pzp * pzp);
-                                    const double gmi_l = sqrt(1.0 + pxm * pxm + pym * pym + pzm * pzm);
-                                    atomicOr(&S.dead[lg >> 5], 1u << (lg & 31));
-                                    t.ev_bh++;
-                                    t.E_bh += Wg * (gpl_l + gmi_l);
-                                    t.dE_ph += -Wg * kd;
-                                    t.W_bh += Wg;
-                                    f_bh = true;
-                                }
-                            }
-                        }
-                    }
-                    int tot;
-                    const int o = block_flag_scan(f_bh, redi, tot);
-                    if (f_bh) {
-                        const int s1 = cnt_ne + o, s2 = cnt_np + o;
-                        if (s1 < cap_ne) {
-                            const int64_t at = A.ne.off[c] + s1;
-                            A.ne.px[at] = pxm; A.ne.py[at] = pym; A.ne.pz[at] = pzm; A.ne.w[at] = Wg;
-                            if (A.ne.parent) A.ne.parent[at] = ig;
-                        } else { t.drop_el++; }
-                        if (s2 < cap_np) {
-                            const int64_t at = A.np.off[c] + s2;
-                            A.np.px[at] = pxp; A.np.py[at] = pyp; A.np.pz[at] = pzp; A.np.w[at] = Wg;
-                            if (A.np.parent) A.np.parent[at] = ig;
-                        } else { t.drop_po++; }
-                    }
-                    killed += tot;
-                    cnt_ne = min(cap_ne, cnt_ne + tot);
-                    cnt_np = min(cap_np, cnt_np + tot);
-                }
-            }
-            any_dead = killed > 0;
-        }
-
-        // ---------------------------------------------- photon compaction
-        if (any_dead) {
-            int wpos = 0;
-            for (int base = 0; base < ph_count; base += kThreads) {
-                const int a = base + tid;
-                bool keep = false;
-                double vx = 0, vy = 0, vz = 0, vw = 0;
-                int64_t par = -1;
-                if (a < ph_count) {
-                    keep = !(a < Ng0 && ((S.dead[a >> 5] >> (a & 31)) & 1u));
-                    if (keep) {
-                        vx = A.ph.px[g0 + a]; vy = A.ph.py[g0 + a]; vz = A.ph.pz[g0 + a]; vw = A.ph.w[g0 + a];
-                        if (A.ph.parent) par = A.ph.parent[g0 + a];
                     }
                 }
                 int tot;
-                const int o = block_flag_scan(keep, redi, tot);   // barrier: all reads precede writes
-                if (keep) {
-                    const int64_t at = g0 + wpos + o;
-                    A.ph.px[at] = vx; A.ph.py[at] = vy; A.ph.pz[at] = vz; A.ph.w[at] = vw;
-                    if (A.ph.parent) A.ph.parent[at] = par;
+                const int o = block_flag_scan(f_bh, redi, tot);
+                if (f_bh) {
+                    const int s1 = cnt_ne + o, s2 = cnt_np + o;
+                    if (s1 < cap_ne) {
+                        const int64_t at = A.ne.off[c] + s1;
+                        A.ne.px[at] = pxm; A.ne.py[at] = pym; A.ne.pz[at] = pzm; A.ne.w[at] = Wg;
+                        if (A.ne.parent) A.ne.parent[at] = ig;
+                    } else { t.drop_el++; }
+                    if (s2 < cap_np) {
+                        const int64_t at = A.np.off[c] + s2;
+                        A.np.px[at] = pxp; A.np.py[at] = pyp; A.np.pz[at] = pzp; A.np.w[at] = Wg;
+                        if (A.np.parent) A.np.parent[at] = ig;
+                    } else { t.drop_po++; }
                 }
-                wpos += tot;
-                __syncthreads();
+                killed += tot;
+                cnt_ne = min(cap_ne, cnt_ne + tot);
+                cnt_np = min(cap_np, cnt_np + tot);
             }
-            ph_count = wpos;
         }
+        any_dead = killed > 0;
+    }
 
-        // ---------------------------------------------- counts, tallies
-        if (high_any) atomicOr(A.status, CMC_ST_GAMMA_HIGH);
-        if (t.drop_ph + t.drop_el + t.drop_po) atomicOr(A.status, CMC_ST_OVERFLOW);
-        if (tid == 0) {
-            if (A.ph.count) A.ph.count[c] = ph_count;
-            A.ne.count[c] = cnt_ne;
-            A.np.count[c] = cnt_np;
+    // ---------------------------------------------- photon compaction
+    if (any_dead) {
+        int wpos = 0;
+        for (int base = 0; base < ph_count; base += kThreads) {
+            const int a = base + tid;
+            bool keep = false;
+            double vx = 0, vy = 0, vz = 0, vw = 0;
+            int64_t par = -1;
+            if (a < ph_count) {
+                keep = !(a < Ng0 && ((S.dead[a >> 5] >> (a & 31)) & 1u));
+                if (keep) {
+                    vx = A.ph.px[g0 + a]; vy = A.ph.py[g0 + a]; vz = A.ph.pz[g0 + a]; vw = A.ph.w[g0 + a];
+                    if (A.ph.parent) par = A.ph.parent[g0 + a];
+                }
+            }
+            int tot;
+            const int o = block_flag_scan(keep, redi, tot);   // barrier: all reads precede writes
+            if (keep) {
+                const int64_t at = g0 + wpos + o;
+                A.ph.px[at] = vx; A.ph.py[at] = vy; A.ph.pz[at] = vz; A.ph.w[at] = vw;
+                if (A.ph.parent) A.ph.parent[at] = par;
+            }
+            wpos += tot;
+            __syncthreads();
         }
-        write_tallies(A, c, t, nab_ei, nab_gi, redl, redd);
+        ph_count = wpos;
+    }
+
+    // ---------------------------------------------- counts, tallies
+    if (high_any) atomicOr(A.status, CMC_ST_GAMMA_HIGH);
+    if (t.drop_ph + t.drop_el + t.drop_po) atomicOr(A.status, CMC_ST_OVERFLOW);
+    if (tid == 0) {
+        if (A.ph.count) A.ph.count[c] = ph_count;
+        A.ne.count[c] = cnt_ne;
+        A.np.count[c] = cnt_np;
+    }
+    write_tallies(A, c, t, nab_ei, nab_gi, redl, redd);
+}
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_collide(StepArgs A, TabView<R> T, TabView<double> T64) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ CollideShared<R> sh;
+    const Smem S = carve(smem_raw, A.maxn);
+    const Rng rng = step_rng(A);
+    const int64_t n_items = A.list ? (int64_t)*A.list_n : A.n_cells;
+    for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+        const int64_t c = A.list ? (int64_t)A.list[item] : item;
+        collide_cell<R>(A, T, T64, rng, c, S, sh);
     }
 }
 
@@ -653,10 +670,10 @@ __global__ __launch_bounds__(kThreads) void k_collide(StepArgs A, TabView<R> T, 
 // per cell; k_events settles them and applies the events of the cell in
 // pair order.  Cells where the start-of-step reading does not hold (an event
 // on a particle used again, more open pairs than kCandCap, more particles
-// than the pass kernel's LDS) are listed for k_collide, the sequential
-// per-cell kernel above, which redoes the whole cell.
+// than the pass kernel's LDS) are redone by k_events with the sequential
+// per-cell step above (collide_cell).
 constexpr int kCandCap = 64;     // open pairs per cell (both passes)
-enum : int32_t { kFlagSlow = 1 };
+enum : int32_t { kFlagSlow = 1, kFlagListed = 2 };
 enum : uint32_t { kEvBr = 1, kEvTrPending = 2, kEvTr = 4, kEvBh = 8 };
 
 struct CellState {
@@ -671,9 +688,8 @@ struct Work {
     int32_t* ncand;                  // open pairs pushed per cell
     double* coef;                    // n_a n_b / n_ab per cell and pass
     uint64_t* step;                  // step number of the current step
-    int32_t* counters;               // [0] cells with open pairs, [1] cells for the sequential kernel
-    int32_t* list_ev;                // cells with open pairs (event kernel)
-    int32_t* list_slow;              // cells the sequential kernel runs
+    int32_t* counters;               // [0] cells listed for the event kernel
+    int32_t* list_ev;                // cells with open pairs or flagged for the sequential step
     uint64_t* cand;                  // [n_cells][kCandCap] open pairs
 };
 
@@ -681,7 +697,7 @@ __host__ __device__ inline size_t align256(size_t b) { return (b + 255) / 256 * 
 
 __host__ __device__ inline size_t work_bytes(int64_t n) {
     return align256(sizeof(CellState) * n) + align256(4 * n) + align256(4 * n) +
-           align256(16 * n) + align256(8) + align256(16) + 2 * align256(4 * n) + align256(8 * (size_t)n * kCandCap);
+           align256(16 * n) + align256(8) + align256(16) + align256(4 * n) + align256(8 * (size_t)n * kCandCap);
 }
 
 inline Work carve_work(void* base, int64_t n) {
@@ -694,7 +710,6 @@ inline Work carve_work(void* base, int64_t n) {
     w.step = reinterpret_cast<uint64_t*>(p); p += align256(8);
     w.counters = reinterpret_cast<int32_t*>(p); p += align256(16);
     w.list_ev = reinterpret_cast<int32_t*>(p); p += align256(4 * n);
-    w.list_slow = reinterpret_cast<int32_t*>(p); p += align256(4 * n);
     w.cand = reinterpret_cast<uint64_t*>(p);
     return w;
 }
@@ -971,16 +986,22 @@ __device__ __forceinline__ bool settle(double x, const U4& r, double rej, double
     return U1 < P && u53(r.z, r.w) < Pej;
 }
 
-// flag a cell for the sequential kernel; it is listed once
-__device__ __forceinline__ void mark_slow(const Work& W, int64_t c) {
-    if (!(atomicOr(&W.flags[c], kFlagSlow) & kFlagSlow)) W.list_slow[atomicAdd(&W.counters[1], 1)] = (int32_t)c;
+// list a cell (once) for the event kernel
+__device__ __forceinline__ void list_cell(const Work& W, int64_t c) {
+    if (!(atomicOr(&W.flags[c], kFlagListed) & kFlagListed)) W.list_ev[atomicAdd(&W.counters[0], 1)] = (int32_t)c;
 }
 
-// a pair the bound on P left open, for the event kernel (the cell is listed
-// with its first one; beyond kCandCap the cell goes to the sequential kernel)
+// a cell the event kernel runs with the sequential step
+__device__ __forceinline__ void mark_slow(const Work& W, int64_t c) {
+    atomicOr(&W.flags[c], kFlagSlow);
+    list_cell(W, c);
+}
+
+// a pair the bound on P left open, for the event kernel (beyond kCandCap
+// the cell takes the sequential step)
 __device__ __forceinline__ void push_cand(const Work& W, int64_t c, uint64_t rec) {
     const int k = atomicAdd(&W.ncand[c], 1);
-    if (k == 0) W.list_ev[atomicAdd(&W.counters[0], 1)] = (int32_t)c;
+    if (k == 0) list_cell(W, c);
     if (k < kCandCap) W.cand[c * kCandCap + k] = rec;
     else mark_slow(W, c);
 }
@@ -1145,320 +1166,351 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
     }
 }
 
-// One wavefront per cell with open pairs: settle them with P (same
-// arithmetic as the pass kernels, lookups from the full tables give the same
-// values as the slices), then apply the events in (pass, pair) order:
-// sample the energies, write the products, drop converted photons.
+// One workgroup per listed cell.  Cells flagged by the pass kernels (more
+// open pairs than kCandCap, more particles than the pass kernel's LDS) run
+// the sequential step.  Otherwise the first wavefront settles the open
+// pairs with P (same arithmetic as the pass kernels: lookups from the full
+// tables give the same values as the slices); an event on a particle used
+// by a later pair of its pass sends the cell to the sequential step too.
+// Else it applies the events in (pass, pair) order: samples the energies,
+// writes the products, and the four wavefronts then drop the converted
+// photons.
 template <typename R>
-__global__ __launch_bounds__(64) void k_events(StepArgs A, TabView<R> T, TabView<double> T64, Work W) {
+__global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, TabView<double> T64, Work W) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ CollideShared<R> sh;
     __shared__ uint64_t rec[kCandCap];
     __shared__ uint32_t killed[CMC_MAX_PER_CELL / 32];
-    const int lane = threadIdx.x;
+    __shared__ int ctl[4];        // [0] sequential step, [1] photons converted, [2] first to move, [3] photon count
+    __shared__ int wcnt[4][4];    // survivors per chunk group and wavefront
+    const Smem S = carve(smem_raw, A.maxn);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int n_items = W.counters[0];
     const double rej = 2.0 * (1.0 + A.near_rel);
     const Rng rng = step_rng(A);
     for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
         const int64_t c = W.list_ev[item];
-        if (W.flags[c] & kFlagSlow) continue;
-        const uint32_t cell = (uint32_t)c;
-        const int nc = min(W.ncand[c], kCandCap);
-        const int64_t e0 = A.el.off[c], g0 = A.ph.off[c], i0 = A.io.off[c];
-        const int Ne = live(A.el, c), Ng0 = live(A.ph, c), Ni = live(A.io, c);
-        // ---- settle the open pairs
-        uint32_t kind = 0;
-        uint64_t mine = 0;
-        int near_br = 0, near_tr = 0, near_bh = 0;
-        bool reused = false;
-        if (lane < nc) {
-            mine = W.cand[c * kCandCap + lane];
-            const int pass = ev_pass(mine), j = ev_j(mine), mi = ev_m(mine), ii = ev_i(mine);
-            const uint32_t bits = ev_kind(mine);
-            const CellTab<R> ct = pick<R>(W.cs[c]);
-            const double coef = W.coef[c * 2 + pass];
-            const double Wi = A.io.w[i0 + ii];
-            if (pass == 0) {
-                const int64_t ie = e0 + mi;
-                const Elec<R> e = electron_p<R>(A.el.px[ie], A.el.py[ie], A.el.pz[ie]);
-                const double We = A.el.w[ie];
-                const double Pej = Wi / (We > Wi ? We : Wi);
-                if (bits & 1u) {
-                    bool hi;
-                    const R sig = brems_lookup<R, false>(T, ct, e.g, e.gm1, hi).sig;
-                    const double x = coef * (double)sig * e.vrel * A.dt;
-                    if (settle(x, rng.draw((uint32_t)j, cell, kTagAccBr), rej, A.near_rel, Pej, near_br))
-                        kind = kEvBr | ((A.proc & CMC_TRIDENT) ? kEvTrPending : 0u);
-                }
-                if ((A.proc & CMC_TRIDENT) && !kind) {
-                    const R sig = (R)phys::trident_sigma(T.Z, (double)e.g);
-                    if (sig > (R)0) {
+        if (threadIdx.x == 0) { ctl[0] = (W.flags[c] & kFlagSlow) ? 1 : 0; ctl[1] = 0; }
+        __syncthreads();
+        const int64_t g0 = A.ph.off[c];
+        const int Ng0 = live(A.ph, c);
+        if (wv == 0 && !ctl[0]) do {
+            const uint32_t cell = (uint32_t)c;
+            const int nc = min(W.ncand[c], kCandCap);
+            const int64_t e0 = A.el.off[c], i0 = A.io.off[c];
+            const int Ne = live(A.el, c), Ni = live(A.io, c);
+            // ---- settle the open pairs
+            uint32_t kind = 0;
+            uint64_t mine = 0;
+            int near_br = 0, near_tr = 0, near_bh = 0;
+            bool reused = false;
+            if (lane < nc) {
+                mine = W.cand[c * kCandCap + lane];
+                const int pass = ev_pass(mine), j = ev_j(mine), mi = ev_m(mine), ii = ev_i(mine);
+                const uint32_t bits = ev_kind(mine);
+                const CellTab<R> ct = pick<R>(W.cs[c]);
+                const double coef = W.coef[c * 2 + pass];
+                const double Wi = A.io.w[i0 + ii];
+                if (pass == 0) {
+                    const int64_t ie = e0 + mi;
+                    const Elec<R> e = electron_p<R>(A.el.px[ie], A.el.py[ie], A.el.pz[ie]);
+                    const double We = A.el.w[ie];
+                    const double Pej = Wi / (We > Wi ? We : Wi);
+                    if (bits & 1u) {
+                        bool hi;
+                        const R sig = brems_lookup<R, false>(T, ct, e.g, e.gm1, hi).sig;
                         const double x = coef * (double)sig * e.vrel * A.dt;
-                        if (settle(x, rng.draw((uint32_t)j, cell, kTagAccTr), rej, A.near_rel, Pej, near_tr))
-                            kind = kEvTr;
+                        if (settle(x, rng.draw((uint32_t)j, cell, kTagAccBr), rej, A.near_rel, Pej, near_br))
+                            kind = kEvBr | ((A.proc & CMC_TRIDENT) ? kEvTrPending : 0u);
                     }
+                    if ((A.proc & CMC_TRIDENT) && !kind) {
+                        const R sig = (R)phys::trident_sigma(T.Z, (double)e.g);
+                        if (sig > (R)0) {
+                            const double x = coef * (double)sig * e.vrel * A.dt;
+                            if (settle(x, rng.draw((uint32_t)j, cell, kTagAccTr), rej, A.near_rel, Pej, near_tr))
+                                kind = kEvTr;
+                        }
+                    }
+                    reused = Ne < Ni && j + Ne < Ni;   // the electron pairs again later
+                } else {
+                    const R k = photon_k<R>(A.ph.px[g0 + mi], A.ph.py[g0 + mi], A.ph.pz[g0 + mi]);
+                    int ik; R wk; bool hi;
+                    const R sig = bh_lookup<R>(T, ct, k, ik, wk, hi);
+                    const double x = coef * (double)sig * phys::kC * A.dt;
+                    const double Wg = A.ph.w[g0 + mi];
+                    const double Pej = Wi / (Wg > Wi ? Wg : Wi);
+                    if (settle(x, rng.draw((uint32_t)j, cell, kTagAccBh), rej, A.near_rel, Pej, near_bh))
+                        kind = kEvBh;
+                    reused = Ng0 < Ni && j + Ng0 < Ni;
                 }
-                reused = Ne < Ni && j + Ne < Ni;   // the electron pairs again later
-            } else {
-                const R k = photon_k<R>(A.ph.px[g0 + mi], A.ph.py[g0 + mi], A.ph.pz[g0 + mi]);
-                int ik; R wk; bool hi;
-                const R sig = bh_lookup<R>(T, ct, k, ik, wk, hi);
-                const double x = coef * (double)sig * phys::kC * A.dt;
-                const double Wg = A.ph.w[g0 + mi];
-                const double Pej = Wi / (Wg > Wi ? Wg : Wi);
-                if (settle(x, rng.draw((uint32_t)j, cell, kTagAccBh), rej, A.near_rel, Pej, near_bh))
-                    kind = kEvBh;
-                reused = Ng0 < Ni && j + Ng0 < Ni;
             }
-        }
-        // an event on a particle used by a later pair of its pass: the
-        // sequential kernel redoes the cell
-        if (__ballot(kind != 0 && reused) != 0ull) {
-            if (lane == 0) mark_slow(W, c);
-            continue;
-        }
-        // ---- events in (pass, pair index) order
-        const unsigned long long evb = __ballot(kind != 0);
-        const int n = __popcll(evb);
-        const uint32_t key = kind ? ev_key(mine) : 0xFFFFFFFFu;
-        int rank = 0;
-        for (int l = 0; l < 64; ++l) {
-            if (!((evb >> l) & 1ull)) continue;
-            rank += __shfl(key, l, 64) < key;
-        }
-        __syncthreads();
-        if (kind) rec[rank] = (mine & ~(0x7Full << 48)) | ((uint64_t)kind << 48);
-        __syncthreads();
-        const uint64_t r = lane < n ? rec[lane] : 0ull;
-        const bool live_ev = lane < n;
-        const int pass = live_ev ? ev_pass(r) : 2;
-        const uint32_t evk = live_ev ? ev_kind(r) : 0u;
-        const int j = ev_j(r), mi = ev_m(r), ii = ev_i(r);
-        const CellTab<double> ct64 = W.cs[c].d;
-        const int cap_ph = (int)(A.ph.off[c + 1] - g0);
-        const int cap_ne = (int)(A.ne.off[c + 1] - A.ne.off[c]), cap_np = (int)(A.np.off[c + 1] - A.np.off[c]);
-        const int cnt_ne0 = A.ne.count[c], cnt_np0 = A.np.count[c];
-        Tally t = {};
-        t.near_br = near_br; t.near_tr = near_tr; t.near_bh = near_bh;
-        bool f_ph = false, f_tr = false, f_bh = false;
-        double kx = 0, ky = 0, kz = 0, pxm = 0, pym = 0, pzm = 0, pxp = 0, pyp = 0, pzp = 0, Wm = 0;
-        int64_t par = 0;
-        // with few events the wavefront inverts each CDF together (one round
-        // of table reads per event), else every lane bisects its own; both
-        // give the same abscissa
-        const bool coop = n <= 8;
-        const auto invert = [&](bool has, const CdfRow<double>& row, double xi, double& ct) {
-            if (coop) return cdf_invert_wave<double>(has, row, ct64, xi, ct);
-            return has ? cdf_invert<double>(row.T, row.kind, row.i, row.w, ct64, xi, ct) : 0.0;
-        };
-        // ---- first draw: Bremsstrahlung photon energy or Bethe-Heitler pair
-        double px = 0, py = 0, pz = 0, kd = 0, gd = 0, gm1d = 0;
-        int64_t ie = 0, ig = 0;
-        BremsLook<double> BLd = {};
-        CdfRow<double> rowA = {};
-        double xiA = 0.0;
-        bool reqA = false;
-        if (pass == 0) {
-            ie = e0 + mi;
-            par = ie;
-            px = A.el.px[ie]; py = A.el.py[ie]; pz = A.el.pz[ie];
-            Wm = A.el.w[ie];
-            if (evk & kEvBr) {
-                const U4 q = rng.draw((uint32_t)j, cell, kTagSmpBr);
-                const double p2d = px * px + py * py + pz * pz;
-                gd = sqrt(1.0 + p2d); gm1d = p2d / (gd + 1.0);
-                bool hi2;
-                BLd = brems_lookup<double, false>(T64, ct64, gd, gm1d, hi2);
-                rowA = brems_row<double>(T64, BLd);
+            // an event on a particle used by a later pair of its pass: the
+            // cell is redone by the sequential step below
+            if (__ballot(kind != 0 && reused) != 0ull) {
+                if (lane == 0) ctl[0] = 1;
+                break;
+            }
+            // ---- events in (pass, pair index) order
+            const unsigned long long evb = __ballot(kind != 0);
+            const int n = __popcll(evb);
+            const uint32_t key = kind ? ev_key(mine) : 0xFFFFFFFFu;
+            int rank = 0;
+            for (int l = 0; l < 64; ++l) {
+                if (!((evb >> l) & 1ull)) continue;
+                rank += __shfl(key, l, 64) < key;
+            }
+            if (kind) rec[rank] = (mine & ~(0x7Full << 48)) | ((uint64_t)kind << 48);
+            Team<64>::sync();
+            const uint64_t r = lane < n ? rec[lane] : 0ull;
+            const bool live_ev = lane < n;
+            const int pass = live_ev ? ev_pass(r) : 2;
+            const uint32_t evk = live_ev ? ev_kind(r) : 0u;
+            const int j = ev_j(r), mi = ev_m(r), ii = ev_i(r);
+            const CellTab<double> ct64 = W.cs[c].d;
+            const int cap_ph = (int)(A.ph.off[c + 1] - g0);
+            const int cap_ne = (int)(A.ne.off[c + 1] - A.ne.off[c]), cap_np = (int)(A.np.off[c + 1] - A.np.off[c]);
+            const int cnt_ne0 = A.ne.count[c], cnt_np0 = A.np.count[c];
+            Tally t = {};
+            t.near_br = near_br; t.near_tr = near_tr; t.near_bh = near_bh;
+            bool f_ph = false, f_tr = false, f_bh = false;
+            double kx = 0, ky = 0, kz = 0, pxm = 0, pym = 0, pzm = 0, pxp = 0, pyp = 0, pzp = 0, Wm = 0;
+            int64_t par = 0;
+            // with few events the wavefront inverts each CDF together (one round
+            // of table reads per event), else every lane bisects its own; both
+            // give the same abscissa
+            const bool coop = n <= 8;
+            const auto invert = [&](bool has, const CdfRow<double>& row, double xi, double& ct) {
+                if (coop) return cdf_invert_wave<double>(has, row, ct64, xi, ct);
+                return has ? cdf_invert<double>(row.T, row.kind, row.i, row.w, ct64, xi, ct) : 0.0;
+            };
+            // ---- first draw: Bremsstrahlung photon energy or Bethe-Heitler pair
+            double px = 0, py = 0, pz = 0, kd = 0, gd = 0, gm1d = 0;
+            int64_t ie = 0, ig = 0;
+            BremsLook<double> BLd = {};
+            CdfRow<double> rowA = {};
+            double xiA = 0.0;
+            bool reqA = false;
+            if (pass == 0) {
+                ie = e0 + mi;
+                par = ie;
+                px = A.el.px[ie]; py = A.el.py[ie]; pz = A.el.pz[ie];
+                Wm = A.el.w[ie];
+                if (evk & kEvBr) {
+                    const U4 q = rng.draw((uint32_t)j, cell, kTagSmpBr);
+                    const double p2d = px * px + py * py + pz * pz;
+                    gd = sqrt(1.0 + p2d); gm1d = p2d / (gd + 1.0);
+                    bool hi2;
+                    BLd = brems_lookup<double, false>(T64, ct64, gd, gm1d, hi2);
+                    rowA = brems_row<double>(T64, BLd);
+                    xiA = u53(q.x, q.y);
+                    reqA = true;
+                }
+            } else if (pass == 1) {
+                ig = g0 + mi;
+                par = ig;
+                px = A.ph.px[ig]; py = A.ph.py[ig]; pz = A.ph.pz[ig];
+                Wm = A.ph.w[ig];
+                kd = sqrt(px * px + py * py + pz * pz);
+                const U4 q = rng.draw((uint32_t)j, cell, kTagSmpBh);
+                int ikd; double wkd; bool hi2;
+                bh_lookup<double>(T64, ct64, kd, ikd, wkd, hi2);
+                rowA = bh_row<double>(T64, ikd, wkd);
                 xiA = u53(q.x, q.y);
                 reqA = true;
             }
-        } else if (pass == 1) {
-            ig = g0 + mi;
-            par = ig;
-            px = A.ph.px[ig]; py = A.ph.py[ig]; pz = A.ph.pz[ig];
-            Wm = A.ph.w[ig];
-            kd = sqrt(px * px + py * py + pz * pz);
-            const U4 q = rng.draw((uint32_t)j, cell, kTagSmpBh);
-            int ikd; double wkd; bool hi2;
-            bh_lookup<double>(T64, ct64, kd, ikd, wkd, hi2);
-            rowA = bh_row<double>(T64, ikd, wkd);
-            xiA = u53(q.x, q.y);
-            reqA = true;
-        }
-        double ctA = 0.0;
-        const double tA = invert(reqA, rowA, xiA, ctA);
-        bool tr = false;
-        if (pass == 0) {
-            if (evk & kEvBr) {
-                double k, g2, g2m1;
-                brems_energies(BLd.seg, gd, gm1d, ctA, k, g2, g2m1);
-                const double pmd = sqrt(px * px + py * py + pz * pz);
-                const double pf = sqrt(g2m1 * (g2 + 1.0));
-                const double f = pf / pmd, h = k / pmd;
-                kx = px * h; ky = py * h; kz = pz * h;
-                px *= f; py *= f; pz *= f;
-                t.ev_br++;
-                t.E_br += Wm * sqrt(kx * kx + ky * ky + kz * kz);
-                t.dE_el += Wm * (-k);
-                t.W_br += Wm;
-                f_ph = true;
-            }
-            tr = (evk & kEvTr) != 0;
-            if (evk & kEvTrPending) {
-                // Trident on the electron left by Bremsstrahlung (same pair)
-                const double Wi = A.io.w[i0 + ii];
-                const double Pej = Wi / (Wm > Wi ? Wm : Wi);
-                const Elec<R> e = electron_p<R>(px, py, pz);
-                const R sig = (R)phys::trident_sigma(T.Z, (double)e.g);
-                if (sig > (R)0) {
-                    const double x = W.coef[c * 2] * (double)sig * e.vrel * A.dt;
-                    const double P = -expm1(-x);
-                    const U4 q = rng.draw((uint32_t)j, cell, kTagAccTr);
-                    const double U1 = u53(q.x, q.y), U2 = u53(q.z, q.w);
-                    if (fabs(U1 - P) <= A.near_rel * P) t.near_tr++;
-                    tr = U1 < P && U2 < Pej;
+            double ctA = 0.0;
+            const double tA = invert(reqA, rowA, xiA, ctA);
+            bool tr = false;
+            if (pass == 0) {
+                if (evk & kEvBr) {
+                    double k, g2, g2m1;
+                    brems_energies(BLd.seg, gd, gm1d, ctA, k, g2, g2m1);
+                    const double pmd = sqrt(px * px + py * py + pz * pz);
+                    const double pf = sqrt(g2m1 * (g2 + 1.0));
+                    const double f = pf / pmd, h = k / pmd;
+                    kx = px * h; ky = py * h; kz = pz * h;
+                    px *= f; py *= f; pz *= f;
+                    t.ev_br++;
+                    t.E_br += Wm * sqrt(kx * kx + ky * ky + kz * kz);
+                    t.dE_el += Wm * (-k);
+                    t.W_br += Wm;
+                    f_ph = true;
                 }
+                tr = (evk & kEvTr) != 0;
+                if (evk & kEvTrPending) {
+                    // Trident on the electron left by Bremsstrahlung (same pair)
+                    const double Wi = A.io.w[i0 + ii];
+                    const double Pej = Wi / (Wm > Wi ? Wm : Wi);
+                    const Elec<R> e = electron_p<R>(px, py, pz);
+                    const R sig = (R)phys::trident_sigma(T.Z, (double)e.g);
+                    if (sig > (R)0) {
+                        const double x = W.coef[c * 2] * (double)sig * e.vrel * A.dt;
+                        const double P = -expm1(-x);
+                        const U4 q = rng.draw((uint32_t)j, cell, kTagAccTr);
+                        const double U1 = u53(q.x, q.y), U2 = u53(q.z, q.w);
+                        if (fabs(U1 - P) <= A.near_rel * P) t.near_tr++;
+                        tr = U1 < P && U2 < Pej;
+                    }
+                }
+            } else if (pass == 1) {
+                double gpl, gmi;
+                bh_energies(kd, tA, ctA, gpl, gmi);
+                const double pplus = sqrt((gpl - 1.0) * (gpl + 1.0)), pminus = sqrt((gmi - 1.0) * (gmi + 1.0));
+                const double fp = pplus / kd, fm = pminus / kd;
+                pxp = px * fp; pyp = py * fp; pzp = pz * fp;
+                pxm = px * fm; pym = py * fm; pzm = pz * fm;
+                t.ev_bh++;
+                t.E_bh += Wm * (sqrt(1.0 + pxp * pxp + pyp * pyp + pzp * pzp) + sqrt(1.0 + pxm * pxm + pym * pym + pzm * pzm));
+                t.dE_ph += -Wm * kd;
+                t.W_bh += Wm;
+                f_bh = true;
             }
-        } else if (pass == 1) {
-            double gpl, gmi;
-            bh_energies(kd, tA, ctA, gpl, gmi);
-            const double pplus = sqrt((gpl - 1.0) * (gpl + 1.0)), pminus = sqrt((gmi - 1.0) * (gmi + 1.0));
-            const double fp = pplus / kd, fm = pminus / kd;
-            pxp = px * fp; pyp = py * fp; pzp = pz * fp;
-            pxm = px * fm; pym = py * fm; pzm = pz * fm;
-            t.ev_bh++;
-            t.E_bh += Wm * (sqrt(1.0 + pxp * pxp + pyp * pyp + pzp * pzp) + sqrt(1.0 + pxm * pxm + pym * pym + pzm * pzm));
-            t.dE_ph += -Wm * kd;
-            t.W_bh += Wm;
-            f_bh = true;
-        }
-        // ---- Trident: pair energy, then the positron split
-        U4 qt = {0u, 0u, 0u, 0u};
-        CdfRow<double> rowB = {};
-        double gt = 0, gtm1 = 0, pmt = 0;
-        if (tr) {
-            qt = rng.draw((uint32_t)j, cell, kTagSmpTr);
-            const double p2d = px * px + py * py + pz * pz;
-            gt = sqrt(1.0 + p2d); gtm1 = p2d / (gt + 1.0); pmt = sqrt(p2d);
-            rowB = trident_row<double>(T64, gt);
-        }
-        double ctB = 0.0;
-        const double tB = invert(tr, rowB, u53(qt.x, qt.y), ctB);
-        double gpair = 0, gpl = 0, gmi = 0, gfm1 = 0;
-        bool reqC = false;
-        CdfRow<double> rowC = {};
-        if (tr) {
-            reqC = trident_pair(gtm1, tB, ctB, gpair, gpl, gmi, gfm1);
-            if (reqC) rowC = split_row<double>(T64, gpair);
-        }
-        double ctC = 0.0;
-        const double tC = invert(reqC, rowC, u53(qt.z, qt.w), ctC);
-        if (reqC) split_energies(gpair, tC, ctC, gpl, gmi);
-        if (tr) {
-            const double gf = gfm1 + 1.0;
-            const double pf = sqrt(gfm1 * (gf + 1.0));
-            const double pplus = sqrt((gpl - 1.0) * (gpl + 1.0)), pminus = sqrt((gmi - 1.0) * (gmi + 1.0));
-            const double f = pf / pmt, fp = pplus / pmt, fm = pminus / pmt;
-            pxp = px * fp; pyp = py * fp; pzp = pz * fp;
-            pxm = px * fm; pym = py * fm; pzm = pz * fm;
-            px *= f; py *= f; pz *= f;
-            t.ev_tr++;
-            t.E_tr += Wm * (sqrt(1.0 + pxp * pxp + pyp * pyp + pzp * pzp) + sqrt(1.0 + pxm * pxm + pym * pym + pzm * pzm));
-            t.dE_el += Wm * (-gpair);
-            t.W_tr += Wm;
-            f_tr = true;
-        }
-        if (pass == 0 && (f_ph || f_tr)) { A.el.px[ie] = px; A.el.py[ie] = py; A.el.pz[ie] = pz; }
-        // slots in (pass, pair) order: lanes are already in that order
-        const unsigned long long b_ph = __ballot(f_ph), b_tr = __ballot(f_tr), b_bh = __ballot(f_bh);
-        const unsigned long long below = (1ull << lane) - 1ull;
-        const int n_ph = __popcll(b_ph), n_tr = __popcll(b_tr), n_bh = __popcll(b_bh);
-        if (f_ph) {
-            const int slot = Ng0 + __popcll(b_ph & below);
-            if (slot < cap_ph) {
-                const int64_t at = g0 + slot;
-                A.ph.px[at] = kx; A.ph.py[at] = ky; A.ph.pz[at] = kz; A.ph.w[at] = Wm;
-                if (A.ph.parent) A.ph.parent[at] = par;
-            } else t.drop_ph++;
-        }
-        if (f_tr || f_bh) {
-            const int o = f_tr ? __popcll(b_tr & below) : n_tr + __popcll(b_bh & below);
-            if (cnt_ne0 + o < cap_ne) {
-                const int64_t at = A.ne.off[c] + cnt_ne0 + o;
-                A.ne.px[at] = pxm; A.ne.py[at] = pym; A.ne.pz[at] = pzm; A.ne.w[at] = Wm;
-                if (A.ne.parent) A.ne.parent[at] = par;
-            } else t.drop_el++;
-            if (cnt_np0 + o < cap_np) {
-                const int64_t at = A.np.off[c] + cnt_np0 + o;
-                A.np.px[at] = pxp; A.np.py[at] = pyp; A.np.pz[at] = pzp; A.np.w[at] = Wm;
-                if (A.np.parent) A.np.parent[at] = par;
-            } else t.drop_po++;
-        }
-        int ph_count = min(cap_ph, Ng0 + n_ph);
-        // remove converted photons (stable, in place): four chunks of 64 are
-        // read before any is written (a survivor only moves down, never into
-        // a chunk not yet read)
-        if (n_bh) {
-            for (int i = lane; i < (Ng0 + 31) / 32; i += 64) killed[i] = 0u;
-            __syncthreads();
-            if (f_bh) atomicOr(&killed[mi >> 5], 1u << (mi & 31));
-            __syncthreads();
-            // photons before the first converted one stay where they are
-            int first = f_bh ? mi : 0x7FFFFFFF;
+            // ---- Trident: pair energy, then the positron split
+            U4 qt = {0u, 0u, 0u, 0u};
+            CdfRow<double> rowB = {};
+            double gt = 0, gtm1 = 0, pmt = 0;
+            if (tr) {
+                qt = rng.draw((uint32_t)j, cell, kTagSmpTr);
+                const double p2d = px * px + py * py + pz * pz;
+                gt = sqrt(1.0 + p2d); gtm1 = p2d / (gt + 1.0); pmt = sqrt(p2d);
+                rowB = trident_row<double>(T64, gt);
+            }
+            double ctB = 0.0;
+            const double tB = invert(tr, rowB, u53(qt.x, qt.y), ctB);
+            double gpair = 0, gpl = 0, gmi = 0, gfm1 = 0;
+            bool reqC = false;
+            CdfRow<double> rowC = {};
+            if (tr) {
+                reqC = trident_pair(gtm1, tB, ctB, gpair, gpl, gmi, gfm1);
+                if (reqC) rowC = split_row<double>(T64, gpair);
+            }
+            double ctC = 0.0;
+            const double tC = invert(reqC, rowC, u53(qt.z, qt.w), ctC);
+            if (reqC) split_energies(gpair, tC, ctC, gpl, gmi);
+            if (tr) {
+                const double gf = gfm1 + 1.0;
+                const double pf = sqrt(gfm1 * (gf + 1.0));
+                const double pplus = sqrt((gpl - 1.0) * (gpl + 1.0)), pminus = sqrt((gmi - 1.0) * (gmi + 1.0));
+                const double f = pf / pmt, fp = pplus / pmt, fm = pminus / pmt;
+                pxp = px * fp; pyp = py * fp; pzp = pz * fp;
+                pxm = px * fm; pym = py * fm; pzm = pz * fm;
+                px *= f; py *= f; pz *= f;
+                t.ev_tr++;
+                t.E_tr += Wm * (sqrt(1.0 + pxp * pxp + pyp * pyp + pzp * pzp) + sqrt(1.0 + pxm * pxm + pym * pym + pzm * pzm));
+                t.dE_el += Wm * (-gpair);
+                t.W_tr += Wm;
+                f_tr = true;
+            }
+            if (pass == 0 && (f_ph || f_tr)) { A.el.px[ie] = px; A.el.py[ie] = py; A.el.pz[ie] = pz; }
+            // slots in (pass, pair) order: lanes are already in that order
+            const unsigned long long b_ph = __ballot(f_ph), b_tr = __ballot(f_tr), b_bh = __ballot(f_bh);
+            const unsigned long long below = (1ull << lane) - 1ull;
+            const int n_ph = __popcll(b_ph), n_tr = __popcll(b_tr), n_bh = __popcll(b_bh);
+            if (f_ph) {
+                const int slot = Ng0 + __popcll(b_ph & below);
+                if (slot < cap_ph) {
+                    const int64_t at = g0 + slot;
+                    A.ph.px[at] = kx; A.ph.py[at] = ky; A.ph.pz[at] = kz; A.ph.w[at] = Wm;
+                    if (A.ph.parent) A.ph.parent[at] = par;
+                } else t.drop_ph++;
+            }
+            if (f_tr || f_bh) {
+                const int o = f_tr ? __popcll(b_tr & below) : n_tr + __popcll(b_bh & below);
+                if (cnt_ne0 + o < cap_ne) {
+                    const int64_t at = A.ne.off[c] + cnt_ne0 + o;
+                    A.ne.px[at] = pxm; A.ne.py[at] = pym; A.ne.pz[at] = pzm; A.ne.w[at] = Wm;
+                    if (A.ne.parent) A.ne.parent[at] = par;
+                } else t.drop_el++;
+                if (cnt_np0 + o < cap_np) {
+                    const int64_t at = A.np.off[c] + cnt_np0 + o;
+                    A.np.px[at] = pxp; A.np.py[at] = pyp; A.np.pz[at] = pzp; A.np.w[at] = Wm;
+                    if (A.np.parent) A.np.parent[at] = par;
+                } else t.drop_po++;
+            }
+            int ph_count = min(cap_ph, Ng0 + n_ph);
+            if (n_bh) {
+                // converted photons: a bitmap for the four wavefronts
+                for (int i = lane; i < (Ng0 + 31) / 32; i += 64) killed[i] = 0u;
+                Team<64>::sync();
+                if (f_bh) atomicOr(&killed[mi >> 5], 1u << (mi & 31));
+                // photons before the first converted one stay where they are
+                int first = f_bh ? mi : 0x7FFFFFFF;
 #pragma unroll
-            for (int o = 32; o > 0; o >>= 1) first = min(first, __shfl_xor(first, o, 64));
-            int wpos = first & ~63;
-            for (int base = wpos; base < ph_count; base += 256) {
+                for (int o = 32; o > 0; o >>= 1) first = min(first, __shfl_xor(first, o, 64));
+                if (lane == 0) { ctl[1] = n_bh; ctl[2] = first & ~63; ctl[3] = ph_count; }
+            }
+            // tallies of the events (the pair counts were written by the passes)
+            long long iv[9] = {t.ev_br, t.ev_tr, t.ev_bh, t.near_br, t.near_tr, t.near_bh, t.drop_ph, t.drop_el, t.drop_po};
+            double dv[8] = {t.E_br, t.E_tr, t.E_bh, t.dE_el, t.dE_ph, t.W_br, t.W_tr, t.W_bh};
+#pragma unroll
+            for (int q = 0; q < 9; ++q)
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) iv[q] += __shfl_xor(iv[q], o, 64);
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) dv[q] += __shfl_xor(dv[q], o, 64);
+            if (lane == 0) {
+                int64_t* ti = A.ti + c * CMC_NI;
+                ti[CMC_I_EV_BR] = iv[0]; ti[CMC_I_EV_TR] = iv[1]; ti[CMC_I_EV_BH] = iv[2];
+                ti[CMC_I_NEAR_BR] = iv[3]; ti[CMC_I_NEAR_TR] = iv[4]; ti[CMC_I_NEAR_BH] = iv[5];
+                ti[CMC_I_DROP_PH] = iv[6]; ti[CMC_I_DROP_EL] = iv[7]; ti[CMC_I_DROP_PO] = iv[8];
+                double* td = A.td + c * CMC_ND + CMC_D_E_BR;
+                for (int q = 0; q < 8; ++q) td[q] = dv[q];
+                if (A.ph.count && !n_bh) A.ph.count[c] = ph_count;
+                A.ne.count[c] = min(cap_ne, cnt_ne0 + n_tr + n_bh);
+                A.np.count[c] = min(cap_np, cnt_np0 + n_tr + n_bh);
+                if (iv[6] + iv[7] + iv[8]) atomicOr(A.status, CMC_ST_OVERFLOW);
+            }
+        } while (0);
+        __syncthreads();
+        if (ctl[0]) {
+            collide_cell<R>(A, T, T64, rng, c, S, sh);
+            continue;
+        }
+        if (ctl[1]) {
+            // stable in-place removal of the converted photons: each
+            // wavefront reads four chunks of 64 of a group of 1024 before any
+            // is written (a survivor only moves down, never into a chunk not
+            // yet read), the chunk counts give every survivor its slot
+            const int end = ctl[3];
+            const unsigned long long below = (1ull << lane) - 1ull;
+            int wpos = ctl[2];
+            for (int base = ctl[2]; base < end; base += 1024) {
                 double vx[4], vy[4], vz[4], vw[4];
                 int64_t pp[4];
                 bool keep[4];
+                unsigned long long bk[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    const int a = base + 64 * u + lane;
-                    keep[u] = a < ph_count && !(a < Ng0 && ((killed[a >> 5] >> (a & 31)) & 1u));
+                    const int a = base + (4 * u + wv) * 64 + lane;
+                    keep[u] = a < end && !(a < Ng0 && ((killed[a >> 5] >> (a & 31)) & 1u));
                     vx[u] = vy[u] = vz[u] = vw[u] = 0.0;
                     pp[u] = -1;
                     if (keep[u]) {
                         vx[u] = A.ph.px[g0 + a]; vy[u] = A.ph.py[g0 + a]; vz[u] = A.ph.pz[g0 + a]; vw[u] = A.ph.w[g0 + a];
                         if (A.ph.parent) pp[u] = A.ph.parent[g0 + a];
                     }
+                    bk[u] = __ballot(keep[u]);
+                    if (lane == 0) wcnt[u][wv] = __popcll(bk[u]);
                 }
+                __syncthreads();
+                int at = wpos;
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    const unsigned long long bk = __ballot(keep[u]);
+                    int mine0 = at;
+                    for (int w = 0; w < 4; ++w) { if (w < wv) mine0 += wcnt[u][w]; at += wcnt[u][w]; }
                     if (keep[u]) {
-                        const int64_t at = g0 + wpos + __popcll(bk & below);
-                        A.ph.px[at] = vx[u]; A.ph.py[at] = vy[u]; A.ph.pz[at] = vz[u]; A.ph.w[at] = vw[u];
-                        if (A.ph.parent) A.ph.parent[at] = pp[u];
+                        const int64_t dst = g0 + mine0 + __popcll(bk[u] & below);
+                        A.ph.px[dst] = vx[u]; A.ph.py[dst] = vy[u]; A.ph.pz[dst] = vz[u]; A.ph.w[dst] = vw[u];
+                        if (A.ph.parent) A.ph.parent[dst] = pp[u];
                     }
-                    wpos += __popcll(bk);
                 }
+                wpos = at;
+                __syncthreads();
             }
-            ph_count = wpos;
+            if (threadIdx.x == 0 && A.ph.count) A.ph.count[c] = wpos;
         }
-        // tallies of the events (the pair counts were written by the passes)
-        long long iv[9] = {t.ev_br, t.ev_tr, t.ev_bh, t.near_br, t.near_tr, t.near_bh, t.drop_ph, t.drop_el, t.drop_po};
-        double dv[8] = {t.E_br, t.E_tr, t.E_bh, t.dE_el, t.dE_ph, t.W_br, t.W_tr, t.W_bh};
-#pragma unroll
-        for (int q = 0; q < 9; ++q)
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) iv[q] += __shfl_xor(iv[q], o, 64);
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) dv[q] += __shfl_xor(dv[q], o, 64);
-        if (lane == 0) {
-            int64_t* ti = A.ti + c * CMC_NI;
-            ti[CMC_I_EV_BR] = iv[0]; ti[CMC_I_EV_TR] = iv[1]; ti[CMC_I_EV_BH] = iv[2];
-            ti[CMC_I_NEAR_BR] = iv[3]; ti[CMC_I_NEAR_TR] = iv[4]; ti[CMC_I_NEAR_BH] = iv[5];
-            ti[CMC_I_DROP_PH] = iv[6]; ti[CMC_I_DROP_EL] = iv[7]; ti[CMC_I_DROP_PO] = iv[8];
-            double* td = A.td + c * CMC_ND + CMC_D_E_BR;
-            for (int q = 0; q < 8; ++q) td[q] = dv[q];
-            if (A.ph.count) A.ph.count[c] = ph_count;
-            A.ne.count[c] = min(cap_ne, cnt_ne0 + n_tr + n_bh);
-            A.np.count[c] = min(cap_np, cnt_np0 + n_tr + n_bh);
-            if (iv[6] + iv[7] + iv[8]) atomicOr(A.status, CMC_ST_OVERFLOW);
-        }
-        __syncthreads();
     }
 }
 
@@ -1750,23 +1802,17 @@ extern "C" cmc_status cmc_collide_step(cmc_tables t, const cmc_cells* cells, cmc
     cmc_status s1 = launch_passes(A, t, W, fp64, team, st);
     if (s1 != CMC_OK) return s1;
     if (P->pass_events[1]) (void)hipEventRecord(static_cast<hipEvent_t>(P->pass_events[1]), st);
-    // open pairs and events of the listed cells, then the sequential kernel
-    // on its list (both lists are short: small grids)
-    A.list = W.list_slow; A.list_n = W.counters + 1;
+    // the listed cells: open pairs and events, or the sequential step (a
+    // short list: a small grid)
     const unsigned gev = (unsigned)std::min<int64_t>(A.n_cells, 512);
-    const unsigned gslow = (unsigned)std::min<int64_t>(A.n_cells, 256);
     if (fp64) {
-        hipLaunchKernelGGL(k_events<double>, dim3(gev), dim3(64), 0, st, A, view64(t), view64(t), W);
-        CMC_CHECK_LAUNCH("cmc_collide_step: k_events");
-        lds_attr((const void*)k_collide<double>, shm, st);
-        hipLaunchKernelGGL(k_collide<double>, dim3(gslow), dim3(kThreads), shm, st, A, view64(t), view64(t));
+        lds_attr((const void*)k_events<double>, shm, st);
+        hipLaunchKernelGGL(k_events<double>, dim3(gev), dim3(kThreads), shm, st, A, view64(t), view64(t), W);
     } else {
-        hipLaunchKernelGGL(k_events<float>, dim3(gev), dim3(64), 0, st, A, view32(t), view64(t), W);
-        CMC_CHECK_LAUNCH("cmc_collide_step: k_events");
-        lds_attr((const void*)k_collide<float>, shm, st);
-        hipLaunchKernelGGL(k_collide<float>, dim3(gslow), dim3(kThreads), shm, st, A, view32(t), view64(t));
+        lds_attr((const void*)k_events<float>, shm, st);
+        hipLaunchKernelGGL(k_events<float>, dim3(gev), dim3(kThreads), shm, st, A, view32(t), view64(t), W);
     }
-    CMC_CHECK_LAUNCH("cmc_collide_step: k_collide");
+    CMC_CHECK_LAUNCH("cmc_collide_step: k_events");
     return CMC_OK;
 }
 
