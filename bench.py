@@ -198,7 +198,7 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="cfg2", choices=sorted(WORKLOADS))
-    ap.add_argument("--schedule", default="auto", choices=["auto", "group", "wave", "cell"])
+    ap.add_argument("--schedule", default="auto", choices=["auto", "group", "wave", "hybrid", "cell"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 plain comparison")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -215,7 +215,7 @@ def main():
     import paper_1907_02814_amd as cmc
     from paper_1907_02814_amd import workloads as W
     sched = {"auto": cmc.SCHED_AUTO, "group": cmc.SCHED_GROUP, "wave": cmc.SCHED_WAVE,
-             "cell": cmc.SCHED_CELL}[a.schedule]
+             "hybrid": cmc.SCHED_HYBRID, "cell": cmc.SCHED_CELL}[a.schedule]
     print(f"[bench] generating {a.workload}", file=sys.stderr, flush=True)
     wl = getattr(W, a.workload)()
     fp32 = run_gpu(wl, cmc.FP32, a.steps, a.warmup, sched)

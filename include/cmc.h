@@ -232,12 +232,15 @@ size_t cmc_step_workspace_bytes(int64_t n_cells, int32_t schedule);
  *                   the sequential kernel;
  *  CMC_SCHED_WAVE   the same with one wavefront per cell (cells above
  *                   1024 particles of a species take the fallback);
- *  CMC_SCHED_AUTO   GROUP or WAVE, whichever is faster on the first step of
- *                   a launch shape (device, n_cells, max_per_cell,
- *                   processes, precision): that first call times both and
- *                   waits for the timing; under stream capture an untimed
- *                   shape uses GROUP. */
-enum { CMC_SCHED_AUTO = 0, CMC_SCHED_CELL = 1, CMC_SCHED_GROUP = 2, CMC_SCHED_WAVE = 3 };
+ *  CMC_SCHED_HYBRID wavefronts for the cells with at most 1024 particles of
+ *                   every species, workgroups for the larger ones (uneven
+ *                   cells);
+ *  CMC_SCHED_AUTO   GROUP against WAVE (max_per_cell <= 1024) or HYBRID,
+ *                   whichever is faster on the first step of a launch shape
+ *                   (device, n_cells, max_per_cell, processes, precision):
+ *                   that first call times both and waits for the timing;
+ *                   under stream capture an untimed shape uses GROUP. */
+enum { CMC_SCHED_AUTO = 0, CMC_SCHED_CELL = 1, CMC_SCHED_GROUP = 2, CMC_SCHED_WAVE = 3, CMC_SCHED_HYBRID = 4 };
 
 /* ------------------------------------------------------------------ */
 /* Expected photon energy yield (deterministic): for every cell c,      */

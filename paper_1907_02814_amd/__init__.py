@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(HERE, "libcmc.so")
 
 BREMS, BH, TRIDENT = 1, 2, 4
 FP64, FP32 = 0, 1
-SCHED_AUTO, SCHED_CELL, SCHED_GROUP, SCHED_WAVE = 0, 1, 2, 3
+SCHED_AUTO, SCHED_CELL, SCHED_GROUP, SCHED_WAVE, SCHED_HYBRID = 0, 1, 2, 3, 4
 MAX_PER_CELL = 16384
 ST_OVERFLOW, ST_GAMMA_HIGH, ST_BAD_CELL, ST_BAD_WEIGHT, ST_TOO_LARGE = 1, 2, 4, 8, 16
 I_NAMES = ["pairs_br", "pairs_tr", "pairs_bh", "ev_br", "ev_tr", "ev_bh",

@@ -1016,7 +1016,7 @@ __device__ __forceinline__ void push_cand(const Work& W, int64_t c, uint64_t rec
 // Workgroup teams run best at six wavefronts per SIMD (a few spilled
 // registers); wavefront teams are limited by LDS anyway.
 template <typename R, int kT, int kPass>
-__global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, TabView<R> T, Work W, int cap) {
+__global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, TabView<R> T, Work W, int cap, int filter, int fcap) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red4[kWaves * 4];
     __shared__ uint32_t redu[kWaves];
@@ -1034,6 +1034,10 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
         const uint32_t cell = (uint32_t)c;
         if (W.cs[c].status) continue;                       // invalid cell (flagged by k_cell_state)
         const int Ne = live(A.el, c), Ng = live(A.ph, c), Ni = live(A.io, c);
+        // size classes of the hybrid schedule: filter 1 takes the cells up
+        // to fcap particles per species, filter 2 the larger ones
+        const int mx = max(Ne, max(Ng, Ni));
+        if ((filter == 1 && mx > fcap) || (filter == 2 && mx <= fcap)) continue;
         if (Ne > A.maxn || Ng > A.maxn || Ni > A.maxn) {
             if (t == 0) atomicOr(A.status, CMC_ST_TOO_LARGE);
             continue;
@@ -1602,31 +1606,47 @@ static void lds_attr(const void* fn, size_t bytes, hipStream_t st) {
 
 template <typename R, int kT>
 static void launch_pass_t(const StepArgs& A, const TabView<R>& T, const Work& W, int cap, size_t dshm,
-                          unsigned grid, hipStream_t st) {
+                          unsigned grid, int filter, int fcap, hipStream_t st) {
     if (A.proc & (CMC_BREMS | CMC_TRIDENT)) {
         lds_attr((const void*)k_pass<R, kT, 0>, dshm, st);
-        hipLaunchKernelGGL((k_pass<R, kT, 0>), dim3(grid), dim3(256), dshm, st, A, T, W, cap);
+        hipLaunchKernelGGL((k_pass<R, kT, 0>), dim3(grid), dim3(256), dshm, st, A, T, W, cap, filter, fcap);
     }
     if (A.proc & CMC_BH) {
         lds_attr((const void*)k_pass<R, kT, 1>, dshm, st);
-        hipLaunchKernelGGL((k_pass<R, kT, 1>), dim3(grid), dim3(256), dshm, st, A, T, W, cap);
+        hipLaunchKernelGGL((k_pass<R, kT, 1>), dim3(grid), dim3(256), dshm, st, A, T, W, cap, filter, fcap);
     }
 }
 
-// the pass kernels with teams of `team` threads
-static cmc_status launch_passes(const StepArgs& A, const cmc_tables_s* t, const Work& W, bool fp64, int team,
-                                hipStream_t st) {
+// the pass kernels with teams of `team` threads over the cells of a size
+// class (filter 0: all)
+static void launch_team(const StepArgs& A, const cmc_tables_s* t, const Work& W, bool fp64, int team, int filter,
+                        int fcap, int64_t max_blocks, hipStream_t st) {
     const int cap = team_cap(team, A.maxn, fp64);
     const size_t per = (team_bytes(cap, fp64 ? 8 : 4) + 15) / 16 * 16;
     const size_t dshm = per * (size_t)(256 / team);
     const int64_t units = team == 64 ? (A.n_cells + 3) / 4 : A.n_cells;
-    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(units, 256 * 64));
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(units, max_blocks));
     if (fp64) {
-        if (team == 64) launch_pass_t<double, 64>(A, view64(t), W, cap, dshm, grid, st);
-        else launch_pass_t<double, 256>(A, view64(t), W, cap, dshm, grid, st);
+        if (team == 64) launch_pass_t<double, 64>(A, view64(t), W, cap, dshm, grid, filter, fcap, st);
+        else launch_pass_t<double, 256>(A, view64(t), W, cap, dshm, grid, filter, fcap, st);
     } else {
-        if (team == 64) launch_pass_t<float, 64>(A, view32(t), W, cap, dshm, grid, st);
-        else launch_pass_t<float, 256>(A, view32(t), W, cap, dshm, grid, st);
+        if (team == 64) launch_pass_t<float, 64>(A, view32(t), W, cap, dshm, grid, filter, fcap, st);
+        else launch_pass_t<float, 256>(A, view32(t), W, cap, dshm, grid, filter, fcap, st);
+    }
+}
+
+// Team shapes: 256 workgroups, 64 wavefronts, kHybrid wavefronts for the
+// cells up to the wavefront capacity and workgroups for the larger ones.
+constexpr int kHybrid = -1;
+
+static cmc_status launch_passes(const StepArgs& A, const cmc_tables_s* t, const Work& W, bool fp64, int shape,
+                                hipStream_t st) {
+    if (shape == kHybrid) {
+        const int small = team_cap(64, A.maxn, fp64);
+        launch_team(A, t, W, fp64, 64, 1, small, 256 * 64, st);
+        launch_team(A, t, W, fp64, 256, 2, small, 2048, st);
+    } else {
+        launch_team(A, t, W, fp64, shape, 0, 0, 256 * 64, st);
     }
     CMC_CHECK_LAUNCH("cmc_collide_step: k_pass");
     return CMC_OK;
@@ -1673,7 +1693,8 @@ static cmc_status tune_passes(const StepArgs& A, const cmc_tables_s* t, const Wo
     float best_ms = 0.0f;
     best = 256;
     cmc_status rc = CMC_OK;
-    for (int team : {256, 64}) {
+    const int other = A.maxn <= team_cap(64, A.maxn, fp64) ? 64 : kHybrid;
+    for (int team : {256, other}) {
         if ((rc = launch_passes(A, t, W, fp64, team, st)) != CMC_OK) break;   // warm-up
         (void)hipEventRecord(e0, st);
         for (int r = 0; r < 3 && rc == CMC_OK; ++r) rc = launch_passes(A, t, W, fp64, team, st);
@@ -1719,7 +1740,7 @@ extern "C" cmc_status cmc_collide_step(cmc_tables t, const cmc_cells* cells, cmc
     CMC_REQUIRE((P->processes & ~7u) == 0, CMC_EINVAL, "cmc_collide_step: unknown process bits");
     CMC_REQUIRE(P->precision == CMC_FP64 || P->precision == CMC_FP32, CMC_EINVAL,
                 "cmc_collide_step: unknown precision %d", P->precision);
-    CMC_REQUIRE(P->schedule >= 0 && P->schedule <= 3, CMC_EINVAL, "cmc_collide_step: unknown schedule");
+    CMC_REQUIRE(P->schedule >= 0 && P->schedule <= 4, CMC_EINVAL, "cmc_collide_step: unknown schedule");
     CMC_REQUIRE(P->max_per_cell >= 1 && P->max_per_cell <= CMC_MAX_PER_CELL, CMC_ERANGE,
                 "cmc_collide_step: max_per_cell = %d outside [1, %d]", P->max_per_cell, CMC_MAX_PER_CELL);
     CMC_REQUIRE(P->near_rel >= 0.0 && P->near_rel <= 1.0, CMC_EINVAL, "cmc_collide_step: near_rel outside [0, 1]");
@@ -1773,7 +1794,7 @@ extern "C" cmc_status cmc_collide_step(cmc_tables t, const cmc_cells* cells, cmc
                            0, st, A.Zs, A.ni, A.Te, A.n_cells, (double)t->Z, t->ax, W, A.ti, A.td, A.status,
                            P->step_counter, P->step, advance);
     };
-    int team = P->schedule == CMC_SCHED_WAVE ? 64 : 256;
+    int team = P->schedule == CMC_SCHED_WAVE ? 64 : (P->schedule == CMC_SCHED_HYBRID ? kHybrid : 256);
     bool tuned = P->schedule != CMC_SCHED_AUTO;
     TuneKey key{};
     if (!tuned) {

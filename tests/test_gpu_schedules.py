@@ -1,7 +1,8 @@
 """Schedules and graph replay of cmc_collide_step.
 
-- Workgroup and wavefront teams give bit-identical results: the densities
-  and n_ab are summed in one canonical order whatever the team shape.
+- Workgroup and wavefront teams, and the hybrid of both, give bit-identical
+  results: the densities and n_ab are summed in one canonical order
+  whatever the team shape.
 - The sequential schedule (one workgroup per cell, pairs in order) gives the
   same events, counts and slots; floating-point values agree to rounding
   (another kernel may contract a * b + c into a fused multiply-add
@@ -39,12 +40,12 @@ def _snap(g, st):
     return out
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_team_shapes_bit_identical(precision):
+@pytest.mark.parametrize("precision,other,hi", [(0, "WAVE", 480), (1, "WAVE", 480), (1, "HYBRID", 3000)])
+def test_team_shapes_bit_identical(precision, other, hi):
     import paper_1907_02814_amd as cmc
-    wl = W.cfg3(np.random.default_rng(21), n_cells=128, dt=2e-13, lo=1, hi=480)
+    wl = W.cfg3(np.random.default_rng(21), n_cells=128, dt=2e-13, lo=1, hi=hi)
     ga, sa = _state(wl, cmc.SCHED_GROUP, precision)
-    gb, sb = _state(wl, cmc.SCHED_WAVE, precision)
+    gb, sb = _state(wl, getattr(cmc, "SCHED_" + other), precision)
     for s in range(3):
         sa.step(s)
         sb.step(s)
