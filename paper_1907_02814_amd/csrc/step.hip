@@ -1203,24 +1203,48 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
             const int nc = min(W.ncand[c], kCandCap);
             const int64_t e0 = A.el.off[c], i0 = A.io.off[c];
             const int Ne = live(A.el, c), Ni = live(A.io, c);
-            // ---- settle the open pairs
+            const uint64_t raw = W.cand[c * kCandCap + lane];
+            // ---- the open pairs in (pass, pair index) order, one per lane
+            {
+                const bool has = lane < nc;
+                const unsigned long long hb = __ballot(has);
+                const uint32_t key = has ? ev_key(raw) : 0xFFFFFFFFu;
+                int rank = 0;
+                for (int l = 0; l < 64; ++l) {
+                    if (!((hb >> l) & 1ull)) continue;
+                    rank += __shfl(key, l, 64) < key;
+                }
+                if (has) rec[rank] = raw;
+                Team<64>::sync();
+            }
+            const bool cand = lane < nc;
+            const uint64_t mine = cand ? rec[lane] : 0ull;
+            const int pass = cand ? ev_pass(mine) : 2;
+            const int j = ev_j(mine), mi = ev_m(mine), ii = ev_i(mine);
+            const CellTab<double> ct64 = W.cs[c].d;
+            // ---- settle them; the particle and the FP64 lookup stay in the
+            // lane for the sampling
             uint32_t kind = 0;
-            uint64_t mine = 0;
             int near_br = 0, near_tr = 0, near_bh = 0;
             bool reused = false;
-            if (lane < nc) {
-                mine = W.cand[c * kCandCap + lane];
-                const int pass = ev_pass(mine), j = ev_j(mine), mi = ev_m(mine), ii = ev_i(mine);
+            double px = 0, py = 0, pz = 0, Wm = 0, Wi = 0, gd = 0, gm1d = 0, kd = 0;
+            BremsLook<double> BLd = {};
+            int ikd = 0; double wkd = 0.0;
+            if (cand) {
                 const uint32_t bits = ev_kind(mine);
                 const CellTab<R> ct = pick<R>(W.cs[c]);
                 const double coef = W.coef[c * 2 + pass];
-                const double Wi = A.io.w[i0 + ii];
+                Wi = A.io.w[i0 + ii];
                 if (pass == 0) {
                     const int64_t ie = e0 + mi;
-                    const Elec<R> e = electron_p<R>(A.el.px[ie], A.el.py[ie], A.el.pz[ie]);
-                    const double We = A.el.w[ie];
-                    const double Pej = Wi / (We > Wi ? We : Wi);
+                    px = A.el.px[ie]; py = A.el.py[ie]; pz = A.el.pz[ie]; Wm = A.el.w[ie];
+                    const Elec<R> e = electron_p<R>(px, py, pz);
+                    const double Pej = Wi / (Wm > Wi ? Wm : Wi);
                     if (bits & 1u) {
+                        const double p2d = px * px + py * py + pz * pz;
+                        gd = sqrt(1.0 + p2d); gm1d = p2d / (gd + 1.0);
+                        bool hi2;
+                        BLd = brems_lookup<double, false>(T64, ct64, gd, gm1d, hi2);
                         bool hi;
                         const R sig = brems_lookup<R, false>(T, ct, e.g, e.gm1, hi).sig;
                         const double x = coef * (double)sig * e.vrel * A.dt;
@@ -1237,12 +1261,16 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
                     }
                     reused = Ne < Ni && j + Ne < Ni;   // the electron pairs again later
                 } else {
-                    const R k = photon_k<R>(A.ph.px[g0 + mi], A.ph.py[g0 + mi], A.ph.pz[g0 + mi]);
+                    const int64_t ig = g0 + mi;
+                    px = A.ph.px[ig]; py = A.ph.py[ig]; pz = A.ph.pz[ig]; Wm = A.ph.w[ig];
+                    kd = sqrt(px * px + py * py + pz * pz);
+                    bool hi2;
+                    bh_lookup<double>(T64, ct64, kd, ikd, wkd, hi2);
+                    const R k = photon_k<R>(px, py, pz);
                     int ik; R wk; bool hi;
                     const R sig = bh_lookup<R>(T, ct, k, ik, wk, hi);
                     const double x = coef * (double)sig * phys::kC * A.dt;
-                    const double Wg = A.ph.w[g0 + mi];
-                    const double Pej = Wi / (Wg > Wi ? Wg : Wi);
+                    const double Pej = Wi / (Wm > Wi ? Wm : Wi);
                     if (settle(x, rng.draw((uint32_t)j, cell, kTagAccBh), rej, A.near_rel, Pej, near_bh))
                         kind = kEvBh;
                     reused = Ng0 < Ni && j + Ng0 < Ni;
@@ -1254,31 +1282,17 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
                 if (lane == 0) ctl[0] = 1;
                 break;
             }
-            // ---- events in (pass, pair index) order
-            const unsigned long long evb = __ballot(kind != 0);
-            const int n = __popcll(evb);
-            const uint32_t key = kind ? ev_key(mine) : 0xFFFFFFFFu;
-            int rank = 0;
-            for (int l = 0; l < 64; ++l) {
-                if (!((evb >> l) & 1ull)) continue;
-                rank += __shfl(key, l, 64) < key;
-            }
-            if (kind) rec[rank] = (mine & ~(0x7Full << 48)) | ((uint64_t)kind << 48);
-            Team<64>::sync();
-            const uint64_t r = lane < n ? rec[lane] : 0ull;
-            const bool live_ev = lane < n;
-            const int pass = live_ev ? ev_pass(r) : 2;
-            const uint32_t evk = live_ev ? ev_kind(r) : 0u;
-            const int j = ev_j(r), mi = ev_m(r), ii = ev_i(r);
-            const CellTab<double> ct64 = W.cs[c].d;
+            // ---- the events, lanes in (pass, pair index) order
+            const int n = __popcll(__ballot(kind != 0));
+            const uint32_t evk = kind;
             const int cap_ph = (int)(A.ph.off[c + 1] - g0);
             const int cap_ne = (int)(A.ne.off[c + 1] - A.ne.off[c]), cap_np = (int)(A.np.off[c + 1] - A.np.off[c]);
             const int cnt_ne0 = A.ne.count[c], cnt_np0 = A.np.count[c];
             Tally t = {};
             t.near_br = near_br; t.near_tr = near_tr; t.near_bh = near_bh;
             bool f_ph = false, f_tr = false, f_bh = false;
-            double kx = 0, ky = 0, kz = 0, pxm = 0, pym = 0, pzm = 0, pxp = 0, pyp = 0, pzp = 0, Wm = 0;
-            int64_t par = 0;
+            double kx = 0, ky = 0, kz = 0, pxm = 0, pym = 0, pzm = 0, pxp = 0, pyp = 0, pzp = 0;
+            const int64_t par = pass == 0 ? e0 + mi : g0 + mi;
             // with few events the wavefront inverts each CDF together (one round
             // of table reads per event), else every lane bisects its own; both
             // give the same abscissa
@@ -1288,36 +1302,16 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
                 return has ? cdf_invert<double>(row.T, row.kind, row.i, row.w, ct64, xi, ct) : 0.0;
             };
             // ---- first draw: Bremsstrahlung photon energy or Bethe-Heitler pair
-            double px = 0, py = 0, pz = 0, kd = 0, gd = 0, gm1d = 0;
-            int64_t ie = 0, ig = 0;
-            BremsLook<double> BLd = {};
             CdfRow<double> rowA = {};
             double xiA = 0.0;
             bool reqA = false;
-            if (pass == 0) {
-                ie = e0 + mi;
-                par = ie;
-                px = A.el.px[ie]; py = A.el.py[ie]; pz = A.el.pz[ie];
-                Wm = A.el.w[ie];
-                if (evk & kEvBr) {
-                    const U4 q = rng.draw((uint32_t)j, cell, kTagSmpBr);
-                    const double p2d = px * px + py * py + pz * pz;
-                    gd = sqrt(1.0 + p2d); gm1d = p2d / (gd + 1.0);
-                    bool hi2;
-                    BLd = brems_lookup<double, false>(T64, ct64, gd, gm1d, hi2);
-                    rowA = brems_row<double>(T64, BLd);
-                    xiA = u53(q.x, q.y);
-                    reqA = true;
-                }
-            } else if (pass == 1) {
-                ig = g0 + mi;
-                par = ig;
-                px = A.ph.px[ig]; py = A.ph.py[ig]; pz = A.ph.pz[ig];
-                Wm = A.ph.w[ig];
-                kd = sqrt(px * px + py * py + pz * pz);
+            if (pass == 0 && (evk & kEvBr)) {
+                const U4 q = rng.draw((uint32_t)j, cell, kTagSmpBr);
+                rowA = brems_row<double>(T64, BLd);
+                xiA = u53(q.x, q.y);
+                reqA = true;
+            } else if (pass == 1 && (evk & kEvBh)) {
                 const U4 q = rng.draw((uint32_t)j, cell, kTagSmpBh);
-                int ikd; double wkd; bool hi2;
-                bh_lookup<double>(T64, ct64, kd, ikd, wkd, hi2);
                 rowA = bh_row<double>(T64, ikd, wkd);
                 xiA = u53(q.x, q.y);
                 reqA = true;
@@ -1325,7 +1319,7 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
             double ctA = 0.0;
             const double tA = invert(reqA, rowA, xiA, ctA);
             bool tr = false;
-            if (pass == 0) {
+            if (pass == 0 && evk) {
                 if (evk & kEvBr) {
                     double k, g2, g2m1;
                     brems_energies(BLd.seg, gd, gm1d, ctA, k, g2, g2m1);
@@ -1343,7 +1337,6 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
                 tr = (evk & kEvTr) != 0;
                 if (evk & kEvTrPending) {
                     // Trident on the electron left by Bremsstrahlung (same pair)
-                    const double Wi = A.io.w[i0 + ii];
                     const double Pej = Wi / (Wm > Wi ? Wm : Wi);
                     const Elec<R> e = electron_p<R>(px, py, pz);
                     const R sig = (R)phys::trident_sigma(T.Z, (double)e.g);
@@ -1356,7 +1349,7 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
                         tr = U1 < P && U2 < Pej;
                     }
                 }
-            } else if (pass == 1) {
+            } else if (pass == 1 && evk) {
                 double gpl, gmi;
                 bh_energies(kd, tA, ctA, gpl, gmi);
                 const double pplus = sqrt((gpl - 1.0) * (gpl + 1.0)), pminus = sqrt((gmi - 1.0) * (gmi + 1.0));
@@ -1405,7 +1398,7 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
                 t.W_tr += Wm;
                 f_tr = true;
             }
-            if (pass == 0 && (f_ph || f_tr)) { A.el.px[ie] = px; A.el.py[ie] = py; A.el.pz[ie] = pz; }
+            if (pass == 0 && (f_ph || f_tr)) { A.el.px[par] = px; A.el.py[par] = py; A.el.pz[par] = pz; }
             // slots in (pass, pair) order: lanes are already in that order
             const unsigned long long b_ph = __ballot(f_ph), b_tr = __ballot(f_tr), b_bh = __ballot(f_bh);
             const unsigned long long below = (1ull << lane) - 1ull;
