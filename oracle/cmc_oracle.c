@@ -1035,6 +1035,20 @@ static void from_ion(const double u[3], double gi, double Ep, const double pp[3]
     for (int d = 0; d < 3; d++) p[d] = pp[d] + f * u[d];
 }
 
+/* The same two transforms for one 4-vector, exported for the pins:
+ * out = (E', p'x, p'y, p'z) in the ion rest frame, and back (momentum). */
+void or_to_ion(const double u[3], double E, const double p[3], double out[4])
+{
+    double gi = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    to_ion(u, gi, E, p, &out[0], out + 1);
+}
+
+void or_from_ion(const double u[3], double Ep, const double pp[3], double out[3])
+{
+    double gi = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    from_ion(u, gi, Ep, pp, out);
+}
+
 /* ------------------------------------------------------------------ */
 /* The Monte Carlo step, Sec. III.A, one cell, sequential in j.        */
 /* ------------------------------------------------------------------ */

@@ -90,6 +90,10 @@ double or_dsdgp_trident(double Z, double g1, double gpair);
 double or_split_shape(double gpair, double gplus);
 void   or_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 double or_u53(uint32_t a, uint32_t b);
+/* Sec. III.A boost to / from the rest frame of an ion of proper velocity
+ * u = gamma_i beta_i: out = (E', p') and p (momentum only) */
+void   or_to_ion(const double u[3], double E, const double p[3], double out[4]);
+void   or_from_ion(const double u[3], double Ep, const double pp[3], double out[3]);
 
 /* cross sections looked up from the tables for one cell state */
 int or_lookup(const or_tables* t, double Zs, double ni, double T, double gamma_or_k,

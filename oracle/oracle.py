@@ -72,6 +72,8 @@ def lib():
         L.or_split_shape.argtypes = [d, d]; L.or_split_shape.restype = d
         L.or_philox.argtypes = [_u32p, _u32p, _u32p]
         L.or_u53.argtypes = [u32, u32]; L.or_u53.restype = d
+        L.or_to_ion.argtypes = [_dp, d, _dp, _dp]
+        L.or_from_ion.argtypes = [_dp, d, _dp, _dp]
         L.or_lookup.argtypes = [vp, d, d, d, d, C.c_int, _dp]
         L.or_sample.argtypes = [vp, d, d, d, d, C.c_int, d, d, _dp]
         L.or_pair_cells.argtypes = [i64, _i64p, _i32p, _i64p, _i32p, _dp, _dp, u64, u64, u32,
@@ -168,6 +170,21 @@ def philox(ctr, key):
     o = np.zeros(4, dtype=np.uint32)
     lib().or_philox(_p(c, _u32p), _p(k, _u32p), _p(o, _u32p))
     return o
+
+
+def to_ion(u, E, p):
+    """(E', p') of the 4-vector (E, p) in the rest frame of an ion of
+    proper velocity u (Sec. III.A)."""
+    out = np.zeros(4)
+    lib().or_to_ion(_p(_f64(u)), float(E), _p(_f64(p)), _p(out))
+    return out[0], out[1:]
+
+
+def from_ion(u, Ep, pp):
+    """Lab momentum of the ion-frame 4-vector (E', p')."""
+    out = np.zeros(3)
+    lib().or_from_ion(_p(_f64(u)), float(Ep), _p(_f64(pp)), _p(out))
+    return out
 
 
 def u53(a, b):

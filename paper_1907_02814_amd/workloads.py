@@ -174,6 +174,17 @@ def assemble(name, Z, dt, processes, steps, Zstar, n_i, T_e,
                     _slab(pair_cap), _slab(pair_cap), seed)
 
 
+def moving_ions(wl: Workload, rng, umax) -> Workload:
+    """Gives the ions proper velocities u = gamma_i beta_i (stored in the
+    ions' px, py, pz): isotropic directions, |u| uniform on [0, umax]."""
+    n = len(wl.ions["w"])
+    d = isotropic(rng, n)
+    m = rng.uniform(0.0, umax, n)
+    wl.ions["px"], wl.ions["py"], wl.ions["pz"] = d[0] * m, d[1] * m, d[2] * m
+    wl.name += "-moving-ions"
+    return wl
+
+
 def _photon_energy(rng, n):
     """k = 1.022 MeV + Exp(mean 5 MeV), in m_e c^2."""
     return (1.022 + rng.exponential(5.0, n)) / MEC2_MEV
