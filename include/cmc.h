@@ -109,7 +109,9 @@ typedef struct {
 typedef struct {
     const int64_t* off;    /* device [n_cells+1], non-decreasing             */
     int32_t* count;        /* device [n_cells] live counts, or NULL (= full)  */
-    double *px, *py, *pz;  /* device momenta; ions: must be NULL (at rest)    */
+    double *px, *py, *pz;  /* device momenta, m_e c (photons: k n).  Ions:
+                              proper velocity u = gamma_i beta_i, all three
+                              set, or all NULL for ions at rest            */
     double* w;             /* device weights                                  */
     int64_t* parent;       /* device, products only (NULL = not recorded):
                               global index of the parent particle            */
@@ -149,7 +151,9 @@ enum { CMC_D_NAB_EI = 0,   /* n_ei = sum_j min(W_e, W_i), eq:proba3          */
        CMC_D_E_TR,         /* sum W (g+ + g-) of Trident pairs               */
        CMC_D_E_BH,         /* sum W (g+ + g-) of Bethe-Heitler pairs         */
        CMC_D_DE_EL,        /* sum W (gamma_after - gamma_before), electrons,
-                              taken as -k / -g_pair (exact for ions at rest) */
+                              from the ion-frame loss dE' = -k / -g_pair:
+                              gamma_i dE' + u.n' (|p'_f| - |p'|), which is
+                              dE' for ions at rest                          */
        CMC_D_DE_PH,        /* -sum W k of photons converted                  */
        CMC_D_W_BR, CMC_D_W_TR, CMC_D_W_BH,  /* created weight per process    */
        CMC_ND };
@@ -194,6 +198,10 @@ cmc_status cmc_pair_cells(int64_t n_cells, const int64_t* a_off, const int32_t* 
 /* gamma_b) dt) in FP64; the event happens iff U1 < P and               */
 /* U2 < W_ion/max(W_mobile, W_ion); the energy is sampled from the      */
 /* tabulated cumulative distribution; products move along the parent.   */
+/* Primed quantities are in the rest frame of the pair's ion, reached   */
+/* by the boost along the ion velocity (Sec. III.A; the photon's flux   */
+/* factor is k' c/(k gamma_i)); products are boosted back to the lab.   */
+/* With ions at rest (ion px = py = pz = NULL) the frames coincide.     */
 /* Updates in place: electron momenta; photons (Bremsstrahlung photons   */
 /* are appended to the photon species of the cell, photons converted by  */
 /* Bethe-Heitler are removed and the survivors kept in order, followed   */
@@ -207,8 +215,8 @@ cmc_status cmc_pair_cells(int64_t n_cells, const int64_t* a_off, const int32_t* 
 /* workspace: device scratch of cmc_step_workspace_bytes() bytes (may be */
 /* NULL when that is 0).                                                 */
 /* Errors: CMC_EINVAL (null or inconsistent pointers, dt <= 0, unknown  */
-/* processes/precision/schedule, near_rel outside [0, 1], ions with     */
-/* momenta), CMC_ERANGE                                                  */
+/* processes/precision/schedule, near_rel outside [0, 1], ion momenta  */
+/* neither all set nor all NULL), CMC_ERANGE                             */
 /* (max_per_cell outside [1, CMC_MAX_PER_CELL]), CMC_EDEVICE.            */
 /* ------------------------------------------------------------------ */
 cmc_status cmc_collide_step(cmc_tables t, const cmc_cells* cells,

@@ -193,7 +193,7 @@ def pair_cells(a_off, a_cnt, b_off, b_cnt, wa, wb, seed, step, pass_, pair_off, 
     return pa[:n_pairs], pb[:n_pairs], nab[:n_cells]
 
 
-def _species(d: Dict, moving_ok=True) -> _Species:
+def _species(d: Dict) -> _Species:
     s = _Species()
     s.off = _ptr(d["off"])
     s.count = _ptr(d.get("count"))

@@ -285,6 +285,114 @@ __device__ __forceinline__ R photon_k(double px, double py, double pz) {
     return Fast<R>::sqrt(qx * qx + qy * qy + qz * qz);
 }
 
+// ---- frame change of Sec. III.A: cross sections, sampling and products
+// live in the rest frame of the ion of the pair, reached by the boost along
+// the ion velocity.  u = gamma_i beta_i is the ion's proper velocity (the
+// ions' px, py, pz); for ions at rest every transform is skipped.  All of it
+// runs in FP64: the energy E' = gamma_i E - u.p cancels for particles that
+// move with the ion.
+struct Ion { double ux, uy, uz, gi; bool mov; };
+
+__device__ __forceinline__ Ion ion_at(const SpeciesDev& io, int64_t ii) {
+    Ion b{0.0, 0.0, 0.0, 1.0, false};
+    if (io.px) {
+        b.ux = io.px[ii]; b.uy = io.py[ii]; b.uz = io.pz[ii];
+        b.gi = sqrt(1.0 + b.ux * b.ux + b.uy * b.uy + b.uz * b.uz);
+        b.mov = true;
+    }
+    return b;
+}
+
+// (E, p) -> (E', p') in the ion frame: E' = gamma_i E - u.p,
+// p' = p + (u.p / (gamma_i + 1) - E) u
+__device__ __forceinline__ double to_ion(const Ion& b, double E, double px, double py, double pz,
+                                         double& qx, double& qy, double& qz) {
+    const double up = b.ux * px + b.uy * py + b.uz * pz;
+    const double s = up / (b.gi + 1.0) - E;
+    qx = px + s * b.ux; qy = py + s * b.uy; qz = pz + s * b.uz;
+    return b.gi * E - up;
+}
+
+// the inverse, momentum only: p = p' + (u.p' / (gamma_i + 1) + E') u
+__device__ __forceinline__ void from_ion(const Ion& b, double E, double qx, double qy, double qz,
+                                         double& px, double& py, double& pz) {
+    const double up = b.ux * qx + b.uy * qy + b.uz * qz;
+    const double s = up / (b.gi + 1.0) + E;
+    px = qx + s * b.ux; py = qy + s * b.uy; pz = qz + s * b.uz;
+}
+
+// a mobile particle seen from the ion, FP64: the energy gamma' (electron) or
+// k' (photon), gamma' - 1, |p'| and p'; E is the lab energy
+struct Frame { double g, gm1, pm, qx, qy, qz, E; };
+
+__device__ __forceinline__ Frame electron_frame(const Ion& b, double px, double py, double pz) {
+    Frame f;
+    const double p2 = px * px + py * py + pz * pz;
+    f.E = sqrt(1.0 + p2);
+    if (!b.mov) {
+        f.g = f.E; f.gm1 = p2 / (f.E + 1.0); f.pm = sqrt(p2);
+        f.qx = px; f.qy = py; f.qz = pz;
+        return f;
+    }
+    f.g = to_ion(b, f.E, px, py, pz, f.qx, f.qy, f.qz);
+    const double q2 = f.qx * f.qx + f.qy * f.qy + f.qz * f.qz;
+    f.gm1 = q2 / (sqrt(1.0 + q2) + 1.0);
+    f.pm = sqrt(q2);
+    return f;
+}
+
+__device__ __forceinline__ Frame photon_frame(const Ion& b, double px, double py, double pz) {
+    Frame f;
+    f.E = sqrt(px * px + py * py + pz * pz);
+    f.gm1 = 0.0;
+    if (!b.mov) {
+        f.g = f.pm = f.E; f.qx = px; f.qy = py; f.qz = pz;
+        return f;
+    }
+    f.g = f.pm = to_ion(b, f.E, px, py, pz, f.qx, f.qy, f.qz);
+    return f;
+}
+
+// eq:proba2: the ion-frame electron for the per-pair test, with the rate
+// factor gamma' v' / (gamma_e gamma_i) = c |p'| / (gamma_e gamma_i)
+template <typename R>
+__device__ __forceinline__ Elec<R> electron_moving(const Frame& f, const Ion& b) {
+    Elec<R> e;
+    e.g = (R)f.g;
+    e.gm1 = (R)f.gm1;
+    e.vrel = phys::kC * f.pm / (f.E * b.gi);
+    return e;
+}
+
+// the photon's flux factor k' c / (k gamma_i) (c for ions at rest)
+__device__ __forceinline__ double photon_flux(const Frame& f, const Ion& b) {
+    return b.mov ? phys::kC * f.pm / (f.E * b.gi) : phys::kC;
+}
+
+// lab momentum of a product with ion-frame energy E and momentum magnitude
+// mag along the parent's ion-frame direction
+__device__ __forceinline__ void lab_along(const Ion& b, const Frame& f, double E, double mag,
+                                          double& x, double& y, double& z) {
+    if (!b.mov) {
+        const double s = mag / f.pm;
+        x = f.qx * s; y = f.qy * s; z = f.qz * s;
+        return;
+    }
+    const double r = 1.0 / f.pm;
+    from_ion(b, E, (f.qx * r) * mag, (f.qy * r) * mag, (f.qz * r) * mag, x, y, z);
+}
+
+// lab energy change of an electron that loses dE in the ion frame (its
+// momentum there goes from pm to pf along the same direction):
+// gamma_i dE + u.n (pf - pm), with pf - pm = dE (gf + g) / (pf + pm) so that
+// nothing cancels when dE << gamma
+__device__ __forceinline__ double lab_energy_change(const Ion& b, const Frame& f, double dE, double gf, double pf) {
+    if (!b.mov) return dE;
+    const double r = 1.0 / f.pm;
+    const double un = b.ux * (f.qx * r) + b.uy * (f.qy * r) + b.uz * (f.qz * r);
+    return b.gi * dE + un * (dE * (gf + f.g) / (pf + f.pm));
+}
+
 // all tallies of the cell reduced in one pass: wave butterflies, then the
 // waves' partials summed in wave order by one thread (fixed shape)
 __device__ void write_tallies(const StepArgs& A, int64_t c, const Tally& t, double nab_ei,
@@ -418,12 +526,15 @@ __device__ __forceinline__ void collide_cell(const StepArgs& A, const TabView<R>
                     const double Wi = A.io.w[ii];
                     const double Pej = Wi / (We > Wi ? We : Wi);
                     double px = A.el.px[ie], py = A.el.py[ie], pz = A.el.pz[ie];
+                    const Ion b = ion_at(A.io, ii);
                     bool moved = false;
                     for (int proc = 0; proc < 2; ++proc) {
                         const uint32_t bit = proc == 0 ? CMC_BREMS : CMC_TRIDENT;
                         if (!(A.proc & bit)) continue;
                         if (proc == 0) t.pairs_br++; else t.pairs_tr++;
-                        const Elec<R> e = electron_p<R>(px, py, pz);
+                        // the electron (after this pair's Bremsstrahlung for Trident) seen from the ion
+                        const Frame f = electron_frame(b, px, py, pz);
+                        const Elec<R> e = b.mov ? electron_moving<R>(f, b) : electron_p<R>(px, py, pz);
                         const R g = e.g, gm1 = e.gm1;
                         R sig;
                         BremsLook<R> BL;
@@ -432,7 +543,7 @@ __device__ __forceinline__ void collide_cell(const StepArgs& A, const TabView<R>
                         else sig = (R)phys::trident_sigma(T.Z, (double)g);
                         high_any |= high;
                         if (!(sig > (R)0)) continue;
-                        // eq:proba3 with gamma' v' = c |p'| (eq:proba2), ions at rest
+                        // eq:proba3 with gamma' v' = c |p'| (eq:proba2)
                         const double x = coef * (double)sig * e.vrel * A.dt;
                         const double P = -expm1(-x);
                         const U4 r = rng.draw((uint32_t)j, cell, proc == 0 ? kTagAccBr : kTagAccTr);
@@ -443,40 +554,36 @@ __device__ __forceinline__ void collide_cell(const StepArgs& A, const TabView<R>
                         const double xi1 = u53(q.x, q.y), xi2 = u53(q.z, q.w);
                         if (proc == 0) t.ev_br++; else t.ev_tr++;
                         moved = true;
-                        // event kinematics in FP64 from the stored momentum
-                        const double p2d = px * px + py * py + pz * pz;
-                        const double gd = sqrt(1.0 + p2d), gm1d = p2d / (gd + 1.0), pmd = sqrt(p2d);
+                        // event kinematics in FP64, in the ion frame
                         if (proc == 0) {
                             bool hi2;
-                            const BremsLook<double> BLd = brems_lookup<double, false>(T64, ct64, gd, gm1d, hi2);
+                            const BremsLook<double> BLd = brems_lookup<double, false>(T64, ct64, f.g, f.gm1, hi2);
                             double k, g2, g2m1;
-                            brems_sample<double>(T64, ct64, BLd, gd, gm1d, xi1, k, g2, g2m1);
+                            brems_sample<double>(T64, ct64, BLd, f.g, f.gm1, xi1, k, g2, g2m1);
+                            // photon along the electron, which keeps its direction
                             const double pf = sqrt(g2m1 * (g2 + 1.0));
-                            const double f = pf / pmd, h = k / pmd;
-                            kx = px * h; ky = py * h; kz = pz * h;
-                            px *= f; py *= f; pz *= f;
-                            const double kl = sqrt(kx * kx + ky * ky + kz * kz);
-                            t.E_br += We * kl;
-                            // electron energy change = -k exactly (ions at rest); the
+                            lab_along(b, f, k, k, kx, ky, kz);
+                            lab_along(b, f, g2, pf, px, py, pz);
+                            t.E_br += We * sqrt(kx * kx + ky * ky + kz * kz);
+                            // energy change from -k (exact in the ion frame): the
                             // difference of two Lorentz factors would cancel for k << gamma
-                            t.dE_el += We * (-k);
+                            t.dE_el += We * lab_energy_change(b, f, -k, g2, pf);
                             t.W_br += We;
                             f_ph = true;
                         } else {
                             double gpair, gpl, gmi, gfm1;
-                            trident_sample<double>(T64, gd, gm1d, xi1, xi2, gpair, gpl, gmi, gfm1);
+                            trident_sample<double>(T64, f.g, f.gm1, xi1, xi2, gpair, gpl, gmi, gfm1);
                             const double gf = gfm1 + 1.0;
                             const double pf = sqrt(gfm1 * (gf + 1.0));
                             const double pplus = sqrt((gpl - 1.0) * (gpl + 1.0));
                             const double pminus = sqrt((gmi - 1.0) * (gmi + 1.0));
-                            const double f = pf / pmd, fp = pplus / pmd, fm = pminus / pmd;
-                            pxp = px * fp; pyp = py * fp; pzp = pz * fp;
-                            pxm = px * fm; pym = py * fm; pzm = pz * fm;
-                            px *= f; py *= f; pz *= f;
+                            lab_along(b, f, gpl, pplus, pxp, pyp, pzp);
+                            lab_along(b, f, gmi, pminus, pxm, pym, pzm);
+                            lab_along(b, f, gf, pf, px, py, pz);
                             const double gpl_l = sqrt(1.0 + pxp * pxp + pyp * pyp + pzp * pzp);
                             const double gmi_l = sqrt(1.0 + pxm * pxm + pym * pym + pzm * pzm);
                             t.E_tr += We * (gpl_l + gmi_l);
-                            t.dE_el += We * (-gpair);
+                            t.dE_el += We * lab_energy_change(b, f, -gpair, gf, pf);
                             t.W_tr += We;
                             f_tr = true;
                         }
@@ -549,35 +656,36 @@ __device__ __forceinline__ void collide_cell(const StepArgs& A, const TabView<R>
                         const double Wi = A.io.w[ii];
                         const double Pej = Wi / (Wg > Wi ? Wg : Wi);
                         const double qx = A.ph.px[ig], qy = A.ph.py[ig], qz = A.ph.pz[ig];
-                        const R k = photon_k<R>(qx, qy, qz);
+                        const Ion b = ion_at(A.io, ii);
+                        const Frame f = photon_frame(b, qx, qy, qz);
+                        const R k = b.mov ? (R)f.g : photon_k<R>(qx, qy, qz);
                         int ik; R wk; bool high;
                         const R sig = bh_lookup<R>(T, ct, k, ik, wk, high);
                         high_any |= high;
                         if (sig > (R)0) {
                             // eq:proba3 for photons: gamma -> k', v' -> c, flux k' c/(k gamma_i)
-                            const double x = coef * (double)sig * phys::kC * A.dt;
+                            const double x = coef * (double)sig * photon_flux(f, b) * A.dt;
                             const double P = -expm1(-x);
                             const U4 r = rng.draw((uint32_t)j, cell, kTagAccBh);
                             const double U1 = u53(r.x, r.y), U2 = u53(r.z, r.w);
                             if (fabs(U1 - P) <= A.near_rel * P) t.near_bh++;
                             if (U1 < P && U2 < Pej) {
                                 const U4 q = rng.draw((uint32_t)j, cell, kTagSmpBh);
-                                const double kd = sqrt(qx * qx + qy * qy + qz * qz);
                                 double gpl, gmi;
                                 int ikd; double wkd; bool hi2;
-                                bh_lookup<double>(T64, ct64, kd, ikd, wkd, hi2);
-                                bh_sample<double>(T64, ct64, kd, ikd, wkd, u53(q.x, q.y), gpl, gmi);
+                                bh_lookup<double>(T64, ct64, f.g, ikd, wkd, hi2);
+                                bh_sample<double>(T64, ct64, f.g, ikd, wkd, u53(q.x, q.y), gpl, gmi);
+                                // the pair travels along the photon (ion frame)
                                 const double pplus = sqrt((gpl - 1.0) * (gpl + 1.0));
                                 const double pminus = sqrt((gmi - 1.0) * (gmi + 1.0));
-                                const double fp = pplus / kd, fm = pminus / kd;
-                                pxp = qx * fp; pyp = qy * fp; pzp = qz * fp;
-                                pxm = qx * fm; pym = qy * fm; pzm = qz * fm;
+                                lab_along(b, f, gpl, pplus, pxp, pyp, pzp);
+                                lab_along(b, f, gmi, pminus, pxm, pym, pzm);
                                 const double gpl_l = sqrt(1.0 + pxp * pxp + pyp * pyp + pzp * pzp);
                                 const double gmi_l = sqrt(1.0 + pxm * pxm + pym * pym + pzm * pzm);
                                 atomicOr(&S.dead[lg >> 5], 1u << (lg & 31));
                                 t.ev_bh++;
                                 t.E_bh += Wg * (gpl_l + gmi_l);
-                                t.dE_ph += -Wg * kd;
+                                t.dE_ph += -Wg * f.E;
                                 t.W_bh += Wg;
                                 f_bh = true;
                             }
@@ -1013,9 +1121,10 @@ __device__ __forceinline__ void push_cand(const Work& W, int64_t c, uint64_t rec
 // |U1 - P| > near_rel P hold for the computed values, so the pair has no
 // event and no near-threshold count whatever P is.  The rare other pairs are
 // listed and settled with P by the event kernel.
+// kMov: the ions move, and each pair is tested in its ion's rest frame.
 // Workgroup teams run best at six wavefronts per SIMD (a few spilled
 // registers); wavefront teams are limited by LDS anyway.
-template <typename R, int kT, int kPass>
+template <typename R, int kT, int kPass, bool kMov>
 __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, TabView<R> T, Work W, int cap, int filter, int fcap) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red4[kWaves * 4];
@@ -1120,8 +1229,12 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
                     cx = S.px[m0 + mi]; cy = S.py[m0 + mi]; cz = S.pz[m0 + mi];
                 }
                 uint32_t bits = 0;
+                Ion b{0.0, 0.0, 0.0, 1.0, false};
+                if constexpr (kMov) b = ion_at(A.io, i0 + ion_of(j));
                 if (kPass == 0) {
-                    const Elec<R> e = electron_p<R>(cx, cy, cz);
+                    Elec<R> e;
+                    if constexpr (kMov) e = electron_moving<R>(electron_frame(b, cx, cy, cz), b);
+                    else e = electron_p<R>(cx, cy, cz);
                     if (A.proc & CMC_BREMS) {
                         bool hi;
                         const R sig = brems_sig_slice<R>(T, slice, e.g, e.gm1, hi);
@@ -1141,12 +1254,20 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
                         }
                     }
                 } else {
-                    const R k = photon_k<R>(cx, cy, cz);
+                    R k;
+                    double flux = phys::kC;
+                    if constexpr (kMov) {
+                        const Frame f = photon_frame(b, cx, cy, cz);
+                        k = (R)f.g;
+                        flux = photon_flux(f, b);
+                    } else {
+                        k = photon_k<R>(cx, cy, cz);
+                    }
                     bool hi;
                     const R sig = bh_sig_slice<R>(T, slice, k, hi);
                     high |= hi;
                     if (sig > (R)0) {
-                        const double x = coef * (double)sig * phys::kC * A.dt;
+                        const double x = coef * (double)sig * flux * A.dt;
                         const U4 r = rng.draw((uint32_t)j, cell, kTagAccBh);
                         if (u53(r.x, r.y) <= rej * x) bits = 1u;
                     }
@@ -1227,7 +1348,9 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
             uint32_t kind = 0;
             int near_br = 0, near_tr = 0, near_bh = 0;
             bool reused = false;
-            double px = 0, py = 0, pz = 0, Wm = 0, Wi = 0, gd = 0, gm1d = 0, kd = 0;
+            double px = 0, py = 0, pz = 0, Wm = 0, Wi = 0;
+            Ion b{0.0, 0.0, 0.0, 1.0, false};
+            Frame fr = {};   // the mobile particle seen from the ion
             BremsLook<double> BLd = {};
             int ikd = 0; double wkd = 0.0;
             if (cand) {
@@ -1235,16 +1358,16 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
                 const CellTab<R> ct = pick<R>(W.cs[c]);
                 const double coef = W.coef[c * 2 + pass];
                 Wi = A.io.w[i0 + ii];
+                b = ion_at(A.io, i0 + ii);
                 if (pass == 0) {
                     const int64_t ie = e0 + mi;
                     px = A.el.px[ie]; py = A.el.py[ie]; pz = A.el.pz[ie]; Wm = A.el.w[ie];
-                    const Elec<R> e = electron_p<R>(px, py, pz);
+                    fr = electron_frame(b, px, py, pz);
+                    const Elec<R> e = b.mov ? electron_moving<R>(fr, b) : electron_p<R>(px, py, pz);
                     const double Pej = Wi / (Wm > Wi ? Wm : Wi);
                     if (bits & 1u) {
-                        const double p2d = px * px + py * py + pz * pz;
-                        gd = sqrt(1.0 + p2d); gm1d = p2d / (gd + 1.0);
                         bool hi2;
-                        BLd = brems_lookup<double, false>(T64, ct64, gd, gm1d, hi2);
+                        BLd = brems_lookup<double, false>(T64, ct64, fr.g, fr.gm1, hi2);
                         bool hi;
                         const R sig = brems_lookup<R, false>(T, ct, e.g, e.gm1, hi).sig;
                         const double x = coef * (double)sig * e.vrel * A.dt;
@@ -1263,13 +1386,13 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
                 } else {
                     const int64_t ig = g0 + mi;
                     px = A.ph.px[ig]; py = A.ph.py[ig]; pz = A.ph.pz[ig]; Wm = A.ph.w[ig];
-                    kd = sqrt(px * px + py * py + pz * pz);
+                    fr = photon_frame(b, px, py, pz);
                     bool hi2;
-                    bh_lookup<double>(T64, ct64, kd, ikd, wkd, hi2);
-                    const R k = photon_k<R>(px, py, pz);
+                    bh_lookup<double>(T64, ct64, fr.g, ikd, wkd, hi2);
+                    const R k = b.mov ? (R)fr.g : photon_k<R>(px, py, pz);
                     int ik; R wk; bool hi;
                     const R sig = bh_lookup<R>(T, ct, k, ik, wk, hi);
-                    const double x = coef * (double)sig * phys::kC * A.dt;
+                    const double x = coef * (double)sig * photon_flux(fr, b) * A.dt;
                     const double Pej = Wi / (Wm > Wi ? Wm : Wi);
                     if (settle(x, rng.draw((uint32_t)j, cell, kTagAccBh), rej, A.near_rel, Pej, near_bh))
                         kind = kEvBh;
@@ -1322,15 +1445,13 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
             if (pass == 0 && evk) {
                 if (evk & kEvBr) {
                     double k, g2, g2m1;
-                    brems_energies(BLd.seg, gd, gm1d, ctA, k, g2, g2m1);
-                    const double pmd = sqrt(px * px + py * py + pz * pz);
+                    brems_energies(BLd.seg, fr.g, fr.gm1, ctA, k, g2, g2m1);
                     const double pf = sqrt(g2m1 * (g2 + 1.0));
-                    const double f = pf / pmd, h = k / pmd;
-                    kx = px * h; ky = py * h; kz = pz * h;
-                    px *= f; py *= f; pz *= f;
+                    lab_along(b, fr, k, k, kx, ky, kz);
+                    lab_along(b, fr, g2, pf, px, py, pz);
                     t.ev_br++;
                     t.E_br += Wm * sqrt(kx * kx + ky * ky + kz * kz);
-                    t.dE_el += Wm * (-k);
+                    t.dE_el += Wm * lab_energy_change(b, fr, -k, g2, pf);
                     t.W_br += Wm;
                     f_ph = true;
                 }
@@ -1338,7 +1459,8 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
                 if (evk & kEvTrPending) {
                     // Trident on the electron left by Bremsstrahlung (same pair)
                     const double Pej = Wi / (Wm > Wi ? Wm : Wi);
-                    const Elec<R> e = electron_p<R>(px, py, pz);
+                    const Elec<R> e = b.mov ? electron_moving<R>(electron_frame(b, px, py, pz), b)
+                                            : electron_p<R>(px, py, pz);
                     const R sig = (R)phys::trident_sigma(T.Z, (double)e.g);
                     if (sig > (R)0) {
                         const double x = W.coef[c * 2] * (double)sig * e.vrel * A.dt;
@@ -1351,26 +1473,24 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
                 }
             } else if (pass == 1 && evk) {
                 double gpl, gmi;
-                bh_energies(kd, tA, ctA, gpl, gmi);
+                bh_energies(fr.g, tA, ctA, gpl, gmi);
                 const double pplus = sqrt((gpl - 1.0) * (gpl + 1.0)), pminus = sqrt((gmi - 1.0) * (gmi + 1.0));
-                const double fp = pplus / kd, fm = pminus / kd;
-                pxp = px * fp; pyp = py * fp; pzp = pz * fp;
-                pxm = px * fm; pym = py * fm; pzm = pz * fm;
+                lab_along(b, fr, gpl, pplus, pxp, pyp, pzp);
+                lab_along(b, fr, gmi, pminus, pxm, pym, pzm);
                 t.ev_bh++;
                 t.E_bh += Wm * (sqrt(1.0 + pxp * pxp + pyp * pyp + pzp * pzp) + sqrt(1.0 + pxm * pxm + pym * pym + pzm * pzm));
-                t.dE_ph += -Wm * kd;
+                t.dE_ph += -Wm * fr.E;
                 t.W_bh += Wm;
                 f_bh = true;
             }
             // ---- Trident: pair energy, then the positron split
             U4 qt = {0u, 0u, 0u, 0u};
             CdfRow<double> rowB = {};
-            double gt = 0, gtm1 = 0, pmt = 0;
+            Frame ft = {};   // the electron, after this pair's Bremsstrahlung, seen from the ion
             if (tr) {
                 qt = rng.draw((uint32_t)j, cell, kTagSmpTr);
-                const double p2d = px * px + py * py + pz * pz;
-                gt = sqrt(1.0 + p2d); gtm1 = p2d / (gt + 1.0); pmt = sqrt(p2d);
-                rowB = trident_row<double>(T64, gt);
+                ft = electron_frame(b, px, py, pz);
+                rowB = trident_row<double>(T64, ft.g);
             }
             double ctB = 0.0;
             const double tB = invert(tr, rowB, u53(qt.x, qt.y), ctB);
@@ -1378,7 +1498,7 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
             bool reqC = false;
             CdfRow<double> rowC = {};
             if (tr) {
-                reqC = trident_pair(gtm1, tB, ctB, gpair, gpl, gmi, gfm1);
+                reqC = trident_pair(ft.gm1, tB, ctB, gpair, gpl, gmi, gfm1);
                 if (reqC) rowC = split_row<double>(T64, gpair);
             }
             double ctC = 0.0;
@@ -1388,13 +1508,12 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
                 const double gf = gfm1 + 1.0;
                 const double pf = sqrt(gfm1 * (gf + 1.0));
                 const double pplus = sqrt((gpl - 1.0) * (gpl + 1.0)), pminus = sqrt((gmi - 1.0) * (gmi + 1.0));
-                const double f = pf / pmt, fp = pplus / pmt, fm = pminus / pmt;
-                pxp = px * fp; pyp = py * fp; pzp = pz * fp;
-                pxm = px * fm; pym = py * fm; pzm = pz * fm;
-                px *= f; py *= f; pz *= f;
+                lab_along(b, ft, gpl, pplus, pxp, pyp, pzp);
+                lab_along(b, ft, gmi, pminus, pxm, pym, pzm);
+                lab_along(b, ft, gf, pf, px, py, pz);
                 t.ev_tr++;
                 t.E_tr += Wm * (sqrt(1.0 + pxp * pxp + pyp * pyp + pzp * pzp) + sqrt(1.0 + pxm * pxm + pym * pym + pzm * pzm));
-                t.dE_el += Wm * (-gpair);
+                t.dE_el += Wm * lab_energy_change(b, ft, -gpair, gf, pf);
                 t.W_tr += Wm;
                 f_tr = true;
             }
@@ -1597,16 +1716,26 @@ static void lds_attr(const void* fn, size_t bytes, hipStream_t st) {
         (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
+template <typename R, int kT, bool kMov>
+static void launch_pass_m(const StepArgs& A, const TabView<R>& T, const Work& W, int cap, size_t dshm,
+                          unsigned grid, int filter, int fcap, hipStream_t st) {
+    if (A.proc & (CMC_BREMS | CMC_TRIDENT)) {
+        lds_attr((const void*)k_pass<R, kT, 0, kMov>, dshm, st);
+        hipLaunchKernelGGL((k_pass<R, kT, 0, kMov>), dim3(grid), dim3(256), dshm, st, A, T, W, cap, filter, fcap);
+    }
+    if (A.proc & CMC_BH) {
+        lds_attr((const void*)k_pass<R, kT, 1, kMov>, dshm, st);
+        hipLaunchKernelGGL((k_pass<R, kT, 1, kMov>), dim3(grid), dim3(256), dshm, st, A, T, W, cap, filter, fcap);
+    }
+}
+
 template <typename R, int kT>
 static void launch_pass_t(const StepArgs& A, const TabView<R>& T, const Work& W, int cap, size_t dshm,
                           unsigned grid, int filter, int fcap, hipStream_t st) {
-    if (A.proc & (CMC_BREMS | CMC_TRIDENT)) {
-        lds_attr((const void*)k_pass<R, kT, 0>, dshm, st);
-        hipLaunchKernelGGL((k_pass<R, kT, 0>), dim3(grid), dim3(256), dshm, st, A, T, W, cap, filter, fcap);
-    }
-    if (A.proc & CMC_BH) {
-        lds_attr((const void*)k_pass<R, kT, 1>, dshm, st);
-        hipLaunchKernelGGL((k_pass<R, kT, 1>), dim3(grid), dim3(256), dshm, st, A, T, W, cap, filter, fcap);
+    if (A.io.px) {
+        launch_pass_m<R, kT, true>(A, T, W, cap, dshm, grid, filter, fcap, st);
+    } else {
+        launch_pass_m<R, kT, false>(A, T, W, cap, dshm, grid, filter, fcap, st);
     }
 }
 
@@ -1653,9 +1782,10 @@ static cmc_status launch_passes(const StepArgs& A, const cmc_tables_s* t, const 
 struct TuneKey {
     int dev;
     int64_t n_cells;
-    int maxn, proc, precision;
+    int maxn, proc, precision, moving;
     bool operator<(const TuneKey& o) const {
-        return std::tie(dev, n_cells, maxn, proc, precision) < std::tie(o.dev, o.n_cells, o.maxn, o.proc, o.precision);
+        return std::tie(dev, n_cells, maxn, proc, precision, moving) <
+               std::tie(o.dev, o.n_cells, o.maxn, o.proc, o.precision, o.moving);
     }
 };
 static std::mutex g_tune_mu;
@@ -1742,8 +1872,8 @@ extern "C" cmc_status cmc_collide_step(cmc_tables t, const cmc_cells* cells, cmc
     if ((s = set_species(A.el, electrons, "electrons", false, true)) != CMC_OK) return s;
     if ((s = set_species(A.ph, photons, "photons", true, true)) != CMC_OK) return s;
     if ((s = set_species(A.io, ions, "ions", false, false)) != CMC_OK) return s;
-    CMC_REQUIRE(!ions->px && !ions->py && !ions->pz, CMC_EINVAL,
-                "cmc_collide_step: moving ions are not supported (ions at rest: px = py = pz = NULL)");
+    CMC_REQUIRE((!ions->px && !ions->py && !ions->pz) || (ions->px && ions->py && ions->pz), CMC_EINVAL,
+                "cmc_collide_step: ions: px, py, pz must be all set (moving) or all NULL (at rest)");
     if ((s = set_species(A.ne, new_el, "new_el", true, true)) != CMC_OK) return s;
     if ((s = set_species(A.np, new_po, "new_po", true, true)) != CMC_OK) return s;
     A.Zs = cells->Zstar; A.ni = cells->n_i; A.Te = cells->T_e;
@@ -1793,7 +1923,7 @@ extern "C" cmc_status cmc_collide_step(cmc_tables t, const cmc_cells* cells, cmc
     if (!tuned) {
         int dev = 0;
         (void)hipGetDevice(&dev);
-        key = TuneKey{dev, A.n_cells, A.maxn, (int)A.proc, P->precision};
+        key = TuneKey{dev, A.n_cells, A.maxn, (int)A.proc, P->precision, A.io.px ? 1 : 0};
         tuned = tune_lookup(key, team);
     }
     // the counter advances once, in the last cell-state launch of the step

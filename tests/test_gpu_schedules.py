@@ -40,10 +40,13 @@ def _snap(g, st):
     return out
 
 
-@pytest.mark.parametrize("precision,other,hi", [(0, "WAVE", 480), (1, "WAVE", 480), (1, "HYBRID", 3000)])
-def test_team_shapes_bit_identical(precision, other, hi):
+@pytest.mark.parametrize("precision,other,hi,moving", [(0, "WAVE", 480, False), (1, "WAVE", 480, False),
+                                                       (1, "HYBRID", 3000, False), (0, "HYBRID", 3000, True)])
+def test_team_shapes_bit_identical(precision, other, hi, moving):
     import paper_1907_02814_amd as cmc
     wl = W.cfg3(np.random.default_rng(21), n_cells=128, dt=2e-13, lo=1, hi=hi)
+    if moving:
+        W.moving_ions(wl, np.random.default_rng(23), 0.5)
     ga, sa = _state(wl, cmc.SCHED_GROUP, precision)
     gb, sb = _state(wl, getattr(cmc, "SCHED_" + other), precision)
     for s in range(3):
@@ -55,10 +58,12 @@ def test_team_shapes_bit_identical(precision, other, hi):
     assert A["ti"][:, 3:6].sum() > 50
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_sequential_schedule_agrees(precision):
+@pytest.mark.parametrize("precision,moving", [(0, False), (1, False), (1, True)])
+def test_sequential_schedule_agrees(precision, moving):
     import paper_1907_02814_amd as cmc
     wl = W.cfg3(np.random.default_rng(22), n_cells=128, dt=2e-13, lo=1, hi=1500)
+    if moving:
+        W.moving_ions(wl, np.random.default_rng(24), 0.5)
     ga, sa = _state(wl, cmc.SCHED_AUTO, precision)
     gb, sb = _state(wl, cmc.SCHED_CELL, precision)
     for s in range(3):

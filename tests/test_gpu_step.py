@@ -50,6 +50,23 @@ def test_all_processes_uneven_cells(precision):
     assert I[3] > 100 and I[5] > 10
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_moving_ions_all_processes(precision):
+    # Sec. III.A frame change: every pair is tested, sampled and given its
+    # products in its ion's rest frame (ion proper velocities up to 0.5)
+    wl = W.cfg3(np.random.default_rng(11), n_cells=96, dt=2e-13, lo=1, hi=2000)
+    W.moving_ions(wl, np.random.default_rng(12), 0.5)
+    P = _run(wl, 2, precision=precision)
+    I = P.state.ti.cpu().numpy().sum(0)
+    assert I[3] > 100 and I[4] > 0 and I[5] > 10
+
+
+def test_moving_ions_bremsstrahlung_fp64():
+    wl = W.moving_ions(W.cfg1(dt=1e-12), np.random.default_rng(13), 0.8)
+    P = _run(wl, 2)
+    assert P.ref.photons["count"].sum() > 1000
+
+
 def test_foil_chain_cells():
     wl = W.cfg5(np.random.default_rng(2), n_cells=6, per_cell=4096, dt=5e-14)
     P = _run(wl, 3)
