@@ -1168,6 +1168,19 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
         const double* wion = A.io.w + i0;
         const bool mobA = Nm >= Ni;
         const int N = mobA ? Nm : Ni;
+        // the weights of the cell are checked (non-negative, finite) as
+        // they are summed into the densities
+        int bad = 0;
+        const auto chk = [&bad](double v) { bad |= !(v >= 0.0) || !isfinite(v); return v; };
+        double v4[4];   // n_mobile, n_ab, n_ion, n_other
+        // When the cell's ions are at rest and share one weight, no decision
+        // and no product depends on which ion a pair gets (P_ej and n_ab see
+        // only that weight): the ion order is then not formed, and the open
+        // pairs name ion 0.
+        const double wi0 = Ni > 0 ? wion[0] : 0.0;
+        bool same = true;
+        v4[2] = canon_part<kT>(Ni, [&](int q) { const double w = wion[q]; same &= w == wi0; return chk(w); });
+        const bool ion_order = active && (kMov || team_any<kT>(!same, redi));
         // when every mobile particle pairs once the pair loop walks them in
         // storage order: its first momenta are loaded before the sort
         double qx = 0.0, qy = 0.0, qz = 0.0;
@@ -1181,29 +1194,27 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
                 for (int i = t; i < kSliceBH; i += kT) slice[i] = slice_node_bh<R>(T, ct, i);
             }
             rank_order<kT>(Nm, cell, kPass == 0 ? kTagKeyE : kTagKeyG, rng, M.keys, M.tmp, M.hist, M.ordM, mobA, redu);
-            rank_order<kT>(Ni, cell, kPass == 0 ? kTagKeyIE : kTagKeyIG, rng, M.keys, M.tmp, M.hist, M.ordI, false, redu);
+            if (ion_order)
+                rank_order<kT>(Ni, cell, kPass == 0 ? kTagKeyIE : kTagKeyIG, rng, M.keys, M.tmp, M.hist, M.ordI, false, redu);
         }
         const float rNm = 1.0f / (float)Nm, rNi = 1.0f / (float)Ni;
         // the smaller species is cycled (j mod N_B); the other one is not
-        const auto ion_of = [&](int j) { return (int)M.ordI[Ni == N ? j : mod_small(j, Ni, rNi)]; };
+        const auto ion_of = [&](int j) { return ion_order ? (int)M.ordI[Ni == N ? j : mod_small(j, Ni, rNi)] : 0; };
+        const auto w_ion = [&](int j) { return ion_order ? wion[ion_of(j)] : wi0; };
         const auto mob_of = [&](int j) { return (int)M.ordM[Nm == N ? j : mod_small(j, Nm, rNm)]; };
-        // the weights, read once: the densities n = sum W of the three
-        // species, n_ab = sum_j min(W_a, W_b) and the weight check (when
-        // every mobile particle pairs once, its density and n_ab share the walk)
-        int bad = 0;
-        const auto chk = [&bad](double v) { bad |= !(v >= 0.0) || !isfinite(v); return v; };
-        double v4[4];   // n_mobile, n_ab, n_ion, n_other
-        v4[2] = canon_part<kT>(Ni, [&](int q) { return chk(wion[q]); });
+        // the other weights, read once: the densities n = sum W, n_ab =
+        // sum_j min(W_a, W_b) and the weight check (when every mobile
+        // particle pairs once, its density and n_ab share the walk)
         if (active && mobA) {
             canon_part2<kT>(N, [&](int q, double& a, double& b) {
-                const double u = chk(wm[q]), v = wion[ion_of((int)M.ordM[q])];
+                const double u = chk(wm[q]), v = w_ion((int)M.ordM[q]);
                 a += u;
                 b += u < v ? u : v;
             }, v4[0], v4[1]);
         } else {
             v4[0] = canon_part<kT>(Nm, [&](int q) { return chk(wm[q]); });
             v4[1] = !active ? 0.0 : canon_part<kT>(N, [&](int j) {
-                const double u = wm[mob_of(j)], v = wion[ion_of(j)];
+                const double u = wm[mob_of(j)], v = w_ion(j);
                 return u < v ? u : v;
             });
         }

@@ -41,11 +41,15 @@ def _snap(g, st):
 
 
 @pytest.mark.parametrize("precision,other,hi,moving", [(0, "WAVE", 480, False), (1, "WAVE", 480, False),
-                                                       (1, "HYBRID", 3000, False), (0, "HYBRID", 3000, True)])
+                                                       (1, "HYBRID", 3000, False), (0, "HYBRID", 3000, True),
+                                                       (1, "WAVE", 480, "weights")])
 def test_team_shapes_bit_identical(precision, other, hi, moving):
     import paper_1907_02814_amd as cmc
     wl = W.cfg3(np.random.default_rng(21), n_cells=128, dt=2e-13, lo=1, hi=hi)
-    if moving:
+    if moving == "weights":       # ions of unequal weight in every other cell
+        odd = np.repeat(np.arange(wl.n_cells) % 2 == 1, np.diff(wl.ions["off"]))
+        wl.ions["w"][odd] *= np.random.default_rng(25).lognormal(0.0, 1.0, int(odd.sum()))
+    elif moving:
         W.moving_ions(wl, np.random.default_rng(23), 0.5)
     ga, sa = _state(wl, cmc.SCHED_GROUP, precision)
     gb, sb = _state(wl, getattr(cmc, "SCHED_" + other), precision)

@@ -67,6 +67,23 @@ def test_moving_ions_bremsstrahlung_fp64():
     assert P.ref.photons["count"].sum() > 1000
 
 
+def _unequal_ion_weights(wl, rng):
+    """Every other cell gets ions of unequal weight (log-normal factors):
+    there the ion order enters n_ab and W_i/max(W, W_i)."""
+    odd = np.repeat(np.arange(wl.n_cells) % 2 == 1, np.diff(wl.ions["off"]))
+    wl.ions["w"][odd] *= rng.lognormal(0.0, 1.0, int(odd.sum()))
+    return wl
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_unequal_ion_weights(precision):
+    wl = _unequal_ion_weights(W.cfg3(np.random.default_rng(31), n_cells=96, dt=2e-13, lo=1, hi=2000),
+                              np.random.default_rng(32))
+    P = _run(wl, 2, precision=precision)
+    I = P.state.ti.cpu().numpy().sum(0)
+    assert I[3] > 100 and I[5] > 10
+
+
 def test_foil_chain_cells():
     wl = W.cfg5(np.random.default_rng(2), n_cells=6, per_cell=4096, dt=5e-14)
     P = _run(wl, 3)
