@@ -944,7 +944,10 @@ enum { TAG_KEY_E = 0x01, TAG_KEY_IE = 0x02, TAG_KEY_G = 0x03, TAG_KEY_IG = 0x04,
 /* per particle (ties by index); the larger species A is walked once   */
 /* in that order and the smaller one B cyclically, pair j =            */
 /* (A[pi_A(j)], B[pi_B(j mod N_B)]); a tie N_a = N_b makes the mobile  */
-/* species A.                                                          */
+/* species A.  The random numbers of pair j are keyed by the index of  */
+/* its mobile particle when every mobile particle pairs once (the      */
+/* mobile species is A), by j otherwise: either way every pair of a    */
+/* pass has its own counter.                                           */
 /* ------------------------------------------------------------------ */
 typedef struct { uint32_t key; int32_t idx; } keyidx;
 
@@ -1126,6 +1129,9 @@ static int32_t cell_step(const stepctx* X, const or_cells* cells, int64_t c, int
         if (!(nab > 0.0)) N = 0;
         for (int64_t j = 0; j < N; j++) {
             int64_t ie = e0 + pa[j], ii = i0 + pb[j];
+            /* the pair's random numbers: keyed by its electron when every
+             * electron pairs once (N_e >= N_i), else by the pair index */
+            uint32_t dkey = (uint32_t)(Ne >= Ni ? pa[j] : j);
             double We = el->w[ie], Wi = io->w[ii];
             double Pej = Wi / (We > Wi ? We : Wi);
             double u[3] = {0, 0, 0}, gi = 1.0;
@@ -1160,11 +1166,11 @@ static int32_t cell_step(const stepctx* X, const or_cells* cells, int64_t c, int
                 double x = coef * sig * (CLIGHT * pm / (ge * gi)) * X->dt;
                 double P = -expm1(-x);
                 uint32_t r[4];
-                draw(X->seed, X->step, cell, (uint32_t)j, proc == 0 ? TAG_ACC_BR : TAG_ACC_TR, r);
+                draw(X->seed, X->step, cell, dkey, proc == 0 ? TAG_ACC_BR : TAG_ACC_TR, r);
                 double U1 = or_u53(r[0], r[1]), U2 = or_u53(r[2], r[3]);
                 if (fabs(U1 - P) <= X->near_rel * P) ti[proc == 0 ? OR_I_NEAR_BR : OR_I_NEAR_TR]++;
                 if (!(U1 < P && U2 < Pej)) continue;
-                draw(X->seed, X->step, cell, (uint32_t)j, proc == 0 ? TAG_SMP_BR : TAG_SMP_TR, r);
+                draw(X->seed, X->step, cell, dkey, proc == 0 ? TAG_SMP_BR : TAG_SMP_TR, r);
                 double xi1 = or_u53(r[0], r[1]), xi2 = or_u53(r[2], r[3]);
                 double sc = 1.0 / pm;
                 double nh[3] = { pp[0] * sc, pp[1] * sc, pp[2] * sc };
@@ -1241,6 +1247,8 @@ static int32_t cell_step(const stepctx* X, const or_cells* cells, int64_t c, int
         for (int64_t j = 0; j < N; j++) {
             if (dead[pa[j]]) continue;
             int64_t ig = g0 + pa[j], ii = i0 + pb[j];
+            /* keyed by the photon when every photon pairs once, else by j */
+            uint32_t dkey = (uint32_t)(Ng >= Ni ? pa[j] : j);
             ti[OR_I_PAIRS_BH]++;
             double Wg = ph->w[ig], Wi = io->w[ii];
             double Pej = Wi / (Wg > Wi ? Wg : Wi);
@@ -1260,11 +1268,11 @@ static int32_t cell_step(const stepctx* X, const or_cells* cells, int64_t c, int
             double x = coef * sig * (CLIGHT * kp / (k * gi)) * X->dt;
             double P = -expm1(-x);
             uint32_t r[4];
-            draw(X->seed, X->step, cell, (uint32_t)j, TAG_ACC_BH, r);
+            draw(X->seed, X->step, cell, dkey, TAG_ACC_BH, r);
             double U1 = or_u53(r[0], r[1]), U2 = or_u53(r[2], r[3]);
             if (fabs(U1 - P) <= X->near_rel * P) ti[OR_I_NEAR_BH]++;
             if (!(U1 < P && U2 < Pej)) continue;
-            draw(X->seed, X->step, cell, (uint32_t)j, TAG_SMP_BH, r);
+            draw(X->seed, X->step, cell, dkey, TAG_SMP_BH, r);
             double xi = or_u53(r[0], r[1]);
             double gpl, gmi;
             bh_sample(tb, &s, kp, ik, wk, xi, &gpl, &gmi);

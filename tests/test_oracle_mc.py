@@ -233,6 +233,45 @@ def test_bad_cells_and_weights_flagged():
     assert np.array_equal(wl.electrons["px"][4:8], before[4:8])
 
 
+@pytest.mark.parametrize("ne,ni", [(6, 3), (3, 6)])
+def test_pair_draws_are_keyed_by_the_mobile_particle_or_the_pair(ne, ni):
+    # x >> 40 makes P = 1: the event is then decided by U2 < W_i/max(W_e, W_i)
+    # = 1/2 alone.  U2 comes from the pair's acceptance draw, whose counter is
+    # (electron index when every electron pairs once, else pair index j,
+    # cell, step, tag 0x11).
+    tab = O.tables(29)
+    n_cells, seed, step = 60, 3, 5
+    wl = _tiny(n_cells, ne, ni, Wratio=0.5, gamma=1 + 200.0 / MEC2_MEV)
+    p0 = np.hypot(np.hypot(wl.electrons["px"], wl.electrons["py"]), wl.electrons["pz"]).reshape(n_cells, ne)
+    ti, td, st = _run(wl, tab, 1e-6, O.BREMS, seed=seed, step=step)
+    p1 = np.hypot(np.hypot(wl.electrons["px"], wl.electrons["py"]), wl.electrons["pz"]).reshape(n_cells, ne)
+    ev = ti[:, O.I_NAMES.index("ev_br")]
+    key = np.array([seed, 0], dtype=np.uint32)
+
+    def hit(x, c):
+        w = O.philox([x, c, step, 0x11 << 24], key)
+        return O.u53(int(w[2]), int(w[3])) < 0.5
+    N = max(ne, ni)
+    pa, _, _ = O.pair_cells(wl.electrons["off"], None, wl.ions["off"], None, wl.electrons["w"],
+                            wl.ions["w"], seed, step, 1, np.arange(n_cells + 1) * N)
+    pa = pa.reshape(n_cells, N)
+    if ne >= ni:
+        # each electron pairs once: it emits iff its own counter says so
+        emitted = p1 < p0
+        own = np.array([[hit(m, c) for m in range(ne)] for c in range(n_cells)])
+        assert np.array_equal(emitted, own)
+        # keying by the pair index would pick other electrons
+        by_j = np.zeros_like(own)
+        for c in range(n_cells):
+            for jj in range(N):
+                by_j[c, pa[c, jj]] = hit(jj, c)
+        assert not np.array_equal(by_j, own)
+    else:
+        # electrons are reused: pair j is decided by counter j
+        assert np.array_equal(ev, [sum(hit(jj, c) for jj in range(N)) for c in range(n_cells)])
+    assert ev.sum() > 0
+
+
 def test_step_is_deterministic_and_resumable():
     tab = O.tables(29)
     a = _tiny(30, 12, 9, seed=4)
