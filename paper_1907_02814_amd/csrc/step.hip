@@ -520,8 +520,11 @@ __device__ __forceinline__ void collide_cell(const StepArgs& A, const TabView<R>
                 double kx = 0, ky = 0, kz = 0, pxm = 0, pym = 0, pzm = 0, pxp = 0, pyp = 0, pzp = 0, We = 0;
                 int64_t ie = 0;
                 if (act) {
-                    ie = e0 + S.pm[j % Ne];
+                    const int me = S.pm[j % Ne];
+                    ie = e0 + me;
                     const int64_t ii = i0 + S.pi[j % Ni];
+                    // the pair's draws: keyed by its electron when every electron pairs once
+                    const uint32_t dk = (uint32_t)(Ne >= Ni ? me : j);
                     We = A.el.w[ie];
                     const double Wi = A.io.w[ii];
                     const double Pej = Wi / (We > Wi ? We : Wi);
@@ -546,11 +549,11 @@ __device__ __forceinline__ void collide_cell(const StepArgs& A, const TabView<R>
                         // eq:proba3 with gamma' v' = c |p'| (eq:proba2)
                         const double x = coef * (double)sig * e.vrel * A.dt;
                         const double P = -expm1(-x);
-                        const U4 r = rng.draw((uint32_t)j, cell, proc == 0 ? kTagAccBr : kTagAccTr);
+                        const U4 r = rng.draw(dk, cell, proc == 0 ? kTagAccBr : kTagAccTr);
                         const double U1 = u53(r.x, r.y), U2 = u53(r.z, r.w);
                         if (fabs(U1 - P) <= A.near_rel * P) { if (proc == 0) t.near_br++; else t.near_tr++; }
                         if (!(U1 < P && U2 < Pej)) continue;
-                        const U4 q = rng.draw((uint32_t)j, cell, proc == 0 ? kTagSmpBr : kTagSmpTr);
+                        const U4 q = rng.draw(dk, cell, proc == 0 ? kTagSmpBr : kTagSmpTr);
                         const double xi1 = u53(q.x, q.y), xi2 = u53(q.z, q.w);
                         if (proc == 0) t.ev_br++; else t.ev_tr++;
                         moved = true;
@@ -651,6 +654,7 @@ __device__ __forceinline__ void collide_cell(const StepArgs& A, const TabView<R>
                     if (!dead) {
                         ig = g0 + lg;
                         const int64_t ii = i0 + S.pi[j % Ni];
+                        const uint32_t dk = (uint32_t)(Ng0 >= Ni ? lg : j);   // keyed by the photon if it pairs once
                         t.pairs_bh++;
                         Wg = A.ph.w[ig];
                         const double Wi = A.io.w[ii];
@@ -666,11 +670,11 @@ __device__ __forceinline__ void collide_cell(const StepArgs& A, const TabView<R>
                             // eq:proba3 for photons: gamma -> k', v' -> c, flux k' c/(k gamma_i)
                             const double x = coef * (double)sig * photon_flux(f, b) * A.dt;
                             const double P = -expm1(-x);
-                            const U4 r = rng.draw((uint32_t)j, cell, kTagAccBh);
+                            const U4 r = rng.draw(dk, cell, kTagAccBh);
                             const double U1 = u53(r.x, r.y), U2 = u53(r.z, r.w);
                             if (fabs(U1 - P) <= A.near_rel * P) t.near_bh++;
                             if (U1 < P && U2 < Pej) {
-                                const U4 q = rng.draw((uint32_t)j, cell, kTagSmpBh);
+                                const U4 q = rng.draw(dk, cell, kTagSmpBh);
                                 double gpl, gmi;
                                 int ikd; double wkd; bool hi2;
                                 bh_lookup<double>(T64, ct64, f.g, ikd, wkd, hi2);
@@ -1047,6 +1051,46 @@ __device__ void rank_order(int n, uint32_t cell, uint32_t tag, const Rng& rng, u
     Team<kT>::sync();
 }
 
+// Pair indices of the open pairs of a pass that formed no order: the rank
+// of each one's particle by (key, index) among the n particles of its
+// species, counted against every key of the species (drawn again, as
+// rank_order draws them).  open[k] = particle | kind << 16; keys[k] gets
+// the particle's key, pj[k] its rank.
+template <int kT>
+__device__ void rank_open(int n, uint32_t cell, uint32_t tag, const Rng& rng, const uint32_t* open,
+                          uint32_t* keys, uint32_t* pj, int n_open) {
+    const int t = Team<kT>::tid();
+    if (t < n_open) {
+        const uint32_t m = open[t] & 0xFFFFu;
+        const U4 r = rng.draw(m >> 2, cell, tag);
+        const uint32_t w4[4] = {r.x, r.y, r.z, r.w};
+        keys[t] = w4[m & 3u];
+        pj[t] = 0u;
+    }
+    Team<kT>::sync();
+    const int nq = (n + 3) >> 2;
+    for (int base = 0; base < nq; base += kT) {
+        const int q = base + t;
+        uint32_t w4[4] = {0u, 0u, 0u, 0u};
+        if (q < nq) {
+            const U4 r = rng.draw((uint32_t)q, cell, tag);
+            w4[0] = r.x; w4[1] = r.y; w4[2] = r.z; w4[3] = r.w;
+        }
+        for (int k = 0; k < n_open; ++k) {
+            const uint32_t kk = keys[k], mk = open[k] & 0xFFFFu;
+            int below = 0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t i = 4u * (uint32_t)q + (uint32_t)u;
+                const bool lt = q < nq && (int)i < n && (w4[u] < kk || (w4[u] == kk && i < mk));
+                below += __popcll(__ballot(lt));
+            }
+            if ((threadIdx.x & 63u) == 0u) atomicAdd(&pj[k], (uint32_t)below);
+        }
+    }
+    Team<kT>::sync();
+}
+
 // j mod n for j < 2^14 from a float reciprocal (quotient off by at most one)
 __device__ __forceinline__ int mod_small(int j, int n, float rn) {
     int r = j - (int)((float)j * rn) * n;
@@ -1131,6 +1175,10 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
     __shared__ uint32_t redu[kWaves];
     __shared__ int redi[kWaves];
     constexpr int kTeams = 256 / kT;
+    __shared__ uint32_t opn[kTeams][kCandCap];    // open pairs found without the order
+    __shared__ uint32_t opk[kTeams][kCandCap];    // their particles' keys
+    __shared__ uint32_t opj[kTeams][kCandCap];    // their pair indices
+    __shared__ int nopen[kTeams];
     const int team = kT == 64 ? (int)(threadIdx.x >> 6) : 0;
     const int t = Team<kT>::tid();
     const size_t tstride = (team_bytes(cap, (int)sizeof(R)) + 15) / 16 * 16;
@@ -1181,6 +1229,12 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
         bool same = true;
         v4[2] = canon_part<kT>(Ni, [&](int q) { const double w = wion[q]; same &= w == wi0; return chk(w); });
         const bool ion_order = active && (kMov || team_any<kT>(!same, redi));
+        // When every mobile particle pairs once, the draws of a pair are
+        // keyed by its mobile particle: with interchangeable ions nothing
+        // then depends on the order, which is not formed; the few open pairs
+        // get their pair index (the rank of their particle) at the end.
+        const bool mob_order = active && (!mobA || ion_order);
+        if (t == 0) nopen[team] = 0;
         // when every mobile particle pairs once the pair loop walks them in
         // storage order: its first momenta are loaded before the sort
         double qx = 0.0, qy = 0.0, qz = 0.0;
@@ -1193,7 +1247,10 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
             } else {
                 for (int i = t; i < kSliceBH; i += kT) slice[i] = slice_node_bh<R>(T, ct, i);
             }
-            rank_order<kT>(Nm, cell, kPass == 0 ? kTagKeyE : kTagKeyG, rng, M.keys, M.tmp, M.hist, M.ordM, mobA, redu);
+            if (mob_order)
+                rank_order<kT>(Nm, cell, kPass == 0 ? kTagKeyE : kTagKeyG, rng, M.keys, M.tmp, M.hist, M.ordM, mobA, redu);
+            else
+                Team<kT>::sync();      // the slice and the open-pair count
             if (ion_order)
                 rank_order<kT>(Ni, cell, kPass == 0 ? kTagKeyIE : kTagKeyIG, rng, M.keys, M.tmp, M.hist, M.ordI, false, redu);
         }
@@ -1207,7 +1264,7 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
         // particle pairs once, its density and n_ab share the walk)
         if (active && mobA) {
             canon_part2<kT>(N, [&](int q, double& a, double& b) {
-                const double u = chk(wm[q]), v = w_ion((int)M.ordM[q]);
+                const double u = chk(wm[q]), v = ion_order ? w_ion((int)M.ordM[q]) : wi0;
                 a += u;
                 b += u < v ? u : v;
             }, v4[0], v4[1]);
@@ -1231,8 +1288,9 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
         if (nab > 0.0) {
             const double coef = v4[0] * v4[2] / nab;
             for (int q = t; q < N; q += kT) {
-                const int j = mobA ? (int)M.ordM[q] : q;
+                const int j = mobA ? (mob_order ? (int)M.ordM[q] : 0) : q;
                 const int mi = mobA ? q : mob_of(j);
+                const uint32_t dk = (uint32_t)(mobA ? mi : j);   // counter of the pair's draws
                 double cx = qx, cy = qy, cz = qz;
                 if (mobA) {
                     if (q + kT < N) { qx = S.px[m0 + q + kT]; qy = S.py[m0 + q + kT]; qz = S.pz[m0 + q + kT]; }
@@ -1252,7 +1310,7 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
                         high |= hi;
                         if (sig > (R)0) {
                             const double x = coef * (double)sig * e.vrel * A.dt;
-                            const U4 r = rng.draw((uint32_t)j, cell, kTagAccBr);
+                            const U4 r = rng.draw(dk, cell, kTagAccBr);
                             if (u53(r.x, r.y) <= rej * x) bits = 1u;
                         }
                     }
@@ -1260,7 +1318,7 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
                         const R sig = (R)phys::trident_sigma(T.Z, (double)e.g);
                         if (sig > (R)0) {
                             const double x = coef * (double)sig * e.vrel * A.dt;
-                            const U4 r = rng.draw((uint32_t)j, cell, kTagAccTr);
+                            const U4 r = rng.draw(dk, cell, kTagAccTr);
                             if (u53(r.x, r.y) <= rej * x) bits = 2u;
                         }
                     }
@@ -1279,11 +1337,29 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
                     high |= hi;
                     if (sig > (R)0) {
                         const double x = coef * (double)sig * flux * A.dt;
-                        const U4 r = rng.draw((uint32_t)j, cell, kTagAccBh);
+                        const U4 r = rng.draw(dk, cell, kTagAccBh);
                         if (u53(r.x, r.y) <= rej * x) bits = 1u;
                     }
                 }
-                if (bits) push_cand(W, c, ev_pack(kPass, j, mi, ion_of(j), bits));
+                if (bits) {
+                    if (mob_order) {
+                        push_cand(W, c, ev_pack(kPass, j, mi, ion_of(j), bits));
+                    } else {
+                        const int k = atomicAdd(&nopen[team], 1);
+                        if (k < kCandCap) opn[team][k] = (uint32_t)mi | (bits << 16);
+                    }
+                }
+            }
+            if (!mob_order) {
+                Team<kT>::sync();
+                const int n_open = nopen[team];
+                if (n_open > kCandCap) {
+                    if (t == 0) mark_slow(W, c);
+                } else if (n_open > 0) {
+                    rank_open<kT>(Nm, cell, kPass == 0 ? kTagKeyE : kTagKeyG, rng, opn[team], opk[team], opj[team], n_open);
+                    if (t < n_open)
+                        push_cand(W, c, ev_pack(kPass, (int)opj[team][t], (int)(opn[team][t] & 0xFFFFu), 0, opn[team][t] >> 16));
+                }
             }
             if (t == 0) W.coef[c * 2 + kPass] = coef;
         }
@@ -1353,6 +1429,8 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
             const uint64_t mine = cand ? rec[lane] : 0ull;
             const int pass = cand ? ev_pass(mine) : 2;
             const int j = ev_j(mine), mi = ev_m(mine), ii = ev_i(mine);
+            // the pair's draws: keyed by its mobile particle when that species pairs once
+            const uint32_t dk = (uint32_t)((pass == 0 ? Ne >= Ni : Ng0 >= Ni) ? mi : j);
             const CellTab<double> ct64 = W.cs[c].d;
             // ---- settle them; the particle and the FP64 lookup stay in the
             // lane for the sampling
@@ -1382,14 +1460,14 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
                         bool hi;
                         const R sig = brems_lookup<R, false>(T, ct, e.g, e.gm1, hi).sig;
                         const double x = coef * (double)sig * e.vrel * A.dt;
-                        if (settle(x, rng.draw((uint32_t)j, cell, kTagAccBr), rej, A.near_rel, Pej, near_br))
+                        if (settle(x, rng.draw(dk, cell, kTagAccBr), rej, A.near_rel, Pej, near_br))
                             kind = kEvBr | ((A.proc & CMC_TRIDENT) ? kEvTrPending : 0u);
                     }
                     if ((A.proc & CMC_TRIDENT) && !kind) {
                         const R sig = (R)phys::trident_sigma(T.Z, (double)e.g);
                         if (sig > (R)0) {
                             const double x = coef * (double)sig * e.vrel * A.dt;
-                            if (settle(x, rng.draw((uint32_t)j, cell, kTagAccTr), rej, A.near_rel, Pej, near_tr))
+                            if (settle(x, rng.draw(dk, cell, kTagAccTr), rej, A.near_rel, Pej, near_tr))
                                 kind = kEvTr;
                         }
                     }
@@ -1405,7 +1483,7 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
                     const R sig = bh_lookup<R>(T, ct, k, ik, wk, hi);
                     const double x = coef * (double)sig * photon_flux(fr, b) * A.dt;
                     const double Pej = Wi / (Wm > Wi ? Wm : Wi);
-                    if (settle(x, rng.draw((uint32_t)j, cell, kTagAccBh), rej, A.near_rel, Pej, near_bh))
+                    if (settle(x, rng.draw(dk, cell, kTagAccBh), rej, A.near_rel, Pej, near_bh))
                         kind = kEvBh;
                     reused = Ng0 < Ni && j + Ng0 < Ni;
                 }
@@ -1440,12 +1518,12 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
             double xiA = 0.0;
             bool reqA = false;
             if (pass == 0 && (evk & kEvBr)) {
-                const U4 q = rng.draw((uint32_t)j, cell, kTagSmpBr);
+                const U4 q = rng.draw(dk, cell, kTagSmpBr);
                 rowA = brems_row<double>(T64, BLd);
                 xiA = u53(q.x, q.y);
                 reqA = true;
             } else if (pass == 1 && (evk & kEvBh)) {
-                const U4 q = rng.draw((uint32_t)j, cell, kTagSmpBh);
+                const U4 q = rng.draw(dk, cell, kTagSmpBh);
                 rowA = bh_row<double>(T64, ikd, wkd);
                 xiA = u53(q.x, q.y);
                 reqA = true;
@@ -1476,7 +1554,7 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
                     if (sig > (R)0) {
                         const double x = W.coef[c * 2] * (double)sig * e.vrel * A.dt;
                         const double P = -expm1(-x);
-                        const U4 q = rng.draw((uint32_t)j, cell, kTagAccTr);
+                        const U4 q = rng.draw(dk, cell, kTagAccTr);
                         const double U1 = u53(q.x, q.y), U2 = u53(q.z, q.w);
                         if (fabs(U1 - P) <= A.near_rel * P) t.near_tr++;
                         tr = U1 < P && U2 < Pej;
@@ -1499,7 +1577,7 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
             CdfRow<double> rowB = {};
             Frame ft = {};   // the electron, after this pair's Bremsstrahlung, seen from the ion
             if (tr) {
-                qt = rng.draw((uint32_t)j, cell, kTagSmpTr);
+                qt = rng.draw(dk, cell, kTagSmpTr);
                 ft = electron_frame(b, px, py, pz);
                 rowB = trident_row<double>(T64, ft.g);
             }
