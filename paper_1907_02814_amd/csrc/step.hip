@@ -33,10 +33,33 @@ constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 
 // ------------------------------------------------------------------ helpers
+// A lane's value after a DPP move of the wavefront (both halves of a double)
+template <int kCtrl>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, kCtrl, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), kCtrl, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
+__device__ __forceinline__ double lane_f64(double v, int lane) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Sum over the 64 lanes of a wavefront (all active), the same value in every
+// lane: a butterfly over lane distances 1, 2, 4, 8 inside each row of 16
+// lanes (DPP quad permutations and mirrors, each lane adding its partner's
+// partial, which a commutative add makes equal on both sides), then the four
+// row sums as (r0 + r1) + (r2 + r3).
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]
+    v += dpp_f64<0x141>(v);   // row_half_mirror: the other quad of 8
+    v += dpp_f64<0x140>(v);   // row_mirror: the other 8 of 16
+    return (lane_f64(v, 0) + lane_f64(v, 16)) + (lane_f64(v, 32) + lane_f64(v, 48));
 }
 
 // fixed-shape workgroup sum (deterministic for a given kThreads)
@@ -990,6 +1013,47 @@ __device__ __forceinline__ void team_reduce4(double (&v)[4], bool& flag, double*
     }
 }
 
+// team_reduce4 with a word of flag bits OR-ed over the team (bits 0..2)
+template <int kT>
+__device__ __forceinline__ void team_reduce4_bits(double (&v)[4], int& bits, double* red4, int* redi) {
+    int wb = 0;
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+        if (__ballot((bits >> b) & 1) != 0ull) wb |= 1 << b;
+    if constexpr (kT == 64) {
+        bits = wb;
+    } else {
+        const int w = threadIdx.x >> 6;
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) red4[w * 4 + k] = v[k];
+            redi[w] = wb;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = ((red4[k] + red4[4 + k]) + red4[8 + k]) + red4[12 + k];
+        bits = redi[0] | redi[1] | redi[2] | redi[3];
+        __syncthreads();
+    }
+}
+
+// The canonical sum (as canon_part2) of values met four per thread, at
+// q = t + kT u for u = 0..3 with n <= 4 kT (zero where q >= n), added as
+// they come: canon_add for each u in order, then canon_end gives the
+// thread's partial after its wavefront's butterfly (workgroup teams) or
+// the team total (wavefront teams).
+template <int kT>
+__device__ __forceinline__ void canon_add(double& s, double v, int u) {
+    if constexpr (kT == 256) s = u == 0 ? v : s + v;
+    else s = u == 0 ? wave_sum(v) : s + wave_sum(v);
+}
+template <int kT>
+__device__ __forceinline__ double canon_end(double s) {
+    if constexpr (kT == 256) return wave_sum(s);
+    else return s;
+}
+
 // Buckets of the rank sort: the power of two at or above n (at most 4096),
 // so that a bucket holds one or two keys on average.
 __host__ __device__ inline int rank_bucket_bits(int n) {
@@ -1216,6 +1280,131 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
         const double* wion = A.io.w + i0;
         const bool mobA = Nm >= Ni;
         const int N = mobA ? Nm : Ni;
+        // ---- direct form: every mobile particle pairs once (N_m >= N_i), at
+        // most four per thread, ions at rest.  The weights are summed
+        // (densities, n_ab against the first ion's weight, the weight checks)
+        // in one reduction, beside the table slice; then every pair is
+        // tested in storage order.  Should the ions not share one weight,
+        // the cell is done again below with both orders.
+        if constexpr (!kMov) {
+            if (active && mobA && N <= 4 * kT) {
+                {
+                    const CellTab<R> ct = pick<R>(W.cs[c]);
+                    if (kPass == 0) {
+                        if (A.proc & CMC_BREMS)
+                            for (int i = t; i < kSliceBrems; i += kT) slice[i] = slice_node_brems<R>(T, ct, i);
+                    } else {
+                        for (int i = t; i < kSliceBH; i += kT) slice[i] = slice_node_bh<R>(T, ct, i);
+                    }
+                }
+                // the first pair's momenta are in flight during the reduction
+                double nx = 0.0, ny = 0.0, nz = 0.0;
+                if (t < N) { nx = S.px[m0 + t]; ny = S.py[m0 + t]; nz = S.pz[m0 + t]; }
+                const double w0 = wion[0];
+                int fl = 0;                 // 1 bad weight, 2 ions of unequal weight, 4 above the tables
+                double v4[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int q = t + kT * u;
+                    const double wq = q < N ? wm[q] : 0.0, wi = q < Ni ? wion[q] : 0.0;
+                    fl |= (!(wq >= 0.0) || !isfinite(wq) || !(wi >= 0.0) || !isfinite(wi)) ? 1 : 0;
+                    fl |= (q < Ni && wi != w0) ? 2 : 0;
+                    canon_add<kT>(v4[0], wq, u);
+                    canon_add<kT>(v4[1], q < N ? (wq < w0 ? wq : w0) : 0.0, u);
+                    canon_add<kT>(v4[2], wi, u);
+                }
+                v4[0] = canon_end<kT>(v4[0]);
+                v4[1] = canon_end<kT>(v4[1]);
+                v4[2] = canon_end<kT>(v4[2]);
+                {
+                    int bad = 0;
+                    v4[3] = canon_part<kT>(No, [&](int q) { const double w = wo[q]; bad |= !(w >= 0.0) || !isfinite(w); return w; });
+                    fl |= bad ? 1 : 0;
+                }
+                if (t == 0) nopen[team] = 0;
+                team_reduce4_bits<kT>(v4, fl, red4, redi);   // its barriers also publish the slice
+                if (kT == 64) Team<kT>::sync();
+                if (!(fl & 2)) {
+                    if (fl & 1) {
+                        if (t == 0) atomicOr(A.status, CMC_ST_BAD_WEIGHT);
+                        continue;
+                    }
+                    const double nab = v4[1];
+                    int high = 0;
+                    if (nab > 0.0) {
+                        const double coef = v4[0] * v4[2] / nab;
+                        // one pair at a time (the tests do not overlap in
+                        // registers), the next pair's momenta in flight
+#pragma unroll 1
+                        for (int u = 0; u < 4; ++u) {
+                            const int q = t + kT * u;
+                            const double cx = nx, cy = ny, cz = nz;
+                            if (q + kT < N) { nx = S.px[m0 + q + kT]; ny = S.py[m0 + q + kT]; nz = S.pz[m0 + q + kT]; }
+                            if (q >= N) continue;
+                            uint32_t bits = 0;
+                            if (kPass == 0) {
+                                const Elec<R> e = electron_p<R>(cx, cy, cz);
+                                if (A.proc & CMC_BREMS) {
+                                    bool hi;
+                                    const R sig = brems_sig_slice<R>(T, slice, e.g, e.gm1, hi);
+                                    high |= hi;
+                                    if (sig > (R)0) {
+                                        const double x = coef * (double)sig * e.vrel * A.dt;
+                                        const U4 r = rng.draw((uint32_t)q, cell, kTagAccBr);
+                                        if (u53(r.x, r.y) <= rej * x) bits = 1u;
+                                    }
+                                }
+                                if ((A.proc & CMC_TRIDENT) && !bits) {
+                                    const R sig = (R)phys::trident_sigma(T.Z, (double)e.g);
+                                    if (sig > (R)0) {
+                                        const double x = coef * (double)sig * e.vrel * A.dt;
+                                        const U4 r = rng.draw((uint32_t)q, cell, kTagAccTr);
+                                        if (u53(r.x, r.y) <= rej * x) bits = 2u;
+                                    }
+                                }
+                            } else {
+                                bool hi;
+                                const R sig = bh_sig_slice<R>(T, slice, photon_k<R>(cx, cy, cz), hi);
+                                high |= hi;
+                                if (sig > (R)0) {
+                                    const double x = coef * (double)sig * phys::kC * A.dt;
+                                    const U4 r = rng.draw((uint32_t)q, cell, kTagAccBh);
+                                    if (u53(r.x, r.y) <= rej * x) bits = 1u;
+                                }
+                            }
+                            if (bits) {
+                                const int k = atomicAdd(&nopen[team], 1);
+                                if (k < kCandCap) opn[team][k] = (uint32_t)q | (bits << 16);
+                            }
+                        }
+                        Team<kT>::sync();
+                        const int n_open = nopen[team];
+                        if (n_open > kCandCap) {
+                            if (t == 0) mark_slow(W, c);
+                        } else if (n_open > 0) {
+                            rank_open<kT>(Nm, cell, kPass == 0 ? kTagKeyE : kTagKeyG, rng, opn[team], opk[team], opj[team], n_open);
+                            if (t < n_open)
+                                push_cand(W, c, ev_pack(kPass, (int)opj[team][t], (int)(opn[team][t] & 0xFFFFu), 0, opn[team][t] >> 16));
+                        }
+                        if (t == 0) W.coef[c * 2 + kPass] = coef;
+                    }
+                    if (t == 0) {
+                        if (kPass == 0) {
+                            A.ti[c * CMC_NI + CMC_I_PAIRS_BR] = (nab > 0.0 && (A.proc & CMC_BREMS)) ? N : 0;
+                            A.ti[c * CMC_NI + CMC_I_PAIRS_TR] = (nab > 0.0 && (A.proc & CMC_TRIDENT)) ? N : 0;
+                            A.td[c * CMC_ND + CMC_D_NAB_EI] = nab;
+                        } else {
+                            A.ti[c * CMC_NI + CMC_I_PAIRS_BH] = nab > 0.0 ? N : 0;
+                            A.td[c * CMC_ND + CMC_D_NAB_GI] = nab;
+                        }
+                    }
+                    if (team_any<kT>(high != 0, redi) && t == 0) atomicOr(A.status, CMC_ST_GAMMA_HIGH);
+                    Team<kT>::sync();   // LDS of this cell is free
+                    continue;
+                }
+                Team<kT>::sync();       // the slice is staged again below
+            }
+        }
         // the weights of the cell are checked (non-negative, finite) as
         // they are summed into the densities
         int bad = 0;
