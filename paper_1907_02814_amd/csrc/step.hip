@@ -37,8 +37,8 @@ constexpr int kWaves = kThreads / 64;
 template <int kCtrl>
 __device__ __forceinline__ double dpp_f64(double v) {
     const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, kCtrl, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), kCtrl, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)b, kCtrl, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), kCtrl, 0xF, 0xF, false);
     return __longlong_as_double((long long)(((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo));
 }
 
@@ -62,6 +62,16 @@ __device__ __forceinline__ double wave_sum(double v) {
     return (lane_f64(v, 0) + lane_f64(v, 16)) + (lane_f64(v, 32) + lane_f64(v, 48));
 }
 
+// The same for 32-bit integers (exact in any order)
+__device__ __forceinline__ int wave_sum_i32(int v) {
+    v += __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);
+    v += __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);
+    v += __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false);
+    v += __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, false);
+    return __builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16) +
+           __builtin_amdgcn_readlane(v, 32) + __builtin_amdgcn_readlane(v, 48);
+}
+
 // fixed-shape workgroup sum (deterministic for a given kThreads)
 __device__ double block_sum(double v, double* red) {
     v = wave_sum(v);
@@ -72,20 +82,6 @@ __device__ double block_sum(double v, double* red) {
     double s = red[0];
 #pragma unroll
     for (int i = 1; i < kWaves; ++i) s += red[i];
-    __syncthreads();
-    return s;
-}
-
-__device__ long long block_sum_ll(long long v, long long* red) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    const int w = threadIdx.x >> 6;
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) red[w] = v;
-    __syncthreads();
-    long long s = 0;
-#pragma unroll
-    for (int i = 0; i < kWaves; ++i) s += red[i];
     __syncthreads();
     return s;
 }
@@ -416,21 +412,18 @@ __device__ __forceinline__ double lab_energy_change(const Ion& b, const Frame& f
     return b.gi * dE + un * (dE * (gf + f.g) / (pf + f.pm));
 }
 
-// all tallies of the cell reduced in one pass: wave butterflies, then the
+// all tallies of the cell reduced in one pass: wavefront sums, then the
 // waves' partials summed in wave order by one thread (fixed shape)
 __device__ void write_tallies(const StepArgs& A, int64_t c, const Tally& t, double nab_ei,
                               double nab_gi, long long* redl, double* redd) {
     long long iv[CMC_NI] = {t.pairs_br, t.pairs_tr, t.pairs_bh, t.ev_br, t.ev_tr, t.ev_bh,
                             t.near_br, t.near_tr, t.near_bh, t.drop_ph, t.drop_el, t.drop_po};
     double dv[8] = {t.E_br, t.E_tr, t.E_bh, t.dE_el, t.dE_ph, t.W_br, t.W_tr, t.W_bh};
+    // (a thread's counts are at most its share of one cell's pairs)
 #pragma unroll
-    for (int q = 0; q < CMC_NI; ++q)
+    for (int q = 0; q < CMC_NI; ++q) iv[q] = wave_sum_i32((int)iv[q]);
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) iv[q] += __shfl_xor(iv[q], o, 64);
-#pragma unroll
-    for (int q = 0; q < 8; ++q)
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) dv[q] += __shfl_xor(dv[q], o, 64);
+    for (int q = 0; q < 8; ++q) dv[q] = wave_sum(dv[q]);
     const int w = threadIdx.x >> 6;
     __syncthreads();
     if ((threadIdx.x & 63) == 0) {
@@ -960,8 +953,8 @@ __device__ __forceinline__ bool team_any(bool v, int* red) {
 }
 
 // Sums over i in [0, n) in one fixed order whatever the team size: as 256
-// threads striding by 256, each wavefront's partials reduced by an xor
-// butterfly and the four wavefront totals added in order (team_reduce4).
+// threads striding by 256, each wavefront's partials reduced by wave_sum
+// and the four wavefront totals added in order (team_reduce4).
 // The two team shapes therefore give bit-identical densities and n_ab.
 // canon_part2 is the per-thread part before the cross-wavefront step
 // (wavefront teams: the team total); it walks once and accumulates two sums.
@@ -1589,13 +1582,19 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
     const int n_items = W.counters[0];
     const double rej = 2.0 * (1.0 + A.near_rel);
     const Rng rng = step_rng(A);
+    // the block's first cell is read beside the count (the list has
+    // n_cells >= gridDim.x entries; an entry past the count is not used)
+    int64_t c_next = W.list_ev[blockIdx.x];
     for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
-        const int64_t c = W.list_ev[item];
-        if (threadIdx.x == 0) { ctl[0] = (W.flags[c] & kFlagSlow) ? 1 : 0; ctl[1] = 0; }
-        __syncthreads();
+        const int64_t c = c_next;
+        if (item + (int)gridDim.x < n_items) c_next = W.list_ev[item + gridDim.x];
+        const bool slow = (W.flags[c] & kFlagSlow) != 0;
+        // ctl is read by the other wavefronts only after the barrier that
+        // ends wavefront 0's work; wavefront 0 may set ctl[0..3] meanwhile
+        if (threadIdx.x == 0) { ctl[0] = slow ? 1 : 0; ctl[1] = 0; }
         const int64_t g0 = A.ph.off[c];
         const int Ng0 = live(A.ph, c);
-        if (wv == 0 && !ctl[0]) do {
+        if (wv == 0 && !slow) do {
             const uint32_t cell = (uint32_t)c;
             const int nc = min(W.ncand[c], kCandCap);
             const int64_t e0 = A.el.off[c], i0 = A.io.off[c];
@@ -1834,16 +1833,13 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
                 if (lane == 0) { ctl[1] = n_bh; ctl[2] = first & ~63; ctl[3] = ph_count; }
             }
             // tallies of the events (the pair counts were written by the passes)
+            // (a lane holds one open pair: its counts are small)
             long long iv[9] = {t.ev_br, t.ev_tr, t.ev_bh, t.near_br, t.near_tr, t.near_bh, t.drop_ph, t.drop_el, t.drop_po};
             double dv[8] = {t.E_br, t.E_tr, t.E_bh, t.dE_el, t.dE_ph, t.W_br, t.W_tr, t.W_bh};
 #pragma unroll
-            for (int q = 0; q < 9; ++q)
+            for (int q = 0; q < 9; ++q) iv[q] = wave_sum_i32((int)iv[q]);
 #pragma unroll
-                for (int o = 32; o > 0; o >>= 1) iv[q] += __shfl_xor(iv[q], o, 64);
-#pragma unroll
-            for (int q = 0; q < 8; ++q)
-#pragma unroll
-                for (int o = 32; o > 0; o >>= 1) dv[q] += __shfl_xor(dv[q], o, 64);
+            for (int q = 0; q < 8; ++q) dv[q] = wave_sum(dv[q]);
             if (lane == 0) {
                 int64_t* ti = A.ti + c * CMC_NI;
                 ti[CMC_I_EV_BR] = iv[0]; ti[CMC_I_EV_TR] = iv[1]; ti[CMC_I_EV_BH] = iv[2];
@@ -1860,6 +1856,7 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
         __syncthreads();
         if (ctl[0]) {
             collide_cell<R>(A, T, T64, rng, c, S, sh);
+            __syncthreads();
             continue;
         }
         if (ctl[1]) {
@@ -1905,6 +1902,7 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
             }
             if (threadIdx.x == 0 && A.ph.count) A.ph.count[c] = wpos;
         }
+        __syncthreads();   // every read of ctl and of the LDS lists precedes the next cell
     }
 }
 
