@@ -5,10 +5,9 @@ python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg2]
 Prints one JSON line: pair evaluations per second over the K timed steps
 (the pair tests of all processes, summed; inputs resident in HBM), the FP32
 form against the plain FP64 form on the same cells, the HBM roofline of the
-pair-test kernel (algorithmic bytes per launch over its duration measured
-with HIP events recorded on its own stream around every launch of K further
-steps) and the FP64 CPU oracle timed on a bounded sample of the same
-workload.
+pair-test kernel (algorithmic bytes per launch over its duration, from HIP
+events that the launches of K further steps stamp at kernel start and end)
+and the FP64 CPU oracle timed on a bounded sample of the same workload.
 
 python bench.py --copy-calibration runs only a device-to-device copy of
 known size: the counter runs that measure the kernel's HBM traffic read the
@@ -31,6 +30,7 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "pair evaluations/sec + % HBM peak; FP32-batched vs FP64-plain at 1e-5 rel err"
 COUNTERS = os.path.join(ROOT, "profiles", "k_pass_bh_cfg2_counters.txt")
 COPY_BYTES = 1 << 30
+HIP_EVENT_DISABLE_SYSTEM_FENCE = 0x20000000
 
 WORKLOADS = {
     "cfg2": ("Bethe-Heitler pairs, FP32 tables + FP64 tallies: 4096 cells x (1024 photons + "
@@ -82,7 +82,7 @@ class HipEvents:
 
     def __init__(self):
         self.lib = ctypes.CDLL("libamdhip64.so")
-        self.lib.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        self.lib.hipEventCreateWithFlags.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint]
         self.lib.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
         self.lib.hipEventDestroy.argtypes = [ctypes.c_void_p]
 
@@ -90,9 +90,11 @@ class HipEvents:
         out = []
         for _ in range(n):
             e = ctypes.c_void_p()
-            rc = self.lib.hipEventCreate(ctypes.byref(e))
+            # timing only: no system-scope fence (cache writeback and
+            # invalidation) when the event completes
+            rc = self.lib.hipEventCreateWithFlags(ctypes.byref(e), HIP_EVENT_DISABLE_SYSTEM_FENCE)
             if rc != 0:
-                raise RuntimeError(f"hipEventCreate failed ({rc})")
+                raise RuntimeError(f"hipEventCreateWithFlags failed ({rc})")
             out.append(e.value)
         return out
 
@@ -128,10 +130,9 @@ def run_gpu(wl, precision, steps, warmup, schedule, seed=1):
         st.step(warmup + i, stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    # K more steps with HIP events recorded around the pair-test kernels on
-    # their stream: the kernel durations.  (An event record between kernels
-    # costs the stream a few microseconds, so these steps are not the ones
-    # whose wall time gives the throughput.)
+    # K more steps whose pair-test launches stamp HIP events at their start
+    # and end (on their stream): the kernel durations.  These steps are kept
+    # apart from the ones whose wall time gives the throughput.
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for i in range(steps):

@@ -128,9 +128,11 @@ typedef struct {
                               per cell (<= CMC_MAX_PER_CELL); sizes the launch */
     double near_rel;       /* band |U - P| <= near_rel * P counted as near-threshold,
                               in [0, 1] (default 1e-6)                        */
-    void* pass_events[2];  /* optional hipEvent_t pair (NULL: none), recorded on
-                              the stream just before and just after the pair-test
-                              kernels of the step, to time them; ignored by
+    void* pass_events[2];  /* optional hipEvent_t pair (both or none), to time
+                              the pair-test kernels of the step: [0] takes the
+                              start of the first of them and [1] the end of the
+                              last, stamped by the launches themselves (no
+                              marker between kernels); ignored by
                               CMC_SCHED_CELL                                  */
     uint64_t* step_counter;/* optional device [1] (NULL: use `step`): the step
                               number is read from it on the device and it is

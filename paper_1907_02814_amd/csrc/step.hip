@@ -15,13 +15,13 @@
 //   5. photons converted by Bethe-Heitler are removed by a stable in-place
 //      compaction; per-cell tallies are reduced in a fixed tree.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <cstdint>
 #include <map>
 #include <mutex>
 #include <tuple>
-#include <algorithm>
 
 #include "common.hpp"
 #include "philox.hpp"
@@ -1992,44 +1992,52 @@ static void lds_attr(const void* fn, size_t bytes, hipStream_t st) {
         (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
+// Optional timing of the pair-test kernels of a step: the first launch
+// records `start` when it begins, every launch records `stop` when it ends
+// (the last one wins), timestamped by the launches themselves.
+struct PassTiming {
+    hipEvent_t start, stop;
+    bool first;
+};
+
 template <typename R, int kT, bool kMov>
 static void launch_pass_m(const StepArgs& A, const TabView<R>& T, const Work& W, int cap, size_t dshm,
-                          unsigned grid, int filter, int fcap, hipStream_t st) {
-    if (A.proc & (CMC_BREMS | CMC_TRIDENT)) {
-        lds_attr((const void*)k_pass<R, kT, 0, kMov>, dshm, st);
-        hipLaunchKernelGGL((k_pass<R, kT, 0, kMov>), dim3(grid), dim3(256), dshm, st, A, T, W, cap, filter, fcap);
-    }
-    if (A.proc & CMC_BH) {
-        lds_attr((const void*)k_pass<R, kT, 1, kMov>, dshm, st);
-        hipLaunchKernelGGL((k_pass<R, kT, 1, kMov>), dim3(grid), dim3(256), dshm, st, A, T, W, cap, filter, fcap);
-    }
+                          unsigned grid, int filter, int fcap, hipStream_t st, PassTiming* pt) {
+    const auto launch = [&](auto kernel) {
+        lds_attr((const void*)kernel, dshm, st);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (pt) { e0 = pt->first ? pt->start : nullptr; e1 = pt->stop; pt->first = false; }
+        hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(256), (uint32_t)dshm, st, e0, e1, 0u, A, T, W, cap, filter, fcap);
+    };
+    if (A.proc & (CMC_BREMS | CMC_TRIDENT)) launch(k_pass<R, kT, 0, kMov>);
+    if (A.proc & CMC_BH) launch(k_pass<R, kT, 1, kMov>);
 }
 
 template <typename R, int kT>
 static void launch_pass_t(const StepArgs& A, const TabView<R>& T, const Work& W, int cap, size_t dshm,
-                          unsigned grid, int filter, int fcap, hipStream_t st) {
+                          unsigned grid, int filter, int fcap, hipStream_t st, PassTiming* pt) {
     if (A.io.px) {
-        launch_pass_m<R, kT, true>(A, T, W, cap, dshm, grid, filter, fcap, st);
+        launch_pass_m<R, kT, true>(A, T, W, cap, dshm, grid, filter, fcap, st, pt);
     } else {
-        launch_pass_m<R, kT, false>(A, T, W, cap, dshm, grid, filter, fcap, st);
+        launch_pass_m<R, kT, false>(A, T, W, cap, dshm, grid, filter, fcap, st, pt);
     }
 }
 
 // the pass kernels with teams of `team` threads over the cells of a size
 // class (filter 0: all)
 static void launch_team(const StepArgs& A, const cmc_tables_s* t, const Work& W, bool fp64, int team, int filter,
-                        int fcap, int64_t max_blocks, hipStream_t st) {
+                        int fcap, int64_t max_blocks, hipStream_t st, PassTiming* pt) {
     const int cap = team_cap(team, A.maxn, fp64);
     const size_t per = (team_bytes(cap, fp64 ? 8 : 4) + 15) / 16 * 16;
     const size_t dshm = per * (size_t)(256 / team);
     const int64_t units = team == 64 ? (A.n_cells + 3) / 4 : A.n_cells;
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(units, max_blocks));
     if (fp64) {
-        if (team == 64) launch_pass_t<double, 64>(A, view64(t), W, cap, dshm, grid, filter, fcap, st);
-        else launch_pass_t<double, 256>(A, view64(t), W, cap, dshm, grid, filter, fcap, st);
+        if (team == 64) launch_pass_t<double, 64>(A, view64(t), W, cap, dshm, grid, filter, fcap, st, pt);
+        else launch_pass_t<double, 256>(A, view64(t), W, cap, dshm, grid, filter, fcap, st, pt);
     } else {
-        if (team == 64) launch_pass_t<float, 64>(A, view32(t), W, cap, dshm, grid, filter, fcap, st);
-        else launch_pass_t<float, 256>(A, view32(t), W, cap, dshm, grid, filter, fcap, st);
+        if (team == 64) launch_pass_t<float, 64>(A, view32(t), W, cap, dshm, grid, filter, fcap, st, pt);
+        else launch_pass_t<float, 256>(A, view32(t), W, cap, dshm, grid, filter, fcap, st, pt);
     }
 }
 
@@ -2038,13 +2046,13 @@ static void launch_team(const StepArgs& A, const cmc_tables_s* t, const Work& W,
 constexpr int kHybrid = -1;
 
 static cmc_status launch_passes(const StepArgs& A, const cmc_tables_s* t, const Work& W, bool fp64, int shape,
-                                hipStream_t st) {
+                                hipStream_t st, PassTiming* pt = nullptr) {
     if (shape == kHybrid) {
         const int small = team_cap(64, A.maxn, fp64);
-        launch_team(A, t, W, fp64, 64, 1, small, 256 * 64, st);
-        launch_team(A, t, W, fp64, 256, 2, small, 2048, st);
+        launch_team(A, t, W, fp64, 64, 1, small, 256 * 64, st, pt);
+        launch_team(A, t, W, fp64, 256, 2, small, 2048, st, pt);
     } else {
-        launch_team(A, t, W, fp64, shape, 0, 0, 256 * 64, st);
+        launch_team(A, t, W, fp64, shape, 0, 0, 256 * 64, st, pt);
     }
     CMC_CHECK_LAUNCH("cmc_collide_step: k_pass");
     return CMC_OK;
@@ -2218,10 +2226,10 @@ extern "C" cmc_status cmc_collide_step(cmc_tables t, const cmc_cells* cells, cmc
         cell_state(1);          // the timing runs filled the cell lists
         CMC_CHECK_LAUNCH("cmc_collide_step: k_cell_state");
     }
-    if (P->pass_events[0]) (void)hipEventRecord(static_cast<hipEvent_t>(P->pass_events[0]), st);
-    cmc_status s1 = launch_passes(A, t, W, fp64, team, st);
+    PassTiming timing{static_cast<hipEvent_t>(P->pass_events[0]), static_cast<hipEvent_t>(P->pass_events[1]), true};
+    cmc_status s1 = launch_passes(A, t, W, fp64, team, st,
+                                  (P->pass_events[0] && P->pass_events[1]) ? &timing : nullptr);
     if (s1 != CMC_OK) return s1;
-    if (P->pass_events[1]) (void)hipEventRecord(static_cast<hipEvent_t>(P->pass_events[1]), st);
     // the listed cells: open pairs and events, or the sequential step (a
     // short list: a small grid)
     const unsigned gev = (unsigned)std::min<int64_t>(A.n_cells, 512);
