@@ -85,6 +85,7 @@ class HipEvents:
         self.lib.hipEventCreateWithFlags.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint]
         self.lib.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
         self.lib.hipEventDestroy.argtypes = [ctypes.c_void_p]
+        self.lib.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
 
     def create(self, n):
         out = []
@@ -97,6 +98,11 @@ class HipEvents:
                 raise RuntimeError(f"hipEventCreateWithFlags failed ({rc})")
             out.append(e.value)
         return out
+
+    def record(self, e, stream):
+        rc = self.lib.hipEventRecord(ctypes.c_void_p(e), ctypes.c_void_p(stream.cuda_stream))
+        if rc != 0:
+            raise RuntimeError(f"hipEventRecord failed ({rc})")
 
     def elapsed_ms(self, a, b):
         ms = ctypes.c_float()
@@ -195,6 +201,78 @@ def cpu_baseline(wl, budget_s=12.0, seed=1):
                       f"{evals} pair evaluations in {el:.2f} s (FP64, OpenMP over cells)"}
 
 
+YIELD_WORKLOAD = ("cfg4: expected yield and its adjoint, 1024 cells x 4096 electrons (FP64 momenta), "
+                  "gamma log-uniform 2-1000, Cu, Z* ~ U[1,29], n_e log-uniform 1e21-1e24 cm^-3, "
+                  "T_e log-uniform 10 eV-10 keV, dt = 0.1 fs")
+
+
+def yield_bytes(n_cells, n_el):
+    """Algorithmic bytes of one call: forward reads px, py, pz, w (32 B per
+    electron) and the cell parameters (24 B), writes Y (8 B per cell); the
+    adjoint also reads gY and writes gpx, gpy, gpz, gw (32 B per electron)
+    and three cell gradients."""
+    fwd = 32 * n_el + 32 * n_cells
+    bwd = 64 * n_el + 56 * n_cells
+    return fwd, bwd
+
+
+def run_yield(calls=20, seed_cells=64, cpu=True):
+    """Expected yield (cfg4), forward and adjoint, both forms: the average
+    time per call of `calls` back-to-back calls between two HIP events on
+    the calls' stream, and the FP64 oracle on the first `seed_cells` cells."""
+    import torch
+    import paper_1907_02814_amd as cmc
+    from paper_1907_02814_amd import workloads as W
+    y = W.cfg4()
+    dev = torch.device("cuda:0")
+    t = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in y.items() if isinstance(v, np.ndarray)}
+    n_cells, n_el = len(y["Zstar"]), len(y["px"])
+    tab = cmc.build_tables(y["Z"])
+    gY = torch.ones(n_cells, dtype=torch.float64, device=dev)
+    H = HipEvents()
+    stream = torch.cuda.current_stream()
+    args = (t["Zstar"], t["n_e"], t["T_e"], t["off"], t["px"], t["py"], t["pz"], t["w"], y["dt"])
+    fwd_b, bwd_b = yield_bytes(n_cells, n_el)
+    out = {"workload": YIELD_WORKLOAD, "electrons": n_el}
+    for name, prec in (("fp32", cmc.FP32), ("fp64", cmc.FP64)):
+        row = {}
+        for kind, fn, nbytes in (("forward", lambda: cmc.expected_yield(tab, *args, precision=prec), fwd_b),
+                                 ("adjoint", lambda: cmc.expected_yield_backward(tab, *args, gY, precision=prec), bwd_b)):
+            for _ in range(3):
+                fn()
+            torch.cuda.synchronize()
+            e0, e1 = H.create(2)
+            H.record(e0, stream)
+            for _ in range(calls):
+                fn()
+            H.record(e1, stream)
+            torch.cuda.synchronize()
+            ms = H.elapsed_ms(e0, e1) / calls
+            H.destroy([e0, e1])
+            row[kind] = {"ms_per_call": ms, "electron_evals_per_s": n_el / (ms * 1e-3),
+                         "alg_bytes": nbytes, "hbm_frac": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        out[name] = row
+    if not cpu:
+        return out
+    # the oracle on a bounded sample of the same cells
+    from oracle import oracle as O
+    otab = O.tables(y["Z"])
+    k = seed_cells
+    e = int(y["off"][k])
+    sl = (y["Zstar"][:k], y["n_e"][:k], y["T_e"][:k], y["off"][:k + 1], y["px"][:e], y["py"][:e],
+          y["pz"][:e], y["w"][:e], y["dt"])
+    cores = len(os.sched_getaffinity(0))
+    t0 = time.perf_counter()
+    O.expected_yield(otab, *sl, nthreads=cores)
+    t1 = time.perf_counter()
+    O.expected_yield_backward(otab, *sl, np.ones(k), nthreads=cores)
+    t2 = time.perf_counter()
+    out["cpu_baseline"] = {"forward_electron_evals_per_s": e / (t1 - t0),
+                           "adjoint_electron_evals_per_s": e / (t2 - t1), "cores": cores, "kind": "oracle",
+                           "sample": f"the first {k} cells ({e} electrons), forward and adjoint once each (FP64)"}
+    return out
+
+
 def copy_calibration():
     import torch
     a = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device="cuda:0").uniform_()
@@ -214,6 +292,7 @@ def main():
     ap.add_argument("--schedule", default="auto", choices=["auto", "group", "wave", "hybrid", "cell"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 plain comparison")
+    ap.add_argument("--no-yield", action="store_true", help="skip the expected-yield measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device copy of known size (counter calibration)")
     a = ap.parse_args()
@@ -265,6 +344,9 @@ def main():
         out["fp64_plain"] = {"value": v64, "ms_per_step": fp64["wall_s"] * 1e3 / a.steps,
                              "kernel_ms": k64, "hbm_frac": alg / (k64 * 1e-3) / 1e9 / HBM_PEAK_GBS}
         out["fp32_speedup_vs_fp64"] = value / v64
+    if not a.no_yield:
+        print("[bench] expected yield", file=sys.stderr, flush=True)
+        out["expected_yield"] = run_yield(cpu=not a.no_cpu)
     if not a.no_cpu:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl)
