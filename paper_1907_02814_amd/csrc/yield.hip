@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include "common.hpp"
+#include "wave.hpp"
 
 namespace cmc {
 namespace {
@@ -18,8 +19,7 @@ constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 
 __device__ double ysum(double v, double* red) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    v = wave_sum(v);
     const int w = threadIdx.x >> 6;
     __syncthreads();
     if ((threadIdx.x & 63) == 0) red[w] = v;
@@ -39,7 +39,53 @@ struct YArgs {
     double dt;
 };
 
-// Bremsstrahlung lookup with the slopes of the interpolant
+// Per-cell slices of the Bremsstrahlung tables, staged in LDS once per
+// cell: the screening blend of sigma_B and sigma_k at every energy node of
+// the three segments (NR | rel | UR, as slice_node_brems), and for the
+// adjoint their slopes at each node along ln L (ln L_D on the NR segment)
+// and along eta_D (NR segment), by the interpolation's own arithmetic.  An
+// electron's lookup then only interpolates the slices along energy, with
+// the operations of brems_lookup, so its values are the same.
+template <typename R>
+__device__ __forceinline__ void yield_slice_node(const TabView<R>& T, const CellTab<R>& c, int i, R* sS, R* sK,
+                                                 double* sa, double* ka, double* se, double* ke) {
+    const double dLn = T.ax.L.du;
+    if (i < grid::kNR) {
+        sS[i] = blend_N<R>(T[grid::kSigN], 1, i, c, 0);
+        sK[i] = blend_N<R>(T[grid::kSkN], 1, i, c, 0);
+        if (sa) {
+            const double dEn = T.ax.eta.du;
+            for (int q = 0; q < 2; ++q) {
+                const R* TS = T[q ? grid::kSkN : grid::kSigN];
+                const R* p = TS + ((size_t)i * grid::kEta + c.iE) * grid::kL + c.iD;
+                const R* r = p + grid::kL;
+                const double v0 = (double)lerp(p[0], p[1], c.wD), v1 = (double)lerp(r[0], r[1], c.wD);
+                const double sl = c.inD ? (double)lerp(p[1] - p[0], r[1] - r[0], c.wE) / dLn : 0.0;
+                const double sv = c.inE ? (v1 - v0) / dEn : 0.0;
+                if (q) { ka[i] = sl; ke[i] = sv; } else { sa[i] = sl; se[i] = sv; }
+            }
+        }
+        return;
+    }
+    const bool rel = i < grid::kNR + grid::kRel;
+    const int ig = rel ? i - grid::kNR : i - grid::kNR - grid::kRel;
+    const R* TS = T[rel ? grid::kSigR : grid::kSigU];
+    const R* TK = T[rel ? grid::kSkR : grid::kSkU];
+    sS[i] = blend_L<R>(TS, 1, ig, c, 0);
+    sK[i] = blend_L<R>(TK, 1, ig, c, 0);
+    if (sa) {
+        const R* p = TS + (size_t)ig * grid::kL + c.iL;
+        const R* r = TK + (size_t)ig * grid::kL + c.iL;
+        sa[i] = c.inL ? (double)(p[1] - p[0]) / dLn : 0.0;
+        ka[i] = c.inL ? (double)(r[1] - r[0]) / dLn : 0.0;
+        se[i] = 0.0;
+        ke[i] = 0.0;
+    }
+}
+
+// Bremsstrahlung lookup from the slices, with the slopes of the
+// interpolant when sa != nullptr: along energy (u = ln(g - 1) on the NR
+// segment, ln g above) and along the screening axes
 template <typename R>
 struct BremsGrad {
     int seg;
@@ -48,52 +94,42 @@ struct BremsGrad {
 };
 
 template <typename R>
-__device__ BremsGrad<R> brems_grad(const TabView<R>& T, const CellTab<R>& c, R g, R gm1) {
+__device__ __forceinline__ BremsGrad<R> brems_grad(const TabView<R>& T, const R* sS, const R* sK, const double* sa,
+                                                  const double* ka, const double* se, const double* ke, R g, R gm1) {
     BremsGrad<R> o = {};
-    bool high;
-    const BremsLook<R> L = brems_lookup<R>(T, c, g, gm1, high);
-    o.seg = L.seg; o.in = L.in;
-    o.sig = (double)L.sig; o.sk = (double)L.sk;
-    if (L.seg == kSegNone) return o;
-    const double dLn = T.ax.L.du;
-    double s0, s1, k0, k1, as[2], ak[2], es[2], ek[2];
-    if (L.seg == kSegNR) {
-        const double dEn = T.ax.eta.du;
-        for (int h = 0; h < 2; ++h) {
-            for (int q = 0; q < 2; ++q) {
-                const R* TS = T[q ? grid::kSkN : grid::kSigN];
-                const R* p = TS + ((size_t)(L.ig + h) * grid::kEta + c.iE) * grid::kL + c.iD;
-                const R* r = p + grid::kL;
-                const double v0 = (double)lerp(p[0], p[1], c.wD), v1 = (double)lerp(r[0], r[1], c.wD);
-                const double sl = c.inD ? (double)lerp(p[1] - p[0], r[1] - r[0], c.wE) / dLn : 0.0;
-                const double se = c.inE ? (v1 - v0) / dEn : 0.0;
-                if (q) { ak[h] = sl; ek[h] = se; } else { as[h] = sl; es[h] = se; }
-            }
-        }
-        s0 = (double)blend_N<R>(T[grid::kSigN], 1, L.ig, c, 0); s1 = (double)blend_N<R>(T[grid::kSigN], 1, L.ig + 1, c, 0);
-        k0 = (double)blend_N<R>(T[grid::kSkN], 1, L.ig, c, 0); k1 = (double)blend_N<R>(T[grid::kSkN], 1, L.ig + 1, c, 0);
+    if (!(gm1 > (R)(grid::kTminEv / grid::kMec2Ev))) return o;
+    int base, ig;
+    R wg;
+    bool in;
+    double du;
+    if (g <= (R)2) {
+        o.seg = kSegNR;
+        locate<R>(Fast<R>::log(gm1), T.ax.nr, ig, wg, in);
+        base = 0;
+        du = T.ax.nr.du;
     } else {
-        const bool rel = L.seg == kSegRel;
-        const R* TS = T[rel ? grid::kSigR : grid::kSigU];
-        const R* TK = T[rel ? grid::kSkR : grid::kSkU];
-        for (int h = 0; h < 2; ++h) {
-            const R* p = TS + (size_t)(L.ig + h) * grid::kL + c.iL;
-            const R* r = TK + (size_t)(L.ig + h) * grid::kL + c.iL;
-            as[h] = c.inL ? (double)(p[1] - p[0]) / dLn : 0.0;
-            ak[h] = c.inL ? (double)(r[1] - r[0]) / dLn : 0.0;
-            es[h] = 0.0; ek[h] = 0.0;
-        }
-        s0 = (double)blend_L<R>(TS, 1, L.ig, c, 0); s1 = (double)blend_L<R>(TS, 1, L.ig + 1, c, 0);
-        k0 = (double)blend_L<R>(TK, 1, L.ig, c, 0); k1 = (double)blend_L<R>(TK, 1, L.ig + 1, c, 0);
+        const bool rel = g <= (R)100;
+        o.seg = rel ? kSegRel : kSegUR;
+        R u;
+        if (!rel && g > (R)grid::kTop) u = (R)log(grid::kTop); else u = Fast<R>::log(g);
+        locate<R>(u, rel ? T.ax.rel : T.ax.ur, ig, wg, in);
+        base = rel ? grid::kNR : grid::kNR + grid::kRel;
+        du = rel ? T.ax.rel.du : T.ax.ur.du;
     }
-    const double du = L.seg == kSegNR ? T.ax.nr.du : (L.seg == kSegRel ? T.ax.rel.du : T.ax.ur.du);
-    const double wg = (double)L.wg;
-    o.ds_du = L.in ? (s1 - s0) / du : 0.0;
-    o.dk_du = L.in ? (k1 - k0) / du : 0.0;
-    o.ds_a = as[0] + wg * (as[1] - as[0]);
-    o.dk_a = ak[0] + wg * (ak[1] - ak[0]);
-    o.ds_e = es[0] + wg * (es[1] - es[0]);
-    o.dk_e = ek[0] + wg * (ek[1] - ek[0]);
+    const int i0 = base + ig;
+    o.in = in;
+    o.sig = (double)lerp(sS[i0], sS[i0 + 1], wg);
+    o.sk = (double)lerp(sK[i0], sK[i0 + 1], wg);
+    if (sa) {
+        const double s0 = (double)sS[i0], s1 = (double)sS[i0 + 1], k0 = (double)sK[i0], k1 = (double)sK[i0 + 1];
+        const double w = (double)wg;
+        o.ds_du = in ? (s1 - s0) / du : 0.0;
+        o.dk_du = in ? (k1 - k0) / du : 0.0;
+        o.ds_a = sa[i0] + w * (sa[i0 + 1] - sa[i0]);
+        o.dk_a = ka[i0] + w * (ka[i0 + 1] - ka[i0]);
+        o.ds_e = se[i0] + w * (se[i0 + 1] - se[i0]);
+        o.dk_e = ke[i0] + w * (ke[i0 + 1] - ke[i0]);
+    }
     return o;
 }
 
@@ -122,29 +158,46 @@ __device__ CellJac cell_jacobian(const phys::Screen& s, double Z, double Zs, dou
     return J;
 }
 
+// One workgroup per cell.  The first electron of each thread is in flight
+// while thread 0 computes the cell's screening state; the slices are then
+// staged, and every electron is evaluated with the next one's record in
+// flight.
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_yield(YArgs A, TabView<R> T) {
     __shared__ double red[kWaves];
     __shared__ CellTab<R> ct_s;
+    __shared__ R sS[kSliceBrems], sK[kSliceBrems];
     for (int64_t c = blockIdx.x; c < A.n_cells; c += gridDim.x) {
         const double Zs = A.Zs[c], ne = A.ne[c], Te = A.Te[c];
         const double ni = ne / Zs;
+        const int64_t j1 = A.off[c + 1];
+        int64_t j = A.off[c] + threadIdx.x;
+        double nx = 0.0, ny = 0.0, nz = 0.0, nw = 0.0;
+        if (j < j1) { nx = A.px[j]; ny = A.py[j]; nz = A.pz[j]; nw = A.w[j]; }
         if (threadIdx.x == 0) ct_s = cell_tab<R>(phys::screening(T.Z, Zs, ni, Te), T.ax);
         __syncthreads();
-        const CellTab<R> ct = ct_s;
+        {
+            const CellTab<R> ct = ct_s;
+            for (int i = threadIdx.x; i < kSliceBrems; i += kThreads)
+                yield_slice_node<R>(T, ct, i, sS, sK, nullptr, nullptr, nullptr, nullptr);
+        }
+        __syncthreads();
         double acc = 0.0;
-        for (int64_t j = A.off[c] + threadIdx.x; j < A.off[c + 1]; j += kThreads) {
-            const R px = (R)A.px[j], py = (R)A.py[j], pz = (R)A.pz[j];
+        for (; j < j1; j += kThreads) {
+            const double qx = nx, qy = ny, qz = nz, w = nw;
+            if (j + kThreads < j1) {
+                nx = A.px[j + kThreads]; ny = A.py[j + kThreads]; nz = A.pz[j + kThreads]; nw = A.w[j + kThreads];
+            }
+            const R px = (R)qx, py = (R)qy, pz = (R)qz;
             const R p2 = px * px + py * py + pz * pz;
             const R g = sqrt((R)1 + p2), gm1 = p2 / (g + (R)1);
-            bool high;
-            const BremsLook<R> L = brems_lookup<R>(T, ct, g, gm1, high);
+            const BremsGrad<R> L = brems_grad<R>(T, sS, sK, nullptr, nullptr, nullptr, nullptr, g, gm1);
             double y = 0.0;
-            if (L.sig > (R)0) {
+            if (L.sig > 0.0) {
                 const double beta = (double)(sqrt(p2) / g);
-                const double x = ni * (double)L.sig * beta * phys::kC * A.dt;
+                const double x = ni * L.sig * beta * phys::kC * A.dt;
                 const double P = -expm1(-x);
-                y = A.w[j] * P * ((double)L.sk / (double)L.sig);
+                y = w * P * (L.sk / L.sig);
             }
             if (A.yp) A.yp[j] = y;
             acc += y;
@@ -160,24 +213,38 @@ __global__ __launch_bounds__(kThreads) void k_yield_bwd(YArgs A, TabView<R> T) {
     __shared__ double red[kWaves];
     __shared__ CellTab<R> ct_s;
     __shared__ CellJac J_s;
+    __shared__ R sS[kSliceBrems], sK[kSliceBrems];
+    __shared__ double sa[kSliceBrems], ka[kSliceBrems], se[kSliceBrems], ke[kSliceBrems];
     for (int64_t c = blockIdx.x; c < A.n_cells; c += gridDim.x) {
         const double Zs = A.Zs[c], ne = A.ne[c], Te = A.Te[c], gY = A.gY[c];
         const double ni = ne / Zs;
+        const int64_t j1 = A.off[c + 1];
+        int64_t j = A.off[c] + threadIdx.x;
+        double nx = 0.0, ny = 0.0, nz = 0.0, nw = 0.0;
+        if (j < j1) { nx = A.px[j]; ny = A.py[j]; nz = A.pz[j]; nw = A.w[j]; }
         if (threadIdx.x == 0) {
             const phys::Screen s = phys::screening(T.Z, Zs, ni, Te);
             ct_s = cell_tab<R>(s, T.ax);
             J_s = cell_jacobian(s, T.Z, Zs, ne, Te);
         }
         __syncthreads();
-        const CellTab<R> ct = ct_s;
+        {
+            const CellTab<R> ct = ct_s;
+            for (int i = threadIdx.x; i < kSliceBrems; i += kThreads)
+                yield_slice_node<R>(T, ct, i, sS, sK, sa, ka, se, ke);
+        }
+        __syncthreads();
         const CellJac J = J_s;
         double gc[3] = {0.0, 0.0, 0.0};
-        for (int64_t j = A.off[c] + threadIdx.x; j < A.off[c + 1]; j += kThreads) {
-            const double qx = A.px[j], qy = A.py[j], qz = A.pz[j], w = A.w[j];
+        for (; j < j1; j += kThreads) {
+            const double qx = nx, qy = ny, qz = nz, w = nw;
+            if (j + kThreads < j1) {
+                nx = A.px[j + kThreads]; ny = A.py[j + kThreads]; nz = A.pz[j + kThreads]; nw = A.w[j + kThreads];
+            }
             const R px = (R)qx, py = (R)qy, pz = (R)qz;
             const R p2 = px * px + py * py + pz * pz;
             const R g = sqrt((R)1 + p2), gm1 = p2 / (g + (R)1);
-            const BremsGrad<R> L = brems_grad<R>(T, ct, g, gm1);
+            const BremsGrad<R> L = brems_grad<R>(T, sS, sK, sa, ka, se, ke, g, gm1);
             double gx = 0.0, gyv = 0.0, gz = 0.0, gwj = 0.0;
             if (L.sig > 0.0) {
                 const double gd = (double)g, beta = (double)(sqrt(p2) / g);
