@@ -1208,8 +1208,17 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
 
     for (int64_t c = (int64_t)blockIdx.x * kTeams + team; c < A.n_cells; c += (int64_t)gridDim.x * kTeams) {
         const uint32_t cell = (uint32_t)c;
-        if (W.cs[c].status) continue;                       // invalid cell (flagged by k_cell_state)
-        const int Ne = live(A.el, c), Ng = live(A.ph, c), Ni = live(A.io, c);
+        // the cell's parameters in one round of loads: its state, the
+        // offsets and live counts of the three species
+        const int32_t cstat = W.cs[c].status;
+        const CellTab<R> ct_c = pick<R>(W.cs[c]);
+        const int64_t eo0 = A.el.off[c], eo1 = A.el.off[c + 1], go0 = A.ph.off[c], go1 = A.ph.off[c + 1];
+        const int64_t io0 = A.io.off[c], io1 = A.io.off[c + 1];
+        const int ecn = A.el.count ? A.el.count[c] : 0x7FFFFFFF, gcn = A.ph.count ? A.ph.count[c] : 0x7FFFFFFF;
+        const int icn = A.io.count ? A.io.count[c] : 0x7FFFFFFF;
+        if (cstat) continue;                                // invalid cell (flagged by k_cell_state)
+        const int Ne = max(0, min(ecn, (int)(eo1 - eo0))), Ng = max(0, min(gcn, (int)(go1 - go0)));
+        const int Ni = max(0, min(icn, (int)(io1 - io0)));
         // size classes of the hybrid schedule: filter 1 takes the cells up
         // to fcap particles per species, filter 2 the larger ones
         const int mx = max(Ne, max(Ng, Ni));
@@ -1225,7 +1234,7 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
             if (t == 0) mark_slow(W, c);
             continue;
         }
-        const int64_t e0 = A.el.off[c], g0 = A.ph.off[c], i0 = A.io.off[c];
+        const int64_t e0 = eo0, g0 = go0, i0 = io0;
         const bool active = kPass == 0 ? ei : gi;
         const int Nm = kPass == 0 ? Ne : Ng, No = kPass == 0 ? Ng : Ne;
         const int64_t m0 = kPass == 0 ? e0 : g0;
@@ -1244,7 +1253,7 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
         if constexpr (!kMov) {
             if (active && mobA && N <= 4 * kT) {
                 {
-                    const CellTab<R> ct = pick<R>(W.cs[c]);
+                    const CellTab<R> ct = ct_c;
                     if (kPass == 0) {
                         if (A.proc & CMC_BREMS)
                             for (int i = t; i < kSliceBrems; i += kT) slice[i] = slice_node_brems<R>(T, ct, i);

@@ -163,7 +163,7 @@ __device__ CellJac cell_jacobian(const phys::Screen& s, double Z, double Zs, dou
 // staged, and every electron is evaluated with the next one's record in
 // flight.
 template <typename R>
-__global__ __launch_bounds__(kThreads) void k_yield(YArgs A, TabView<R> T) {
+__global__ __launch_bounds__(kThreads, 3) void k_yield(YArgs A, TabView<R> T) {
     __shared__ double red[kWaves];
     __shared__ CellTab<R> ct_s;
     __shared__ R sS[kSliceBrems], sK[kSliceBrems];
@@ -208,8 +208,10 @@ __global__ __launch_bounds__(kThreads) void k_yield(YArgs A, TabView<R> T) {
     }
 }
 
+// Three wavefronts per SIMD: the cell's screening and Jacobian (thread 0,
+// once per cell) then spill a little, the electron loop does not.
 template <typename R>
-__global__ __launch_bounds__(kThreads) void k_yield_bwd(YArgs A, TabView<R> T) {
+__global__ __launch_bounds__(kThreads, 3) void k_yield_bwd(YArgs A, TabView<R> T) {
     __shared__ double red[kWaves];
     __shared__ CellTab<R> ct_s;
     __shared__ CellJac J_s;
@@ -234,8 +236,12 @@ __global__ __launch_bounds__(kThreads) void k_yield_bwd(YArgs A, TabView<R> T) {
                 yield_slice_node<R>(T, ct, i, sS, sK, sa, ka, se, ke);
         }
         __syncthreads();
-        const CellJac J = J_s;
-        double gc[3] = {0.0, 0.0, 0.0};
+        // The cell gradients are linear in the cell's Jacobian: dx/dq and
+        // dK/dq of an electron are n_i and the screening slopes times
+        // d ln n_i/dq, d ln L_D/dq (NR segment), d ln L_R/dq (above) and
+        // d eta_D/dq.  The electrons' coefficients of these four are summed,
+        // and the Jacobian applied once per cell.
+        double a0 = 0.0, aD = 0.0, aR = 0.0, aE = 0.0;
         for (; j < j1; j += kThreads) {
             const double qx = nx, qy = ny, qz = nz, w = nw;
             if (j + kThreads < j1) {
@@ -258,25 +264,30 @@ __global__ __launch_bounds__(kThreads) void k_yield_bwd(YArgs A, TabView<R> T) {
                 const double f = gY * (w * (Pp * dx * K + P * dK)) / gd;
                 gx = f * qx; gyv = f * qy; gz = f * qz;
                 gwj = gY * P * K;
-                for (int q = 0; q < 3; ++q) {
-                    double ds, dk;
-                    if (L.seg == kSegNR) {
-                        ds = L.ds_a * J.dlnLd[q] + L.ds_e * J.deta[q];
-                        dk = L.dk_a * J.dlnLd[q] + L.dk_e * J.deta[q];
-                    } else {
-                        ds = L.ds_a * J.dlnLr[q];
-                        dk = L.dk_a * J.dlnLr[q];
-                    }
-                    const double dxq = x * J.dlnni[q] + ni * beta * phys::kC * A.dt * ds;
-                    const double dKq = (dk * L.sig - L.sk * ds) / (L.sig * L.sig);
-                    gc[q] += gY * w * (Pp * dxq * K + P * dKq);
+                // d(w P K)/dq = w (P' dx/dq K + P dK/dq), dx/dq = x d ln n_i/dq +
+                // n_i beta c dt dsig/dq, dK/dq = dsk/dq / sig - sk dsig/dq / sig^2
+                const double gw_ = gY * w;
+                const double c1 = gw_ * (Pp * K * ni * beta * phys::kC * A.dt - P * L.sk / (L.sig * L.sig));
+                const double c2 = gw_ * P / L.sig;
+                a0 += gw_ * Pp * K * x;
+                const double ta = c1 * L.ds_a + c2 * L.dk_a;
+                if (L.seg == kSegNR) {
+                    aD += ta;
+                    aE += c1 * L.ds_e + c2 * L.dk_e;
+                } else {
+                    aR += ta;
                 }
             }
             A.gpx[j] = gx; A.gpy[j] = gyv; A.gpz[j] = gz;
             if (A.gw) A.gw[j] = gwj;
         }
-        const double s0 = ysum(gc[0], red), s1 = ysum(gc[1], red), s2 = ysum(gc[2], red);
-        if (threadIdx.x == 0) { A.gZs[c] = s0; A.gne[c] = s1; A.gTe[c] = s2; }
+        const double s0 = ysum(a0, red), sD = ysum(aD, red), sR = ysum(aR, red), sE = ysum(aE, red);
+        if (threadIdx.x < 3) {
+            const CellJac& J = J_s;
+            const int q = threadIdx.x;
+            const double gq = s0 * J.dlnni[q] + sD * J.dlnLd[q] + sR * J.dlnLr[q] + sE * J.deta[q];
+            (q == 0 ? A.gZs : q == 1 ? A.gne : A.gTe)[c] = gq;
+        }
         __syncthreads();
     }
 }
