@@ -31,6 +31,15 @@ __device__ double ysum(double v, double* red) {
     return s;
 }
 
+// 1 - exp(-x) for x >= 0: the series to x^6 below 2^-10, where it is
+// -expm1(-x) to within an ulp (the next term is below 2^-70 x), else
+// -expm1(-x).
+__device__ __forceinline__ double one_minus_exp(double x) {
+    if (x < 0x1p-10)
+        return x * (1.0 - x * (0.5 - x * (1.0 / 6 - x * (1.0 / 24 - x * (1.0 / 120 - x * (1.0 / 720))))));
+    return -expm1(-x);
+}
+
 struct YArgs {
     const double *Zs, *ne, *Te, *px, *py, *pz, *w, *gY;
     const int64_t* off;
@@ -190,13 +199,13 @@ __global__ __launch_bounds__(kThreads, 3) void k_yield(YArgs A, TabView<R> T) {
             }
             const R px = (R)qx, py = (R)qy, pz = (R)qz;
             const R p2 = px * px + py * py + pz * pz;
-            const R g = sqrt((R)1 + p2), gm1 = p2 / (g + (R)1);
+            const R g = Fast<R>::sqrt((R)1 + p2), gm1 = Fast<R>::div(p2, g + (R)1);
             const BremsGrad<R> L = brems_grad<R>(T, sS, sK, nullptr, nullptr, nullptr, nullptr, g, gm1);
             double y = 0.0;
             if (L.sig > 0.0) {
-                const double beta = (double)(sqrt(p2) / g);
+                const double beta = (double)Fast<R>::div(Fast<R>::sqrt(p2), g);
                 const double x = ni * L.sig * beta * phys::kC * A.dt;
-                const double P = -expm1(-x);
+                const double P = one_minus_exp(x);
                 y = w * P * (L.sk / L.sig);
             }
             if (A.yp) A.yp[j] = y;
@@ -249,26 +258,28 @@ __global__ __launch_bounds__(kThreads, 3) void k_yield_bwd(YArgs A, TabView<R> T
             }
             const R px = (R)qx, py = (R)qy, pz = (R)qz;
             const R p2 = px * px + py * py + pz * pz;
-            const R g = sqrt((R)1 + p2), gm1 = p2 / (g + (R)1);
+            const R g = Fast<R>::sqrt((R)1 + p2), gm1 = Fast<R>::div(p2, g + (R)1);
             const BremsGrad<R> L = brems_grad<R>(T, sS, sK, sa, ka, se, ke, g, gm1);
             double gx = 0.0, gyv = 0.0, gz = 0.0, gwj = 0.0;
             if (L.sig > 0.0) {
-                const double gd = (double)g, beta = (double)(sqrt(p2) / g);
+                const double gd = (double)g, beta = (double)Fast<R>::div(Fast<R>::sqrt(p2), g);
                 const double x = ni * L.sig * beta * phys::kC * A.dt;
-                const double P = -expm1(-x), Pp = exp(-x), K = L.sk / L.sig;
-                const double du_dg = L.seg == kSegNR ? 1.0 / (double)gm1 : 1.0 / gd;
+                // P' = exp(-x) = 1 - P, without cancellation for x < 1/2
+                const double P = one_minus_exp(x), Pp = x < 0.5 ? 1.0 - P : exp(-x);
+                const double is = 1.0 / L.sig, K = L.sk * is, igd = 1.0 / gd;
+                const double du_dg = L.seg == kSegNR ? 1.0 / (double)gm1 : igd;
                 const double dsig = L.ds_du * du_dg, dsk = L.dk_du * du_dg;
-                const double dbeta = 1.0 / (gd * gd * gd * beta);
+                const double dbeta = igd * igd * igd / beta;
                 const double dx = ni * phys::kC * A.dt * (dsig * beta + L.sig * dbeta);
-                const double dK = (dsk * L.sig - L.sk * dsig) / (L.sig * L.sig);
-                const double f = gY * (w * (Pp * dx * K + P * dK)) / gd;
+                const double dK = (dsk - K * dsig) * is;
+                const double f = gY * (w * (Pp * dx * K + P * dK)) * igd;
                 gx = f * qx; gyv = f * qy; gz = f * qz;
                 gwj = gY * P * K;
                 // d(w P K)/dq = w (P' dx/dq K + P dK/dq), dx/dq = x d ln n_i/dq +
                 // n_i beta c dt dsig/dq, dK/dq = dsk/dq / sig - sk dsig/dq / sig^2
                 const double gw_ = gY * w;
-                const double c1 = gw_ * (Pp * K * ni * beta * phys::kC * A.dt - P * L.sk / (L.sig * L.sig));
-                const double c2 = gw_ * P / L.sig;
+                const double c1 = gw_ * (Pp * K * ni * beta * phys::kC * A.dt - P * K * is);
+                const double c2 = gw_ * P * is;
                 a0 += gw_ * Pp * K * x;
                 const double ta = c1 * L.ds_a + c2 * L.dk_a;
                 if (L.seg == kSegNR) {
