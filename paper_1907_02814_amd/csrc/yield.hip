@@ -40,6 +40,13 @@ __device__ __forceinline__ double one_minus_exp(double x) {
     return -expm1(-x);
 }
 
+// 1/v in the form's precision: v holds an R value
+template <typename R>
+__device__ __forceinline__ double rcp_r(double v) {
+    if constexpr (sizeof(R) == 4) return (double)__builtin_amdgcn_rcpf((float)v);
+    else return 1.0 / v;
+}
+
 struct YArgs {
     const double *Zs, *ne, *Te, *px, *py, *pz, *w, *gY;
     const int64_t* off;
@@ -206,7 +213,7 @@ __global__ __launch_bounds__(kThreads, 3) void k_yield(YArgs A, TabView<R> T) {
                 const double beta = (double)Fast<R>::div(Fast<R>::sqrt(p2), g);
                 const double x = ni * L.sig * beta * phys::kC * A.dt;
                 const double P = one_minus_exp(x);
-                y = w * P * (L.sk / L.sig);
+                y = w * P * (L.sk * rcp_r<R>(L.sig));
             }
             if (A.yp) A.yp[j] = y;
             acc += y;
@@ -266,10 +273,10 @@ __global__ __launch_bounds__(kThreads, 3) void k_yield_bwd(YArgs A, TabView<R> T
                 const double x = ni * L.sig * beta * phys::kC * A.dt;
                 // P' = exp(-x) = 1 - P, without cancellation for x < 1/2
                 const double P = one_minus_exp(x), Pp = x < 0.5 ? 1.0 - P : exp(-x);
-                const double is = 1.0 / L.sig, K = L.sk * is, igd = 1.0 / gd;
-                const double du_dg = L.seg == kSegNR ? 1.0 / (double)gm1 : igd;
+                const double is = rcp_r<R>(L.sig), K = L.sk * is, igd = rcp_r<R>(gd);
+                const double du_dg = L.seg == kSegNR ? rcp_r<R>((double)gm1) : igd;
                 const double dsig = L.ds_du * du_dg, dsk = L.dk_du * du_dg;
-                const double dbeta = igd * igd * igd / beta;
+                const double dbeta = igd * igd * igd * rcp_r<R>(beta);
                 const double dx = ni * phys::kC * A.dt * (dsig * beta + L.sig * dbeta);
                 const double dK = (dsk - K * dsig) * is;
                 const double f = gY * (w * (Pp * dx * K + P * dK)) * igd;
