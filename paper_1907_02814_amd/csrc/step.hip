@@ -22,6 +22,7 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <type_traits>
 
 #include "common.hpp"
 #include "philox.hpp"
@@ -763,6 +764,7 @@ __global__ __launch_bounds__(kThreads) void k_collide(StepArgs A, TabView<R> T, 
 // than the pass kernel's LDS) are redone by k_events with the sequential
 // per-cell step above (collide_cell).
 constexpr int kCandCap = 64;     // open pairs per cell (both passes)
+constexpr int kStagePh = 1024;   // photons the event kernel stages in LDS per cell
 enum : int32_t { kFlagSlow = 1, kFlagListed = 2 };
 enum : uint32_t { kEvBr = 1, kEvTrPending = 2, kEvTr = 4, kEvBh = 8 };
 
@@ -1549,6 +1551,13 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
     __shared__ int ctl[4];        // [0] sequential step, [1] photons converted, [2] first to move, [3] photon count
     __shared__ int wcnt[4][4];    // survivors per chunk group and wavefront
     const Smem S = carve(smem_raw, A.maxn);
+    // staged photons (over S: an item takes either the sequential step or
+    // the event path)
+    double* const stx = reinterpret_cast<double*>(smem_raw);
+    double* const sty = stx + kStagePh;
+    double* const stz = sty + kStagePh;
+    double* const stw = stz + kStagePh;
+    int64_t* const stp = reinterpret_cast<int64_t*>(stw + kStagePh);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int n_items = W.counters[0];
     const double rej = 2.0 * (1.0 + A.near_rel);
@@ -1559,28 +1568,56 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
     for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
         const int64_t c = c_next;
         if (item + (int)gridDim.x < n_items) c_next = W.list_ev[item + gridDim.x];
-        const bool slow = (W.flags[c] & kFlagSlow) != 0;
+        // every per-cell value of the item is read in this one round: each
+        // later round of dependent reads costs the chain about a microsecond
+        const int32_t flg = W.flags[c], ncr = W.ncand[c];
+        const uint64_t raw = W.cand[c * kCandCap + lane];
+        const int64_t g0 = A.ph.off[c], e0 = A.el.off[c], i0 = A.io.off[c];
+        const int Ng0 = live(A.ph, c), Ne = live(A.el, c), Ni = live(A.io, c);
+        const int cap_ph = (int)(A.ph.off[c + 1] - g0);
+        const int64_t ne0 = A.ne.off[c], np0 = A.np.off[c];
+        const int cap_ne = (int)(A.ne.off[c + 1] - ne0), cap_np = (int)(A.np.off[c + 1] - np0);
+        const int cnt_ne0 = A.ne.count[c], cnt_np0 = A.np.count[c];
+        const CellTab<double> ct64 = W.cs[c].d;
+        const CellTab<R> ct = pick<R>(W.cs[c]);
+        const double coef0 = W.coef[c * 2], coef1 = W.coef[c * 2 + 1];
+        const bool slow = (flg & kFlagSlow) != 0;
         // ctl is read by the other wavefronts only after the barrier that
         // ends wavefront 0's work; wavefront 0 may set ctl[0..3] meanwhile
         if (threadIdx.x == 0) { ctl[0] = slow ? 1 : 0; ctl[1] = 0; }
-        const int64_t g0 = A.ph.off[c];
-        const int Ng0 = live(A.ph, c);
+        // while wavefront 0 settles the open pairs, the others copy the
+        // cell's first photons to LDS (when a Bethe-Heitler pair is open):
+        // the removal of converted photons then reads them from there
+        const bool bh_open = __ballot(lane < min(ncr, kCandCap) && ev_pass(raw) == 1) != 0ull;
+        const int n_st = (!slow && bh_open) ? min(Ng0, kStagePh) : 0;
+        if (wv != 0 && n_st > 0) {
+            constexpr int kPer = (kStagePh + kThreads - 65) / (kThreads - 64);
+            double vx[kPer], vy[kPer], vz[kPer], vw[kPer];
+            int64_t vp[kPer];
+#pragma unroll
+            for (int k = 0; k < kPer; ++k) {
+                // clamped into the live photons: every load is issued at once
+                const int64_t at = g0 + min((int)threadIdx.x - 64 + k * (kThreads - 64), n_st - 1);
+                vx[k] = A.ph.px[at]; vy[k] = A.ph.py[at]; vz[k] = A.ph.pz[at]; vw[k] = A.ph.w[at];
+                vp[k] = A.ph.parent ? A.ph.parent[at] : -1;
+            }
+#pragma unroll
+            for (int k = 0; k < kPer; ++k) {
+                const int a = (int)threadIdx.x - 64 + k * (kThreads - 64);
+                if (a < n_st) { stx[a] = vx[k]; sty[a] = vy[k]; stz[a] = vz[k]; stw[a] = vw[k]; stp[a] = vp[k]; }
+            }
+        }
         if (wv == 0 && !slow) do {
             const uint32_t cell = (uint32_t)c;
-            const int nc = min(W.ncand[c], kCandCap);
-            const int64_t e0 = A.el.off[c], i0 = A.io.off[c];
-            const int Ne = live(A.el, c), Ni = live(A.io, c);
-            const uint64_t raw = W.cand[c * kCandCap + lane];
+            const int nc = min(ncr, kCandCap);
             // ---- the open pairs in (pass, pair index) order, one per lane
             {
                 const bool has = lane < nc;
                 const unsigned long long hb = __ballot(has);
                 const uint32_t key = has ? ev_key(raw) : 0xFFFFFFFFu;
                 int rank = 0;
-                for (int l = 0; l < 64; ++l) {
-                    if (!((hb >> l) & 1ull)) continue;
-                    rank += __shfl(key, l, 64) < key;
-                }
+                for (unsigned long long m = hb; m; m &= m - 1ull)
+                    rank += (uint32_t)__builtin_amdgcn_readlane((int)key, __ffsll((long long)m) - 1) < key;
                 if (has) rec[rank] = raw;
                 Team<64>::sync();
             }
@@ -1590,7 +1627,6 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
             const int j = ev_j(mine), mi = ev_m(mine), ii = ev_i(mine);
             // the pair's draws: keyed by its mobile particle when that species pairs once
             const uint32_t dk = (uint32_t)((pass == 0 ? Ne >= Ni : Ng0 >= Ni) ? mi : j);
-            const CellTab<double> ct64 = W.cs[c].d;
             // ---- settle them; the particle and the FP64 lookup stay in the
             // lane for the sampling
             uint32_t kind = 0;
@@ -1603,8 +1639,7 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
             int ikd = 0; double wkd = 0.0;
             if (cand) {
                 const uint32_t bits = ev_kind(mine);
-                const CellTab<R> ct = pick<R>(W.cs[c]);
-                const double coef = W.coef[c * 2 + pass];
+                const double coef = pass == 0 ? coef0 : coef1;
                 Wi = A.io.w[i0 + ii];
                 b = ion_at(A.io, i0 + ii);
                 if (pass == 0) {
@@ -1656,9 +1691,6 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
             // ---- the events, lanes in (pass, pair index) order
             const int n = __popcll(__ballot(kind != 0));
             const uint32_t evk = kind;
-            const int cap_ph = (int)(A.ph.off[c + 1] - g0);
-            const int cap_ne = (int)(A.ne.off[c + 1] - A.ne.off[c]), cap_np = (int)(A.np.off[c + 1] - A.np.off[c]);
-            const int cnt_ne0 = A.ne.count[c], cnt_np0 = A.np.count[c];
             Tally t = {};
             t.near_br = near_br; t.near_tr = near_tr; t.near_bh = near_bh;
             bool f_ph = false, f_tr = false, f_bh = false;
@@ -1711,7 +1743,7 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
                                             : electron_p<R>(px, py, pz);
                     const R sig = (R)phys::trident_sigma(T.Z, (double)e.g);
                     if (sig > (R)0) {
-                        const double x = W.coef[c * 2] * (double)sig * e.vrel * A.dt;
+                        const double x = coef0 * (double)sig * e.vrel * A.dt;
                         const double P = -expm1(-x);
                         const U4 q = rng.draw(dk, cell, kTagAccTr);
                         const double U1 = u53(q.x, q.y), U2 = u53(q.z, q.w);
@@ -1781,12 +1813,12 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
             if (f_tr || f_bh) {
                 const int o = f_tr ? __popcll(b_tr & below) : n_tr + __popcll(b_bh & below);
                 if (cnt_ne0 + o < cap_ne) {
-                    const int64_t at = A.ne.off[c] + cnt_ne0 + o;
+                    const int64_t at = ne0 + cnt_ne0 + o;
                     A.ne.px[at] = pxm; A.ne.py[at] = pym; A.ne.pz[at] = pzm; A.ne.w[at] = Wm;
                     if (A.ne.parent) A.ne.parent[at] = par;
                 } else t.drop_el++;
                 if (cnt_np0 + o < cap_np) {
-                    const int64_t at = A.np.off[c] + cnt_np0 + o;
+                    const int64_t at = np0 + cnt_np0 + o;
                     A.np.px[at] = pxp; A.np.py[at] = pyp; A.np.pz[at] = pzp; A.np.w[at] = Wm;
                     if (A.np.parent) A.np.parent[at] = par;
                 } else t.drop_po++;
@@ -1803,14 +1835,21 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
                 for (int o = 32; o > 0; o >>= 1) first = min(first, __shfl_xor(first, o, 64));
                 if (lane == 0) { ctl[1] = n_bh; ctl[2] = first & ~63; ctl[3] = ph_count; }
             }
-            // tallies of the events (the pair counts were written by the passes)
-            // (a lane holds one open pair: its counts are small)
-            long long iv[9] = {t.ev_br, t.ev_tr, t.ev_bh, t.near_br, t.near_tr, t.near_bh, t.drop_ph, t.drop_el, t.drop_po};
-            double dv[8] = {t.E_br, t.E_tr, t.E_bh, t.dE_el, t.dE_ph, t.W_br, t.W_tr, t.W_bh};
-#pragma unroll
-            for (int q = 0; q < 9; ++q) iv[q] = wave_sum_i32((int)iv[q]);
-#pragma unroll
-            for (int q = 0; q < 8; ++q) dv[q] = wave_sum(dv[q]);
+            // tallies of the events (the pair counts were written by the
+            // passes).  A lane holds one open pair: each of its counts is 0 or
+            // 1 (one event of a kind, one near-threshold test of a process,
+            // one product of a kind), and only lanes with an event carry
+            // energies and weights, which are added lane by lane in pair order.
+            const auto count = [](long long v) { return (long long)__popcll(__ballot(v != 0)); };
+            const long long iv[9] = {count(t.ev_br), count(t.ev_tr), count(t.ev_bh), count(t.near_br), count(t.near_tr),
+                                     count(t.near_bh), count(t.drop_ph), count(t.drop_el), count(t.drop_po)};
+            double dv[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            for (unsigned long long m = __ballot(f_ph || f_tr || f_bh); m; m &= m - 1ull) {
+                const int e = __ffsll((long long)m) - 1;
+                dv[0] += lane_f64(t.E_br, e); dv[1] += lane_f64(t.E_tr, e); dv[2] += lane_f64(t.E_bh, e);
+                dv[3] += lane_f64(t.dE_el, e); dv[4] += lane_f64(t.dE_ph, e);
+                dv[5] += lane_f64(t.W_br, e); dv[6] += lane_f64(t.W_tr, e); dv[7] += lane_f64(t.W_bh, e);
+            }
             if (lane == 0) {
                 int64_t* ti = A.ti + c * CMC_NI;
                 ti[CMC_I_EV_BR] = iv[0]; ti[CMC_I_EV_TR] = iv[1]; ti[CMC_I_EV_BH] = iv[2];
@@ -1837,8 +1876,9 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
             // yet read), the chunk counts give every survivor its slot
             const int end = ctl[3];
             const unsigned long long below = (1ull << lane) - 1ull;
-            int wpos = ctl[2];
-            for (int base = ctl[2]; base < end; base += 1024) {
+            // one group; with every photon of it staged no global read is
+            // made, so the wavefronts never wait for the product writes
+            const auto group = [&](int base, int wpos, auto staged) {
                 double vx[4], vy[4], vz[4], vw[4];
                 int64_t pp[4];
                 bool keep[4];
@@ -1849,7 +1889,9 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
                     keep[u] = a < end && !(a < Ng0 && ((killed[a >> 5] >> (a & 31)) & 1u));
                     vx[u] = vy[u] = vz[u] = vw[u] = 0.0;
                     pp[u] = -1;
-                    if (keep[u]) {
+                    if (keep[u] && (decltype(staged)::value || a < n_st)) {
+                        vx[u] = stx[a]; vy[u] = sty[a]; vz[u] = stz[a]; vw[u] = stw[a]; pp[u] = stp[a];
+                    } else if (!decltype(staged)::value && keep[u]) {
                         vx[u] = A.ph.px[g0 + a]; vy[u] = A.ph.py[g0 + a]; vz[u] = A.ph.pz[g0 + a]; vw[u] = A.ph.w[g0 + a];
                         if (A.ph.parent) pp[u] = A.ph.parent[g0 + a];
                     }
@@ -1868,9 +1910,13 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
                         if (A.ph.parent) A.ph.parent[dst] = pp[u];
                     }
                 }
-                wpos = at;
                 __syncthreads();
-            }
+                return at;
+            };
+            int wpos = ctl[2];
+            for (int base = ctl[2]; base < end; base += 1024)
+                wpos = (base + 1024 <= n_st || end <= n_st) ? group(base, wpos, std::true_type{})
+                                                            : group(base, wpos, std::false_type{});
             if (threadIdx.x == 0 && A.ph.count) A.ph.count[c] = wpos;
         }
         __syncthreads();   // every read of ctl and of the LDS lists precedes the next cell
@@ -2204,12 +2250,13 @@ extern "C" cmc_status cmc_collide_step(cmc_tables t, const cmc_cells* cells, cmc
     // the listed cells: open pairs and events, or the sequential step (a
     // short list: a small grid)
     const unsigned gev = (unsigned)std::min<int64_t>(A.n_cells, 512);
+    const size_t shm_ev = std::max(shm, (size_t)kStagePh * 40);
     if (fp64) {
-        lds_attr((const void*)k_events<double>, shm, st);
-        hipLaunchKernelGGL(k_events<double>, dim3(gev), dim3(kThreads), shm, st, A, view64(t), view64(t), W);
+        lds_attr((const void*)k_events<double>, shm_ev, st);
+        hipLaunchKernelGGL(k_events<double>, dim3(gev), dim3(kThreads), shm_ev, st, A, view64(t), view64(t), W);
     } else {
-        lds_attr((const void*)k_events<float>, shm, st);
-        hipLaunchKernelGGL(k_events<float>, dim3(gev), dim3(kThreads), shm, st, A, view32(t), view64(t), W);
+        lds_attr((const void*)k_events<float>, shm_ev, st);
+        hipLaunchKernelGGL(k_events<float>, dim3(gev), dim3(kThreads), shm_ev, st, A, view32(t), view64(t), W);
     }
     CMC_CHECK_LAUNCH("cmc_collide_step: k_events");
     return CMC_OK;
