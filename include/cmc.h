@@ -97,7 +97,8 @@ cmc_status cmc_tables_export(cmc_tables t, int32_t which, double* dst, int64_t n
 /* ------------------------------------------------------------------ */
 /* Particle layout: structure of arrays, grouped by cell.  Cell c owns   */
 /* positions [off[c], off[c+1]) of every array of the species; the first */
-/* count[c] of them are live (count == NULL: all of them).               */
+/* count[c] of them are live (count == NULL: all of them).  The others   */
+/* hold no particle: a step may leave any value there.                   */
 /* ------------------------------------------------------------------ */
 typedef struct {
     int64_t n_cells;

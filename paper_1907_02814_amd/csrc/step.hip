@@ -1550,6 +1550,7 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
     __shared__ uint32_t killed[CMC_MAX_PER_CELL / 32];
     __shared__ int ctl[4];        // [0] sequential step, [1] photons converted, [2] first to move, [3] photon count
     __shared__ int wcnt[4][4];    // survivors per chunk group and wavefront
+    __shared__ int kpre[kStagePh / 32];   // converted photons before each bitmap word
     const Smem S = carve(smem_raw, A.maxn);
     // staged photons (over S: an item takes either the sequential step or
     // the event path)
@@ -1607,9 +1608,24 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
                 if (a < n_st) { stx[a] = vx[k]; sty[a] = vy[k]; stz[a] = vz[k]; stw[a] = vw[k]; stp[a] = vp[k]; }
             }
         }
-        if (wv == 0 && !slow) do {
-            const uint32_t cell = (uint32_t)c;
-            const int nc = min(ncr, kCandCap);
+        // Wavefront 0 settles the open pairs; its lanes keep the pair's
+        // particle, ion and FP64 lookup for the sampling after the barrier.
+        const uint32_t cell = (uint32_t)c;
+        const int nc = min(ncr, kCandCap);
+        const bool cand = lane < nc;
+        uint64_t mine = 0ull;
+        int pass = 2, j = 0, mi = 0, ii = 0;
+        uint32_t dk = 0, kind = 0;
+        int near_br = 0, near_tr = 0, near_bh = 0;
+        double px = 0, py = 0, pz = 0, Wm = 0, Wi = 0;
+        Ion b{0.0, 0.0, 0.0, 1.0, false};
+        Frame fr = {};   // the mobile particle seen from the ion
+        BremsLook<double> BLd = {};
+        int ikd = 0; double wkd = 0.0;
+        // with every live photon staged, the survivors of a conversion are
+        // moved by wavefronts 1-3 while wavefront 0 samples the events
+        const bool staged_all = n_st == Ng0;
+        if (wv == 0 && !slow) {
             // ---- the open pairs in (pass, pair index) order, one per lane
             {
                 const bool has = lane < nc;
@@ -1621,22 +1637,13 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
                 if (has) rec[rank] = raw;
                 Team<64>::sync();
             }
-            const bool cand = lane < nc;
-            const uint64_t mine = cand ? rec[lane] : 0ull;
-            const int pass = cand ? ev_pass(mine) : 2;
-            const int j = ev_j(mine), mi = ev_m(mine), ii = ev_i(mine);
+            mine = cand ? rec[lane] : 0ull;
+            pass = cand ? ev_pass(mine) : 2;
+            j = ev_j(mine); mi = ev_m(mine); ii = ev_i(mine);
             // the pair's draws: keyed by its mobile particle when that species pairs once
-            const uint32_t dk = (uint32_t)((pass == 0 ? Ne >= Ni : Ng0 >= Ni) ? mi : j);
-            // ---- settle them; the particle and the FP64 lookup stay in the
-            // lane for the sampling
-            uint32_t kind = 0;
-            int near_br = 0, near_tr = 0, near_bh = 0;
+            dk = (uint32_t)((pass == 0 ? Ne >= Ni : Ng0 >= Ni) ? mi : j);
+            // ---- settle them
             bool reused = false;
-            double px = 0, py = 0, pz = 0, Wm = 0, Wi = 0;
-            Ion b{0.0, 0.0, 0.0, 1.0, false};
-            Frame fr = {};   // the mobile particle seen from the ion
-            BremsLook<double> BLd = {};
-            int ikd = 0; double wkd = 0.0;
             if (cand) {
                 const uint32_t bits = ev_kind(mine);
                 const double coef = pass == 0 ? coef0 : coef1;
@@ -1686,8 +1693,44 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
             // cell is redone by the sequential step below
             if (__ballot(kind != 0 && reused) != 0ull) {
                 if (lane == 0) ctl[0] = 1;
-                break;
+            } else {
+                const bool conv = pass == 1 && (kind & kEvBh);
+                const unsigned long long b_cv = __ballot(conv);
+                if (b_cv) {
+                    // converted photons: a bitmap, and for the staged case the
+                    // count before each of its words
+                    const int words = (Ng0 + 31) / 32;
+                    for (int i = lane; i < words; i += 64) killed[i] = 0u;
+                    Team<64>::sync();
+                    if (conv) atomicOr(&killed[mi >> 5], 1u << (mi & 31));
+                    Team<64>::sync();
+                    if (staged_all) {
+                        const int v = lane < words ? __popc(killed[lane]) : 0;
+                        int incl = v;
+#pragma unroll
+                        for (int o = 1; o < 32; o <<= 1) {
+                            const int y = __shfl_up(incl, o, 64);
+                            if (lane >= o) incl += y;
+                        }
+                        if (lane < words) kpre[lane] = incl - v;
+                    }
+                    // photons before the first converted one stay where they are
+                    int first = conv ? mi : 0x7FFFFFFF;
+#pragma unroll
+                    for (int o = 32; o > 0; o >>= 1) first = min(first, __shfl_xor(first, o, 64));
+                    const int n_new = __popcll(__ballot(pass == 0 && (kind & kEvBr)));
+                    if (lane == 0) { ctl[1] = __popcll(b_cv); ctl[2] = first; ctl[3] = min(cap_ph, Ng0 + n_new); }
+                }
             }
+        }
+        __syncthreads();   // ctl, the bitmap and the staged photons
+        if (ctl[0]) {
+            collide_cell<R>(A, T, T64, rng, c, S, sh);
+            __syncthreads();
+            continue;
+        }
+        const int n_conv = ctl[1];
+        if (wv == 0 && !slow) do {
             // ---- the events, lanes in (pass, pair index) order
             const int n = __popcll(__ballot(kind != 0));
             const uint32_t evk = kind;
@@ -1802,10 +1845,13 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
             const unsigned long long b_ph = __ballot(f_ph), b_tr = __ballot(f_tr), b_bh = __ballot(f_bh);
             const unsigned long long below = (1ull << lane) - 1ull;
             const int n_ph = __popcll(b_ph), n_tr = __popcll(b_tr), n_bh = __popcll(b_bh);
+            // with every photon staged the converted ones are removed beside
+            // this: the new photons go straight to their final slots
+            const int shift = staged_all ? n_conv : 0;
             if (f_ph) {
                 const int slot = Ng0 + __popcll(b_ph & below);
                 if (slot < cap_ph) {
-                    const int64_t at = g0 + slot;
+                    const int64_t at = g0 + slot - shift;
                     A.ph.px[at] = kx; A.ph.py[at] = ky; A.ph.pz[at] = kz; A.ph.w[at] = Wm;
                     if (A.ph.parent) A.ph.parent[at] = par;
                 } else t.drop_ph++;
@@ -1823,18 +1869,7 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
                     if (A.np.parent) A.np.parent[at] = par;
                 } else t.drop_po++;
             }
-            int ph_count = min(cap_ph, Ng0 + n_ph);
-            if (n_bh) {
-                // converted photons: a bitmap for the four wavefronts
-                for (int i = lane; i < (Ng0 + 31) / 32; i += 64) killed[i] = 0u;
-                Team<64>::sync();
-                if (f_bh) atomicOr(&killed[mi >> 5], 1u << (mi & 31));
-                // photons before the first converted one stay where they are
-                int first = f_bh ? mi : 0x7FFFFFFF;
-#pragma unroll
-                for (int o = 32; o > 0; o >>= 1) first = min(first, __shfl_xor(first, o, 64));
-                if (lane == 0) { ctl[1] = n_bh; ctl[2] = first & ~63; ctl[3] = ph_count; }
-            }
+            const int ph_count = min(cap_ph, Ng0 + n_ph) - shift;
             // tallies of the events (the pair counts were written by the
             // passes).  A lane holds one open pair: each of its counts is 0 or
             // 1 (one event of a kind, one near-threshold test of a process,
@@ -1857,19 +1892,26 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
                 ti[CMC_I_DROP_PH] = iv[6]; ti[CMC_I_DROP_EL] = iv[7]; ti[CMC_I_DROP_PO] = iv[8];
                 double* td = A.td + c * CMC_ND + CMC_D_E_BR;
                 for (int q = 0; q < 8; ++q) td[q] = dv[q];
-                if (A.ph.count && !n_bh) A.ph.count[c] = ph_count;
+                if (A.ph.count && (!n_bh || staged_all)) A.ph.count[c] = ph_count;
                 A.ne.count[c] = min(cap_ne, cnt_ne0 + n_tr + n_bh);
                 A.np.count[c] = min(cap_np, cnt_np0 + n_tr + n_bh);
                 if (iv[6] + iv[7] + iv[8]) atomicOr(A.status, CMC_ST_OVERFLOW);
             }
         } while (0);
-        __syncthreads();
-        if (ctl[0]) {
-            collide_cell<R>(A, T, T64, rng, c, S, sh);
-            __syncthreads();
-            continue;
+        if (wv != 0 && n_conv && staged_all) {
+            // each survivor at or after the first converted photon moves down
+            // by the converted photons before it, read from LDS: no photon is
+            // read from global memory, so the moves need no ordering
+            for (int a = ctl[2] + (int)threadIdx.x - 64; a < Ng0; a += kThreads - 64) {
+                const uint32_t kw = killed[a >> 5];
+                if ((kw >> (a & 31)) & 1u) continue;
+                const int64_t dst = g0 + a - (kpre[a >> 5] + __popc(kw & ((1u << (a & 31)) - 1u)));
+                A.ph.px[dst] = stx[a]; A.ph.py[dst] = sty[a]; A.ph.pz[dst] = stz[a]; A.ph.w[dst] = stw[a];
+                if (A.ph.parent) A.ph.parent[dst] = stp[a];
+            }
         }
-        if (ctl[1]) {
+        __syncthreads();
+        if (n_conv && !staged_all) {
             // stable in-place removal of the converted photons: each
             // wavefront reads four chunks of 64 of a group of 1024 before any
             // is written (a survivor only moves down, never into a chunk not
@@ -1913,8 +1955,8 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
                 __syncthreads();
                 return at;
             };
-            int wpos = ctl[2];
-            for (int base = ctl[2]; base < end; base += 1024)
+            int wpos = ctl[2] & ~63;
+            for (int base = ctl[2] & ~63; base < end; base += 1024)
                 wpos = (base + 1024 <= n_st || end <= n_st) ? group(base, wpos, std::true_type{})
                                                             : group(base, wpos, std::false_type{});
             if (threadIdx.x == 0 && A.ph.count) A.ph.count[c] = wpos;
