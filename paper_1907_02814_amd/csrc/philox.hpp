@@ -35,7 +35,12 @@ enum : uint32_t {
 struct Rng {
     uint32_t k0, k1, step_lo, step_hi;
     __device__ __forceinline__ U4 draw(uint32_t x, uint32_t cell, uint32_t tag) const {
-        return philox4x32_10(x, cell, step_lo, (tag << 24) | (step_hi & 0xFFFFFFu), k0, k1);
+        // The round keys are derived from (k0, k1) inside each draw: hoisted
+        // out of a loop of draws they would be twenty live scalar registers,
+        // more than a kernel with other uniform state keeps.
+        uint32_t a = k0, b = k1;
+        asm volatile("" : "+s"(a), "+s"(b));
+        return philox4x32_10(x, cell, step_lo, (tag << 24) | (step_hi & 0xFFFFFFu), a, b);
     }
 };
 

@@ -1151,6 +1151,15 @@ __device__ __forceinline__ TeamMem carve_team(unsigned char* p, int cap, int rby
 
 // one test settled with P = -expm1(-x) in FP64: the near-threshold count,
 // then the event iff U1 < P and U2 < P_ej
+// The pass kernels' bound test of a pair, in FP32.  It passes every pair
+// whose exact test could hold (an event needs U1 < P, the near band
+// U1 <= (1 + near_rel) P, and P = 1 - exp(-x) <= x): the top 24 bits of the
+// draw's first word are at most 2^24 U1, and xs, 2^24 rej x formed from a few
+// FP32 roundings, stays far above 2^24 (1 + near_rel) x since rej is twice
+// 1 + near_rel.  The event kernel settles the pairs it passes in FP64 and
+// applies the FP64 bound again.
+__device__ __forceinline__ bool bound24(uint32_t rx, float xs) { return (float)(rx >> 8) <= xs; }
+
 __device__ __forceinline__ bool settle(double x, const U4& r, double rej, double near_rel, double Pej, int& near) {
     const double U1 = u53(r.x, r.y);
     if (!(U1 <= rej * x)) return false;
@@ -1299,6 +1308,7 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
                     int high = 0;
                     if (nab > 0.0) {
                         const double coef = v4[0] * v4[2] / nab;
+                        const float kx = (float)(coef * A.dt * rej * 16777216.0);
                         // one pair at a time (the tests do not overlap in
                         // registers), the next pair's momenta in flight
 #pragma unroll 1
@@ -1315,17 +1325,15 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
                                     const R sig = brems_sig_slice<R>(T, slice, e.g, e.gm1, hi);
                                     high |= hi;
                                     if (sig > (R)0) {
-                                        const double x = coef * (double)sig * e.vrel * A.dt;
                                         const U4 r = rng.draw((uint32_t)q, cell, kTagAccBr);
-                                        if (u53(r.x, r.y) <= rej * x) bits = 1u;
+                                        if (bound24(r.x, kx * (float)sig * (float)e.vrel)) bits = 1u;
                                     }
                                 }
                                 if ((A.proc & CMC_TRIDENT) && !bits) {
                                     const R sig = (R)phys::trident_sigma(T.Z, (double)e.g);
                                     if (sig > (R)0) {
-                                        const double x = coef * (double)sig * e.vrel * A.dt;
                                         const U4 r = rng.draw((uint32_t)q, cell, kTagAccTr);
-                                        if (u53(r.x, r.y) <= rej * x) bits = 2u;
+                                        if (bound24(r.x, kx * (float)sig * (float)e.vrel)) bits = 2u;
                                     }
                                 }
                             } else {
@@ -1333,9 +1341,8 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
                                 const R sig = bh_sig_slice<R>(T, slice, photon_k<R>(cx, cy, cz), hi);
                                 high |= hi;
                                 if (sig > (R)0) {
-                                    const double x = coef * (double)sig * phys::kC * A.dt;
                                     const U4 r = rng.draw((uint32_t)q, cell, kTagAccBh);
-                                    if (u53(r.x, r.y) <= rej * x) bits = 1u;
+                                    if (bound24(r.x, kx * (float)sig * (float)phys::kC)) bits = 1u;
                                 }
                             }
                             if (bits) {
@@ -1442,6 +1449,7 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
         int high = 0;
         if (nab > 0.0) {
             const double coef = v4[0] * v4[2] / nab;
+            const float kx = (float)(coef * A.dt * rej * 16777216.0);
             for (int q = t; q < N; q += kT) {
                 const int j = mobA ? (mob_order ? (int)M.ordM[q] : 0) : q;
                 const int mi = mobA ? q : mob_of(j);
@@ -1464,17 +1472,15 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
                         const R sig = brems_sig_slice<R>(T, slice, e.g, e.gm1, hi);
                         high |= hi;
                         if (sig > (R)0) {
-                            const double x = coef * (double)sig * e.vrel * A.dt;
                             const U4 r = rng.draw(dk, cell, kTagAccBr);
-                            if (u53(r.x, r.y) <= rej * x) bits = 1u;
+                            if (bound24(r.x, kx * (float)sig * (float)e.vrel)) bits = 1u;
                         }
                     }
                     if ((A.proc & CMC_TRIDENT) && !bits) {
                         const R sig = (R)phys::trident_sigma(T.Z, (double)e.g);
                         if (sig > (R)0) {
-                            const double x = coef * (double)sig * e.vrel * A.dt;
                             const U4 r = rng.draw(dk, cell, kTagAccTr);
-                            if (u53(r.x, r.y) <= rej * x) bits = 2u;
+                            if (bound24(r.x, kx * (float)sig * (float)e.vrel)) bits = 2u;
                         }
                     }
                 } else {
@@ -1491,9 +1497,8 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
                     const R sig = bh_sig_slice<R>(T, slice, k, hi);
                     high |= hi;
                     if (sig > (R)0) {
-                        const double x = coef * (double)sig * flux * A.dt;
                         const U4 r = rng.draw(dk, cell, kTagAccBh);
-                        if (u53(r.x, r.y) <= rej * x) bits = 1u;
+                        if (bound24(r.x, kx * (float)sig * (float)flux)) bits = 1u;
                     }
                 }
                 if (bits) {
