@@ -935,8 +935,27 @@ static void draw(uint64_t seed, uint64_t step, uint32_t cell, uint32_t x, uint32
 }
 
 enum { TAG_KEY_E = 0x01, TAG_KEY_IE = 0x02, TAG_KEY_G = 0x03, TAG_KEY_IG = 0x04,
-       TAG_ACC_BR = 0x11, TAG_SMP_BR = 0x12, TAG_ACC_TR = 0x21, TAG_SMP_TR = 0x22,
-       TAG_ACC_BH = 0x31, TAG_SMP_BH = 0x32 };
+       TAG_ACC_BR = 0x11, TAG_SMP_BR = 0x12, TAG_HI_BR = 0x13,
+       TAG_ACC_TR = 0x21, TAG_SMP_TR = 0x22, TAG_HI_TR = 0x23,
+       TAG_ACC_BH = 0x31, TAG_SMP_BH = 0x32, TAG_HI_BH = 0x33 };
+
+/* The two uniforms of a pair's acceptance test, eq:proba3 (U1 against P,  */
+/* U2 against W_ion/max(W_mobile, W_ion)), for the pair whose numbers are  */
+/* keyed by x.  Reading (the paper fixes no generator): U1 has 53 random   */
+/* bits, the upper 32 of them word ((x >> 8) & 3) of the draw with the    */
+/* process's "hi" tag keyed by ((x >> 10) << 8) | (x & 255), so that four */
+/* pairs share one draw, the lower 21 the top bits of word 0 of the       */
+/* pair's own draw with the acceptance tag; U2 is u53 of words 2 and 3 of */
+/* that draw.                                                              */
+void or_accept_uniforms(uint64_t seed, uint64_t step, uint32_t cell, uint32_t x, uint32_t tag,
+                        uint32_t tag_hi, double* U1, double* U2)
+{
+    uint32_t h[4], r[4];
+    draw(seed, step, cell, ((x >> 10) << 8) | (x & 255u), tag_hi, h);
+    draw(seed, step, cell, x, tag, r);
+    *U1 = ((double)h[(x >> 8) & 3u] * 2097152.0 + (double)(r[0] >> 11)) * (1.0 / 9007199254740992.0);
+    *U2 = or_u53(r[2], r[3]);
+}
 
 /* ------------------------------------------------------------------ */
 /* Pairing, Sec. III.A: N = max(N_a, N_b) macro-pairs, each drawn     */
@@ -1166,8 +1185,9 @@ static int32_t cell_step(const stepctx* X, const or_cells* cells, int64_t c, int
                 double x = coef * sig * (CLIGHT * pm / (ge * gi)) * X->dt;
                 double P = -expm1(-x);
                 uint32_t r[4];
-                draw(X->seed, X->step, cell, dkey, proc == 0 ? TAG_ACC_BR : TAG_ACC_TR, r);
-                double U1 = or_u53(r[0], r[1]), U2 = or_u53(r[2], r[3]);
+                double U1, U2;
+                or_accept_uniforms(X->seed, X->step, cell, dkey, proc == 0 ? TAG_ACC_BR : TAG_ACC_TR,
+                                proc == 0 ? TAG_HI_BR : TAG_HI_TR, &U1, &U2);
                 if (fabs(U1 - P) <= X->near_rel * P) ti[proc == 0 ? OR_I_NEAR_BR : OR_I_NEAR_TR]++;
                 if (!(U1 < P && U2 < Pej)) continue;
                 draw(X->seed, X->step, cell, dkey, proc == 0 ? TAG_SMP_BR : TAG_SMP_TR, r);
@@ -1268,8 +1288,8 @@ static int32_t cell_step(const stepctx* X, const or_cells* cells, int64_t c, int
             double x = coef * sig * (CLIGHT * kp / (k * gi)) * X->dt;
             double P = -expm1(-x);
             uint32_t r[4];
-            draw(X->seed, X->step, cell, dkey, TAG_ACC_BH, r);
-            double U1 = or_u53(r[0], r[1]), U2 = or_u53(r[2], r[3]);
+            double U1, U2;
+            or_accept_uniforms(X->seed, X->step, cell, dkey, TAG_ACC_BH, TAG_HI_BH, &U1, &U2);
             if (fabs(U1 - P) <= X->near_rel * P) ti[OR_I_NEAR_BH]++;
             if (!(U1 < P && U2 < Pej)) continue;
             draw(X->seed, X->step, cell, dkey, TAG_SMP_BH, r);

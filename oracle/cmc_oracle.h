@@ -90,6 +90,9 @@ double or_dsdgp_trident(double Z, double g1, double gpair);
 double or_split_shape(double gpair, double gplus);
 void   or_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 double or_u53(uint32_t a, uint32_t b);
+/* U1 and U2 of the acceptance test of the pair keyed by x (see the .c file) */
+void or_accept_uniforms(uint64_t seed, uint64_t step, uint32_t cell, uint32_t x, uint32_t tag,
+                        uint32_t tag_hi, double* U1, double* U2);
 /* Sec. III.A boost to / from the rest frame of an ion of proper velocity
  * u = gamma_i beta_i: out = (E', p') and p (momentum only) */
 void   or_to_ion(const double u[3], double E, const double p[3], double out[4]);

@@ -72,6 +72,7 @@ def lib():
         L.or_split_shape.argtypes = [d, d]; L.or_split_shape.restype = d
         L.or_philox.argtypes = [_u32p, _u32p, _u32p]
         L.or_u53.argtypes = [u32, u32]; L.or_u53.restype = d
+        L.or_accept_uniforms.argtypes = [u64, u64, u32, u32, u32, u32, _dp, _dp]
         L.or_to_ion.argtypes = [_dp, d, _dp, _dp]
         L.or_from_ion.argtypes = [_dp, d, _dp, _dp]
         L.or_lookup.argtypes = [vp, d, d, d, d, C.c_int, _dp]
@@ -189,6 +190,18 @@ def from_ion(u, Ep, pp):
 
 def u53(a, b):
     return lib().or_u53(int(a), int(b))
+
+
+# tags of the acceptance draws: (pair's own draw, shared draw of U1's upper bits)
+ACC_TAGS = {"br": (0x11, 0x13), "tr": (0x21, 0x23), "bh": (0x31, 0x33)}
+
+
+def accept_uniforms(seed, step, cell, x, proc="bh"):
+    """(U1, U2) of the acceptance test of the pair keyed by x."""
+    u1, u2 = C.c_double(), C.c_double()
+    tag, tag_hi = ACC_TAGS[proc]
+    lib().or_accept_uniforms(int(seed), int(step), int(cell), int(x), tag, tag_hi, C.byref(u1), C.byref(u2))
+    return u1.value, u2.value
 
 
 # ---------------------------------------------------------------- tables

@@ -528,8 +528,9 @@ __device__ __forceinline__ void collide_cell(const StepArgs& A, const TabView<R>
                         // eq:proba3 with gamma' v' = c |p'| (eq:proba2)
                         const double x = coef * (double)sig * e.vrel * A.dt;
                         const double P = -expm1(-x);
-                        const U4 r = rng.draw(dk, cell, proc == 0 ? kTagAccBr : kTagAccTr);
-                        const double U1 = u53(r.x, r.y), U2 = u53(r.z, r.w);
+                        double U1, U2;
+                        accept_uniforms(rng, dk, cell, proc == 0 ? kTagAccBr : kTagAccTr, proc == 0 ? kTagHiBr : kTagHiTr,
+                                        U1, U2);
                         if (fabs(U1 - P) <= A.near_rel * P) { if (proc == 0) t.near_br++; else t.near_tr++; }
                         if (!(U1 < P && U2 < Pej)) continue;
                         const U4 q = rng.draw(dk, cell, proc == 0 ? kTagSmpBr : kTagSmpTr);
@@ -649,8 +650,8 @@ __device__ __forceinline__ void collide_cell(const StepArgs& A, const TabView<R>
                             // eq:proba3 for photons: gamma -> k', v' -> c, flux k' c/(k gamma_i)
                             const double x = coef * (double)sig * photon_flux(f, b) * A.dt;
                             const double P = -expm1(-x);
-                            const U4 r = rng.draw(dk, cell, kTagAccBh);
-                            const double U1 = u53(r.x, r.y), U2 = u53(r.z, r.w);
+                            double U1, U2;
+                            accept_uniforms(rng, dk, cell, kTagAccBh, kTagHiBh, U1, U2);
                             if (fabs(U1 - P) <= A.near_rel * P) t.near_bh++;
                             if (U1 < P && U2 < Pej) {
                                 const U4 q = rng.draw(dk, cell, kTagSmpBh);
@@ -922,19 +923,38 @@ __device__ __forceinline__ bool team_any(bool v, int* red) {
 // The two team shapes therefore give bit-identical densities and n_ab.
 // canon_part2 is the per-thread part before the cross-wavefront step
 // (wavefront teams: the team total); it walks once and accumulates two sums.
+// A thread reads four terms at a time (indices clamped into [0, n), so the
+// reads are issued together) and then adds those below n in the canonical
+// order: each term is first added to zero, which gives it exactly.
 template <int kT, typename F>
 __device__ __forceinline__ void canon_part2(int n, F f, double& s1, double& s2) {
     if constexpr (kT == 256) {
         double a = 0.0, b = 0.0;
-        for (int q = threadIdx.x; q < n; q += 256) f(q, a, b);
+        for (int q = threadIdx.x; q < n; q += 1024) {
+            double ta[4], tb[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                ta[r] = 0.0; tb[r] = 0.0;
+                f(min(q + 256 * r, n - 1), ta[r], tb[r]);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (q + 256 * r < n) { a += ta[r]; b += tb[r]; }
+        }
         s1 = wave_sum(a); s2 = wave_sum(b);
     } else {
         const int l = threadIdx.x & 63;
         double a[4] = {0.0, 0.0, 0.0, 0.0}, b[4] = {0.0, 0.0, 0.0, 0.0};
         for (int q = l; q < n; q += 256) {
+            double ta[4], tb[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                ta[r] = 0.0; tb[r] = 0.0;
+                f(min(q + 64 * r, n - 1), ta[r], tb[r]);
+            }
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                if (q + 64 * r < n) f(q + 64 * r, a[r], b[r]);
+                if (q + 64 * r < n) { a[r] += ta[r]; b[r] += tb[r]; }
         }
         s1 = ((wave_sum(a[0]) + wave_sum(a[1])) + wave_sum(a[2])) + wave_sum(a[3]);
         s2 = ((wave_sum(b[0]) + wave_sum(b[1])) + wave_sum(b[2])) + wave_sum(b[3]);
@@ -1160,12 +1180,14 @@ __device__ __forceinline__ TeamMem carve_team(unsigned char* p, int cap, int rby
 // applies the FP64 bound again.
 __device__ __forceinline__ bool bound24(uint32_t rx, float xs) { return (float)(rx >> 8) <= xs; }
 
-__device__ __forceinline__ bool settle(double x, const U4& r, double rej, double near_rel, double Pej, int& near) {
-    const double U1 = u53(r.x, r.y);
+__device__ __forceinline__ bool settle(double x, const Rng& rng, uint32_t dk, uint32_t cell, uint32_t tag,
+                                       uint32_t tag_hi, double rej, double near_rel, double Pej, int& near) {
+    double U1, U2;
+    accept_uniforms(rng, dk, cell, tag, tag_hi, U1, U2);
     if (!(U1 <= rej * x)) return false;
     const double P = -expm1(-x);
     if (fabs(U1 - P) <= near_rel * P) near++;
-    return U1 < P && u53(r.z, r.w) < Pej;
+    return U1 < P && U2 < Pej;
 }
 
 // list a cell (once) for the event kernel
@@ -1309,6 +1331,15 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
                     if (nab > 0.0) {
                         const double coef = v4[0] * v4[2] / nab;
                         const float kx = (float)(coef * A.dt * rej * 16777216.0);
+                        // workgroup teams: a thread's pairs q = t + 256 u share
+                        // the draw of the upper bits of U1 (hi_group(q) = t,
+                        // word u), drawn once per process
+                        const uint32_t tagA = kPass == 0 ? kTagHiBr : kTagHiBh;
+                        U4 hA{0u, 0u, 0u, 0u}, hT{0u, 0u, 0u, 0u};
+                        if constexpr (kT == 256) {
+                            if (kPass == 1 || (A.proc & CMC_BREMS)) hA = rng.draw(hi_group((uint32_t)t), cell, tagA);
+                            if (kPass == 0 && (A.proc & CMC_TRIDENT)) hT = rng.draw(hi_group((uint32_t)t), cell, kTagHiTr);
+                        }
                         // one pair at a time (the tests do not overlap in
                         // registers), the next pair's momenta in flight
 #pragma unroll 1
@@ -1325,15 +1356,17 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
                                     const R sig = brems_sig_slice<R>(T, slice, e.g, e.gm1, hi);
                                     high |= hi;
                                     if (sig > (R)0) {
-                                        const U4 r = rng.draw((uint32_t)q, cell, kTagAccBr);
-                                        if (bound24(r.x, kx * (float)sig * (float)e.vrel)) bits = 1u;
+                                        const U4 h = kT == 256 ? hA : rng.draw(hi_group((uint32_t)q), cell, kTagHiBr);
+                                        if (bound24(hi_word(h, ((uint32_t)q >> 8) & 3u), kx * (float)sig * (float)e.vrel))
+                                            bits = 1u;
                                     }
                                 }
                                 if ((A.proc & CMC_TRIDENT) && !bits) {
                                     const R sig = (R)phys::trident_sigma(T.Z, (double)e.g);
                                     if (sig > (R)0) {
-                                        const U4 r = rng.draw((uint32_t)q, cell, kTagAccTr);
-                                        if (bound24(r.x, kx * (float)sig * (float)e.vrel)) bits = 2u;
+                                        const U4 h = kT == 256 ? hT : rng.draw(hi_group((uint32_t)q), cell, kTagHiTr);
+                                        if (bound24(hi_word(h, ((uint32_t)q >> 8) & 3u), kx * (float)sig * (float)e.vrel))
+                                            bits = 2u;
                                     }
                                 }
                             } else {
@@ -1341,8 +1374,9 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
                                 const R sig = bh_sig_slice<R>(T, slice, photon_k<R>(cx, cy, cz), hi);
                                 high |= hi;
                                 if (sig > (R)0) {
-                                    const U4 r = rng.draw((uint32_t)q, cell, kTagAccBh);
-                                    if (bound24(r.x, kx * (float)sig * (float)phys::kC)) bits = 1u;
+                                    const U4 h = kT == 256 ? hA : rng.draw(hi_group((uint32_t)q), cell, kTagHiBh);
+                                    if (bound24(hi_word(h, ((uint32_t)q >> 8) & 3u), kx * (float)sig * (float)phys::kC))
+                                        bits = 1u;
                                 }
                             }
                             if (bits) {
@@ -1421,6 +1455,9 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
         const auto ion_of = [&](int j) { return ion_order ? (int)M.ordI[Ni == N ? j : mod_small(j, Ni, rNi)] : 0; };
         const auto w_ion = [&](int j) { return ion_order ? wion[ion_of(j)] : wi0; };
         const auto mob_of = [&](int j) { return (int)M.ordM[Nm == N ? j : mod_small(j, Nm, rNm)]; };
+        // a cycled mobile species is walked in rank order: its first momenta
+        // are read once the order is formed
+        if (active && !mobA && t < N) { const int m = mob_of(t); qx = S.px[m0 + m]; qy = S.py[m0 + m]; qz = S.pz[m0 + m]; }
         // the other weights, read once: the densities n = sum W, n_ab =
         // sum_j min(W_a, W_b) and the weight check (when every mobile
         // particle pairs once, its density and n_ab share the walk)
@@ -1454,11 +1491,11 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
                 const int j = mobA ? (mob_order ? (int)M.ordM[q] : 0) : q;
                 const int mi = mobA ? q : mob_of(j);
                 const uint32_t dk = (uint32_t)(mobA ? mi : j);   // counter of the pair's draws
-                double cx = qx, cy = qy, cz = qz;
-                if (mobA) {
-                    if (q + kT < N) { qx = S.px[m0 + q + kT]; qy = S.py[m0 + q + kT]; qz = S.pz[m0 + q + kT]; }
-                } else {
-                    cx = S.px[m0 + mi]; cy = S.py[m0 + mi]; cz = S.pz[m0 + mi];
+                // this pair's momenta; the next pair's are read meanwhile
+                const double cx = qx, cy = qy, cz = qz;
+                if (q + kT < N) {
+                    const int mn = mobA ? q + kT : mob_of(q + kT);
+                    qx = S.px[m0 + mn]; qy = S.py[m0 + mn]; qz = S.pz[m0 + mn];
                 }
                 uint32_t bits = 0;
                 Ion b{0.0, 0.0, 0.0, 1.0, false};
@@ -1472,15 +1509,15 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
                         const R sig = brems_sig_slice<R>(T, slice, e.g, e.gm1, hi);
                         high |= hi;
                         if (sig > (R)0) {
-                            const U4 r = rng.draw(dk, cell, kTagAccBr);
-                            if (bound24(r.x, kx * (float)sig * (float)e.vrel)) bits = 1u;
+                            const U4 h = rng.draw(hi_group(dk), cell, kTagHiBr);
+                            if (bound24(hi_word(h, (dk >> 8) & 3u), kx * (float)sig * (float)e.vrel)) bits = 1u;
                         }
                     }
                     if ((A.proc & CMC_TRIDENT) && !bits) {
                         const R sig = (R)phys::trident_sigma(T.Z, (double)e.g);
                         if (sig > (R)0) {
-                            const U4 r = rng.draw(dk, cell, kTagAccTr);
-                            if (bound24(r.x, kx * (float)sig * (float)e.vrel)) bits = 2u;
+                            const U4 h = rng.draw(hi_group(dk), cell, kTagHiTr);
+                            if (bound24(hi_word(h, (dk >> 8) & 3u), kx * (float)sig * (float)e.vrel)) bits = 2u;
                         }
                     }
                 } else {
@@ -1497,8 +1534,8 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
                     const R sig = bh_sig_slice<R>(T, slice, k, hi);
                     high |= hi;
                     if (sig > (R)0) {
-                        const U4 r = rng.draw(dk, cell, kTagAccBh);
-                        if (bound24(r.x, kx * (float)sig * (float)flux)) bits = 1u;
+                        const U4 h = rng.draw(hi_group(dk), cell, kTagHiBh);
+                        if (bound24(hi_word(h, (dk >> 8) & 3u), kx * (float)sig * (float)flux)) bits = 1u;
                     }
                 }
                 if (bits) {
@@ -1666,14 +1703,14 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
                         bool hi;
                         const R sig = brems_lookup<R, false>(T, ct, e.g, e.gm1, hi).sig;
                         const double x = coef * (double)sig * e.vrel * A.dt;
-                        if (settle(x, rng.draw(dk, cell, kTagAccBr), rej, A.near_rel, Pej, near_br))
+                        if (settle(x, rng, dk, cell, kTagAccBr, kTagHiBr, rej, A.near_rel, Pej, near_br))
                             kind = kEvBr | ((A.proc & CMC_TRIDENT) ? kEvTrPending : 0u);
                     }
                     if ((A.proc & CMC_TRIDENT) && !kind) {
                         const R sig = (R)phys::trident_sigma(T.Z, (double)e.g);
                         if (sig > (R)0) {
                             const double x = coef * (double)sig * e.vrel * A.dt;
-                            if (settle(x, rng.draw(dk, cell, kTagAccTr), rej, A.near_rel, Pej, near_tr))
+                            if (settle(x, rng, dk, cell, kTagAccTr, kTagHiTr, rej, A.near_rel, Pej, near_tr))
                                 kind = kEvTr;
                         }
                     }
@@ -1689,7 +1726,7 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
                     const R sig = bh_lookup<R>(T, ct, k, ik, wk, hi);
                     const double x = coef * (double)sig * photon_flux(fr, b) * A.dt;
                     const double Pej = Wi / (Wm > Wi ? Wm : Wi);
-                    if (settle(x, rng.draw(dk, cell, kTagAccBh), rej, A.near_rel, Pej, near_bh))
+                    if (settle(x, rng, dk, cell, kTagAccBh, kTagHiBh, rej, A.near_rel, Pej, near_bh))
                         kind = kEvBh;
                     reused = Ng0 < Ni && j + Ng0 < Ni;
                 }
@@ -1793,8 +1830,8 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
                     if (sig > (R)0) {
                         const double x = coef0 * (double)sig * e.vrel * A.dt;
                         const double P = -expm1(-x);
-                        const U4 q = rng.draw(dk, cell, kTagAccTr);
-                        const double U1 = u53(q.x, q.y), U2 = u53(q.z, q.w);
+                        double U1, U2;
+                        accept_uniforms(rng, dk, cell, kTagAccTr, kTagHiTr, U1, U2);
                         if (fabs(U1 - P) <= A.near_rel * P) t.near_tr++;
                         tr = U1 < P && U2 < Pej;
                     }

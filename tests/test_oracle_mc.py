@@ -335,3 +335,24 @@ def test_fig9_early_time_photon_yield_and_spectrum():
     cdf /= cdf[-1]
     res = stats.kstest(np.log(all_k), lambda x: np.interp(x, grid, cdf))
     assert res.pvalue > 1e-3
+
+
+def test_acceptance_uniform_takes_its_upper_bits_from_a_draw_shared_by_four_pairs():
+    """Reading of the acceptance numbers: the upper 32 of U1's 53 bits are
+    word (x >> 8) & 3 of the hi draw keyed by ((x >> 10) << 8) | (x & 255).
+    Pins: U1 lies in the 2^-32 bin that word names (a bound test on the word
+    alone is therefore conservative), U1 and U2 are uniform, and the U1 of
+    the four pairs that share a draw are uncorrelated."""
+    from scipy import stats
+    seed, step, cell = 11, 4, 9
+    key = np.array([seed, 0], dtype=np.uint32)
+    xs = np.arange(8192)
+    U = np.array([O.accept_uniforms(seed, step, cell, x, "bh") for x in xs])
+    for x in (0, 1, 255, 256, 700, 1023, 1024, 5000, 8191):
+        h = int(O.philox([((x >> 10) << 8) | (x & 255), cell, step, 0x33 << 24], key)[(x >> 8) & 3])
+        assert h * 2.0 ** -32 <= U[x, 0] < (h + 1) * 2.0 ** -32
+    assert stats.kstest(U[:, 0], "uniform").pvalue > 1e-3
+    assert stats.kstest(U[:, 1], "uniform").pvalue > 1e-3
+    # x = 1024 b + 256 w + l: words w of one draw are the four columns
+    g = U[:, 0].reshape(8, 4, 256).transpose(1, 0, 2).reshape(4, -1)
+    assert np.max(np.abs(np.corrcoef(g) - np.eye(4))) < 0.1
