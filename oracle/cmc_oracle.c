@@ -963,10 +963,11 @@ void or_accept_uniforms(uint64_t seed, uint64_t step, uint32_t cell, uint32_t x,
 /* per particle (ties by index); the larger species A is walked once   */
 /* in that order and the smaller one B cyclically, pair j =            */
 /* (A[pi_A(j)], B[pi_B(j mod N_B)]); a tie N_a = N_b makes the mobile  */
-/* species A.  The random numbers of pair j are keyed by the index of  */
-/* its mobile particle when every mobile particle pairs once (the      */
-/* mobile species is A), by j otherwise: either way every pair of a    */
-/* pass has its own counter.                                           */
+/* species A.  The random numbers of pair j are keyed by              */
+/* x = i + k N_m: i is the index of its mobile particle and k = j div  */
+/* N_m counts that particle's earlier pairs in the pass (k = 0 when    */
+/* every mobile particle pairs once).  Every pair of a pass has its    */
+/* own counter, and the key does not depend on the order of the pairs. */
 /* ------------------------------------------------------------------ */
 typedef struct { uint32_t key; int32_t idx; } keyidx;
 
@@ -1150,7 +1151,7 @@ static int32_t cell_step(const stepctx* X, const or_cells* cells, int64_t c, int
             int64_t ie = e0 + pa[j], ii = i0 + pb[j];
             /* the pair's random numbers: keyed by its electron when every
              * electron pairs once (N_e >= N_i), else by the pair index */
-            uint32_t dkey = (uint32_t)(Ne >= Ni ? pa[j] : j);
+            uint32_t dkey = (uint32_t)(pa[j] + (j / Ne) * Ne);
             double We = el->w[ie], Wi = io->w[ii];
             double Pej = Wi / (We > Wi ? We : Wi);
             double u[3] = {0, 0, 0}, gi = 1.0;
@@ -1268,7 +1269,7 @@ static int32_t cell_step(const stepctx* X, const or_cells* cells, int64_t c, int
             if (dead[pa[j]]) continue;
             int64_t ig = g0 + pa[j], ii = i0 + pb[j];
             /* keyed by the photon when every photon pairs once, else by j */
-            uint32_t dkey = (uint32_t)(Ng >= Ni ? pa[j] : j);
+            uint32_t dkey = (uint32_t)(pa[j] + (j / Ng) * Ng);
             ti[OR_I_PAIRS_BH]++;
             double Wg = ph->w[ig], Wi = io->w[ii];
             double Pej = Wi / (Wg > Wi ? Wg : Wi);

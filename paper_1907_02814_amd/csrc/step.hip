@@ -502,8 +502,8 @@ __device__ __forceinline__ void collide_cell(const StepArgs& A, const TabView<R>
                     const int me = S.pm[j % Ne];
                     ie = e0 + me;
                     const int64_t ii = i0 + S.pi[j % Ni];
-                    // the pair's draws: keyed by its electron when every electron pairs once
-                    const uint32_t dk = (uint32_t)(Ne >= Ni ? me : j);
+                    // the pair's draws: keyed by its electron and its repetition
+                    const uint32_t dk = (uint32_t)(me + (j / Ne) * Ne);
                     We = A.el.w[ie];
                     const double Wi = A.io.w[ii];
                     const double Pej = Wi / (We > Wi ? We : Wi);
@@ -634,7 +634,7 @@ __device__ __forceinline__ void collide_cell(const StepArgs& A, const TabView<R>
                     if (!dead) {
                         ig = g0 + lg;
                         const int64_t ii = i0 + S.pi[j % Ni];
-                        const uint32_t dk = (uint32_t)(Ng0 >= Ni ? lg : j);   // keyed by the photon if it pairs once
+                        const uint32_t dk = (uint32_t)(lg + (j / Ng0) * Ng0);   // keyed by the photon and its repetition
                         t.pairs_bh++;
                         Wg = A.ph.w[ig];
                         const double Wi = A.io.w[ii];
@@ -1347,6 +1347,10 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
                             const int q = t + kT * u;
                             const double cx = nx, cy = ny, cz = nz;
                             if (q + kT < N) { nx = S.px[m0 + q + kT]; ny = S.py[m0 + q + kT]; nz = S.pz[m0 + q + kT]; }
+                            // word u of the shared draws: the words move down one per pair
+                            const uint32_t wA = hA.x, wT = hT.x;
+                            hA = U4{hA.y, hA.z, hA.w, 0u};
+                            hT = U4{hT.y, hT.z, hT.w, 0u};
                             if (q >= N) continue;
                             uint32_t bits = 0;
                             if (kPass == 0) {
@@ -1356,17 +1360,15 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
                                     const R sig = brems_sig_slice<R>(T, slice, e.g, e.gm1, hi);
                                     high |= hi;
                                     if (sig > (R)0) {
-                                        const U4 h = kT == 256 ? hA : rng.draw(hi_group((uint32_t)q), cell, kTagHiBr);
-                                        if (bound24(hi_word(h, ((uint32_t)q >> 8) & 3u), kx * (float)sig * (float)e.vrel))
-                                            bits = 1u;
+                                        const uint32_t w = kT == 256 ? wA : hi_word(rng.draw(hi_group((uint32_t)q), cell, kTagHiBr), ((uint32_t)q >> 8) & 3u);
+                                        if (bound24(w, kx * (float)sig * (float)e.vrel)) bits = 1u;
                                     }
                                 }
                                 if ((A.proc & CMC_TRIDENT) && !bits) {
                                     const R sig = (R)phys::trident_sigma(T.Z, (double)e.g);
                                     if (sig > (R)0) {
-                                        const U4 h = kT == 256 ? hT : rng.draw(hi_group((uint32_t)q), cell, kTagHiTr);
-                                        if (bound24(hi_word(h, ((uint32_t)q >> 8) & 3u), kx * (float)sig * (float)e.vrel))
-                                            bits = 2u;
+                                        const uint32_t w = kT == 256 ? wT : hi_word(rng.draw(hi_group((uint32_t)q), cell, kTagHiTr), ((uint32_t)q >> 8) & 3u);
+                                        if (bound24(w, kx * (float)sig * (float)e.vrel)) bits = 2u;
                                     }
                                 }
                             } else {
@@ -1374,9 +1376,8 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
                                 const R sig = bh_sig_slice<R>(T, slice, photon_k<R>(cx, cy, cz), hi);
                                 high |= hi;
                                 if (sig > (R)0) {
-                                    const U4 h = kT == 256 ? hA : rng.draw(hi_group((uint32_t)q), cell, kTagHiBh);
-                                    if (bound24(hi_word(h, ((uint32_t)q >> 8) & 3u), kx * (float)sig * (float)phys::kC))
-                                        bits = 1u;
+                                    const uint32_t w = kT == 256 ? wA : hi_word(rng.draw(hi_group((uint32_t)q), cell, kTagHiBh), ((uint32_t)q >> 8) & 3u);
+                                    if (bound24(w, kx * (float)sig * (float)phys::kC)) bits = 1u;
                                 }
                             }
                             if (bits) {
@@ -1489,8 +1490,10 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
             const float kx = (float)(coef * A.dt * rej * 16777216.0);
             for (int q = t; q < N; q += kT) {
                 const int j = mobA ? (mob_order ? (int)M.ordM[q] : 0) : q;
-                const int mi = mobA ? q : mob_of(j);
-                const uint32_t dk = (uint32_t)(mobA ? mi : j);   // counter of the pair's draws
+                const int jm = mobA ? 0 : (Nm == N ? j : mod_small(j, Nm, rNm));   // rank of the cycled particle
+                const int mi = mobA ? q : (int)M.ordM[jm];
+                // counter of the pair's draws: its mobile particle and repetition
+                const uint32_t dk = (uint32_t)(mobA ? mi : mi + (j - jm));
                 // this pair's momenta; the next pair's are read meanwhile
                 const double cx = qx, cy = qy, cz = qz;
                 if (q + kT < N) {
@@ -1682,8 +1685,11 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
             mine = cand ? rec[lane] : 0ull;
             pass = cand ? ev_pass(mine) : 2;
             j = ev_j(mine); mi = ev_m(mine); ii = ev_i(mine);
-            // the pair's draws: keyed by its mobile particle when that species pairs once
-            dk = (uint32_t)((pass == 0 ? Ne >= Ni : Ng0 >= Ni) ? mi : j);
+            // the pair's draws: keyed by its mobile particle and its repetition
+            {
+                const int nm = pass == 0 ? Ne : Ng0;
+                dk = cand && nm > 0 ? (uint32_t)(mi + (j / nm) * nm) : 0u;
+            }
             // ---- settle them
             bool reused = false;
             if (cand) {

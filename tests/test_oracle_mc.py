@@ -233,12 +233,12 @@ def test_bad_cells_and_weights_flagged():
     assert np.array_equal(wl.electrons["px"][4:8], before[4:8])
 
 
-@pytest.mark.parametrize("ne,ni", [(6, 3), (3, 6)])
-def test_pair_draws_are_keyed_by_the_mobile_particle_or_the_pair(ne, ni):
+@pytest.mark.parametrize("ne,ni", [(6, 3), (3, 6), (2, 5)])
+def test_pair_draws_are_keyed_by_the_mobile_particle_and_its_repetition(ne, ni):
     # x >> 40 makes P = 1: the event is then decided by U2 < W_i/max(W_e, W_i)
     # = 1/2 alone.  U2 comes from the pair's acceptance draw, whose counter is
-    # (electron index when every electron pairs once, else pair index j,
-    # cell, step, tag 0x11).
+    # (i + k ne, cell, step, tag 0x11): i the pair's electron, k = j div ne its
+    # earlier pairs in the pass (0 when every electron pairs once).
     tab = O.tables(29)
     n_cells, seed, step = 60, 3, 5
     wl = _tiny(n_cells, ne, ni, Wratio=0.5, gamma=1 + 200.0 / MEC2_MEV)
@@ -267,8 +267,11 @@ def test_pair_draws_are_keyed_by_the_mobile_particle_or_the_pair(ne, ni):
                 by_j[c, pa[c, jj]] = hit(jj, c)
         assert not np.array_equal(by_j, own)
     else:
-        # electrons are reused: pair j is decided by counter j
-        assert np.array_equal(ev, [sum(hit(jj, c) for jj in range(N)) for c in range(n_cells)])
+        # electrons are reused: pair j is decided by counter pa[j] + (j // ne) ne
+        assert np.array_equal(ev, [sum(hit(pa[c, jj] + (jj // ne) * ne, c) for jj in range(N)) for c in range(n_cells)])
+        # (with ne = 3, ni = 6 the counters i + k ne are the pair indices
+        # 0..5 in another order; with ne = 2, ni = 5 the third pair of a
+        # cell takes counter 4 or 5, so keying by j would give other counts)
     assert ev.sum() > 0
 
 
