@@ -1092,6 +1092,93 @@ __device__ void rank_order(int n, uint32_t cell, uint32_t tag, const Rng& rng, u
     Team<kT>::sync();
 }
 
+// Particles that pair once more when the mobile species is cycled: the e
+// of smallest (key, index) among n <= 4 kT, in the order rank_order forms
+// (the key of particle i is word i & 3 of the draw keyed by i >> 2), found
+// without forming that order.  The keys are counted by their top 8 bits;
+// every key in a bin below the one where the count reaches e is selected,
+// and the keys of that bin are ranked among themselves.  Sets the bits of
+// the selected particles in sel.  Returns false (nothing decided) when
+// that bin holds more than kSelList keys: the caller then forms the order.
+// LDS: kSelBytes at scr, the last of them the bitmap sel (32 words).
+constexpr int kSelList = 128;
+constexpr int kSelBytes = 1024 + 8 * kSelList + 16 + 128;
+
+template <int kT>
+__device__ bool select_smallest(int n, int e, uint32_t cell, uint32_t tag, const Rng& rng, unsigned char* scr,
+                                uint32_t* sel, int t) {
+    uint32_t* hist = reinterpret_cast<uint32_t*>(scr);                 // 256 bins
+    uint2* list = reinterpret_cast<uint2*>(scr + 1024);                // (key, particle)
+    int* sc = reinterpret_cast<int*>(scr + 1024 + 8 * kSelList);       // bin, still needed, list length
+    for (int i = t; i < 256; i += kT) hist[i] = 0u;
+    for (int i = t; i < 32; i += kT) sel[i] = 0u;
+    if (t == 0) sc[2] = 0;
+    // n <= 4 kT: one draw per thread gives the keys of particles 4t .. 4t + 3
+    const bool has = 4 * t < n;
+    U4 r{0u, 0u, 0u, 0u};
+    if (has) r = rng.draw((uint32_t)t, cell, tag);
+    const uint32_t k4[4] = {r.x, r.y, r.z, r.w};
+    Team<kT>::sync();
+    if (has) {
+#pragma unroll
+        for (int w = 0; w < 4; ++w)
+            if (4 * t + w < n) atomicAdd(&hist[k4[w] >> 24], 1u);
+    }
+    Team<kT>::sync();
+    if (t < 64) {
+        // the first wavefront finds the bin where the count reaches e
+        const uint32_t h[4] = {hist[4 * t], hist[4 * t + 1], hist[4 * t + 2], hist[4 * t + 3]};
+        const uint32_t sum = h[0] + h[1] + h[2] + h[3];
+        uint32_t incl = sum;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(incl, o, 64);
+            if (t >= o) incl += y;
+        }
+        uint32_t below = incl - sum;
+        if (below < (uint32_t)e && (uint32_t)e <= incl) {
+            int b = 4 * t + 3;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if (below + h[i] >= (uint32_t)e) { b = 4 * t + i; break; }
+                below += h[i];
+            }
+            sc[0] = b;
+            sc[1] = e - (int)below;
+        }
+    }
+    Team<kT>::sync();
+    const uint32_t bin = (uint32_t)sc[0];
+    if (has) {
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const int p = 4 * t + w;
+            if (p >= n) continue;
+            const uint32_t top = k4[w] >> 24;
+            if (top < bin) {
+                atomicOr(&sel[p >> 5], 1u << (p & 31));
+            } else if (top == bin) {
+                const int slot = atomicAdd(&sc[2], 1);
+                if (slot < kSelList) list[slot] = make_uint2(k4[w], (uint32_t)p);
+            }
+        }
+    }
+    Team<kT>::sync();
+    const int m = sc[2], need = sc[1];
+    if (m > kSelList) return false;
+    for (int i = t; i < m; i += kT) {
+        const uint2 a = list[i];
+        int rk = 0;
+        for (int j = 0; j < m; ++j) {
+            const uint2 o = list[j];
+            rk += (o.x < a.x) | ((o.x == a.x) & (o.y < a.y));
+        }
+        if (rk < need) atomicOr(&sel[a.y >> 5], 1u << (a.y & 31));
+    }
+    Team<kT>::sync();
+    return true;
+}
+
 // Pair indices of the open pairs of a pass that formed no order: the rank
 // of each one's particle by (key, index) among the n particles of its
 // species, counted against every key of the species (drawn again, as
@@ -1143,9 +1230,18 @@ __device__ __forceinline__ int mod_small(int j, int n, float rn) {
 // per-team LDS of the pass kernel
 constexpr int kSliceMax = 168;   // >= kSliceBrems, kSliceBH
 
-__host__ __device__ inline size_t team_bytes(int cap, int rbytes) {
+// The team's region holds the arrays of the rank sort or, in the direct
+// form of a cycled mobile species, the selection scratch (kSelBytes); the
+// table slice follows it.
+__host__ __device__ inline size_t team_region(int cap, int kT) {
+    (void)kT;
     const size_t n = (size_t)((cap + 63) / 64 * 64);
-    return n * 10 + ((size_t)4 << rank_bucket_bits(cap)) + (size_t)kSliceMax * rbytes + 16;
+    const size_t sort = n * 10 + ((size_t)4 << rank_bucket_bits(cap));
+    return sort > (size_t)kSelBytes ? sort : (size_t)kSelBytes;
+}
+
+__host__ __device__ inline size_t team_bytes(int cap, int rbytes, int kT) {
+    return team_region(cap, kT) + (size_t)kSliceMax * rbytes + 16;
 }
 
 struct TeamMem {
@@ -1154,18 +1250,20 @@ struct TeamMem {
     uint32_t* hist;
     uint16_t* ordM;   // mobile species: rank of each particle, or particle of each rank
     uint16_t* ordI;   // ions: particle of each rank
+    unsigned char* base;   // the region (selection scratch in the direct form)
     unsigned char* slice;
 };
 
-__device__ __forceinline__ TeamMem carve_team(unsigned char* p, int cap, int rbytes) {
+__device__ __forceinline__ TeamMem carve_team(unsigned char* p, int cap, int kT) {
     const size_t n = (size_t)((cap + 63) / 64 * 64);
     TeamMem m;
+    m.base = p;
+    m.slice = p + team_region(cap, kT);
     m.keys = reinterpret_cast<uint32_t*>(p); p += n * 4;
     m.tmp = reinterpret_cast<uint16_t*>(p); p += n * 2;
     m.hist = reinterpret_cast<uint32_t*>(p); p += (size_t)4 << rank_bucket_bits(cap);
     m.ordM = reinterpret_cast<uint16_t*>(p); p += n * 2;
-    m.ordI = reinterpret_cast<uint16_t*>(p); p += n * 2;
-    m.slice = p;
+    m.ordI = reinterpret_cast<uint16_t*>(p);
     return m;
 }
 
@@ -1233,8 +1331,8 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
     __shared__ int nopen[kTeams];
     const int team = kT == 64 ? (int)(threadIdx.x >> 6) : 0;
     const int t = Team<kT>::tid();
-    const size_t tstride = (team_bytes(cap, (int)sizeof(R)) + 15) / 16 * 16;
-    const TeamMem M = carve_team(smem_raw + tstride * team, cap, (int)sizeof(R));
+    const size_t tstride = (team_bytes(cap, (int)sizeof(R), kT) + 15) / 16 * 16;
+    const TeamMem M = carve_team(smem_raw + tstride * team, cap, kT);
     R* slice = reinterpret_cast<R*>(M.slice);
     const double rej = 2.0 * (1.0 + A.near_rel);
     const Rng rng = step_rng(A);
@@ -1277,14 +1375,22 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
         const double* wion = A.io.w + i0;
         const bool mobA = Nm >= Ni;
         const int N = mobA ? Nm : Ni;
-        // ---- direct form: every mobile particle pairs once (N_m >= N_i), at
-        // most four per thread, ions at rest.  The weights are summed
-        // (densities, n_ab against the first ion's weight, the weight checks)
-        // in one reduction, beside the table slice; then every pair is
-        // tested in storage order.  Should the ions not share one weight,
-        // the cell is done again below with both orders.
+        // ---- direct form: ions at rest, at most four mobile particles per
+        // thread.  The weights are summed (densities, the mobile particles'
+        // n_ab terms against the first ion's weight, the weight checks) in
+        // one reduction, beside the table slice; then every pair is tested
+        // in storage order of its mobile particle.  A cycled mobile species
+        // (N_m < N_i, K = N_i div N_m pairs per particle, e = N_i mod N_m of
+        // them one more) takes the e particles of smallest key as the order
+        // would, found by select_smallest; n_ab = fma(K, A, B), A the
+        // canonical sum of the terms and B that of the selected particles'.
+        // Should the ions not share one weight, the cell is done again below
+        // with both orders.
         if constexpr (!kMov) {
-            if (active && mobA && N <= 4 * kT) {
+            if (active && N <= 4 * kT) {
+                const bool cyc = !mobA;
+                const int K = N / Nm, e = N - K * Nm;
+                uint32_t* sel = reinterpret_cast<uint32_t*>(M.base + kSelBytes - 128);
                 {
                     const CellTab<R> ct = ct_c;
                     if (kPass == 0) {
@@ -1296,18 +1402,18 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
                 }
                 // the first pair's momenta are in flight during the reduction
                 double nx = 0.0, ny = 0.0, nz = 0.0;
-                if (t < N) { nx = S.px[m0 + t]; ny = S.py[m0 + t]; nz = S.pz[m0 + t]; }
+                if (t < Nm) { nx = S.px[m0 + t]; ny = S.py[m0 + t]; nz = S.pz[m0 + t]; }
                 const double w0 = wion[0];
                 int fl = 0;                 // 1 bad weight, 2 ions of unequal weight, 4 above the tables
                 double v4[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const int q = t + kT * u;
-                    const double wq = q < N ? wm[q] : 0.0, wi = q < Ni ? wion[q] : 0.0;
+                    const double wq = q < Nm ? wm[q] : 0.0, wi = q < Ni ? wion[q] : 0.0;
                     fl |= (!(wq >= 0.0) || !isfinite(wq) || !(wi >= 0.0) || !isfinite(wi)) ? 1 : 0;
                     fl |= (q < Ni && wi != w0) ? 2 : 0;
                     canon_add<kT>(v4[0], wq, u);
-                    canon_add<kT>(v4[1], q < N ? (wq < w0 ? wq : w0) : 0.0, u);
+                    canon_add<kT>(v4[1], q < Nm ? (wq < w0 ? wq : w0) : 0.0, u);
                     canon_add<kT>(v4[2], wi, u);
                 }
                 v4[0] = canon_end<kT>(v4[0]);
@@ -1321,7 +1427,33 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
                 if (t == 0) nopen[team] = 0;
                 team_reduce4_bits<kT>(v4, fl, red4, redi);   // its barriers also publish the slice
                 if (kT == 64) Team<kT>::sync();
-                if (!(fl & 2)) {
+                bool chosen = true;
+                if (!(fl & 3) && cyc) {
+                    // indices of the cycled case come from an opaque copy of the
+                    // thread's index: formed here, not kept across cells in
+                    // registers that the pairs need
+                    int tt = t;
+                    asm volatile("" : "+v"(tt));
+                    if (e > 0)
+                        chosen = select_smallest<kT>(Nm, e, cell, kPass == 0 ? kTagKeyE : kTagKeyG, rng, M.base, sel, tt);
+                    if (chosen) {
+                        double vb[4] = {0.0, 0.0, 0.0, 0.0};
+                        if (e > 0) {
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) {
+                                const int q = tt + kT * u;
+                                const bool sq = q < Nm && ((sel[q >> 5] >> (q & 31)) & 1u);
+                                const double wq = sq ? wm[q] : 0.0;
+                                canon_add<kT>(vb[0], sq ? (wq < w0 ? wq : w0) : 0.0, u);
+                            }
+                            vb[0] = canon_end<kT>(vb[0]);
+                            bool none = false;
+                            team_reduce4<kT>(vb, none, red4, redi);
+                        }
+                        v4[1] = fma((double)K, v4[1], vb[0]);   // one rounding, as in the ordered form
+                    }
+                }
+                if (!(fl & 2) && chosen) {
                     if (fl & 1) {
                         if (t == 0) atomicOr(A.status, CMC_ST_BAD_WEIGHT);
                         continue;
@@ -1331,58 +1463,95 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
                     if (nab > 0.0) {
                         const double coef = v4[0] * v4[2] / nab;
                         const float kx = (float)(coef * A.dt * rej * 16777216.0);
-                        // workgroup teams: a thread's pairs q = t + 256 u share
-                        // the draw of the upper bits of U1 (hi_group(q) = t,
-                        // word u), drawn once per process
+                        // workgroup teams: the first pairs of a thread's particles
+                        // q = t + 256 u share the draw of the upper bits of U1
+                        // (hi_group(q) = t, word u), drawn once per process
                         const uint32_t tagA = kPass == 0 ? kTagHiBr : kTagHiBh;
                         U4 hA{0u, 0u, 0u, 0u}, hT{0u, 0u, 0u, 0u};
                         if constexpr (kT == 256) {
                             if (kPass == 1 || (A.proc & CMC_BREMS)) hA = rng.draw(hi_group((uint32_t)t), cell, tagA);
                             if (kPass == 0 && (A.proc & CMC_TRIDENT)) hT = rng.draw(hi_group((uint32_t)t), cell, kTagHiTr);
                         }
-                        // one pair at a time (the tests do not overlap in
-                        // registers), the next pair's momenta in flight
+                        // the word of U1's upper bits for the pair keyed by x:
+                        // the shared one for a particle's first pair
+                        const auto word = [&](uint32_t x, bool first, uint32_t shared, uint32_t tag) {
+                            return kT == 256 && first ? shared : hi_word(rng.draw(hi_group(x), cell, tag), (x >> 8) & 3u);
+                        };
+                        // every particle's first pair, one at a time (the tests do
+                        // not overlap in registers), the next momenta in flight
 #pragma unroll 1
                         for (int u = 0; u < 4; ++u) {
                             const int q = t + kT * u;
                             const double cx = nx, cy = ny, cz = nz;
-                            if (q + kT < N) { nx = S.px[m0 + q + kT]; ny = S.py[m0 + q + kT]; nz = S.pz[m0 + q + kT]; }
+                            if (q + kT < Nm) { nx = S.px[m0 + q + kT]; ny = S.py[m0 + q + kT]; nz = S.pz[m0 + q + kT]; }
                             // word u of the shared draws: the words move down one per pair
                             const uint32_t wA = hA.x, wT = hT.x;
                             hA = U4{hA.y, hA.z, hA.w, 0u};
                             hT = U4{hT.y, hT.z, hT.w, 0u};
-                            if (q >= N) continue;
+                            if (q >= Nm) continue;
                             uint32_t bits = 0;
                             if (kPass == 0) {
-                                const Elec<R> e = electron_p<R>(cx, cy, cz);
+                                const Elec<R> el = electron_p<R>(cx, cy, cz);
                                 if (A.proc & CMC_BREMS) {
                                     bool hi;
-                                    const R sig = brems_sig_slice<R>(T, slice, e.g, e.gm1, hi);
+                                    const R sig = brems_sig_slice<R>(T, slice, el.g, el.gm1, hi);
                                     high |= hi;
-                                    if (sig > (R)0) {
-                                        const uint32_t w = kT == 256 ? wA : hi_word(rng.draw(hi_group((uint32_t)q), cell, kTagHiBr), ((uint32_t)q >> 8) & 3u);
-                                        if (bound24(w, kx * (float)sig * (float)e.vrel)) bits = 1u;
-                                    }
+                                    if (sig > (R)0 && bound24(word((uint32_t)q, true, wA, kTagHiBr), kx * (float)sig * (float)el.vrel))
+                                        bits = 1u;
                                 }
                                 if ((A.proc & CMC_TRIDENT) && !bits) {
-                                    const R sig = (R)phys::trident_sigma(T.Z, (double)e.g);
-                                    if (sig > (R)0) {
-                                        const uint32_t w = kT == 256 ? wT : hi_word(rng.draw(hi_group((uint32_t)q), cell, kTagHiTr), ((uint32_t)q >> 8) & 3u);
-                                        if (bound24(w, kx * (float)sig * (float)e.vrel)) bits = 2u;
-                                    }
+                                    const R sig = (R)phys::trident_sigma(T.Z, (double)el.g);
+                                    if (sig > (R)0 && bound24(word((uint32_t)q, true, wT, kTagHiTr), kx * (float)sig * (float)el.vrel))
+                                        bits = 2u;
                                 }
                             } else {
                                 bool hi;
                                 const R sig = bh_sig_slice<R>(T, slice, photon_k<R>(cx, cy, cz), hi);
                                 high |= hi;
-                                if (sig > (R)0) {
-                                    const uint32_t w = kT == 256 ? wA : hi_word(rng.draw(hi_group((uint32_t)q), cell, kTagHiBh), ((uint32_t)q >> 8) & 3u);
-                                    if (bound24(w, kx * (float)sig * (float)phys::kC)) bits = 1u;
-                                }
+                                if (sig > (R)0 && bound24(word((uint32_t)q, true, wA, kTagHiBh), kx * (float)sig * (float)phys::kC))
+                                    bits = 1u;
                             }
                             if (bits) {
-                                const int k = atomicAdd(&nopen[team], 1);
-                                if (k < kCandCap) opn[team][k] = (uint32_t)q | (bits << 16);
+                                const int o = atomicAdd(&nopen[team], 1);
+                                if (o < kCandCap) opn[team][o] = (uint32_t)q | (bits << 16);
+                            }
+                        }
+                        // cycled mobile species: the further pairs k = 1 .. reps - 1 of
+                        // each particle (K - 1 for all, one more for the selected),
+                        // keyed by q + k N_m, the momenta read again
+                        if (cyc && (K > 1 || e > 0)) {
+                            int tt = t;
+                            asm volatile("" : "+v"(tt));
+#pragma unroll 1
+                            for (int u = 0; u < 4; ++u) {
+                                const int q = tt + kT * u;
+                                if (q >= Nm) continue;
+                                const int reps = K + ((e > 0 && ((sel[q >> 5] >> (q & 31)) & 1u)) ? 1 : 0);
+                                if (reps < 2) continue;
+                                const double cx = S.px[m0 + q], cy = S.py[m0 + q], cz = S.pz[m0 + q];
+                                for (int k = 1; k < reps; ++k) {
+                                    const uint32_t x = (uint32_t)(q + k * Nm);
+                                    uint32_t bits = 0;
+                                    if (kPass == 0) {
+                                        const Elec<R> el = electron_p<R>(cx, cy, cz);
+                                        bool hi;
+                                        const R sb = (A.proc & CMC_BREMS) ? brems_sig_slice<R>(T, slice, el.g, el.gm1, hi) : (R)0;
+                                        if (sb > (R)0 && bound24(word(x, false, 0u, kTagHiBr), kx * (float)sb * (float)el.vrel))
+                                            bits = 1u;
+                                        const R st = (A.proc & CMC_TRIDENT) ? (R)phys::trident_sigma(T.Z, (double)el.g) : (R)0;
+                                        if (!bits && st > (R)0 && bound24(word(x, false, 0u, kTagHiTr), kx * (float)st * (float)el.vrel))
+                                            bits = 2u;
+                                    } else {
+                                        bool hi;
+                                        const R sig = bh_sig_slice<R>(T, slice, photon_k<R>(cx, cy, cz), hi);
+                                        if (sig > (R)0 && bound24(word(x, false, 0u, kTagHiBh), kx * (float)sig * (float)phys::kC))
+                                            bits = 1u;
+                                    }
+                                    if (bits) {
+                                        const int o = atomicAdd(&nopen[team], 1);
+                                        if (o < kCandCap) opn[team][o] = (uint32_t)q | (bits << 16) | ((uint32_t)k << 20);
+                                    }
+                                }
                             }
                         }
                         Team<kT>::sync();
@@ -1390,9 +1559,13 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
                         if (n_open > kCandCap) {
                             if (t == 0) mark_slow(W, c);
                         } else if (n_open > 0) {
+                            // pair index of an open pair: its particle's rank plus k N_m
                             rank_open<kT>(Nm, cell, kPass == 0 ? kTagKeyE : kTagKeyG, rng, opn[team], opk[team], opj[team], n_open);
-                            if (t < n_open)
-                                push_cand(W, c, ev_pack(kPass, (int)opj[team][t], (int)(opn[team][t] & 0xFFFFu), 0, opn[team][t] >> 16));
+                            if (t < n_open) {
+                                const uint32_t o = opn[team][t];
+                                push_cand(W, c, ev_pack(kPass, (int)opj[team][t] + (int)(o >> 20) * Nm, (int)(o & 0xFFFFu), 0,
+                                                        (o >> 16) & 0xFu));
+                            }
                         }
                         if (t == 0) W.coef[c * 2 + kPass] = coef;
                     }
@@ -1462,12 +1635,36 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
         // the other weights, read once: the densities n = sum W, n_ab =
         // sum_j min(W_a, W_b) and the weight check (when every mobile
         // particle pairs once, its density and n_ab share the walk)
+        double cyc_b = 0.0;
+        int cyc_k = 0;
         if (active && mobA) {
             canon_part2<kT>(N, [&](int q, double& a, double& b) {
                 const double u = chk(wm[q]), v = ion_order ? w_ion((int)M.ordM[q]) : wi0;
                 a += u;
                 b += u < v ? u : v;
             }, v4[0], v4[1]);
+        } else if (active && !ion_order) {
+            // a cycled mobile species with interchangeable ions: n_ab = K A + B
+            // as the direct form forms it (A over all the mobile particles' terms,
+            // B over those of the e particles of smallest key, ranks 0 .. e - 1)
+            uint32_t* selb = M.keys;   // free once the order is formed
+            for (int i = t; i < (Nm + 31) / 32; i += kT) selb[i] = 0u;
+            Team<kT>::sync();
+            for (int r = t; r < N - (N / Nm) * Nm; r += kT) {
+                const int p = (int)M.ordM[r];
+                atomicOr(&selb[p >> 5], 1u << (p & 31));
+            }
+            Team<kT>::sync();
+            canon_part2<kT>(Nm, [&](int q, double& a, double& b) {
+                const double u = chk(wm[q]);
+                a += u;
+                b += u < wi0 ? u : wi0;
+            }, v4[0], v4[1]);
+            cyc_b = canon_part<kT>(Nm, [&](int q) {
+                const double u = wm[q];
+                return ((selb[q >> 5] >> (q & 31)) & 1u) ? (u < wi0 ? u : wi0) : 0.0;
+            });
+            cyc_k = N / Nm;
         } else {
             v4[0] = canon_part<kT>(Nm, [&](int q) { return chk(wm[q]); });
             v4[1] = !active ? 0.0 : canon_part<kT>(N, [&](int j) {
@@ -1478,6 +1675,12 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
         v4[3] = canon_part<kT>(No, [&](int q) { return chk(wo[q]); });
         bool badw = bad != 0;
         team_reduce4<kT>(v4, badw, red4, redi);
+        if (cyc_k > 0) {
+            double vb[4] = {cyc_b, 0.0, 0.0, 0.0};
+            bool none = false;
+            team_reduce4<kT>(vb, none, red4, redi);
+            v4[1] = fma((double)cyc_k, v4[1], vb[0]);   // one rounding, as in the direct form
+        }
         if (badw) {
             if (t == 0) atomicOr(A.status, CMC_ST_BAD_WEIGHT);
             continue;
@@ -2085,7 +2288,7 @@ static int team_cap(int team, int maxn, bool fp64) {
     const int rb = fp64 ? 8 : 4;
     int cap = team == 64 ? std::min(maxn, kWaveCap) : maxn;
     const size_t static_lds = 256;
-    while (cap > 64 && (size_t)(256 / team) * ((team_bytes(cap, rb) + 15) / 16 * 16) + static_lds > kLdsMax)
+    while (cap > 64 && (size_t)(256 / team) * ((team_bytes(cap, rb, team) + 15) / 16 * 16) + static_lds > kLdsMax)
         cap -= 64;
     return cap;
 }
@@ -2135,7 +2338,7 @@ static void launch_pass_t(const StepArgs& A, const TabView<R>& T, const Work& W,
 static void launch_team(const StepArgs& A, const cmc_tables_s* t, const Work& W, bool fp64, int team, int filter,
                         int fcap, int64_t max_blocks, hipStream_t st, PassTiming* pt) {
     const int cap = team_cap(team, A.maxn, fp64);
-    const size_t per = (team_bytes(cap, fp64 ? 8 : 4) + 15) / 16 * 16;
+    const size_t per = (team_bytes(cap, fp64 ? 8 : 4, team) + 15) / 16 * 16;
     const size_t dshm = per * (size_t)(256 / team);
     const int64_t units = team == 64 ? (A.n_cells + 3) / 4 : A.n_cells;
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(units, max_blocks));

@@ -119,3 +119,23 @@ def test_graph_replay_matches_eager_steps():
             assert np.array_equal(A[k], B[k]), (s, k)
         assert int(counter.item()) == s + 1
     assert A["ti"][:, 3:6].sum() > 20
+
+
+@pytest.mark.parametrize("precision,other", [(0, "WAVE"), (1, "WAVE"), (1, "HYBRID")])
+def test_cycled_photons_bit_identical_across_team_shapes(precision, other):
+    """Cells with fewer photons than ions (300-1023 photons, 1024 ions of one
+    weight): workgroup teams take the direct form with the selection of the
+    photons that pair once more, wavefront teams (at most 256 pairs in their
+    direct form) the ordered form; both give the same bits."""
+    import paper_1907_02814_amd as cmc
+    from test_gpu_step import _cycled_photons
+    wl = _cycled_photons(64, 43)
+    ga, sa = _state(wl, cmc.SCHED_GROUP, precision)
+    gb, sb = _state(wl, getattr(cmc, "SCHED_" + other), precision)
+    for s in range(3):
+        sa.step(s)
+        sb.step(s)
+        A, B = _snap(ga, sa), _snap(gb, sb)
+        for k in A:
+            assert np.array_equal(A[k], B[k]), (s, k)
+    assert A["ti"][:, 5].sum() > 20

@@ -42,6 +42,24 @@ def test_bethe_heitler_cells(precision):
     assert (wl.photons["count"].sum() - P.ref.photons["count"].sum()) > 100
 
 
+def _cycled_photons(n_cells, seed):
+    """cfg2 cells (1024 Au ions of one weight) holding fewer photons than
+    ions: the photon species is cycled, K = 1 .. 3 pairs per photon and
+    e = N_i mod N_photon photons once more."""
+    wl = W.cfg2(np.random.default_rng(seed), n_cells=n_cells, per_cell=1024, dt=3e-13)
+    live = np.random.default_rng(seed + 1).integers(300, 1024, n_cells)
+    live[:4] = (1023, 1000, 512, 341)        # e = 1, e = 24, K = 2 with e = 0, K = 3 with e = 1
+    wl.photons["count"][:] = live
+    return wl
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_cycled_photons_against_the_oracle(precision):
+    wl = _cycled_photons(48, 41)
+    P = _run(wl, 2, precision=precision)
+    assert (wl.photons["count"].sum() - P.ref.photons["count"].sum()) > 50
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_all_processes_uneven_cells(precision):
     wl = W.cfg3(np.random.default_rng(9), n_cells=160, dt=2e-13, lo=1, hi=3000)
