@@ -18,6 +18,7 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 
+template <int kW>
 __device__ double ysum(double v, double* red) {
     v = wave_sum(v);
     const int w = threadIdx.x >> 6;
@@ -26,7 +27,7 @@ __device__ double ysum(double v, double* red) {
     __syncthreads();
     double s = red[0];
 #pragma unroll
-    for (int i = 1; i < kWaves; ++i) s += red[i];
+    for (int i = 1; i < kW; ++i) s += red[i];
     __syncthreads();
     return s;
 }
@@ -218,17 +219,20 @@ __global__ __launch_bounds__(kThreads, 3) void k_yield(YArgs A, TabView<R> T) {
             if (A.yp) A.yp[j] = y;
             acc += y;
         }
-        const double s = ysum(acc, red);
+        const double s = ysum<kWaves>(acc, red);
         if (threadIdx.x == 0) A.Y[c] = s;
         __syncthreads();
     }
 }
 
-// Three wavefronts per SIMD: the cell's screening and Jacobian (thread 0,
-// once per cell) then spill a little, the electron loop does not.
+// Three wavefronts per SIMD (the electron loop holds more registers than
+// four would leave), and workgroups of three wavefronts: a CU then holds
+// four cells at once, so that 256 CUs take 1024 cells in one round.
+constexpr int kBwdThreads = 192;
 template <typename R>
-__global__ __launch_bounds__(kThreads, 3) void k_yield_bwd(YArgs A, TabView<R> T) {
-    __shared__ double red[kWaves];
+__global__ __launch_bounds__(kBwdThreads, 3) void k_yield_bwd(YArgs A, TabView<R> T) {
+    constexpr int kThreads = kBwdThreads;
+    __shared__ double red[kThreads / 64];
     __shared__ CellTab<R> ct_s;
     __shared__ CellJac J_s;
     __shared__ R sS[kSliceBrems], sK[kSliceBrems];
@@ -299,7 +303,8 @@ __global__ __launch_bounds__(kThreads, 3) void k_yield_bwd(YArgs A, TabView<R> T
             A.gpx[j] = gx; A.gpy[j] = gyv; A.gpz[j] = gz;
             if (A.gw) A.gw[j] = gwj;
         }
-        const double s0 = ysum(a0, red), sD = ysum(aD, red), sR = ysum(aR, red), sE = ysum(aE, red);
+        const double s0 = ysum<kThreads / 64>(a0, red), sD = ysum<kThreads / 64>(aD, red);
+        const double sR = ysum<kThreads / 64>(aR, red), sE = ysum<kThreads / 64>(aE, red);
         if (threadIdx.x < 3) {
             const CellJac& J = J_s;
             const int q = threadIdx.x;
@@ -371,9 +376,9 @@ extern "C" cmc_status cmc_expected_yield_backward(cmc_tables t, int64_t n_cells,
     A.gTe = gT_e; A.n_cells = n_cells; A.dt = dt;
     hipStream_t st = as_stream(stream);
     if (precision == CMC_FP64)
-        hipLaunchKernelGGL(k_yield_bwd<double>, dim3(ygrid(n_cells)), dim3(kThreads), 0, st, A, view64(t));
+        hipLaunchKernelGGL(k_yield_bwd<double>, dim3(ygrid(n_cells)), dim3(kBwdThreads), 0, st, A, view64(t));
     else
-        hipLaunchKernelGGL(k_yield_bwd<float>, dim3(ygrid(n_cells)), dim3(kThreads), 0, st, A, view32(t));
+        hipLaunchKernelGGL(k_yield_bwd<float>, dim3(ygrid(n_cells)), dim3(kBwdThreads), 0, st, A, view32(t));
     CMC_CHECK_LAUNCH("cmc_expected_yield_backward");
     return CMC_OK;
 }
