@@ -227,7 +227,10 @@ __global__ __launch_bounds__(kThreads, 3) void k_yield(YArgs A, TabView<R> T) {
 
 // Three wavefronts per SIMD (the electron loop holds more registers than
 // four would leave), and workgroups of three wavefronts: a CU then holds
-// four cells at once, so that 256 CUs take 1024 cells in one round.
+// four cells at once, so that 256 CUs take 1024 cells in one round.  Thread
+// 0 computes the cell's screening state and lookup positions while thread 64
+// computes the same state and its Jacobian, which is read only after the
+// electron loop: the two serial parts run side by side.
 constexpr int kBwdThreads = 192;
 template <typename R>
 __global__ __launch_bounds__(kBwdThreads, 3) void k_yield_bwd(YArgs A, TabView<R> T) {
@@ -245,9 +248,9 @@ __global__ __launch_bounds__(kBwdThreads, 3) void k_yield_bwd(YArgs A, TabView<R
         double nx = 0.0, ny = 0.0, nz = 0.0, nw = 0.0;
         if (j < j1) { nx = A.px[j]; ny = A.py[j]; nz = A.pz[j]; nw = A.w[j]; }
         if (threadIdx.x == 0) {
-            const phys::Screen s = phys::screening(T.Z, Zs, ni, Te);
-            ct_s = cell_tab<R>(s, T.ax);
-            J_s = cell_jacobian(s, T.Z, Zs, ne, Te);
+            ct_s = cell_tab<R>(phys::screening(T.Z, Zs, ni, Te), T.ax);
+        } else if (threadIdx.x == 64) {
+            J_s = cell_jacobian(phys::screening(T.Z, Zs, ni, Te), T.Z, Zs, ne, Te);
         }
         __syncthreads();
         {
