@@ -28,11 +28,18 @@ constexpr double kMec2Ev = grid::kMec2Ev;
 
 // ---------------------------------------------------------------- Lambert W
 // Principal branch, used by eq:lambert-W (the coefficient a > 0 puts the
-// argument in [-1/e, 0)).  Halley's method on f(w) = w e^w - z.
+// argument in [-1/e, 0)).  Halley's method on f(w) = w e^w - z.  For
+// |z| <= 2^-7 it starts from the Taylor series of W0 about 0, whose n-th
+// coefficient is (-n)^(n-1)/n!: to z^10 the remainder is below 1e-18 of w,
+// so the first step already meets the tolerance.
 CMC_HD double lambert_w0(double z) {
     if (z == 0.0) return 0.0;
     double w;
-    if (z > -0.25 && z < 3.0) {
+    if (fabs(z) <= 0x1p-7) {
+        w = z * (1.0 + z * (-1.0 + z * (1.5 + z * (-8.0 / 3.0 + z * (125.0 / 24.0 + z * (-54.0 / 5.0
+              + z * (16807.0 / 720.0 + z * (-16384.0 / 315.0 + z * (531441.0 / 4480.0
+              + z * (-156250.0 / 567.0))))))))));
+    } else if (z > -0.25 && z < 3.0) {
         w = log1p(z);
     } else if (z <= -0.25) {
         const double q = sqrt(2.0 * (2.718281828459045 * z + 1.0));
@@ -93,17 +100,38 @@ CMC_HD double itfd(double eta_tf, double eta_d, double Ltf, double Ld) {
     return a;
 }
 
-// eq:lambert-W: L_R = sqrt(exp(W(-e^{-1-2a}) + 1 + 2a) - 1)
-CMC_HD double reduced_length(double a) {
+// eq:lambert-W: L_R = sqrt(exp(u) - 1), u = W(-e^{-1-2a}) + 1 + 2a.  W e^W
+// equals the argument, so e^u = -1/W: L_R^2 = -(1 + W)/W and
+// ln L_R = (u + ln(1 + W))/2, with ln(1 + W) from its series for
+// |W| <= 2^-7 (to W^8: the remainder is below 2e-20).  W = 0 (an argument
+// below the double range) keeps the exponential form.
+struct Reduced { double Lr, lnLr; };
+CMC_HD Reduced reduced_length_log(double a) {
     const double W = lambert_w0(-exp(-(1.0 + 2.0 * a)));
-    return sqrt(expm1(W + 1.0 + 2.0 * a));
+    Reduced r;
+    if (W == 0.0) {
+        r.Lr = sqrt(expm1(1.0 + 2.0 * a));
+        r.lnLr = log(r.Lr);
+        return r;
+    }
+    const double L2 = -(1.0 + W) / W;
+    r.Lr = sqrt(L2);
+    if (fabs(W) <= 0x1p-7) {
+        const double l1w = W * (1.0 + W * (-1.0 / 2 + W * (1.0 / 3 + W * (-1.0 / 4 + W * (1.0 / 5
+                         + W * (-1.0 / 6 + W * (1.0 / 7 + W * (-1.0 / 8))))))));
+        r.lnLr = 0.5 * ((W + 1.0 + 2.0 * a) + l1w);
+    } else {
+        r.lnLr = 0.5 * log(L2);
+    }
+    return r;
 }
+CMC_HD double reduced_length(double a) { return reduced_length_log(a).Lr; }
 
 struct Screen {
     double Ltf, Ld;        // normalised screening lengths L/r_C
     double eta_tf, eta_d;  // q_TF/q = 1 - Z*/Z, q_D/q = Z*/Z
     double a;              // I_TFD
-    double Lr;             // reduced length
+    double Lr, lnLr;       // reduced length and its logarithm
     int branch;            // 0: Z* = 0; 1: Debye; 2: L_D = r_i; 3: top of the L axis
 };
 
@@ -125,7 +153,9 @@ CMC_HD Screen screening(double Z, double Zs, double ni, double T) {
         if (s.Ld > grid::kLmax) { s.Ld = grid::kLmax; s.branch = 3; }
     }
     s.a = itfd(s.eta_tf, s.eta_d, s.Ltf, s.Ld);
-    s.Lr = reduced_length(s.a);
+    const Reduced r = reduced_length_log(s.a);
+    s.Lr = r.Lr;
+    s.lnLr = r.lnLr;
     return s;
 }
 

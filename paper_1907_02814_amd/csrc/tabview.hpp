@@ -72,7 +72,7 @@ struct CellTab {
 template <typename R>
 __device__ __forceinline__ CellTab<R> cell_tab(const phys::Screen& s, const Axes& ax) {
     CellTab<R> t;
-    locate<R>((R)log(s.Lr), ax.L, t.iL, t.wL, t.inL);
+    locate<R>((R)s.lnLr, ax.L, t.iL, t.wL, t.inL);
     locate<R>((R)s.eta_d, ax.eta, t.iE, t.wE, t.inE);
     const double lnLd = s.eta_d > 0.0 ? log(s.Ld) : log(grid::kLmin);
     locate<R>((R)lnLd, ax.L, t.iD, t.wD, t.inD);

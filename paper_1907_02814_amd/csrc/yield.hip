@@ -178,9 +178,10 @@ __device__ CellJac cell_jacobian(const phys::Screen& s, double Z, double Zs, dou
 // One workgroup per cell.  The first electron of each thread is in flight
 // while thread 0 computes the cell's screening state; the slices are then
 // staged, and every electron is evaluated with the next one's record in
-// flight.
+// flight.  The FP32 form runs four wavefronts per SIMD (four cells per CU,
+// 1024 cells in one round), the FP64 form three.
 template <typename R>
-__global__ __launch_bounds__(kThreads, 3) void k_yield(YArgs A, TabView<R> T) {
+__global__ __launch_bounds__(kThreads, sizeof(R) == 4 ? 4 : 3) void k_yield(YArgs A, TabView<R> T) {
     __shared__ double red[kWaves];
     __shared__ CellTab<R> ct_s;
     __shared__ R sS[kSliceBrems], sK[kSliceBrems];
