@@ -298,8 +298,8 @@ def main():
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py: one GPU only (--gpus 1); cells are independent within a step, so the "
-              "path shards by contiguous cell ranges with no exchange, but this build runs and "
-              "measures one GPU's share", file=sys.stderr)
+              "path would shard by contiguous cell ranges with no exchange; the library runs "
+              "and this benchmark measures one GPU's share", file=sys.stderr)
         sys.exit(2)
     if a.copy_calibration:
         copy_calibration()
