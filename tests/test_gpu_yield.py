@@ -93,3 +93,49 @@ def test_autograd_function_against_finite_differences():
         fd = float((fp - fm) / (2 * h))
         an = float(sum((leaves[k].grad * v[k]).sum() for k in v))
         assert abs(fd - an) <= 2e-6 * abs(an)
+
+
+def _dense_inputs():
+    """Cells so dense that L_D is clamped to r_i near the foot of the L axis
+    (Z* close to Z = 29, n_e ~ 1e35 m^-3): I_TFD falls below 1.93, where the
+    principal Lambert W branch of eq:lambert-W starts from log1p instead of
+    its series about 0.  L_R = 10.5, 10.7 (inside the axis), 8.4 (below it,
+    clamped) and 11.5 (I_TFD = 1.95, the series start) beside ordinary cells."""
+    y = _inputs(n_cells=8, per_cell=300, seed=13)
+    y["Zstar"][:4] = [29.0, 28.5, 29.0, 29.0]
+    y["n_e"][:4] = [1.04e35, 1.0e35, 2.0e35, 8.0e34]
+    y["T_e"][:4] = 10.0
+    return y
+
+
+def test_dense_cells_reach_the_general_lambert_start():
+    # the premise, from the oracle: which start each dense cell takes
+    y = _dense_inputs()
+    a = np.array([O.screening(29, y["Zstar"][c], y["n_e"][c] / y["Zstar"][c], y["T_e"][c])["a"]
+                  for c in range(4)])
+    z = np.exp(-(1.0 + 2.0 * a))
+    assert np.all(z[:3] > 2.0 ** -7) and z[3] <= 2.0 ** -7
+
+
+@pytest.mark.parametrize("precision,rtol,rtol_g", [(0, 1e-12, 1e-11), (1, 1e-5, 2e-5)])
+def test_dense_cells_against_the_oracle(precision, rtol, rtol_g):
+    import paper_1907_02814_amd as cmc
+    from gpu_parity import gpu_tables
+    y = _dense_inputs()
+    g = _dev(y)
+    args = (g["Zstar"], g["n_e"], g["T_e"], g["off"], g["px"], g["py"], g["pz"], g["w"], y["dt"])
+    oargs = (y["Zstar"], y["n_e"], y["T_e"], y["off"], y["px"], y["py"], y["pz"], y["w"], y["dt"])
+    Y = cmc.expected_yield(gpu_tables(29), *args, precision)
+    Yo = O.expected_yield(O.tables(29), *oargs)
+    assert np.all(Yo[:4] > 0.0)
+    np.testing.assert_allclose(Y.cpu().numpy(), Yo, rtol=rtol, atol=0)
+    gY = np.linspace(0.5, 2.0, len(y["Zstar"]))
+    G = cmc.expected_yield_backward(gpu_tables(29), *args, _dev({"a": gY})["a"], precision)
+    Go = O.expected_yield_backward(O.tables(29), *oargs, gY)
+    for k in ("gZstar", "gn_e", "gT_e", "gw"):
+        a, b = G[k].cpu().numpy(), Go[k]
+        assert np.all(np.abs(a - b) <= rtol_g * np.abs(b) + 1e-300 + 1e-12 * rtol_g * np.abs(b).max()), k
+    a = np.stack([G[k].cpu().numpy() for k in ("gpx", "gpy", "gpz")])
+    b = np.stack([Go[k] for k in ("gpx", "gpy", "gpz")])
+    err = np.sqrt(((a - b) ** 2).sum(0)); mag = np.sqrt((b ** 2).sum(0))
+    assert np.all(err <= rtol_g * mag + 1e-300)
