@@ -262,7 +262,9 @@ enum { CMC_SCHED_AUTO = 0, CMC_SCHED_CELL = 1, CMC_SCHED_GROUP = 2, CMC_SCHED_WA
 /* off device [n_cells+1]; px..w device [off[n_cells]]; Y device        */
 /* [n_cells]; y_part device per-electron terms or NULL.                 */
 /* precision: CMC_FP64 or CMC_FP32 (table lookups in FP32, P and sums   */
-/* in FP64).  Errors: CMC_EINVAL, CMC_EDEVICE.                          */
+/* in FP64).  A cell without electrons gets Y = 0.  n_cells = 0 does    */
+/* nothing, and then every array may be NULL.                           */
+/* Errors: CMC_EINVAL, CMC_EDEVICE.                                     */
 /* ------------------------------------------------------------------ */
 cmc_status cmc_expected_yield(cmc_tables t, int64_t n_cells, const double* Zstar,
                               const double* n_e, const double* T_e, const int64_t* off,
@@ -275,7 +277,9 @@ cmc_status cmc_expected_yield(cmc_tables t, int64_t n_cells, const double* Zstar
  * be NULL) and dL/dZ*, dL/dn_e, dL/dT_e (per cell), L = sum_c gY_c Y_c.
  * The table lookups are recomputed, not stored.  The derivative of the
  * piecewise-linear table interpolant is taken inside the bracketing
- * interval (one-sided at knots).  Errors: CMC_EINVAL, CMC_EDEVICE. */
+ * interval (one-sided at knots).  A cell without electrons gets zero
+ * cell gradients; n_cells = 0 does nothing, and then every array may be
+ * NULL.  Errors: CMC_EINVAL, CMC_EDEVICE. */
 cmc_status cmc_expected_yield_backward(cmc_tables t, int64_t n_cells, const double* Zstar,
                                        const double* n_e, const double* T_e, const int64_t* off,
                                        const double* px, const double* py, const double* pz,

@@ -332,9 +332,10 @@ static cmc_status yield_common(cmc_tables t, int64_t n_cells, const double* Zs, 
                                const char* who) {
     CMC_REQUIRE(t, CMC_EINVAL, "%s: tables is NULL", who);
     CMC_REQUIRE(n_cells >= 0, CMC_EINVAL, "%s: n_cells < 0", who);
-    CMC_REQUIRE(Zs && ne && Te && off && px && py && pz && w, CMC_EINVAL, "%s: NULL array", who);
     CMC_REQUIRE(dt > 0.0, CMC_EINVAL, "%s: dt must be > 0", who);
     CMC_REQUIRE(precision == CMC_FP64 || precision == CMC_FP32, CMC_EINVAL, "%s: unknown precision", who);
+    // with no cell nothing is read or written: the arrays may be NULL
+    CMC_REQUIRE(n_cells == 0 || (Zs && ne && Te && off && px && py && pz && w), CMC_EINVAL, "%s: NULL array", who);
     return CMC_OK;
 }
 
@@ -346,8 +347,8 @@ extern "C" cmc_status cmc_expected_yield(cmc_tables t, int64_t n_cells, const do
     cmc_status s = yield_common(t, n_cells, Zstar, n_e, T_e, off, px, py, pz, w, dt, precision,
                                 "cmc_expected_yield");
     if (s != CMC_OK) return s;
-    CMC_REQUIRE(Y, CMC_EINVAL, "cmc_expected_yield: Y is NULL");
     if (n_cells == 0) return CMC_OK;
+    CMC_REQUIRE(Y, CMC_EINVAL, "cmc_expected_yield: Y is NULL");
     YArgs A{};
     A.Zs = Zstar; A.ne = n_e; A.Te = T_e; A.off = off; A.px = px; A.py = py; A.pz = pz; A.w = w;
     A.Y = Y; A.yp = y_part; A.n_cells = n_cells; A.dt = dt;
@@ -371,9 +372,9 @@ extern "C" cmc_status cmc_expected_yield_backward(cmc_tables t, int64_t n_cells,
     cmc_status s = yield_common(t, n_cells, Zstar, n_e, T_e, off, px, py, pz, w, dt, precision,
                                 "cmc_expected_yield_backward");
     if (s != CMC_OK) return s;
+    if (n_cells == 0) return CMC_OK;
     CMC_REQUIRE(gY && gpx && gpy && gpz && gZstar && gn_e && gT_e, CMC_EINVAL,
                 "cmc_expected_yield_backward: NULL output");
-    if (n_cells == 0) return CMC_OK;
     YArgs A{};
     A.Zs = Zstar; A.ne = n_e; A.Te = T_e; A.off = off; A.px = px; A.py = py; A.pz = pz; A.w = w;
     A.gY = gY; A.gpx = gpx; A.gpy = gpy; A.gpz = gpz; A.gw = gw; A.gZs = gZstar; A.gne = gn_e;

@@ -37,5 +37,20 @@ def test_host_argument_errors_without_gpu():
                             None) == 1
     assert L.cmc_collide_step(None, None, None, None, None, None, None, None, None, None, 0, None) == 1
     assert L.cmc_expected_yield(None, 1, *([None] * 8), 1e-16, 0, None, None, None) == 1
+    # the expected-yield calls check their arguments before touching the
+    # tables (a placeholder handle is never dereferenced): no cell is a
+    # no-op with NULL arrays; cells need every array; dt and the precision
+    # are checked either way
+    t = C.c_void_p(1)
+    assert L.cmc_expected_yield(t, 0, *([None] * 8), 1e-16, 0, None, None, None) == 0
+    assert L.cmc_expected_yield_backward(t, 0, *([None] * 8), 1e-16, 1, *([None] * 8), None) == 0
+    assert L.cmc_expected_yield(t, 2, *([None] * 8), 1e-16, 0, None, None, None) == 1
+    assert b"NULL array" in L.cmc_last_error()
+    assert L.cmc_expected_yield_backward(t, 2, *([None] * 8), 1e-16, 0, *([None] * 8), None) == 1
+    assert L.cmc_expected_yield(t, 0, *([None] * 8), 0.0, 0, None, None, None) == 1
+    assert b"dt" in L.cmc_last_error()
+    assert L.cmc_expected_yield(t, 0, *([None] * 8), 1e-16, 7, None, None, None) == 1
+    assert b"precision" in L.cmc_last_error()
+    assert L.cmc_expected_yield(t, -1, *([None] * 8), 1e-16, 0, None, None, None) == 1
     assert L.cmc_tables_size(None, 0) == -1
     assert L.cmc_tables_free(None) == 0

@@ -139,3 +139,59 @@ def test_dense_cells_against_the_oracle(precision, rtol, rtol_g):
     b = np.stack([Go[k] for k in ("gpx", "gpy", "gpz")])
     err = np.sqrt(((a - b) ** 2).sum(0)); mag = np.sqrt((b ** 2).sum(0))
     assert np.all(err <= rtol_g * mag + 1e-300)
+
+
+def _ragged_inputs():
+    """Cells of 0, 1 and team-boundary sizes (the forward runs 256 threads
+    per cell, the adjoint 192), and one larger cell."""
+    counts = np.array([0, 1, 63, 64, 65, 191, 192, 193, 0, 255, 256, 257, 384, 1000, 2])
+    y = W.cfg4(np.random.default_rng(14), n_cells=len(counts), per_cell=int(counts.max()))
+    n = int(counts.sum())
+    off = np.zeros(len(counts) + 1, np.int64)
+    off[1:] = np.cumsum(counts)
+    for k in ("px", "py", "pz", "w"):
+        y[k] = np.ascontiguousarray(y[k][:n])
+    y["w"] = np.random.default_rng(15).lognormal(0.0, 0.5, n)
+    y["off"] = off
+    return y
+
+
+@pytest.mark.parametrize("precision,rtol,rtol_g", [(0, 1e-12, 1e-11), (1, 1e-5, 2e-5)])
+def test_ragged_and_empty_cells_against_the_oracle(precision, rtol, rtol_g):
+    import paper_1907_02814_amd as cmc
+    from gpu_parity import gpu_tables
+    y = _ragged_inputs()
+    g = _dev(y)
+    args = (g["Zstar"], g["n_e"], g["T_e"], g["off"], g["px"], g["py"], g["pz"], g["w"], y["dt"])
+    oargs = (y["Zstar"], y["n_e"], y["T_e"], y["off"], y["px"], y["py"], y["pz"], y["w"], y["dt"])
+    Y, yp = cmc.expected_yield(gpu_tables(29), *args, precision, per_particle=True)
+    Yo, ypo = O.expected_yield(O.tables(29), *oargs, per_particle=True)
+    empty = np.diff(y["off"]) == 0
+    assert np.all(Y.cpu().numpy()[empty] == 0.0)
+    np.testing.assert_allclose(Y.cpu().numpy(), Yo, rtol=rtol, atol=0)
+    np.testing.assert_allclose(yp.cpu().numpy(), ypo, rtol=rtol, atol=1e-300)
+    gY = np.linspace(0.5, 2.0, len(y["Zstar"]))
+    G = cmc.expected_yield_backward(gpu_tables(29), *args, _dev({"a": gY})["a"], precision)
+    Go = O.expected_yield_backward(O.tables(29), *oargs, gY)
+    for k in ("gZstar", "gn_e", "gT_e"):
+        assert np.all(G[k].cpu().numpy()[empty] == 0.0), k
+    for k in ("gZstar", "gn_e", "gT_e", "gw"):
+        a, b = G[k].cpu().numpy(), Go[k]
+        assert np.all(np.abs(a - b) <= rtol_g * np.abs(b) + 1e-300 + 1e-12 * rtol_g * np.abs(b).max()), k
+    a = np.stack([G[k].cpu().numpy() for k in ("gpx", "gpy", "gpz")])
+    b = np.stack([Go[k] for k in ("gpx", "gpy", "gpz")])
+    err = np.sqrt(((a - b) ** 2).sum(0)); mag = np.sqrt((b ** 2).sum(0))
+    assert np.all(err <= rtol_g * mag + 1e-300)
+
+
+def test_zero_cells_is_a_no_op():
+    import torch
+    import paper_1907_02814_amd as cmc
+    from gpu_parity import gpu_tables
+    z = torch.zeros(0, dtype=torch.float64, device="cuda")
+    off = torch.zeros(1, dtype=torch.int64, device="cuda")
+    for p in (cmc.FP64, cmc.FP32):
+        Y = cmc.expected_yield(gpu_tables(29), z, z, z, off, z, z, z, z, 1e-16, p)
+        G = cmc.expected_yield_backward(gpu_tables(29), z, z, z, off, z, z, z, z, 1e-16, z, p)
+        torch.cuda.synchronize()
+        assert Y.numel() == 0 and all(v.numel() == 0 for v in G.values())
