@@ -117,12 +117,16 @@ def _check(rc: int, what: str):
 _PLACEHOLDER = {}
 
 
-def _ptr(t) -> Optional[int]:
-    """Device pointer of a contiguous tensor (None -> NULL).  An empty tensor
-    (a species with no particles anywhere) gets a one-element placeholder so
-    that required arrays are never NULL; the kernels never address it."""
+def _ptr(t, dtype=None) -> Optional[int]:
+    """Device pointer of a contiguous tensor (None -> NULL) of the element
+    type the C ABI reads there (`dtype`, a torch dtype name, checked when
+    given).  An empty tensor (a species with no particles anywhere) gets a
+    one-element placeholder so that required arrays are never NULL; the
+    kernels never address it."""
     if t is None:
         return None
+    if dtype is not None and str(t.dtype) != "torch." + dtype:
+        raise TypeError(f"expected a {dtype} tensor, got {t.dtype}")
     if not t.is_contiguous():
         raise ValueError("tensors must be contiguous")
     if not t.is_cuda:
@@ -187,19 +191,20 @@ def pair_cells(a_off, a_cnt, b_off, b_cnt, wa, wb, seed, step, pass_, pair_off, 
     pa = torch.empty(max(n_pairs, 1), dtype=torch.int32, device=dev)
     pb = torch.empty(max(n_pairs, 1), dtype=torch.int32, device=dev)
     nab = torch.empty(max(n_cells, 1), dtype=torch.float64, device=dev)
-    _check(get_lib().cmc_pair_cells(n_cells, _ptr(a_off), _ptr(a_cnt), _ptr(b_off), _ptr(b_cnt),
-                              _ptr(wa), _ptr(wb), int(seed), int(step), int(pass_), _ptr(pair_off),
+    _check(get_lib().cmc_pair_cells(n_cells, _ptr(a_off, "int64"), _ptr(a_cnt, "int32"), _ptr(b_off, "int64"),
+                              _ptr(b_cnt, "int32"), _ptr(wa, "float64"), _ptr(wb, "float64"), int(seed),
+                              int(step), int(pass_), _ptr(pair_off, "int64"),
                               _ptr(pa), _ptr(pb), _ptr(nab), _stream(stream)), "cmc_pair_cells")
     return pa[:n_pairs], pb[:n_pairs], nab[:n_cells]
 
 
 def _species(d: Dict) -> _Species:
     s = _Species()
-    s.off = _ptr(d["off"])
-    s.count = _ptr(d.get("count"))
+    s.off = _ptr(d["off"], "int64")
+    s.count = _ptr(d.get("count"), "int32")
     for k in ("px", "py", "pz", "w"):
-        setattr(s, k, _ptr(d.get(k)))
-    s.parent = _ptr(d.get("parent"))
+        setattr(s, k, _ptr(d.get(k), "float64"))
+    s.parent = _ptr(d.get("parent"), "int64")
     return s
 
 
@@ -214,7 +219,8 @@ class StepState:
         self.tables = tables
         n = cells["Zstar"].numel()
         dev = cells["Zstar"].device
-        self.cells = _Cells(n, _ptr(cells["Zstar"]), _ptr(cells["n_i"]), _ptr(cells["T_e"]))
+        self.cells = _Cells(n, _ptr(cells["Zstar"], "float64"), _ptr(cells["n_i"], "float64"),
+                            _ptr(cells["T_e"], "float64"))
         self.sp = [_species(x) for x in (electrons, photons, ions, new_el, new_po)]
         if max_per_cell is None:
             def mx(d):
@@ -288,8 +294,10 @@ def expected_yield(tables: Tables, Zstar, n_e, T_e, off, px, py, pz, w, dt, prec
     n = Zstar.numel()
     Y = torch.empty(n, dtype=torch.float64, device=Zstar.device)
     yp = torch.empty_like(px) if per_particle else None
-    _check(get_lib().cmc_expected_yield(tables.handle, n, _ptr(Zstar), _ptr(n_e), _ptr(T_e), _ptr(off),
-                                  _ptr(px), _ptr(py), _ptr(pz), _ptr(w), float(dt), int(precision),
+    f8 = "float64"
+    _check(get_lib().cmc_expected_yield(tables.handle, n, _ptr(Zstar, f8), _ptr(n_e, f8), _ptr(T_e, f8),
+                                  _ptr(off, "int64"), _ptr(px, f8), _ptr(py, f8), _ptr(pz, f8), _ptr(w, f8),
+                                  float(dt), int(precision),
                                   _ptr(Y), _ptr(yp), _stream(stream)), "cmc_expected_yield")
     return (Y, yp) if per_particle else Y
 
@@ -299,9 +307,11 @@ def expected_yield_backward(tables: Tables, Zstar, n_e, T_e, off, px, py, pz, w,
     import torch
     out = {k: torch.empty_like(px) for k in ("gpx", "gpy", "gpz", "gw")}
     out.update({k: torch.empty_like(Zstar) for k in ("gZstar", "gn_e", "gT_e")})
+    f8 = "float64"
     _check(get_lib().cmc_expected_yield_backward(
-        tables.handle, Zstar.numel(), _ptr(Zstar), _ptr(n_e), _ptr(T_e), _ptr(off), _ptr(px),
-        _ptr(py), _ptr(pz), _ptr(w), float(dt), int(precision), _ptr(gY.contiguous()),
+        tables.handle, Zstar.numel(), _ptr(Zstar, f8), _ptr(n_e, f8), _ptr(T_e, f8), _ptr(off, "int64"),
+        _ptr(px, f8), _ptr(py, f8), _ptr(pz, f8), _ptr(w, f8), float(dt), int(precision),
+        _ptr(gY.contiguous(), f8),
         _ptr(out["gpx"]), _ptr(out["gpy"]), _ptr(out["gpz"]), _ptr(out["gw"]), _ptr(out["gZstar"]),
         _ptr(out["gn_e"]), _ptr(out["gT_e"]), _stream(stream)), "cmc_expected_yield_backward")
     return out

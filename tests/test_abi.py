@@ -54,3 +54,29 @@ def test_host_argument_errors_without_gpu():
     assert L.cmc_expected_yield(t, -1, *([None] * 8), 1e-16, 0, None, None, None) == 1
     assert L.cmc_tables_size(None, 0) == -1
     assert L.cmc_tables_free(None) == 0
+
+
+def test_binding_rejects_wrong_element_types():
+    # the binding checks the element type the C ABI reads before anything
+    # else (here on host tensors, so the first array of each call is the
+    # wrong one): float32 where doubles are read, int32 offsets
+    import pytest
+    import torch
+    import paper_1907_02814_amd as cmc
+    f4 = torch.zeros(4, dtype=torch.float32)
+    f8 = torch.zeros(4, dtype=torch.float64)
+    off32 = torch.zeros(3, dtype=torch.int32)
+    off64 = torch.zeros(3, dtype=torch.int64)
+
+    class T:
+        handle = None
+    with pytest.raises(TypeError, match="float64"):
+        cmc.expected_yield(T(), f4[:2], f8[:2], f8[:2], off64, f8, f8, f8, f8, 1e-16)
+    with pytest.raises(TypeError, match="float64"):
+        cmc.expected_yield_backward(T(), f4[:2], f8[:2], f8[:2], off64, f8, f8, f8, f8, 1e-16, f8[:2])
+    with pytest.raises(TypeError, match="int64"):
+        cmc.pair_cells(off32, off32[:2], off64, off32[:2], f8, f8, 1, 0, 1, off64)
+    with pytest.raises(TypeError, match="int64"):
+        cmc._species({"off": off32, "px": f8, "py": f8, "pz": f8, "w": f8})
+    with pytest.raises(TypeError, match="int32"):
+        cmc._species({"off": off64.cuda() if torch.cuda.is_available() else None, "count": off64})
