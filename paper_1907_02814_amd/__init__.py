@@ -140,6 +140,15 @@ def _ptr(t, dtype=None) -> Optional[int]:
     return t.data_ptr()
 
 
+def _lengths(**groups):
+    """Element counts that must agree (no device read): each keyword names
+    a group as (expected count, tensors...)."""
+    for name, (n, *ts) in groups.items():
+        for t in ts:
+            if t is not None and t.numel() != n:
+                raise ValueError(f"{name}: expected {n} elements, got {t.numel()}")
+
+
 def _stream(stream=None) -> Optional[int]:
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
@@ -186,6 +195,7 @@ def pair_cells(a_off, a_cnt, b_off, b_cnt, wa, wb, seed, step, pass_, pair_off, 
     """Pair indices of every cell (cmc_pair_cells); returns (pa, pb, n_ab)."""
     import torch
     n_cells = a_off.numel() - 1
+    _lengths(offsets=(n_cells + 1, a_off, b_off, pair_off), counts=(n_cells, a_cnt, b_cnt))
     n_pairs = int(pair_off[-1].item())
     dev = a_off.device
     pa = torch.empty(max(n_pairs, 1), dtype=torch.int32, device=dev)
@@ -219,6 +229,16 @@ class StepState:
         self.tables = tables
         n = cells["Zstar"].numel()
         dev = cells["Zstar"].device
+        _lengths(cells=(n, cells["n_i"], cells["T_e"]))
+        # every array must cover its species' offsets (read once, here)
+        for name, d in zip(("electrons", "photons", "ions", "new_el", "new_po"),
+                           (electrons, photons, ions, new_el, new_po)):
+            _lengths(**{f"{name} off": (n + 1, d["off"]), f"{name} count": (n, d.get("count"))})
+            end = int(d["off"][-1].item()) if d["off"].numel() else 0
+            for k in ("px", "py", "pz", "w", "parent"):
+                a = d.get(k)
+                if a is not None and a.numel() < end:
+                    raise ValueError(f"{name} {k}: {a.numel()} elements for offsets up to {end}")
         self.cells = _Cells(n, _ptr(cells["Zstar"], "float64"), _ptr(cells["n_i"], "float64"),
                             _ptr(cells["T_e"], "float64"))
         self.sp = [_species(x) for x in (electrons, photons, ions, new_el, new_po)]
@@ -292,6 +312,7 @@ def expected_yield(tables: Tables, Zstar, n_e, T_e, off, px, py, pz, w, dt, prec
                    per_particle=False, stream=None):
     import torch
     n = Zstar.numel()
+    _lengths(cells=(n, n_e, T_e), off=(n + 1, off), electrons=(px.numel(), py, pz, w))
     Y = torch.empty(n, dtype=torch.float64, device=Zstar.device)
     yp = torch.empty_like(px) if per_particle else None
     f8 = "float64"
@@ -305,6 +326,8 @@ def expected_yield(tables: Tables, Zstar, n_e, T_e, off, px, py, pz, w, dt, prec
 def expected_yield_backward(tables: Tables, Zstar, n_e, T_e, off, px, py, pz, w, dt, gY,
                             precision=FP64, stream=None):
     import torch
+    n = Zstar.numel()
+    _lengths(cells=(n, n_e, T_e, gY), off=(n + 1, off), electrons=(px.numel(), py, pz, w))
     out = {k: torch.empty_like(px) for k in ("gpx", "gpy", "gpz", "gw")}
     out.update({k: torch.empty_like(Zstar) for k in ("gZstar", "gn_e", "gT_e")})
     f8 = "float64"

@@ -80,3 +80,25 @@ def test_binding_rejects_wrong_element_types():
         cmc._species({"off": off32, "px": f8, "py": f8, "pz": f8, "w": f8})
     with pytest.raises(TypeError, match="int32"):
         cmc._species({"off": off64.cuda() if torch.cuda.is_available() else None, "count": off64})
+
+
+def test_binding_rejects_inconsistent_lengths():
+    import pytest
+    import torch
+    import paper_1907_02814_amd as cmc
+    f8 = torch.zeros(4, dtype=torch.float64)
+    off = torch.zeros(3, dtype=torch.int64)
+
+    class T:
+        handle = None
+    with pytest.raises(ValueError, match="cells"):
+        cmc.expected_yield(T(), f8[:2], f8[:3], f8[:2], off, f8, f8, f8, f8, 1e-16)
+    with pytest.raises(ValueError, match="off"):
+        cmc.expected_yield(T(), f8[:2], f8[:2], f8[:2], off[:2], f8, f8, f8, f8, 1e-16)
+    with pytest.raises(ValueError, match="electrons"):
+        cmc.expected_yield(T(), f8[:2], f8[:2], f8[:2], off, f8, f8[:3], f8, f8, 1e-16)
+    with pytest.raises(ValueError, match="cells"):
+        cmc.expected_yield_backward(T(), f8[:2], f8[:2], f8[:2], off, f8, f8, f8, f8, 1e-16, f8[:3])
+    cnt = torch.zeros(2, dtype=torch.int32)
+    with pytest.raises(ValueError, match="offsets"):
+        cmc.pair_cells(off, cnt, off[:2], cnt, f8, f8, 1, 0, 1, off)
