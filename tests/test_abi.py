@@ -102,3 +102,18 @@ def test_binding_rejects_inconsistent_lengths():
     cnt = torch.zeros(2, dtype=torch.int32)
     with pytest.raises(ValueError, match="offsets"):
         cmc.pair_cells(off, cnt, off[:2], cnt, f8, f8, 1, 0, 1, off)
+
+
+def test_missing_library_fails_loudly():
+    # no fallback: without the built HIP library every call raises
+    import pytest
+    import paper_1907_02814_amd as cmc
+    saved_path, saved_lib = cmc.LIB_PATH, cmc._LIB
+    try:
+        cmc.LIB_PATH, cmc._LIB = "/nonexistent/libcmc.so", None
+        with pytest.raises(ImportError, match="not built"):
+            cmc.get_lib()
+        with pytest.raises(ImportError):
+            cmc.build_tables(29)
+    finally:
+        cmc.LIB_PATH, cmc._LIB = saved_path, saved_lib
