@@ -60,7 +60,9 @@ enum {
     CMC_ST_GAMMA_HIGH = 2,  /* an energy above the table top (clamped)      */
     CMC_ST_BAD_CELL = 4,    /* Z* outside [0, Z], n_i <= 0 or T < 0: skipped */
     CMC_ST_BAD_WEIGHT = 8,  /* a negative or non-finite weight: cell skipped */
-    CMC_ST_TOO_LARGE = 16   /* a cell above max_per_cell: cell skipped       */
+    CMC_ST_TOO_LARGE = 16,  /* a cell above max_per_cell: cell skipped       */
+    CMC_ST_BAD_OFFSETS = 32 /* expected yield: a cell's offsets decrease or
+                               leave [0, n_part]: cell skipped               */
 };
 
 /* ------------------------------------------------------------------ */
@@ -105,6 +107,12 @@ typedef struct {
     const double* Zstar;   /* device [n_cells]: ionisation degree, 0 <= Z* <= Z */
     const double* n_i;     /* device [n_cells]: ion density for screening (eq:LDH) */
     const double* T_e;     /* device [n_cells]: temperature T_e = T_i, eV */
+    const int64_t* cell_id;/* device [n_cells]: global index of each cell, the
+                              cell word of every Philox counter (only its low
+                              32 bits are used); NULL = the position c.  With
+                              global indices a subset of the cells, or the
+                              cells split over several launches, draws the
+                              same numbers as one launch over all of them */
 } cmc_cells;
 
 typedef struct {
@@ -180,11 +188,13 @@ typedef struct {
 /* max(N_a, N_b).  Outputs (device): pa[pair_off[c]+j], pb[...] = local  */
 /* index (within the cell) of the a and b particle of pair j; n_ab       */
 /* (nullable) [n_cells] = sum_j min(W_a, W_b).                           */
+/* cell_id: device [n_cells] global cell indices keying the draws, or   */
+/* NULL = position (as in cmc_cells).                                    */
 /* Cells with more than CMC_MAX_PER_CELL particles of a species produce  */
 /* no pairs and set pa = pb = -1.                                        */
 /* Errors: CMC_EINVAL (null pointers, pass), CMC_EDEVICE.                */
 /* ------------------------------------------------------------------ */
-cmc_status cmc_pair_cells(int64_t n_cells, const int64_t* a_off, const int32_t* a_cnt,
+cmc_status cmc_pair_cells(int64_t n_cells, const int64_t* cell_id, const int64_t* a_off, const int32_t* a_cnt,
                           const int64_t* b_off, const int32_t* b_cnt,
                           const double* wa, const double* wb,
                           uint64_t seed, uint64_t step, uint32_t pass,
@@ -213,8 +223,10 @@ cmc_status cmc_pair_cells(int64_t n_cells, const int64_t* a_off, const int32_t* 
 /* required, capacity off[c+1]-off[c]); products are appended in pair    */
 /* order; a full buffer drops the product (counted, CMC_ST_OVERFLOW).    */
 /* Random numbers: Philox4x32-10 keyed by (seed) with counter            */
-/* (pair or particle index, cell, step, tag): results do not depend on   */
-/* the schedule or on how cells are split across launches or devices.   */
+/* (pair or particle index, cell, step, tag), the cell word taken from   */
+/* cells->cell_id: results do not depend on the schedule, and with       */
+/* global cell indices not on how cells are split across launches or    */
+/* devices (without cell_id each launch numbers its cells from 0).       */
 /* workspace: device scratch of cmc_step_workspace_bytes() bytes (may be */
 /* NULL when that is 0).                                                 */
 /* Errors: CMC_EINVAL (null or inconsistent pointers, dt <= 0, unknown  */
@@ -258,35 +270,44 @@ enum { CMC_SCHED_AUTO = 0, CMC_SCHED_CELL = 1, CMC_SCHED_GROUP = 2, CMC_SCHED_WA
 /*   Y_c = sum_j w_j P_j <k>_j,  P = 1 - exp(-n_i sigma_B(gamma) beta c dt), */
 /* each electron against the cell's ions at rest with n_i = n_e/Z*      */
 /* (eq:proba1, eq:LDH), <k> = sigma_k/sigma_B the mean photon energy of */
-/* the tabulated spectrum.  Zstar, n_e, T_e: device [n_cells] (Z* > 0); */
-/* off device [n_cells+1]; px..w device [off[n_cells]]; Y device        */
-/* [n_cells]; y_part device per-electron terms or NULL.                 */
+/* the tabulated spectrum.  Zstar, n_e, T_e: device [n_cells]; off      */
+/* device [n_cells+1]; px..w device [n_part] (n_part >= off[n_cells]);  */
+/* Y device [n_cells]; y_part device [n_part] per-electron terms or     */
+/* NULL; status device [1] or NULL, OR-ed with CMC_ST_* (caller clears).*/
 /* precision: CMC_FP64 or CMC_FP32 (table lookups in FP32, P and sums   */
-/* in FP64).  A cell without electrons gets Y = 0.  n_cells = 0 does    */
+/* in FP64).  A cell without electrons gets Y = 0.  Checked per cell on */
+/* the device: a cell whose offsets decrease or leave [0, n_part] is    */
+/* skipped (Y = 0, nothing else written; CMC_ST_BAD_OFFSETS), and a cell */
+/* with Z* outside (0, Z], n_e <= 0 or T_e < 0 (or a non-finite value)  */
+/* gets Y = 0 and zero terms (CMC_ST_BAD_CELL).  n_cells = 0 does       */
 /* nothing, and then every array may be NULL.                           */
-/* Errors: CMC_EINVAL, CMC_EDEVICE.                                     */
+/* Errors: CMC_EINVAL (NULL arrays, dt <= 0, n_part < 0, precision),    */
+/* CMC_EDEVICE.                                                         */
 /* ------------------------------------------------------------------ */
 cmc_status cmc_expected_yield(cmc_tables t, int64_t n_cells, const double* Zstar,
                               const double* n_e, const double* T_e, const int64_t* off,
-                              const double* px, const double* py, const double* pz,
+                              int64_t n_part, const double* px, const double* py, const double* pz,
                               const double* w, double dt, int32_t precision,
-                              double* Y, double* y_part, void* stream);
+                              double* Y, double* y_part, int32_t* status, void* stream);
 
 /* Adjoint of cmc_expected_yield for upstream gradient gY (device
- * [n_cells]): writes dL/dpx, dL/dpy, dL/dpz, dL/dw (per electron; gw may
- * be NULL) and dL/dZ*, dL/dn_e, dL/dT_e (per cell), L = sum_c gY_c Y_c.
- * The table lookups are recomputed, not stored.  The derivative of the
- * piecewise-linear table interpolant is taken inside the bracketing
- * interval (one-sided at knots).  A cell without electrons gets zero
- * cell gradients; n_cells = 0 does nothing, and then every array may be
- * NULL.  Errors: CMC_EINVAL, CMC_EDEVICE. */
+ * [n_cells]): writes dL/dpx, dL/dpy, dL/dpz, dL/dw (per electron, device
+ * [n_part]; gw may be NULL) and dL/dZ*, dL/dn_e, dL/dT_e (per cell),
+ * L = sum_c gY_c Y_c.  The table lookups are recomputed, not stored.  The
+ * derivative of the piecewise-linear table interpolant is taken inside the
+ * bracketing interval (one-sided at knots), the interval being located
+ * from the FP64 energy in both forms.  A cell without electrons gets zero
+ * cell gradients.  Cells are checked as in cmc_expected_yield: a cell with
+ * bad offsets is skipped (zero cell gradients, CMC_ST_BAD_OFFSETS), a bad
+ * cell gets zero gradients (CMC_ST_BAD_CELL).  n_cells = 0 does nothing,
+ * and then every array may be NULL.  Errors: CMC_EINVAL, CMC_EDEVICE. */
 cmc_status cmc_expected_yield_backward(cmc_tables t, int64_t n_cells, const double* Zstar,
                                        const double* n_e, const double* T_e, const int64_t* off,
-                                       const double* px, const double* py, const double* pz,
-                                       const double* w, double dt, int32_t precision,
-                                       const double* gY, double* gpx, double* gpy, double* gpz,
-                                       double* gw, double* gZstar, double* gn_e, double* gT_e,
-                                       void* stream);
+                                       int64_t n_part, const double* px, const double* py,
+                                       const double* pz, const double* w, double dt,
+                                       int32_t precision, const double* gY, double* gpx,
+                                       double* gpy, double* gpz, double* gw, double* gZstar,
+                                       double* gn_e, double* gT_e, int32_t* status, void* stream);
 
 #ifdef __cplusplus
 }

@@ -1010,7 +1010,7 @@ static int64_t pair_one_cell(int32_t na, int32_t nb, uint64_t seed, uint64_t ste
     return n;
 }
 
-int or_pair_cells(int64_t n_cells, const int64_t* a_off, const int32_t* a_cnt,
+int or_pair_cells(int64_t n_cells, const int64_t* cell_id, const int64_t* a_off, const int32_t* a_cnt,
                   const int64_t* b_off, const int32_t* b_cnt,
                   const double* wa, const double* wb,
                   uint64_t seed, uint64_t step, uint32_t pass,
@@ -1022,7 +1022,8 @@ int or_pair_cells(int64_t n_cells, const int64_t* a_off, const int32_t* a_cnt,
     for (int64_t c = 0; c < n_cells; c++) {
         int32_t na = a_cnt ? a_cnt[c] : (int32_t)(a_off[c + 1] - a_off[c]);
         int32_t nb = b_cnt ? b_cnt[c] : (int32_t)(b_off[c + 1] - b_off[c]);
-        int64_t n = pair_one_cell(na, nb, seed, step, (uint32_t)c, ta, tb,
+        uint32_t cell = (uint32_t)(cell_id ? cell_id[c] : c);
+        int64_t n = pair_one_cell(na, nb, seed, step, cell, ta, tb,
                                   pa + pair_off[c], pb + pair_off[c]);
         if (n_ab) {
             double s = 0.0;
@@ -1414,7 +1415,7 @@ static void cell_jacobian(const cellstate* s, double ne, cellgrad* G)
 
 static double yield_one(const or_tables* tb, const cellstate* s, double ni, double px, double py,
                         double pz, double w, double dt, double gout[3], double* gw, double gcell[3],
-                        const cellgrad* G, double gY)
+                        double gabs[3], const cellgrad* G, double gY)
 {
     double p2 = px * px + py * py + pz * pz, g = sqrt(1.0 + p2), gm1 = p2 / (g + 1.0);
     brems_lookup_t L; int high;
@@ -1450,6 +1451,20 @@ static double yield_one(const or_tables* tb, const cellstate* s, double ni, doub
             double dxq = x * G->dlnni[q] + ni * beta * CLIGHT * dt * ds;
             double dKq = (dk * L.sig - L.sk * ds) / (L.sig * L.sig);
             gcell[q] += gY * w * (Pp * dxq * K + P * dKq);
+            if (gabs) {
+                /* the size of the terms summed into gcell: the scale of its
+                 * rounding error under any order of summation (tests only) */
+                double ads, adk;
+                if (L.seg == SEG_NR) {
+                    ads = fabs(L.dsig_a * G->dlnLd[q]) + fabs(L.dsig_e * G->deta[q]);
+                    adk = fabs(L.dsk_a * G->dlnLd[q]) + fabs(L.dsk_e * G->deta[q]);
+                } else {
+                    ads = fabs(L.dsig_a * G->dlnLr[q]);
+                    adk = fabs(L.dsk_a * G->dlnLr[q]);
+                }
+                gabs[q] += fabs(gY * w) * (Pp * K * (fabs(x * G->dlnni[q]) + ni * beta * CLIGHT * dt * ads)
+                                           + P * (adk * L.sig + L.sk * ads) / (L.sig * L.sig));
+            }
         }
     }
     return y;
@@ -1471,7 +1486,7 @@ int or_expected_yield(const or_tables* t, int64_t n_cells, const double* Zs,
         cellstate s; cell_init(t, Zs[c], ni, T_e[c], &s);
         double acc = 0.0;
         for (int64_t j = off[c]; j < off[c + 1]; j++) {
-            double y = yield_one(t, &s, ni, px[j], py[j], pz[j], w[j], dt, NULL, NULL, NULL, NULL, 0.0);
+            double y = yield_one(t, &s, ni, px[j], py[j], pz[j], w[j], dt, NULL, NULL, NULL, NULL, NULL, 0.0);
             if (y_part) y_part[j] = y;
             acc += y;
         }
@@ -1485,7 +1500,7 @@ int or_expected_yield_backward(const or_tables* t, int64_t n_cells, const double
                       const double* px, const double* py, const double* pz,
                       const double* w, double dt, const double* gY,
                       double* gpx, double* gpy, double* gpz, double* gw,
-                      double* gZs, double* gne, double* gTe, int nthreads)
+                      double* gZs, double* gne, double* gTe, double* gabs, int nthreads)
 {
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
@@ -1497,14 +1512,15 @@ int or_expected_yield_backward(const or_tables* t, int64_t n_cells, const double
         double ni = n_e[c] / Zs[c];
         cellstate s; cell_init(t, Zs[c], ni, T_e[c], &s);
         cellgrad G; cell_jacobian(&s, n_e[c], &G);
-        double gc[3] = {0, 0, 0};
+        double gc[3] = {0, 0, 0}, ga[3] = {0, 0, 0};
         for (int64_t j = off[c]; j < off[c + 1]; j++) {
             double g3[3], gwj;
-            yield_one(t, &s, ni, px[j], py[j], pz[j], w[j], dt, g3, &gwj, gc, &G, gY[c]);
+            yield_one(t, &s, ni, px[j], py[j], pz[j], w[j], dt, g3, &gwj, gc, gabs ? ga : NULL, &G, gY[c]);
             gpx[j] = g3[0]; gpy[j] = g3[1]; gpz[j] = g3[2];
             if (gw) gw[j] = gwj;
         }
         gZs[c] = gc[0]; gne[c] = gc[1]; gTe[c] = gc[2];
+        if (gabs) { gabs[3 * c] = ga[0]; gabs[3 * c + 1] = ga[1]; gabs[3 * c + 2] = ga[2]; }
     }
     return 0;
 }

@@ -105,7 +105,8 @@ int or_lookup(const or_tables* t, double Zs, double ni, double T, double gamma_o
 int or_sample(const or_tables* t, double Zs, double ni, double T, double e1,
               int process, double xi1, double xi2, double out[2]);
 
-int or_pair_cells(int64_t n_cells, const int64_t* a_off, const int32_t* a_cnt,
+/* cell_id: global cell index keying Philox (NULL = position) */
+int or_pair_cells(int64_t n_cells, const int64_t* cell_id, const int64_t* a_off, const int32_t* a_cnt,
                   const int64_t* b_off, const int32_t* b_cnt,
                   const double* wa, const double* wb,
                   uint64_t seed, uint64_t step, uint32_t pass,
@@ -128,7 +129,9 @@ int or_expected_yield_backward(const or_tables* t, int64_t n_cells, const double
                       const double* px, const double* py, const double* pz,
                       const double* w, double dt, const double* gY,
                       double* gpx, double* gpy, double* gpz, double* gw,
-                      double* gZs, double* gne, double* gTe, int nthreads);
+                      double* gZs, double* gne, double* gTe,
+                      double* gabs /* [n_cells][3] sum of |terms| of each cell gradient, or NULL */,
+                      int nthreads);
 
 #ifdef __cplusplus
 }

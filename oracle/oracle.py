@@ -77,7 +77,7 @@ def lib():
         L.or_from_ion.argtypes = [_dp, d, _dp, _dp]
         L.or_lookup.argtypes = [vp, d, d, d, d, C.c_int, _dp]
         L.or_sample.argtypes = [vp, d, d, d, d, C.c_int, d, d, _dp]
-        L.or_pair_cells.argtypes = [i64, _i64p, _i32p, _i64p, _i32p, _dp, _dp, u64, u64, u32,
+        L.or_pair_cells.argtypes = [i64, _i64p, _i64p, _i32p, _i64p, _i32p, _dp, _dp, u64, u64, u32,
                                     _i64p, _i32p, _i32p, _dp]
         L.or_collide_step.argtypes = [vp, C.POINTER(_Cells), C.POINTER(_Species),
                                       C.POINTER(_Species), C.POINTER(_Species),
@@ -87,7 +87,7 @@ def lib():
                                         _dp, _dp, C.c_int]
         L.or_expected_yield_backward.argtypes = [vp, i64, _dp, _dp, _dp, _i64p, _dp, _dp, _dp,
                                                  _dp, d, _dp, _dp, _dp, _dp, _dp, _dp, _dp,
-                                                 _dp, C.c_int]
+                                                 _dp, _dp, C.c_int]
         _LIB = L
     return _LIB
 
@@ -259,8 +259,11 @@ def tables(Z):
 
 
 # ---------------------------------------------------------------- step
-def pair_cells(a_off, a_cnt, b_off, b_cnt, wa, wb, seed, step, pass_, pair_off):
+def pair_cells(a_off, a_cnt, b_off, b_cnt, wa, wb, seed, step, pass_, pair_off, cell_id=None):
+    """Pair indices of every cell; cell_id (int64, or None = position) is the
+    global cell index that keys the draws."""
     n_cells = len(a_off) - 1
+    cid = None if cell_id is None else np.ascontiguousarray(cell_id, np.int64)
     n_pairs = int(pair_off[-1])
     pa = np.zeros(max(n_pairs, 1), dtype=np.int32)
     pb = np.zeros(max(n_pairs, 1), dtype=np.int32)
@@ -269,7 +272,7 @@ def pair_cells(a_off, a_cnt, b_off, b_cnt, wa, wb, seed, step, pass_, pair_off):
     a_cnt = None if a_cnt is None else np.ascontiguousarray(a_cnt, np.int32)
     b_cnt = None if b_cnt is None else np.ascontiguousarray(b_cnt, np.int32)
     pair_off = np.ascontiguousarray(pair_off, np.int64)
-    rc = lib().or_pair_cells(n_cells, _p(a_off, _i64p), _p(a_cnt, _i32p), _p(b_off, _i64p),
+    rc = lib().or_pair_cells(n_cells, _p(cid, _i64p), _p(a_off, _i64p), _p(a_cnt, _i32p), _p(b_off, _i64p),
                              _p(b_cnt, _i32p), _p(_f64(wa)), _p(_f64(wb)), int(seed), int(step),
                              int(pass_), _p(pair_off, _i64p), _p(pa, _i32p), _p(pb, _i32p),
                              _p(nab))
@@ -321,15 +324,22 @@ def expected_yield(tab, Zs, n_e, T_e, off, px, py, pz, w, dt, per_particle=False
     return (Y, yp) if per_particle else Y
 
 
-def expected_yield_backward(tab, Zs, n_e, T_e, off, px, py, pz, w, dt, gY, nthreads=0):
+def expected_yield_backward(tab, Zs, n_e, T_e, off, px, py, pz, w, dt, gY, nthreads=0, scale=False):
+    """Adjoint of expected_yield; with scale=True also 'gabs': per cell and
+    cell gradient (Z*, n_e, T_e), the sum of the magnitudes of the terms it
+    is summed from (the scale of its rounding error in any summation order)."""
     n = len(Zs); m = len(px)
     arrs = [_f64(a) for a in (Zs, n_e, T_e, gY)]
     pa = [_f64(a) for a in (px, py, pz, w)]
     off = np.ascontiguousarray(off, np.int64)
     out = [np.zeros(m) for _ in range(4)] + [np.zeros(n) for _ in range(3)]
+    gabs = np.zeros((n, 3)) if scale else None
     lib().or_expected_yield_backward(tab.handle, n, _p(arrs[0]), _p(arrs[1]), _p(arrs[2]),
                                      _p(off, _i64p), _p(pa[0]), _p(pa[1]), _p(pa[2]), _p(pa[3]),
-                                     float(dt), _p(arrs[3]), *[_p(o) for o in out],
+                                     float(dt), _p(arrs[3]), *[_p(o) for o in out], _p(gabs),
                                      int(nthreads))
     keys = ["gpx", "gpy", "gpz", "gw", "gZstar", "gn_e", "gT_e"]
-    return dict(zip(keys, out))
+    res = dict(zip(keys, out))
+    if scale:
+        res["gabs"] = gabs
+    return res

@@ -25,7 +25,7 @@ BREMS, BH, TRIDENT = 1, 2, 4
 FP64, FP32 = 0, 1
 SCHED_AUTO, SCHED_CELL, SCHED_GROUP, SCHED_WAVE, SCHED_HYBRID = 0, 1, 2, 3, 4
 MAX_PER_CELL = 16384
-ST_OVERFLOW, ST_GAMMA_HIGH, ST_BAD_CELL, ST_BAD_WEIGHT, ST_TOO_LARGE = 1, 2, 4, 8, 16
+ST_OVERFLOW, ST_GAMMA_HIGH, ST_BAD_CELL, ST_BAD_WEIGHT, ST_TOO_LARGE, ST_BAD_OFFSETS = 1, 2, 4, 8, 16, 32
 I_NAMES = ["pairs_br", "pairs_tr", "pairs_bh", "ev_br", "ev_tr", "ev_bh",
            "near_br", "near_tr", "near_bh", "drop_ph", "drop_el", "drop_po"]
 D_NAMES = ["nab_ei", "nab_gi", "E_br", "E_tr", "E_bh", "dE_el", "dE_ph",
@@ -45,7 +45,7 @@ class CmcError(RuntimeError):
 
 
 class _Cells(C.Structure):
-    _fields_ = [("n_cells", C.c_int64), ("Zstar", _vp), ("n_i", _vp), ("T_e", _vp)]
+    _fields_ = [("n_cells", C.c_int64), ("Zstar", _vp), ("n_i", _vp), ("T_e", _vp), ("cell_id", _vp)]
 
 
 class _Species(C.Structure):
@@ -75,16 +75,17 @@ def _load():
     L.cmc_tables_size.argtypes = [_vp, C.c_int32]
     L.cmc_tables_size.restype = _i64
     L.cmc_tables_export.argtypes = [_vp, C.c_int32, _vp, _i64]
-    L.cmc_pair_cells.argtypes = [_i64, _vp, _vp, _vp, _vp, _vp, _vp, C.c_uint64, C.c_uint64,
+    L.cmc_pair_cells.argtypes = [_i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, C.c_uint64, C.c_uint64,
                                  C.c_uint32, _vp, _vp, _vp, _vp, _vp]
     L.cmc_collide_step.argtypes = [_vp, C.POINTER(_Cells), C.POINTER(_Species), C.POINTER(_Species),
                                    C.POINTER(_Species), C.POINTER(_Species), C.POINTER(_Species),
                                    C.POINTER(_StepParams), C.POINTER(_Tallies), _vp, C.c_size_t, _vp]
     L.cmc_step_workspace_bytes.argtypes = [_i64, C.c_int32]
     L.cmc_step_workspace_bytes.restype = C.c_size_t
-    L.cmc_expected_yield.argtypes = [_vp, _i64] + [_vp] * 8 + [C.c_double, C.c_int32, _vp, _vp, _vp]
-    L.cmc_expected_yield_backward.argtypes = ([_vp, _i64] + [_vp] * 8 + [C.c_double, C.c_int32]
-                                              + [_vp] * 8 + [_vp])
+    L.cmc_expected_yield.argtypes = ([_vp, _i64] + [_vp] * 4 + [_i64] + [_vp] * 4
+                                     + [C.c_double, C.c_int32, _vp, _vp, _vp, _vp])
+    L.cmc_expected_yield_backward.argtypes = ([_vp, _i64] + [_vp] * 4 + [_i64] + [_vp] * 4
+                                              + [C.c_double, C.c_int32] + [_vp] * 8 + [_vp, _vp])
     for name in ("cmc_build_tables", "cmc_tables_free", "cmc_tables_export", "cmc_pair_cells",
                  "cmc_collide_step", "cmc_expected_yield", "cmc_expected_yield_backward"):
         getattr(L, name).restype = C.c_int
@@ -191,17 +192,20 @@ def build_tables(Z: int, stream=None) -> Tables:
     return Tables(Z, stream)
 
 
-def pair_cells(a_off, a_cnt, b_off, b_cnt, wa, wb, seed, step, pass_, pair_off, stream=None):
-    """Pair indices of every cell (cmc_pair_cells); returns (pa, pb, n_ab)."""
+def pair_cells(a_off, a_cnt, b_off, b_cnt, wa, wb, seed, step, pass_, pair_off, stream=None, cell_id=None):
+    """Pair indices of every cell (cmc_pair_cells); returns (pa, pb, n_ab).
+    cell_id: int64 global cell indices keying the draws (None = position)."""
     import torch
     n_cells = a_off.numel() - 1
-    _lengths(offsets=(n_cells + 1, a_off, b_off, pair_off), counts=(n_cells, a_cnt, b_cnt))
+    _lengths(offsets=(n_cells + 1, a_off, b_off, pair_off), counts=(n_cells, a_cnt, b_cnt),
+             cell_id=(n_cells, cell_id))
     n_pairs = int(pair_off[-1].item())
     dev = a_off.device
     pa = torch.empty(max(n_pairs, 1), dtype=torch.int32, device=dev)
     pb = torch.empty(max(n_pairs, 1), dtype=torch.int32, device=dev)
     nab = torch.empty(max(n_cells, 1), dtype=torch.float64, device=dev)
-    _check(get_lib().cmc_pair_cells(n_cells, _ptr(a_off, "int64"), _ptr(a_cnt, "int32"), _ptr(b_off, "int64"),
+    _check(get_lib().cmc_pair_cells(n_cells, _ptr(cell_id, "int64"), _ptr(a_off, "int64"), _ptr(a_cnt, "int32"),
+                              _ptr(b_off, "int64"),
                               _ptr(b_cnt, "int32"), _ptr(wa, "float64"), _ptr(wb, "float64"), int(seed),
                               int(step), int(pass_), _ptr(pair_off, "int64"),
                               _ptr(pa), _ptr(pb), _ptr(nab), _stream(stream)), "cmc_pair_cells")
@@ -229,7 +233,7 @@ class StepState:
         self.tables = tables
         n = cells["Zstar"].numel()
         dev = cells["Zstar"].device
-        _lengths(cells=(n, cells["n_i"], cells["T_e"]))
+        _lengths(cells=(n, cells["n_i"], cells["T_e"], cells.get("cell_id")))
         # every array must cover its species' offsets (read once, here)
         for name, d in zip(("electrons", "photons", "ions", "new_el", "new_po"),
                            (electrons, photons, ions, new_el, new_po)):
@@ -240,7 +244,7 @@ class StepState:
                 if a is not None and a.numel() < end:
                     raise ValueError(f"{name} {k}: {a.numel()} elements for offsets up to {end}")
         self.cells = _Cells(n, _ptr(cells["Zstar"], "float64"), _ptr(cells["n_i"], "float64"),
-                            _ptr(cells["T_e"], "float64"))
+                            _ptr(cells["T_e"], "float64"), _ptr(cells.get("cell_id"), "int64"))
         self.sp = [_species(x) for x in (electrons, photons, ions, new_el, new_po)]
         if max_per_cell is None:
             def mx(d):
@@ -308,35 +312,64 @@ def collide_step(tables: Tables, cells, electrons, photons, ions, new_el, new_po
     return st.ti, st.td, st.status
 
 
+_OFF_OK = {}
+
+
+def _check_offsets(off, n_part):
+    """off must start at 0, never decrease and end at or below n_part.  The
+    check reads off from the device once per (tensor, version): repeated
+    calls on the same offsets do not wait for the device.  The kernels
+    check every cell again on the device (CMC_ST_BAD_OFFSETS)."""
+    import weakref
+    key = (id(off), off._version, int(n_part))
+    ref = _OFF_OK.get(key)
+    if ref is not None and ref() is off:
+        return
+    o = off.detach().cpu().numpy()
+    if o.size == 0 or o[0] != 0 or np.any(np.diff(o) < 0) or o[-1] > n_part:
+        raise ValueError("off must start at 0, be non-decreasing and end at or below the number of electrons "
+                         f"({n_part})")
+    if len(_OFF_OK) > 64:
+        _OFF_OK.clear()
+    _OFF_OK[key] = weakref.ref(off)
+
+
 def expected_yield(tables: Tables, Zstar, n_e, T_e, off, px, py, pz, w, dt, precision=FP64,
-                   per_particle=False, stream=None):
+                   per_particle=False, stream=None, status=None):
+    """Y[c] = sum_j w_j P_j <k>_j per cell (cmc_expected_yield).  status: an
+    optional int32 device tensor [1] OR-ed with CMC_ST_* bits (bad cells are
+    skipped with Y = 0)."""
     import torch
     n = Zstar.numel()
-    _lengths(cells=(n, n_e, T_e), off=(n + 1, off), electrons=(px.numel(), py, pz, w))
+    _lengths(cells=(n, n_e, T_e), off=(n + 1, off), electrons=(px.numel(), py, pz, w), status=(1, status))
+    _check_offsets(off, px.numel())
     Y = torch.empty(n, dtype=torch.float64, device=Zstar.device)
     yp = torch.empty_like(px) if per_particle else None
     f8 = "float64"
     _check(get_lib().cmc_expected_yield(tables.handle, n, _ptr(Zstar, f8), _ptr(n_e, f8), _ptr(T_e, f8),
-                                  _ptr(off, "int64"), _ptr(px, f8), _ptr(py, f8), _ptr(pz, f8), _ptr(w, f8),
-                                  float(dt), int(precision),
-                                  _ptr(Y), _ptr(yp), _stream(stream)), "cmc_expected_yield")
+                                  _ptr(off, "int64"), px.numel(), _ptr(px, f8), _ptr(py, f8), _ptr(pz, f8),
+                                  _ptr(w, f8), float(dt), int(precision),
+                                  _ptr(Y), _ptr(yp), _ptr(status, "int32"), _stream(stream)),
+           "cmc_expected_yield")
     return (Y, yp) if per_particle else Y
 
 
 def expected_yield_backward(tables: Tables, Zstar, n_e, T_e, off, px, py, pz, w, dt, gY,
-                            precision=FP64, stream=None):
+                            precision=FP64, stream=None, status=None):
     import torch
     n = Zstar.numel()
-    _lengths(cells=(n, n_e, T_e, gY), off=(n + 1, off), electrons=(px.numel(), py, pz, w))
+    _lengths(cells=(n, n_e, T_e, gY), off=(n + 1, off), electrons=(px.numel(), py, pz, w), status=(1, status))
+    _check_offsets(off, px.numel())
     out = {k: torch.empty_like(px) for k in ("gpx", "gpy", "gpz", "gw")}
     out.update({k: torch.empty_like(Zstar) for k in ("gZstar", "gn_e", "gT_e")})
     f8 = "float64"
     _check(get_lib().cmc_expected_yield_backward(
         tables.handle, Zstar.numel(), _ptr(Zstar, f8), _ptr(n_e, f8), _ptr(T_e, f8), _ptr(off, "int64"),
-        _ptr(px, f8), _ptr(py, f8), _ptr(pz, f8), _ptr(w, f8), float(dt), int(precision),
+        px.numel(), _ptr(px, f8), _ptr(py, f8), _ptr(pz, f8), _ptr(w, f8), float(dt), int(precision),
         _ptr(gY.contiguous(), f8),
         _ptr(out["gpx"]), _ptr(out["gpy"]), _ptr(out["gpz"]), _ptr(out["gw"]), _ptr(out["gZstar"]),
-        _ptr(out["gn_e"]), _ptr(out["gT_e"]), _stream(stream)), "cmc_expected_yield_backward")
+        _ptr(out["gn_e"]), _ptr(out["gT_e"]), _ptr(status, "int32"), _stream(stream)),
+        "cmc_expected_yield_backward")
     return out
 
 

@@ -200,6 +200,7 @@ struct SpeciesDev {
 struct StepArgs {
     SpeciesDev el, ph, io, ne, np;
     const double *Zs, *ni, *Te;
+    const int64_t* cid;         // global cell indices (NULL: the position)
     int64_t n_cells;
     double dt, near_rel;
     Rng rng;
@@ -212,6 +213,11 @@ struct StepArgs {
     const int32_t* list_n;
     const uint64_t* step_dev;   // non-NULL: the step number is read from device memory
 };
+
+// the cell word of the Philox counters of cell c: its global index
+__device__ __forceinline__ uint32_t cell_word(const int64_t* cid, int64_t c) {
+    return (uint32_t)(cid ? cid[c] : c);
+}
 
 // the generator of the step (step from device memory when it is there)
 __device__ __forceinline__ Rng step_rng(const StepArgs& A) {
@@ -436,7 +442,7 @@ __device__ __forceinline__ void collide_cell(const StepArgs& A, const TabView<R>
     uint32_t* redu = sh.redu;
     CellShared<R>& cs = sh.cs;
     const int tid = threadIdx.x;
-    const uint32_t cell = (uint32_t)c;
+    const uint32_t cell = cell_word(A.cid, c);
     const int Ne = live(A.el, c), Ng0 = live(A.ph, c), Ni = live(A.io, c);
     const int64_t e0 = A.el.off[c], g0 = A.ph.off[c], i0 = A.io.off[c];
     const double Zs = A.Zs[c], nic = A.ni[c], Te = A.Te[c];
@@ -1338,9 +1344,9 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
     const Rng rng = step_rng(A);
 
     for (int64_t c = (int64_t)blockIdx.x * kTeams + team; c < A.n_cells; c += (int64_t)gridDim.x * kTeams) {
-        const uint32_t cell = (uint32_t)c;
         // the cell's parameters in one round of loads: its state, the
-        // offsets and live counts of the three species
+        // offsets and live counts of the three species, its global index
+        const uint32_t cell = cell_word(A.cid, c);
         const int32_t cstat = W.cs[c].status;
         const CellTab<R> ct_c = pick<R>(W.cs[c]);
         const int64_t eo0 = A.el.off[c], eo1 = A.el.off[c + 1], go0 = A.ph.off[c], go1 = A.ph.off[c + 1];
@@ -1830,6 +1836,7 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
         const CellTab<double> ct64 = W.cs[c].d;
         const CellTab<R> ct = pick<R>(W.cs[c]);
         const double coef0 = W.coef[c * 2], coef1 = W.coef[c * 2 + 1];
+        const uint32_t cell = cell_word(A.cid, c);
         const bool slow = (flg & kFlagSlow) != 0;
         // ctl is read by the other wavefronts only after the barrier that
         // ends wavefront 0's work; wavefront 0 may set ctl[0..3] meanwhile
@@ -1858,7 +1865,6 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
         }
         // Wavefront 0 settles the open pairs; its lanes keep the pair's
         // particle, ion and FP64 lookup for the sampling after the barrier.
-        const uint32_t cell = (uint32_t)c;
         const int nc = min(ncr, kCandCap);
         const bool cand = lane < nc;
         uint64_t mine = 0ull;
@@ -2218,7 +2224,7 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
 
 // ------------------------------------------------------------------ pair_cells
 struct PairArgs {
-    const int64_t *a_off, *b_off, *pair_off;
+    const int64_t *a_off, *b_off, *pair_off, *cid;
     const int32_t *a_cnt, *b_cnt;
     const double *wa, *wb;
     int32_t *pa, *pb;
@@ -2248,8 +2254,9 @@ __global__ __launch_bounds__(kThreads) void k_pair(PairArgs A) {
         }
         double part = 0.0;
         if (N > 0) {
-            key_order(na, (uint32_t)c, A.tag_a, A.rng, S.keys, S.pm, S.bcnt, redu);
-            key_order(nb, (uint32_t)c, A.tag_b, A.rng, S.keys, S.pi, S.bcnt, redu);
+            const uint32_t cell = cell_word(A.cid, c);
+            key_order(na, cell, A.tag_a, A.rng, S.keys, S.pm, S.bcnt, redu);
+            key_order(nb, cell, A.tag_b, A.rng, S.keys, S.pi, S.bcnt, redu);
             for (int j = threadIdx.x; j < N; j += kThreads) {
                 const int a = S.pm[j % na], b = S.pi[j % nb];
                 A.pa[po + j] = a; A.pb[po + j] = b;
@@ -2470,7 +2477,7 @@ extern "C" cmc_status cmc_collide_step(cmc_tables t, const cmc_cells* cells, cmc
                 "cmc_collide_step: ions: px, py, pz must be all set (moving) or all NULL (at rest)");
     if ((s = set_species(A.ne, new_el, "new_el", true, true)) != CMC_OK) return s;
     if ((s = set_species(A.np, new_po, "new_po", true, true)) != CMC_OK) return s;
-    A.Zs = cells->Zstar; A.ni = cells->n_i; A.Te = cells->T_e;
+    A.Zs = cells->Zstar; A.ni = cells->n_i; A.Te = cells->T_e; A.cid = cells->cell_id;
     A.n_cells = cells->n_cells;
     A.dt = P->dt; A.near_rel = P->near_rel;
     A.rng.k0 = (uint32_t)P->seed; A.rng.k1 = (uint32_t)(P->seed >> 32);
@@ -2555,7 +2562,7 @@ extern "C" cmc_status cmc_collide_step(cmc_tables t, const cmc_cells* cells, cmc
     return CMC_OK;
 }
 
-extern "C" cmc_status cmc_pair_cells(int64_t n_cells, const int64_t* a_off, const int32_t* a_cnt,
+extern "C" cmc_status cmc_pair_cells(int64_t n_cells, const int64_t* cell_id, const int64_t* a_off, const int32_t* a_cnt,
                                      const int64_t* b_off, const int32_t* b_cnt, const double* wa,
                                      const double* wb, uint64_t seed, uint64_t step, uint32_t pass,
                                      const int64_t* pair_off, int32_t* pa, int32_t* pb, double* n_ab,
@@ -2565,7 +2572,7 @@ extern "C" cmc_status cmc_pair_cells(int64_t n_cells, const int64_t* a_off, cons
     CMC_REQUIRE(pass == 1 || pass == 2, CMC_EINVAL, "cmc_pair_cells: pass must be 1 or 2");
     if (n_cells == 0) return CMC_OK;
     PairArgs A{};
-    A.a_off = a_off; A.b_off = b_off; A.pair_off = pair_off; A.a_cnt = a_cnt; A.b_cnt = b_cnt;
+    A.a_off = a_off; A.b_off = b_off; A.pair_off = pair_off; A.cid = cell_id; A.a_cnt = a_cnt; A.b_cnt = b_cnt;
     A.wa = wa; A.wb = wb; A.pa = pa; A.pb = pb; A.nab = n_ab; A.n_cells = n_cells;
     A.rng.k0 = (uint32_t)seed; A.rng.k1 = (uint32_t)(seed >> 32);
     A.rng.step_lo = (uint32_t)step; A.rng.step_hi = (uint32_t)(step >> 32);

@@ -33,25 +33,32 @@ def test_host_argument_errors_without_gpu():
     assert b"Z = 0" in L.cmc_last_error()
     assert L.cmc_build_tables(101, None, C.byref(h)) == 1
     assert L.cmc_build_tables(29, None, None) == 1
-    assert L.cmc_pair_cells(1, None, None, None, None, None, None, 1, 0, 1, None, None, None, None,
-                            None) == 1
+    assert L.cmc_pair_cells(1, None, None, None, None, None, None, None, 1, 0, 1, None, None, None,
+                            None, None) == 1
     assert L.cmc_collide_step(None, None, None, None, None, None, None, None, None, None, 0, None) == 1
-    assert L.cmc_expected_yield(None, 1, *([None] * 8), 1e-16, 0, None, None, None) == 1
+    assert L.cmc_expected_yield(None, 1, *([None] * 4), 0, *([None] * 4), 1e-16, 0, None, None, None, None) == 1
     # the expected-yield calls check their arguments before touching the
     # tables (a placeholder handle is never dereferenced): no cell is a
     # no-op with NULL arrays; cells need every array; dt and the precision
     # are checked either way
     t = C.c_void_p(1)
-    assert L.cmc_expected_yield(t, 0, *([None] * 8), 1e-16, 0, None, None, None) == 0
-    assert L.cmc_expected_yield_backward(t, 0, *([None] * 8), 1e-16, 1, *([None] * 8), None) == 0
-    assert L.cmc_expected_yield(t, 2, *([None] * 8), 1e-16, 0, None, None, None) == 1
-    assert b"NULL array" in L.cmc_last_error()
-    assert L.cmc_expected_yield_backward(t, 2, *([None] * 8), 1e-16, 0, *([None] * 8), None) == 1
-    assert L.cmc_expected_yield(t, 0, *([None] * 8), 0.0, 0, None, None, None) == 1
+    assert L.cmc_expected_yield(t, 0, *([None] * 4), 0, *([None] * 4), 1e-16, 0, None, None, None, None) == 0
+    assert L.cmc_expected_yield_backward(t, 0, *([None] * 4), 0, *([None] * 4), 1e-16, 1, *([None] * 8), None, None) == 0
+    assert L.cmc_expected_yield(t, 2, *([None] * 4), 0, *([None] * 4), 1e-16, 0, None, None, None, None) == 1
+    assert b"NULL cell array" in L.cmc_last_error()
+    # cells with particles need the particle arrays; n_part < 0 is refused
+    assert L.cmc_expected_yield(t, 2, *([C.c_void_p(8)] * 4), 3, *([None] * 4), 1e-16, 0, None, None,
+                                None, None) == 1
+    assert b"NULL particle array" in L.cmc_last_error()
+    assert L.cmc_expected_yield(t, 0, *([None] * 4), -1, *([None] * 4), 1e-16, 0, None, None, None,
+                                None) == 1
+    assert b"n_part" in L.cmc_last_error()
+    assert L.cmc_expected_yield_backward(t, 2, *([None] * 4), 0, *([None] * 4), 1e-16, 0, *([None] * 8), None, None) == 1
+    assert L.cmc_expected_yield(t, 0, *([None] * 4), 0, *([None] * 4), 0.0, 0, None, None, None, None) == 1
     assert b"dt" in L.cmc_last_error()
-    assert L.cmc_expected_yield(t, 0, *([None] * 8), 1e-16, 7, None, None, None) == 1
+    assert L.cmc_expected_yield(t, 0, *([None] * 4), 0, *([None] * 4), 1e-16, 7, None, None, None, None) == 1
     assert b"precision" in L.cmc_last_error()
-    assert L.cmc_expected_yield(t, -1, *([None] * 8), 1e-16, 0, None, None, None) == 1
+    assert L.cmc_expected_yield(t, -1, *([None] * 4), 0, *([None] * 4), 1e-16, 0, None, None, None, None) == 1
     assert L.cmc_tables_size(None, 0) == -1
     assert L.cmc_tables_free(None) == 0
 
@@ -102,6 +109,27 @@ def test_binding_rejects_inconsistent_lengths():
     cnt = torch.zeros(2, dtype=torch.int32)
     with pytest.raises(ValueError, match="offsets"):
         cmc.pair_cells(off, cnt, off[:2], cnt, f8, f8, 1, 0, 1, off)
+    with pytest.raises(ValueError, match="cell_id"):
+        cmc.pair_cells(off, cnt, off, cnt, f8, f8, 1, 0, 1, off, cell_id=off)
+
+
+def test_binding_rejects_bad_yield_offsets():
+    # offsets that decrease, do not start at 0 or pass the end of the
+    # electron arrays are refused before any launch (the kernels check
+    # every cell again on the device)
+    import pytest
+    import torch
+    import paper_1907_02814_amd as cmc
+    f8 = torch.zeros(4, dtype=torch.float64)
+
+    class T:
+        handle = None
+    for bad in ([0, 3, 2], [1, 2, 4], [0, 2, 5]):
+        off = torch.tensor(bad, dtype=torch.int64)
+        with pytest.raises(ValueError, match="non-decreasing"):
+            cmc.expected_yield(T(), f8[:2], f8[:2], f8[:2], off, f8, f8, f8, f8, 1e-16)
+        with pytest.raises(ValueError, match="non-decreasing"):
+            cmc.expected_yield_backward(T(), f8[:2], f8[:2], f8[:2], off, f8, f8, f8, f8, 1e-16, f8[:2])
 
 
 def test_missing_library_fails_loudly():
