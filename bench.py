@@ -1,6 +1,6 @@
 """Benchmark of the Coulomb-process Monte Carlo step on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg2]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg5]
 
 Prints one JSON line: pair evaluations per second over the K timed steps
 (the pair tests of all processes, summed; inputs resident in HBM), the FP32
@@ -28,11 +28,17 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "pair evaluations/sec + % HBM peak; FP32-batched vs FP64-plain at 1e-5 rel err"
-COUNTERS = os.path.join(ROOT, "profiles", "k_pass_bh_cfg2_counters.txt")
+COUNTERS = {"cfg2": os.path.join(ROOT, "profiles", "k_pass_bh_cfg2_counters.txt"),
+            "cfg5": os.path.join(ROOT, "profiles", "k_pass_cfg5_counters.txt")}
+CFG5_SAMPLE = 1024             # seeded cells of cfg5 the oracle runs (global cell ids)
 COPY_BYTES = 1 << 30
 HIP_EVENT_DISABLE_SYSTEM_FENCE = 0x20000000
 
 WORKLOADS = {
+    "cfg5": ("Foil-transport scale, Bremsstrahlung -> Bethe-Heitler chain: 131072 cells x (4096 electrons "
+             "+ 4096 Au ions), Z* = 5, n_i = 5.9e22 cm^-3, T_e = 1 eV, electrons Maxwell-Juttner T = 5 MeV "
+             "(isotropic, W_e = 1.5e19 cm^-3/4096), photon/e-/e+ slabs 2 x 4096 per cell, dt = 0.05 fs; "
+             "generated in HBM"),
     "cfg2": ("Bethe-Heitler pairs, FP32 tables + FP64 tallies: 4096 cells x (1024 photons + "
              "1024 Au ions), Z* ~ U[0,79] per cell, n_i = 5.9e22 cm^-3, T_e log-uniform "
              "10 eV-10 keV, photon energy 1.022 MeV + Exp(5 MeV), log-normal weights, dt = 0.1 fs"),
@@ -53,27 +59,6 @@ def source_digest():
             with open(os.path.join(d, f), "rb") as fh:
                 h.update(f.encode() + b"\0" + fh.read())
     return h.hexdigest()
-
-
-def algorithmic_bytes(wl):
-    """Bytes the pair tests of one step must move: one read of every live
-    record per pass (mobile px, py, pz, w = 32 B; ion w = 8 B) and the
-    per-cell tallies the passes write (pairs and n_ab: 16 B per pass)."""
-    ne = int(np.diff(wl.electrons["off"]).sum())
-    ng = int(wl.photons["count"].sum())
-    ni = int(np.diff(wl.ions["off"]).sum())
-    b = 0
-    if wl.processes & 5:
-        b += 32 * ne + 8 * ni + 16 * wl.n_cells
-    if wl.processes & 2:
-        b += 32 * ng + 8 * ni + 16 * wl.n_cells
-    return b
-
-
-def step_bytes(wl):
-    """Whole-step algorithmic bytes: the passes plus the cell parameters
-    (24 B) and the full tally rows (12 * 8 + 10 * 8 B) per cell."""
-    return algorithmic_bytes(wl) + wl.n_cells * (24 + 12 * 8 + 10 * 8)
 
 
 class HipEvents:
@@ -116,14 +101,29 @@ class HipEvents:
             self.lib.hipEventDestroy(ctypes.c_void_p(e))
 
 
-def run_gpu(wl, precision, steps, warmup, schedule, seed=1):
+def make_workload(name, W):
+    """The workload in device memory: cfg5 is generated there (125 GB),
+    the others on the host and copied."""
+    if name == "cfg5":
+        return W.cfg5_device("cuda:0")
+    return getattr(W, name)().to_torch("cuda:0")
+
+
+def run_gpu(make, precision, steps, warmup, schedule, seed=1):
+    """K timed steps of a fresh copy of the workload (make() builds it in
+    device memory), then K more whose pair-test launches stamp HIP events
+    (the kernel durations).  Each timed step writes its integer tallies to
+    a row of its own (the pass kernels count the pairs they test), so the
+    pair evaluations of the timed steps are summed afterwards, outside the
+    timed region."""
     import torch
     import paper_1907_02814_amd as cmc
-    dev = torch.device("cuda:0")
-    g = wl.copy().to_torch(dev)
-    tab = cmc.build_tables(wl.Z)
-    st = cmc.StepState(tab, g.cells, g.electrons, g.photons, g.ions, g.new_el, g.new_po, dt=wl.dt,
-                       seed=seed, processes=wl.processes, precision=precision, schedule=schedule)
+    g = make()
+    tab = cmc.build_tables(g.Z)
+    st = cmc.StepState(tab, g.cells, g.electrons, g.photons, g.ions, g.new_el, g.new_po, dt=g.dt,
+                       seed=seed, processes=g.processes, precision=precision, schedule=schedule)
+    n = g.cells["Zstar"].numel()
+    rows = torch.zeros((steps, n, len(cmc.I_NAMES)), dtype=torch.int64, device="cuda:0")
     stream = torch.cuda.current_stream()
     H = HipEvents()
     evs = H.create(2 * steps)
@@ -133,42 +133,64 @@ def run_gpu(wl, precision, steps, warmup, schedule, seed=1):
     # the K timed steps, as a user runs them
     t0 = time.perf_counter()
     for i in range(steps):
+        st.set_tallies(ti=rows[i])
         st.step(warmup + i, stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    st.set_tallies(ti=None)
+    evals = int(rows[:, :, 0:3].sum().item())
+    events = rows[:, :, 3:6].sum((0, 1)).tolist()
+    del rows
     # K more steps whose pair-test launches stamp HIP events at their start
     # and end (on their stream): the kernel durations.  These steps are kept
     # apart from the ones whose wall time gives the throughput.
-    torch.cuda.synchronize()
+    # (the photons live before each of them, for its algorithmic bytes, are
+    # counted between the steps, outside the stamped kernels)
+    ng = torch.zeros(steps, dtype=torch.int64, device="cuda:0")
     t1 = time.perf_counter()
     for i in range(steps):
+        ng[i] = g.photons["count"].sum()
         st.step(warmup + steps + i, stream, events=(evs[2 * i], evs[2 * i + 1]))
     torch.cuda.synchronize()
     wall_ev = time.perf_counter() - t1
     pass_ms = [H.elapsed_ms(evs[2 * i], evs[2 * i + 1]) for i in range(steps)]
     H.destroy(evs)
     status = int(st.status.item())
-    # pair evaluations of the timed steps, counted step by step in a second,
-    # untimed run of the same steps from the same state
-    g2 = wl.copy().to_torch(dev)
-    st2 = cmc.StepState(tab, g2.cells, g2.electrons, g2.photons, g2.ions, g2.new_el, g2.new_po,
-                        dt=wl.dt, seed=seed, processes=wl.processes, precision=precision, schedule=schedule)
-    for s in range(warmup):
-        st2.step(s)
-    evals = 0
-    for i in range(steps):
-        st2.step(warmup + i)
-        evals += int(st2.ti[:, 0:3].sum().item())
+    alg = algorithmic_bytes_dev(g, float(ng.double().mean().item()))
+    step_b = alg + g.cells["Zstar"].numel() * (24 + 12 * 8 + 10 * 8)
+    del st, g
+    torch.cuda.empty_cache()
     return {"wall_s": wall, "wall_events_s": wall_ev, "pass_ms": pass_ms, "evals": evals, "status": status,
-            "events": st.ti[:, 3:6].sum(0).tolist()}
+            "events": events, "alg_bytes": alg, "step_bytes": step_b}
 
 
-def stored_traffic(kernel_ms_unused=None):
-    """HBM bytes per launch of the pass kernel from the stored counter runs
+def algorithmic_bytes_dev(g, ng):
+    """Bytes the pair tests of one step must move, for a device workload
+    with ng live photons (the mean over the measured steps): one read of
+    every live record per pass (mobile px, py, pz, w = 32 B; ion w = 8 B)
+    and the per-cell tallies the passes write (pairs and n_ab: 16 B per
+    pass).  The whole step adds the cell parameters (24 B) and the full
+    tally rows (12 * 8 + 10 * 8 B) per cell."""
+    ne = int((g.electrons["off"][-1] - g.electrons["off"][0]).item())
+    ni = int((g.ions["off"][-1] - g.ions["off"][0]).item())
+    n = g.cells["Zstar"].numel()
+    b = 0
+    if g.processes & 5:
+        b += 32 * ne + 8 * ni + 16 * n
+    if g.processes & 2:
+        b += 32 * ng + 8 * ni + 16 * n
+    return b
+
+
+def stored_traffic(workload):
+    """HBM bytes per step of the pass kernels from the stored counter runs
     (FETCH_SIZE + WRITE_SIZE, each scaled by the same counter on a copy of
     known size), or None when absent or taken on other kernel sources."""
+    path = COUNTERS.get(workload)
+    if path is None:
+        return None
     try:
-        with open(COUNTERS) as fh:
+        with open(path) as fh:
             kv = dict(l.split(":", 1) for l in fh if ":" in l and not l.startswith("#"))
         kv = {k.strip(): v.strip() for k, v in kv.items()}
         if kv.get("source_sha256") != source_digest():
@@ -180,10 +202,9 @@ def stored_traffic(kernel_ms_unused=None):
         return None
 
 
-def cpu_baseline(wl, budget_s=12.0, seed=1):
+def _oracle_rate(wl, cores, budget_s, seed):
     from oracle import oracle as O
     tab = O.tables(wl.Z)
-    cores = len(os.sched_getaffinity(0))
     ref = wl.copy()
     evals = 0
     steps = 0
@@ -196,9 +217,21 @@ def cpu_baseline(wl, budget_s=12.0, seed=1):
         el = time.perf_counter() - t0
         if el > budget_s or steps >= 1000:
             break
-    return {"value": evals / el, "unit": "pair-evals/s", "cores": cores, "kind": "oracle",
-            "sample": f"{steps} step(s) of all {wl.n_cells} cells of the same workload, "
-                      f"{evals} pair evaluations in {el:.2f} s (FP64, OpenMP over cells)"}
+    return evals / el, steps, evals, el
+
+
+def cpu_baseline(wl, what, budget_s=12.0, seed=1):
+    """The FP64 oracle on the host cores, on `wl` (a host workload: the
+    whole workload, or the seeded sample of cfg5's cells with their global
+    ids, so that it draws the numbers the GPU run draws there), stepping
+    from step 0 for about budget_s; then on one core for a third of that."""
+    cores = len(os.sched_getaffinity(0))
+    v, steps, evals, el = _oracle_rate(wl, cores, budget_s, seed)
+    v1, steps1, evals1, el1 = _oracle_rate(wl, 1, budget_s / 3.0, seed)
+    return {"value": v, "unit": "pair-evals/s", "cores": cores, "kind": "oracle",
+            "sample": f"{steps} step(s) of {what}, {evals} pair evaluations in {el:.2f} s "
+                      f"(FP64, OpenMP over cells)",
+            "one_core": {"value": v1, "steps": steps1, "seconds": el1}}
 
 
 YIELD_WORKLOAD = ("cfg4: expected yield and its adjoint, 1024 cells x 4096 electrons (FP64 momenta), "
@@ -286,9 +319,9 @@ def copy_calibration():
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="cfg2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="cfg5", choices=sorted(WORKLOADS))
     ap.add_argument("--schedule", default="auto", choices=["auto", "group", "wave", "hybrid", "cell"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 plain comparison")
@@ -308,48 +341,62 @@ def main():
     from paper_1907_02814_amd import workloads as W
     sched = {"auto": cmc.SCHED_AUTO, "group": cmc.SCHED_GROUP, "wave": cmc.SCHED_WAVE,
              "hybrid": cmc.SCHED_HYBRID, "cell": cmc.SCHED_CELL}[a.schedule]
-    print(f"[bench] generating {a.workload}", file=sys.stderr, flush=True)
-    wl = getattr(W, a.workload)()
-    fp32 = run_gpu(wl, cmc.FP32, a.steps, a.warmup, sched)
+    print(f"[bench] {a.workload}", file=sys.stderr, flush=True)
+    make = lambda: make_workload(a.workload, W)
+    if a.workload == "cfg5":
+        # the oracle's sample: seeded cells of the same initial state
+        g0 = make()
+        sample = np.sort(np.random.default_rng(1005).choice(g0.cells["Zstar"].numel(), CFG5_SAMPLE, replace=False))
+        host_wl = g0.host_subset(sample)
+        what = f"{CFG5_SAMPLE} seeded cells of the same workload (global cell ids)"
+        del g0
+        import torch
+        torch.cuda.empty_cache()
+    else:
+        host_wl = getattr(W, a.workload)()
+        what = f"all {host_wl.n_cells} cells of the same workload"
+    fp32 = run_gpu(make, cmc.FP32, a.steps, a.warmup, sched)
     print(f"[bench] fp32 done: {fp32['wall_s'] * 1e3 / a.steps:.3f} ms/step", file=sys.stderr, flush=True)
-    fp64 = None if a.no_fp64 else run_gpu(wl, cmc.FP64, a.steps, a.warmup, sched)
+    fp64 = None if a.no_fp64 else run_gpu(make, cmc.FP64, a.steps, a.warmup, sched)
     if fp64:
         print(f"[bench] fp64 done: {fp64['wall_s'] * 1e3 / a.steps:.3f} ms/step", file=sys.stderr, flush=True)
     kavg = float(np.mean(fp32["pass_ms"]))
-    alg = algorithmic_bytes(wl)
+    alg = fp32["alg_bytes"]
     achieved = alg / (kavg * 1e-3) / 1e9
     ms = fp32["wall_s"] * 1e3 / a.steps
     value = fp32["evals"] / fp32["wall_s"]
-    traffic = stored_traffic() if a.workload == "cfg2" and a.schedule == "auto" else None
+    traffic = stored_traffic(a.workload) if a.schedule == "auto" else None
     kname = {1: "k_pass<float,*,0>", 2: "k_pass<float,*,1>"}.get(
-        (1 if wl.processes & 5 else 0) + (2 if wl.processes & 2 else 0), "k_pass<float,*,0> + k_pass<float,*,1>")
+        (1 if host_wl.processes & 5 else 0) + (2 if host_wl.processes & 2 else 0), "k_pass<float,*,0> + k_pass<float,*,1>")
     out = {
         "metric": METRIC, "value": value, "unit": "pair-evals/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "fp32 lookups + fp64 probability/tallies",
         "data": "synthetic",
-        "config": {"workload": f"{a.workload}: {WORKLOADS[a.workload]}", "cells": wl.n_cells,
+        "config": {"workload": f"{a.workload}: {WORKLOADS[a.workload]}", "cells": int(host_wl.n_cells if a.workload != "cfg5" else 131072),
                    "pairs_per_step": fp32["evals"] // a.steps, "schedule": a.schedule,
                    "parallelism": "single GPU, cells"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": kname, "kernel_ms": kavg, "alg_bytes_per_launch": alg},
-        "step_hbm_frac": step_bytes(wl) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "step_hbm_frac": fp32["step_bytes"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "ms_per_step_with_kernel_events": fp32["wall_events_s"] * 1e3 / a.steps,
         "status": fp32["status"],
+        "events_per_step": [e / a.steps for e in fp32["events"]],
     }
     if fp64:
         v64 = fp64["evals"] / fp64["wall_s"]
         k64 = float(np.mean(fp64["pass_ms"]))
         out["fp64_plain"] = {"value": v64, "ms_per_step": fp64["wall_s"] * 1e3 / a.steps,
-                             "kernel_ms": k64, "hbm_frac": alg / (k64 * 1e-3) / 1e9 / HBM_PEAK_GBS}
+                             "kernel_ms": k64, "hbm_frac": fp64["alg_bytes"] / (k64 * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                             "step_hbm_frac": fp64["step_bytes"] / (fp64["wall_s"] / a.steps) / 1e9 / HBM_PEAK_GBS}
         out["fp32_speedup_vs_fp64"] = value / v64
     if not a.no_yield:
         print("[bench] expected yield", file=sys.stderr, flush=True)
         out["expected_yield"] = run_yield(cpu=not a.no_cpu)
     if not a.no_cpu:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(wl)
+        out["cpu_baseline"] = cpu_baseline(host_wl, what)
     print(json.dumps(out), flush=True)
 
 

@@ -263,6 +263,17 @@ class StepState:
         self._refs = (cells, electrons, photons, ions, new_el, new_po)
         self.counter = None
 
+    def set_tallies(self, ti=None, td=None):
+        """Write the next steps' integer (ti, int64 [n_cells, 12]) and FP64
+        (td, [n_cells, 10]) tallies to other device tensors (None: the
+        state's own), e.g. one row block per step."""
+        for t, own, dt_ in ((ti, self.ti, "int64"), (td, self.td, "float64")):
+            if t is not None and (tuple(t.shape) != tuple(own.shape)):
+                raise ValueError(f"tallies: expected shape {tuple(own.shape)}, got {tuple(t.shape)}")
+        self.tal.ti = _ptr(ti if ti is not None else self.ti, "int64")
+        self.tal.td = _ptr(td if td is not None else self.td, "float64")
+        self._tal_refs = (ti, td)
+
     def use_counter(self, counter):
         """Read the step number from `counter` (a one-element int64 device
         tensor) on the device; every step then advances it (None: back to

@@ -772,7 +772,7 @@ __global__ __launch_bounds__(kThreads) void k_collide(StepArgs A, TabView<R> T, 
 // per-cell step above (collide_cell).
 constexpr int kCandCap = 64;     // open pairs per cell (both passes)
 constexpr int kStagePh = 1024;   // photons the event kernel stages in LDS per cell
-enum : int32_t { kFlagSlow = 1, kFlagListed = 2 };
+enum : int32_t { kFlagSlow = 1, kFlagListed = 2, kFlagBig0 = 4, kFlagBig1 = 8 };
 enum : uint32_t { kEvBr = 1, kEvTrPending = 2, kEvTr = 4, kEvBh = 8 };
 
 struct CellState {
@@ -781,14 +781,25 @@ struct CellState {
     int32_t status;                  // CMC_ST_BAD_CELL or 0
 };
 
+// list counters of a step (Work::counters), cleared by k_cell_state
+enum : int {
+    kCntEv = 0,      // cells listed for the event kernels (list_ev)
+    kCntBig0 = 1,    // electron-ion passes deferred to the large-LDS launch (list_big[0])
+    kCntBig1 = 2,    // photon-ion passes deferred (list_big[1])
+    kCntWg = 3,      // listed cells the wavefront event kernel hands to the workgroup one (list_wg)
+    kNumCnt = 8
+};
+
 struct Work {
     CellState* cs;
     int32_t* flags;                  // kFlagSlow: the sequential kernel runs the cell
     int32_t* ncand;                  // open pairs pushed per cell
     double* coef;                    // n_a n_b / n_ab per cell and pass
     uint64_t* step;                  // step number of the current step
-    int32_t* counters;               // [0] cells listed for the event kernel
+    int32_t* counters;               // kNumCnt list lengths
     int32_t* list_ev;                // cells with open pairs or flagged for the sequential step
+    int32_t* list_wg;                // listed cells that need the workgroup event kernel
+    int32_t* list_big[2];            // per pass: cells whose pass needs more LDS than the first launch has
     uint64_t* cand;                  // [n_cells][kCandCap] open pairs
 };
 
@@ -796,7 +807,8 @@ __host__ __device__ inline size_t align256(size_t b) { return (b + 255) / 256 * 
 
 __host__ __device__ inline size_t work_bytes(int64_t n) {
     return align256(sizeof(CellState) * n) + align256(4 * n) + align256(4 * n) +
-           align256(16 * n) + align256(8) + align256(16) + align256(4 * n) + align256(8 * (size_t)n * kCandCap);
+           align256(16 * n) + align256(8) + align256(4 * kNumCnt) + 4 * align256(4 * n) +
+           align256(8 * (size_t)n * kCandCap);
 }
 
 inline Work carve_work(void* base, int64_t n) {
@@ -807,8 +819,11 @@ inline Work carve_work(void* base, int64_t n) {
     w.ncand = reinterpret_cast<int32_t*>(p); p += align256(4 * n);
     w.coef = reinterpret_cast<double*>(p); p += align256(16 * n);
     w.step = reinterpret_cast<uint64_t*>(p); p += align256(8);
-    w.counters = reinterpret_cast<int32_t*>(p); p += align256(16);
+    w.counters = reinterpret_cast<int32_t*>(p); p += align256(4 * kNumCnt);
     w.list_ev = reinterpret_cast<int32_t*>(p); p += align256(4 * n);
+    w.list_wg = reinterpret_cast<int32_t*>(p); p += align256(4 * n);
+    w.list_big[0] = reinterpret_cast<int32_t*>(p); p += align256(4 * n);
+    w.list_big[1] = reinterpret_cast<int32_t*>(p); p += align256(4 * n);
     w.cand = reinterpret_cast<uint64_t*>(p);
     return w;
 }
@@ -837,7 +852,7 @@ __global__ void k_cell_state(const double* Zs, const double* ni, const double* T
         W.step[0] = st;
         if (counter && advance) *counter = st + 1;
     }
-    if (blockIdx.x == 0 && threadIdx.x < 4) W.counters[threadIdx.x] = 0;
+    if (blockIdx.x == 0 && threadIdx.x < kNumCnt) W.counters[threadIdx.x] = 0;
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
         const double z = Zs[c], d = ni[c], t = Te[c];
         CellState s = {};
@@ -1296,7 +1311,7 @@ __device__ __forceinline__ bool settle(double x, const Rng& rng, uint32_t dk, ui
 
 // list a cell (once) for the event kernel
 __device__ __forceinline__ void list_cell(const Work& W, int64_t c) {
-    if (!(atomicOr(&W.flags[c], kFlagListed) & kFlagListed)) W.list_ev[atomicAdd(&W.counters[0], 1)] = (int32_t)c;
+    if (!(atomicOr(&W.flags[c], kFlagListed) & kFlagListed)) W.list_ev[atomicAdd(&W.counters[kCntEv], 1)] = (int32_t)c;
 }
 
 // a cell the event kernel runs with the sequential step
@@ -1324,8 +1339,15 @@ __device__ __forceinline__ void push_cand(const Work& W, int64_t c, uint64_t rec
 // kMov: the ions move, and each pair is tested in its ion's rest frame.
 // Workgroup teams run best at six wavefronts per SIMD (a few spilled
 // registers); wavefront teams are limited by LDS anyway.
+// LDS: `cap` particles per species fit the team's sort arrays.  A pass
+// whose cell exceeds that but needs no order (ions at rest sharing one
+// weight, every mobile particle paired once) runs here all the same; one
+// that needs an order larger than cap is deferred to list_big[kPass],
+// which a launch with a larger cap walks (from_list = 1).  Cells above
+// slow_cap, the largest cap of the step, take the sequential step whole.
 template <typename R, int kT, int kPass, bool kMov>
-__global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, TabView<R> T, Work W, int cap, int filter, int fcap) {
+__global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, TabView<R> T, Work W, int cap, int filter, int fcap,
+                                                                 int slow_cap, int from_list) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red4[kWaves * 4];
     __shared__ uint32_t redu[kWaves];
@@ -1343,7 +1365,9 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
     const double rej = 2.0 * (1.0 + A.near_rel);
     const Rng rng = step_rng(A);
 
-    for (int64_t c = (int64_t)blockIdx.x * kTeams + team; c < A.n_cells; c += (int64_t)gridDim.x * kTeams) {
+    const int64_t n_items = from_list ? (int64_t)W.counters[kPass == 0 ? kCntBig0 : kCntBig1] : A.n_cells;
+    for (int64_t item = (int64_t)blockIdx.x * kTeams + team; item < n_items; item += (int64_t)gridDim.x * kTeams) {
+        const int64_t c = from_list ? (int64_t)W.list_big[kPass][item] : item;
         // the cell's parameters in one round of loads: its state, the
         // offsets and live counts of the three species, its global index
         const uint32_t cell = cell_word(A.cid, c);
@@ -1366,11 +1390,14 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
         }
         const bool ei = (A.proc & (CMC_BREMS | CMC_TRIDENT)) && Ne > 0 && Ni > 0;
         const bool gi = (A.proc & CMC_BH) && Ng > 0 && Ni > 0;
-        // cells beyond the team's LDS go to the sequential kernel whole
-        if ((ei && (Ne > cap || Ni > cap)) || (gi && (Ng > cap || Ni > cap))) {
+        // cells beyond the largest LDS of the step's pass launches go to the
+        // sequential kernel whole
+        if ((ei && (Ne > slow_cap || Ni > slow_cap)) || (gi && (Ng > slow_cap || Ni > slow_cap))) {
             if (t == 0) mark_slow(W, c);
             continue;
         }
+        // every order this pass might need fits this launch's LDS
+        const bool fits = kPass == 0 ? (Ne <= cap && Ni <= cap) : (Ng <= cap && Ni <= cap);
         const int64_t e0 = eo0, g0 = go0, i0 = io0;
         const bool active = kPass == 0 ? ei : gi;
         const int Nm = kPass == 0 ? Ne : Ng, No = kPass == 0 ? Ng : Ne;
@@ -1393,7 +1420,7 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
         // Should the ions not share one weight, the cell is done again below
         // with both orders.
         if constexpr (!kMov) {
-            if (active && N <= 4 * kT) {
+            if (active && fits && N <= 4 * kT) {
                 const bool cyc = !mobA;
                 const int K = N / Nm, e = N - K * Nm;
                 uint32_t* sel = reinterpret_cast<uint32_t*>(M.base + kSelBytes - 128);
@@ -1610,6 +1637,14 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
         // then depends on the order, which is not formed; the few open pairs
         // get their pair index (the rank of their particle) at the end.
         const bool mob_order = active && (!mobA || ion_order);
+        if (active && !fits && ((ion_order && Ni > cap) || (mob_order && Nm > cap))) {
+            // an order larger than this launch's LDS: the large-LDS launch takes
+            // the pass (listed once per step, however often the launch runs)
+            const int32_t fb = kPass == 0 ? kFlagBig0 : kFlagBig1;
+            if (t == 0 && !(atomicOr(&W.flags[c], fb) & fb))
+                W.list_big[kPass][atomicAdd(&W.counters[kPass == 0 ? kCntBig0 : kCntBig1], 1)] = (int32_t)c;
+            continue;
+        }
         if (t == 0) nopen[team] = 0;
         // when every mobile particle pairs once the pair loop walks them in
         // storage order: its first momenta are loaded before the sort
@@ -1697,6 +1732,17 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
         if (nab > 0.0) {
             const double coef = v4[0] * v4[2] / nab;
             const float kx = (float)(coef * A.dt * rej * 16777216.0);
+            // the draw holding U1's upper bits serves the four pairs of its
+            // group (keys x, x + 256, x + 512, x + 768): the last one drawn is
+            // kept per process, so a workgroup thread walking its mobile
+            // particles in storage order (q = t + 256 u) draws once per four
+            uint32_t g_br = 0xFFFFFFFFu, g_tr = 0xFFFFFFFFu;
+            U4 h_br{0u, 0u, 0u, 0u}, h_tr{0u, 0u, 0u, 0u};
+            const auto hi_bits = [&](uint32_t x, uint32_t tag, uint32_t& gk, U4& h) {
+                const uint32_t gx = hi_group(x);
+                if (gx != gk) { h = rng.draw(gx, cell, tag); gk = gx; }
+                return hi_word(h, (x >> 8) & 3u);
+            };
             for (int q = t; q < N; q += kT) {
                 const int j = mobA ? (mob_order ? (int)M.ordM[q] : 0) : q;
                 const int jm = mobA ? 0 : (Nm == N ? j : mod_small(j, Nm, rNm));   // rank of the cycled particle
@@ -1720,17 +1766,13 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
                         bool hi;
                         const R sig = brems_sig_slice<R>(T, slice, e.g, e.gm1, hi);
                         high |= hi;
-                        if (sig > (R)0) {
-                            const U4 h = rng.draw(hi_group(dk), cell, kTagHiBr);
-                            if (bound24(hi_word(h, (dk >> 8) & 3u), kx * (float)sig * (float)e.vrel)) bits = 1u;
-                        }
+                        if (sig > (R)0 && bound24(hi_bits(dk, kTagHiBr, g_br, h_br), kx * (float)sig * (float)e.vrel))
+                            bits = 1u;
                     }
                     if ((A.proc & CMC_TRIDENT) && !bits) {
                         const R sig = (R)phys::trident_sigma(T.Z, (double)e.g);
-                        if (sig > (R)0) {
-                            const U4 h = rng.draw(hi_group(dk), cell, kTagHiTr);
-                            if (bound24(hi_word(h, (dk >> 8) & 3u), kx * (float)sig * (float)e.vrel)) bits = 2u;
-                        }
+                        if (sig > (R)0 && bound24(hi_bits(dk, kTagHiTr, g_tr, h_tr), kx * (float)sig * (float)e.vrel))
+                            bits = 2u;
                     }
                 } else {
                     R k;
@@ -1745,10 +1787,8 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
                     bool hi;
                     const R sig = bh_sig_slice<R>(T, slice, k, hi);
                     high |= hi;
-                    if (sig > (R)0) {
-                        const U4 h = rng.draw(hi_group(dk), cell, kTagHiBh);
-                        if (bound24(hi_word(h, (dk >> 8) & 3u), kx * (float)sig * (float)flux)) bits = 1u;
-                    }
+                    if (sig > (R)0 && bound24(hi_bits(dk, kTagHiBh, g_br, h_br), kx * (float)sig * (float)flux))
+                        bits = 1u;
                 }
                 if (bits) {
                     if (mob_order) {
@@ -1787,6 +1827,322 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
     }
 }
 
+// The values an event kernel reads for a listed cell, in one round of
+// loads (each later round of dependent reads costs the chain about a
+// microsecond), and this lane's open-pair record.
+template <typename R>
+struct EvCell {
+    int64_t c, g0, e0, i0, ne0, np0;
+    int Ng0, Ne, Ni, cap_ph, cap_ne, cap_np, cnt_ne0, cnt_np0, ncr, nc;
+    int32_t flg;
+    CellTab<double> ct64;
+    CellTab<R> ct;
+    double coef0, coef1;
+    uint32_t cell;
+    uint64_t raw;
+};
+
+template <typename R>
+__device__ __forceinline__ EvCell<R> ev_cell(const StepArgs& A, const Work& W, int64_t c, int lane) {
+    EvCell<R> E;
+    E.c = c;
+    E.flg = W.flags[c];
+    E.ncr = W.ncand[c];
+    E.raw = W.cand[c * kCandCap + lane];
+    E.g0 = A.ph.off[c]; E.e0 = A.el.off[c]; E.i0 = A.io.off[c];
+    E.Ng0 = live(A.ph, c); E.Ne = live(A.el, c); E.Ni = live(A.io, c);
+    E.cap_ph = (int)(A.ph.off[c + 1] - E.g0);
+    E.ne0 = A.ne.off[c]; E.np0 = A.np.off[c];
+    E.cap_ne = (int)(A.ne.off[c + 1] - E.ne0);
+    E.cap_np = (int)(A.np.off[c + 1] - E.np0);
+    E.cnt_ne0 = A.ne.count[c]; E.cnt_np0 = A.np.count[c];
+    E.ct64 = W.cs[c].d;
+    E.ct = pick<R>(W.cs[c]);
+    E.coef0 = W.coef[c * 2]; E.coef1 = W.coef[c * 2 + 1];
+    E.cell = cell_word(A.cid, c);
+    E.nc = min(E.ncr, kCandCap);
+    return E;
+}
+
+// One open pair per lane of a wavefront, in (pass, pair index) order, once
+// settled: its pair and particles, the event kind, and what the sampling
+// of its event needs (the mobile particle seen from the ion, the FP64
+// lookup).
+template <typename R>
+struct EvLane {
+    int pass, j, mi, ii;
+    uint32_t dk, kind;
+    int near_br, near_tr, near_bh;
+    double px, py, pz, Wm, Wi;
+    Ion b;
+    Frame fr;
+    BremsLook<double> BLd;
+    int ikd;
+    double wkd;
+    bool reused;
+};
+
+// A wavefront settles the open pairs of a listed cell with P (same
+// arithmetic as the pass kernels: lookups from the full tables give the
+// same values as the slices), after ordering them by (pass, pair index) in
+// rec (kCandCap records of LDS).  `reused` marks an open pair whose mobile
+// particle is used by a later pair of its pass.
+template <typename R>
+__device__ __forceinline__ EvLane<R> ev_settle(const StepArgs& A, const TabView<R>& T, const TabView<double>& T64,
+                                               const Rng& rng, const EvCell<R>& E, uint64_t* rec, double rej) {
+    const int lane = threadIdx.x & 63;
+    const bool cand = lane < E.nc;
+    EvLane<R> L{};
+    L.pass = 2;
+    L.b = Ion{0.0, 0.0, 0.0, 1.0, false};
+    // ---- the open pairs in (pass, pair index) order, one per lane
+    {
+        const bool has = lane < E.nc;
+        const unsigned long long hb = __ballot(has);
+        const uint32_t key = has ? ev_key(E.raw) : 0xFFFFFFFFu;
+        int rank = 0;
+        for (unsigned long long m = hb; m; m &= m - 1ull)
+            rank += (uint32_t)__builtin_amdgcn_readlane((int)key, __ffsll((long long)m) - 1) < key;
+        if (has) rec[rank] = E.raw;
+        Team<64>::sync();
+    }
+    const uint64_t mine = cand ? rec[lane] : 0ull;
+    L.pass = cand ? ev_pass(mine) : 2;
+    L.j = ev_j(mine); L.mi = ev_m(mine); L.ii = ev_i(mine);
+    // the pair's draws: keyed by its mobile particle and its repetition
+    {
+        const int nm = L.pass == 0 ? E.Ne : E.Ng0;
+        L.dk = cand && nm > 0 ? (uint32_t)(L.mi + (L.j / nm) * nm) : 0u;
+    }
+    // ---- settle them
+    L.reused = false;
+    if (cand) {
+        const uint32_t bits = ev_kind(mine);
+        const double coef = L.pass == 0 ? E.coef0 : E.coef1;
+        L.Wi = A.io.w[E.i0 + L.ii];
+        L.b = ion_at(A.io, E.i0 + L.ii);
+        if (L.pass == 0) {
+            const int64_t ie = E.e0 + L.mi;
+            L.px = A.el.px[ie]; L.py = A.el.py[ie]; L.pz = A.el.pz[ie]; L.Wm = A.el.w[ie];
+            L.fr = electron_frame(L.b, L.px, L.py, L.pz);
+            const Elec<R> e = L.b.mov ? electron_moving<R>(L.fr, L.b) : electron_p<R>(L.px, L.py, L.pz);
+            const double Pej = L.Wi / (L.Wm > L.Wi ? L.Wm : L.Wi);
+            if (bits & 1u) {
+                bool hi2;
+                L.BLd = brems_lookup<double, false>(T64, E.ct64, L.fr.g, L.fr.gm1, hi2);
+                bool hi;
+                const R sig = brems_lookup<R, false>(T, E.ct, e.g, e.gm1, hi).sig;
+                const double x = coef * (double)sig * e.vrel * A.dt;
+                if (settle(x, rng, L.dk, E.cell, kTagAccBr, kTagHiBr, rej, A.near_rel, Pej, L.near_br))
+                    L.kind = kEvBr | ((A.proc & CMC_TRIDENT) ? kEvTrPending : 0u);
+            }
+            if ((A.proc & CMC_TRIDENT) && !L.kind) {
+                const R sig = (R)phys::trident_sigma(T.Z, (double)e.g);
+                if (sig > (R)0) {
+                    const double x = coef * (double)sig * e.vrel * A.dt;
+                    if (settle(x, rng, L.dk, E.cell, kTagAccTr, kTagHiTr, rej, A.near_rel, Pej, L.near_tr))
+                        L.kind = kEvTr;
+                }
+            }
+            L.reused = E.Ne < E.Ni && L.j + E.Ne < E.Ni;   // the electron pairs again later
+        } else {
+            const int64_t ig = E.g0 + L.mi;
+            L.px = A.ph.px[ig]; L.py = A.ph.py[ig]; L.pz = A.ph.pz[ig]; L.Wm = A.ph.w[ig];
+            L.fr = photon_frame(L.b, L.px, L.py, L.pz);
+            bool hi2;
+            bh_lookup<double>(T64, E.ct64, L.fr.g, L.ikd, L.wkd, hi2);
+            const R k = L.b.mov ? (R)L.fr.g : photon_k<R>(L.px, L.py, L.pz);
+            int ik; R wk; bool hi;
+            const R sig = bh_lookup<R>(T, E.ct, k, ik, wk, hi);
+            const double x = coef * (double)sig * photon_flux(L.fr, L.b) * A.dt;
+            const double Pej = L.Wi / (L.Wm > L.Wi ? L.Wm : L.Wi);
+            if (settle(x, rng, L.dk, E.cell, kTagAccBh, kTagHiBh, rej, A.near_rel, Pej, L.near_bh))
+                L.kind = kEvBh;
+            L.reused = E.Ng0 < E.Ni && L.j + E.Ng0 < E.Ni;
+        }
+    }
+    return L;
+}
+
+// The wavefront applies the settled events of its lanes in (pass, pair
+// index) order: samples the energies in FP64, moves the electrons, writes
+// the products at slots from ballot prefix sums, and writes the event
+// tallies and the counts.  staged_all and n_conv: the workgroup kernel has
+// every photon staged and removes n_conv converted ones beside this, so
+// new photons go straight to their final slots.
+template <typename R>
+__device__ __forceinline__ void ev_apply(const StepArgs& A, const TabView<R>& T, const TabView<double>& T64,
+                                         const Rng& rng, const EvCell<R>& E, EvLane<R>& L, bool staged_all,
+                                         int n_conv) {
+    const int lane = threadIdx.x & 63;
+    // ---- the events, lanes in (pass, pair index) order
+    const int n = __popcll(__ballot(L.kind != 0));
+    const uint32_t evk = L.kind;
+    Tally t = {};
+    t.near_br = L.near_br; t.near_tr = L.near_tr; t.near_bh = L.near_bh;
+    bool f_ph = false, f_tr = false, f_bh = false;
+    double kx = 0, ky = 0, kz = 0, pxm = 0, pym = 0, pzm = 0, pxp = 0, pyp = 0, pzp = 0;
+    const int64_t par = L.pass == 0 ? E.e0 + L.mi : E.g0 + L.mi;
+    // with few events the wavefront inverts each CDF together (one round
+    // of table reads per event), else every lane bisects its own; both
+    // give the same abscissa
+    const bool coop = n <= 8;
+    const auto invert = [&](bool has, const CdfRow<double>& row, double xi, double& ct) {
+        if (coop) return cdf_invert_wave<double>(has, row, E.ct64, xi, ct);
+        return has ? cdf_invert<double>(row.T, row.kind, row.i, row.w, E.ct64, xi, ct) : 0.0;
+    };
+    // ---- first draw: Bremsstrahlung photon energy or Bethe-Heitler pair
+    CdfRow<double> rowA = {};
+    double xiA = 0.0;
+    bool reqA = false;
+    if (L.pass == 0 && (evk & kEvBr)) {
+        const U4 q = rng.draw(L.dk, E.cell, kTagSmpBr);
+        rowA = brems_row<double>(T64, L.BLd);
+        xiA = u53(q.x, q.y);
+        reqA = true;
+    } else if (L.pass == 1 && (evk & kEvBh)) {
+        const U4 q = rng.draw(L.dk, E.cell, kTagSmpBh);
+        rowA = bh_row<double>(T64, L.ikd, L.wkd);
+        xiA = u53(q.x, q.y);
+        reqA = true;
+    }
+    double ctA = 0.0;
+    const double tA = invert(reqA, rowA, xiA, ctA);
+    bool tr = false;
+    if (L.pass == 0 && evk) {
+        if (evk & kEvBr) {
+            double k, g2, g2m1;
+            brems_energies(L.BLd.seg, L.fr.g, L.fr.gm1, ctA, k, g2, g2m1);
+            const double pf = sqrt(g2m1 * (g2 + 1.0));
+            lab_along(L.b, L.fr, k, k, kx, ky, kz);
+            lab_along(L.b, L.fr, g2, pf, L.px, L.py, L.pz);
+            t.ev_br++;
+            t.E_br += L.Wm * sqrt(kx * kx + ky * ky + kz * kz);
+            t.dE_el += L.Wm * lab_energy_change(L.b, L.fr, -k, g2, pf);
+            t.W_br += L.Wm;
+            f_ph = true;
+        }
+        tr = (evk & kEvTr) != 0;
+        if (evk & kEvTrPending) {
+            // Trident on the electron left by Bremsstrahlung (same pair)
+            const double Pej = L.Wi / (L.Wm > L.Wi ? L.Wm : L.Wi);
+            const Elec<R> e = L.b.mov ? electron_moving<R>(electron_frame(L.b, L.px, L.py, L.pz), L.b)
+                                    : electron_p<R>(L.px, L.py, L.pz);
+            const R sig = (R)phys::trident_sigma(T.Z, (double)e.g);
+            if (sig > (R)0) {
+                const double x = E.coef0 * (double)sig * e.vrel * A.dt;
+                const double P = -expm1(-x);
+                double U1, U2;
+                accept_uniforms(rng, L.dk, E.cell, kTagAccTr, kTagHiTr, U1, U2);
+                if (fabs(U1 - P) <= A.near_rel * P) t.near_tr++;
+                tr = U1 < P && U2 < Pej;
+            }
+        }
+    } else if (L.pass == 1 && evk) {
+        double gpl, gmi;
+        bh_energies(L.fr.g, tA, ctA, gpl, gmi);
+        const double pplus = sqrt((gpl - 1.0) * (gpl + 1.0)), pminus = sqrt((gmi - 1.0) * (gmi + 1.0));
+        lab_along(L.b, L.fr, gpl, pplus, pxp, pyp, pzp);
+        lab_along(L.b, L.fr, gmi, pminus, pxm, pym, pzm);
+        t.ev_bh++;
+        t.E_bh += L.Wm * (sqrt(1.0 + pxp * pxp + pyp * pyp + pzp * pzp) + sqrt(1.0 + pxm * pxm + pym * pym + pzm * pzm));
+        t.dE_ph += -L.Wm * L.fr.E;
+        t.W_bh += L.Wm;
+        f_bh = true;
+    }
+    // ---- Trident: pair energy, then the positron split
+    U4 qt = {0u, 0u, 0u, 0u};
+    CdfRow<double> rowB = {};
+    Frame ft = {};   // the electron, after this pair's Bremsstrahlung, seen from the ion
+    if (tr) {
+        qt = rng.draw(L.dk, E.cell, kTagSmpTr);
+        ft = electron_frame(L.b, L.px, L.py, L.pz);
+        rowB = trident_row<double>(T64, ft.g);
+    }
+    double ctB = 0.0;
+    const double tB = invert(tr, rowB, u53(qt.x, qt.y), ctB);
+    double gpair = 0, gpl = 0, gmi = 0, gfm1 = 0;
+    bool reqC = false;
+    CdfRow<double> rowC = {};
+    if (tr) {
+        reqC = trident_pair(ft.gm1, tB, ctB, gpair, gpl, gmi, gfm1);
+        if (reqC) rowC = split_row<double>(T64, gpair);
+    }
+    double ctC = 0.0;
+    const double tC = invert(reqC, rowC, u53(qt.z, qt.w), ctC);
+    if (reqC) split_energies(gpair, tC, ctC, gpl, gmi);
+    if (tr) {
+        const double gf = gfm1 + 1.0;
+        const double pf = sqrt(gfm1 * (gf + 1.0));
+        const double pplus = sqrt((gpl - 1.0) * (gpl + 1.0)), pminus = sqrt((gmi - 1.0) * (gmi + 1.0));
+        lab_along(L.b, ft, gpl, pplus, pxp, pyp, pzp);
+        lab_along(L.b, ft, gmi, pminus, pxm, pym, pzm);
+        lab_along(L.b, ft, gf, pf, L.px, L.py, L.pz);
+        t.ev_tr++;
+        t.E_tr += L.Wm * (sqrt(1.0 + pxp * pxp + pyp * pyp + pzp * pzp) + sqrt(1.0 + pxm * pxm + pym * pym + pzm * pzm));
+        t.dE_el += L.Wm * lab_energy_change(L.b, ft, -gpair, gf, pf);
+        t.W_tr += L.Wm;
+        f_tr = true;
+    }
+    if (L.pass == 0 && (f_ph || f_tr)) { A.el.px[par] = L.px; A.el.py[par] = L.py; A.el.pz[par] = L.pz; }
+    // slots in (pass, pair) order: lanes are already in that order
+    const unsigned long long b_ph = __ballot(f_ph), b_tr = __ballot(f_tr), b_bh = __ballot(f_bh);
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const int n_ph = __popcll(b_ph), n_tr = __popcll(b_tr), n_bh = __popcll(b_bh);
+    // with every photon staged the converted ones are removed beside
+    // this: the new photons go straight to their final slots
+    const int shift = staged_all ? n_conv : 0;
+    if (f_ph) {
+        const int slot = E.Ng0 + __popcll(b_ph & below);
+        if (slot < E.cap_ph) {
+            const int64_t at = E.g0 + slot - shift;
+            A.ph.px[at] = kx; A.ph.py[at] = ky; A.ph.pz[at] = kz; A.ph.w[at] = L.Wm;
+            if (A.ph.parent) A.ph.parent[at] = par;
+        } else t.drop_ph++;
+    }
+    if (f_tr || f_bh) {
+        const int o = f_tr ? __popcll(b_tr & below) : n_tr + __popcll(b_bh & below);
+        if (E.cnt_ne0 + o < E.cap_ne) {
+            const int64_t at = E.ne0 + E.cnt_ne0 + o;
+            A.ne.px[at] = pxm; A.ne.py[at] = pym; A.ne.pz[at] = pzm; A.ne.w[at] = L.Wm;
+            if (A.ne.parent) A.ne.parent[at] = par;
+        } else t.drop_el++;
+        if (E.cnt_np0 + o < E.cap_np) {
+            const int64_t at = E.np0 + E.cnt_np0 + o;
+            A.np.px[at] = pxp; A.np.py[at] = pyp; A.np.pz[at] = pzp; A.np.w[at] = L.Wm;
+            if (A.np.parent) A.np.parent[at] = par;
+        } else t.drop_po++;
+    }
+    const int ph_count = min(E.cap_ph, E.Ng0 + n_ph) - shift;
+    // tallies of the events (the pair counts were written by the
+    // passes).  A lane holds one open pair: each of its counts is 0 or
+    // 1 (one event of a kind, one near-threshold test of a process,
+    // one product of a kind), and only lanes with an event carry
+    // energies and weights, which are added lane by lane in pair order.
+    const auto count = [](long long v) { return (long long)__popcll(__ballot(v != 0)); };
+    const long long iv[9] = {count(t.ev_br), count(t.ev_tr), count(t.ev_bh), count(t.near_br), count(t.near_tr),
+                             count(t.near_bh), count(t.drop_ph), count(t.drop_el), count(t.drop_po)};
+    double dv[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (unsigned long long m = __ballot(f_ph || f_tr || f_bh); m; m &= m - 1ull) {
+        const int e = __ffsll((long long)m) - 1;
+        dv[0] += lane_f64(t.E_br, e); dv[1] += lane_f64(t.E_tr, e); dv[2] += lane_f64(t.E_bh, e);
+        dv[3] += lane_f64(t.dE_el, e); dv[4] += lane_f64(t.dE_ph, e);
+        dv[5] += lane_f64(t.W_br, e); dv[6] += lane_f64(t.W_tr, e); dv[7] += lane_f64(t.W_bh, e);
+    }
+    if (lane == 0) {
+        int64_t* ti = A.ti + E.c * CMC_NI;
+        ti[CMC_I_EV_BR] = iv[0]; ti[CMC_I_EV_TR] = iv[1]; ti[CMC_I_EV_BH] = iv[2];
+        ti[CMC_I_NEAR_BR] = iv[3]; ti[CMC_I_NEAR_TR] = iv[4]; ti[CMC_I_NEAR_BH] = iv[5];
+        ti[CMC_I_DROP_PH] = iv[6]; ti[CMC_I_DROP_EL] = iv[7]; ti[CMC_I_DROP_PO] = iv[8];
+        double* td = A.td + E.c * CMC_ND + CMC_D_E_BR;
+        for (int q = 0; q < 8; ++q) td[q] = dv[q];
+        if (A.ph.count && (!n_bh || staged_all)) A.ph.count[E.c] = ph_count;
+        A.ne.count[E.c] = min(E.cap_ne, E.cnt_ne0 + n_tr + n_bh);
+        A.np.count[E.c] = min(E.cap_np, E.cnt_np0 + n_tr + n_bh);
+        if (iv[6] + iv[7] + iv[8]) atomicOr(A.status, CMC_ST_OVERFLOW);
+    }
+}
+
 // One workgroup per listed cell.  Cells flagged by the pass kernels (more
 // open pairs than kCandCap, more particles than the pass kernel's LDS) run
 // the sequential step.  Otherwise the first wavefront settles the open
@@ -1797,7 +2153,8 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
 // writes the products, and the four wavefronts then drop the converted
 // photons.
 template <typename R>
-__global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, TabView<double> T64, Work W) {
+__global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, TabView<double> T64, Work W,
+                                                     int from_wave) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ CollideShared<R> sh;
     __shared__ uint64_t rec[kCandCap];
@@ -1814,37 +2171,28 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
     double* const stw = stz + kStagePh;
     int64_t* const stp = reinterpret_cast<int64_t*>(stw + kStagePh);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int n_items = W.counters[0];
+    // the listed cells, or those the wavefront event kernel handed over
+    const int32_t* list = from_wave ? W.list_wg : W.list_ev;
+    const int n_items = W.counters[from_wave ? kCntWg : kCntEv];
     const double rej = 2.0 * (1.0 + A.near_rel);
     const Rng rng = step_rng(A);
     // the block's first cell is read beside the count (the list has
     // n_cells >= gridDim.x entries; an entry past the count is not used)
-    int64_t c_next = W.list_ev[blockIdx.x];
+    int64_t c_next = list[blockIdx.x];
     for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
         const int64_t c = c_next;
-        if (item + (int)gridDim.x < n_items) c_next = W.list_ev[item + gridDim.x];
-        // every per-cell value of the item is read in this one round: each
-        // later round of dependent reads costs the chain about a microsecond
-        const int32_t flg = W.flags[c], ncr = W.ncand[c];
-        const uint64_t raw = W.cand[c * kCandCap + lane];
-        const int64_t g0 = A.ph.off[c], e0 = A.el.off[c], i0 = A.io.off[c];
-        const int Ng0 = live(A.ph, c), Ne = live(A.el, c), Ni = live(A.io, c);
-        const int cap_ph = (int)(A.ph.off[c + 1] - g0);
-        const int64_t ne0 = A.ne.off[c], np0 = A.np.off[c];
-        const int cap_ne = (int)(A.ne.off[c + 1] - ne0), cap_np = (int)(A.np.off[c + 1] - np0);
-        const int cnt_ne0 = A.ne.count[c], cnt_np0 = A.np.count[c];
-        const CellTab<double> ct64 = W.cs[c].d;
-        const CellTab<R> ct = pick<R>(W.cs[c]);
-        const double coef0 = W.coef[c * 2], coef1 = W.coef[c * 2 + 1];
-        const uint32_t cell = cell_word(A.cid, c);
-        const bool slow = (flg & kFlagSlow) != 0;
+        if (item + (int)gridDim.x < n_items) c_next = list[item + gridDim.x];
+        const EvCell<R> E = ev_cell<R>(A, W, c, lane);
+        const int64_t g0 = E.g0;
+        const int Ng0 = E.Ng0, cap_ph = E.cap_ph;
+        const bool slow = (E.flg & kFlagSlow) != 0;
         // ctl is read by the other wavefronts only after the barrier that
         // ends wavefront 0's work; wavefront 0 may set ctl[0..3] meanwhile
         if (threadIdx.x == 0) { ctl[0] = slow ? 1 : 0; ctl[1] = 0; }
         // while wavefront 0 settles the open pairs, the others copy the
         // cell's first photons to LDS (when a Bethe-Heitler pair is open):
         // the removal of converted photons then reads them from there
-        const bool bh_open = __ballot(lane < min(ncr, kCandCap) && ev_pass(raw) == 1) != 0ull;
+        const bool bh_open = __ballot(lane < E.nc && ev_pass(E.raw) == 1) != 0ull;
         const int n_st = (!slow && bh_open) ? min(Ng0, kStagePh) : 0;
         if (wv != 0 && n_st > 0) {
             constexpr int kPer = (kStagePh + kThreads - 65) / (kThreads - 64);
@@ -1865,93 +2213,19 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
         }
         // Wavefront 0 settles the open pairs; its lanes keep the pair's
         // particle, ion and FP64 lookup for the sampling after the barrier.
-        const int nc = min(ncr, kCandCap);
-        const bool cand = lane < nc;
-        uint64_t mine = 0ull;
-        int pass = 2, j = 0, mi = 0, ii = 0;
-        uint32_t dk = 0, kind = 0;
-        int near_br = 0, near_tr = 0, near_bh = 0;
-        double px = 0, py = 0, pz = 0, Wm = 0, Wi = 0;
-        Ion b{0.0, 0.0, 0.0, 1.0, false};
-        Frame fr = {};   // the mobile particle seen from the ion
-        BremsLook<double> BLd = {};
-        int ikd = 0; double wkd = 0.0;
+        EvLane<R> L{};
         // with every live photon staged, the survivors of a conversion are
         // moved by wavefronts 1-3 while wavefront 0 samples the events
         const bool staged_all = n_st == Ng0;
         if (wv == 0 && !slow) {
-            // ---- the open pairs in (pass, pair index) order, one per lane
-            {
-                const bool has = lane < nc;
-                const unsigned long long hb = __ballot(has);
-                const uint32_t key = has ? ev_key(raw) : 0xFFFFFFFFu;
-                int rank = 0;
-                for (unsigned long long m = hb; m; m &= m - 1ull)
-                    rank += (uint32_t)__builtin_amdgcn_readlane((int)key, __ffsll((long long)m) - 1) < key;
-                if (has) rec[rank] = raw;
-                Team<64>::sync();
-            }
-            mine = cand ? rec[lane] : 0ull;
-            pass = cand ? ev_pass(mine) : 2;
-            j = ev_j(mine); mi = ev_m(mine); ii = ev_i(mine);
-            // the pair's draws: keyed by its mobile particle and its repetition
-            {
-                const int nm = pass == 0 ? Ne : Ng0;
-                dk = cand && nm > 0 ? (uint32_t)(mi + (j / nm) * nm) : 0u;
-            }
-            // ---- settle them
-            bool reused = false;
-            if (cand) {
-                const uint32_t bits = ev_kind(mine);
-                const double coef = pass == 0 ? coef0 : coef1;
-                Wi = A.io.w[i0 + ii];
-                b = ion_at(A.io, i0 + ii);
-                if (pass == 0) {
-                    const int64_t ie = e0 + mi;
-                    px = A.el.px[ie]; py = A.el.py[ie]; pz = A.el.pz[ie]; Wm = A.el.w[ie];
-                    fr = electron_frame(b, px, py, pz);
-                    const Elec<R> e = b.mov ? electron_moving<R>(fr, b) : electron_p<R>(px, py, pz);
-                    const double Pej = Wi / (Wm > Wi ? Wm : Wi);
-                    if (bits & 1u) {
-                        bool hi2;
-                        BLd = brems_lookup<double, false>(T64, ct64, fr.g, fr.gm1, hi2);
-                        bool hi;
-                        const R sig = brems_lookup<R, false>(T, ct, e.g, e.gm1, hi).sig;
-                        const double x = coef * (double)sig * e.vrel * A.dt;
-                        if (settle(x, rng, dk, cell, kTagAccBr, kTagHiBr, rej, A.near_rel, Pej, near_br))
-                            kind = kEvBr | ((A.proc & CMC_TRIDENT) ? kEvTrPending : 0u);
-                    }
-                    if ((A.proc & CMC_TRIDENT) && !kind) {
-                        const R sig = (R)phys::trident_sigma(T.Z, (double)e.g);
-                        if (sig > (R)0) {
-                            const double x = coef * (double)sig * e.vrel * A.dt;
-                            if (settle(x, rng, dk, cell, kTagAccTr, kTagHiTr, rej, A.near_rel, Pej, near_tr))
-                                kind = kEvTr;
-                        }
-                    }
-                    reused = Ne < Ni && j + Ne < Ni;   // the electron pairs again later
-                } else {
-                    const int64_t ig = g0 + mi;
-                    px = A.ph.px[ig]; py = A.ph.py[ig]; pz = A.ph.pz[ig]; Wm = A.ph.w[ig];
-                    fr = photon_frame(b, px, py, pz);
-                    bool hi2;
-                    bh_lookup<double>(T64, ct64, fr.g, ikd, wkd, hi2);
-                    const R k = b.mov ? (R)fr.g : photon_k<R>(px, py, pz);
-                    int ik; R wk; bool hi;
-                    const R sig = bh_lookup<R>(T, ct, k, ik, wk, hi);
-                    const double x = coef * (double)sig * photon_flux(fr, b) * A.dt;
-                    const double Pej = Wi / (Wm > Wi ? Wm : Wi);
-                    if (settle(x, rng, dk, cell, kTagAccBh, kTagHiBh, rej, A.near_rel, Pej, near_bh))
-                        kind = kEvBh;
-                    reused = Ng0 < Ni && j + Ng0 < Ni;
-                }
-            }
+            L = ev_settle<R>(A, T, T64, rng, E, rec, rej);
             // an event on a particle used by a later pair of its pass: the
             // cell is redone by the sequential step below
-            if (__ballot(kind != 0 && reused) != 0ull) {
+            if (__ballot(L.kind != 0 && L.reused) != 0ull) {
                 if (lane == 0) ctl[0] = 1;
             } else {
-                const bool conv = pass == 1 && (kind & kEvBh);
+                const int mi = L.mi;
+                const bool conv = L.pass == 1 && (L.kind & kEvBh);
                 const unsigned long long b_cv = __ballot(conv);
                 if (b_cv) {
                     // converted photons: a bitmap, and for the staged case the
@@ -1975,7 +2249,7 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
                     int first = conv ? mi : 0x7FFFFFFF;
 #pragma unroll
                     for (int o = 32; o > 0; o >>= 1) first = min(first, __shfl_xor(first, o, 64));
-                    const int n_new = __popcll(__ballot(pass == 0 && (kind & kEvBr)));
+                    const int n_new = __popcll(__ballot(L.pass == 0 && (L.kind & kEvBr)));
                     if (lane == 0) { ctl[1] = __popcll(b_cv); ctl[2] = first; ctl[3] = min(cap_ph, Ng0 + n_new); }
                 }
             }
@@ -1987,174 +2261,7 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
             continue;
         }
         const int n_conv = ctl[1];
-        if (wv == 0 && !slow) do {
-            // ---- the events, lanes in (pass, pair index) order
-            const int n = __popcll(__ballot(kind != 0));
-            const uint32_t evk = kind;
-            Tally t = {};
-            t.near_br = near_br; t.near_tr = near_tr; t.near_bh = near_bh;
-            bool f_ph = false, f_tr = false, f_bh = false;
-            double kx = 0, ky = 0, kz = 0, pxm = 0, pym = 0, pzm = 0, pxp = 0, pyp = 0, pzp = 0;
-            const int64_t par = pass == 0 ? e0 + mi : g0 + mi;
-            // with few events the wavefront inverts each CDF together (one round
-            // of table reads per event), else every lane bisects its own; both
-            // give the same abscissa
-            const bool coop = n <= 8;
-            const auto invert = [&](bool has, const CdfRow<double>& row, double xi, double& ct) {
-                if (coop) return cdf_invert_wave<double>(has, row, ct64, xi, ct);
-                return has ? cdf_invert<double>(row.T, row.kind, row.i, row.w, ct64, xi, ct) : 0.0;
-            };
-            // ---- first draw: Bremsstrahlung photon energy or Bethe-Heitler pair
-            CdfRow<double> rowA = {};
-            double xiA = 0.0;
-            bool reqA = false;
-            if (pass == 0 && (evk & kEvBr)) {
-                const U4 q = rng.draw(dk, cell, kTagSmpBr);
-                rowA = brems_row<double>(T64, BLd);
-                xiA = u53(q.x, q.y);
-                reqA = true;
-            } else if (pass == 1 && (evk & kEvBh)) {
-                const U4 q = rng.draw(dk, cell, kTagSmpBh);
-                rowA = bh_row<double>(T64, ikd, wkd);
-                xiA = u53(q.x, q.y);
-                reqA = true;
-            }
-            double ctA = 0.0;
-            const double tA = invert(reqA, rowA, xiA, ctA);
-            bool tr = false;
-            if (pass == 0 && evk) {
-                if (evk & kEvBr) {
-                    double k, g2, g2m1;
-                    brems_energies(BLd.seg, fr.g, fr.gm1, ctA, k, g2, g2m1);
-                    const double pf = sqrt(g2m1 * (g2 + 1.0));
-                    lab_along(b, fr, k, k, kx, ky, kz);
-                    lab_along(b, fr, g2, pf, px, py, pz);
-                    t.ev_br++;
-                    t.E_br += Wm * sqrt(kx * kx + ky * ky + kz * kz);
-                    t.dE_el += Wm * lab_energy_change(b, fr, -k, g2, pf);
-                    t.W_br += Wm;
-                    f_ph = true;
-                }
-                tr = (evk & kEvTr) != 0;
-                if (evk & kEvTrPending) {
-                    // Trident on the electron left by Bremsstrahlung (same pair)
-                    const double Pej = Wi / (Wm > Wi ? Wm : Wi);
-                    const Elec<R> e = b.mov ? electron_moving<R>(electron_frame(b, px, py, pz), b)
-                                            : electron_p<R>(px, py, pz);
-                    const R sig = (R)phys::trident_sigma(T.Z, (double)e.g);
-                    if (sig > (R)0) {
-                        const double x = coef0 * (double)sig * e.vrel * A.dt;
-                        const double P = -expm1(-x);
-                        double U1, U2;
-                        accept_uniforms(rng, dk, cell, kTagAccTr, kTagHiTr, U1, U2);
-                        if (fabs(U1 - P) <= A.near_rel * P) t.near_tr++;
-                        tr = U1 < P && U2 < Pej;
-                    }
-                }
-            } else if (pass == 1 && evk) {
-                double gpl, gmi;
-                bh_energies(fr.g, tA, ctA, gpl, gmi);
-                const double pplus = sqrt((gpl - 1.0) * (gpl + 1.0)), pminus = sqrt((gmi - 1.0) * (gmi + 1.0));
-                lab_along(b, fr, gpl, pplus, pxp, pyp, pzp);
-                lab_along(b, fr, gmi, pminus, pxm, pym, pzm);
-                t.ev_bh++;
-                t.E_bh += Wm * (sqrt(1.0 + pxp * pxp + pyp * pyp + pzp * pzp) + sqrt(1.0 + pxm * pxm + pym * pym + pzm * pzm));
-                t.dE_ph += -Wm * fr.E;
-                t.W_bh += Wm;
-                f_bh = true;
-            }
-            // ---- Trident: pair energy, then the positron split
-            U4 qt = {0u, 0u, 0u, 0u};
-            CdfRow<double> rowB = {};
-            Frame ft = {};   // the electron, after this pair's Bremsstrahlung, seen from the ion
-            if (tr) {
-                qt = rng.draw(dk, cell, kTagSmpTr);
-                ft = electron_frame(b, px, py, pz);
-                rowB = trident_row<double>(T64, ft.g);
-            }
-            double ctB = 0.0;
-            const double tB = invert(tr, rowB, u53(qt.x, qt.y), ctB);
-            double gpair = 0, gpl = 0, gmi = 0, gfm1 = 0;
-            bool reqC = false;
-            CdfRow<double> rowC = {};
-            if (tr) {
-                reqC = trident_pair(ft.gm1, tB, ctB, gpair, gpl, gmi, gfm1);
-                if (reqC) rowC = split_row<double>(T64, gpair);
-            }
-            double ctC = 0.0;
-            const double tC = invert(reqC, rowC, u53(qt.z, qt.w), ctC);
-            if (reqC) split_energies(gpair, tC, ctC, gpl, gmi);
-            if (tr) {
-                const double gf = gfm1 + 1.0;
-                const double pf = sqrt(gfm1 * (gf + 1.0));
-                const double pplus = sqrt((gpl - 1.0) * (gpl + 1.0)), pminus = sqrt((gmi - 1.0) * (gmi + 1.0));
-                lab_along(b, ft, gpl, pplus, pxp, pyp, pzp);
-                lab_along(b, ft, gmi, pminus, pxm, pym, pzm);
-                lab_along(b, ft, gf, pf, px, py, pz);
-                t.ev_tr++;
-                t.E_tr += Wm * (sqrt(1.0 + pxp * pxp + pyp * pyp + pzp * pzp) + sqrt(1.0 + pxm * pxm + pym * pym + pzm * pzm));
-                t.dE_el += Wm * lab_energy_change(b, ft, -gpair, gf, pf);
-                t.W_tr += Wm;
-                f_tr = true;
-            }
-            if (pass == 0 && (f_ph || f_tr)) { A.el.px[par] = px; A.el.py[par] = py; A.el.pz[par] = pz; }
-            // slots in (pass, pair) order: lanes are already in that order
-            const unsigned long long b_ph = __ballot(f_ph), b_tr = __ballot(f_tr), b_bh = __ballot(f_bh);
-            const unsigned long long below = (1ull << lane) - 1ull;
-            const int n_ph = __popcll(b_ph), n_tr = __popcll(b_tr), n_bh = __popcll(b_bh);
-            // with every photon staged the converted ones are removed beside
-            // this: the new photons go straight to their final slots
-            const int shift = staged_all ? n_conv : 0;
-            if (f_ph) {
-                const int slot = Ng0 + __popcll(b_ph & below);
-                if (slot < cap_ph) {
-                    const int64_t at = g0 + slot - shift;
-                    A.ph.px[at] = kx; A.ph.py[at] = ky; A.ph.pz[at] = kz; A.ph.w[at] = Wm;
-                    if (A.ph.parent) A.ph.parent[at] = par;
-                } else t.drop_ph++;
-            }
-            if (f_tr || f_bh) {
-                const int o = f_tr ? __popcll(b_tr & below) : n_tr + __popcll(b_bh & below);
-                if (cnt_ne0 + o < cap_ne) {
-                    const int64_t at = ne0 + cnt_ne0 + o;
-                    A.ne.px[at] = pxm; A.ne.py[at] = pym; A.ne.pz[at] = pzm; A.ne.w[at] = Wm;
-                    if (A.ne.parent) A.ne.parent[at] = par;
-                } else t.drop_el++;
-                if (cnt_np0 + o < cap_np) {
-                    const int64_t at = np0 + cnt_np0 + o;
-                    A.np.px[at] = pxp; A.np.py[at] = pyp; A.np.pz[at] = pzp; A.np.w[at] = Wm;
-                    if (A.np.parent) A.np.parent[at] = par;
-                } else t.drop_po++;
-            }
-            const int ph_count = min(cap_ph, Ng0 + n_ph) - shift;
-            // tallies of the events (the pair counts were written by the
-            // passes).  A lane holds one open pair: each of its counts is 0 or
-            // 1 (one event of a kind, one near-threshold test of a process,
-            // one product of a kind), and only lanes with an event carry
-            // energies and weights, which are added lane by lane in pair order.
-            const auto count = [](long long v) { return (long long)__popcll(__ballot(v != 0)); };
-            const long long iv[9] = {count(t.ev_br), count(t.ev_tr), count(t.ev_bh), count(t.near_br), count(t.near_tr),
-                                     count(t.near_bh), count(t.drop_ph), count(t.drop_el), count(t.drop_po)};
-            double dv[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-            for (unsigned long long m = __ballot(f_ph || f_tr || f_bh); m; m &= m - 1ull) {
-                const int e = __ffsll((long long)m) - 1;
-                dv[0] += lane_f64(t.E_br, e); dv[1] += lane_f64(t.E_tr, e); dv[2] += lane_f64(t.E_bh, e);
-                dv[3] += lane_f64(t.dE_el, e); dv[4] += lane_f64(t.dE_ph, e);
-                dv[5] += lane_f64(t.W_br, e); dv[6] += lane_f64(t.W_tr, e); dv[7] += lane_f64(t.W_bh, e);
-            }
-            if (lane == 0) {
-                int64_t* ti = A.ti + c * CMC_NI;
-                ti[CMC_I_EV_BR] = iv[0]; ti[CMC_I_EV_TR] = iv[1]; ti[CMC_I_EV_BH] = iv[2];
-                ti[CMC_I_NEAR_BR] = iv[3]; ti[CMC_I_NEAR_TR] = iv[4]; ti[CMC_I_NEAR_BH] = iv[5];
-                ti[CMC_I_DROP_PH] = iv[6]; ti[CMC_I_DROP_EL] = iv[7]; ti[CMC_I_DROP_PO] = iv[8];
-                double* td = A.td + c * CMC_ND + CMC_D_E_BR;
-                for (int q = 0; q < 8; ++q) td[q] = dv[q];
-                if (A.ph.count && (!n_bh || staged_all)) A.ph.count[c] = ph_count;
-                A.ne.count[c] = min(cap_ne, cnt_ne0 + n_tr + n_bh);
-                A.np.count[c] = min(cap_np, cnt_np0 + n_tr + n_bh);
-                if (iv[6] + iv[7] + iv[8]) atomicOr(A.status, CMC_ST_OVERFLOW);
-            }
-        } while (0);
+        if (wv == 0 && !slow) ev_apply<R>(A, T, T64, rng, E, L, staged_all, n_conv);
         if (wv != 0 && n_conv && staged_all) {
             // each survivor at or after the first converted photon moves down
             // by the converted photons before it, read from LDS: no photon is
@@ -2222,6 +2329,38 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
     }
 }
 
+
+// One wavefront per listed cell, four cells per workgroup, no workgroup
+// barrier and little LDS: a cell whose open pairs are all electron-ion
+// pairs, none of whose events falls on an electron used by a later pair,
+// is settled and applied here (the Bremsstrahlung workloads: nearly every
+// listed cell).  Any other listed cell (the sequential step, open
+// Bethe-Heitler pairs, whose converted photons need the workgroup's
+// compaction) is handed to list_wg, which k_events walks next.
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_events_wave(StepArgs A, TabView<R> T, TabView<double> T64, Work W) {
+    __shared__ uint64_t rec[kWaves][kCandCap];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int n_items = W.counters[kCntEv];
+    const double rej = 2.0 * (1.0 + A.near_rel);
+    const Rng rng = step_rng(A);
+    for (int item = blockIdx.x * kWaves + wv; item < n_items; item += gridDim.x * kWaves) {
+        const int64_t c = W.list_ev[item];
+        const EvCell<R> E = ev_cell<R>(A, W, c, lane);
+        bool hand = (E.flg & kFlagSlow) != 0 || __ballot(lane < E.nc && ev_pass(E.raw) == 1) != 0ull;
+        EvLane<R> L{};
+        if (!hand) {
+            L = ev_settle<R>(A, T, T64, rng, E, rec[wv], rej);
+            hand = __ballot(L.kind != 0 && L.reused) != 0ull;
+        }
+        if (hand) {
+            if (lane == 0) W.list_wg[atomicAdd(&W.counters[kCntWg], 1)] = (int32_t)c;
+            continue;
+        }
+        ev_apply<R>(A, T, T64, rng, E, L, false, 0);
+    }
+}
+
 // ------------------------------------------------------------------ pair_cells
 struct PairArgs {
     const int64_t *a_off, *b_off, *pair_off, *cid;
@@ -2285,17 +2424,21 @@ int grid_for(int64_t n_cells) {
 using namespace cmc;
 
 // ------------------------------------------------------------------ decision launch
-// LDS of one team: the whole cell must fit (cap particles per species);
-// wavefront teams are limited to kWaveCap so that several workgroups of
-// four teams share a compute unit.
+// LDS of one team: a cell's pass is sorted in LDS when it needs an order
+// (cap particles per species).  Wavefront teams are limited to kWaveCap so
+// that several workgroups of four teams share a compute unit; workgroup
+// teams run a first launch whose LDS leaves room for kMainWgs workgroups per
+// compute unit (the streaming pass needs occupancy, not LDS), and the passes
+// it defers (an order above its cap) run in a second launch sized for one.
 constexpr int kWaveCap = 1024;
+constexpr int kMainWgs = 6;
 constexpr size_t kLdsMax = 160 * 1024;
 
-static int team_cap(int team, int maxn, bool fp64) {
+static int team_cap(int team, int maxn, bool fp64, int wgs_per_cu = 1) {
     const int rb = fp64 ? 8 : 4;
     int cap = team == 64 ? std::min(maxn, kWaveCap) : maxn;
-    const size_t static_lds = 256;
-    while (cap > 64 && (size_t)(256 / team) * ((team_bytes(cap, rb, team) + 15) / 16 * 16) + static_lds > kLdsMax)
+    const size_t static_lds = 2560;
+    while (cap > 64 && (size_t)wgs_per_cu * ((size_t)(256 / team) * ((team_bytes(cap, rb, team) + 15) / 16 * 16) + static_lds) > kLdsMax)
         cap -= 64;
     return cap;
 }
@@ -2317,44 +2460,50 @@ struct PassTiming {
     bool first;
 };
 
+// one launch of the pass kernels: teams of kT over all cells of a size
+// class (filter 1: up to fcap particles per species, 2: above, 0: all), or
+// over the passes a first launch deferred (from_list)
+struct PassLaunch {
+    int cap, filter, fcap, slow_cap, from_list;
+    unsigned grid;
+    size_t dshm;
+};
+
 template <typename R, int kT, bool kMov>
-static void launch_pass_m(const StepArgs& A, const TabView<R>& T, const Work& W, int cap, size_t dshm,
-                          unsigned grid, int filter, int fcap, hipStream_t st, PassTiming* pt) {
+static void launch_pass_m(const StepArgs& A, const TabView<R>& T, const Work& W, const PassLaunch& L,
+                          hipStream_t st, PassTiming* pt) {
     const auto launch = [&](auto kernel) {
-        lds_attr((const void*)kernel, dshm, st);
+        lds_attr((const void*)kernel, L.dshm, st);
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (pt) { e0 = pt->first ? pt->start : nullptr; e1 = pt->stop; pt->first = false; }
-        hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(256), (uint32_t)dshm, st, e0, e1, 0u, A, T, W, cap, filter, fcap);
+        hipExtLaunchKernelGGL(kernel, dim3(L.grid), dim3(256), (uint32_t)L.dshm, st, e0, e1, 0u, A, T, W, L.cap,
+                              L.filter, L.fcap, L.slow_cap, L.from_list);
     };
     if (A.proc & (CMC_BREMS | CMC_TRIDENT)) launch(k_pass<R, kT, 0, kMov>);
     if (A.proc & CMC_BH) launch(k_pass<R, kT, 1, kMov>);
 }
 
 template <typename R, int kT>
-static void launch_pass_t(const StepArgs& A, const TabView<R>& T, const Work& W, int cap, size_t dshm,
-                          unsigned grid, int filter, int fcap, hipStream_t st, PassTiming* pt) {
-    if (A.io.px) {
-        launch_pass_m<R, kT, true>(A, T, W, cap, dshm, grid, filter, fcap, st, pt);
-    } else {
-        launch_pass_m<R, kT, false>(A, T, W, cap, dshm, grid, filter, fcap, st, pt);
-    }
+static void launch_pass_t(const StepArgs& A, const TabView<R>& T, const Work& W, const PassLaunch& L,
+                          hipStream_t st, PassTiming* pt) {
+    if (A.io.px) launch_pass_m<R, kT, true>(A, T, W, L, st, pt);
+    else launch_pass_m<R, kT, false>(A, T, W, L, st, pt);
 }
 
-// the pass kernels with teams of `team` threads over the cells of a size
-// class (filter 0: all)
-static void launch_team(const StepArgs& A, const cmc_tables_s* t, const Work& W, bool fp64, int team, int filter,
-                        int fcap, int64_t max_blocks, hipStream_t st, PassTiming* pt) {
-    const int cap = team_cap(team, A.maxn, fp64);
-    const size_t per = (team_bytes(cap, fp64 ? 8 : 4, team) + 15) / 16 * 16;
-    const size_t dshm = per * (size_t)(256 / team);
+static void launch_team(const StepArgs& A, const cmc_tables_s* t, const Work& W, bool fp64, int team, int cap,
+                        int filter, int fcap, int slow_cap, int from_list, int64_t max_blocks, hipStream_t st,
+                        PassTiming* pt) {
+    PassLaunch L;
+    L.cap = cap; L.filter = filter; L.fcap = fcap; L.slow_cap = slow_cap; L.from_list = from_list;
+    L.dshm = ((team_bytes(cap, fp64 ? 8 : 4, team) + 15) / 16 * 16) * (size_t)(256 / team);
     const int64_t units = team == 64 ? (A.n_cells + 3) / 4 : A.n_cells;
-    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(units, max_blocks));
+    L.grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(units, max_blocks));
     if (fp64) {
-        if (team == 64) launch_pass_t<double, 64>(A, view64(t), W, cap, dshm, grid, filter, fcap, st, pt);
-        else launch_pass_t<double, 256>(A, view64(t), W, cap, dshm, grid, filter, fcap, st, pt);
+        if (team == 64) launch_pass_t<double, 64>(A, view64(t), W, L, st, pt);
+        else launch_pass_t<double, 256>(A, view64(t), W, L, st, pt);
     } else {
-        if (team == 64) launch_pass_t<float, 64>(A, view32(t), W, cap, dshm, grid, filter, fcap, st, pt);
-        else launch_pass_t<float, 256>(A, view32(t), W, cap, dshm, grid, filter, fcap, st, pt);
+        if (team == 64) launch_pass_t<float, 64>(A, view32(t), W, L, st, pt);
+        else launch_pass_t<float, 256>(A, view32(t), W, L, st, pt);
     }
 }
 
@@ -2364,12 +2513,21 @@ constexpr int kHybrid = -1;
 
 static cmc_status launch_passes(const StepArgs& A, const cmc_tables_s* t, const Work& W, bool fp64, int shape,
                                 hipStream_t st, PassTiming* pt = nullptr) {
-    if (shape == kHybrid) {
-        const int small = team_cap(64, A.maxn, fp64);
-        launch_team(A, t, W, fp64, 64, 1, small, 256 * 64, st, pt);
-        launch_team(A, t, W, fp64, 256, 2, small, 2048, st, pt);
+    const int big = team_cap(256, A.maxn, fp64, 1);
+    const int main = std::min(big, team_cap(256, A.maxn, fp64, kMainWgs));
+    const int small = team_cap(64, A.maxn, fp64);
+    if (shape == 64) {
+        // wavefront teams only: cells above their capacity take the sequential step
+        launch_team(A, t, W, fp64, 64, small, 0, 0, small, 0, 256 * 64, st, pt);
     } else {
-        launch_team(A, t, W, fp64, shape, 0, 0, 256 * 64, st, pt);
+        if (shape == kHybrid) {
+            launch_team(A, t, W, fp64, 64, small, 1, small, big, 0, 256 * 64, st, pt);
+            launch_team(A, t, W, fp64, 256, main, 2, small, big, 0, 256 * 64, st, pt);
+        } else {
+            launch_team(A, t, W, fp64, 256, main, 0, 0, big, 0, 256 * 64, st, pt);
+        }
+        // the passes that needed more LDS than the first launch has
+        if (big > main) launch_team(A, t, W, fp64, 256, big, 0, 0, big, 1, 1024, st, pt);
     }
     CMC_CHECK_LAUNCH("cmc_collide_step: k_pass");
     return CMC_OK;
@@ -2549,14 +2707,27 @@ extern "C" cmc_status cmc_collide_step(cmc_tables t, const cmc_cells* cells, cmc
     if (s1 != CMC_OK) return s1;
     // the listed cells: open pairs and events, or the sequential step (a
     // short list: a small grid)
+    // When electron-ion pairs can be open, a wavefront per listed cell
+    // first settles and applies the cells that need no workgroup and hands
+    // the others on; with Bethe-Heitler alone every listed cell needs the
+    // workgroup kernel, which then walks the list itself.
     const unsigned gev = (unsigned)std::min<int64_t>(A.n_cells, 512);
     const size_t shm_ev = std::max(shm, (size_t)kStagePh * 40);
+    const int from_wave = (A.proc & (CMC_BREMS | CMC_TRIDENT)) ? 1 : 0;
+    if (from_wave) {
+        const unsigned gw = (unsigned)std::min<int64_t>((A.n_cells + kWaves - 1) / kWaves, 2048);
+        if (fp64) hipLaunchKernelGGL(k_events_wave<double>, dim3(gw), dim3(kThreads), 0, st, A, view64(t), view64(t), W);
+        else hipLaunchKernelGGL(k_events_wave<float>, dim3(gw), dim3(kThreads), 0, st, A, view32(t), view64(t), W);
+        CMC_CHECK_LAUNCH("cmc_collide_step: k_events_wave");
+    }
     if (fp64) {
         lds_attr((const void*)k_events<double>, shm_ev, st);
-        hipLaunchKernelGGL(k_events<double>, dim3(gev), dim3(kThreads), shm_ev, st, A, view64(t), view64(t), W);
+        hipLaunchKernelGGL(k_events<double>, dim3(gev), dim3(kThreads), shm_ev, st, A, view64(t), view64(t), W,
+                           from_wave);
     } else {
         lds_attr((const void*)k_events<float>, shm_ev, st);
-        hipLaunchKernelGGL(k_events<float>, dim3(gev), dim3(kThreads), shm_ev, st, A, view32(t), view64(t), W);
+        hipLaunchKernelGGL(k_events<float>, dim3(gev), dim3(kThreads), shm_ev, st, A, view32(t), view64(t), W,
+                           from_wave);
     }
     CMC_CHECK_LAUNCH("cmc_collide_step: k_events");
     return CMC_OK;

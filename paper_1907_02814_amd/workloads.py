@@ -59,6 +59,38 @@ class Workload:
                                    photons=tt(self.photons), ions=tt(self.ions),
                                    new_el=tt(self.new_el), new_po=tt(self.new_po))
 
+    def host_subset(self, cells_idx) -> "Workload":
+        """The given cells of a workload held in device tensors, copied to a
+        host workload of numpy arrays (global ids in cells['cell_id']);
+        only those cells' ranges are read from the device."""
+        import torch
+        idx = np.asarray(cells_idx, dtype=np.int64)
+
+        def sub(d):
+            off = d["off"].cpu().numpy()
+            starts, ends = off[idx], off[idx + 1]
+            new_off = np.zeros(len(idx) + 1, dtype=np.int64)
+            np.cumsum(ends - starts, out=new_off[1:])
+            take = np.concatenate([np.arange(a, b) for a, b in zip(starts, ends)]) if len(idx) else np.zeros(0, np.int64)
+            out = {"off": new_off}
+            for k, v in d.items():
+                if k == "off":
+                    continue
+                if v is None:
+                    out[k] = None
+                elif k == "count":
+                    out[k] = np.ascontiguousarray(v.cpu().numpy()[idx])
+                else:
+                    t = torch.from_numpy(take).to(v.device)
+                    out[k] = np.ascontiguousarray(v.index_select(0, t).cpu().numpy())
+            return out
+        cells = {k: np.ascontiguousarray(v.cpu().numpy()[idx]) for k, v in self.cells.items() if k != "cell_id"}
+        base_id = self.cells.get("cell_id")
+        cells["cell_id"] = idx.copy() if base_id is None else np.ascontiguousarray(base_id.cpu().numpy()[idx])
+        return dataclasses.replace(self, name=self.name + "-subset", cells=cells,
+                                   electrons=sub(self.electrons), photons=sub(self.photons),
+                                   ions=sub(self.ions), new_el=sub(self.new_el), new_po=sub(self.new_po))
+
     def subset(self, cells_idx) -> "Workload":
         """The given cells (global ids kept in cells['cell_id']) as a new workload."""
         idx = np.asarray(cells_idx, dtype=np.int64)
@@ -123,14 +155,23 @@ def power_law_counts(rng, n, alpha, lo, hi):
     return np.clip(np.floor(x).astype(np.int64), lo, hi)
 
 
-def maxwell_juttner_gamma(rng, n, theta, grid=200000):
-    """Lorentz factors from f ~ gamma^2 beta exp(-gamma/theta) (isotropic
-    relativistic Maxwellian) by inverse CDF on a fine grid."""
+def maxwell_juttner_table(theta, grid=200000):
+    """Lorentz factors g and the cumulative distribution of
+    f ~ gamma^2 beta exp(-gamma/theta) (isotropic relativistic Maxwellian)
+    at them, on a fine grid (trapezoid rule): the inverse-CDF table of the
+    samplers below."""
     g = 1.0 + np.linspace(0.0, 60.0 * theta + 40.0, grid) ** 1.0
     g = np.concatenate([1.0 + np.geomspace(1e-9, 1e-2, 2000), g[g > 1.0 + 1e-2]])
     pdf = g * np.sqrt(g * g - 1.0) * np.exp(-(g - 1.0) / theta)
     cdf = np.concatenate([[0.0], np.cumsum(0.5 * (pdf[1:] + pdf[:-1]) * np.diff(g))])
     cdf /= cdf[-1]
+    return g, cdf
+
+
+def maxwell_juttner_gamma(rng, n, theta, grid=200000):
+    """Lorentz factors from f ~ gamma^2 beta exp(-gamma/theta) (isotropic
+    relativistic Maxwellian) by inverse CDF on a fine grid."""
+    g, cdf = maxwell_juttner_table(theta, grid)
     return np.interp(rng.uniform(0.0, 1.0, n), cdf, g)
 
 
@@ -266,23 +307,85 @@ def cfg4(rng: Optional[np.random.Generator] = None, n_cells=1024, per_cell=4096,
 
 
 MJ_THETA = 5.0 / MEC2_MEV      # T = 5 MeV
+CFG5_W_E = 1.5e25              # fast-electron density of the 10 um foil, m^-3 (Sec. IV)
 
 
-def cfg5(rng: Optional[np.random.Generator] = None, n_cells=131072, per_cell=4096, dt=5e-17) -> Workload:
+def cfg5(rng: Optional[np.random.Generator] = None, n_cells=131072, per_cell=4096, dt=5e-17,
+         processes=PROC_BREMS | PROC_BH) -> Workload:
     """Foil-transport scale Bremsstrahlung -> Bethe-Heitler chain: Au ions,
     n_i=5.9e22 cm^-3, Z*=5, T=1 eV (the paper's foil values applied to Au);
     electrons Maxwell-Juttner with T=5 MeV, isotropic, W_e=1.5e19 cm^-3/4096;
-    photon and pair buffers 2x the electron count per cell; dt=0.05 fs."""
+    photon and pair buffers 2x the electron count per cell; dt=0.05 fs.
+    Host arrays, for cells in numbers the host holds (cfg5_device builds the
+    full size in device memory)."""
     rng = rng or np.random.default_rng(1005)
     n_i = 5.9e28
     N = n_cells * per_cell
     g = maxwell_juttner_gamma(rng, N, MJ_THETA)
     cnt = np.full(n_cells, per_cell)
-    return assemble("cfg5-foil-chain", 79, dt, PROC_BREMS | PROC_BH | PROC_TRIDENT, 1000,
+    return assemble("cfg5-foil-chain", 79, dt, processes, 1000,
                     np.full(n_cells, 5.0), np.full(n_cells, n_i), np.full(n_cells, 1.0),
-                    g, np.full(N, 1.5e25 / per_cell), cnt, np.zeros(0), np.zeros(0),
+                    g, np.full(N, CFG5_W_E / per_cell), cnt, np.zeros(0), np.zeros(0),
                     np.zeros(n_cells, np.int64), np.full(N, n_i / per_cell), cnt, rng,
                     photon_extra=2 * cnt, pair_cap=2 * cnt)
+
+
+def cfg5_device(device, n_cells=131072, per_cell=4096, dt=5e-17, seed=1005, chunk=1 << 25) -> Workload:
+    """The foil-transport chain of cfg5 generated in device memory, for the
+    full size (about 125 GB in HBM: electrons 17.2 GB, ion weights 4.3 GB,
+    three product slabs of 34.4 GB, no parent arrays): the same recipe as
+    cfg5, drawn from torch's device generator seeded `seed` (uniforms in
+    FP64) instead of numpy's.  Electrons: Maxwell-Juttner with T = 5 MeV
+    by inverse CDF on the table of maxwell_juttner_table (linear between
+    its nodes), isotropic directions; W_e = 1.5e19 cm^-3/4096, ions
+    W_i = n_i/4096; photon, e- and e+ slabs 2 x 4096 per cell, empty.
+    Processes: the Bremsstrahlung -> Bethe-Heitler chain."""
+    import torch
+    dev = torch.device(device)
+    f8, i8 = torch.float64, torch.int64
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
+    N = n_cells * per_cell
+    n_i = 5.9e28
+    g_tab, cdf = maxwell_juttner_table(MJ_THETA)
+    gt = torch.from_numpy(g_tab).to(dev)
+    ct = torch.from_numpy(cdf).to(dev)
+    px = torch.empty(N, dtype=f8, device=dev)
+    py = torch.empty(N, dtype=f8, device=dev)
+    pz = torch.empty(N, dtype=f8, device=dev)
+    for a in range(0, N, chunk):
+        b = min(N, a + chunk)
+        n = b - a
+        u = torch.rand(n, generator=gen, dtype=f8, device=dev)
+        hi = torch.searchsorted(ct, u).clamp_(1, len(cdf) - 1)
+        lo = hi - 1
+        c0, c1, g0, g1 = ct[lo], ct[hi], gt[lo], gt[hi]
+        g = g0 + (u - c0) / (c1 - c0) * (g1 - g0)
+        p = torch.sqrt(torch.clamp(g * g - 1.0, min=0.0))
+        mu = torch.rand(n, generator=gen, dtype=f8, device=dev) * 2.0 - 1.0
+        phi = torch.rand(n, generator=gen, dtype=f8, device=dev) * (2.0 * math.pi)
+        st = torch.sqrt(torch.clamp(1.0 - mu * mu, min=0.0))
+        px[a:b] = p * st * torch.cos(phi)
+        py[a:b] = p * st * torch.sin(phi)
+        pz[a:b] = p * mu
+        del u, hi, lo, c0, c1, g0, g1, g, p, mu, phi, st
+    off = torch.arange(n_cells + 1, dtype=i8, device=dev) * per_cell
+    electrons = {"off": off, "count": None, "px": px, "py": py, "pz": pz,
+                 "w": torch.full((N,), CFG5_W_E / per_cell, dtype=f8, device=dev), "parent": None}
+    ions = {"off": off, "count": None, "px": None, "py": None, "pz": None,
+            "w": torch.full((N,), n_i / per_cell, dtype=f8, device=dev), "parent": None}
+
+    def slab():
+        cap = 2 * per_cell
+        return {"off": torch.arange(n_cells + 1, dtype=i8, device=dev) * cap,
+                "count": torch.zeros(n_cells, dtype=torch.int32, device=dev),
+                **{k: torch.empty(n_cells * cap, dtype=f8, device=dev) for k in ("px", "py", "pz", "w")},
+                "parent": None}
+    cells = {"Zstar": torch.full((n_cells,), 5.0, dtype=f8, device=dev),
+             "n_i": torch.full((n_cells,), n_i, dtype=f8, device=dev),
+             "T_e": torch.full((n_cells,), 1.0, dtype=f8, device=dev)}
+    return Workload("cfg5-foil-chain", 79, dt, PROC_BREMS | PROC_BH, 1000, cells, electrons, slab(), ions,
+                    slab(), slab(), 1)
 
 
 CONFIGS = {"cfg1": cfg1, "cfg2": cfg2, "cfg3": cfg3, "cfg5": cfg5}

@@ -39,6 +39,49 @@ def test_foil_cells_full_size_fp32():
     assert P.ref.photons["count"].sum() > 0
 
 
+@pytest.mark.parametrize("precision", [1, 0])
+def test_cfg5_full_size_sampled_cells(precision):
+    """cfg5 in full (131072 cells x (4096 electrons + 4096 Au ions),
+    generated in HBM, about 125 GB), in the launch configuration bench.py
+    times, three steps of the Bremsstrahlung -> Bethe-Heitler chain: 1024
+    seeded cells (the bench's oracle sample) against the oracle run on the
+    same cells with their global ids, after every step."""
+    import gc
+    import torch
+    import paper_1907_02814_amd as cmc
+    from gpu_parity import compare_host_subsets, gpu_tables
+    g = W.cfg5_device("cuda:0")
+    n = g.cells["Zstar"].numel()
+    assert n == 131072 and int(g.electrons["off"][-1].item()) == 131072 * 4096
+    sample = np.sort(np.random.default_rng(1005).choice(n, 1024, replace=False))
+    ref = g.host_subset(sample)
+    st = cmc.StepState(gpu_tables(79), g.cells, g.electrons, g.photons, g.ions, g.new_el, g.new_po, dt=g.dt,
+                       seed=1, processes=g.processes, precision=precision)
+    rtol = 1e-12 if precision == cmc.FP64 else 1e-5
+    skip = np.zeros(len(sample), bool)
+    events = 0
+    try:
+        for s in range(3):
+            st.step(s)
+            torch.cuda.synchronize()
+            oti, otd, ost = O.collide_step(O.tables(79), ref.cells, ref.electrons, ref.photons, ref.ions,
+                                           ref.new_el, ref.new_po, g.dt, 1, s, g.processes)
+            ti = st.ti.cpu().numpy()[sample]
+            td = st.td.cpu().numpy()[sample]
+            now = g.host_subset(sample)
+            skip, errs = compare_host_subsets(ti, td, now, ref, oti, otd, rtol, skip)
+            events += int(oti[:, 3:6].sum())
+            print(f"[parity] cfg5 full, precision {precision}, step {s}: {int(skip.sum())} cell(s) left out "
+                  f"(near threshold); " + ", ".join(f"{k} {v:.1e}" for k, v in errs.items()))
+        assert int(st.status.item()) == 0
+        assert skip.sum() <= 4
+        assert events > 500
+    finally:
+        del st, g
+        gc.collect()
+        torch.cuda.empty_cache()
+
+
 def test_cfg3_full_sampled_cells():
     import torch
     import paper_1907_02814_amd as cmc

@@ -103,7 +103,8 @@ def test_unequal_ion_weights(precision):
 
 
 def test_foil_chain_cells():
-    wl = W.cfg5(np.random.default_rng(2), n_cells=6, per_cell=4096, dt=5e-14)
+    # foil cells with all three processes (the benchmark chain is Bremsstrahlung -> Bethe-Heitler)
+    wl = W.cfg5(np.random.default_rng(2), n_cells=6, per_cell=4096, dt=5e-14, processes=7)
     P = _run(wl, 3)
     assert P.ref.photons["count"].sum() > 0
 
