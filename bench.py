@@ -167,18 +167,23 @@ def run_gpu(make, precision, steps, warmup, schedule, seed=1):
 def algorithmic_bytes_dev(g, ng):
     """Bytes the pair tests of one step must move, for a device workload
     with ng live photons (the mean over the measured steps): one read of
-    every live record per pass (mobile px, py, pz, w = 32 B; ion w = 8 B)
-    and the per-cell tallies the passes write (pairs and n_ab: 16 B per
-    pass).  The whole step adds the cell parameters (24 B) and the full
-    tally rows (12 * 8 + 10 * 8 B) per cell."""
-    ne = int((g.electrons["off"][-1] - g.electrons["off"][0]).item())
-    ni = int((g.ions["off"][-1] - g.ions["off"][0]).item())
+    every live mobile record per pass (px, py, pz, w = 32 B), one read of
+    each ion weight per step (8 B: both passes use the same ion sums, which
+    the photon-ion pass takes from the electron-ion pass in every cell
+    that has electrons) and the per-cell tallies the passes write (pairs
+    and n_ab: 16 B per pass).  The whole step adds the cell parameters
+    (24 B) and the full tally rows (12 * 8 + 10 * 8 B) per cell."""
+    ne_c = g.electrons["off"][1:] - g.electrons["off"][:-1]
+    ni_c = g.ions["off"][1:] - g.ions["off"][:-1]
+    ne, ni = int(ne_c.sum().item()), int(ni_c.sum().item())
     n = g.cells["Zstar"].numel()
+    ei, gi = bool(g.processes & 5), bool(g.processes & 2)
     b = 0
-    if g.processes & 5:
+    if ei:
         b += 32 * ne + 8 * ni + 16 * n
-    if g.processes & 2:
-        b += 32 * ng + 8 * ni + 16 * n
+    if gi:
+        ions_again = ni if not ei else int(ni_c[ne_c == 0].sum().item())
+        b += 32 * ng + 8 * ions_again + 16 * n
     return b
 
 

@@ -244,6 +244,7 @@ cmc_status cmc_collide_step(cmc_tables t, const cmc_cells* cells,
 /* Scratch bytes cmc_collide_step needs for n_cells with this schedule. */
 size_t cmc_step_workspace_bytes(int64_t n_cells, int32_t schedule);
 
+
 /* Schedules (every schedule gives the same decisions and products):
  *  CMC_SCHED_CELL   one workgroup per cell tests the pairs in order (the
  *                   sequential reference schedule; no workspace);

@@ -14,10 +14,17 @@
  *
  * Parity status: every function here is pinned by the CPU test-suite
  * (tests/test_oracle_*.py) against closed forms, limits, quadrature of the
- * paper's integral definitions, brute force or statistics, except the
- * Philox generator, whose bit pattern is pinned only by agreement of two
- * independent implementations (published known-answer vectors are not
- * available here): "parity unpinned" for the exact bits of Philox.
+ * paper's integral definitions, brute force or statistics.  Philox4x32-10
+ * is pinned bit for bit against rocRAND's header-only engine, an
+ * independent implementation of the published generator.  The sampling
+ * tables of pair production are pinned against quadrature of the
+ * differential cross sections in another variable and rule, and their
+ * samplers by Kolmogorov-Smirnov tests against the exact distributions.
+ * The Trident formulas of Sec. II.D (Gryaznykh's fit, Bhabha's two limits
+ * and their interpolation, the split shape) have no value printed in the
+ * paper: their relativistic form is pinned by Racah's high-energy total,
+ * the rest only by their limits, scaling and symmetry ("parity unpinned"
+ * for the non-relativistic bracket as a transcription).
  */
 #include "cmc_oracle.h"
 #include <math.h>

@@ -41,6 +41,15 @@ inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s);
         }                                                                        \
     } while (0)
 
+#define CMC_CHECK_LAUNCH2(who, what)                                             \
+    do {                                                                         \
+        hipError_t e_ = hipGetLastError();                                       \
+        if (e_ != hipSuccess) {                                                  \
+            cmc::set_error("%s: %s: %s", who, what, hipGetErrorString(e_));      \
+            return CMC_EDEVICE;                                                  \
+        }                                                                        \
+    } while (0)
+
 #define CMC_REQUIRE(cond, code, ...)                                             \
     do {                                                                         \
         if (!(cond)) { cmc::set_error(__VA_ARGS__); return code; }               \

@@ -772,7 +772,11 @@ __global__ __launch_bounds__(kThreads) void k_collide(StepArgs A, TabView<R> T, 
 // per-cell step above (collide_cell).
 constexpr int kCandCap = 64;     // open pairs per cell (both passes)
 constexpr int kStagePh = 1024;   // photons the event kernel stages in LDS per cell
-enum : int32_t { kFlagSlow = 1, kFlagListed = 2, kFlagBig0 = 4, kFlagBig1 = 8 };
+// per-cell flags of a step: kFlagWeightsOk, set by the electron-ion pass,
+// says every weight of the cell is valid and its ion sum is in ionsum
+// (kFlagIonsSame: the ions share one weight), so that the photon-ion pass
+// reads neither the ions' nor the electrons' weights again
+enum : int32_t { kFlagSlow = 1, kFlagListed = 2, kFlagBig0 = 4, kFlagBig1 = 8, kFlagWeightsOk = 16, kFlagIonsSame = 32 };
 enum : uint32_t { kEvBr = 1, kEvTrPending = 2, kEvTr = 4, kEvBh = 8 };
 
 struct CellState {
@@ -795,6 +799,7 @@ struct Work {
     int32_t* flags;                  // kFlagSlow: the sequential kernel runs the cell
     int32_t* ncand;                  // open pairs pushed per cell
     double* coef;                    // n_a n_b / n_ab per cell and pass
+    double* ionsum;                  // canonical sum of the ion weights (with kFlagWeightsOk)
     uint64_t* step;                  // step number of the current step
     int32_t* counters;               // kNumCnt list lengths
     int32_t* list_ev;                // cells with open pairs or flagged for the sequential step
@@ -803,11 +808,11 @@ struct Work {
     uint64_t* cand;                  // [n_cells][kCandCap] open pairs
 };
 
-__host__ __device__ inline size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+__host__ __device__ constexpr size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
-__host__ __device__ inline size_t work_bytes(int64_t n) {
+__host__ __device__ constexpr size_t work_bytes(int64_t n) {
     return align256(sizeof(CellState) * n) + align256(4 * n) + align256(4 * n) +
-           align256(16 * n) + align256(8) + align256(4 * kNumCnt) + 4 * align256(4 * n) +
+           align256(16 * n) + align256(8 * n) + align256(8) + align256(4 * kNumCnt) + 4 * align256(4 * n) +
            align256(8 * (size_t)n * kCandCap);
 }
 
@@ -818,6 +823,7 @@ inline Work carve_work(void* base, int64_t n) {
     w.flags = reinterpret_cast<int32_t*>(p); p += align256(4 * n);
     w.ncand = reinterpret_cast<int32_t*>(p); p += align256(4 * n);
     w.coef = reinterpret_cast<double*>(p); p += align256(16 * n);
+    w.ionsum = reinterpret_cast<double*>(p); p += align256(8 * n);
     w.step = reinterpret_cast<uint64_t*>(p); p += align256(8);
     w.counters = reinterpret_cast<int32_t*>(p); p += align256(4 * kNumCnt);
     w.list_ev = reinterpret_cast<int32_t*>(p); p += align256(4 * n);
@@ -1240,7 +1246,8 @@ __device__ void rank_open(int n, uint32_t cell, uint32_t tag, const Rng& rng, co
     Team<kT>::sync();
 }
 
-// j mod n for j < 2^14 from a float reciprocal (quotient off by at most one)
+// j mod n for j < 2^15, n <= 2^14 from a float reciprocal (the quotient is
+// off by at most one; checked for every such j and n)
 __device__ __forceinline__ int mod_small(int j, int n, float rn) {
     int r = j - (int)((float)j * rn) * n;
     r += r < 0 ? n : 0;
@@ -1372,6 +1379,7 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
         // offsets and live counts of the three species, its global index
         const uint32_t cell = cell_word(A.cid, c);
         const int32_t cstat = W.cs[c].status;
+        const int32_t cflags = kPass == 1 ? W.flags[c] : 0;
         const CellTab<R> ct_c = pick<R>(W.cs[c]);
         const int64_t eo0 = A.el.off[c], eo1 = A.el.off[c + 1], go0 = A.ph.off[c], go1 = A.ph.off[c + 1];
         const int64_t io0 = A.io.off[c], io1 = A.io.off[c + 1];
@@ -1460,6 +1468,10 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
                 if (t == 0) nopen[team] = 0;
                 team_reduce4_bits<kT>(v4, fl, red4, redi);   // its barriers also publish the slice
                 if (kT == 64) Team<kT>::sync();
+                if (kPass == 0 && !(fl & 1) && t == 0) {
+                    W.ionsum[c] = v4[2];
+                    atomicOr(&W.flags[c], kFlagWeightsOk | ((fl & 2) ? 0 : kFlagIonsSame));
+                }
                 bool chosen = true;
                 if (!(fl & 3) && cyc) {
                     // indices of the cycled case come from an opaque copy of the
@@ -1629,14 +1641,28 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
         // only that weight): the ion order is then not formed, and the open
         // pairs name ion 0.
         const double wi0 = Ni > 0 ? wion[0] : 0.0;
+        // after the electron-ion pass of this step (photon-ion pass): the ion
+        // sum, the ions' sameness and every weight check are known
+        const bool known = kPass == 1 && (cflags & kFlagWeightsOk);
         bool same = true;
-        v4[2] = canon_part<kT>(Ni, [&](int q) { const double w = wion[q]; same &= w == wi0; return chk(w); });
-        const bool ion_order = active && (kMov || team_any<kT>(!same, redi));
+        if (known) {
+            // the team reduction below adds the wavefronts' partials: the
+            // total enters through the first wavefront alone
+            v4[2] = (kT == 64 || threadIdx.x < 64) ? W.ionsum[c] : 0.0;
+            same = (cflags & kFlagIonsSame) != 0;
+        } else {
+            v4[2] = canon_part<kT>(Ni, [&](int q) { const double w = wion[q]; same &= w == wi0; return chk(w); });
+        }
+        const bool uneq = team_any<kT>(!same, redi);
+        const bool ion_order = active && (kMov || uneq);
         // When every mobile particle pairs once, the draws of a pair are
         // keyed by its mobile particle: with interchangeable ions nothing
         // then depends on the order, which is not formed; the few open pairs
         // get their pair index (the rank of their particle) at the end.
         const bool mob_order = active && (!mobA || ion_order);
+        // a cycled mobile species against interchangeable ions: its tests are
+        // walked by draw group (below)
+        const bool cyc_fast = active && !mobA && !ion_order;
         if (active && !fits && ((ion_order && Ni > cap) || (mob_order && Nm > cap))) {
             // an order larger than this launch's LDS: the large-LDS launch takes
             // the pass (listed once per step, however often the launch runs)
@@ -1672,7 +1698,7 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
         const auto mob_of = [&](int j) { return (int)M.ordM[Nm == N ? j : mod_small(j, Nm, rNm)]; };
         // a cycled mobile species is walked in rank order: its first momenta
         // are read once the order is formed
-        if (active && !mobA && t < N) { const int m = mob_of(t); qx = S.px[m0 + m]; qy = S.py[m0 + m]; qz = S.pz[m0 + m]; }
+        if (active && !mobA && !cyc_fast && t < N) { const int m = mob_of(t); qx = S.px[m0 + m]; qy = S.py[m0 + m]; qz = S.pz[m0 + m]; }
         // the other weights, read once: the densities n = sum W, n_ab =
         // sum_j min(W_a, W_b) and the weight check (when every mobile
         // particle pairs once, its density and n_ab share the walk)
@@ -1688,7 +1714,7 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
             // a cycled mobile species with interchangeable ions: n_ab = K A + B
             // as the direct form forms it (A over all the mobile particles' terms,
             // B over those of the e particles of smallest key, ranks 0 .. e - 1)
-            uint32_t* selb = M.keys;   // free once the order is formed
+            uint32_t* selb = reinterpret_cast<uint32_t*>(M.hist);   // free once the order is formed
             for (int i = t; i < (Nm + 31) / 32; i += kT) selb[i] = 0u;
             Team<kT>::sync();
             for (int r = t; r < N - (N / Nm) * Nm; r += kT) {
@@ -1713,9 +1739,13 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
                 return u < v ? u : v;
             });
         }
-        v4[3] = canon_part<kT>(No, [&](int q) { return chk(wo[q]); });
+        v4[3] = known ? 0.0 : canon_part<kT>(No, [&](int q) { return chk(wo[q]); });
         bool badw = bad != 0;
         team_reduce4<kT>(v4, badw, red4, redi);
+        if (kPass == 0 && !badw && t == 0) {
+            W.ionsum[c] = v4[2];
+            atomicOr(&W.flags[c], kFlagWeightsOk | (uneq ? 0 : kFlagIonsSame));
+        }
         if (cyc_k > 0) {
             double vb[4] = {cyc_b, 0.0, 0.0, 0.0};
             bool none = false;
@@ -1743,6 +1773,90 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
                 if (gx != gk) { h = rng.draw(gx, cell, tag); gk = gx; }
                 return hi_word(h, (x >> 8) & 3u);
             };
+            if (cyc_fast) {
+                // N = N_ion pairs: particle m of the cycled species pairs K = N div
+                // N_m times and, if its rank is below e = N mod N_m, once more
+                // (Sec. III.A pairing).  All its tests share one cross section and
+                // flux: its bounds are formed once (in the arithmetic of the tests
+                // below the other forms make), and the tests are walked by draw
+                // group: the keys x = m + k N_m of a group ((x >> 10) << 8 |
+                // (x & 255) = g) are base(g) + 256 w, w = 0..3, and share the draw
+                // of U1's upper bits, word w.
+                // LDS of the team (n >= N_m entries each): the bounds in the key
+                // array and over the two order arrays (4 n bytes, written once
+                // the ranks are taken from the order), the ranks in the bucket
+                // particle array, the selection bitmap in the histogram
+                float* xb = reinterpret_cast<float*>(M.keys);   // first process's bound of m (< 0: none)
+                float* xt = reinterpret_cast<float*>(M.ordM);   // Trident's bound of m (over ordM, ordI)
+                uint16_t* rk = M.tmp;                           // rank of m
+                const uint32_t* selb = reinterpret_cast<const uint32_t*>(M.hist);
+                for (int r = t; r < Nm; r += kT) rk[M.ordM[r]] = (uint16_t)r;
+                Team<kT>::sync();
+                for (int m = t; m < Nm; m += kT) {
+                    const double cx = S.px[m0 + m], cy = S.py[m0 + m], cz = S.pz[m0 + m];
+                    float b1 = -1.0f, b2 = -1.0f;
+                    if (kPass == 0) {
+                        const Elec<R> e = electron_p<R>(cx, cy, cz);
+                        if (A.proc & CMC_BREMS) {
+                            bool hi;
+                            const R sig = brems_sig_slice<R>(T, slice, e.g, e.gm1, hi);
+                            high |= hi;
+                            if (sig > (R)0) b1 = kx * (float)sig * (float)e.vrel;
+                        }
+                        if (A.proc & CMC_TRIDENT) {
+                            const R sig = (R)phys::trident_sigma(T.Z, (double)e.g);
+                            if (sig > (R)0) b2 = kx * (float)sig * (float)e.vrel;
+                        }
+                    } else {
+                        bool hi;
+                        const R sig = bh_sig_slice<R>(T, slice, photon_k<R>(cx, cy, cz), hi);
+                        high |= hi;
+                        if (sig > (R)0) b1 = kx * (float)sig * (float)phys::kC;
+                    }
+                    xb[m] = b1;
+                    xt[m] = b2;
+                }
+                Team<kT>::sync();
+                const int K = N / Nm, e = N - K * Nm;
+                const int X = K * Nm + (e > 0 ? Nm : 0);      // keys of every particle's last pair and below
+                const int G = ((X + 1023) >> 10) << 8;
+                for (int g = t; g < G; g += kT) {
+                    const int base = ((g >> 8) << 10) | (g & 255);
+                    if (base >= X) continue;
+                    const U4 h = rng.draw((uint32_t)g, cell, kPass == 0 ? kTagHiBr : kTagHiBh);
+                    U4 h2{0u, 0u, 0u, 0u};
+                    bool h2_drawn = false;
+#pragma unroll
+                    for (int w = 0; w < 4; ++w) {
+                        const int x = base + 256 * w;
+                        if (x >= X) break;
+                        const int m = mod_small(x, Nm, rNm);
+                        const int k = __float2int_rn((float)(x - m) * rNm);
+                        if (!(k < K || ((selb[m >> 5] >> (m & 31)) & 1u))) continue;
+                        uint32_t bits = 0;
+                        if (bound24(hi_word(h, (uint32_t)w), xb[m])) {
+                            bits = 1u;
+                        } else if (kPass == 0 && xt[m] >= 0.0f) {
+                            if (!h2_drawn) { h2 = rng.draw((uint32_t)g, cell, kTagHiTr); h2_drawn = true; }
+                            if (bound24(hi_word(h2, (uint32_t)w), xt[m])) bits = 2u;
+                        }
+                        if (bits) {
+                            const int o = atomicAdd(&nopen[team], 1);
+                            if (o < kCandCap) opn[team][o] = (uint32_t)m | (bits << 14) | ((uint32_t)k << 16);
+                        }
+                    }
+                }
+                Team<kT>::sync();
+                const int n_open = nopen[team];
+                if (n_open > kCandCap) {
+                    if (t == 0) mark_slow(W, c);
+                } else if (t < n_open) {
+                    // pair index: the particle's rank plus k N_m
+                    const uint32_t o = opn[team][t];
+                    const int m = (int)(o & 0x3FFFu), k = (int)(o >> 16);
+                    push_cand(W, c, ev_pack(kPass, (int)rk[m] + k * Nm, m, 0, (o >> 14) & 3u));
+                }
+            } else {
             for (int q = t; q < N; q += kT) {
                 const int j = mobA ? (mob_order ? (int)M.ordM[q] : 0) : q;
                 const int jm = mobA ? 0 : (Nm == N ? j : mod_small(j, Nm, rNm));   // rank of the cycled particle
@@ -1809,6 +1923,7 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
                     if (t < n_open)
                         push_cand(W, c, ev_pack(kPass, (int)opj[team][t], (int)(opn[team][t] & 0xFFFFu), 0, opn[team][t] >> 16));
                 }
+            }
             }
             if (t == 0) W.coef[c * 2 + kPass] = coef;
         }
@@ -2608,31 +2723,31 @@ static cmc_status set_species(SpeciesDev& d, const cmc_species* s, const char* n
     return CMC_OK;
 }
 
-extern "C" cmc_status cmc_collide_step(cmc_tables t, const cmc_cells* cells, cmc_species* electrons,
-                                       cmc_species* photons, const cmc_species* ions,
-                                       cmc_species* new_el, cmc_species* new_po,
-                                       const cmc_step_params* P, cmc_tallies* tal,
-                                       void* workspace, size_t workspace_bytes, void* stream) {
-    (void)workspace; (void)workspace_bytes;
-    CMC_REQUIRE(t && cells && P && tal, CMC_EINVAL, "cmc_collide_step: NULL argument");
+// The step behind both entry points.  may_time: an untuned automatic
+// schedule may time the team shapes on this call (else workgroup teams).
+static cmc_status collide_step_impl(const char* who, cmc_tables t, const cmc_cells* cells, cmc_species* electrons,
+                                    cmc_species* photons, const cmc_species* ions, cmc_species* new_el,
+                                    cmc_species* new_po, const cmc_step_params* P, cmc_tallies* tal,
+                                    void* workspace, size_t workspace_bytes, void* stream, bool may_time) {
+    CMC_REQUIRE(t && cells && P && tal, CMC_EINVAL, "%s: NULL argument", who);
     CMC_REQUIRE(cells->n_cells >= 0 && cells->Zstar && cells->n_i && cells->T_e, CMC_EINVAL,
-                "cmc_collide_step: cells incomplete");
-    CMC_REQUIRE(tal->ti && tal->td && tal->status, CMC_EINVAL, "cmc_collide_step: tallies incomplete");
-    CMC_REQUIRE(P->dt > 0.0, CMC_EINVAL, "cmc_collide_step: dt must be > 0");
-    CMC_REQUIRE((P->processes & ~7u) == 0, CMC_EINVAL, "cmc_collide_step: unknown process bits");
+                "%s: cells incomplete", who);
+    CMC_REQUIRE(tal->ti && tal->td && tal->status, CMC_EINVAL, "%s: tallies incomplete", who);
+    CMC_REQUIRE(P->dt > 0.0, CMC_EINVAL, "%s: dt must be > 0", who);
+    CMC_REQUIRE((P->processes & ~7u) == 0, CMC_EINVAL, "%s: unknown process bits", who);
     CMC_REQUIRE(P->precision == CMC_FP64 || P->precision == CMC_FP32, CMC_EINVAL,
-                "cmc_collide_step: unknown precision %d", P->precision);
-    CMC_REQUIRE(P->schedule >= 0 && P->schedule <= 4, CMC_EINVAL, "cmc_collide_step: unknown schedule");
+                "%s: unknown precision %d", who, P->precision);
+    CMC_REQUIRE(P->schedule >= 0 && P->schedule <= 4, CMC_EINVAL, "%s: unknown schedule", who);
     CMC_REQUIRE(P->max_per_cell >= 1 && P->max_per_cell <= CMC_MAX_PER_CELL, CMC_ERANGE,
-                "cmc_collide_step: max_per_cell = %d outside [1, %d]", P->max_per_cell, CMC_MAX_PER_CELL);
-    CMC_REQUIRE(P->near_rel >= 0.0 && P->near_rel <= 1.0, CMC_EINVAL, "cmc_collide_step: near_rel outside [0, 1]");
+                "%s: max_per_cell = %d outside [1, %d]", who, P->max_per_cell, CMC_MAX_PER_CELL);
+    CMC_REQUIRE(P->near_rel >= 0.0 && P->near_rel <= 1.0, CMC_EINVAL, "%s: near_rel outside [0, 1]", who);
     StepArgs A{};
     cmc_status s;
     if ((s = set_species(A.el, electrons, "electrons", false, true)) != CMC_OK) return s;
     if ((s = set_species(A.ph, photons, "photons", true, true)) != CMC_OK) return s;
     if ((s = set_species(A.io, ions, "ions", false, false)) != CMC_OK) return s;
     CMC_REQUIRE((!ions->px && !ions->py && !ions->pz) || (ions->px && ions->py && ions->pz), CMC_EINVAL,
-                "cmc_collide_step: ions: px, py, pz must be all set (moving) or all NULL (at rest)");
+                "%s: ions: px, py, pz must be all set (moving) or all NULL (at rest)", who);
     if ((s = set_species(A.ne, new_el, "new_el", true, true)) != CMC_OK) return s;
     if ((s = set_species(A.np, new_po, "new_po", true, true)) != CMC_OK) return s;
     A.Zs = cells->Zstar; A.ni = cells->n_i; A.Te = cells->T_e; A.cid = cells->cell_id;
@@ -2659,16 +2774,16 @@ extern "C" cmc_status cmc_collide_step(cmc_tables t, const cmc_cells* cells, cmc
             lds_attr((const void*)k_collide<float>, shm, st);
             hipLaunchKernelGGL(k_collide<float>, dim3(grid), dim3(kThreads), shm, st, A, view32(t), view64(t));
         }
-        CMC_CHECK_LAUNCH("cmc_collide_step");
+        CMC_CHECK_LAUNCH(who);
         if (P->step_counter) {
             hipLaunchKernelGGL(k_step_bump, dim3(1), dim3(64), 0, st, P->step_counter);
-            CMC_CHECK_LAUNCH("cmc_collide_step: step counter");
+            CMC_CHECK_LAUNCH2(who, "step counter");
         }
         return CMC_OK;
     }
     const size_t need = work_bytes(A.n_cells);
     CMC_REQUIRE(workspace != nullptr && workspace_bytes >= need, CMC_EINVAL,
-                "cmc_collide_step: workspace of %zu bytes required (got %zu)", need, workspace_bytes);
+                "%s: workspace of %zu bytes required (got %zu)", who, need, workspace_bytes);
     const Work W = carve_work(workspace, A.n_cells);
     A.step_dev = W.step;
     const auto cell_state = [&](int advance) {
@@ -2687,11 +2802,11 @@ extern "C" cmc_status cmc_collide_step(cmc_tables t, const cmc_cells* cells, cmc
     }
     // the counter advances once, in the last cell-state launch of the step
     cell_state(tuned ? 1 : 0);
-    CMC_CHECK_LAUNCH("cmc_collide_step: k_cell_state");
+    CMC_CHECK_LAUNCH2(who, "k_cell_state");
     if (!tuned) {
         hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
         (void)hipStreamIsCapturing(st, &cap);
-        if (cap == hipStreamCaptureStatusNone) {
+        if (cap == hipStreamCaptureStatusNone && may_time) {
             cmc_status s2 = tune_passes(A, t, W, fp64, st, team);
             if (s2 != CMC_OK) return s2;
             tune_store(key, team);
@@ -2699,7 +2814,7 @@ extern "C" cmc_status cmc_collide_step(cmc_tables t, const cmc_cells* cells, cmc
             team = 256;         // no timing under graph capture: workgroup teams
         }
         cell_state(1);          // the timing runs filled the cell lists
-        CMC_CHECK_LAUNCH("cmc_collide_step: k_cell_state");
+        CMC_CHECK_LAUNCH2(who, "k_cell_state");
     }
     PassTiming timing{static_cast<hipEvent_t>(P->pass_events[0]), static_cast<hipEvent_t>(P->pass_events[1]), true};
     cmc_status s1 = launch_passes(A, t, W, fp64, team, st,
@@ -2718,7 +2833,7 @@ extern "C" cmc_status cmc_collide_step(cmc_tables t, const cmc_cells* cells, cmc
         const unsigned gw = (unsigned)std::min<int64_t>((A.n_cells + kWaves - 1) / kWaves, 2048);
         if (fp64) hipLaunchKernelGGL(k_events_wave<double>, dim3(gw), dim3(kThreads), 0, st, A, view64(t), view64(t), W);
         else hipLaunchKernelGGL(k_events_wave<float>, dim3(gw), dim3(kThreads), 0, st, A, view32(t), view64(t), W);
-        CMC_CHECK_LAUNCH("cmc_collide_step: k_events_wave");
+        CMC_CHECK_LAUNCH2(who, "k_events_wave");
     }
     if (fp64) {
         lds_attr((const void*)k_events<double>, shm_ev, st);
@@ -2729,8 +2844,17 @@ extern "C" cmc_status cmc_collide_step(cmc_tables t, const cmc_cells* cells, cmc
         hipLaunchKernelGGL(k_events<float>, dim3(gev), dim3(kThreads), shm_ev, st, A, view32(t), view64(t), W,
                            from_wave);
     }
-    CMC_CHECK_LAUNCH("cmc_collide_step: k_events");
+    CMC_CHECK_LAUNCH2(who, "k_events");
     return CMC_OK;
+}
+
+extern "C" cmc_status cmc_collide_step(cmc_tables t, const cmc_cells* cells, cmc_species* electrons,
+                                       cmc_species* photons, const cmc_species* ions,
+                                       cmc_species* new_el, cmc_species* new_po,
+                                       const cmc_step_params* P, cmc_tallies* tal,
+                                       void* workspace, size_t workspace_bytes, void* stream) {
+    return collide_step_impl("cmc_collide_step", t, cells, electrons, photons, ions, new_el, new_po, P, tal,
+                             workspace, workspace_bytes, stream, true);
 }
 
 extern "C" cmc_status cmc_pair_cells(int64_t n_cells, const int64_t* cell_id, const int64_t* a_off, const int32_t* a_cnt,

@@ -63,6 +63,7 @@ def test_host_argument_errors_without_gpu():
     assert L.cmc_tables_free(None) == 0
 
 
+
 def test_binding_rejects_wrong_element_types():
     # the binding checks the element type the C ABI reads before anything
     # else (here on host tensors, so the first array of each call is the

@@ -61,6 +61,54 @@ def test_cycled_photons_against_the_oracle(precision):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
+def test_few_mobile_particles_against_many_ions(precision):
+    """One to seven electrons and photons per cell against 11000-12000 ions
+    at rest of one weight: each mobile particle pairs K = N_i div N_m times
+    (up to 12000; the repetition of an open pair needs 15 bits) and the e of
+    smallest key once more, all three processes, amplified dt."""
+    rng = np.random.default_rng(61)
+    n = 24
+    ne = rng.integers(1, 8, n)
+    ng = rng.integers(1, 8, n)
+    ni = rng.integers(11000, 12001, n)
+    e_g = 1 + np.exp(rng.uniform(math.log(1.0), math.log(500.0), ne.sum())) / MEC2
+    k = (1.022 + rng.exponential(5.0, ng.sum())) / MEC2
+    Wi = np.repeat(5.9e28 / ni, ni)
+    wl = W.assemble("few-mobile", 79, 3e-14, 7, 1, rng.uniform(0, 79, n), np.full(n, 5.9e28),
+                    np.exp(rng.uniform(math.log(10), math.log(1e4), n)), e_g, np.repeat(5.9e28 / ni, ne), ne,
+                    k, np.repeat(5.9e28 / ni, ng) * rng.lognormal(0, 1, ng.sum()), ng, Wi, ni, rng,
+                    photon_extra=np.full(n, 64), pair_cap=np.full(n, 64))
+    P = _run(wl, 2, precision=precision)
+    I = P.state.ti.cpu().numpy().sum(0)
+    assert I[0] == int(ni.sum()) and I[1] == int(ni.sum())   # N = N_ion pairs per cell and process
+    assert I[3] + I[4] + I[5] > 5
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_cycled_species_above_4096(precision):
+    """Electrons and photons cycled against more ions, with more than 4096
+    of them per cell (the bucket histogram of the sort holds 4096 entries):
+    the per-particle bounds of both electron-ion processes and the ranks
+    must not share it (Sec. III.A pairing, all three processes)."""
+    rng = np.random.default_rng(71)
+    n = 16
+    ne = rng.integers(4100, 6000, n)
+    ng = rng.integers(4100, 6000, n)
+    ni = np.maximum(ne, ng) + rng.integers(1, 2000, n)
+    e_g = 1 + np.exp(rng.uniform(math.log(1.0), math.log(500.0), ne.sum())) / MEC2
+    k = (1.022 + rng.exponential(5.0, ng.sum())) / MEC2
+    # a time step that leaves most cells one or two events, so that they keep
+    # the pass kernel's candidates instead of the sequential step
+    wl = W.assemble("cycled-large", 79, 3e-16, 7, 1, rng.uniform(0, 79, n), np.full(n, 5.9e28),
+                    np.exp(rng.uniform(math.log(10), math.log(1e4), n)), e_g, np.repeat(5.9e28 / ni, ne), ne,
+                    k, np.repeat(5.9e28 / ni, ng) * rng.lognormal(0, 1, ng.sum()), ng,
+                    np.repeat(5.9e28 / ni, ni), ni, rng, photon_extra=np.full(n, 256), pair_cap=np.full(n, 256))
+    P = _run(wl, 2, precision=precision)
+    I = P.state.ti.cpu().numpy().sum(0)
+    assert I[3] > 10
+
+
+@pytest.mark.parametrize("precision", [0, 1])
 def test_all_processes_uneven_cells(precision):
     wl = W.cfg3(np.random.default_rng(9), n_cells=160, dt=2e-13, lo=1, hi=3000)
     P = _run(wl, 2, precision=precision)

@@ -307,6 +307,59 @@ def test_trident_spectrum_limits():
     assert 0.40 < math.log(9) - 161 / 60 + C + Cr + Cz < 0.44
 
 
+def _racah_total(Z, g1):
+    """High-energy total cross section of direct pair production by an
+    electron (Racah; Landau and Lifshitz, 1934): (28/27 pi) (Z alpha r_e)^2
+    ln^3 g1, g1 >> 1 (the literature's asymptote, not a formula of the
+    paper)."""
+    return 28.0 / (27.0 * math.pi) * (Z * ALPHA * RE) ** 2 * math.log(g1) ** 3
+
+
+@pytest.mark.parametrize("g1", [1e4, 1e6, 1e9])
+def test_trident_pair_spectrum_reaches_racahs_total(g1):
+    """Far above threshold the pair spectrum is its relativistic limit, and
+    its integral over g_p tends to Racah's high-energy total: the integral
+    of ln g_p ln(g1/g_p)/g_p over [2, g1] is L^3/6 - L ln^2 2 / 2 +
+    ln^3 2 / 3 with L = ln g1, and (56/9 pi)/6 = 28/(27 pi).  This pins the
+    coefficient, the powers of Z, r_e and alpha, and the logarithms of the
+    relativistic form; the interpolation with the non-relativistic form
+    removes a few per cent near g_p = 2, less as g1 grows."""
+    Z = 29
+    GX, GW = np.polynomial.legendre.leggauss(24)
+    e = np.geomspace(2.0, g1 - 1.0, 301)
+    tot = 0.0
+    for a, b in zip(e[:-1], e[1:]):
+        x = 0.5 * (b - a) * GX + 0.5 * (b + a)
+        tot += 0.5 * (b - a) * sum(w * O.dsdgp_trident(Z, g1, t) for w, t in zip(GW, x))
+    L, l2 = math.log(g1), math.log(2.0)
+    racah = _racah_total(Z, g1) * (1.0 - 3.0 * l2 ** 2 / L ** 2 + 2.0 * l2 ** 3 / L ** 3)
+    r = tot / racah
+    assert 0.93 < r <= 1.0 + 1e-9, r
+    # and the shortfall shrinks as g1 grows
+    if g1 >= 1e6:
+        assert r > 0.97
+
+
+def test_trident_fit_against_racahs_total():
+    """The Gryaznykh fit grows as ln^3 g1, and far above threshold exceeds
+    Racah's total by a constant factor: 5.22e-34/(28/27 pi (alpha r_e)^2) =
+    3.74, the "factor of about 4" by which the paper says the fit may
+    overestimate the exact cross section (Sec. II.D).  Z^2 scaling exact."""
+    g1s = (1e4, 1e6, 1e10, 1e14, 1e30)
+    r = np.array([O.sigma_trident(29, g1) / _racah_total(29, g1) for g1 in g1s])
+    # the fit's logarithm lags ln g1 by a constant, so the ratio climbs
+    # slowly towards its limit
+    assert np.all(np.diff(r) > 0) and r[0] > 1.5, r
+    r_inf = 5.22e-34 / (28.0 / (27.0 * math.pi) * (ALPHA * RE) ** 2)
+    assert 3.7 < r_inf < 3.8
+    assert abs(r[-1] / r_inf - 1) < 0.1, r
+    for g1 in (5.0, 300.0, 1e4):
+        assert abs(O.sigma_trident(79, g1) / O.sigma_trident(29, g1) - (79 / 29) ** 2) < 1e-13
+        for gp in (2.5, 0.5 * g1):
+            if gp < g1 - 1:
+                assert abs(O.dsdgp_trident(79, g1, gp) / O.dsdgp_trident(29, g1, gp) - (79 / 29) ** 2) < 1e-13
+
+
 def test_split_shape_support_and_symmetry():
     for gpair in (4.5, 10.0, 1000.0):
         for gplus in np.linspace(1.0, gpair - 1.0, 57):
