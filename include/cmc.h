@@ -244,6 +244,30 @@ cmc_status cmc_collide_step(cmc_tables t, const cmc_cells* cells,
 /* Scratch bytes cmc_collide_step needs for n_cells with this schedule. */
 size_t cmc_step_workspace_bytes(int64_t n_cells, int32_t schedule);
 
+/* ------------------------------------------------------------------ */
+/* For callers that cannot allocate device memory (code under HIP graph */
+/* capture, tight serving loops, harnesses that forbid hipMalloc): the  */
+/* step of cmc_collide_step with no workspace argument.  Its scratch is */
+/* a file-scope device array of the library, one per GPU it runs on,    */
+/* sized for cmc_noalloc_max_cells() cells (16384, about 10 MB) and     */
+/* held until the process ends.  Every call on a GPU shares that GPU's  */
+/* array, which keeps the last call's contents (each step clears what   */
+/* it needs before use): calls that overlap on one GPU race.  The call  */
+/* allocates nothing; an automatic schedule never times team shapes     */
+/* here (it takes the shape an earlier cmc_collide_step chose for the   */
+/* same launch shape, else workgroup teams).  Results are those of      */
+/* cmc_collide_step.  Errors: as cmc_collide_step, and CMC_ERANGE for   */
+/* more cells than the array holds.                                      */
+/* ------------------------------------------------------------------ */
+cmc_status cmc_collide_step_noalloc(cmc_tables t, const cmc_cells* cells,
+                                    cmc_species* electrons, cmc_species* photons,
+                                    const cmc_species* ions,
+                                    cmc_species* new_el, cmc_species* new_po,
+                                    const cmc_step_params* params, cmc_tallies* tallies,
+                                    void* stream);
+
+/* Cells cmc_collide_step_noalloc's static workspace holds. */
+size_t cmc_noalloc_max_cells(void);
 
 /* Schedules (every schedule gives the same decisions and products):
  *  CMC_SCHED_CELL   one workgroup per cell tests the pairs in order (the

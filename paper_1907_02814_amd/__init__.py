@@ -34,7 +34,8 @@ TABLE_NAMES = ["sigR", "skR", "cdfR", "sigU", "skU", "cdfU", "sigN", "skN", "cdf
                "sigB", "cdfB", "cdfT", "cdfS"]
 EXPORTS = ["cmc_last_error", "cmc_build_tables", "cmc_tables_free", "cmc_tables_size",
            "cmc_tables_export", "cmc_pair_cells", "cmc_collide_step", "cmc_step_workspace_bytes",
-           "cmc_expected_yield", "cmc_expected_yield_backward"]
+           "cmc_expected_yield", "cmc_expected_yield_backward", "cmc_collide_step_noalloc",
+           "cmc_noalloc_max_cells"]
 
 _vp = C.c_void_p
 _i64 = C.c_int64
@@ -82,12 +83,18 @@ def _load():
                                    C.POINTER(_StepParams), C.POINTER(_Tallies), _vp, C.c_size_t, _vp]
     L.cmc_step_workspace_bytes.argtypes = [_i64, C.c_int32]
     L.cmc_step_workspace_bytes.restype = C.c_size_t
+    L.cmc_collide_step_noalloc.argtypes = [_vp, C.POINTER(_Cells), C.POINTER(_Species), C.POINTER(_Species),
+                                           C.POINTER(_Species), C.POINTER(_Species), C.POINTER(_Species),
+                                           C.POINTER(_StepParams), C.POINTER(_Tallies), _vp]
+    L.cmc_noalloc_max_cells.argtypes = []
+    L.cmc_noalloc_max_cells.restype = C.c_size_t
     L.cmc_expected_yield.argtypes = ([_vp, _i64] + [_vp] * 4 + [_i64] + [_vp] * 4
                                      + [C.c_double, C.c_int32, _vp, _vp, _vp, _vp])
     L.cmc_expected_yield_backward.argtypes = ([_vp, _i64] + [_vp] * 4 + [_i64] + [_vp] * 4
                                               + [C.c_double, C.c_int32] + [_vp] * 8 + [_vp, _vp])
     for name in ("cmc_build_tables", "cmc_tables_free", "cmc_tables_export", "cmc_pair_cells",
-                 "cmc_collide_step", "cmc_expected_yield", "cmc_expected_yield_backward"):
+                 "cmc_collide_step", "cmc_expected_yield", "cmc_expected_yield_backward",
+                 "cmc_collide_step_noalloc"):
         getattr(L, name).restype = C.c_int
     return L
 
@@ -297,12 +304,21 @@ class StepState:
         torch.cuda.current_stream().wait_stream(side)
         return g, counter
 
-    def step(self, step: int, stream=None, events=None):
+    def step(self, step: int, stream=None, events=None, noalloc=False):
         """One step; `events` = optional pair of raw hipEvent_t handles
-        recorded around the pair-test kernels."""
+        recorded around the pair-test kernels.  noalloc: through
+        cmc_collide_step_noalloc (the library's static workspace) instead of
+        this state's workspace."""
         self.params.step = int(step)
         self.params.pass_events[0] = events[0] if events else None
         self.params.pass_events[1] = events[1] if events else None
+        if noalloc:
+            _check(get_lib().cmc_collide_step_noalloc(self.tables.handle, C.byref(self.cells), C.byref(self.sp[0]),
+                                                      C.byref(self.sp[1]), C.byref(self.sp[2]), C.byref(self.sp[3]),
+                                                      C.byref(self.sp[4]), C.byref(self.params), C.byref(self.tal),
+                                                      _stream(stream)),
+                   "cmc_collide_step_noalloc")
+            return
         _check(get_lib().cmc_collide_step(self.tables.handle, C.byref(self.cells), C.byref(self.sp[0]),
                                     C.byref(self.sp[1]), C.byref(self.sp[2]), C.byref(self.sp[3]),
                                     C.byref(self.sp[4]), C.byref(self.params), C.byref(self.tal),

@@ -2857,6 +2857,61 @@ extern "C" cmc_status cmc_collide_step(cmc_tables t, const cmc_cells* cells, cmc
                              workspace, workspace_bytes, stream, true);
 }
 
+// ------------------------------------------------------------------ no-allocation entry point
+// The workspace of cmc_collide_step_noalloc, for callers that cannot
+// allocate: a file-scope device array, one copy on every GPU the library
+// runs on, held until the process ends.  In host code `scratch` names a
+// host-side stand-in, not device memory: the device address of each GPU's
+// copy is taken once per device (hipGetSymbolAddress, with that device
+// current) and only that address reaches the kernels.
+constexpr int64_t kNoallocCells = 16384;
+constexpr size_t kNoallocBytes = work_bytes(kNoallocCells);
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+static std::mutex g_scratch_mu;
+static std::map<int, void*> g_scratch_ptr;   // device -> address of its `scratch`
+
+static cmc_status scratch_of_current_device(void** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        set_error("cmc_collide_step_noalloc: hipGetDevice failed");
+        return CMC_EDEVICE;
+    }
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it == g_scratch_ptr.end()) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr) {
+            set_error("cmc_collide_step_noalloc: hipGetSymbolAddress failed on device %d: %s", dev,
+                      hipGetErrorString(e));
+            return CMC_EDEVICE;
+        }
+        it = g_scratch_ptr.emplace(dev, p).first;
+    }
+    *out = it->second;
+    return CMC_OK;
+}
+
+extern "C" size_t cmc_noalloc_max_cells(void) { return (size_t)kNoallocCells; }
+
+extern "C" cmc_status cmc_collide_step_noalloc(cmc_tables t, const cmc_cells* cells, cmc_species* electrons,
+                                               cmc_species* photons, const cmc_species* ions,
+                                               cmc_species* new_el, cmc_species* new_po,
+                                               const cmc_step_params* P, cmc_tallies* tal, void* stream) {
+    CMC_REQUIRE(cells && P, CMC_EINVAL, "cmc_collide_step_noalloc: NULL argument");
+    CMC_REQUIRE(cells->n_cells <= kNoallocCells, CMC_ERANGE,
+                "cmc_collide_step_noalloc: %lld cells, above the %lld its static workspace holds",
+                (long long)cells->n_cells, (long long)kNoallocCells);
+    void* ws = nullptr;
+    if (cells->n_cells > 0 && P->schedule != CMC_SCHED_CELL) {
+        const cmc_status s = scratch_of_current_device(&ws);
+        if (s != CMC_OK) return s;
+    }
+    return collide_step_impl("cmc_collide_step_noalloc", t, cells, electrons, photons, ions, new_el, new_po, P, tal,
+                             ws, kNoallocBytes, stream, false);
+}
+
 extern "C" cmc_status cmc_pair_cells(int64_t n_cells, const int64_t* cell_id, const int64_t* a_off, const int32_t* a_cnt,
                                      const int64_t* b_off, const int32_t* b_cnt, const double* wa,
                                      const double* wb, uint64_t seed, uint64_t step, uint32_t pass,

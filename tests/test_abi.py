@@ -61,7 +61,15 @@ def test_host_argument_errors_without_gpu():
     assert L.cmc_expected_yield(t, -1, *([None] * 4), 0, *([None] * 4), 1e-16, 0, None, None, None, None) == 1
     assert L.cmc_tables_size(None, 0) == -1
     assert L.cmc_tables_free(None) == 0
-
+    # the no-allocation step: its static workspace bounds the cells, checked
+    # before any device call
+    assert L.cmc_noalloc_max_cells() == 16384
+    big = cmc._Cells(16385, None, None, None, None)
+    prm = cmc._StepParams(1e-16, 1, 0, 1, 0, 0, 1, 1e-6)
+    assert L.cmc_collide_step_noalloc(None, C.byref(big), None, None, None, None, None, C.byref(prm), None,
+                                      None) == 2
+    assert b"16384" in L.cmc_last_error()
+    assert L.cmc_collide_step_noalloc(None, None, None, None, None, None, None, None, None, None) == 1
 
 
 def test_binding_rejects_wrong_element_types():
