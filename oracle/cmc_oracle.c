@@ -20,6 +20,10 @@
  * tables of pair production are pinned against quadrature of the
  * differential cross sections in another variable and rule, and their
  * samplers by Kolmogorov-Smirnov tests against the exact distributions.
+ * The screening functions of the two-exponential potential (quadrature of
+ * eq:defphi1, eq:defphi2) are pinned by the printed one-exponential forms,
+ * by eq:ITFD as delta -> 0, and by a partial-fraction closed form with a
+ * dilogarithm for any two exponentials.
  * The Trident formulas of Sec. II.D (Gryaznykh's fit, Bhabha's two limits
  * and their interpolation, the split shape) have no value printed in the
  * paper: their relativistic form is pinned by Racah's high-energy total,
@@ -264,6 +268,100 @@ double or_fc(double Z)
     for (int n = 0; n < 4; n++) { s += p * zm1[n]; p *= -a2; }
     return a2 * s;
 }
+
+/* ------------------------------------------------------------------ */
+/* Screening functions of the two-exponential potential eq:V_TFD       */
+/* (Sec. II.B.2; the comparison curves of Figs. 5, 7 and 8):           */
+/* eq:defphi1 and eq:defphi2 with the form factor of eq:defF for       */
+/*   V = (q_TF/r) exp(-r/L_TF) + (q_D/r) exp(-r/L_D),                  */
+/*   1 - F_e(u) = etf (Ltf u)^2/(1 + (Ltf u)^2)                        */
+/*              + ed (Ld u)^2/(1 + (Ld u)^2),                          */
+/* etf = q_TF/q, ed = q_D/q, lengths in units of r_C.  Computed by      */
+/* quadrature of the definitions, in t = ln u over [ln delta, 0]:      */
+/* panels no wider than TFD_PANEL in t, split at the form factor's     */
+/* scales ln(1/Ltf) and ln(1/Ld), each with TFD_NGL-point              */
+/* Gauss-Legendre.  The integrands are analytic in t within a strip of */
+/* half-width pi/2, so the rule converges geometrically.               */
+/* ------------------------------------------------------------------ */
+#define TFD_NGL 16
+#define TFD_PANEL 0.25
+
+static double one_minus_F(double u, double etf, double ed, double Ltf, double Ld)
+{
+    double a = Ltf * u, v = etf * a * a / (1.0 + a * a);
+    if (ed > 0.0) {
+        double b = Ld * u;
+        v += ed * b * b / (1.0 + b * b);
+    }
+    return v;
+}
+
+/* eq:defphi1 and eq:defphi2 integrands per unit t = ln u (du = u dt),
+ * with r = u / delta: (u - delta)^2/u^2 G^2 and
+ * [1 - 6 ln(r)/r^2 + 3/r^2 - 4/r^3] G^2. */
+static void tfd_panel(double t0, double t1, double d, double etf, double ed, double Ltf, double Ld,
+                      double* s1, double* s2)
+{
+    static double X[TFD_NGL], Wt[TFD_NGL];
+    static int done = 0;
+    if (!done) { or_gauss_legendre(TFD_NGL, X, Wt); done = 1; }
+    double h = 0.5 * (t1 - t0), m = 0.5 * (t1 + t0);
+    for (int i = 0; i < TFD_NGL; i++) {
+        double t = m + h * X[i], u = exp(t), r = u / d;
+        double G = one_minus_F(u, etf, ed, Ltf, Ld), G2 = G * G;
+        double ir = 1.0 / r;
+        double k1 = (1.0 - ir) * (1.0 - ir);
+        double k2 = 1.0 - 6.0 * log(r) * ir * ir + 3.0 * ir * ir - 4.0 * ir * ir * ir;
+        *s1 += h * Wt[i] * k1 * G2;
+        *s2 += h * Wt[i] * k2 * G2;
+    }
+}
+
+void or_I12_tfd(double d, double etf, double ed, double Ltf, double Ld, double* I1, double* I2)
+{
+    double s1 = 0.0, s2 = 0.0;
+    double lo = log(d);
+    double cut[4];
+    int nc = 0;
+    cut[nc++] = lo;
+    double c1 = -log(Ltf), c2 = ed > 0.0 ? -log(Ld) : 0.0;
+    if (c1 > c2) { double tmp = c1; c1 = c2; c2 = tmp; }
+    if (c1 > lo && c1 < 0.0) cut[nc++] = c1;
+    if (c2 > lo && c2 < 0.0 && c2 > cut[nc - 1]) cut[nc++] = c2;
+    cut[nc++] = 0.0;
+    for (int j = 0; j + 1 < nc; j++) {
+        double a = cut[j], b = cut[j + 1];
+        int np = (int)ceil((b - a) / TFD_PANEL);
+        if (np < 1) np = 1;
+        double w = (b - a) / np;
+        for (int p = 0; p < np; p++) {
+            double t0 = a + p * w, t1 = (p + 1 == np) ? b : a + (p + 1) * w;
+            tfd_panel(t0, t1, d, etf, ed, Ltf, Ld, &s1, &s2);
+        }
+    }
+    *I1 = s1;
+    *I2 = s2;
+}
+
+/* eq:csre / eq:csur and eq:dsdkbh with the screening functions of the
+ * two-exponential potential (the numerically computed TFD forms). */
+double or_dsdk_rel_tfd(double Z, double g1, double k, double etf, double ed, double Ltf, double Ld, int coulomb)
+{
+    double g2 = g1 - k, d = k / (2.0 * g1 * g2), r = g2 / g1, I1, I2;
+    double fc = coulomb ? or_fc(Z) : 0.0;
+    or_I12_tfd(d, etf, ed, Ltf, Ld, &I1, &I2);
+    return 4.0 * Z * Z * RE * RE * ALPHA / k
+         * ((1.0 + r * r) * (I1 + 1.0 - fc) - (2.0 / 3.0) * r * (I2 + 5.0 / 6.0 - fc));
+}
+
+double or_dsdgp_bh_tfd(double Z, double k, double gp, double etf, double ed, double Ltf, double Ld)
+{
+    double gm = k - gp, d = k / (2.0 * gp * gm), I1, I2;
+    or_I12_tfd(d, etf, ed, Ltf, Ld, &I1, &I2);
+    return 4.0 * Z * Z * RE * RE * ALPHA / (k * k * k)
+         * ((gp * gp + gm * gm) * (I1 + 1.0) + (2.0 / 3.0) * gp * gm * (I2 + 5.0 / 6.0));
+}
+
 
 /* ------------------------------------------------------------------ */
 /* Bremsstrahlung differential cross sections (ion rest frame)        */

@@ -80,6 +80,9 @@ double or_lambert_w0(double z);
 double or_fc(double Z);
 void   or_I12(double delta, double L, double* I1, double* I2);
 double or_I_tfd(double etf, double ed, double Ltf, double Ld);
+void   or_I12_tfd(double delta, double etf, double ed, double Ltf, double Ld, double* I1, double* I2);
+double or_dsdk_rel_tfd(double Z, double g1, double k, double etf, double ed, double Ltf, double Ld, int coulomb);
+double or_dsdgp_bh_tfd(double Z, double k, double gp, double etf, double ed, double Ltf, double Ld);
 double or_L_reduced(double a);
 void   or_screening(double Z, double Zs, double ni, double T, double out[8]);
 double or_dsdk_nr(double Z, double g1, double k, double etd, double Ltf, double Ld, int elwert);

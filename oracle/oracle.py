@@ -62,6 +62,9 @@ def lib():
         L.or_fc.argtypes = [d]; L.or_fc.restype = d
         L.or_I12.argtypes = [d, d, _dp, _dp]
         L.or_I_tfd.argtypes = [d, d, d, d]; L.or_I_tfd.restype = d
+        L.or_I12_tfd.argtypes = [d, d, d, d, d, _dp, _dp]
+        L.or_dsdk_rel_tfd.argtypes = [d, d, d, d, d, d, d, C.c_int]; L.or_dsdk_rel_tfd.restype = d
+        L.or_dsdgp_bh_tfd.argtypes = [d, d, d, d, d, d, d]; L.or_dsdgp_bh_tfd.restype = d
         L.or_L_reduced.argtypes = [d]; L.or_L_reduced.restype = d
         L.or_screening.argtypes = [d, d, d, d, _dp]
         L.or_dsdk_nr.argtypes = [d, d, d, d, d, d, C.c_int]; L.or_dsdk_nr.restype = d
@@ -126,6 +129,23 @@ def I12(delta, L):
 
 def I_tfd(etf, ed, Ltf, Ld):
     return lib().or_I_tfd(float(etf), float(ed), float(Ltf), float(Ld))
+
+
+def I12_tfd(delta, etf, ed, Ltf, Ld):
+    """eq:defphi1, eq:defphi2 for the two-exponential potential eq:V_TFD
+    (quadrature of the definitions)."""
+    a = C.c_double(); b = C.c_double()
+    lib().or_I12_tfd(float(delta), float(etf), float(ed), float(Ltf), float(Ld), C.byref(a), C.byref(b))
+    return a.value, b.value
+
+
+def dsdk_rel_tfd(Z, g1, k, etf, ed, Ltf, Ld, coulomb=False):
+    return lib().or_dsdk_rel_tfd(float(Z), float(g1), float(k), float(etf), float(ed), float(Ltf), float(Ld),
+                                 int(coulomb))
+
+
+def dsdgp_bh_tfd(Z, k, gp, etf, ed, Ltf, Ld):
+    return lib().or_dsdgp_bh_tfd(float(Z), float(k), float(gp), float(etf), float(ed), float(Ltf), float(Ld))
 
 
 def L_reduced(a):
