@@ -109,13 +109,40 @@ def make_workload(name, W):
     return getattr(W, name)().to_torch("cuda:0")
 
 
-def run_gpu(make, precision, steps, warmup, schedule, seed=1):
+def count_evals(make, precision, steps, warmup, schedule, seed=1):
+    """Pair evaluations and events of steps warmup .. warmup + K - 1, run
+    eagerly on a fresh copy of the workload with a tally row per step.  A
+    step's results do not depend on the launch shape or on graph replay, so
+    these are the counts of the graph-replayed steps of the same numbers."""
+    import torch
+    import paper_1907_02814_amd as cmc
+    g = make()
+    tab = cmc.build_tables(g.Z)
+    st = cmc.StepState(tab, g.cells, g.electrons, g.photons, g.ions, g.new_el, g.new_po, dt=g.dt,
+                       seed=seed, processes=g.processes, precision=precision, schedule=schedule)
+    n = g.cells["Zstar"].numel()
+    rows = torch.zeros((steps, n, len(cmc.I_NAMES)), dtype=torch.int64, device="cuda:0")
+    for s in range(warmup):
+        st.step(s)
+    for i in range(steps):
+        st.set_tallies(ti=rows[i])
+        st.step(warmup + i)
+    torch.cuda.synchronize()
+    evals = int(rows[:, :, 0:3].sum().item())
+    events = rows[:, :, 3:6].sum((0, 1)).tolist()
+    del st, g, rows
+    torch.cuda.empty_cache()
+    return evals, events
+
+
+def run_gpu(make, precision, steps, warmup, schedule, seed=1, graph=False):
     """K timed steps of a fresh copy of the workload (make() builds it in
     device memory), then K more whose pair-test launches stamp HIP events
     (the kernel durations).  Each timed step writes its integer tallies to
     a row of its own (the pass kernels count the pairs they test), so the
     pair evaluations of the timed steps are summed afterwards, outside the
-    timed region."""
+    timed region.  graph: the timed steps are replays of one captured step
+    (its tallies in one buffer; the counts come from count_evals)."""
     import torch
     import paper_1907_02814_amd as cmc
     g = make()
@@ -131,16 +158,28 @@ def run_gpu(make, precision, steps, warmup, schedule, seed=1):
         st.step(s, stream)
     torch.cuda.synchronize()
     # the K timed steps, as a user runs them
-    t0 = time.perf_counter()
-    for i in range(steps):
-        st.set_tallies(ti=rows[i])
-        st.step(warmup + i, stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    st.set_tallies(ti=None)
-    evals = int(rows[:, :, 0:3].sum().item())
-    events = rows[:, :, 3:6].sum((0, 1)).tolist()
-    del rows
+    if graph:
+        gr, counter = st.graph(warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            gr.replay()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        st.use_counter(None)
+        del gr, counter, rows
+        evals, events = None, None
+    else:
+        t0 = time.perf_counter()
+        for i in range(steps):
+            st.set_tallies(ti=rows[i])
+            st.step(warmup + i, stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        st.set_tallies(ti=None)
+        evals = int(rows[:, :, 0:3].sum().item())
+        events = rows[:, :, 3:6].sum((0, 1)).tolist()
+        del rows
     # K more steps whose pair-test launches stamp HIP events at their start
     # and end (on their stream): the kernel durations.  These steps are kept
     # apart from the ones whose wall time gives the throughput.
@@ -160,6 +199,8 @@ def run_gpu(make, precision, steps, warmup, schedule, seed=1):
     step_b = alg + g.cells["Zstar"].numel() * (24 + 12 * 8 + 10 * 8)
     del st, g
     torch.cuda.empty_cache()
+    if graph:
+        evals, events = count_evals(make, precision, steps, warmup, schedule, seed)
     return {"wall_s": wall, "wall_events_s": wall_ev, "pass_ms": pass_ms, "evals": evals, "status": status,
             "events": events, "alg_bytes": alg, "step_bytes": step_b}
 
@@ -331,6 +372,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 plain comparison")
     ap.add_argument("--no-yield", action="store_true", help="skip the expected-yield measurement")
+    ap.add_argument("--graph", action="store_true",
+                    help="time replays of a captured step (default for cfg3, the batched form)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device copy of known size (counter calibration)")
     a = ap.parse_args()
@@ -360,9 +403,10 @@ def main():
     else:
         host_wl = getattr(W, a.workload)()
         what = f"all {host_wl.n_cells} cells of the same workload"
-    fp32 = run_gpu(make, cmc.FP32, a.steps, a.warmup, sched)
+    graph = a.graph or a.workload == "cfg3"
+    fp32 = run_gpu(make, cmc.FP32, a.steps, a.warmup, sched, graph=graph)
     print(f"[bench] fp32 done: {fp32['wall_s'] * 1e3 / a.steps:.3f} ms/step", file=sys.stderr, flush=True)
-    fp64 = None if a.no_fp64 else run_gpu(make, cmc.FP64, a.steps, a.warmup, sched)
+    fp64 = None if a.no_fp64 else run_gpu(make, cmc.FP64, a.steps, a.warmup, sched, graph=graph)
     if fp64:
         print(f"[bench] fp64 done: {fp64['wall_s'] * 1e3 / a.steps:.3f} ms/step", file=sys.stderr, flush=True)
     kavg = float(np.mean(fp32["pass_ms"]))
@@ -379,7 +423,7 @@ def main():
         "vs_baseline": None, "dtype": "fp32 lookups + fp64 probability/tallies",
         "data": "synthetic",
         "config": {"workload": f"{a.workload}: {WORKLOADS[a.workload]}", "cells": int(host_wl.n_cells if a.workload != "cfg5" else 131072),
-                   "pairs_per_step": fp32["evals"] // a.steps, "schedule": a.schedule,
+                   "pairs_per_step": fp32["evals"] // a.steps, "schedule": a.schedule, "graph_replay": graph,
                    "parallelism": "single GPU, cells"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

@@ -1336,9 +1336,609 @@ __device__ __forceinline__ void push_cand(const Work& W, int64_t c, uint64_t rec
     else mark_slow(W, c);
 }
 
+// LDS of a team beside its dynamic region: reduction scratch and the open
+// pairs found without an order
+struct PassLds {
+    double* red4;
+    uint32_t* redu;
+    int* redi;
+    uint32_t* opn;      // open pairs found without the order
+    uint32_t* opk;      // their particles' keys
+    uint32_t* opj;      // their pair indices
+    int* nopen;
+};
+
+// What the electron-ion pass of a cell hands to the photon-ion pass of the
+// same cell when one team runs both: the weight checks passed and whether
+// the ions share one weight (flags), and the ions' weight sum.
+struct PassCarry {
+    int32_t flags;
+    double ionsum;
+};
+
+// The pass kPass over cell c by one team (see k_pass).  kFused: the same
+// team has just run the electron-ion pass of this cell, whose results are
+// in carry; otherwise the photon-ion pass reads them from the workspace.
+template <typename R, int kT, int kPass, bool kMov, bool kFused>
+__device__ __forceinline__ void pass_cell(const StepArgs& A, const TabView<R>& T, const Work& W, int cap, int filter,
+                                          int fcap, int slow_cap, int64_t c, const TeamMem M, const Rng rng,
+                                          double rej, int t, const PassLds L, PassCarry& carry) {
+    R* slice = reinterpret_cast<R*>(M.slice);
+    // the cell's parameters in one round of loads: its state, the
+    // offsets and live counts of the three species, its global index
+    const uint32_t cell = cell_word(A.cid, c);
+    const int32_t cstat = W.cs[c].status;
+    const int32_t cflags = kPass == 1 ? (kFused ? carry.flags : W.flags[c]) : 0;
+    const CellTab<R> ct_c = pick<R>(W.cs[c]);
+    const int64_t eo0 = A.el.off[c], eo1 = A.el.off[c + 1], go0 = A.ph.off[c], go1 = A.ph.off[c + 1];
+    const int64_t io0 = A.io.off[c], io1 = A.io.off[c + 1];
+    const int ecn = A.el.count ? A.el.count[c] : 0x7FFFFFFF, gcn = A.ph.count ? A.ph.count[c] : 0x7FFFFFFF;
+    const int icn = A.io.count ? A.io.count[c] : 0x7FFFFFFF;
+    if (cstat) return;                                // invalid cell (flagged by k_cell_state)
+    const int Ne = max(0, min(ecn, (int)(eo1 - eo0))), Ng = max(0, min(gcn, (int)(go1 - go0)));
+    const int Ni = max(0, min(icn, (int)(io1 - io0)));
+    // size classes of the hybrid schedule: filter 1 takes the cells up
+    // to fcap particles per species, filter 2 the larger ones
+    const int mx = max(Ne, max(Ng, Ni));
+    if ((filter == 1 && mx > fcap) || (filter == 2 && mx <= fcap)) return;
+    if (Ne > A.maxn || Ng > A.maxn || Ni > A.maxn) {
+        if (t == 0) atomicOr(A.status, CMC_ST_TOO_LARGE);
+        return;
+    }
+    const bool ei = (A.proc & (CMC_BREMS | CMC_TRIDENT)) && Ne > 0 && Ni > 0;
+    const bool gi = (A.proc & CMC_BH) && Ng > 0 && Ni > 0;
+    // cells beyond the largest LDS of the step's pass launches go to the
+    // sequential kernel whole
+    if ((ei && (Ne > slow_cap || Ni > slow_cap)) || (gi && (Ng > slow_cap || Ni > slow_cap))) {
+        if (t == 0) mark_slow(W, c);
+        return;
+    }
+    // every order this pass might need fits this launch's LDS
+    const bool fits = kPass == 0 ? (Ne <= cap && Ni <= cap) : (Ng <= cap && Ni <= cap);
+    const int64_t e0 = eo0, g0 = go0, i0 = io0;
+    const bool active = kPass == 0 ? ei : gi;
+    const int Nm = kPass == 0 ? Ne : Ng, No = kPass == 0 ? Ng : Ne;
+    const int64_t m0 = kPass == 0 ? e0 : g0;
+    const SpeciesDev& S = kPass == 0 ? A.el : A.ph;
+    const double* wm = S.w + m0;
+    const double* wo = kPass == 0 ? A.ph.w + g0 : A.el.w + e0;
+    const double* wion = A.io.w + i0;
+    const bool mobA = Nm >= Ni;
+    const int N = mobA ? Nm : Ni;
+    // ---- direct form: ions at rest, at most four mobile particles per
+    // thread.  The weights are summed (densities, the mobile particles'
+    // n_ab terms against the first ion's weight, the weight checks) in
+    // one reduction, beside the table slice; then every pair is tested
+    // in storage order of its mobile particle.  A cycled mobile species
+    // (N_m < N_i, K = N_i div N_m pairs per particle, e = N_i mod N_m of
+    // them one more) takes the e particles of smallest key as the order
+    // would, found by select_smallest; n_ab = fma(K, A, B), A the
+    // canonical sum of the terms and B that of the selected particles'.
+    // Should the ions not share one weight, the cell is done again below
+    // with both orders.
+    if constexpr (!kMov) {
+        if (active && fits && N <= 4 * kT) {
+            const bool cyc = !mobA;
+            const int K = N / Nm, e = N - K * Nm;
+            uint32_t* sel = reinterpret_cast<uint32_t*>(M.base + kSelBytes - 128);
+            {
+                const CellTab<R> ct = ct_c;
+                if (kPass == 0) {
+                    if (A.proc & CMC_BREMS)
+                        for (int i = t; i < kSliceBrems; i += kT) slice[i] = slice_node_brems<R>(T, ct, i);
+                } else {
+                    for (int i = t; i < kSliceBH; i += kT) slice[i] = slice_node_bh<R>(T, ct, i);
+                }
+            }
+            // the first pair's momenta are in flight during the reduction
+            double nx = 0.0, ny = 0.0, nz = 0.0;
+            if (t < Nm) { nx = S.px[m0 + t]; ny = S.py[m0 + t]; nz = S.pz[m0 + t]; }
+            const double w0 = wion[0];
+            int fl = 0;                 // 1 bad weight, 2 ions of unequal weight, 4 above the tables
+            double v4[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int q = t + kT * u;
+                const double wq = q < Nm ? wm[q] : 0.0, wi = q < Ni ? wion[q] : 0.0;
+                fl |= (!(wq >= 0.0) || !isfinite(wq) || !(wi >= 0.0) || !isfinite(wi)) ? 1 : 0;
+                fl |= (q < Ni && wi != w0) ? 2 : 0;
+                canon_add<kT>(v4[0], wq, u);
+                canon_add<kT>(v4[1], q < Nm ? (wq < w0 ? wq : w0) : 0.0, u);
+                canon_add<kT>(v4[2], wi, u);
+            }
+            v4[0] = canon_end<kT>(v4[0]);
+            v4[1] = canon_end<kT>(v4[1]);
+            v4[2] = canon_end<kT>(v4[2]);
+            {
+                int bad = 0;
+                v4[3] = canon_part<kT>(No, [&](int q) { const double w = wo[q]; bad |= !(w >= 0.0) || !isfinite(w); return w; });
+                fl |= bad ? 1 : 0;
+            }
+            if (t == 0) L.nopen[0] = 0;
+            team_reduce4_bits<kT>(v4, fl, L.red4, L.redi);   // its barriers also publish the slice
+            if (kT == 64) Team<kT>::sync();
+            if (kPass == 0 && !(fl & 1) && t == 0) {
+                W.ionsum[c] = v4[2];
+                atomicOr(&W.flags[c], kFlagWeightsOk | ((fl & 2) ? 0 : kFlagIonsSame));
+            }
+            if (kPass == 0 && !(fl & 1)) carry = PassCarry{kFlagWeightsOk | ((fl & 2) ? 0 : kFlagIonsSame), v4[2]};
+            bool chosen = true;
+            if (!(fl & 3) && cyc) {
+                // indices of the cycled case come from an opaque copy of the
+                // thread's index: formed here, not kept across cells in
+                // registers that the pairs need
+                int tt = t;
+                asm volatile("" : "+v"(tt));
+                if (e > 0)
+                    chosen = select_smallest<kT>(Nm, e, cell, kPass == 0 ? kTagKeyE : kTagKeyG, rng, M.base, sel, tt);
+                if (chosen) {
+                    double vb[4] = {0.0, 0.0, 0.0, 0.0};
+                    if (e > 0) {
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const int q = tt + kT * u;
+                            const bool sq = q < Nm && ((sel[q >> 5] >> (q & 31)) & 1u);
+                            const double wq = sq ? wm[q] : 0.0;
+                            canon_add<kT>(vb[0], sq ? (wq < w0 ? wq : w0) : 0.0, u);
+                        }
+                        vb[0] = canon_end<kT>(vb[0]);
+                        bool none = false;
+                        team_reduce4<kT>(vb, none, L.red4, L.redi);
+                    }
+                    v4[1] = fma((double)K, v4[1], vb[0]);   // one rounding, as in the ordered form
+                }
+            }
+            if (!(fl & 2) && chosen) {
+                if (fl & 1) {
+                    if (t == 0) atomicOr(A.status, CMC_ST_BAD_WEIGHT);
+                    return;
+                }
+                const double nab = v4[1];
+                int high = 0;
+                if (nab > 0.0) {
+                    const double coef = v4[0] * v4[2] / nab;
+                    const float kx = (float)(coef * A.dt * rej * 16777216.0);
+                    // workgroup teams: the first pairs of a thread's particles
+                    // q = t + 256 u share the draw of the upper bits of U1
+                    // (hi_group(q) = t, word u), drawn once per process
+                    const uint32_t tagA = kPass == 0 ? kTagHiBr : kTagHiBh;
+                    U4 hA{0u, 0u, 0u, 0u}, hT{0u, 0u, 0u, 0u};
+                    if constexpr (kT == 256) {
+                        if (kPass == 1 || (A.proc & CMC_BREMS)) hA = rng.draw(hi_group((uint32_t)t), cell, tagA);
+                        if (kPass == 0 && (A.proc & CMC_TRIDENT)) hT = rng.draw(hi_group((uint32_t)t), cell, kTagHiTr);
+                    }
+                    // the word of U1's upper bits for the pair keyed by x:
+                    // the shared one for a particle's first pair
+                    const auto word = [&](uint32_t x, bool first, uint32_t shared, uint32_t tag) {
+                        return kT == 256 && first ? shared : hi_word(rng.draw(hi_group(x), cell, tag), (x >> 8) & 3u);
+                    };
+                    // every particle's first pair, one at a time (the tests do
+                    // not overlap in registers), the next momenta in flight
+#pragma unroll 1
+                    for (int u = 0; u < 4; ++u) {
+                        const int q = t + kT * u;
+                        const double cx = nx, cy = ny, cz = nz;
+                        if (q + kT < Nm) { nx = S.px[m0 + q + kT]; ny = S.py[m0 + q + kT]; nz = S.pz[m0 + q + kT]; }
+                        // word u of the shared draws: the words move down one per pair
+                        const uint32_t wA = hA.x, wT = hT.x;
+                        hA = U4{hA.y, hA.z, hA.w, 0u};
+                        hT = U4{hT.y, hT.z, hT.w, 0u};
+                        if (q >= Nm) continue;
+                        uint32_t bits = 0;
+                        if (kPass == 0) {
+                            const Elec<R> el = electron_p<R>(cx, cy, cz);
+                            if (A.proc & CMC_BREMS) {
+                                bool hi;
+                                const R sig = brems_sig_slice<R>(T, slice, el.g, el.gm1, hi);
+                                high |= hi;
+                                if (sig > (R)0 && bound24(word((uint32_t)q, true, wA, kTagHiBr), kx * (float)sig * (float)el.vrel))
+                                    bits = 1u;
+                            }
+                            if ((A.proc & CMC_TRIDENT) && !bits) {
+                                const R sig = (R)phys::trident_sigma(T.Z, (double)el.g);
+                                if (sig > (R)0 && bound24(word((uint32_t)q, true, wT, kTagHiTr), kx * (float)sig * (float)el.vrel))
+                                    bits = 2u;
+                            }
+                        } else {
+                            bool hi;
+                            const R sig = bh_sig_slice<R>(T, slice, photon_k<R>(cx, cy, cz), hi);
+                            high |= hi;
+                            if (sig > (R)0 && bound24(word((uint32_t)q, true, wA, kTagHiBh), kx * (float)sig * (float)phys::kC))
+                                bits = 1u;
+                        }
+                        if (bits) {
+                            const int o = atomicAdd(&L.nopen[0], 1);
+                            if (o < kCandCap) L.opn[o] = (uint32_t)q | (bits << 16);
+                        }
+                    }
+                    // cycled mobile species: the further pairs k = 1 .. reps - 1 of
+                    // each particle (K - 1 for all, one more for the selected),
+                    // keyed by q + k N_m, the momenta read again
+                    if (cyc && (K > 1 || e > 0)) {
+                        int tt = t;
+                        asm volatile("" : "+v"(tt));
+#pragma unroll 1
+                        for (int u = 0; u < 4; ++u) {
+                            const int q = tt + kT * u;
+                            if (q >= Nm) continue;
+                            const int reps = K + ((e > 0 && ((sel[q >> 5] >> (q & 31)) & 1u)) ? 1 : 0);
+                            if (reps < 2) continue;
+                            const double cx = S.px[m0 + q], cy = S.py[m0 + q], cz = S.pz[m0 + q];
+                            for (int k = 1; k < reps; ++k) {
+                                const uint32_t x = (uint32_t)(q + k * Nm);
+                                uint32_t bits = 0;
+                                if (kPass == 0) {
+                                    const Elec<R> el = electron_p<R>(cx, cy, cz);
+                                    bool hi;
+                                    const R sb = (A.proc & CMC_BREMS) ? brems_sig_slice<R>(T, slice, el.g, el.gm1, hi) : (R)0;
+                                    if (sb > (R)0 && bound24(word(x, false, 0u, kTagHiBr), kx * (float)sb * (float)el.vrel))
+                                        bits = 1u;
+                                    const R st = (A.proc & CMC_TRIDENT) ? (R)phys::trident_sigma(T.Z, (double)el.g) : (R)0;
+                                    if (!bits && st > (R)0 && bound24(word(x, false, 0u, kTagHiTr), kx * (float)st * (float)el.vrel))
+                                        bits = 2u;
+                                } else {
+                                    bool hi;
+                                    const R sig = bh_sig_slice<R>(T, slice, photon_k<R>(cx, cy, cz), hi);
+                                    if (sig > (R)0 && bound24(word(x, false, 0u, kTagHiBh), kx * (float)sig * (float)phys::kC))
+                                        bits = 1u;
+                                }
+                                if (bits) {
+                                    const int o = atomicAdd(&L.nopen[0], 1);
+                                    if (o < kCandCap) L.opn[o] = (uint32_t)q | (bits << 16) | ((uint32_t)k << 20);
+                                }
+                            }
+                        }
+                    }
+                    Team<kT>::sync();
+                    const int n_open = L.nopen[0];
+                    if (n_open > kCandCap) {
+                        if (t == 0) mark_slow(W, c);
+                    } else if (n_open > 0) {
+                        // pair index of an open pair: its particle's rank plus k N_m
+                        rank_open<kT>(Nm, cell, kPass == 0 ? kTagKeyE : kTagKeyG, rng, L.opn, L.opk, L.opj, n_open);
+                        if (t < n_open) {
+                            const uint32_t o = L.opn[t];
+                            push_cand(W, c, ev_pack(kPass, (int)L.opj[t] + (int)(o >> 20) * Nm, (int)(o & 0xFFFFu), 0,
+                                                    (o >> 16) & 0xFu));
+                        }
+                    }
+                    if (t == 0) W.coef[c * 2 + kPass] = coef;
+                }
+                if (t == 0) {
+                    if (kPass == 0) {
+                        A.ti[c * CMC_NI + CMC_I_PAIRS_BR] = (nab > 0.0 && (A.proc & CMC_BREMS)) ? N : 0;
+                        A.ti[c * CMC_NI + CMC_I_PAIRS_TR] = (nab > 0.0 && (A.proc & CMC_TRIDENT)) ? N : 0;
+                        A.td[c * CMC_ND + CMC_D_NAB_EI] = nab;
+                    } else {
+                        A.ti[c * CMC_NI + CMC_I_PAIRS_BH] = nab > 0.0 ? N : 0;
+                        A.td[c * CMC_ND + CMC_D_NAB_GI] = nab;
+                    }
+                }
+                if (team_any<kT>(high != 0, L.redi) && t == 0) atomicOr(A.status, CMC_ST_GAMMA_HIGH);
+                Team<kT>::sync();   // LDS of this cell is free
+                return;
+            }
+            Team<kT>::sync();       // the slice is staged again below
+        }
+    }
+    // the weights of the cell are checked (non-negative, finite) as
+    // they are summed into the densities
+    int bad = 0;
+    const auto chk = [&bad](double v) { bad |= !(v >= 0.0) || !isfinite(v); return v; };
+    double v4[4];   // n_mobile, n_ab, n_ion, n_other
+    // When the cell's ions are at rest and share one weight, no decision
+    // and no product depends on which ion a pair gets (P_ej and n_ab see
+    // only that weight): the ion order is then not formed, and the open
+    // pairs name ion 0.
+    const double wi0 = Ni > 0 ? wion[0] : 0.0;
+    // after the electron-ion pass of this step (photon-ion pass): the ion
+    // sum, the ions' sameness and every weight check are known
+    const bool known = kPass == 1 && (cflags & kFlagWeightsOk);
+    bool same = true;
+    if (known) {
+        // the team reduction below adds the wavefronts' partials: the
+        // total enters through the first wavefront alone
+        v4[2] = (kT == 64 || threadIdx.x < 64) ? (kFused ? carry.ionsum : W.ionsum[c]) : 0.0;
+        same = (cflags & kFlagIonsSame) != 0;
+    } else {
+        v4[2] = canon_part<kT>(Ni, [&](int q) { const double w = wion[q]; same &= w == wi0; return chk(w); });
+    }
+    const bool uneq = team_any<kT>(!same, L.redi);
+    const bool ion_order = active && (kMov || uneq);
+    // When every mobile particle pairs once, the draws of a pair are
+    // keyed by its mobile particle: with interchangeable ions nothing
+    // then depends on the order, which is not formed; the few open pairs
+    // get their pair index (the rank of their particle) at the end.
+    const bool mob_order = active && (!mobA || ion_order);
+    // a cycled mobile species against interchangeable ions: its tests are
+    // walked by draw group (below)
+    const bool cyc_fast = active && !mobA && !ion_order;
+    if (active && !fits && ((ion_order && Ni > cap) || (mob_order && Nm > cap))) {
+        // an order larger than this launch's LDS: the large-LDS launch takes
+        // the pass (listed once per step, however often the launch runs)
+        const int32_t fb = kPass == 0 ? kFlagBig0 : kFlagBig1;
+        if (t == 0 && !(atomicOr(&W.flags[c], fb) & fb))
+            W.list_big[kPass][atomicAdd(&W.counters[kPass == 0 ? kCntBig0 : kCntBig1], 1)] = (int32_t)c;
+        return;
+    }
+    if (t == 0) L.nopen[0] = 0;
+    // when every mobile particle pairs once the pair loop walks them in
+    // storage order: its first momenta are loaded before the sort
+    double qx = 0.0, qy = 0.0, qz = 0.0;
+    if (active) {
+        if (mobA && t < N) { qx = S.px[m0 + t]; qy = S.py[m0 + t]; qz = S.pz[m0 + t]; }
+        const CellTab<R> ct = pick<R>(W.cs[c]);
+        if (kPass == 0) {
+            if (A.proc & CMC_BREMS)
+                for (int i = t; i < kSliceBrems; i += kT) slice[i] = slice_node_brems<R>(T, ct, i);
+        } else {
+            for (int i = t; i < kSliceBH; i += kT) slice[i] = slice_node_bh<R>(T, ct, i);
+        }
+        if (mob_order)
+            rank_order<kT>(Nm, cell, kPass == 0 ? kTagKeyE : kTagKeyG, rng, M.keys, M.tmp, M.hist, M.ordM, mobA, L.redu);
+        else
+            Team<kT>::sync();      // the slice and the open-pair count
+        if (ion_order)
+            rank_order<kT>(Ni, cell, kPass == 0 ? kTagKeyIE : kTagKeyIG, rng, M.keys, M.tmp, M.hist, M.ordI, false, L.redu);
+    }
+    const float rNm = 1.0f / (float)Nm, rNi = 1.0f / (float)Ni;
+    // the smaller species is cycled (j mod N_B); the other one is not
+    const auto ion_of = [&](int j) { return ion_order ? (int)M.ordI[Ni == N ? j : mod_small(j, Ni, rNi)] : 0; };
+    const auto w_ion = [&](int j) { return ion_order ? wion[ion_of(j)] : wi0; };
+    const auto mob_of = [&](int j) { return (int)M.ordM[Nm == N ? j : mod_small(j, Nm, rNm)]; };
+    // a cycled mobile species is walked in rank order: its first momenta
+    // are read once the order is formed
+    if (active && !mobA && !cyc_fast && t < N) { const int m = mob_of(t); qx = S.px[m0 + m]; qy = S.py[m0 + m]; qz = S.pz[m0 + m]; }
+    // the other weights, read once: the densities n = sum W, n_ab =
+    // sum_j min(W_a, W_b) and the weight check (when every mobile
+    // particle pairs once, its density and n_ab share the walk)
+    double cyc_b = 0.0;
+    int cyc_k = 0;
+    if (active && mobA) {
+        canon_part2<kT>(N, [&](int q, double& a, double& b) {
+            const double u = chk(wm[q]), v = ion_order ? w_ion((int)M.ordM[q]) : wi0;
+            a += u;
+            b += u < v ? u : v;
+        }, v4[0], v4[1]);
+    } else if (active && !ion_order) {
+        // a cycled mobile species with interchangeable ions: n_ab = K A + B
+        // as the direct form forms it (A over all the mobile particles' terms,
+        // B over those of the e particles of smallest key, ranks 0 .. e - 1)
+        uint32_t* selb = reinterpret_cast<uint32_t*>(M.hist);   // free once the order is formed
+        for (int i = t; i < (Nm + 31) / 32; i += kT) selb[i] = 0u;
+        Team<kT>::sync();
+        for (int r = t; r < N - (N / Nm) * Nm; r += kT) {
+            const int p = (int)M.ordM[r];
+            atomicOr(&selb[p >> 5], 1u << (p & 31));
+        }
+        Team<kT>::sync();
+        canon_part2<kT>(Nm, [&](int q, double& a, double& b) {
+            const double u = chk(wm[q]);
+            a += u;
+            b += u < wi0 ? u : wi0;
+        }, v4[0], v4[1]);
+        cyc_b = canon_part<kT>(Nm, [&](int q) {
+            const double u = wm[q];
+            return ((selb[q >> 5] >> (q & 31)) & 1u) ? (u < wi0 ? u : wi0) : 0.0;
+        });
+        cyc_k = N / Nm;
+    } else {
+        v4[0] = canon_part<kT>(Nm, [&](int q) { return chk(wm[q]); });
+        v4[1] = !active ? 0.0 : canon_part<kT>(N, [&](int j) {
+            const double u = wm[mob_of(j)], v = w_ion(j);
+            return u < v ? u : v;
+        });
+    }
+    v4[3] = known ? 0.0 : canon_part<kT>(No, [&](int q) { return chk(wo[q]); });
+    bool badw = bad != 0;
+    team_reduce4<kT>(v4, badw, L.red4, L.redi);
+    if (kPass == 0 && !badw && t == 0) {
+        W.ionsum[c] = v4[2];
+        atomicOr(&W.flags[c], kFlagWeightsOk | (uneq ? 0 : kFlagIonsSame));
+    }
+    if (kPass == 0 && !badw) carry = PassCarry{kFlagWeightsOk | (uneq ? 0 : kFlagIonsSame), v4[2]};
+    if (cyc_k > 0) {
+        double vb[4] = {cyc_b, 0.0, 0.0, 0.0};
+        bool none = false;
+        team_reduce4<kT>(vb, none, L.red4, L.redi);
+        v4[1] = fma((double)cyc_k, v4[1], vb[0]);   // one rounding, as in the direct form
+    }
+    if (badw) {
+        if (t == 0) atomicOr(A.status, CMC_ST_BAD_WEIGHT);
+        return;
+    }
+    if (!active) return;
+    const double nab = v4[1];
+    int high = 0;
+    if (nab > 0.0) {
+        const double coef = v4[0] * v4[2] / nab;
+        const float kx = (float)(coef * A.dt * rej * 16777216.0);
+        // the draw holding U1's upper bits serves the four pairs of its
+        // group (keys x, x + 256, x + 512, x + 768): the last one drawn is
+        // kept per process, so a workgroup thread walking its mobile
+        // particles in storage order (q = t + 256 u) draws once per four
+        uint32_t g_br = 0xFFFFFFFFu, g_tr = 0xFFFFFFFFu;
+        U4 h_br{0u, 0u, 0u, 0u}, h_tr{0u, 0u, 0u, 0u};
+        const auto hi_bits = [&](uint32_t x, uint32_t tag, uint32_t& gk, U4& h) {
+            const uint32_t gx = hi_group(x);
+            if (gx != gk) { h = rng.draw(gx, cell, tag); gk = gx; }
+            return hi_word(h, (x >> 8) & 3u);
+        };
+        if (cyc_fast) {
+            // N = N_ion pairs: particle m of the cycled species pairs K = N div
+            // N_m times and, if its rank is below e = N mod N_m, once more
+            // (Sec. III.A pairing).  All its tests share one cross section and
+            // flux: its bounds are formed once (in the arithmetic of the tests
+            // below the other forms make), and the tests are walked by draw
+            // group: the keys x = m + k N_m of a group ((x >> 10) << 8 |
+            // (x & 255) = g) are base(g) + 256 w, w = 0..3, and share the draw
+            // of U1's upper bits, word w.
+            // LDS of the team (n >= N_m entries each): the bounds in the key
+            // array and over the two order arrays (4 n bytes, written once
+            // the ranks are taken from the order), the ranks in the bucket
+            // particle array, the selection bitmap in the histogram
+            float* xb = reinterpret_cast<float*>(M.keys);   // first process's bound of m (< 0: none)
+            float* xt = reinterpret_cast<float*>(M.ordM);   // Trident's bound of m (over ordM, ordI)
+            uint16_t* rk = M.tmp;                           // rank of m
+            const uint32_t* selb = reinterpret_cast<const uint32_t*>(M.hist);
+            for (int r = t; r < Nm; r += kT) rk[M.ordM[r]] = (uint16_t)r;
+            Team<kT>::sync();
+            for (int m = t; m < Nm; m += kT) {
+                const double cx = S.px[m0 + m], cy = S.py[m0 + m], cz = S.pz[m0 + m];
+                float b1 = -1.0f, b2 = -1.0f;
+                if (kPass == 0) {
+                    const Elec<R> e = electron_p<R>(cx, cy, cz);
+                    if (A.proc & CMC_BREMS) {
+                        bool hi;
+                        const R sig = brems_sig_slice<R>(T, slice, e.g, e.gm1, hi);
+                        high |= hi;
+                        if (sig > (R)0) b1 = kx * (float)sig * (float)e.vrel;
+                    }
+                    if (A.proc & CMC_TRIDENT) {
+                        const R sig = (R)phys::trident_sigma(T.Z, (double)e.g);
+                        if (sig > (R)0) b2 = kx * (float)sig * (float)e.vrel;
+                    }
+                } else {
+                    bool hi;
+                    const R sig = bh_sig_slice<R>(T, slice, photon_k<R>(cx, cy, cz), hi);
+                    high |= hi;
+                    if (sig > (R)0) b1 = kx * (float)sig * (float)phys::kC;
+                }
+                xb[m] = b1;
+                xt[m] = b2;
+            }
+            Team<kT>::sync();
+            const int K = N / Nm, e = N - K * Nm;
+            const int X = K * Nm + (e > 0 ? Nm : 0);      // keys of every particle's last pair and below
+            const int G = ((X + 1023) >> 10) << 8;
+            for (int g = t; g < G; g += kT) {
+                const int base = ((g >> 8) << 10) | (g & 255);
+                if (base >= X) continue;
+                const U4 h = rng.draw((uint32_t)g, cell, kPass == 0 ? kTagHiBr : kTagHiBh);
+                U4 h2{0u, 0u, 0u, 0u};
+                bool h2_drawn = false;
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    const int x = base + 256 * w;
+                    if (x >= X) break;
+                    const int m = mod_small(x, Nm, rNm);
+                    const int k = __float2int_rn((float)(x - m) * rNm);
+                    if (!(k < K || ((selb[m >> 5] >> (m & 31)) & 1u))) continue;
+                    uint32_t bits = 0;
+                    if (bound24(hi_word(h, (uint32_t)w), xb[m])) {
+                        bits = 1u;
+                    } else if (kPass == 0 && xt[m] >= 0.0f) {
+                        if (!h2_drawn) { h2 = rng.draw((uint32_t)g, cell, kTagHiTr); h2_drawn = true; }
+                        if (bound24(hi_word(h2, (uint32_t)w), xt[m])) bits = 2u;
+                    }
+                    if (bits) {
+                        const int o = atomicAdd(&L.nopen[0], 1);
+                        if (o < kCandCap) L.opn[o] = (uint32_t)m | (bits << 14) | ((uint32_t)k << 16);
+                    }
+                }
+            }
+            Team<kT>::sync();
+            const int n_open = L.nopen[0];
+            if (n_open > kCandCap) {
+                if (t == 0) mark_slow(W, c);
+            } else if (t < n_open) {
+                // pair index: the particle's rank plus k N_m
+                const uint32_t o = L.opn[t];
+                const int m = (int)(o & 0x3FFFu), k = (int)(o >> 16);
+                push_cand(W, c, ev_pack(kPass, (int)rk[m] + k * Nm, m, 0, (o >> 14) & 3u));
+            }
+        } else {
+        for (int q = t; q < N; q += kT) {
+            const int j = mobA ? (mob_order ? (int)M.ordM[q] : 0) : q;
+            const int jm = mobA ? 0 : (Nm == N ? j : mod_small(j, Nm, rNm));   // rank of the cycled particle
+            const int mi = mobA ? q : (int)M.ordM[jm];
+            // counter of the pair's draws: its mobile particle and repetition
+            const uint32_t dk = (uint32_t)(mobA ? mi : mi + (j - jm));
+            // this pair's momenta; the next pair's are read meanwhile
+            const double cx = qx, cy = qy, cz = qz;
+            if (q + kT < N) {
+                const int mn = mobA ? q + kT : mob_of(q + kT);
+                qx = S.px[m0 + mn]; qy = S.py[m0 + mn]; qz = S.pz[m0 + mn];
+            }
+            uint32_t bits = 0;
+            Ion b{0.0, 0.0, 0.0, 1.0, false};
+            if constexpr (kMov) b = ion_at(A.io, i0 + ion_of(j));
+            if (kPass == 0) {
+                Elec<R> e;
+                if constexpr (kMov) e = electron_moving<R>(electron_frame(b, cx, cy, cz), b);
+                else e = electron_p<R>(cx, cy, cz);
+                if (A.proc & CMC_BREMS) {
+                    bool hi;
+                    const R sig = brems_sig_slice<R>(T, slice, e.g, e.gm1, hi);
+                    high |= hi;
+                    if (sig > (R)0 && bound24(hi_bits(dk, kTagHiBr, g_br, h_br), kx * (float)sig * (float)e.vrel))
+                        bits = 1u;
+                }
+                if ((A.proc & CMC_TRIDENT) && !bits) {
+                    const R sig = (R)phys::trident_sigma(T.Z, (double)e.g);
+                    if (sig > (R)0 && bound24(hi_bits(dk, kTagHiTr, g_tr, h_tr), kx * (float)sig * (float)e.vrel))
+                        bits = 2u;
+                }
+            } else {
+                R k;
+                double flux = phys::kC;
+                if constexpr (kMov) {
+                    const Frame f = photon_frame(b, cx, cy, cz);
+                    k = (R)f.g;
+                    flux = photon_flux(f, b);
+                } else {
+                    k = photon_k<R>(cx, cy, cz);
+                }
+                bool hi;
+                const R sig = bh_sig_slice<R>(T, slice, k, hi);
+                high |= hi;
+                if (sig > (R)0 && bound24(hi_bits(dk, kTagHiBh, g_br, h_br), kx * (float)sig * (float)flux))
+                    bits = 1u;
+            }
+            if (bits) {
+                if (mob_order) {
+                    push_cand(W, c, ev_pack(kPass, j, mi, ion_of(j), bits));
+                } else {
+                    const int k = atomicAdd(&L.nopen[0], 1);
+                    if (k < kCandCap) L.opn[k] = (uint32_t)mi | (bits << 16);
+                }
+            }
+        }
+        if (!mob_order) {
+            Team<kT>::sync();
+            const int n_open = L.nopen[0];
+            if (n_open > kCandCap) {
+                if (t == 0) mark_slow(W, c);
+            } else if (n_open > 0) {
+                rank_open<kT>(Nm, cell, kPass == 0 ? kTagKeyE : kTagKeyG, rng, L.opn, L.opk, L.opj, n_open);
+                if (t < n_open)
+                    push_cand(W, c, ev_pack(kPass, (int)L.opj[t], (int)(L.opn[t] & 0xFFFFu), 0, L.opn[t] >> 16));
+            }
+        }
+        }
+        if (t == 0) W.coef[c * 2 + kPass] = coef;
+    }
+    if (t == 0) {
+        if (kPass == 0) {
+            A.ti[c * CMC_NI + CMC_I_PAIRS_BR] = (nab > 0.0 && (A.proc & CMC_BREMS)) ? N : 0;
+            A.ti[c * CMC_NI + CMC_I_PAIRS_TR] = (nab > 0.0 && (A.proc & CMC_TRIDENT)) ? N : 0;
+            A.td[c * CMC_ND + CMC_D_NAB_EI] = nab;
+        } else {
+            A.ti[c * CMC_NI + CMC_I_PAIRS_BH] = nab > 0.0 ? N : 0;
+            A.td[c * CMC_ND + CMC_D_NAB_GI] = nab;
+        }
+    }
+    if (team_any<kT>(high != 0, L.redi) && t == 0) atomicOr(A.status, CMC_ST_GAMMA_HIGH);
+    Team<kT>::sync();   // LDS of this cell is free
+}
+
 // One pass of pair tests over all cells from the particles as they are at
 // the start of the step: kPass 0 electron-ion (Bremsstrahlung, then Trident
-// when Bremsstrahlung is not accepted), kPass 1 photon-ion (Bethe-Heitler).
+// when Bremsstrahlung is not accepted), kPass 1 photon-ion (Bethe-Heitler),
+// kPass 2 both, one after the other by the same team for each cell (the
+// photon-ion pass then takes the ions' weight sum from the electron-ion
+// pass in registers, and its latency-bound work overlaps the streaming of
+// the other teams on the compute unit).
 // A test is settled here when U1 > 2 (1 + near_rel) x: then P <= x < U1 and
 // |U1 - P| > near_rel P hold for the computed values, so the pair has no
 // event and no near-threshold count whatever P is.  The rare other pairs are
@@ -1368,577 +1968,18 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
     const int t = Team<kT>::tid();
     const size_t tstride = (team_bytes(cap, (int)sizeof(R), kT) + 15) / 16 * 16;
     const TeamMem M = carve_team(smem_raw + tstride * team, cap, kT);
-    R* slice = reinterpret_cast<R*>(M.slice);
     const double rej = 2.0 * (1.0 + A.near_rel);
     const Rng rng = step_rng(A);
 
-    const int64_t n_items = from_list ? (int64_t)W.counters[kPass == 0 ? kCntBig0 : kCntBig1] : A.n_cells;
+    const PassLds L{red4, redu, redi, opn[team], opk[team], opj[team], &nopen[team]};
+    const int64_t n_items = from_list ? (int64_t)W.counters[kPass == 1 ? kCntBig1 : kCntBig0] : A.n_cells;
     for (int64_t item = (int64_t)blockIdx.x * kTeams + team; item < n_items; item += (int64_t)gridDim.x * kTeams) {
-        const int64_t c = from_list ? (int64_t)W.list_big[kPass][item] : item;
-        // the cell's parameters in one round of loads: its state, the
-        // offsets and live counts of the three species, its global index
-        const uint32_t cell = cell_word(A.cid, c);
-        const int32_t cstat = W.cs[c].status;
-        const int32_t cflags = kPass == 1 ? W.flags[c] : 0;
-        const CellTab<R> ct_c = pick<R>(W.cs[c]);
-        const int64_t eo0 = A.el.off[c], eo1 = A.el.off[c + 1], go0 = A.ph.off[c], go1 = A.ph.off[c + 1];
-        const int64_t io0 = A.io.off[c], io1 = A.io.off[c + 1];
-        const int ecn = A.el.count ? A.el.count[c] : 0x7FFFFFFF, gcn = A.ph.count ? A.ph.count[c] : 0x7FFFFFFF;
-        const int icn = A.io.count ? A.io.count[c] : 0x7FFFFFFF;
-        if (cstat) continue;                                // invalid cell (flagged by k_cell_state)
-        const int Ne = max(0, min(ecn, (int)(eo1 - eo0))), Ng = max(0, min(gcn, (int)(go1 - go0)));
-        const int Ni = max(0, min(icn, (int)(io1 - io0)));
-        // size classes of the hybrid schedule: filter 1 takes the cells up
-        // to fcap particles per species, filter 2 the larger ones
-        const int mx = max(Ne, max(Ng, Ni));
-        if ((filter == 1 && mx > fcap) || (filter == 2 && mx <= fcap)) continue;
-        if (Ne > A.maxn || Ng > A.maxn || Ni > A.maxn) {
-            if (t == 0) atomicOr(A.status, CMC_ST_TOO_LARGE);
-            continue;
-        }
-        const bool ei = (A.proc & (CMC_BREMS | CMC_TRIDENT)) && Ne > 0 && Ni > 0;
-        const bool gi = (A.proc & CMC_BH) && Ng > 0 && Ni > 0;
-        // cells beyond the largest LDS of the step's pass launches go to the
-        // sequential kernel whole
-        if ((ei && (Ne > slow_cap || Ni > slow_cap)) || (gi && (Ng > slow_cap || Ni > slow_cap))) {
-            if (t == 0) mark_slow(W, c);
-            continue;
-        }
-        // every order this pass might need fits this launch's LDS
-        const bool fits = kPass == 0 ? (Ne <= cap && Ni <= cap) : (Ng <= cap && Ni <= cap);
-        const int64_t e0 = eo0, g0 = go0, i0 = io0;
-        const bool active = kPass == 0 ? ei : gi;
-        const int Nm = kPass == 0 ? Ne : Ng, No = kPass == 0 ? Ng : Ne;
-        const int64_t m0 = kPass == 0 ? e0 : g0;
-        const SpeciesDev& S = kPass == 0 ? A.el : A.ph;
-        const double* wm = S.w + m0;
-        const double* wo = kPass == 0 ? A.ph.w + g0 : A.el.w + e0;
-        const double* wion = A.io.w + i0;
-        const bool mobA = Nm >= Ni;
-        const int N = mobA ? Nm : Ni;
-        // ---- direct form: ions at rest, at most four mobile particles per
-        // thread.  The weights are summed (densities, the mobile particles'
-        // n_ab terms against the first ion's weight, the weight checks) in
-        // one reduction, beside the table slice; then every pair is tested
-        // in storage order of its mobile particle.  A cycled mobile species
-        // (N_m < N_i, K = N_i div N_m pairs per particle, e = N_i mod N_m of
-        // them one more) takes the e particles of smallest key as the order
-        // would, found by select_smallest; n_ab = fma(K, A, B), A the
-        // canonical sum of the terms and B that of the selected particles'.
-        // Should the ions not share one weight, the cell is done again below
-        // with both orders.
-        if constexpr (!kMov) {
-            if (active && fits && N <= 4 * kT) {
-                const bool cyc = !mobA;
-                const int K = N / Nm, e = N - K * Nm;
-                uint32_t* sel = reinterpret_cast<uint32_t*>(M.base + kSelBytes - 128);
-                {
-                    const CellTab<R> ct = ct_c;
-                    if (kPass == 0) {
-                        if (A.proc & CMC_BREMS)
-                            for (int i = t; i < kSliceBrems; i += kT) slice[i] = slice_node_brems<R>(T, ct, i);
-                    } else {
-                        for (int i = t; i < kSliceBH; i += kT) slice[i] = slice_node_bh<R>(T, ct, i);
-                    }
-                }
-                // the first pair's momenta are in flight during the reduction
-                double nx = 0.0, ny = 0.0, nz = 0.0;
-                if (t < Nm) { nx = S.px[m0 + t]; ny = S.py[m0 + t]; nz = S.pz[m0 + t]; }
-                const double w0 = wion[0];
-                int fl = 0;                 // 1 bad weight, 2 ions of unequal weight, 4 above the tables
-                double v4[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int q = t + kT * u;
-                    const double wq = q < Nm ? wm[q] : 0.0, wi = q < Ni ? wion[q] : 0.0;
-                    fl |= (!(wq >= 0.0) || !isfinite(wq) || !(wi >= 0.0) || !isfinite(wi)) ? 1 : 0;
-                    fl |= (q < Ni && wi != w0) ? 2 : 0;
-                    canon_add<kT>(v4[0], wq, u);
-                    canon_add<kT>(v4[1], q < Nm ? (wq < w0 ? wq : w0) : 0.0, u);
-                    canon_add<kT>(v4[2], wi, u);
-                }
-                v4[0] = canon_end<kT>(v4[0]);
-                v4[1] = canon_end<kT>(v4[1]);
-                v4[2] = canon_end<kT>(v4[2]);
-                {
-                    int bad = 0;
-                    v4[3] = canon_part<kT>(No, [&](int q) { const double w = wo[q]; bad |= !(w >= 0.0) || !isfinite(w); return w; });
-                    fl |= bad ? 1 : 0;
-                }
-                if (t == 0) nopen[team] = 0;
-                team_reduce4_bits<kT>(v4, fl, red4, redi);   // its barriers also publish the slice
-                if (kT == 64) Team<kT>::sync();
-                if (kPass == 0 && !(fl & 1) && t == 0) {
-                    W.ionsum[c] = v4[2];
-                    atomicOr(&W.flags[c], kFlagWeightsOk | ((fl & 2) ? 0 : kFlagIonsSame));
-                }
-                bool chosen = true;
-                if (!(fl & 3) && cyc) {
-                    // indices of the cycled case come from an opaque copy of the
-                    // thread's index: formed here, not kept across cells in
-                    // registers that the pairs need
-                    int tt = t;
-                    asm volatile("" : "+v"(tt));
-                    if (e > 0)
-                        chosen = select_smallest<kT>(Nm, e, cell, kPass == 0 ? kTagKeyE : kTagKeyG, rng, M.base, sel, tt);
-                    if (chosen) {
-                        double vb[4] = {0.0, 0.0, 0.0, 0.0};
-                        if (e > 0) {
-#pragma unroll
-                            for (int u = 0; u < 4; ++u) {
-                                const int q = tt + kT * u;
-                                const bool sq = q < Nm && ((sel[q >> 5] >> (q & 31)) & 1u);
-                                const double wq = sq ? wm[q] : 0.0;
-                                canon_add<kT>(vb[0], sq ? (wq < w0 ? wq : w0) : 0.0, u);
-                            }
-                            vb[0] = canon_end<kT>(vb[0]);
-                            bool none = false;
-                            team_reduce4<kT>(vb, none, red4, redi);
-                        }
-                        v4[1] = fma((double)K, v4[1], vb[0]);   // one rounding, as in the ordered form
-                    }
-                }
-                if (!(fl & 2) && chosen) {
-                    if (fl & 1) {
-                        if (t == 0) atomicOr(A.status, CMC_ST_BAD_WEIGHT);
-                        continue;
-                    }
-                    const double nab = v4[1];
-                    int high = 0;
-                    if (nab > 0.0) {
-                        const double coef = v4[0] * v4[2] / nab;
-                        const float kx = (float)(coef * A.dt * rej * 16777216.0);
-                        // workgroup teams: the first pairs of a thread's particles
-                        // q = t + 256 u share the draw of the upper bits of U1
-                        // (hi_group(q) = t, word u), drawn once per process
-                        const uint32_t tagA = kPass == 0 ? kTagHiBr : kTagHiBh;
-                        U4 hA{0u, 0u, 0u, 0u}, hT{0u, 0u, 0u, 0u};
-                        if constexpr (kT == 256) {
-                            if (kPass == 1 || (A.proc & CMC_BREMS)) hA = rng.draw(hi_group((uint32_t)t), cell, tagA);
-                            if (kPass == 0 && (A.proc & CMC_TRIDENT)) hT = rng.draw(hi_group((uint32_t)t), cell, kTagHiTr);
-                        }
-                        // the word of U1's upper bits for the pair keyed by x:
-                        // the shared one for a particle's first pair
-                        const auto word = [&](uint32_t x, bool first, uint32_t shared, uint32_t tag) {
-                            return kT == 256 && first ? shared : hi_word(rng.draw(hi_group(x), cell, tag), (x >> 8) & 3u);
-                        };
-                        // every particle's first pair, one at a time (the tests do
-                        // not overlap in registers), the next momenta in flight
-#pragma unroll 1
-                        for (int u = 0; u < 4; ++u) {
-                            const int q = t + kT * u;
-                            const double cx = nx, cy = ny, cz = nz;
-                            if (q + kT < Nm) { nx = S.px[m0 + q + kT]; ny = S.py[m0 + q + kT]; nz = S.pz[m0 + q + kT]; }
-                            // word u of the shared draws: the words move down one per pair
-                            const uint32_t wA = hA.x, wT = hT.x;
-                            hA = U4{hA.y, hA.z, hA.w, 0u};
-                            hT = U4{hT.y, hT.z, hT.w, 0u};
-                            if (q >= Nm) continue;
-                            uint32_t bits = 0;
-                            if (kPass == 0) {
-                                const Elec<R> el = electron_p<R>(cx, cy, cz);
-                                if (A.proc & CMC_BREMS) {
-                                    bool hi;
-                                    const R sig = brems_sig_slice<R>(T, slice, el.g, el.gm1, hi);
-                                    high |= hi;
-                                    if (sig > (R)0 && bound24(word((uint32_t)q, true, wA, kTagHiBr), kx * (float)sig * (float)el.vrel))
-                                        bits = 1u;
-                                }
-                                if ((A.proc & CMC_TRIDENT) && !bits) {
-                                    const R sig = (R)phys::trident_sigma(T.Z, (double)el.g);
-                                    if (sig > (R)0 && bound24(word((uint32_t)q, true, wT, kTagHiTr), kx * (float)sig * (float)el.vrel))
-                                        bits = 2u;
-                                }
-                            } else {
-                                bool hi;
-                                const R sig = bh_sig_slice<R>(T, slice, photon_k<R>(cx, cy, cz), hi);
-                                high |= hi;
-                                if (sig > (R)0 && bound24(word((uint32_t)q, true, wA, kTagHiBh), kx * (float)sig * (float)phys::kC))
-                                    bits = 1u;
-                            }
-                            if (bits) {
-                                const int o = atomicAdd(&nopen[team], 1);
-                                if (o < kCandCap) opn[team][o] = (uint32_t)q | (bits << 16);
-                            }
-                        }
-                        // cycled mobile species: the further pairs k = 1 .. reps - 1 of
-                        // each particle (K - 1 for all, one more for the selected),
-                        // keyed by q + k N_m, the momenta read again
-                        if (cyc && (K > 1 || e > 0)) {
-                            int tt = t;
-                            asm volatile("" : "+v"(tt));
-#pragma unroll 1
-                            for (int u = 0; u < 4; ++u) {
-                                const int q = tt + kT * u;
-                                if (q >= Nm) continue;
-                                const int reps = K + ((e > 0 && ((sel[q >> 5] >> (q & 31)) & 1u)) ? 1 : 0);
-                                if (reps < 2) continue;
-                                const double cx = S.px[m0 + q], cy = S.py[m0 + q], cz = S.pz[m0 + q];
-                                for (int k = 1; k < reps; ++k) {
-                                    const uint32_t x = (uint32_t)(q + k * Nm);
-                                    uint32_t bits = 0;
-                                    if (kPass == 0) {
-                                        const Elec<R> el = electron_p<R>(cx, cy, cz);
-                                        bool hi;
-                                        const R sb = (A.proc & CMC_BREMS) ? brems_sig_slice<R>(T, slice, el.g, el.gm1, hi) : (R)0;
-                                        if (sb > (R)0 && bound24(word(x, false, 0u, kTagHiBr), kx * (float)sb * (float)el.vrel))
-                                            bits = 1u;
-                                        const R st = (A.proc & CMC_TRIDENT) ? (R)phys::trident_sigma(T.Z, (double)el.g) : (R)0;
-                                        if (!bits && st > (R)0 && bound24(word(x, false, 0u, kTagHiTr), kx * (float)st * (float)el.vrel))
-                                            bits = 2u;
-                                    } else {
-                                        bool hi;
-                                        const R sig = bh_sig_slice<R>(T, slice, photon_k<R>(cx, cy, cz), hi);
-                                        if (sig > (R)0 && bound24(word(x, false, 0u, kTagHiBh), kx * (float)sig * (float)phys::kC))
-                                            bits = 1u;
-                                    }
-                                    if (bits) {
-                                        const int o = atomicAdd(&nopen[team], 1);
-                                        if (o < kCandCap) opn[team][o] = (uint32_t)q | (bits << 16) | ((uint32_t)k << 20);
-                                    }
-                                }
-                            }
-                        }
-                        Team<kT>::sync();
-                        const int n_open = nopen[team];
-                        if (n_open > kCandCap) {
-                            if (t == 0) mark_slow(W, c);
-                        } else if (n_open > 0) {
-                            // pair index of an open pair: its particle's rank plus k N_m
-                            rank_open<kT>(Nm, cell, kPass == 0 ? kTagKeyE : kTagKeyG, rng, opn[team], opk[team], opj[team], n_open);
-                            if (t < n_open) {
-                                const uint32_t o = opn[team][t];
-                                push_cand(W, c, ev_pack(kPass, (int)opj[team][t] + (int)(o >> 20) * Nm, (int)(o & 0xFFFFu), 0,
-                                                        (o >> 16) & 0xFu));
-                            }
-                        }
-                        if (t == 0) W.coef[c * 2 + kPass] = coef;
-                    }
-                    if (t == 0) {
-                        if (kPass == 0) {
-                            A.ti[c * CMC_NI + CMC_I_PAIRS_BR] = (nab > 0.0 && (A.proc & CMC_BREMS)) ? N : 0;
-                            A.ti[c * CMC_NI + CMC_I_PAIRS_TR] = (nab > 0.0 && (A.proc & CMC_TRIDENT)) ? N : 0;
-                            A.td[c * CMC_ND + CMC_D_NAB_EI] = nab;
-                        } else {
-                            A.ti[c * CMC_NI + CMC_I_PAIRS_BH] = nab > 0.0 ? N : 0;
-                            A.td[c * CMC_ND + CMC_D_NAB_GI] = nab;
-                        }
-                    }
-                    if (team_any<kT>(high != 0, redi) && t == 0) atomicOr(A.status, CMC_ST_GAMMA_HIGH);
-                    Team<kT>::sync();   // LDS of this cell is free
-                    continue;
-                }
-                Team<kT>::sync();       // the slice is staged again below
-            }
-        }
-        // the weights of the cell are checked (non-negative, finite) as
-        // they are summed into the densities
-        int bad = 0;
-        const auto chk = [&bad](double v) { bad |= !(v >= 0.0) || !isfinite(v); return v; };
-        double v4[4];   // n_mobile, n_ab, n_ion, n_other
-        // When the cell's ions are at rest and share one weight, no decision
-        // and no product depends on which ion a pair gets (P_ej and n_ab see
-        // only that weight): the ion order is then not formed, and the open
-        // pairs name ion 0.
-        const double wi0 = Ni > 0 ? wion[0] : 0.0;
-        // after the electron-ion pass of this step (photon-ion pass): the ion
-        // sum, the ions' sameness and every weight check are known
-        const bool known = kPass == 1 && (cflags & kFlagWeightsOk);
-        bool same = true;
-        if (known) {
-            // the team reduction below adds the wavefronts' partials: the
-            // total enters through the first wavefront alone
-            v4[2] = (kT == 64 || threadIdx.x < 64) ? W.ionsum[c] : 0.0;
-            same = (cflags & kFlagIonsSame) != 0;
-        } else {
-            v4[2] = canon_part<kT>(Ni, [&](int q) { const double w = wion[q]; same &= w == wi0; return chk(w); });
-        }
-        const bool uneq = team_any<kT>(!same, redi);
-        const bool ion_order = active && (kMov || uneq);
-        // When every mobile particle pairs once, the draws of a pair are
-        // keyed by its mobile particle: with interchangeable ions nothing
-        // then depends on the order, which is not formed; the few open pairs
-        // get their pair index (the rank of their particle) at the end.
-        const bool mob_order = active && (!mobA || ion_order);
-        // a cycled mobile species against interchangeable ions: its tests are
-        // walked by draw group (below)
-        const bool cyc_fast = active && !mobA && !ion_order;
-        if (active && !fits && ((ion_order && Ni > cap) || (mob_order && Nm > cap))) {
-            // an order larger than this launch's LDS: the large-LDS launch takes
-            // the pass (listed once per step, however often the launch runs)
-            const int32_t fb = kPass == 0 ? kFlagBig0 : kFlagBig1;
-            if (t == 0 && !(atomicOr(&W.flags[c], fb) & fb))
-                W.list_big[kPass][atomicAdd(&W.counters[kPass == 0 ? kCntBig0 : kCntBig1], 1)] = (int32_t)c;
-            continue;
-        }
-        if (t == 0) nopen[team] = 0;
-        // when every mobile particle pairs once the pair loop walks them in
-        // storage order: its first momenta are loaded before the sort
-        double qx = 0.0, qy = 0.0, qz = 0.0;
-        if (active) {
-            if (mobA && t < N) { qx = S.px[m0 + t]; qy = S.py[m0 + t]; qz = S.pz[m0 + t]; }
-            const CellTab<R> ct = pick<R>(W.cs[c]);
-            if (kPass == 0) {
-                if (A.proc & CMC_BREMS)
-                    for (int i = t; i < kSliceBrems; i += kT) slice[i] = slice_node_brems<R>(T, ct, i);
-            } else {
-                for (int i = t; i < kSliceBH; i += kT) slice[i] = slice_node_bh<R>(T, ct, i);
-            }
-            if (mob_order)
-                rank_order<kT>(Nm, cell, kPass == 0 ? kTagKeyE : kTagKeyG, rng, M.keys, M.tmp, M.hist, M.ordM, mobA, redu);
-            else
-                Team<kT>::sync();      // the slice and the open-pair count
-            if (ion_order)
-                rank_order<kT>(Ni, cell, kPass == 0 ? kTagKeyIE : kTagKeyIG, rng, M.keys, M.tmp, M.hist, M.ordI, false, redu);
-        }
-        const float rNm = 1.0f / (float)Nm, rNi = 1.0f / (float)Ni;
-        // the smaller species is cycled (j mod N_B); the other one is not
-        const auto ion_of = [&](int j) { return ion_order ? (int)M.ordI[Ni == N ? j : mod_small(j, Ni, rNi)] : 0; };
-        const auto w_ion = [&](int j) { return ion_order ? wion[ion_of(j)] : wi0; };
-        const auto mob_of = [&](int j) { return (int)M.ordM[Nm == N ? j : mod_small(j, Nm, rNm)]; };
-        // a cycled mobile species is walked in rank order: its first momenta
-        // are read once the order is formed
-        if (active && !mobA && !cyc_fast && t < N) { const int m = mob_of(t); qx = S.px[m0 + m]; qy = S.py[m0 + m]; qz = S.pz[m0 + m]; }
-        // the other weights, read once: the densities n = sum W, n_ab =
-        // sum_j min(W_a, W_b) and the weight check (when every mobile
-        // particle pairs once, its density and n_ab share the walk)
-        double cyc_b = 0.0;
-        int cyc_k = 0;
-        if (active && mobA) {
-            canon_part2<kT>(N, [&](int q, double& a, double& b) {
-                const double u = chk(wm[q]), v = ion_order ? w_ion((int)M.ordM[q]) : wi0;
-                a += u;
-                b += u < v ? u : v;
-            }, v4[0], v4[1]);
-        } else if (active && !ion_order) {
-            // a cycled mobile species with interchangeable ions: n_ab = K A + B
-            // as the direct form forms it (A over all the mobile particles' terms,
-            // B over those of the e particles of smallest key, ranks 0 .. e - 1)
-            uint32_t* selb = reinterpret_cast<uint32_t*>(M.hist);   // free once the order is formed
-            for (int i = t; i < (Nm + 31) / 32; i += kT) selb[i] = 0u;
-            Team<kT>::sync();
-            for (int r = t; r < N - (N / Nm) * Nm; r += kT) {
-                const int p = (int)M.ordM[r];
-                atomicOr(&selb[p >> 5], 1u << (p & 31));
-            }
-            Team<kT>::sync();
-            canon_part2<kT>(Nm, [&](int q, double& a, double& b) {
-                const double u = chk(wm[q]);
-                a += u;
-                b += u < wi0 ? u : wi0;
-            }, v4[0], v4[1]);
-            cyc_b = canon_part<kT>(Nm, [&](int q) {
-                const double u = wm[q];
-                return ((selb[q >> 5] >> (q & 31)) & 1u) ? (u < wi0 ? u : wi0) : 0.0;
-            });
-            cyc_k = N / Nm;
-        } else {
-            v4[0] = canon_part<kT>(Nm, [&](int q) { return chk(wm[q]); });
-            v4[1] = !active ? 0.0 : canon_part<kT>(N, [&](int j) {
-                const double u = wm[mob_of(j)], v = w_ion(j);
-                return u < v ? u : v;
-            });
-        }
-        v4[3] = known ? 0.0 : canon_part<kT>(No, [&](int q) { return chk(wo[q]); });
-        bool badw = bad != 0;
-        team_reduce4<kT>(v4, badw, red4, redi);
-        if (kPass == 0 && !badw && t == 0) {
-            W.ionsum[c] = v4[2];
-            atomicOr(&W.flags[c], kFlagWeightsOk | (uneq ? 0 : kFlagIonsSame));
-        }
-        if (cyc_k > 0) {
-            double vb[4] = {cyc_b, 0.0, 0.0, 0.0};
-            bool none = false;
-            team_reduce4<kT>(vb, none, red4, redi);
-            v4[1] = fma((double)cyc_k, v4[1], vb[0]);   // one rounding, as in the direct form
-        }
-        if (badw) {
-            if (t == 0) atomicOr(A.status, CMC_ST_BAD_WEIGHT);
-            continue;
-        }
-        if (!active) continue;
-        const double nab = v4[1];
-        int high = 0;
-        if (nab > 0.0) {
-            const double coef = v4[0] * v4[2] / nab;
-            const float kx = (float)(coef * A.dt * rej * 16777216.0);
-            // the draw holding U1's upper bits serves the four pairs of its
-            // group (keys x, x + 256, x + 512, x + 768): the last one drawn is
-            // kept per process, so a workgroup thread walking its mobile
-            // particles in storage order (q = t + 256 u) draws once per four
-            uint32_t g_br = 0xFFFFFFFFu, g_tr = 0xFFFFFFFFu;
-            U4 h_br{0u, 0u, 0u, 0u}, h_tr{0u, 0u, 0u, 0u};
-            const auto hi_bits = [&](uint32_t x, uint32_t tag, uint32_t& gk, U4& h) {
-                const uint32_t gx = hi_group(x);
-                if (gx != gk) { h = rng.draw(gx, cell, tag); gk = gx; }
-                return hi_word(h, (x >> 8) & 3u);
-            };
-            if (cyc_fast) {
-                // N = N_ion pairs: particle m of the cycled species pairs K = N div
-                // N_m times and, if its rank is below e = N mod N_m, once more
-                // (Sec. III.A pairing).  All its tests share one cross section and
-                // flux: its bounds are formed once (in the arithmetic of the tests
-                // below the other forms make), and the tests are walked by draw
-                // group: the keys x = m + k N_m of a group ((x >> 10) << 8 |
-                // (x & 255) = g) are base(g) + 256 w, w = 0..3, and share the draw
-                // of U1's upper bits, word w.
-                // LDS of the team (n >= N_m entries each): the bounds in the key
-                // array and over the two order arrays (4 n bytes, written once
-                // the ranks are taken from the order), the ranks in the bucket
-                // particle array, the selection bitmap in the histogram
-                float* xb = reinterpret_cast<float*>(M.keys);   // first process's bound of m (< 0: none)
-                float* xt = reinterpret_cast<float*>(M.ordM);   // Trident's bound of m (over ordM, ordI)
-                uint16_t* rk = M.tmp;                           // rank of m
-                const uint32_t* selb = reinterpret_cast<const uint32_t*>(M.hist);
-                for (int r = t; r < Nm; r += kT) rk[M.ordM[r]] = (uint16_t)r;
-                Team<kT>::sync();
-                for (int m = t; m < Nm; m += kT) {
-                    const double cx = S.px[m0 + m], cy = S.py[m0 + m], cz = S.pz[m0 + m];
-                    float b1 = -1.0f, b2 = -1.0f;
-                    if (kPass == 0) {
-                        const Elec<R> e = electron_p<R>(cx, cy, cz);
-                        if (A.proc & CMC_BREMS) {
-                            bool hi;
-                            const R sig = brems_sig_slice<R>(T, slice, e.g, e.gm1, hi);
-                            high |= hi;
-                            if (sig > (R)0) b1 = kx * (float)sig * (float)e.vrel;
-                        }
-                        if (A.proc & CMC_TRIDENT) {
-                            const R sig = (R)phys::trident_sigma(T.Z, (double)e.g);
-                            if (sig > (R)0) b2 = kx * (float)sig * (float)e.vrel;
-                        }
-                    } else {
-                        bool hi;
-                        const R sig = bh_sig_slice<R>(T, slice, photon_k<R>(cx, cy, cz), hi);
-                        high |= hi;
-                        if (sig > (R)0) b1 = kx * (float)sig * (float)phys::kC;
-                    }
-                    xb[m] = b1;
-                    xt[m] = b2;
-                }
-                Team<kT>::sync();
-                const int K = N / Nm, e = N - K * Nm;
-                const int X = K * Nm + (e > 0 ? Nm : 0);      // keys of every particle's last pair and below
-                const int G = ((X + 1023) >> 10) << 8;
-                for (int g = t; g < G; g += kT) {
-                    const int base = ((g >> 8) << 10) | (g & 255);
-                    if (base >= X) continue;
-                    const U4 h = rng.draw((uint32_t)g, cell, kPass == 0 ? kTagHiBr : kTagHiBh);
-                    U4 h2{0u, 0u, 0u, 0u};
-                    bool h2_drawn = false;
-#pragma unroll
-                    for (int w = 0; w < 4; ++w) {
-                        const int x = base + 256 * w;
-                        if (x >= X) break;
-                        const int m = mod_small(x, Nm, rNm);
-                        const int k = __float2int_rn((float)(x - m) * rNm);
-                        if (!(k < K || ((selb[m >> 5] >> (m & 31)) & 1u))) continue;
-                        uint32_t bits = 0;
-                        if (bound24(hi_word(h, (uint32_t)w), xb[m])) {
-                            bits = 1u;
-                        } else if (kPass == 0 && xt[m] >= 0.0f) {
-                            if (!h2_drawn) { h2 = rng.draw((uint32_t)g, cell, kTagHiTr); h2_drawn = true; }
-                            if (bound24(hi_word(h2, (uint32_t)w), xt[m])) bits = 2u;
-                        }
-                        if (bits) {
-                            const int o = atomicAdd(&nopen[team], 1);
-                            if (o < kCandCap) opn[team][o] = (uint32_t)m | (bits << 14) | ((uint32_t)k << 16);
-                        }
-                    }
-                }
-                Team<kT>::sync();
-                const int n_open = nopen[team];
-                if (n_open > kCandCap) {
-                    if (t == 0) mark_slow(W, c);
-                } else if (t < n_open) {
-                    // pair index: the particle's rank plus k N_m
-                    const uint32_t o = opn[team][t];
-                    const int m = (int)(o & 0x3FFFu), k = (int)(o >> 16);
-                    push_cand(W, c, ev_pack(kPass, (int)rk[m] + k * Nm, m, 0, (o >> 14) & 3u));
-                }
-            } else {
-            for (int q = t; q < N; q += kT) {
-                const int j = mobA ? (mob_order ? (int)M.ordM[q] : 0) : q;
-                const int jm = mobA ? 0 : (Nm == N ? j : mod_small(j, Nm, rNm));   // rank of the cycled particle
-                const int mi = mobA ? q : (int)M.ordM[jm];
-                // counter of the pair's draws: its mobile particle and repetition
-                const uint32_t dk = (uint32_t)(mobA ? mi : mi + (j - jm));
-                // this pair's momenta; the next pair's are read meanwhile
-                const double cx = qx, cy = qy, cz = qz;
-                if (q + kT < N) {
-                    const int mn = mobA ? q + kT : mob_of(q + kT);
-                    qx = S.px[m0 + mn]; qy = S.py[m0 + mn]; qz = S.pz[m0 + mn];
-                }
-                uint32_t bits = 0;
-                Ion b{0.0, 0.0, 0.0, 1.0, false};
-                if constexpr (kMov) b = ion_at(A.io, i0 + ion_of(j));
-                if (kPass == 0) {
-                    Elec<R> e;
-                    if constexpr (kMov) e = electron_moving<R>(electron_frame(b, cx, cy, cz), b);
-                    else e = electron_p<R>(cx, cy, cz);
-                    if (A.proc & CMC_BREMS) {
-                        bool hi;
-                        const R sig = brems_sig_slice<R>(T, slice, e.g, e.gm1, hi);
-                        high |= hi;
-                        if (sig > (R)0 && bound24(hi_bits(dk, kTagHiBr, g_br, h_br), kx * (float)sig * (float)e.vrel))
-                            bits = 1u;
-                    }
-                    if ((A.proc & CMC_TRIDENT) && !bits) {
-                        const R sig = (R)phys::trident_sigma(T.Z, (double)e.g);
-                        if (sig > (R)0 && bound24(hi_bits(dk, kTagHiTr, g_tr, h_tr), kx * (float)sig * (float)e.vrel))
-                            bits = 2u;
-                    }
-                } else {
-                    R k;
-                    double flux = phys::kC;
-                    if constexpr (kMov) {
-                        const Frame f = photon_frame(b, cx, cy, cz);
-                        k = (R)f.g;
-                        flux = photon_flux(f, b);
-                    } else {
-                        k = photon_k<R>(cx, cy, cz);
-                    }
-                    bool hi;
-                    const R sig = bh_sig_slice<R>(T, slice, k, hi);
-                    high |= hi;
-                    if (sig > (R)0 && bound24(hi_bits(dk, kTagHiBh, g_br, h_br), kx * (float)sig * (float)flux))
-                        bits = 1u;
-                }
-                if (bits) {
-                    if (mob_order) {
-                        push_cand(W, c, ev_pack(kPass, j, mi, ion_of(j), bits));
-                    } else {
-                        const int k = atomicAdd(&nopen[team], 1);
-                        if (k < kCandCap) opn[team][k] = (uint32_t)mi | (bits << 16);
-                    }
-                }
-            }
-            if (!mob_order) {
-                Team<kT>::sync();
-                const int n_open = nopen[team];
-                if (n_open > kCandCap) {
-                    if (t == 0) mark_slow(W, c);
-                } else if (n_open > 0) {
-                    rank_open<kT>(Nm, cell, kPass == 0 ? kTagKeyE : kTagKeyG, rng, opn[team], opk[team], opj[team], n_open);
-                    if (t < n_open)
-                        push_cand(W, c, ev_pack(kPass, (int)opj[team][t], (int)(opn[team][t] & 0xFFFFu), 0, opn[team][t] >> 16));
-                }
-            }
-            }
-            if (t == 0) W.coef[c * 2 + kPass] = coef;
-        }
-        if (t == 0) {
-            if (kPass == 0) {
-                A.ti[c * CMC_NI + CMC_I_PAIRS_BR] = (nab > 0.0 && (A.proc & CMC_BREMS)) ? N : 0;
-                A.ti[c * CMC_NI + CMC_I_PAIRS_TR] = (nab > 0.0 && (A.proc & CMC_TRIDENT)) ? N : 0;
-                A.td[c * CMC_ND + CMC_D_NAB_EI] = nab;
-            } else {
-                A.ti[c * CMC_NI + CMC_I_PAIRS_BH] = nab > 0.0 ? N : 0;
-                A.td[c * CMC_ND + CMC_D_NAB_GI] = nab;
-            }
-        }
-        if (team_any<kT>(high != 0, redi) && t == 0) atomicOr(A.status, CMC_ST_GAMMA_HIGH);
-        Team<kT>::sync();   // LDS of this cell is free
+        const int64_t c = from_list ? (int64_t)W.list_big[kPass == 1 ? 1 : 0][item] : item;
+        PassCarry carry{0, 0.0};
+        if constexpr (kPass != 1)
+            pass_cell<R, kT, 0, kMov, false>(A, T, W, cap, filter, fcap, slow_cap, c, M, rng, rej, t, L, carry);
+        if constexpr (kPass != 0)
+            pass_cell<R, kT, 1, kMov, kPass == 2>(A, T, W, cap, filter, fcap, slow_cap, c, M, rng, rej, t, L, carry);
     }
 }
 
@@ -2594,8 +2635,13 @@ static void launch_pass_m(const StepArgs& A, const TabView<R>& T, const Work& W,
         hipExtLaunchKernelGGL(kernel, dim3(L.grid), dim3(256), (uint32_t)L.dshm, st, e0, e1, 0u, A, T, W, L.cap,
                               L.filter, L.fcap, L.slow_cap, L.from_list);
     };
-    if (A.proc & (CMC_BREMS | CMC_TRIDENT)) launch(k_pass<R, kT, 0, kMov>);
-    if (A.proc & CMC_BH) launch(k_pass<R, kT, 1, kMov>);
+    const bool ei = (A.proc & (CMC_BREMS | CMC_TRIDENT)) != 0, gi = (A.proc & CMC_BH) != 0;
+    if (ei && gi && !L.from_list) {
+        launch(k_pass<R, kT, 2, kMov>);
+    } else {
+        if (ei) launch(k_pass<R, kT, 0, kMov>);
+        if (gi) launch(k_pass<R, kT, 1, kMov>);
+    }
 }
 
 template <typename R, int kT>
