@@ -334,6 +334,49 @@ cmc_status cmc_expected_yield_backward(cmc_tables t, int64_t n_cells, const doub
                                        double* gpy, double* gpz, double* gw, double* gZstar,
                                        double* gn_e, double* gT_e, int32_t* status, void* stream);
 
+/* ------------------------------------------------------------------ */
+/* Screening forms (Sec. II.B.2).  The cross sections of the           */
+/* relativistic regimes (eq:csre, eq:csur) and of Bethe-Heitler pair   */
+/* production (eq:dsdkbh) see the atomic potential through the         */
+/* screening functions I1, I2 (eq:defphi1, eq:defphi2).  The step uses */
+/* the reduced potential, one exponential of length L_R (eq:reduit,    */
+/* eq:lambert-W), whose functions have closed forms (eq:deriv_I1,      */
+/* eq:deriv_I2).  These calls give them in either form: the reduced    */
+/* one, or that of the two-exponential Thomas-Fermi-Debye potential    */
+/* itself (eq:V_TFD), computed by quadrature -- the comparison of      */
+/* Figs. 5, 7 and 8.                                                    */
+/* ------------------------------------------------------------------ */
+enum { CMC_SCREEN_REDUCED = 0, CMC_SCREEN_TFD = 1 };
+
+/* I1[i], I2[i] at delta[i] (eq:defphi1, eq:defphi2) for the cell state  */
+/* (Zstar[i], n_i[i], T_e[i]) of point i (Sec. II.A, for the element of */
+/* the tables t) in screening form `form`.  Every array is a device     */
+/* array of n doubles owned by the caller; status is a device int32 or  */
+/* NULL, OR-ed with CMC_ST_* (caller clears).  A point with delta       */
+/* outside (0, 1] or an invalid cell state (Z* outside [0, Z], n_i <= 0, */
+/* T_e < 0 or non-finite) gets NaN in both outputs and sets              */
+/* CMC_ST_BAD_CELL.  n = 0 does nothing (the arrays may then be NULL).  */
+/* Asynchronous on stream.  Errors: CMC_EINVAL (NULL handle or array,   */
+/* unknown form, n < 0), CMC_EDEVICE.                                   */
+cmc_status cmc_screening_functions(cmc_tables t, int32_t form, int64_t n, const double* Zstar,
+                                   const double* n_i, const double* T_e, const double* delta,
+                                   double* I1, double* I2, int32_t* status, void* stream);
+
+/* Differential cross sections at n points in screening form `form`,     */
+/* each with its cell state as above:                                    */
+/*   process CMC_BREMS: e1[i] = gamma_1 >= 2, x[i] = k/(gamma_1 - 1) in  */
+/*     (0, 1); out[i] = k dsigma/dk in m^2, eq:csre for gamma_1 <= 100   */
+/*     and eq:csur (Coulomb correction f_C(Z)) above;                    */
+/*   process CMC_BH: e1[i] = k > 2, x[i] = (gamma_+ - 1)/(k - 2) in      */
+/*     (0, 1); out[i] = dsigma/dgamma_+ in m^2, eq:dsdkbh.               */
+/* Device arrays of n doubles, caller-owned; an invalid point gets NaN   */
+/* and sets CMC_ST_BAD_CELL.  Errors as for cmc_screening_functions, and */
+/* CMC_EINVAL for another process.                                       */
+cmc_status cmc_cross_sections(cmc_tables t, int32_t process, int32_t form, int64_t n,
+                              const double* Zstar, const double* n_i, const double* T_e,
+                              const double* e1, const double* x, double* out, int32_t* status,
+                              void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -24,6 +24,7 @@ LIB_PATH = os.path.join(HERE, "libcmc.so")
 BREMS, BH, TRIDENT = 1, 2, 4
 FP64, FP32 = 0, 1
 SCHED_AUTO, SCHED_CELL, SCHED_GROUP, SCHED_WAVE, SCHED_HYBRID = 0, 1, 2, 3, 4
+SCREEN_REDUCED, SCREEN_TFD = 0, 1
 MAX_PER_CELL = 16384
 ST_OVERFLOW, ST_GAMMA_HIGH, ST_BAD_CELL, ST_BAD_WEIGHT, ST_TOO_LARGE, ST_BAD_OFFSETS = 1, 2, 4, 8, 16, 32
 I_NAMES = ["pairs_br", "pairs_tr", "pairs_bh", "ev_br", "ev_tr", "ev_bh",
@@ -35,7 +36,7 @@ TABLE_NAMES = ["sigR", "skR", "cdfR", "sigU", "skU", "cdfU", "sigN", "skN", "cdf
 EXPORTS = ["cmc_last_error", "cmc_build_tables", "cmc_tables_free", "cmc_tables_size",
            "cmc_tables_export", "cmc_pair_cells", "cmc_collide_step", "cmc_step_workspace_bytes",
            "cmc_expected_yield", "cmc_expected_yield_backward", "cmc_collide_step_noalloc",
-           "cmc_noalloc_max_cells"]
+           "cmc_noalloc_max_cells", "cmc_screening_functions", "cmc_cross_sections"]
 
 _vp = C.c_void_p
 _i64 = C.c_int64
@@ -92,9 +93,11 @@ def _load():
                                      + [C.c_double, C.c_int32, _vp, _vp, _vp, _vp])
     L.cmc_expected_yield_backward.argtypes = ([_vp, _i64] + [_vp] * 4 + [_i64] + [_vp] * 4
                                               + [C.c_double, C.c_int32] + [_vp] * 8 + [_vp, _vp])
+    L.cmc_screening_functions.argtypes = [_vp, C.c_int32, _i64] + [_vp] * 8
+    L.cmc_cross_sections.argtypes = [_vp, C.c_int32, C.c_int32, _i64] + [_vp] * 8
     for name in ("cmc_build_tables", "cmc_tables_free", "cmc_tables_export", "cmc_pair_cells",
                  "cmc_collide_step", "cmc_expected_yield", "cmc_expected_yield_backward",
-                 "cmc_collide_step_noalloc"):
+                 "cmc_collide_step_noalloc", "cmc_screening_functions", "cmc_cross_sections"):
         getattr(L, name).restype = C.c_int
     return L
 
@@ -397,6 +400,41 @@ def expected_yield_backward(tables: Tables, Zstar, n_e, T_e, off, px, py, pz, w,
         _ptr(out["gpx"]), _ptr(out["gpy"]), _ptr(out["gpz"]), _ptr(out["gw"]), _ptr(out["gZstar"]),
         _ptr(out["gn_e"]), _ptr(out["gT_e"]), _ptr(status, "int32"), _stream(stream)),
         "cmc_expected_yield_backward")
+    return out
+
+
+def screening_functions(tables: Tables, Zstar, n_i, T_e, delta, form=SCREEN_REDUCED, stream=None, status=None):
+    """(I1, I2) at delta per point, each with its cell state, in the reduced
+    or the two-exponential form (cmc_screening_functions).  status: an
+    optional int32 device tensor [1] OR-ed with CMC_ST_* bits."""
+    import torch
+    n = Zstar.numel()
+    _lengths(points=(n, n_i, T_e, delta), status=(1, status))
+    I1 = torch.empty(n, dtype=torch.float64, device=Zstar.device)
+    I2 = torch.empty_like(I1)
+    f8 = "float64"
+    _check(get_lib().cmc_screening_functions(tables.handle, int(form), n, _ptr(Zstar, f8), _ptr(n_i, f8),
+                                             _ptr(T_e, f8), _ptr(delta, f8), _ptr(I1), _ptr(I2),
+                                             _ptr(status, "int32"), _stream(stream)),
+           "cmc_screening_functions")
+    return I1, I2
+
+
+def cross_sections(tables: Tables, process, Zstar, n_i, T_e, e1, x, form=SCREEN_REDUCED, stream=None,
+                   status=None):
+    """k dsigma/dk (process BREMS: e1 = gamma_1, x = k/(gamma_1 - 1)) or
+    dsigma/dgamma_+ (process BH: e1 = k, x = (gamma_+ - 1)/(k - 2)) per
+    point, in m^2, in the reduced or the two-exponential screening form
+    (cmc_cross_sections)."""
+    import torch
+    n = Zstar.numel()
+    _lengths(points=(n, n_i, T_e, e1, x), status=(1, status))
+    out = torch.empty(n, dtype=torch.float64, device=Zstar.device)
+    f8 = "float64"
+    _check(get_lib().cmc_cross_sections(tables.handle, int(process), int(form), n, _ptr(Zstar, f8), _ptr(n_i, f8),
+                                        _ptr(T_e, f8), _ptr(e1, f8), _ptr(x, f8), _ptr(out),
+                                        _ptr(status, "int32"), _stream(stream)),
+           "cmc_cross_sections")
     return out
 
 

@@ -154,3 +154,25 @@ def test_missing_library_fails_loudly():
             cmc.build_tables(29)
     finally:
         cmc.LIB_PATH, cmc._LIB = saved_path, saved_lib
+
+
+def test_screening_calls_check_arguments_without_gpu():
+    """cmc_screening_functions / cmc_cross_sections: the handle, the form,
+    the process and n are checked on the host; n = 0 is a no-op with NULL
+    arrays (a placeholder handle is never dereferenced before that)."""
+    import paper_1907_02814_amd as cmc
+    L = cmc.get_lib()
+    t = C.c_void_p(1)
+    assert L.cmc_screening_functions(None, 0, 4, *([None] * 8)) == 1
+    assert b"tables is NULL" in L.cmc_last_error()
+    assert L.cmc_screening_functions(t, 2, 4, *([None] * 8)) == 1
+    assert b"unknown form" in L.cmc_last_error()
+    assert L.cmc_screening_functions(t, 1, -1, *([None] * 8)) == 1
+    assert L.cmc_screening_functions(t, 1, 0, *([None] * 8)) == 0
+    assert L.cmc_screening_functions(t, 1, 3, *([None] * 8)) == 1
+    assert b"NULL array" in L.cmc_last_error()
+    assert L.cmc_cross_sections(t, cmc.TRIDENT, 0, 0, *([None] * 8)) == 1
+    assert b"process" in L.cmc_last_error()
+    assert L.cmc_cross_sections(t, cmc.BH, 5, 0, *([None] * 8)) == 1
+    assert L.cmc_cross_sections(t, cmc.BREMS, 1, 0, *([None] * 8)) == 0
+    assert L.cmc_cross_sections(t, cmc.BREMS, 1, 2, *([None] * 8)) == 1

@@ -20,7 +20,13 @@ import pytest
 
 from oracle import oracle as O
 
-mp.mp.dps = 40
+
+
+@pytest.fixture(autouse=True)
+def _digits():
+    """40 digits for every test here (other modules set their own)"""
+    with mp.workdps(40):
+        yield
 
 
 def I1_single(d, L):
