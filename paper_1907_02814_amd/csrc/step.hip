@@ -2036,6 +2036,7 @@ struct EvLane {
     int ikd;
     double wkd;
     bool reused;
+    bool last;     // no later event of its pass on the same particle
 };
 
 // A wavefront settles the open pairs of a listed cell with P (same
@@ -2072,6 +2073,7 @@ __device__ __forceinline__ EvLane<R> ev_settle(const StepArgs& A, const TabView<
     }
     // ---- settle them
     L.reused = false;
+    L.last = true;
     if (cand) {
         const uint32_t bits = ev_kind(mine);
         const double coef = L.pass == 0 ? E.coef0 : E.coef1;
@@ -2120,29 +2122,26 @@ __device__ __forceinline__ EvLane<R> ev_settle(const StepArgs& A, const TabView<
     return L;
 }
 
-// The wavefront applies the settled events of its lanes in (pass, pair
-// index) order: samples the energies in FP64, moves the electrons, writes
-// the products at slots from ballot prefix sums, and writes the event
-// tallies and the counts.  staged_all and n_conv: the workgroup kernel has
-// every photon staged and removes n_conv converted ones beside this, so
-// new photons go straight to their final slots.
+// The kinematics of each lane's event: the energies sampled from the FP64
+// tables (Sec. III.A), the mobile particle moved (L.px, L.py, L.pz), the
+// products formed, the event's tallies (with the Trident test of a pair
+// whose Bremsstrahlung was accepted, on the electron it left).  Lanes
+// without an event do nothing.  Every lane of the wavefront calls it: with
+// coop the wavefront inverts each CDF together (one round of table reads
+// per event), else every lane bisects its own; both give the same abscissa.
+struct EvKin {
+    bool f_ph, f_tr, f_bh;
+    double kx, ky, kz, pxm, pym, pzm, pxp, pyp, pzp;
+    Tally t;
+};
+
 template <typename R>
-__device__ __forceinline__ void ev_apply(const StepArgs& A, const TabView<R>& T, const TabView<double>& T64,
-                                         const Rng& rng, const EvCell<R>& E, EvLane<R>& L, bool staged_all,
-                                         int n_conv) {
-    const int lane = threadIdx.x & 63;
-    // ---- the events, lanes in (pass, pair index) order
-    const int n = __popcll(__ballot(L.kind != 0));
+__device__ __forceinline__ EvKin ev_kin(const StepArgs& A, const TabView<R>& T, const TabView<double>& T64,
+                                           const Rng& rng, const EvCell<R>& E, EvLane<R>& L, bool coop) {
     const uint32_t evk = L.kind;
     Tally t = {};
-    t.near_br = L.near_br; t.near_tr = L.near_tr; t.near_bh = L.near_bh;
     bool f_ph = false, f_tr = false, f_bh = false;
     double kx = 0, ky = 0, kz = 0, pxm = 0, pym = 0, pzm = 0, pxp = 0, pyp = 0, pzp = 0;
-    const int64_t par = L.pass == 0 ? E.e0 + L.mi : E.g0 + L.mi;
-    // with few events the wavefront inverts each CDF together (one round
-    // of table reads per event), else every lane bisects its own; both
-    // give the same abscissa
-    const bool coop = n <= 8;
     const auto invert = [&](bool has, const CdfRow<double>& row, double xi, double& ct) {
         if (coop) return cdf_invert_wave<double>(has, row, E.ct64, xi, ct);
         return has ? cdf_invert<double>(row.T, row.kind, row.i, row.w, E.ct64, xi, ct) : 0.0;
@@ -2240,16 +2239,209 @@ __device__ __forceinline__ void ev_apply(const StepArgs& A, const TabView<R>& T,
         t.W_tr += L.Wm;
         f_tr = true;
     }
-    if (L.pass == 0 && (f_ph || f_tr)) { A.el.px[par] = L.px; A.el.py[par] = L.py; A.el.pz[par] = L.pz; }
-    // slots in (pass, pair) order: lanes are already in that order
+    return EvKin{f_ph, f_tr, f_bh, kx, ky, kz, pxm, pym, pzm, pxp, pyp, pzp, t};
+}
+
+// Tallies of a cell's pairs that ev_resolve settled beyond the lanes'
+// records: near-threshold tests, and the pairs of converted photons after
+// their conversion (counted by the pass, never tested).
+struct ChainTally {
+    int near_br, near_tr, near_bh;
+    int bh_unpaired;
+};
+
+// rank of key among the lanes of mask (distinct keys)
+__device__ __forceinline__ int key_rank(unsigned long long mask, uint32_t key) {
+    int r = 0;
+    for (unsigned long long m = mask; m; m &= m - 1ull)
+        r += (uint32_t)__builtin_amdgcn_readlane((int)key, __ffsll((long long)m) - 1) < key;
+    return r;
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+    const uint64_t u = __double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// Events on particles that pair again later in their pass.  The pairs of
+// a step are taken in order (Sec. III.A), so a particle's later pairs see
+// it as its earlier events left it; the pass kernels tested every pair
+// with the particles as the step found them.  Here, in one wavefront,
+// each particle's first event stands and its later open pairs are
+// dropped; then
+//  - a converted photon pairs no more: its remaining pairs are not tested
+//    (nor counted);
+//  - an electron's remaining pairs are tested again, in order, with the
+//    electron as each event leaves it (the cell's ions, at rest and of one
+//    weight, are interchangeable, so the pair's ion does not matter): 64
+//    pairs at a time, the first event found taking a free lane, and its
+//    kinematics giving the electron's next state.
+// The tests are those of ev_settle (FP64 P, the same draws keyed by the
+// pair).  Returns false when an electron's pairs need testing again but
+// the ions move or differ in weight, or when the lanes run out: the cell
+// then takes the sequential step.  Every lane of the wavefront calls it.
+template <typename R>
+__device__ bool ev_resolve(const StepArgs& A, const TabView<R>& T, const TabView<double>& T64, const Rng& rng,
+                           const EvCell<R>& E, EvLane<R>& L, double rej, ChainTally& X) {
+    const int lane = threadIdx.x & 63;
+    X = ChainTally{0, 0, 0, 0};
+    if (!__ballot(L.kind != 0 && L.reused)) return true;
+    // a particle's open pairs after its first event are dropped
+    {
+        const unsigned long long bev = __ballot(L.kind != 0);
+        bool stale = false;
+        for (unsigned long long m = bev; m; m &= m - 1ull) {
+            const int o = __ffsll((long long)m) - 1;
+            stale |= __builtin_amdgcn_readlane(L.pass, o) == L.pass && __builtin_amdgcn_readlane(L.mi, o) == L.mi &&
+                     __builtin_amdgcn_readlane(L.j, o) < L.j;
+        }
+        if (stale) { L.kind = 0u; L.near_br = L.near_tr = L.near_bh = 0; }
+    }
+    const bool trig = L.kind != 0 && L.reused;
+    // a converted photon's remaining pairs: of the pairs j = r + k N_g < N_i
+    // of the photon of rank r, those after its conversion
+    int unp = 0;
+    if (trig && L.pass == 1) {
+        const int Nm = E.Ng0, r = L.j % Nm, k = L.j / Nm;
+        unp = (E.Ni - r + Nm - 1) / Nm - k - 1;
+    }
+    const unsigned long long chains = __ballot(trig && L.pass == 0);
+    int nb_x = 0, nt_x = 0, nh_x = 0;
+    bool ok = true;
+    if (chains) {
+        ok = (E.flg & kFlagIonsSame) != 0 && A.io.px == nullptr;
+        // the lanes without an event are freed; their near counts are kept
+        if (ok && L.kind == 0u) {
+            nb_x += L.near_br; nt_x += L.near_tr; nh_x += L.near_bh;
+            L.near_br = L.near_tr = L.near_bh = 0;
+            L.pass = 2;
+        }
+        const int Nm = E.Ne, N = E.Ni;
+        for (unsigned long long todo = ok ? chains : 0ull; todo && ok; todo &= todo - 1ull) {
+            int tl = __ffsll((long long)todo) - 1;
+            const int mi = __builtin_amdgcn_readlane(L.mi, tl);
+            const double Wm = readlane_f64(L.Wm, tl), Wi = readlane_f64(L.Wi, tl);
+            const double Pej = Wi / (Wm > Wi ? Wm : Wi);
+            int jn = __builtin_amdgcn_readlane(L.j, tl) + Nm;    // the electron's next pair
+            while (ok) {
+                // the electron after the event on lane tl
+                double px, py, pz;
+                {
+                    EvLane<R> Le = L;
+                    if (lane != tl) Le.kind = 0u;
+                    (void)ev_kin<R>(A, T, T64, rng, E, Le, true);
+                    px = readlane_f64(Le.px, tl); py = readlane_f64(Le.py, tl); pz = readlane_f64(Le.pz, tl);
+                }
+                if (jn >= N) break;
+                const Elec<R> e = electron_p<R>(px, py, pz);
+                bool hi;
+                const R sb = (A.proc & CMC_BREMS) ? brems_lookup<R, false>(T, E.ct, e.g, e.gm1, hi).sig : (R)0;
+                const R st = (A.proc & CMC_TRIDENT) ? (R)phys::trident_sigma(T.Z, (double)e.g) : (R)0;
+                const double xb = E.coef0 * (double)sb * e.vrel * A.dt;
+                const double xt = E.coef0 * (double)st * e.vrel * A.dt;
+                // the next pairs, 64 at a time, until one has an event
+                int first = 64, jf = 0;
+                uint32_t kf = 0u;
+                int nbf = 0, ntf = 0;
+                for (; jn < N; jn += 64 * Nm) {
+                    const int jq = jn + lane * Nm;
+                    const uint32_t dk = (uint32_t)(mi + (jq / Nm) * Nm);
+                    int nb = 0, nt = 0;
+                    uint32_t kind = 0u;
+                    if (jq < N) {
+                        if (sb > (R)0 && settle(xb, rng, dk, E.cell, kTagAccBr, kTagHiBr, rej, A.near_rel, Pej, nb))
+                            kind = kEvBr | ((A.proc & CMC_TRIDENT) ? kEvTrPending : 0u);
+                        if (!kind && st > (R)0 && settle(xt, rng, dk, E.cell, kTagAccTr, kTagHiTr, rej, A.near_rel, Pej, nt))
+                            kind = kEvTr;
+                    }
+                    const unsigned long long bk = __ballot(kind != 0u);
+                    first = bk ? __ffsll((long long)bk) - 1 : 64;
+                    if (lane < first) { nb_x += nb; nt_x += nt; }   // tests that stand
+                    if (bk) {
+                        kf = (uint32_t)__builtin_amdgcn_readlane((int)kind, first);
+                        nbf = __builtin_amdgcn_readlane(nb, first);
+                        ntf = __builtin_amdgcn_readlane(nt, first);
+                        jf = jn + first * Nm;
+                        break;
+                    }
+                }
+                if (first == 64) break;                   // no further event
+                // the event takes a free lane
+                const unsigned long long bfree = __ballot(L.kind == 0u);
+                if (!bfree) { ok = false; break; }
+                const int fl = __ffsll((long long)bfree) - 1;
+                if (lane == fl) {
+                    L.pass = 0; L.j = jf; L.mi = mi; L.ii = 0;
+                    L.dk = (uint32_t)(mi + (jf / Nm) * Nm);
+                    L.kind = kf;
+                    L.near_br = nbf; L.near_tr = ntf; L.near_bh = 0;
+                    L.px = px; L.py = py; L.pz = pz; L.Wm = Wm; L.Wi = Wi;
+                    L.b = Ion{0.0, 0.0, 0.0, 1.0, false};
+                    L.fr = electron_frame(L.b, px, py, pz);
+                    if (kf & kEvBr) {
+                        bool hi2;
+                        L.BLd = brems_lookup<double, false>(T64, E.ct64, L.fr.g, L.fr.gm1, hi2);
+                    }
+                    L.reused = true;
+                    L.last = true;
+                }
+                tl = fl;
+                jn = jf + Nm;
+            }
+        }
+    }
+    if (!ok) return false;
+    // the last event of each electron writes its momentum
+    {
+        const unsigned long long bev = __ballot(L.kind != 0u && L.pass == 0);
+        bool later = false;
+        for (unsigned long long m = bev; m; m &= m - 1ull) {
+            const int o = __ffsll((long long)m) - 1;
+            later |= __builtin_amdgcn_readlane(L.mi, o) == L.mi && __builtin_amdgcn_readlane(L.j, o) > L.j;
+        }
+        L.last = !later;
+    }
+    X.near_br = wave_sum_i32(nb_x);
+    X.near_tr = wave_sum_i32(nt_x);
+    X.near_bh = wave_sum_i32(nh_x);
+    X.bh_unpaired = wave_sum_i32(unp);
+    return true;
+}
+
+// The wavefront applies the settled events of its lanes: samples the
+// energies in FP64, moves the mobile particles, writes the products at
+// slots in (pass, pair index) order (ranks of the pair keys among the
+// lanes), and writes the event tallies and the counts.  staged_all and
+// n_conv: the workgroup kernel has every photon staged and removes n_conv
+// converted ones beside this, so new photons go straight to their final
+// slots.  X: the tallies of the pairs ev_resolve evaluated beyond the lanes.
+template <typename R>
+__device__ __forceinline__ void ev_apply(const StepArgs& A, const TabView<R>& T, const TabView<double>& T64,
+                                         const Rng& rng, const EvCell<R>& E, EvLane<R>& L, bool staged_all,
+                                         int n_conv, const ChainTally& X) {
+    const int lane = threadIdx.x & 63;
+    const int n = __popcll(__ballot(L.kind != 0));
+    const EvKin K = ev_kin<R>(A, T, T64, rng, E, L, n <= 8);
+    Tally t = K.t;
+    t.near_br += L.near_br; t.near_tr += L.near_tr; t.near_bh += L.near_bh;
+    const bool f_ph = K.f_ph, f_tr = K.f_tr, f_bh = K.f_bh;
+    const double kx = K.kx, ky = K.ky, kz = K.kz, pxm = K.pxm, pym = K.pym, pzm = K.pzm;
+    const double pxp = K.pxp, pyp = K.pyp, pzp = K.pzp;
+    const int64_t par = L.pass == 0 ? E.e0 + L.mi : E.g0 + L.mi;
+    if (L.pass == 0 && (f_ph || f_tr) && L.last) { A.el.px[par] = L.px; A.el.py[par] = L.py; A.el.pz[par] = L.pz; }
+    // slots in (pass, pair) order: the rank of the lane's key among the
+    // lanes with a product of the kind
     const unsigned long long b_ph = __ballot(f_ph), b_tr = __ballot(f_tr), b_bh = __ballot(f_bh);
-    const unsigned long long below = (1ull << lane) - 1ull;
     const int n_ph = __popcll(b_ph), n_tr = __popcll(b_tr), n_bh = __popcll(b_bh);
+    const uint32_t key = ((uint32_t)L.pass << 16) | (uint32_t)L.j;
+    const int r_ph = key_rank(b_ph, key), r_tr = key_rank(b_tr, key), r_bh = key_rank(b_bh, key);
     // with every photon staged the converted ones are removed beside
     // this: the new photons go straight to their final slots
     const int shift = staged_all ? n_conv : 0;
     if (f_ph) {
-        const int slot = E.Ng0 + __popcll(b_ph & below);
+        const int slot = E.Ng0 + r_ph;
         if (slot < E.cap_ph) {
             const int64_t at = E.g0 + slot - shift;
             A.ph.px[at] = kx; A.ph.py[at] = ky; A.ph.pz[at] = kz; A.ph.w[at] = L.Wm;
@@ -2257,7 +2449,7 @@ __device__ __forceinline__ void ev_apply(const StepArgs& A, const TabView<R>& T,
         } else t.drop_ph++;
     }
     if (f_tr || f_bh) {
-        const int o = f_tr ? __popcll(b_tr & below) : n_tr + __popcll(b_bh & below);
+        const int o = f_tr ? r_tr : n_tr + r_bh;
         if (E.cnt_ne0 + o < E.cap_ne) {
             const int64_t at = E.ne0 + E.cnt_ne0 + o;
             A.ne.px[at] = pxm; A.ne.py[at] = pym; A.ne.pz[at] = pzm; A.ne.w[at] = L.Wm;
@@ -2276,8 +2468,9 @@ __device__ __forceinline__ void ev_apply(const StepArgs& A, const TabView<R>& T,
     // one product of a kind), and only lanes with an event carry
     // energies and weights, which are added lane by lane in pair order.
     const auto count = [](long long v) { return (long long)__popcll(__ballot(v != 0)); };
-    const long long iv[9] = {count(t.ev_br), count(t.ev_tr), count(t.ev_bh), count(t.near_br), count(t.near_tr),
-                             count(t.near_bh), count(t.drop_ph), count(t.drop_el), count(t.drop_po)};
+    const long long iv[9] = {count(t.ev_br), count(t.ev_tr), count(t.ev_bh), count(t.near_br) + X.near_br,
+                             count(t.near_tr) + X.near_tr, count(t.near_bh) + X.near_bh, count(t.drop_ph), count(t.drop_el),
+                             count(t.drop_po)};
     double dv[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (unsigned long long m = __ballot(f_ph || f_tr || f_bh); m; m &= m - 1ull) {
         const int e = __ffsll((long long)m) - 1;
@@ -2290,6 +2483,7 @@ __device__ __forceinline__ void ev_apply(const StepArgs& A, const TabView<R>& T,
         ti[CMC_I_EV_BR] = iv[0]; ti[CMC_I_EV_TR] = iv[1]; ti[CMC_I_EV_BH] = iv[2];
         ti[CMC_I_NEAR_BR] = iv[3]; ti[CMC_I_NEAR_TR] = iv[4]; ti[CMC_I_NEAR_BH] = iv[5];
         ti[CMC_I_DROP_PH] = iv[6]; ti[CMC_I_DROP_EL] = iv[7]; ti[CMC_I_DROP_PO] = iv[8];
+        if (X.bh_unpaired) ti[CMC_I_PAIRS_BH] -= X.bh_unpaired;
         double* td = A.td + E.c * CMC_ND + CMC_D_E_BR;
         for (int q = 0; q < 8; ++q) td[q] = dv[q];
         if (A.ph.count && (!n_bh || staged_all)) A.ph.count[E.c] = ph_count;
@@ -2370,14 +2564,16 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
         // Wavefront 0 settles the open pairs; its lanes keep the pair's
         // particle, ion and FP64 lookup for the sampling after the barrier.
         EvLane<R> L{};
+        ChainTally X{};
         // with every live photon staged, the survivors of a conversion are
         // moved by wavefronts 1-3 while wavefront 0 samples the events
         const bool staged_all = n_st == Ng0;
         if (wv == 0 && !slow) {
             L = ev_settle<R>(A, T, T64, rng, E, rec, rej);
-            // an event on a particle used by a later pair of its pass: the
-            // cell is redone by the sequential step below
-            if (__ballot(L.kind != 0 && L.reused) != 0ull) {
+            // events on particles that pair again later: resolved in order,
+            // or (when that cannot be done here) the cell is redone by the
+            // sequential step below
+            if (!ev_resolve<R>(A, T, T64, rng, E, L, rej, X)) {
                 if (lane == 0) ctl[0] = 1;
             } else {
                 const int mi = L.mi;
@@ -2417,7 +2613,7 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
             continue;
         }
         const int n_conv = ctl[1];
-        if (wv == 0 && !slow) ev_apply<R>(A, T, T64, rng, E, L, staged_all, n_conv);
+        if (wv == 0 && !slow) ev_apply<R>(A, T, T64, rng, E, L, staged_all, n_conv, X);
         if (wv != 0 && n_conv && staged_all) {
             // each survivor at or after the first converted photon moves down
             // by the converted photons before it, read from LDS: no photon is
@@ -2505,15 +2701,16 @@ __global__ __launch_bounds__(kThreads) void k_events_wave(StepArgs A, TabView<R>
         const EvCell<R> E = ev_cell<R>(A, W, c, lane);
         bool hand = (E.flg & kFlagSlow) != 0 || __ballot(lane < E.nc && ev_pass(E.raw) == 1) != 0ull;
         EvLane<R> L{};
+        ChainTally X{};
         if (!hand) {
             L = ev_settle<R>(A, T, T64, rng, E, rec[wv], rej);
-            hand = __ballot(L.kind != 0 && L.reused) != 0ull;
+            hand = !ev_resolve<R>(A, T, T64, rng, E, L, rej, X);
         }
         if (hand) {
             if (lane == 0) W.list_wg[atomicAdd(&W.counters[kCntWg], 1)] = (int32_t)c;
             continue;
         }
-        ev_apply<R>(A, T, T64, rng, E, L, false, 0);
+        ev_apply<R>(A, T, T64, rng, E, L, false, 0, X);
     }
 }
 

@@ -85,6 +85,33 @@ def test_few_mobile_particles_against_many_ions(precision):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
+def test_events_on_cycled_particles_in_pair_order(precision):
+    """A few electrons and photons per cell, each paired hundreds of times
+    with the ions (one weight, at rest), at a time step that gives about
+    every second electron an event in a step: an electron's later pairs see
+    it as its earlier events left it, a converted photon pairs no more, and
+    the products keep pair order (Sec. III.A), whichever kernel settles
+    them."""
+    rng = np.random.default_rng(83)
+    n = 40
+    ne = rng.integers(6, 15, n)
+    ng = rng.integers(3, 10, n)
+    ni = rng.integers(2500, 4001, n)
+    e_g = 1 + np.exp(rng.uniform(math.log(5.0), math.log(500.0), ne.sum())) / MEC2
+    k = (1.022 + rng.exponential(20.0, ng.sum())) / MEC2
+    wl = W.assemble("cycled-events", 79, 3e-13, 7, 1, rng.uniform(0, 79, n), np.full(n, 5.9e28),
+                    np.exp(rng.uniform(math.log(10), math.log(1e4), n)), e_g, np.repeat(5.9e28 / ni, ne), ne,
+                    k, np.repeat(5.9e28 / ni, ng) * rng.lognormal(0, 1, ng.sum()), ng,
+                    np.repeat(5.9e28 / ni, ni), ni, rng, photon_extra=np.full(n, 128), pair_cap=np.full(n, 128))
+    P = _run(wl, 2, precision=precision)
+    I = P.state.ti.cpu().numpy().sum(0)
+    # the last step: an event for about every second electron (up to 20 in
+    # a cell), and converted photons whose remaining pairs were not tested
+    assert I[3] > int(ne.sum()) // 2
+    assert I[5] > 0 and I[2] < I[0]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
 def test_cycled_species_above_4096(precision):
     """Electrons and photons cycled against more ions, with more than 4096
     of them per cell (the bucket histogram of the sort holds 4096 entries):
