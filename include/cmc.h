@@ -283,12 +283,19 @@ size_t cmc_noalloc_max_cells(void);
  *  CMC_SCHED_HYBRID wavefronts for the cells with at most 1024 particles of
  *                   every species, workgroups for the larger ones (uneven
  *                   cells);
- *  CMC_SCHED_AUTO   GROUP against WAVE (max_per_cell <= 1024) or HYBRID,
- *                   whichever is faster on the first step of a launch shape
- *                   (device, n_cells, max_per_cell, processes, precision):
- *                   that first call times both and waits for the timing;
- *                   under stream capture an untimed shape uses GROUP. */
-enum { CMC_SCHED_AUTO = 0, CMC_SCHED_CELL = 1, CMC_SCHED_GROUP = 2, CMC_SCHED_WAVE = 3, CMC_SCHED_HYBRID = 4 };
+ *  CMC_SCHED_QUEUE  workgroups that take the cells from a work queue, in
+ *                   decreasing order of cost (pairs of both passes), in
+ *                   one persistent launch (as many workgroups as the
+ *                   device holds at once; the batched form for uneven
+ *                   cells);
+ *  CMC_SCHED_AUTO   GROUP, WAVE (max_per_cell <= 1024) or HYBRID, and
+ *                   QUEUE, whichever is fastest on the first step of a
+ *                   launch shape (device, n_cells, max_per_cell, processes,
+ *                   precision): that first call times them and waits for
+ *                   the timing; under stream capture an untimed shape uses
+ *                   GROUP. */
+enum { CMC_SCHED_AUTO = 0, CMC_SCHED_CELL = 1, CMC_SCHED_GROUP = 2, CMC_SCHED_WAVE = 3, CMC_SCHED_HYBRID = 4,
+       CMC_SCHED_QUEUE = 5 };
 
 /* ------------------------------------------------------------------ */
 /* Expected photon energy yield (deterministic): for every cell c,      */
@@ -376,6 +383,42 @@ cmc_status cmc_cross_sections(cmc_tables t, int32_t process, int32_t form, int64
                               const double* Zstar, const double* n_i, const double* T_e,
                               const double* e1, const double* x, double* out, int32_t* status,
                               void* stream);
+
+/* ------------------------------------------------------------------ */
+/* The step after.  Created particles are macro-particles of their      */
+/* species (Sec. III.A): the photons one step creates convert in the    */
+/* next (a step appends them to the photon population itself), and the  */
+/* electrons and positrons of a pair radiate and make pairs in turn (the */
+/* chains of Sec. IV).  These calls move particle records on the device; */
+/* species as for cmc_collide_step, device pointers, caller-owned, all   */
+/* asynchronous on stream.                                               */
+/* ------------------------------------------------------------------ */
+/* Cell by cell, appends the live particles of src after the live ones   */
+/* of dst, in src's order, as far as dst's slab of the cell holds them;  */
+/* sets dst->count, and src->count to 0.  Particles that do not fit are  */
+/* dropped: their number per cell goes to dropped (device [n_cells], or  */
+/* NULL) and CMC_ST_OVERFLOW is OR-ed into *status (device, or NULL).    */
+/* Both species need count, off and w; px, py, pz on both or neither;    */
+/* parent is copied when both have it.  n_cells = 0 does nothing.        */
+/* Errors: CMC_EINVAL (NULL arrays, missing counts), CMC_EDEVICE.        */
+cmc_status cmc_merge_species(int64_t n_cells, const cmc_species* dst, const cmc_species* src,
+                             int64_t* dropped, int32_t* status, void* stream);
+
+/* New slabs for a species: off_new (device [n_cells+1]) gets           */
+/* off_new[0] = 0, off_new[c+1] = off_new[c] + live(c) + headroom,        */
+/* live(c) the cell's live count (count == NULL: its whole slab).  The   */
+/* caller reads off_new[n_cells], allocates the new arrays and calls     */
+/* cmc_rebin_copy.  Errors: CMC_EINVAL (NULL, n_cells < 0, headroom < 0), */
+/* CMC_EDEVICE.                                                          */
+cmc_status cmc_rebin_offsets(int64_t n_cells, const cmc_species* src, int32_t headroom,
+                             int64_t* off_new, void* stream);
+
+/* Copies each cell's live particles of src to the start of its slab in  */
+/* dst (dst->off from cmc_rebin_offsets) and sets dst->count to their    */
+/* number; the rest of each slab is left as it is.  Arrays as for        */
+/* cmc_merge_species (dst->count required).  Errors: CMC_EINVAL,         */
+/* CMC_EDEVICE.                                                          */
+cmc_status cmc_rebin_copy(int64_t n_cells, const cmc_species* src, const cmc_species* dst, void* stream);
 
 #ifdef __cplusplus
 }

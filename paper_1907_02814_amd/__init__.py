@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(HERE, "libcmc.so")
 
 BREMS, BH, TRIDENT = 1, 2, 4
 FP64, FP32 = 0, 1
-SCHED_AUTO, SCHED_CELL, SCHED_GROUP, SCHED_WAVE, SCHED_HYBRID = 0, 1, 2, 3, 4
+SCHED_AUTO, SCHED_CELL, SCHED_GROUP, SCHED_WAVE, SCHED_HYBRID, SCHED_QUEUE = 0, 1, 2, 3, 4, 5
 SCREEN_REDUCED, SCREEN_TFD = 0, 1
 MAX_PER_CELL = 16384
 ST_OVERFLOW, ST_GAMMA_HIGH, ST_BAD_CELL, ST_BAD_WEIGHT, ST_TOO_LARGE, ST_BAD_OFFSETS = 1, 2, 4, 8, 16, 32
@@ -36,7 +36,8 @@ TABLE_NAMES = ["sigR", "skR", "cdfR", "sigU", "skU", "cdfU", "sigN", "skN", "cdf
 EXPORTS = ["cmc_last_error", "cmc_build_tables", "cmc_tables_free", "cmc_tables_size",
            "cmc_tables_export", "cmc_pair_cells", "cmc_collide_step", "cmc_step_workspace_bytes",
            "cmc_expected_yield", "cmc_expected_yield_backward", "cmc_collide_step_noalloc",
-           "cmc_noalloc_max_cells", "cmc_screening_functions", "cmc_cross_sections"]
+           "cmc_noalloc_max_cells", "cmc_screening_functions", "cmc_cross_sections",
+           "cmc_merge_species", "cmc_rebin_offsets", "cmc_rebin_copy"]
 
 _vp = C.c_void_p
 _i64 = C.c_int64
@@ -93,11 +94,15 @@ def _load():
                                      + [C.c_double, C.c_int32, _vp, _vp, _vp, _vp])
     L.cmc_expected_yield_backward.argtypes = ([_vp, _i64] + [_vp] * 4 + [_i64] + [_vp] * 4
                                               + [C.c_double, C.c_int32] + [_vp] * 8 + [_vp, _vp])
+    L.cmc_merge_species.argtypes = [_i64, C.POINTER(_Species), C.POINTER(_Species), _vp, _vp, _vp]
+    L.cmc_rebin_offsets.argtypes = [_i64, C.POINTER(_Species), C.c_int32, _vp, _vp]
+    L.cmc_rebin_copy.argtypes = [_i64, C.POINTER(_Species), C.POINTER(_Species), _vp]
     L.cmc_screening_functions.argtypes = [_vp, C.c_int32, _i64] + [_vp] * 8
     L.cmc_cross_sections.argtypes = [_vp, C.c_int32, C.c_int32, _i64] + [_vp] * 8
     for name in ("cmc_build_tables", "cmc_tables_free", "cmc_tables_export", "cmc_pair_cells",
                  "cmc_collide_step", "cmc_expected_yield", "cmc_expected_yield_backward",
-                 "cmc_collide_step_noalloc", "cmc_screening_functions", "cmc_cross_sections"):
+                 "cmc_collide_step_noalloc", "cmc_screening_functions", "cmc_cross_sections",
+                 "cmc_merge_species", "cmc_rebin_offsets", "cmc_rebin_copy"):
         getattr(L, name).restype = C.c_int
     return L
 
@@ -400,6 +405,42 @@ def expected_yield_backward(tables: Tables, Zstar, n_e, T_e, off, px, py, pz, w,
         _ptr(out["gpx"]), _ptr(out["gpy"]), _ptr(out["gpz"]), _ptr(out["gw"]), _ptr(out["gZstar"]),
         _ptr(out["gn_e"]), _ptr(out["gT_e"]), _ptr(status, "int32"), _stream(stream)),
         "cmc_expected_yield_backward")
+    return out
+
+
+def merge_species(dst: Dict, src: Dict, stream=None, status=None, dropped=False):
+    """Append src's live particles to dst's, cell by cell, as far as dst's
+    slabs hold them; src is emptied (cmc_merge_species).  Both need
+    'count'.  dropped=True: also return the dropped count per cell."""
+    import torch
+    n = dst["off"].numel() - 1
+    _lengths(cells=(n, dst.get("count"), src.get("count")), offsets=(n + 1, src["off"]), status=(1, status))
+    dr = torch.empty(n, dtype=torch.int64, device=dst["off"].device) if dropped else None
+    d, s = _species(dst), _species(src)
+    _check(get_lib().cmc_merge_species(n, C.byref(d), C.byref(s), _ptr(dr), _ptr(status, "int32"),
+                                       _stream(stream)), "cmc_merge_species")
+    return dr
+
+
+def rebin(sp: Dict, headroom: int, stream=None) -> Dict:
+    """A copy of species sp in new slabs on the device: each cell's live
+    particles, then headroom free slots (cmc_rebin_offsets, then
+    cmc_rebin_copy; the new total is read on the host in between)."""
+    import torch
+    n = sp["off"].numel() - 1
+    dev = sp["off"].device
+    off = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    src = _species(sp)
+    _check(get_lib().cmc_rebin_offsets(n, C.byref(src), int(headroom), _ptr(off), _stream(stream)),
+           "cmc_rebin_offsets")
+    m = int(off[-1].item())
+    out = {"off": off, "count": torch.zeros(n, dtype=torch.int32, device=dev)}
+    for k in ("px", "py", "pz", "w"):
+        out[k] = torch.zeros(m, dtype=torch.float64, device=dev) if sp.get(k) is not None else None
+    out["parent"] = (torch.full((m,), -1, dtype=torch.int64, device=dev) if sp.get("parent") is not None
+                     else None)
+    dst = _species(out)
+    _check(get_lib().cmc_rebin_copy(n, C.byref(src), C.byref(dst), _stream(stream)), "cmc_rebin_copy")
     return out
 
 

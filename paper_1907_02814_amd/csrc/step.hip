@@ -791,6 +791,7 @@ enum : int {
     kCntBig0 = 1,    // electron-ion passes deferred to the large-LDS launch (list_big[0])
     kCntBig1 = 2,    // photon-ion passes deferred (list_big[1])
     kCntWg = 3,      // listed cells the wavefront event kernel hands to the workgroup one (list_wg)
+    kCntQ = 4,       // next entry of the work queue to hand out (queue)
     kNumCnt = 8
 };
 
@@ -805,6 +806,7 @@ struct Work {
     int32_t* list_ev;                // cells with open pairs or flagged for the sequential step
     int32_t* list_wg;                // listed cells that need the workgroup event kernel
     int32_t* list_big[2];            // per pass: cells whose pass needs more LDS than the first launch has
+    int32_t* queue;                  // the cells in decreasing order of cost (batched schedule)
     uint64_t* cand;                  // [n_cells][kCandCap] open pairs
 };
 
@@ -812,7 +814,7 @@ __host__ __device__ constexpr size_t align256(size_t b) { return (b + 255) / 256
 
 __host__ __device__ constexpr size_t work_bytes(int64_t n) {
     return align256(sizeof(CellState) * n) + align256(4 * n) + align256(4 * n) +
-           align256(16 * n) + align256(8 * n) + align256(8) + align256(4 * kNumCnt) + 4 * align256(4 * n) +
+           align256(16 * n) + align256(8 * n) + align256(8) + align256(4 * kNumCnt) + 5 * align256(4 * n) +
            align256(8 * (size_t)n * kCandCap);
 }
 
@@ -830,6 +832,7 @@ inline Work carve_work(void* base, int64_t n) {
     w.list_wg = reinterpret_cast<int32_t*>(p); p += align256(4 * n);
     w.list_big[0] = reinterpret_cast<int32_t*>(p); p += align256(4 * n);
     w.list_big[1] = reinterpret_cast<int32_t*>(p); p += align256(4 * n);
+    w.queue = reinterpret_cast<int32_t*>(p); p += align256(4 * n);
     w.cand = reinterpret_cast<uint64_t*>(p);
     return w;
 }
@@ -1972,15 +1975,70 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
     const Rng rng = step_rng(A);
 
     const PassLds L{red4, redu, redi, opn[team], opk[team], opj[team], &nopen[team]};
-    const int64_t n_items = from_list ? (int64_t)W.counters[kPass == 1 ? kCntBig1 : kCntBig0] : A.n_cells;
-    for (int64_t item = (int64_t)blockIdx.x * kTeams + team; item < n_items; item += (int64_t)gridDim.x * kTeams) {
-        const int64_t c = from_list ? (int64_t)W.list_big[kPass == 1 ? 1 : 0][item] : item;
+    __shared__ int qslot[kTeams];
+    // from_list 0: every cell in index order; 1: the deferred list of the
+    // pass; 2: the work queue, one cell per dequeue (a team takes the next
+    // entry when it is done with its cell, so the costliest cells start
+    // first and the rest fill in behind them)
+    const int64_t n_items = from_list == 2 ? A.n_cells
+                          : from_list ? (int64_t)W.counters[kPass == 1 ? kCntBig1 : kCntBig0] : A.n_cells;
+    int64_t item = (int64_t)blockIdx.x * kTeams + team;
+    for (;;) {
+        int64_t c;
+        if (from_list == 2) {
+            if (t == 0) qslot[team] = atomicAdd(&W.counters[kCntQ], 1);
+            Team<kT>::sync();
+            const int q = qslot[team];
+            Team<kT>::sync();
+            if (q >= n_items) break;
+            c = W.queue[q];
+        } else {
+            if (item >= n_items) break;
+            c = from_list ? (int64_t)W.list_big[kPass == 1 ? 1 : 0][item] : item;
+            item += (int64_t)gridDim.x * kTeams;
+        }
         PassCarry carry{0, 0.0};
         if constexpr (kPass != 1)
             pass_cell<R, kT, 0, kMov, false>(A, T, W, cap, filter, fcap, slow_cap, c, M, rng, rej, t, L, carry);
         if constexpr (kPass != 0)
             pass_cell<R, kT, 1, kMov, kPass == 2>(A, T, W, cap, filter, fcap, slow_cap, c, M, rng, rej, t, L, carry);
     }
+}
+
+// The work queue of the batched schedule: the cells in decreasing order
+// of their cost in the pass kernel, the pairs of both passes (max(N_a, N_b)
+// each) plus a fixed per-cell term, counted into buckets of a quarter
+// octave, costliest first.  The order within a bucket is whatever the
+// atomics give: no result depends on which team runs which cell when.
+// One workgroup: the counts are read twice rather than stored.
+constexpr int kQBuckets = 128;
+constexpr int kQThreads = 1024;
+
+__device__ __forceinline__ int queue_bucket(const StepArgs& A, int64_t c) {
+    const int Ne = live(A.el, c), Ng = live(A.ph, c), Ni = live(A.io, c);
+    const bool ei = (A.proc & (CMC_BREMS | CMC_TRIDENT)) && Ne > 0 && Ni > 0;
+    const bool gi = (A.proc & CMC_BH) && Ng > 0 && Ni > 0;
+    const uint32_t cost = 64u + (ei ? (uint32_t)max(Ne, Ni) : 0u) + (gi ? (uint32_t)max(Ng, Ni) : 0u);
+    const int b = 31 - __clz((int)cost);                     // cost >= 64: b >= 6
+    return min(kQBuckets - 1, 4 * b + (int)((cost >> (b - 2)) & 3u));
+}
+
+__global__ __launch_bounds__(kQThreads) void k_queue(StepArgs A, Work W) {
+    __shared__ int hist[kQBuckets];
+    __shared__ int base[kQBuckets];
+    const int t = threadIdx.x;
+    for (int b = t; b < kQBuckets; b += kQThreads) hist[b] = 0;
+    __syncthreads();
+    for (int64_t c = t; c < A.n_cells; c += kQThreads) atomicAdd(&hist[queue_bucket(A, c)], 1);
+    __syncthreads();
+    if (t < kQBuckets) {
+        int s = 0;
+        for (int b = kQBuckets - 1; b > t; --b) s += hist[b];
+        base[t] = s;
+    }
+    __syncthreads();
+    for (int64_t c = t; c < A.n_cells; c += kQThreads) W.queue[atomicAdd(&base[queue_bucket(A, c)], 1)] = (int32_t)c;
+    if (t == 0) W.counters[kCntQ] = 0;
 }
 
 // The values an event kernel reads for a listed cell, in one round of
@@ -2822,6 +2880,26 @@ struct PassLaunch {
     size_t dshm;
 };
 
+// Workgroups of 256 threads of `fn` that the device holds at once (its
+// compute units times the occupancy at dshm bytes of dynamic LDS): the grid
+// of a persistent launch.  Cached per (device, kernel, LDS).
+static unsigned resident_blocks(const void* fn, size_t dshm) {
+    static std::mutex mu;
+    static std::map<std::tuple<int, const void*, size_t>, unsigned> cache;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> g(mu);
+    const auto key = std::make_tuple(dev, fn, dshm);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    int ncu = 0, nb = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) ncu = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 256, dshm) != hipSuccess) nb = 1;
+    const unsigned r = (unsigned)std::max(1, ncu) * (unsigned)std::max(1, nb);
+    cache[key] = r;
+    return r;
+}
+
 template <typename R, int kT, bool kMov>
 static void launch_pass_m(const StepArgs& A, const TabView<R>& T, const Work& W, const PassLaunch& L,
                           hipStream_t st, PassTiming* pt) {
@@ -2829,11 +2907,14 @@ static void launch_pass_m(const StepArgs& A, const TabView<R>& T, const Work& W,
         lds_attr((const void*)kernel, L.dshm, st);
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (pt) { e0 = pt->first ? pt->start : nullptr; e1 = pt->stop; pt->first = false; }
-        hipExtLaunchKernelGGL(kernel, dim3(L.grid), dim3(256), (uint32_t)L.dshm, st, e0, e1, 0u, A, T, W, L.cap,
+        // the work queue is drained by as many workgroups as fit at once
+        const unsigned grid = L.from_list == 2 ? std::min(L.grid, resident_blocks((const void*)kernel, L.dshm)) : L.grid;
+        hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(256), (uint32_t)L.dshm, st, e0, e1, 0u, A, T, W, L.cap,
                               L.filter, L.fcap, L.slow_cap, L.from_list);
     };
+    // (a work queue is drained once: both passes then run in the one launch)
     const bool ei = (A.proc & (CMC_BREMS | CMC_TRIDENT)) != 0, gi = (A.proc & CMC_BH) != 0;
-    if (ei && gi && !L.from_list) {
+    if (ei && gi && L.from_list != 1) {
         launch(k_pass<R, kT, 2, kMov>);
     } else {
         if (ei) launch(k_pass<R, kT, 0, kMov>);
@@ -2866,8 +2947,10 @@ static void launch_team(const StepArgs& A, const cmc_tables_s* t, const Work& W,
 }
 
 // Team shapes: 256 workgroups, 64 wavefronts, kHybrid wavefronts for the
-// cells up to the wavefront capacity and workgroups for the larger ones.
+// cells up to the wavefront capacity and workgroups for the larger ones,
+// kQueue workgroups that take the cells from the cost-sorted work queue.
 constexpr int kHybrid = -1;
+constexpr int kQueue = -2;
 
 static cmc_status launch_passes(const StepArgs& A, const cmc_tables_s* t, const Work& W, bool fp64, int shape,
                                 hipStream_t st, PassTiming* pt = nullptr) {
@@ -2877,6 +2960,11 @@ static cmc_status launch_passes(const StepArgs& A, const cmc_tables_s* t, const 
     if (shape == 64) {
         // wavefront teams only: cells above their capacity take the sequential step
         launch_team(A, t, W, fp64, 64, small, 0, 0, small, 0, 256 * 64, st, pt);
+    } else if (shape == kQueue) {
+        // the cells sorted by cost, then one persistent launch that drains them
+        hipLaunchKernelGGL(k_queue, dim3(1), dim3(kQThreads), 0, st, A, W);
+        launch_team(A, t, W, fp64, 256, main, 0, 0, big, 2, A.n_cells, st, pt);
+        if (big > main) launch_team(A, t, W, fp64, 256, big, 0, 0, big, 1, 1024, st, pt);
     } else {
         if (shape == kHybrid) {
             launch_team(A, t, W, fp64, 64, small, 1, small, big, 0, 256 * 64, st, pt);
@@ -2934,7 +3022,7 @@ static cmc_status tune_passes(const StepArgs& A, const cmc_tables_s* t, const Wo
     best = 256;
     cmc_status rc = CMC_OK;
     const int other = A.maxn <= team_cap(64, A.maxn, fp64) ? 64 : kHybrid;
-    for (int team : {256, other}) {
+    for (int team : {256, other, kQueue}) {
         if ((rc = launch_passes(A, t, W, fp64, team, st)) != CMC_OK) break;   // warm-up
         (void)hipEventRecord(e0, st);
         for (int r = 0; r < 3 && rc == CMC_OK; ++r) rc = launch_passes(A, t, W, fp64, team, st);
@@ -2980,7 +3068,7 @@ static cmc_status collide_step_impl(const char* who, cmc_tables t, const cmc_cel
     CMC_REQUIRE((P->processes & ~7u) == 0, CMC_EINVAL, "%s: unknown process bits", who);
     CMC_REQUIRE(P->precision == CMC_FP64 || P->precision == CMC_FP32, CMC_EINVAL,
                 "%s: unknown precision %d", who, P->precision);
-    CMC_REQUIRE(P->schedule >= 0 && P->schedule <= 4, CMC_EINVAL, "%s: unknown schedule", who);
+    CMC_REQUIRE(P->schedule >= 0 && P->schedule <= 5, CMC_EINVAL, "%s: unknown schedule", who);
     CMC_REQUIRE(P->max_per_cell >= 1 && P->max_per_cell <= CMC_MAX_PER_CELL, CMC_ERANGE,
                 "%s: max_per_cell = %d outside [1, %d]", who, P->max_per_cell, CMC_MAX_PER_CELL);
     CMC_REQUIRE(P->near_rel >= 0.0 && P->near_rel <= 1.0, CMC_EINVAL, "%s: near_rel outside [0, 1]", who);
@@ -3034,7 +3122,9 @@ static cmc_status collide_step_impl(const char* who, cmc_tables t, const cmc_cel
                            0, st, A.Zs, A.ni, A.Te, A.n_cells, (double)t->Z, t->ax, W, A.ti, A.td, A.status,
                            P->step_counter, P->step, advance);
     };
-    int team = P->schedule == CMC_SCHED_WAVE ? 64 : (P->schedule == CMC_SCHED_HYBRID ? kHybrid : 256);
+    int team = P->schedule == CMC_SCHED_WAVE ? 64
+             : P->schedule == CMC_SCHED_HYBRID ? kHybrid
+             : P->schedule == CMC_SCHED_QUEUE ? kQueue : 256;
     bool tuned = P->schedule != CMC_SCHED_AUTO;
     TuneKey key{};
     if (!tuned) {

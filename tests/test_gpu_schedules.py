@@ -1,8 +1,9 @@
 """Schedules and graph replay of cmc_collide_step.
 
-- Workgroup and wavefront teams, and the hybrid of both, give bit-identical
-  results: the densities and n_ab are summed in one canonical order
-  whatever the team shape.
+- Workgroup and wavefront teams, the hybrid of both, and workgroups taking
+  the cells from the cost-sorted work queue give bit-identical results: the
+  densities and n_ab are summed in one canonical order whatever the team
+  shape, and every draw is keyed by where it is used.
 - The sequential schedule (one workgroup per cell, pairs in order) gives the
   same events, counts and live slots; floating-point values agree to rounding
   (another kernel may contract a * b + c into a fused multiply-add
@@ -56,7 +57,8 @@ def _snap(g, st):
 
 @pytest.mark.parametrize("precision,other,hi,moving", [(0, "WAVE", 480, False), (1, "WAVE", 480, False),
                                                        (1, "HYBRID", 3000, False), (0, "HYBRID", 3000, True),
-                                                       (1, "WAVE", 480, "weights")])
+                                                       (1, "WAVE", 480, "weights"), (0, "QUEUE", 3000, False),
+                                                       (1, "QUEUE", 3000, "weights"), (1, "QUEUE", 3000, True)])
 def test_team_shapes_bit_identical(precision, other, hi, moving):
     import paper_1907_02814_amd as cmc
     wl = W.cfg3(np.random.default_rng(21), n_cells=128, dt=2e-13, lo=1, hi=hi)
@@ -98,12 +100,15 @@ def test_sequential_schedule_agrees(precision, moving):
     assert A["ti"][:, 3:6].sum() > 50
 
 
-def test_graph_replay_matches_eager_steps():
+@pytest.mark.parametrize("schedule", ["AUTO", "QUEUE"])
+def test_graph_replay_matches_eager_steps(schedule):
+    """(the work queue is rebuilt and drained inside the captured step)"""
     import torch
     import paper_1907_02814_amd as cmc
     wl = W.cfg3(np.random.default_rng(23), n_cells=96, dt=2e-13, lo=1, hi=1200)
-    ge, se = _state(wl, cmc.SCHED_AUTO, cmc.FP32)
-    gg, sg = _state(wl, cmc.SCHED_AUTO, cmc.FP32)
+    sched = getattr(cmc, "SCHED_" + schedule)
+    ge, se = _state(wl, sched, cmc.FP32)
+    gg, sg = _state(wl, sched, cmc.FP32)
     se.step(0)
     sg.step(0)
     graph, counter = sg.graph(1)
