@@ -1629,3 +1629,59 @@ int or_expected_yield_backward(const or_tables* t, int64_t n_cells, const double
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* The step after.  Created particles are macro-particles of their     */
+/* species (Sec. III.A): the photons a step creates convert in the     */
+/* next one, and the electrons and positrons of a pair radiate and make */
+/* pairs in turn (the chains of Sec. IV).  Merging appends a product    */
+/* buffer to its population; rebinning gives a population new slabs.   */
+/* Plain per-cell loops.                                                */
+/* ------------------------------------------------------------------ */
+static int32_t or_live(const or_species* s, int64_t c)
+{
+    int64_t cap = s->off[c + 1] - s->off[c];
+    if (!s->count) return (int32_t)cap;
+    int64_t n = s->count[c];
+    if (n < 0) n = 0;
+    return (int32_t)(n < cap ? n : cap);
+}
+
+void or_merge_species(int64_t n_cells, or_species* dst, or_species* src, int64_t* dropped)
+{
+    for (int64_t c = 0; c < n_cells; c++) {
+        int32_t nd = or_live(dst, c), ns = or_live(src, c);
+        int64_t cap = dst->off[c + 1] - dst->off[c];
+        int64_t room = cap - nd;
+        int32_t nk = (int32_t)(ns < room ? ns : room);
+        for (int32_t i = 0; i < nk; i++) {
+            int64_t a = src->off[c] + i, b = dst->off[c] + nd + i;
+            dst->px[b] = src->px[a]; dst->py[b] = src->py[a]; dst->pz[b] = src->pz[a];
+            dst->w[b] = src->w[a];
+            if (dst->parent && src->parent) dst->parent[b] = src->parent[a];
+        }
+        dst->count[c] = nd + nk;
+        src->count[c] = 0;
+        if (dropped) dropped[c] = ns - nk;
+    }
+}
+
+void or_rebin_offsets(int64_t n_cells, const or_species* s, int32_t headroom, int64_t* off_new)
+{
+    off_new[0] = 0;
+    for (int64_t c = 0; c < n_cells; c++) off_new[c + 1] = off_new[c] + or_live(s, c) + headroom;
+}
+
+void or_rebin_copy(int64_t n_cells, const or_species* s, or_species* d)
+{
+    for (int64_t c = 0; c < n_cells; c++) {
+        int32_t n = or_live(s, c);
+        for (int32_t i = 0; i < n; i++) {
+            int64_t a = s->off[c] + i, b = d->off[c] + i;
+            d->px[b] = s->px[a]; d->py[b] = s->py[a]; d->pz[b] = s->pz[a]; d->w[b] = s->w[a];
+            if (d->parent && s->parent) d->parent[b] = s->parent[a];
+        }
+        d->count[c] = n;
+    }
+}
+

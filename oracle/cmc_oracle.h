@@ -136,6 +136,12 @@ int or_expected_yield_backward(const or_tables* t, int64_t n_cells, const double
                       double* gabs /* [n_cells][3] sum of |terms| of each cell gradient, or NULL */,
                       int nthreads);
 
+/* The step after: append src to dst cell by cell (dropped per cell, may be
+ * NULL; src emptied), and new slabs with headroom for a species. */
+void or_merge_species(int64_t n_cells, or_species* dst, or_species* src, int64_t* dropped);
+void or_rebin_offsets(int64_t n_cells, const or_species* s, int32_t headroom, int64_t* off_new);
+void or_rebin_copy(int64_t n_cells, const or_species* s, or_species* d);
+
 #ifdef __cplusplus
 }
 #endif

@@ -76,6 +76,9 @@ def lib():
         L.or_philox.argtypes = [_u32p, _u32p, _u32p]
         L.or_u53.argtypes = [u32, u32]; L.or_u53.restype = d
         L.or_accept_uniforms.argtypes = [u64, u64, u32, u32, u32, u32, _dp, _dp]
+        L.or_merge_species.argtypes = [i64, C.POINTER(_Species), C.POINTER(_Species), _i64p]
+        L.or_rebin_offsets.argtypes = [i64, C.POINTER(_Species), C.c_int32, _i64p]
+        L.or_rebin_copy.argtypes = [i64, C.POINTER(_Species), C.POINTER(_Species)]
         L.or_to_ion.argtypes = [_dp, d, _dp, _dp]
         L.or_from_ion.argtypes = [_dp, d, _dp, _dp]
         L.or_lookup.argtypes = [vp, d, d, d, d, C.c_int, _dp]
@@ -363,3 +366,33 @@ def expected_yield_backward(tab, Zs, n_e, T_e, off, px, py, pz, w, dt, gY, nthre
     if scale:
         res["gabs"] = gabs
     return res
+
+
+def merge_species(dst, src):
+    """Append src's live particles to dst's, cell by cell, as far as dst's
+    slabs hold them; src is emptied (the arrays are updated in place).
+    dst and src need live counts.  Returns the dropped count per cell."""
+    n = len(dst["off"]) - 1
+    assert dst.get("count") is not None and src.get("count") is not None
+    dropped = np.zeros(n, dtype=np.int64)
+    d, s_ = _species(dst), _species(src)
+    lib().or_merge_species(n, C.byref(d), C.byref(s_), _p(dropped, _i64p))
+    return dropped
+
+
+def rebin(sp, headroom):
+    """A copy of species sp in new slabs: each cell's live particles, then
+    headroom free slots (zeros)."""
+    n = len(sp["off"]) - 1
+    off = np.zeros(n + 1, dtype=np.int64)
+    src = _species(sp)
+    lib().or_rebin_offsets(n, C.byref(src), int(headroom), _p(off, _i64p))
+    m = int(off[-1])
+    out = {"off": off, "count": np.zeros(n, dtype=np.int32)}
+    for k in ("px", "py", "pz", "w"):
+        out[k] = np.zeros(m) if sp.get(k) is not None else None
+    out["parent"] = np.full(m, -1, dtype=np.int64) if sp.get("parent") is not None else None
+    dst = _species(out)
+    lib().or_rebin_copy(n, C.byref(src), C.byref(dst))
+    return out
+
