@@ -284,10 +284,10 @@ size_t cmc_noalloc_max_cells(void);
  *                   every species, workgroups for the larger ones (uneven
  *                   cells);
  *  CMC_SCHED_QUEUE  workgroups that take the cells from a work queue, in
- *                   decreasing order of cost (pairs of both passes), in
- *                   one persistent launch (as many workgroups as the
- *                   device holds at once; the batched form for uneven
- *                   cells);
+ *                   decreasing order of cost (pairs of both passes): one
+ *                   workgroup per entry, dispatched in queue order as
+ *                   compute units free up, so the costliest cells start
+ *                   first (the batched form for uneven cells);
  *  CMC_SCHED_AUTO   GROUP, WAVE (max_per_cell <= 1024) or HYBRID, and
  *                   QUEUE, whichever is fastest on the first step of a
  *                   launch shape (device, n_cells, max_per_cell, processes,

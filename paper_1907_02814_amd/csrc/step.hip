@@ -791,7 +791,6 @@ enum : int {
     kCntBig0 = 1,    // electron-ion passes deferred to the large-LDS launch (list_big[0])
     kCntBig1 = 2,    // photon-ion passes deferred (list_big[1])
     kCntWg = 3,      // listed cells the wavefront event kernel hands to the workgroup one (list_wg)
-    kCntQ = 4,       // next entry of the work queue to hand out (queue)
     kNumCnt = 8
 };
 
@@ -1975,28 +1974,14 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
     const Rng rng = step_rng(A);
 
     const PassLds L{red4, redu, redi, opn[team], opk[team], opj[team], &nopen[team]};
-    __shared__ int qslot[kTeams];
-    // from_list 0: every cell in index order; 1: the deferred list of the
-    // pass; 2: the work queue, one cell per dequeue (a team takes the next
-    // entry when it is done with its cell, so the costliest cells start
-    // first and the rest fill in behind them)
-    const int64_t n_items = from_list == 2 ? A.n_cells
-                          : from_list ? (int64_t)W.counters[kPass == 1 ? kCntBig1 : kCntBig0] : A.n_cells;
-    int64_t item = (int64_t)blockIdx.x * kTeams + team;
-    for (;;) {
-        int64_t c;
-        if (from_list == 2) {
-            if (t == 0) qslot[team] = atomicAdd(&W.counters[kCntQ], 1);
-            Team<kT>::sync();
-            const int q = qslot[team];
-            Team<kT>::sync();
-            if (q >= n_items) break;
-            c = W.queue[q];
-        } else {
-            if (item >= n_items) break;
-            c = from_list ? (int64_t)W.list_big[kPass == 1 ? 1 : 0][item] : item;
-            item += (int64_t)gridDim.x * kTeams;
-        }
+    // from_list 0: every cell in index order; 1: the pass's deferred list;
+    // 2: the work queue, the cells costliest first (workgroups are
+    // dispatched in index order as compute units free up, so the largest
+    // cells start first and the rest fill in behind them)
+    const int64_t n_items = from_list == 1 ? (int64_t)W.counters[kPass == 1 ? kCntBig1 : kCntBig0] : A.n_cells;
+    for (int64_t item = (int64_t)blockIdx.x * kTeams + team; item < n_items; item += (int64_t)gridDim.x * kTeams) {
+        const int64_t c = from_list == 2 ? (int64_t)W.queue[item]
+                        : from_list ? (int64_t)W.list_big[kPass == 1 ? 1 : 0][item] : item;
         PassCarry carry{0, 0.0};
         if constexpr (kPass != 1)
             pass_cell<R, kT, 0, kMov, false>(A, T, W, cap, filter, fcap, slow_cap, c, M, rng, rej, t, L, carry);
@@ -2038,7 +2023,6 @@ __global__ __launch_bounds__(kQThreads) void k_queue(StepArgs A, Work W) {
     }
     __syncthreads();
     for (int64_t c = t; c < A.n_cells; c += kQThreads) W.queue[atomicAdd(&base[queue_bucket(A, c)], 1)] = (int32_t)c;
-    if (t == 0) W.counters[kCntQ] = 0;
 }
 
 // The values an event kernel reads for a listed cell, in one round of
@@ -2880,26 +2864,6 @@ struct PassLaunch {
     size_t dshm;
 };
 
-// Workgroups of 256 threads of `fn` that the device holds at once (its
-// compute units times the occupancy at dshm bytes of dynamic LDS): the grid
-// of a persistent launch.  Cached per (device, kernel, LDS).
-static unsigned resident_blocks(const void* fn, size_t dshm) {
-    static std::mutex mu;
-    static std::map<std::tuple<int, const void*, size_t>, unsigned> cache;
-    int dev = 0;
-    (void)hipGetDevice(&dev);
-    std::lock_guard<std::mutex> g(mu);
-    const auto key = std::make_tuple(dev, fn, dshm);
-    auto it = cache.find(key);
-    if (it != cache.end()) return it->second;
-    int ncu = 0, nb = 0;
-    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) ncu = 1;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 256, dshm) != hipSuccess) nb = 1;
-    const unsigned r = (unsigned)std::max(1, ncu) * (unsigned)std::max(1, nb);
-    cache[key] = r;
-    return r;
-}
-
 template <typename R, int kT, bool kMov>
 static void launch_pass_m(const StepArgs& A, const TabView<R>& T, const Work& W, const PassLaunch& L,
                           hipStream_t st, PassTiming* pt) {
@@ -2907,12 +2871,9 @@ static void launch_pass_m(const StepArgs& A, const TabView<R>& T, const Work& W,
         lds_attr((const void*)kernel, L.dshm, st);
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (pt) { e0 = pt->first ? pt->start : nullptr; e1 = pt->stop; pt->first = false; }
-        // the work queue is drained by as many workgroups as fit at once
-        const unsigned grid = L.from_list == 2 ? std::min(L.grid, resident_blocks((const void*)kernel, L.dshm)) : L.grid;
-        hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(256), (uint32_t)L.dshm, st, e0, e1, 0u, A, T, W, L.cap,
+        hipExtLaunchKernelGGL(kernel, dim3(L.grid), dim3(256), (uint32_t)L.dshm, st, e0, e1, 0u, A, T, W, L.cap,
                               L.filter, L.fcap, L.slow_cap, L.from_list);
     };
-    // (a work queue is drained once: both passes then run in the one launch)
     const bool ei = (A.proc & (CMC_BREMS | CMC_TRIDENT)) != 0, gi = (A.proc & CMC_BH) != 0;
     if (ei && gi && L.from_list != 1) {
         launch(k_pass<R, kT, 2, kMov>);
@@ -2961,9 +2922,10 @@ static cmc_status launch_passes(const StepArgs& A, const cmc_tables_s* t, const 
         // wavefront teams only: cells above their capacity take the sequential step
         launch_team(A, t, W, fp64, 64, small, 0, 0, small, 0, 256 * 64, st, pt);
     } else if (shape == kQueue) {
-        // the cells sorted by cost, then one persistent launch that drains them
+        // the cells sorted by cost, then one launch of a workgroup per queue
+        // entry (up to 2^20 workgroups; beyond, each strides over the queue)
         hipLaunchKernelGGL(k_queue, dim3(1), dim3(kQThreads), 0, st, A, W);
-        launch_team(A, t, W, fp64, 256, main, 0, 0, big, 2, A.n_cells, st, pt);
+        launch_team(A, t, W, fp64, 256, main, 0, 0, big, 2, (int64_t)1 << 20, st, pt);
         if (big > main) launch_team(A, t, W, fp64, 256, big, 0, 0, big, 1, 1024, st, pt);
     } else {
         if (shape == kHybrid) {
@@ -3031,7 +2993,9 @@ static cmc_status tune_passes(const StepArgs& A, const cmc_tables_s* t, const Wo
         if (hipEventSynchronize(e1) != hipSuccess) { set_error("cmc_collide_step: timing failed"); rc = CMC_EDEVICE; break; }
         float ms = 0.0f;
         (void)hipEventElapsedTime(&ms, e0, e1);
-        if (team == 256 || ms < best_ms) { best_ms = ms; best = team; }
+        // another shape must beat workgroup teams by 3% (timing noise of a
+        // few runs would otherwise pick a slower shape now and then)
+        if (team == 256 || ms < best_ms * (best == 256 ? 0.97f : 1.0f)) { best_ms = ms; best = team; }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
