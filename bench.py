@@ -368,7 +368,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="cfg5", choices=sorted(WORKLOADS))
-    ap.add_argument("--schedule", default="auto", choices=["auto", "group", "wave", "hybrid", "cell", "queue"])
+    ap.add_argument("--schedule", default="auto", choices=["auto", "group", "wave", "hybrid", "cell", "queue", "split"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 plain comparison")
     ap.add_argument("--no-yield", action="store_true", help="skip the expected-yield measurement")
@@ -388,7 +388,8 @@ def main():
     import paper_1907_02814_amd as cmc
     from paper_1907_02814_amd import workloads as W
     sched = {"auto": cmc.SCHED_AUTO, "group": cmc.SCHED_GROUP, "wave": cmc.SCHED_WAVE,
-             "hybrid": cmc.SCHED_HYBRID, "cell": cmc.SCHED_CELL, "queue": cmc.SCHED_QUEUE}[a.schedule]
+             "hybrid": cmc.SCHED_HYBRID, "cell": cmc.SCHED_CELL, "queue": cmc.SCHED_QUEUE,
+             "split": cmc.SCHED_SPLIT}[a.schedule]
     print(f"[bench] {a.workload}", file=sys.stderr, flush=True)
     make = lambda: make_workload(a.workload, W)
     if a.workload == "cfg5":

@@ -288,14 +288,21 @@ size_t cmc_noalloc_max_cells(void);
  *                   workgroup per entry, dispatched in queue order as
  *                   compute units free up, so the costliest cells start
  *                   first (the batched form for uneven cells);
- *  CMC_SCHED_AUTO   GROUP, WAVE (max_per_cell <= 1024) or HYBRID, and
- *                   QUEUE, whichever is fastest on the first step of a
+ *  CMC_SCHED_SPLIT  workgroups for the electron-ion pass, then one
+ *                   wavefront per cell for the photon-ion pass (its order,
+ *                   when it needs one, of up to 256 photons; larger orders
+ *                   take a workgroup): for a few photons cycled against
+ *                   many ions, as in a foil's Bremsstrahlung -> Bethe-
+ *                   Heitler chain;
+ *  CMC_SCHED_AUTO   GROUP, WAVE (max_per_cell <= 1024) or HYBRID, QUEUE
+ *                   and, with both passes on, SPLIT, whichever is fastest
+ *                   on the first step of a
  *                   launch shape (device, n_cells, max_per_cell, processes,
  *                   precision): that first call times them and waits for
  *                   the timing; under stream capture an untimed shape uses
  *                   GROUP. */
 enum { CMC_SCHED_AUTO = 0, CMC_SCHED_CELL = 1, CMC_SCHED_GROUP = 2, CMC_SCHED_WAVE = 3, CMC_SCHED_HYBRID = 4,
-       CMC_SCHED_QUEUE = 5 };
+       CMC_SCHED_QUEUE = 5, CMC_SCHED_SPLIT = 6 };
 
 /* ------------------------------------------------------------------ */
 /* Expected photon energy yield (deterministic): for every cell c,      */

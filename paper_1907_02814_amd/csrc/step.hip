@@ -775,8 +775,10 @@ constexpr int kStagePh = 1024;   // photons the event kernel stages in LDS per c
 // per-cell flags of a step: kFlagWeightsOk, set by the electron-ion pass,
 // says every weight of the cell is valid and its ion sum is in ionsum
 // (kFlagIonsSame: the ions share one weight), so that the photon-ion pass
-// reads neither the ions' nor the electrons' weights again
-enum : int32_t { kFlagSlow = 1, kFlagListed = 2, kFlagBig0 = 4, kFlagBig1 = 8, kFlagWeightsOk = 16, kFlagIonsSame = 32 };
+// reads neither the ions' nor the electrons' weights again; kFlagDone0:
+// the stream kernel has run the cell's electron-ion pass
+enum : int32_t { kFlagSlow = 1, kFlagListed = 2, kFlagBig0 = 4, kFlagBig1 = 8, kFlagWeightsOk = 16, kFlagIonsSame = 32,
+                 kFlagDone0 = 64 };
 enum : uint32_t { kEvBr = 1, kEvTrPending = 2, kEvTr = 4, kEvBh = 8 };
 
 struct CellState {
@@ -1259,6 +1261,10 @@ __device__ __forceinline__ int mod_small(int j, int n, float rn) {
 
 // per-team LDS of the pass kernel
 constexpr int kSliceMax = 168;   // >= kSliceBrems, kSliceBH
+// the stream kernel: electrons per cell it takes at most, workgroups per CU
+// (the FP64 form and Trident need more registers)
+constexpr int kStreamCap = 4096;
+template <typename R, bool kTri> constexpr int kStreamWgs = sizeof(R) == 4 && !kTri ? 6 : 4;
 
 // The team's region holds the arrays of the rank sort or, in the direct
 // form of a cycled mobile species, the selection scratch (kSelBytes); the
@@ -1370,13 +1376,18 @@ __device__ __forceinline__ void pass_cell(const StepArgs& A, const TabView<R>& T
     // offsets and live counts of the three species, its global index
     const uint32_t cell = cell_word(A.cid, c);
     const int32_t cstat = W.cs[c].status;
-    const int32_t cflags = kPass == 1 ? (kFused ? carry.flags : W.flags[c]) : 0;
+    const int32_t cflags = (kPass == 0 || !kFused) ? W.flags[c] : carry.flags;
     const CellTab<R> ct_c = pick<R>(W.cs[c]);
     const int64_t eo0 = A.el.off[c], eo1 = A.el.off[c + 1], go0 = A.ph.off[c], go1 = A.ph.off[c + 1];
     const int64_t io0 = A.io.off[c], io1 = A.io.off[c + 1];
     const int ecn = A.el.count ? A.el.count[c] : 0x7FFFFFFF, gcn = A.ph.count ? A.ph.count[c] : 0x7FFFFFFF;
     const int icn = A.io.count ? A.io.count[c] : 0x7FFFFFFF;
     if (cstat) return;                                // invalid cell (flagged by k_cell_state)
+    if (kPass == 0 && (cflags & kFlagDone0)) {
+        // done by the stream kernel, whose results the photon-ion pass takes
+        carry = PassCarry{cflags & (kFlagWeightsOk | kFlagIonsSame), W.ionsum[c]};
+        return;
+    }
     const int Ne = max(0, min(ecn, (int)(eo1 - eo0))), Ng = max(0, min(gcn, (int)(go1 - go0)));
     const int Ni = max(0, min(icn, (int)(io1 - io0)));
     // size classes of the hybrid schedule: filter 1 takes the cells up
@@ -1932,6 +1943,164 @@ __device__ __forceinline__ void pass_cell(const StepArgs& A, const TabView<R>& T
     }
     if (team_any<kT>(high != 0, L.redi) && t == 0) atomicOr(A.status, CMC_ST_GAMMA_HIGH);
     Team<kT>::sync();   // LDS of this cell is free
+}
+
+// The electron-ion pass of the cells whose ions are at rest and whose
+// electrons each pair once (N_i <= N_e), above the direct form's size and up
+// to the stream capacity `scap` (the LDS of one sigma v factor per electron,
+// two with Trident): nothing depends on an order, and a cell is one walk
+// over its records.  Every electron's momenta and weight and every ion's
+// weight are read once, two records ahead of their use, while the walk
+// forms each electron's FP32 test factor sigma v into LDS and the canonical
+// per-thread parts of the densities and of n_ab (the order of canon_part2).
+// After the team reduction the pairs are tested from LDS with the pass
+// kernel's bound, and the open pairs are listed as it lists them.  A cell
+// done here is flagged kFlagDone0; cells of unequal ion weights, and all
+// others, are left to the pass kernel.  One workgroup per cell, walking the
+// cells in index order or (from_list 2) the work queue.
+template <typename R, bool kTri>
+__global__ __launch_bounds__(256, (kStreamWgs<R, kTri>)) void k_stream(StepArgs A, TabView<R> T, Work W, int scap, int from_list) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ R slice[kSliceMax];
+    __shared__ double red4[kWaves * 4];
+    __shared__ int redi[kWaves];
+    __shared__ uint32_t opn[kCandCap], opk[kCandCap], opj[kCandCap];
+    __shared__ int nopen;
+    const int t = (int)threadIdx.x;
+    const double rej = 2.0 * (1.0 + A.near_rel);
+    const Rng rng = step_rng(A);
+    constexpr bool tri = kTri;
+    const bool brm = (A.proc & CMC_BREMS) != 0;
+    float* sv = reinterpret_cast<float*>(smem_raw);   // sigma v of electron q (< 0: no test)
+    float* svt = sv + scap;                           // Trident's
+    for (int64_t item = blockIdx.x; item < A.n_cells; item += gridDim.x) {
+        const int64_t c = from_list == 2 ? (int64_t)W.queue[item] : item;
+        const uint32_t cell = cell_word(A.cid, c);
+        const int32_t cstat = W.cs[c].status;
+        const CellTab<R> ct = pick<R>(W.cs[c]);
+        const int64_t e0 = A.el.off[c], eo1 = A.el.off[c + 1], g0 = A.ph.off[c], go1 = A.ph.off[c + 1];
+        const int64_t i0 = A.io.off[c], io1 = A.io.off[c + 1];
+        const int ecn = A.el.count ? A.el.count[c] : 0x7FFFFFFF, gcn = A.ph.count ? A.ph.count[c] : 0x7FFFFFFF;
+        const int icn = A.io.count ? A.io.count[c] : 0x7FFFFFFF;
+        const int Ne = max(0, min(ecn, (int)(eo1 - e0))), Ng = max(0, min(gcn, (int)(go1 - g0)));
+        const int Ni = max(0, min(icn, (int)(io1 - i0)));
+        if (cstat || Ni == 0 || Ne < Ni || Ne <= 1024 || Ne > scap || Ne > A.maxn || Ng > A.maxn) continue;
+        const int N = Ne, U = (N + 255) / 256;
+        const double* wm = A.el.w + e0;
+        const double* wion = A.io.w + i0;
+        const double* wo = A.ph.w + g0;
+        struct Rec { double x, y, z, w, wi; };
+        const auto load = [&](int u) {
+            const int q = min(t + 256 * u, N - 1), qi = min(t + 256 * u, Ni - 1);
+            return Rec{A.el.px[e0 + q], A.el.py[e0 + q], A.el.pz[e0 + q], wm[q], wion[qi]};
+        };
+        // the first two records are in flight while the slice is staged
+        Rec r0 = load(0), r1 = load(1);
+        if (brm)
+            for (int i = t; i < kSliceBrems; i += 256) slice[i] = slice_node_brems<R>(T, ct, i);
+        const double w0 = wion[0];
+        if (t == 0) nopen = 0;
+        __syncthreads();
+        double sa = 0.0, sb = 0.0, si = 0.0;     // n_e, n_ab and n_i: canonical per-thread parts
+        int fl = 0;                              // 1 bad weight, 2 ions of unequal weight, 4 above the tables
+#pragma unroll 1
+        for (int u = 0; u < U; ++u) {
+            const Rec cur = r0;
+            r0 = r1;
+            if (u + 2 < U) r1 = load(u + 2);
+            const int q = t + 256 * u;
+            if (q < N) {
+                fl |= (!(cur.w >= 0.0) || !isfinite(cur.w)) ? 1 : 0;
+                sa += cur.w;
+                sb += cur.w < w0 ? cur.w : w0;
+                const Elec<R> el = electron_p<R>(cur.x, cur.y, cur.z);
+                float s1 = -1.0f;
+                if (brm) {
+                    bool hi;
+                    const R sig = brems_sig_slice<R>(T, slice, el.g, el.gm1, hi);
+                    fl |= hi ? 4 : 0;
+                    if (sig > (R)0) s1 = (float)sig * (float)el.vrel;
+                }
+                sv[q] = s1;
+                if (tri) {
+                    const R st = (R)phys::trident_sigma(T.Z, (double)el.g);
+                    svt[q] = st > (R)0 ? (float)st * (float)el.vrel : -1.0f;
+                }
+            }
+            if (q < Ni) {
+                fl |= (!(cur.wi >= 0.0) || !isfinite(cur.wi)) ? 1 : 0;
+                fl |= cur.wi != w0 ? 2 : 0;
+                si += cur.wi;
+            }
+        }
+        double v4[4];
+        v4[0] = wave_sum(sa);
+        v4[1] = wave_sum(sb);
+        v4[2] = wave_sum(si);
+        {
+            int bad = 0;
+            v4[3] = canon_part<256>(Ng, [&](int q) { const double w = wo[q]; bad |= !(w >= 0.0) || !isfinite(w); return w; });
+            fl |= bad ? 1 : 0;
+        }
+        team_reduce4_bits<256>(v4, fl, red4, redi);   // its barriers also publish sv
+        if (fl & 2) continue;                        // the ordered form, in the pass kernel
+        if (fl & 1) {
+            // bad weights: flagged, and the pass kernel skips the cell
+            if (t == 0) {
+                atomicOr(A.status, CMC_ST_BAD_WEIGHT);
+                atomicOr(&W.flags[c], kFlagDone0);
+            }
+            continue;
+        }
+        const double nab = v4[1];
+        if (nab > 0.0) {
+            const double coef = v4[0] * v4[2] / nab;
+            const float kx = (float)(coef * A.dt * rej * 16777216.0);
+            // pair q = t + 256 u: U1's upper bits are word u & 3 of the draw
+            // hi_group(q) = (u >> 2) << 8 | t, one per four pairs
+            U4 hb{0u, 0u, 0u, 0u}, ht{0u, 0u, 0u, 0u};
+#pragma unroll 1
+            for (int u = 0; u < U; ++u) {
+                const int q = t + 256 * u;
+                if ((u & 3) == 0) {
+                    if (brm) hb = rng.draw(hi_group((uint32_t)q), cell, kTagHiBr);
+                    if (tri) ht = rng.draw(hi_group((uint32_t)q), cell, kTagHiTr);
+                }
+                if (q >= N) continue;
+                uint32_t bits = 0;
+                const float s1 = sv[q];
+                if (s1 > 0.0f && bound24(hi_word(hb, (uint32_t)u & 3u), kx * s1)) bits = 1u;
+                if (tri && !bits) {
+                    const float s2 = svt[q];
+                    if (s2 > 0.0f && bound24(hi_word(ht, (uint32_t)u & 3u), kx * s2)) bits = 2u;
+                }
+                if (bits) {
+                    const int o = atomicAdd(&nopen, 1);
+                    if (o < kCandCap) opn[o] = (uint32_t)q | (bits << 16);
+                }
+            }
+            __syncthreads();
+            const int n_open = nopen;
+            if (n_open > kCandCap) {
+                if (t == 0) mark_slow(W, c);
+            } else if (n_open > 0) {
+                // pair index of an open pair: the rank of its electron's key
+                rank_open<256>(N, cell, kTagKeyE, rng, opn, opk, opj, n_open);
+                if (t < n_open)
+                    push_cand(W, c, ev_pack(0, (int)opj[t], (int)(opn[t] & 0xFFFFu), 0, opn[t] >> 16));
+            }
+            if (t == 0) W.coef[c * 2] = coef;
+        }
+        if (t == 0) {
+            A.ti[c * CMC_NI + CMC_I_PAIRS_BR] = (nab > 0.0 && brm) ? N : 0;
+            A.ti[c * CMC_NI + CMC_I_PAIRS_TR] = (nab > 0.0 && tri) ? N : 0;
+            A.td[c * CMC_ND + CMC_D_NAB_EI] = nab;
+            if (nab > 0.0 && (fl & 4)) atomicOr(A.status, CMC_ST_GAMMA_HIGH);
+            W.ionsum[c] = v4[2];
+            atomicOr(&W.flags[c], kFlagWeightsOk | kFlagIonsSame | kFlagDone0);
+        }
+        __syncthreads();   // LDS of this cell is free
+    }
 }
 
 // One pass of pair tests over all cells from the particles as they are at
@@ -2860,6 +3029,7 @@ struct PassTiming {
 // over the passes a first launch deferred (from_list)
 struct PassLaunch {
     int cap, filter, fcap, slow_cap, from_list;
+    int passes;         // bit 0: the electron-ion pass, bit 1: the photon-ion pass
     unsigned grid;
     size_t dshm;
 };
@@ -2874,7 +3044,8 @@ static void launch_pass_m(const StepArgs& A, const TabView<R>& T, const Work& W,
         hipExtLaunchKernelGGL(kernel, dim3(L.grid), dim3(256), (uint32_t)L.dshm, st, e0, e1, 0u, A, T, W, L.cap,
                               L.filter, L.fcap, L.slow_cap, L.from_list);
     };
-    const bool ei = (A.proc & (CMC_BREMS | CMC_TRIDENT)) != 0, gi = (A.proc & CMC_BH) != 0;
+    const bool ei = (L.passes & 1) && (A.proc & (CMC_BREMS | CMC_TRIDENT)) != 0;
+    const bool gi = (L.passes & 2) && (A.proc & CMC_BH) != 0;
     if (ei && gi && L.from_list != 1) {
         launch(k_pass<R, kT, 2, kMov>);
     } else {
@@ -2892,9 +3063,10 @@ static void launch_pass_t(const StepArgs& A, const TabView<R>& T, const Work& W,
 
 static void launch_team(const StepArgs& A, const cmc_tables_s* t, const Work& W, bool fp64, int team, int cap,
                         int filter, int fcap, int slow_cap, int from_list, int64_t max_blocks, hipStream_t st,
-                        PassTiming* pt) {
+                        PassTiming* pt, int passes = 3) {
     PassLaunch L;
     L.cap = cap; L.filter = filter; L.fcap = fcap; L.slow_cap = slow_cap; L.from_list = from_list;
+    L.passes = passes;
     L.dshm = ((team_bytes(cap, fp64 ? 8 : 4, team) + 15) / 16 * 16) * (size_t)(256 / team);
     const int64_t units = team == 64 ? (A.n_cells + 3) / 4 : A.n_cells;
     L.grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(units, max_blocks));
@@ -2909,9 +3081,39 @@ static void launch_team(const StepArgs& A, const cmc_tables_s* t, const Work& W,
 
 // Team shapes: 256 workgroups, 64 wavefronts, kHybrid wavefronts for the
 // cells up to the wavefront capacity and workgroups for the larger ones,
-// kQueue workgroups that take the cells from the cost-sorted work queue.
+// kQueue workgroups that take the cells from the cost-sorted work queue,
+// kSplit workgroups for the electron-ion pass and then wavefronts for the
+// photon-ion pass (each wavefront's LDS sized for kSplitCap photons: a few
+// photons cycled against many ions need no more, and small teams keep many
+// cells in flight; larger orders are deferred to the large-LDS launch).
 constexpr int kHybrid = -1;
 constexpr int kQueue = -2;
+constexpr int kSplit = -3;
+constexpr int kSplitCap = 256;
+
+// the stream kernel over all cells (cells in index order, or the work
+// queue), before the pass kernels: ions at rest and an electron-ion process
+template <typename R>
+static void launch_stream_r(const StepArgs& A, const TabView<R>& T, const Work& W, int scap, int from_list,
+                            hipStream_t st, PassTiming* pt) {
+    const size_t dshm = (size_t)scap * ((A.proc & CMC_TRIDENT) ? 8 : 4);
+    const auto kernel = (A.proc & CMC_TRIDENT) ? k_stream<R, true> : k_stream<R, false>;
+    lds_attr((const void*)kernel, dshm, st);
+    const int64_t cap_blocks = from_list == 2 ? ((int64_t)1 << 20) : 256 * 64;
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(A.n_cells, cap_blocks));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (pt) { e0 = pt->first ? pt->start : nullptr; e1 = pt->stop; pt->first = false; }
+    hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(256), (uint32_t)dshm, st, e0, e1, 0u, A, T, W, scap, from_list);
+}
+
+static void launch_stream(const StepArgs& A, const cmc_tables_s* t, const Work& W, bool fp64, int big, int from_list,
+                          hipStream_t st, PassTiming* pt) {
+    if (A.io.px || !(A.proc & (CMC_BREMS | CMC_TRIDENT))) return;
+    const int scap = std::min(std::min(kStreamCap, A.maxn), big);
+    if (scap <= 1024) return;
+    if (fp64) launch_stream_r<double>(A, view64(t), W, scap, from_list, st, pt);
+    else launch_stream_r<float>(A, view32(t), W, scap, from_list, st, pt);
+}
 
 static cmc_status launch_passes(const StepArgs& A, const cmc_tables_s* t, const Work& W, bool fp64, int shape,
                                 hipStream_t st, PassTiming* pt = nullptr) {
@@ -2921,13 +3123,26 @@ static cmc_status launch_passes(const StepArgs& A, const cmc_tables_s* t, const 
     if (shape == 64) {
         // wavefront teams only: cells above their capacity take the sequential step
         launch_team(A, t, W, fp64, 64, small, 0, 0, small, 0, 256 * 64, st, pt);
+    } else if (shape == kSplit) {
+        // the electron-ion passes the stream kernel takes, then wavefront
+        // teams for the rest of both passes
+        // teams for the rest, one launch per pass (the fused wavefront
+        // kernel holds too many registers for the occupancy the photon-ion
+        // pass needs)
+        const int sc = std::min(big, kSplitCap);
+        launch_stream(A, t, W, fp64, big, 0, st, pt);
+        launch_team(A, t, W, fp64, 64, sc, 0, 0, big, 0, 256 * 64, st, pt, 1);
+        launch_team(A, t, W, fp64, 64, sc, 0, 0, big, 0, 256 * 64, st, pt, 2);
+        if (big > sc) launch_team(A, t, W, fp64, 256, big, 0, 0, big, 1, 1024, st, pt);
     } else if (shape == kQueue) {
         // the cells sorted by cost, then one launch of a workgroup per queue
         // entry (up to 2^20 workgroups; beyond, each strides over the queue)
         hipLaunchKernelGGL(k_queue, dim3(1), dim3(kQThreads), 0, st, A, W);
+        launch_stream(A, t, W, fp64, big, 2, st, pt);
         launch_team(A, t, W, fp64, 256, main, 0, 0, big, 2, (int64_t)1 << 20, st, pt);
         if (big > main) launch_team(A, t, W, fp64, 256, big, 0, 0, big, 1, 1024, st, pt);
     } else {
+        launch_stream(A, t, W, fp64, big, 0, st, pt);
         if (shape == kHybrid) {
             launch_team(A, t, W, fp64, 64, small, 1, small, big, 0, 256 * 64, st, pt);
             launch_team(A, t, W, fp64, 256, main, 2, small, big, 0, 256 * 64, st, pt);
@@ -2984,7 +3199,9 @@ static cmc_status tune_passes(const StepArgs& A, const cmc_tables_s* t, const Wo
     best = 256;
     cmc_status rc = CMC_OK;
     const int other = A.maxn <= team_cap(64, A.maxn, fp64) ? 64 : kHybrid;
-    for (int team : {256, other, kQueue}) {
+    const bool both = (A.proc & (CMC_BREMS | CMC_TRIDENT)) && (A.proc & CMC_BH);
+    for (int team : {256, other, kQueue, both ? kSplit : 256}) {
+        if (team == 256 && best_ms > 0.0f) continue;
         if ((rc = launch_passes(A, t, W, fp64, team, st)) != CMC_OK) break;   // warm-up
         (void)hipEventRecord(e0, st);
         for (int r = 0; r < 3 && rc == CMC_OK; ++r) rc = launch_passes(A, t, W, fp64, team, st);
@@ -3032,7 +3249,7 @@ static cmc_status collide_step_impl(const char* who, cmc_tables t, const cmc_cel
     CMC_REQUIRE((P->processes & ~7u) == 0, CMC_EINVAL, "%s: unknown process bits", who);
     CMC_REQUIRE(P->precision == CMC_FP64 || P->precision == CMC_FP32, CMC_EINVAL,
                 "%s: unknown precision %d", who, P->precision);
-    CMC_REQUIRE(P->schedule >= 0 && P->schedule <= 5, CMC_EINVAL, "%s: unknown schedule", who);
+    CMC_REQUIRE(P->schedule >= 0 && P->schedule <= 6, CMC_EINVAL, "%s: unknown schedule", who);
     CMC_REQUIRE(P->max_per_cell >= 1 && P->max_per_cell <= CMC_MAX_PER_CELL, CMC_ERANGE,
                 "%s: max_per_cell = %d outside [1, %d]", who, P->max_per_cell, CMC_MAX_PER_CELL);
     CMC_REQUIRE(P->near_rel >= 0.0 && P->near_rel <= 1.0, CMC_EINVAL, "%s: near_rel outside [0, 1]", who);
@@ -3088,7 +3305,8 @@ static cmc_status collide_step_impl(const char* who, cmc_tables t, const cmc_cel
     };
     int team = P->schedule == CMC_SCHED_WAVE ? 64
              : P->schedule == CMC_SCHED_HYBRID ? kHybrid
-             : P->schedule == CMC_SCHED_QUEUE ? kQueue : 256;
+             : P->schedule == CMC_SCHED_QUEUE ? kQueue
+             : P->schedule == CMC_SCHED_SPLIT ? kSplit : 256;
     bool tuned = P->schedule != CMC_SCHED_AUTO;
     TuneKey key{};
     if (!tuned) {

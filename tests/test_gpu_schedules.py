@@ -58,7 +58,9 @@ def _snap(g, st):
 @pytest.mark.parametrize("precision,other,hi,moving", [(0, "WAVE", 480, False), (1, "WAVE", 480, False),
                                                        (1, "HYBRID", 3000, False), (0, "HYBRID", 3000, True),
                                                        (1, "WAVE", 480, "weights"), (0, "QUEUE", 3000, False),
-                                                       (1, "QUEUE", 3000, "weights"), (1, "QUEUE", 3000, True)])
+                                                       (1, "QUEUE", 3000, "weights"), (1, "QUEUE", 3000, True),
+                                                       (0, "SPLIT", 3000, False), (1, "SPLIT", 3000, "weights"),
+                                                       (1, "SPLIT", 3000, True)])
 def test_team_shapes_bit_identical(precision, other, hi, moving):
     import paper_1907_02814_amd as cmc
     wl = W.cfg3(np.random.default_rng(21), n_cells=128, dt=2e-13, lo=1, hi=hi)
@@ -100,7 +102,7 @@ def test_sequential_schedule_agrees(precision, moving):
     assert A["ti"][:, 3:6].sum() > 50
 
 
-@pytest.mark.parametrize("schedule", ["AUTO", "QUEUE"])
+@pytest.mark.parametrize("schedule", ["AUTO", "QUEUE", "SPLIT"])
 def test_graph_replay_matches_eager_steps(schedule):
     """(the work queue is rebuilt and drained inside the captured step)"""
     import torch
@@ -126,7 +128,7 @@ def test_graph_replay_matches_eager_steps(schedule):
     assert A["ti"][:, 3:6].sum() > 20
 
 
-@pytest.mark.parametrize("precision,other", [(0, "WAVE"), (1, "WAVE"), (1, "HYBRID")])
+@pytest.mark.parametrize("precision,other", [(0, "WAVE"), (1, "WAVE"), (1, "HYBRID"), (1, "SPLIT")])
 def test_cycled_photons_bit_identical_across_team_shapes(precision, other):
     """Cells with fewer photons than ions (300-1023 photons, 1024 ions of one
     weight): workgroup teams take the direct form with the selection of the
@@ -144,3 +146,22 @@ def test_cycled_photons_bit_identical_across_team_shapes(precision, other):
         for k in A:
             assert np.array_equal(A[k], B[k]), (s, k)
     assert A["ti"][:, 5].sum() > 20
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_foil_cells_bit_identical_across_schedules(precision):
+    """Foil cells (4096 electrons + 4096 Au ions, the photons of earlier steps
+    cycled against the ions): the stream kernel with workgroup teams, with
+    wavefront teams (SPLIT) and from the work queue give the same bits."""
+    import paper_1907_02814_amd as cmc
+    wl = W.cfg5(np.random.default_rng(61), n_cells=48, per_cell=4096, dt=4e-15, processes=7)
+    states = [_state(wl, getattr(cmc, "SCHED_" + s), precision) for s in ("GROUP", "SPLIT", "QUEUE")]
+    for s in range(4):
+        snaps = []
+        for g, st in states:
+            st.step(s)
+            snaps.append(_snap(g, st))
+        for other in snaps[1:]:
+            for k in snaps[0]:
+                assert np.array_equal(snaps[0][k], other[k]), (s, k)
+    assert snaps[0]["ti"][:, 3].sum() > 1000 and snaps[0]["ti"][:, 2].sum() > 0

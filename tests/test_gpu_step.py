@@ -184,6 +184,51 @@ def test_foil_chain_cells():
     assert P.ref.photons["count"].sum() > 0
 
 
+def _stream_cells(rng, bad=False):
+    """Cells for the stream kernel (ions at rest, N_e >= N_i, 1024 < N_e <=
+    4096) beside cells it leaves to the pass kernel: ions of unequal weight
+    (cell 6), N_e above 4096 (cell 4), N_e = 1024 (the direct form, cell 5)
+    and electrons cycled against more ions (cell 7).  bad: a NaN electron
+    weight in cell 1 and a negative ion weight in cell 3."""
+    ne = np.array([1025, 4096, 2000, 3000, 4097, 1024, 2500, 1500])
+    ni = np.array([1025, 4096, 1, 2999, 4000, 1024, 2500, 1600])
+    ng = np.array([0, 12, 3, 0, 5, 2, 40, 7])
+    n = len(ne)
+    n_i = np.full(n, 5.9e28)
+    e_g = 1 + np.exp(rng.uniform(math.log(1.0), math.log(500.0), ne.sum())) / MEC2
+    k = 2.0 + rng.exponential(5.0 / MEC2, ng.sum())
+    iw = np.repeat(n_i / ni, ni)
+    ioff = np.concatenate([[0], np.cumsum(ni)])
+    iw[ioff[6]:ioff[7]] *= rng.lognormal(0.0, 1.0, ni[6])
+    ew = np.repeat(n_i / ni, ne) * rng.lognormal(0.0, 1.0, ne.sum())
+    if bad:
+        ew[ne[0] + 17] = np.nan
+        iw[ioff[3] + 5] = -1.0
+    wl = W.assemble("stream-cells", 79, 2e-15, 7, 1, rng.uniform(0.0, 79.0, n), n_i, np.full(n, 100.0),
+                    e_g, ew, ne, k, np.repeat(n_i / ni, ng) * rng.lognormal(0, 1, ng.sum()), ng, iw, ni, rng,
+                    photon_extra=np.full(n, 512), pair_cap=np.full(n, 128))
+    return wl
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_stream_kernel_cells(precision):
+    """The electron-ion pass of the stream kernel and of the pass kernel's
+    forms on the cells beside it, against the oracle (all processes)."""
+    P = _run(_stream_cells(np.random.default_rng(51)), 3, precision=precision)
+    I = P.state.ti.cpu().numpy()
+    assert I[:, 3].sum() > 100
+
+
+@pytest.mark.parametrize("schedule", ["GROUP", "SPLIT", "QUEUE"])
+def test_stream_kernel_bad_weights(schedule):
+    import paper_1907_02814_amd as cmc
+    P = _run(_stream_cells(np.random.default_rng(52), bad=True), 2, precision=cmc.FP32,
+             schedule=getattr(cmc, "SCHED_" + schedule))
+    assert int(P.state.status.item()) & cmc.ST_BAD_WEIGHT
+    I = P.state.ti.cpu().numpy()
+    assert I[1, 0] == 0 and I[3, 0] == 0 and I[0, 0] > 0
+
+
 def test_edge_cells():
     rng = np.random.default_rng(4)
     ne = np.array([0, 3, 1, 50, 7, 1, 200, 5])
