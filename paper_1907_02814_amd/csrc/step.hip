@@ -775,10 +775,11 @@ constexpr int kStagePh = 1024;   // photons the event kernel stages in LDS per c
 // per-cell flags of a step: kFlagWeightsOk, set by the electron-ion pass,
 // says every weight of the cell is valid and its ion sum is in ionsum
 // (kFlagIonsSame: the ions share one weight), so that the photon-ion pass
-// reads neither the ions' nor the electrons' weights again; kFlagDone0:
-// the stream kernel has run the cell's electron-ion pass
+// reads neither the ions' nor the electrons' weights again; kFlagDone0,
+// kFlagDone1: the stream kernel has run the cell's electron-ion pass, its
+// photon-ion pass
 enum : int32_t { kFlagSlow = 1, kFlagListed = 2, kFlagBig0 = 4, kFlagBig1 = 8, kFlagWeightsOk = 16, kFlagIonsSame = 32,
-                 kFlagDone0 = 64 };
+                 kFlagDone0 = 64, kFlagDone1 = 128 };
 enum : uint32_t { kEvBr = 1, kEvTrPending = 2, kEvTr = 4, kEvBh = 8 };
 
 struct CellState {
@@ -1385,9 +1386,10 @@ __device__ __forceinline__ void pass_cell(const StepArgs& A, const TabView<R>& T
     if (cstat) return;                                // invalid cell (flagged by k_cell_state)
     if (kPass == 0 && (cflags & kFlagDone0)) {
         // done by the stream kernel, whose results the photon-ion pass takes
-        carry = PassCarry{cflags & (kFlagWeightsOk | kFlagIonsSame), W.ionsum[c]};
+        carry = PassCarry{cflags & (kFlagWeightsOk | kFlagIonsSame | kFlagDone1), W.ionsum[c]};
         return;
     }
+    if (kPass == 1 && (cflags & kFlagDone1)) return;
     const int Ne = max(0, min(ecn, (int)(eo1 - eo0))), Ng = max(0, min(gcn, (int)(go1 - go0)));
     const int Ni = max(0, min(icn, (int)(io1 - io0)));
     // size classes of the hybrid schedule: filter 1 takes the cells up
@@ -1945,27 +1947,44 @@ __device__ __forceinline__ void pass_cell(const StepArgs& A, const TabView<R>& T
     Team<kT>::sync();   // LDS of this cell is free
 }
 
-// The electron-ion pass of the cells whose ions are at rest and whose
-// electrons each pair once (N_i <= N_e), above the direct form's size and up
-// to the stream capacity `scap` (the LDS of one sigma v factor per electron,
-// two with Trident): nothing depends on an order, and a cell is one walk
-// over its records.  Every electron's momenta and weight and every ion's
-// weight are read once, two records ahead of their use, while the walk
-// forms each electron's FP32 test factor sigma v into LDS and the canonical
-// per-thread parts of the densities and of n_ab (the order of canon_part2).
-// After the team reduction the pairs are tested from LDS with the pass
-// kernel's bound, and the open pairs are listed as it lists them.  A cell
-// done here is flagged kFlagDone0; cells of unequal ion weights, and all
-// others, are left to the pass kernel.  One workgroup per cell, walking the
-// cells in index order or (from_list 2) the work queue.
-template <typename R, bool kTri>
-__global__ __launch_bounds__(256, (kStreamWgs<R, kTri>)) void k_stream(StepArgs A, TabView<R> T, Work W, int scap, int from_list) {
+// The pair tests of the cells whose ions are at rest and whose electrons
+// each pair once (N_i <= N_e), above the direct form's size and up to the
+// stream capacity `scap` (the LDS of one sigma v factor per electron, two
+// with Trident): nothing depends on an order, and a cell is one walk over
+// its records.  Every electron's momenta and weight and every ion's weight
+// are read once, two records ahead of their use, while the walk forms each
+// electron's FP32 test factor sigma v into LDS and the canonical per-thread
+// parts of the densities and of n_ab (the order of canon_part2).  After the
+// team reduction the electron-ion pairs are tested from LDS with the pass
+// kernel's bound, and the open pairs are listed as it lists them.
+// kPh: the photon-ion pass of the same cell runs in the walk as well when
+// its photons are cycled against the ions (0 < N_g < N_i, N_g <= 256): the
+// photons' keys, ranks, repetitions and 1/(sigma c) are formed before the
+// walk, and the draws of U1's upper bits (one per four tests, 1024 for 4096
+// ions) are made inside it, where the loads leave the ALUs idle.  Each
+// thread keeps the smallest kx at which one of its tests would pass the
+// bound; once the reduction gives kx, a thread whose smallest value lies
+// below it tests its pairs again exactly as the pass kernel does, so the
+// open pairs are the pass kernel's.
+// Done passes are flagged (kFlagDone0, kFlagDone1); cells of unequal ion
+// weights, and all others, are left to the pass kernel.  One workgroup per
+// cell, walking the cells in index order or (from_list 2) the work queue.
+constexpr int kStreamPh = 256;   // photons per cell the stream kernel's photon-ion pass takes
+
+template <typename R, bool kTri, bool kPh>
+__global__ __launch_bounds__(256, (kStreamWgs<R, kTri>)) void k_stream(StepArgs A, TabView<R> T, Work W, int scap,
+                                                                     int from_list) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ R slice[kSliceMax];
+    __shared__ R slice_g[kPh ? kSliceMax : 1];
     __shared__ double red4[kWaves * 4];
     __shared__ int redi[kWaves];
     __shared__ uint32_t opn[kCandCap], opk[kCandCap], opj[kCandCap];
     __shared__ int nopen;
+    // the photons of the cell: key, then rank; repetitions; sigma and 1/(sigma c)
+    __shared__ uint32_t gkey[kPh ? kStreamPh : 1];
+    __shared__ uint16_t grank[kPh ? kStreamPh : 1], greps[kPh ? kStreamPh : 1];
+    __shared__ float gsig[kPh ? kStreamPh : 1], ginv[kPh ? kStreamPh : 1];
     const int t = (int)threadIdx.x;
     const double rej = 2.0 * (1.0 + A.near_rel);
     const Rng rng = step_rng(A);
@@ -1994,15 +2013,69 @@ __global__ __launch_bounds__(256, (kStreamWgs<R, kTri>)) void k_stream(StepArgs 
             const int q = min(t + 256 * u, N - 1), qi = min(t + 256 * u, Ni - 1);
             return Rec{A.el.px[e0 + q], A.el.py[e0 + q], A.el.pz[e0 + q], wm[q], wion[qi]};
         };
-        // the first two records are in flight while the slice is staged
+        // the photon-ion pass here: photons cycled against the ions (the pair
+        // count is N_i; photon m pairs K = N_i div N_g times and, if its rank
+        // is below e = N_i mod N_g, once more, keys x = m + k N_g < X)
+        const bool ph = kPh && Ng > 0 && Ng < Ni && Ng <= kStreamPh;
+        const int K = ph ? Ni / Ng : 0, ee = ph ? Ni - K * Ng : 0;
+        const int X = K * Ng + (ee > 0 ? Ng : 0);
+        const int Gt = ph ? (((X + 1023) >> 10) << 8) / 256 : 0;   // draw groups per thread
+        const float rNg = ph ? 1.0f / (float)Ng : 0.0f;
+        double gw = 0.0, gk = 0.0;                                  // this thread's photon: weight, energy
+        // the first two records are in flight while the slices are staged
         Rec r0 = load(0), r1 = load(1);
+        if (ph && t < Ng) {
+            const double qx = A.ph.px[g0 + t], qy = A.ph.py[g0 + t], qz = A.ph.pz[g0 + t];
+            gw = wo[t];
+            gk = (double)photon_k<R>(qx, qy, qz);
+            const U4 r = rng.draw((uint32_t)t >> 2, cell, kTagKeyG);
+            gkey[t] = hi_word(r, (uint32_t)t & 3u);
+        }
         if (brm)
             for (int i = t; i < kSliceBrems; i += 256) slice[i] = slice_node_brems<R>(T, ct, i);
+        if (ph)
+            for (int i = t; i < kSliceBH; i += 256) slice_g[i] = slice_node_bh<R>(T, ct, i);
         const double w0 = wion[0];
         if (t == 0) nopen = 0;
         __syncthreads();
-        double sa = 0.0, sb = 0.0, si = 0.0;     // n_e, n_ab and n_i: canonical per-thread parts
         int fl = 0;                              // 1 bad weight, 2 ions of unequal weight, 4 above the tables
+        int flg = 0;                             // the photons': 4 above the tables
+        if (ph && t < Ng) {
+            // rank of photon t by (key, index); its tests; sigma and 1/(sigma c)
+            const uint32_t kt = gkey[t];
+            int rk = 0;
+            for (int j = 0; j < Ng; ++j) {
+                const uint32_t kj = gkey[j];
+                rk += (kj < kt || (kj == kt && j < t)) ? 1 : 0;
+            }
+            grank[t] = (uint16_t)rk;
+            greps[t] = (uint16_t)(K + (rk < ee ? 1 : 0));
+            bool hi;
+            const R sig = bh_sig_slice<R>(T, slice_g, (R)gk, hi);
+            flg |= hi ? 4 : 0;
+            gsig[t] = (float)sig;
+            const float s = (float)sig * (float)phys::kC;
+            ginv[t] = sig > (R)0 ? 1.0f / s : -1.0f;
+        }
+        if (ph) __syncthreads();
+        double sa = 0.0, sb = 0.0, si = 0.0;     // n_e, n_ab and n_i: canonical per-thread parts
+        float ymin = INFINITY;                   // the photon-ion tests: smallest kx that passes one
+        // draw group j of this thread: g = t + 256 j, keys base(g) + 256 w
+        const auto group = [&](int j) {
+            const int g = t + 256 * j;
+            const int base = ((g >> 8) << 10) | (g & 255);
+            if (base >= X) return;
+            const U4 h = rng.draw((uint32_t)g, cell, kTagHiBh);
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                const int x = base + 256 * w;
+                if (x >= X) break;
+                const int m = mod_small(x, Ng, rNg);
+                const int k = __float2int_rn((float)(x - m) * rNg);
+                const float inv = ginv[m];
+                if (k < (int)greps[m] && inv > 0.0f) ymin = fminf(ymin, (float)(hi_word(h, (uint32_t)w) >> 8) * inv);
+            }
+        };
 #pragma unroll 1
         for (int u = 0; u < U; ++u) {
             const Rec cur = r0;
@@ -2032,12 +2105,16 @@ __global__ __launch_bounds__(256, (kStreamWgs<R, kTri>)) void k_stream(StepArgs 
                 fl |= cur.wi != w0 ? 2 : 0;
                 si += cur.wi;
             }
+            if (ph && (u & 3) == 3 && (u >> 2) < Gt) group(u >> 2);
         }
+        if (ph)
+            for (int j = U >> 2; j < Gt; ++j) group(j);
         double v4[4];
         v4[0] = wave_sum(sa);
         v4[1] = wave_sum(sb);
         v4[2] = wave_sum(si);
         {
+            // the photons' weights: checked (and summed: n_g) in canonical order
             int bad = 0;
             v4[3] = canon_part<256>(Ng, [&](int q) { const double w = wo[q]; bad |= !(w >= 0.0) || !isfinite(w); return w; });
             fl |= bad ? 1 : 0;
@@ -2048,7 +2125,7 @@ __global__ __launch_bounds__(256, (kStreamWgs<R, kTri>)) void k_stream(StepArgs 
             // bad weights: flagged, and the pass kernel skips the cell
             if (t == 0) {
                 atomicOr(A.status, CMC_ST_BAD_WEIGHT);
-                atomicOr(&W.flags[c], kFlagDone0);
+                atomicOr(&W.flags[c], kFlagDone0 | (ph ? kFlagDone1 : 0));
             }
             continue;
         }
@@ -2091,13 +2168,73 @@ __global__ __launch_bounds__(256, (kStreamWgs<R, kTri>)) void k_stream(StepArgs 
             }
             if (t == 0) W.coef[c * 2] = coef;
         }
+        if (ph) {
+            // n_g, A = sum min(W_g, W_i) and B, the same over the photons that
+            // pair once more: n_ab = fma(K, A, B), as the pass kernel forms it
+            double vg[4] = {0.0, 0.0, 0.0, 0.0};
+            if (t < Ng) {
+                const double m = gw < w0 ? gw : w0;
+                vg[0] = 0.0 + m;
+                vg[1] = (int)grank[t] < ee ? 0.0 + m : 0.0;
+            }
+            vg[0] = wave_sum(vg[0]);
+            vg[1] = wave_sum(vg[1]);
+            int fg = flg;
+            team_reduce4_bits<256>(vg, fg, red4, redi);
+            const double nabg = fma((double)K, vg[0], vg[1]);
+            if (t == 0) nopen = 0;
+            __syncthreads();
+            if (nabg > 0.0) {
+                const double coefg = v4[3] * v4[2] / nabg;
+                const float kxg = (float)(coefg * A.dt * rej * 16777216.0);
+                // a thread whose smallest value is near or below kx tests its
+                // pairs again with the pass kernel's bound (the margin covers
+                // the roundings of 1/(sigma c))
+                if (ymin <= kxg * 1.001f) {
+                    for (int j = 0; j < Gt; ++j) {
+                        const int g = t + 256 * j;
+                        const int base = ((g >> 8) << 10) | (g & 255);
+                        if (base >= X) continue;
+                        const U4 h = rng.draw((uint32_t)g, cell, kTagHiBh);
+                        for (int w = 0; w < 4; ++w) {
+                            const int x = base + 256 * w;
+                            if (x >= X) break;
+                            const int m = mod_small(x, Ng, rNg);
+                            const int k = __float2int_rn((float)(x - m) * rNg);
+                            if (!(k < (int)greps[m])) continue;
+                            const float sg = gsig[m];
+                            if (sg > 0.0f && bound24(hi_word(h, (uint32_t)w), kxg * sg * (float)phys::kC)) {
+                                const int o = atomicAdd(&nopen, 1);
+                                if (o < kCandCap) opn[o] = (uint32_t)m | ((uint32_t)k << 16);
+                            }
+                        }
+                    }
+                }
+                __syncthreads();
+                const int n_open = nopen;
+                if (n_open > kCandCap) {
+                    if (t == 0) mark_slow(W, c);
+                } else if (t < n_open) {
+                    // pair index: the photon's rank plus k N_g
+                    const uint32_t o = opn[t];
+                    const int m = (int)(o & 0xFFFFu), k = (int)(o >> 16);
+                    push_cand(W, c, ev_pack(1, (int)grank[m] + k * Ng, m, 0, 1u));
+                }
+                if (t == 0) W.coef[c * 2 + 1] = coefg;
+            }
+            if (t == 0) {
+                A.ti[c * CMC_NI + CMC_I_PAIRS_BH] = nabg > 0.0 ? Ni : 0;
+                A.td[c * CMC_ND + CMC_D_NAB_GI] = nabg;
+                if (nabg > 0.0 && (fg & 4)) atomicOr(A.status, CMC_ST_GAMMA_HIGH);
+            }
+        }
         if (t == 0) {
             A.ti[c * CMC_NI + CMC_I_PAIRS_BR] = (nab > 0.0 && brm) ? N : 0;
             A.ti[c * CMC_NI + CMC_I_PAIRS_TR] = (nab > 0.0 && tri) ? N : 0;
             A.td[c * CMC_ND + CMC_D_NAB_EI] = nab;
             if (nab > 0.0 && (fl & 4)) atomicOr(A.status, CMC_ST_GAMMA_HIGH);
             W.ionsum[c] = v4[2];
-            atomicOr(&W.flags[c], kFlagWeightsOk | kFlagIonsSame | kFlagDone0);
+            atomicOr(&W.flags[c], kFlagWeightsOk | kFlagIonsSame | kFlagDone0 | (ph ? kFlagDone1 : 0));
         }
         __syncthreads();   // LDS of this cell is free
     }
@@ -3097,7 +3234,9 @@ template <typename R>
 static void launch_stream_r(const StepArgs& A, const TabView<R>& T, const Work& W, int scap, int from_list,
                             hipStream_t st, PassTiming* pt) {
     const size_t dshm = (size_t)scap * ((A.proc & CMC_TRIDENT) ? 8 : 4);
-    const auto kernel = (A.proc & CMC_TRIDENT) ? k_stream<R, true> : k_stream<R, false>;
+    const bool tri = (A.proc & CMC_TRIDENT) != 0, ph = (A.proc & CMC_BH) != 0;
+    const auto kernel = tri ? (ph ? k_stream<R, true, true> : k_stream<R, true, false>)
+                            : (ph ? k_stream<R, false, true> : k_stream<R, false, false>);
     lds_attr((const void*)kernel, dshm, st);
     const int64_t cap_blocks = from_list == 2 ? ((int64_t)1 << 20) : 256 * 64;
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(A.n_cells, cap_blocks));
