@@ -777,9 +777,9 @@ constexpr int kStagePh = 1024;   // photons the event kernel stages in LDS per c
 // (kFlagIonsSame: the ions share one weight), so that the photon-ion pass
 // reads neither the ions' nor the electrons' weights again; kFlagDone0,
 // kFlagDone1: the stream kernel has run the cell's electron-ion pass, its
-// photon-ion pass
+// photon-ion pass; kFlagRest: the cell is in list_rest
 enum : int32_t { kFlagSlow = 1, kFlagListed = 2, kFlagBig0 = 4, kFlagBig1 = 8, kFlagWeightsOk = 16, kFlagIonsSame = 32,
-                 kFlagDone0 = 64, kFlagDone1 = 128 };
+                 kFlagDone0 = 64, kFlagDone1 = 128, kFlagRest = 256 };
 enum : uint32_t { kEvBr = 1, kEvTrPending = 2, kEvTr = 4, kEvBh = 8 };
 
 struct CellState {
@@ -794,6 +794,7 @@ enum : int {
     kCntBig0 = 1,    // electron-ion passes deferred to the large-LDS launch (list_big[0])
     kCntBig1 = 2,    // photon-ion passes deferred (list_big[1])
     kCntWg = 3,      // listed cells the wavefront event kernel hands to the workgroup one (list_wg)
+    kCntRest = 4,    // cells the stream kernel leaves (wholly or in part) to the pass kernel (list_rest)
     kNumCnt = 8
 };
 
@@ -809,6 +810,7 @@ struct Work {
     int32_t* list_wg;                // listed cells that need the workgroup event kernel
     int32_t* list_big[2];            // per pass: cells whose pass needs more LDS than the first launch has
     int32_t* queue;                  // the cells in decreasing order of cost (batched schedule)
+    int32_t* list_rest;              // cells with a pass the stream kernel did not run
     uint64_t* cand;                  // [n_cells][kCandCap] open pairs
 };
 
@@ -816,7 +818,7 @@ __host__ __device__ constexpr size_t align256(size_t b) { return (b + 255) / 256
 
 __host__ __device__ constexpr size_t work_bytes(int64_t n) {
     return align256(sizeof(CellState) * n) + align256(4 * n) + align256(4 * n) +
-           align256(16 * n) + align256(8 * n) + align256(8) + align256(4 * kNumCnt) + 5 * align256(4 * n) +
+           align256(16 * n) + align256(8 * n) + align256(8) + align256(4 * kNumCnt) + 6 * align256(4 * n) +
            align256(8 * (size_t)n * kCandCap);
 }
 
@@ -835,6 +837,7 @@ inline Work carve_work(void* base, int64_t n) {
     w.list_big[0] = reinterpret_cast<int32_t*>(p); p += align256(4 * n);
     w.list_big[1] = reinterpret_cast<int32_t*>(p); p += align256(4 * n);
     w.queue = reinterpret_cast<int32_t*>(p); p += align256(4 * n);
+    w.list_rest = reinterpret_cast<int32_t*>(p); p += align256(4 * n);
     w.cand = reinterpret_cast<uint64_t*>(p);
     return w;
 }
@@ -1967,7 +1970,8 @@ __device__ __forceinline__ void pass_cell(const StepArgs& A, const TabView<R>& T
 // below it tests its pairs again exactly as the pass kernel does, so the
 // open pairs are the pass kernel's.
 // Done passes are flagged (kFlagDone0, kFlagDone1); cells of unequal ion
-// weights, and all others, are left to the pass kernel.  One workgroup per
+// weights, and all others, are left to the pass kernel, listed in
+// list_rest (a cell whose photon-ion pass is left, too).  One workgroup per
 // cell, walking the cells in index order or (from_list 2) the work queue.
 constexpr int kStreamPh = 256;   // photons per cell the stream kernel's photon-ion pass takes
 
@@ -2003,7 +2007,16 @@ __global__ __launch_bounds__(256, (kStreamWgs<R, kTri>)) void k_stream(StepArgs 
         const int icn = A.io.count ? A.io.count[c] : 0x7FFFFFFF;
         const int Ne = max(0, min(ecn, (int)(eo1 - e0))), Ng = max(0, min(gcn, (int)(go1 - g0)));
         const int Ni = max(0, min(icn, (int)(io1 - i0)));
-        if (cstat || Ni == 0 || Ne < Ni || Ne <= 1024 || Ne > scap || Ne > A.maxn || Ng > A.maxn) continue;
+        // the cell to the pass kernel (one thread lists it, once a step)
+        const auto rest = [&]() {
+            if (t == 0 && !(atomicOr(&W.flags[c], kFlagRest) & kFlagRest))
+                W.list_rest[atomicAdd(&W.counters[kCntRest], 1)] = (int32_t)c;
+        };
+        if (cstat) continue;                     // invalid cell (flagged by k_cell_state)
+        if (Ni == 0 || Ne < Ni || Ne <= 1024 || Ne > scap || Ne > A.maxn || Ng > A.maxn) {
+            rest();
+            continue;
+        }
         const int N = Ne, U = (N + 255) / 256;
         const double* wm = A.el.w + e0;
         const double* wion = A.io.w + i0;
@@ -2017,6 +2030,7 @@ __global__ __launch_bounds__(256, (kStreamWgs<R, kTri>)) void k_stream(StepArgs 
         // count is N_i; photon m pairs K = N_i div N_g times and, if its rank
         // is below e = N_i mod N_g, once more, keys x = m + k N_g < X)
         const bool ph = kPh && Ng > 0 && Ng < Ni && Ng <= kStreamPh;
+        const bool left1 = !ph && (A.proc & CMC_BH) && Ng > 0;      // a photon-ion pass for the pass kernel
         const int K = ph ? Ni / Ng : 0, ee = ph ? Ni - K * Ng : 0;
         const int X = K * Ng + (ee > 0 ? Ng : 0);
         const int Gt = ph ? (((X + 1023) >> 10) << 8) / 256 : 0;   // draw groups per thread
@@ -2120,13 +2134,17 @@ __global__ __launch_bounds__(256, (kStreamWgs<R, kTri>)) void k_stream(StepArgs 
             fl |= bad ? 1 : 0;
         }
         team_reduce4_bits<256>(v4, fl, red4, redi);   // its barriers also publish sv
-        if (fl & 2) continue;                        // the ordered form, in the pass kernel
+        if (fl & 2) {                                // the ordered form, in the pass kernel
+            rest();
+            continue;
+        }
         if (fl & 1) {
-            // bad weights: flagged, and the pass kernel skips the cell
+            // bad weights: flagged, and the pass kernel skips the cell's passes done here
             if (t == 0) {
                 atomicOr(A.status, CMC_ST_BAD_WEIGHT);
                 atomicOr(&W.flags[c], kFlagDone0 | (ph ? kFlagDone1 : 0));
             }
+            if (left1) rest();
             continue;
         }
         const double nab = v4[1];
@@ -2236,6 +2254,7 @@ __global__ __launch_bounds__(256, (kStreamWgs<R, kTri>)) void k_stream(StepArgs 
             W.ionsum[c] = v4[2];
             atomicOr(&W.flags[c], kFlagWeightsOk | kFlagIonsSame | kFlagDone0 | (ph ? kFlagDone1 : 0));
         }
+        if (left1) rest();
         __syncthreads();   // LDS of this cell is free
     }
 }
@@ -2281,12 +2300,15 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
 
     const PassLds L{red4, redu, redi, opn[team], opk[team], opj[team], &nopen[team]};
     // from_list 0: every cell in index order; 1: the pass's deferred list;
+    // 3: the cells the stream kernel left;
     // 2: the work queue, the cells costliest first (workgroups are
     // dispatched in index order as compute units free up, so the largest
     // cells start first and the rest fill in behind them)
-    const int64_t n_items = from_list == 1 ? (int64_t)W.counters[kPass == 1 ? kCntBig1 : kCntBig0] : A.n_cells;
+    const int64_t n_items = from_list == 1 ? (int64_t)W.counters[kPass == 1 ? kCntBig1 : kCntBig0]
+                          : from_list == 3 ? (int64_t)W.counters[kCntRest] : A.n_cells;
     for (int64_t item = (int64_t)blockIdx.x * kTeams + team; item < n_items; item += (int64_t)gridDim.x * kTeams) {
         const int64_t c = from_list == 2 ? (int64_t)W.queue[item]
+                        : from_list == 3 ? (int64_t)W.list_rest[item]
                         : from_list ? (int64_t)W.list_big[kPass == 1 ? 1 : 0][item] : item;
         PassCarry carry{0, 0.0};
         if constexpr (kPass != 1)
@@ -3245,13 +3267,15 @@ static void launch_stream_r(const StepArgs& A, const TabView<R>& T, const Work& 
     hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(256), (uint32_t)dshm, st, e0, e1, 0u, A, T, W, scap, from_list);
 }
 
-static void launch_stream(const StepArgs& A, const cmc_tables_s* t, const Work& W, bool fp64, int big, int from_list,
+// true when it ran: the pass kernels then walk the cells it left (from_list 3)
+static bool launch_stream(const StepArgs& A, const cmc_tables_s* t, const Work& W, bool fp64, int big, int from_list,
                           hipStream_t st, PassTiming* pt) {
-    if (A.io.px || !(A.proc & (CMC_BREMS | CMC_TRIDENT))) return;
+    if (A.io.px || !(A.proc & (CMC_BREMS | CMC_TRIDENT))) return false;
     const int scap = std::min(std::min(kStreamCap, A.maxn), big);
-    if (scap <= 1024) return;
+    if (scap <= 1024) return false;
     if (fp64) launch_stream_r<double>(A, view64(t), W, scap, from_list, st, pt);
     else launch_stream_r<float>(A, view32(t), W, scap, from_list, st, pt);
+    return true;
 }
 
 static cmc_status launch_passes(const StepArgs& A, const cmc_tables_s* t, const Work& W, bool fp64, int shape,
@@ -3263,30 +3287,30 @@ static cmc_status launch_passes(const StepArgs& A, const cmc_tables_s* t, const 
         // wavefront teams only: cells above their capacity take the sequential step
         launch_team(A, t, W, fp64, 64, small, 0, 0, small, 0, 256 * 64, st, pt);
     } else if (shape == kSplit) {
-        // the electron-ion passes the stream kernel takes, then wavefront
-        // teams for the rest of both passes
-        // teams for the rest, one launch per pass (the fused wavefront
-        // kernel holds too many registers for the occupancy the photon-ion
-        // pass needs)
+        // the stream kernel, then wavefront teams for the passes it left,
+        // one launch per pass (the fused wavefront kernel holds too many
+        // registers for the occupancy the photon-ion pass needs)
         const int sc = std::min(big, kSplitCap);
-        launch_stream(A, t, W, fp64, big, 0, st, pt);
-        launch_team(A, t, W, fp64, 64, sc, 0, 0, big, 0, 256 * 64, st, pt, 1);
-        launch_team(A, t, W, fp64, 64, sc, 0, 0, big, 0, 256 * 64, st, pt, 2);
+        const int fl = launch_stream(A, t, W, fp64, big, 0, st, pt) ? 3 : 0;
+        launch_team(A, t, W, fp64, 64, sc, 0, 0, big, fl, 256 * 64, st, pt, 1);
+        launch_team(A, t, W, fp64, 64, sc, 0, 0, big, fl, 256 * 64, st, pt, 2);
         if (big > sc) launch_team(A, t, W, fp64, 256, big, 0, 0, big, 1, 1024, st, pt);
     } else if (shape == kQueue) {
         // the cells sorted by cost, then one launch of a workgroup per queue
-        // entry (up to 2^20 workgroups; beyond, each strides over the queue)
+        // entry (up to 2^20 workgroups; beyond, each strides over the queue);
+        // after the stream kernel, the cells it left (listed in about the
+        // order it took them from the queue)
         hipLaunchKernelGGL(k_queue, dim3(1), dim3(kQThreads), 0, st, A, W);
-        launch_stream(A, t, W, fp64, big, 2, st, pt);
-        launch_team(A, t, W, fp64, 256, main, 0, 0, big, 2, (int64_t)1 << 20, st, pt);
+        const int fl = launch_stream(A, t, W, fp64, big, 2, st, pt) ? 3 : 2;
+        launch_team(A, t, W, fp64, 256, main, 0, 0, big, fl, (int64_t)1 << 20, st, pt);
         if (big > main) launch_team(A, t, W, fp64, 256, big, 0, 0, big, 1, 1024, st, pt);
     } else {
-        launch_stream(A, t, W, fp64, big, 0, st, pt);
+        const int fl = launch_stream(A, t, W, fp64, big, 0, st, pt) ? 3 : 0;
         if (shape == kHybrid) {
-            launch_team(A, t, W, fp64, 64, small, 1, small, big, 0, 256 * 64, st, pt);
-            launch_team(A, t, W, fp64, 256, main, 2, small, big, 0, 256 * 64, st, pt);
+            launch_team(A, t, W, fp64, 64, small, 1, small, big, fl, 256 * 64, st, pt);
+            launch_team(A, t, W, fp64, 256, main, 2, small, big, fl, 256 * 64, st, pt);
         } else {
-            launch_team(A, t, W, fp64, 256, main, 0, 0, big, 0, 256 * 64, st, pt);
+            launch_team(A, t, W, fp64, 256, main, 0, 0, big, fl, 256 * 64, st, pt);
         }
         // the passes that needed more LDS than the first launch has
         if (big > main) launch_team(A, t, W, fp64, 256, big, 0, 0, big, 1, 1024, st, pt);
