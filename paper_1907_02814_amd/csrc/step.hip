@@ -1956,24 +1956,60 @@ __device__ __forceinline__ void pass_cell(const StepArgs& A, const TabView<R>& T
 // with Trident): nothing depends on an order, and a cell is one walk over
 // its records.  Every electron's momenta and weight and every ion's weight
 // are read once, two records ahead of their use, while the walk forms each
-// electron's FP32 test factor sigma v into LDS and the canonical per-thread
-// parts of the densities and of n_ab (the order of canon_part2).  After the
-// team reduction the electron-ion pairs are tested from LDS with the pass
-// kernel's bound, and the open pairs are listed as it lists them.
+// electron's FP32 test factor sigma v (into LDS) and the canonical
+// per-thread parts of the densities and of n_ab (the order of canon_part2).
+// The draws of U1's upper bits (one per four pairs) are made in the walk
+// too, where the loads leave the ALUs idle, and each thread keeps the
+// smallest kx at which one of its tests would pass the bound.  Once the
+// team reduction gives kx, only a thread whose smallest value lies near or
+// below it tests its pairs exactly as the pass kernel does, so the open
+// pairs are the pass kernel's.
 // kPh: the photon-ion pass of the same cell runs in the walk as well when
 // its photons are cycled against the ions (0 < N_g < N_i, N_g <= 256): the
-// photons' keys, ranks, repetitions and 1/(sigma c) are formed before the
-// walk, and the draws of U1's upper bits (one per four tests, 1024 for 4096
-// ions) are made inside it, where the loads leave the ALUs idle.  Each
-// thread keeps the smallest kx at which one of its tests would pass the
-// bound; once the reduction gives kx, a thread whose smallest value lies
-// below it tests its pairs again exactly as the pass kernel does, so the
-// open pairs are the pass kernel's.
-// Done passes are flagged (kFlagDone0, kFlagDone1); cells of unequal ion
-// weights, and all others, are left to the pass kernel, listed in
-// list_rest (a cell whose photon-ion pass is left, too).  One workgroup per
-// cell, walking the cells in index order or (from_list 2) the work queue.
+// photons' keys, ranks, repetitions, 1/(sigma c) and weight sums are formed
+// before the walk, and its draws (one per four tests, 1024 for 4096 ions)
+// are made inside it, filtered the same way.
+// The open pairs are written to the cell's candidate records with their
+// count (no atomics per pair); the cell is listed for the event kernels
+// once, after the workgroup's last barrier.  Done passes are flagged
+// (kFlagDone0, kFlagDone1); cells of unequal ion weights, and all others,
+// are left to the pass kernel, listed in list_rest (a cell whose photon-ion
+// pass is left, too).  One workgroup per cell, walking the cells in index
+// order or (from_list 2) the work queue.
 constexpr int kStreamPh = 256;   // photons per cell the stream kernel's photon-ion pass takes
+
+// An electron record of the stream kernel's walk, and the ion weight beside it
+struct Rec { double x, y, z, w, wi; };
+
+// The two smallest values met, and the place of the smallest
+struct Low {
+    float y1 = INFINITY, y2 = INFINITY;
+    int u1 = 0;
+    __device__ __forceinline__ void add(float y, int u) {
+        const bool lo = y < y1;
+        y2 = lo ? y1 : fminf(y2, y);
+        u1 = lo ? u : u1;
+        y1 = lo ? y : y1;
+    }
+};
+
+// A copy of v in registers of its own (an instruction the compiler cannot
+// fold), so that the registers v arrived in may take the next load at once.
+__device__ __forceinline__ double fresh(double v) {
+    double r;
+    asm("v_mov_b64 %0, %1" : "=v"(r) : "v"(v));
+    return r;
+}
+__device__ __forceinline__ Rec fresh(const Rec& r) {
+    return Rec{fresh(r.x), fresh(r.y), fresh(r.z), fresh(r.w), fresh(r.wi)};
+}
+
+// 2^-24 2^24 w / s for the filter of the bound test (an upper bound on kx
+// is not needed: the filter keeps a margin and the exact test decides)
+__device__ __forceinline__ float kx_needed(uint32_t word, float s) {
+    const uint32_t v = word >> 8;
+    return v == 0u ? 0.0f : (float)v * __builtin_amdgcn_rcpf(s);
+}
 
 template <typename R, bool kTri, bool kPh>
 __global__ __launch_bounds__(256, (kStreamWgs<R, kTri>)) void k_stream(StepArgs A, TabView<R> T, Work W, int scap,
@@ -1981,15 +2017,17 @@ __global__ __launch_bounds__(256, (kStreamWgs<R, kTri>)) void k_stream(StepArgs 
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ R slice[kSliceMax];
     __shared__ R slice_g[kPh ? kSliceMax : 1];
-    __shared__ double red4[kWaves * 4];
-    __shared__ int redi[kWaves];
-    __shared__ uint32_t opn[kCandCap], opk[kCandCap], opj[kCandCap];
+    __shared__ double rs[kWaves][4];              // per wavefront: the canonical parts of n_e, n_ab, n_i, n_g
+    __shared__ int rsf[kWaves];                   // per wavefront: flag bits
+    __shared__ double pg[kPh ? kWaves * 3 : 1];   // per wavefront: the photons' n_g, A, B parts
+    __shared__ int pgf[kPh ? kWaves : 1];         // per wavefront: 1 bad photon weight, 4 above the tables
+    __shared__ uint32_t opn[kCandCap];
     __shared__ int nopen;
     // the photons of the cell: key, then rank; repetitions; sigma and 1/(sigma c)
     __shared__ uint32_t gkey[kPh ? kStreamPh : 1];
     __shared__ uint16_t grank[kPh ? kStreamPh : 1], greps[kPh ? kStreamPh : 1];
     __shared__ float gsig[kPh ? kStreamPh : 1], ginv[kPh ? kStreamPh : 1];
-    const int t = (int)threadIdx.x;
+    const int t = (int)threadIdx.x, lane = t & 63, wv = t >> 6;
     const double rej = 2.0 * (1.0 + A.near_rel);
     const Rng rng = step_rng(A);
     constexpr bool tri = kTri;
@@ -2021,7 +2059,6 @@ __global__ __launch_bounds__(256, (kStreamWgs<R, kTri>)) void k_stream(StepArgs 
         const double* wm = A.el.w + e0;
         const double* wion = A.io.w + i0;
         const double* wo = A.ph.w + g0;
-        struct Rec { double x, y, z, w, wi; };
         const auto load = [&](int u) {
             const int q = min(t + 256 * u, N - 1), qi = min(t + 256 * u, Ni - 1);
             return Rec{A.el.px[e0 + q], A.el.py[e0 + q], A.el.pz[e0 + q], wm[q], wion[qi]};
@@ -2035,46 +2072,72 @@ __global__ __launch_bounds__(256, (kStreamWgs<R, kTri>)) void k_stream(StepArgs 
         const int X = K * Ng + (ee > 0 ? Ng : 0);
         const int Gt = ph ? (((X + 1023) >> 10) << 8) / 256 : 0;   // draw groups per thread
         const float rNg = ph ? 1.0f / (float)Ng : 0.0f;
-        double gw = 0.0, gk = 0.0;                                  // this thread's photon: weight, energy
-        // the first two records are in flight while the slices are staged
-        Rec r0 = load(0), r1 = load(1);
-        if (ph && t < Ng) {
-            const double qx = A.ph.px[g0 + t], qy = A.ph.py[g0 + t], qz = A.ph.pz[g0 + t];
-            gw = wo[t];
-            gk = (double)photon_k<R>(qx, qy, qz);
-            const U4 r = rng.draw((uint32_t)t >> 2, cell, kTagKeyG);
-            gkey[t] = hi_word(r, (uint32_t)t & 3u);
-        }
+        // Loads in the order their values are needed: the table slices (from
+        // L2) first, then the photons, then the first two electron records,
+        // which stay in flight through the staging and the photons' setup.
         if (brm)
             for (int i = t; i < kSliceBrems; i += 256) slice[i] = slice_node_brems<R>(T, ct, i);
         if (ph)
             for (int i = t; i < kSliceBH; i += 256) slice_g[i] = slice_node_bh<R>(T, ct, i);
+        double gw = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;          // this thread's photon
+        if (ph && t < Ng) {
+            gx = A.ph.px[g0 + t]; gy = A.ph.py[g0 + t]; gz = A.ph.pz[g0 + t];
+            gw = wo[t];
+        }
         const double w0 = wion[0];
+        Rec r0 = load(0), r1 = load(1);
+        if (ph && t < Ng) {
+            const U4 r = rng.draw((uint32_t)t >> 2, cell, kTagKeyG);
+            gkey[t] = hi_word(r, (uint32_t)t & 3u);
+        }
         if (t == 0) nopen = 0;
         __syncthreads();
-        int fl = 0;                              // 1 bad weight, 2 ions of unequal weight, 4 above the tables
-        int flg = 0;                             // the photons': 4 above the tables
-        if (ph && t < Ng) {
-            // rank of photon t by (key, index); its tests; sigma and 1/(sigma c)
-            const uint32_t kt = gkey[t];
-            int rk = 0;
-            for (int j = 0; j < Ng; ++j) {
-                const uint32_t kj = gkey[j];
-                rk += (kj < kt || (kj == kt && j < t)) ? 1 : 0;
+        if (ph) {
+            // rank of photon t by (key, index); its tests; sigma and 1/(sigma c);
+            // the canonical per-wavefront parts of n_g, A = sum min(W_g, W_i)
+            // and B, the same over the photons that pair once more
+            int flg = 0;
+            double pa = 0.0, pb = 0.0, pc = 0.0;
+            if (t < Ng) {
+                const uint32_t kt = gkey[t];
+                int rk = 0;
+                for (int j = 0; j < Ng; ++j) {
+                    const uint32_t kj = gkey[j];
+                    rk += (kj < kt || (kj == kt && j < t)) ? 1 : 0;
+                }
+                grank[t] = (uint16_t)rk;
+                greps[t] = (uint16_t)(K + (rk < ee ? 1 : 0));
+                bool hi;
+                const R sig = bh_sig_slice<R>(T, slice_g, photon_k<R>(gx, gy, gz), hi);
+                flg |= hi ? 4 : 0;
+                gsig[t] = (float)sig;
+                ginv[t] = sig > (R)0 ? 1.0f / ((float)sig * (float)phys::kC) : -1.0f;
+                flg |= (!(gw >= 0.0) || !isfinite(gw)) ? 1 : 0;
+                const double m = gw < w0 ? gw : w0;
+                pa = 0.0 + gw;
+                pb = 0.0 + m;
+                pc = rk < ee ? 0.0 + m : 0.0;
             }
-            grank[t] = (uint16_t)rk;
-            greps[t] = (uint16_t)(K + (rk < ee ? 1 : 0));
-            bool hi;
-            const R sig = bh_sig_slice<R>(T, slice_g, (R)gk, hi);
-            flg |= hi ? 4 : 0;
-            gsig[t] = (float)sig;
-            const float s = (float)sig * (float)phys::kC;
-            ginv[t] = sig > (R)0 ? 1.0f / s : -1.0f;
+            pa = wave_sum(pa);
+            pb = wave_sum(pb);
+            pc = wave_sum(pc);
+            const int f1 = __ballot(flg & 1) != 0ull ? 1 : 0, f4 = __ballot(flg & 4) != 0ull ? 4 : 0;
+            if (lane == 0) {
+                pg[wv * 3] = pa;
+                pg[wv * 3 + 1] = pb;
+                pg[wv * 3 + 2] = pc;
+                pgf[wv] = f1 | f4;
+            }
+            __syncthreads();
         }
-        if (ph) __syncthreads();
         double sa = 0.0, sb = 0.0, si = 0.0;     // n_e, n_ab and n_i: canonical per-thread parts
-        float ymin = INFINITY;                   // the photon-ion tests: smallest kx that passes one
-        // draw group j of this thread: g = t + 256 j, keys base(g) + 256 w
+        int fl = 0;                              // 1 bad weight, 2 ions of unequal weight, 4 above the tables
+        // the two smallest kx at which one of this thread's tests would pass
+        // the bound, with the word and place of the smallest: Bremsstrahlung,
+        // Trident, Bethe-Heitler
+        Low lb, lt, lg;
+        U4 hb{0u, 0u, 0u, 0u}, ht{0u, 0u, 0u, 0u};
+        // draw group j of this thread's photon-ion tests: g = t + 256 j, keys base(g) + 256 w
         const auto group = [&](int j) {
             const int g = t + 256 * j;
             const int base = ((g >> 8) << 10) | (g & 255);
@@ -2087,15 +2150,21 @@ __global__ __launch_bounds__(256, (kStreamWgs<R, kTri>)) void k_stream(StepArgs 
                 const int m = mod_small(x, Ng, rNg);
                 const int k = __float2int_rn((float)(x - m) * rNg);
                 const float inv = ginv[m];
-                if (k < (int)greps[m] && inv > 0.0f) ymin = fminf(ymin, (float)(hi_word(h, (uint32_t)w) >> 8) * inv);
+                if (k < (int)greps[m] && inv > 0.0f) {
+                    const uint32_t v = hi_word(h, (uint32_t)w) >> 8;
+                    lg.add(v == 0u ? 0.0f : (float)v * inv, x);
+                }
             }
         };
-#pragma unroll 1
-        for (int u = 0; u < U; ++u) {
-            const Rec cur = r0;
-            r0 = r1;
-            if (u + 2 < U) r1 = load(u + 2);
+        // record u of the walk (q = t + 256 u)
+        const auto take = [&](int u, const Rec& cur) {
             const int q = t + 256 * u;
+            // pair q: U1's upper bits are word u & 3 of the draw
+            // hi_group(q) = (u >> 2) << 8 | t, one per four pairs
+            if ((u & 3) == 0) {
+                if (brm) hb = rng.draw(hi_group((uint32_t)q), cell, kTagHiBr);
+                if (tri) ht = rng.draw(hi_group((uint32_t)q), cell, kTagHiTr);
+            }
             if (q < N) {
                 fl |= (!(cur.w >= 0.0) || !isfinite(cur.w)) ? 1 : 0;
                 sa += cur.w;
@@ -2106,12 +2175,20 @@ __global__ __launch_bounds__(256, (kStreamWgs<R, kTri>)) void k_stream(StepArgs 
                     bool hi;
                     const R sig = brems_sig_slice<R>(T, slice, el.g, el.gm1, hi);
                     fl |= hi ? 4 : 0;
-                    if (sig > (R)0) s1 = (float)sig * (float)el.vrel;
+                    if (sig > (R)0) {
+                        s1 = (float)sig * (float)el.vrel;
+                        lb.add(kx_needed(hi_word(hb, (uint32_t)u & 3u), s1), u);
+                    }
                 }
                 sv[q] = s1;
                 if (tri) {
                     const R st = (R)phys::trident_sigma(T.Z, (double)el.g);
-                    svt[q] = st > (R)0 ? (float)st * (float)el.vrel : -1.0f;
+                    float s2 = -1.0f;
+                    if (st > (R)0) {
+                        s2 = (float)st * (float)el.vrel;
+                        lt.add(kx_needed(hi_word(ht, (uint32_t)u & 3u), s2), u);
+                    }
+                    svt[q] = s2;
                 }
             }
             if (q < Ni) {
@@ -2120,22 +2197,60 @@ __global__ __launch_bounds__(256, (kStreamWgs<R, kTri>)) void k_stream(StepArgs 
                 si += cur.wi;
             }
             if (ph && (u & 3) == 3 && (u >> 2) < Gt) group(u >> 2);
+        };
+        // Two records in flight per thread, each in registers of its own: the
+        // walk takes two records a round, each copied out (fresh, once it has
+        // arrived) before the load of the record two ahead goes out into its
+        // registers.  A plain rotation (r0 = r1) would move a value still in
+        // flight, which waits for every load.  The last round's loads are
+        // clamped to the last record.
+#pragma unroll 1
+        for (int u = 0; u < U; u += 2) {
+            const Rec ca = fresh(r0);
+            r0 = load(min(u + 2, U - 1));
+            take(u, ca);
+            const Rec cb = fresh(r1);
+            r1 = load(min(u + 3, U - 1));
+            if (u + 1 < U) take(u + 1, cb);
         }
         if (ph)
             for (int j = U >> 2; j < Gt; ++j) group(j);
-        double v4[4];
-        v4[0] = wave_sum(sa);
-        v4[1] = wave_sum(sb);
-        v4[2] = wave_sum(si);
         {
-            // the photons' weights: checked (and summed: n_g) in canonical order
-            int bad = 0;
-            v4[3] = canon_part<256>(Ng, [&](int q) { const double w = wo[q]; bad |= !(w >= 0.0) || !isfinite(w); return w; });
-            fl |= bad ? 1 : 0;
+            // the team reduction: per-wavefront parts, one barrier (which also
+            // publishes sv), the four parts added in order
+            double p3 = 0.0;
+            if (!ph) {
+                // the photons' weights are checked (their pass is left to the pass kernel)
+                int bad = 0;
+                p3 = canon_part<256>(Ng, [&](int q) { const double w = wo[q]; bad |= !(w >= 0.0) || !isfinite(w); return w; });
+                fl |= bad ? 1 : 0;
+            }
+            const double p0 = wave_sum(sa), p1 = wave_sum(sb), p2 = wave_sum(si);
+            int wf = 0;
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                if (__ballot((fl >> b) & 1) != 0ull) wf |= 1 << b;
+            if (lane == 0) {
+                rs[wv][0] = p0;
+                rs[wv][1] = p1;
+                rs[wv][2] = p2;
+                rs[wv][3] = p3;
+                rsf[wv] = wf;
+            }
+            __syncthreads();
         }
-        team_reduce4_bits<256>(v4, fl, red4, redi);   // its barriers also publish sv
+        double v4[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v4[k] = ((rs[0][k] + rs[1][k]) + rs[2][k]) + rs[3][k];
+        fl = rsf[0] | rsf[1] | rsf[2] | rsf[3];
+        int flg = 0;
+        if (ph) {
+            flg = pgf[0] | pgf[1] | pgf[2] | pgf[3];
+            fl |= flg & 1;
+        }
         if (fl & 2) {                                // the ordered form, in the pass kernel
             rest();
+            __syncthreads();                         // rs is read by every thread
             continue;
         }
         if (fl & 1) {
@@ -2145,105 +2260,138 @@ __global__ __launch_bounds__(256, (kStreamWgs<R, kTri>)) void k_stream(StepArgs 
                 atomicOr(&W.flags[c], kFlagDone0 | (ph ? kFlagDone1 : 0));
             }
             if (left1) rest();
+            __syncthreads();
             continue;
         }
+        int nc = 0;                                  // candidate records written
         const double nab = v4[1];
         if (nab > 0.0) {
             const double coef = v4[0] * v4[2] / nab;
             const float kx = (float)(coef * A.dt * rej * 16777216.0);
-            // pair q = t + 256 u: U1's upper bits are word u & 3 of the draw
-            // hi_group(q) = (u >> 2) << 8 | t, one per four pairs
-            U4 hb{0u, 0u, 0u, 0u}, ht{0u, 0u, 0u, 0u};
-#pragma unroll 1
-            for (int u = 0; u < U; ++u) {
-                const int q = t + 256 * u;
-                if ((u & 3) == 0) {
-                    if (brm) hb = rng.draw(hi_group((uint32_t)q), cell, kTagHiBr);
-                    if (tri) ht = rng.draw(hi_group((uint32_t)q), cell, kTagHiTr);
+            const float kxf = kx * 1.001f;           // the filter's margin over the roundings of kx_needed
+            // the exact test of the pass kernel: every pair of the thread when
+            // two of them pass the filter, else the one that does
+            const auto open_pair = [&](int q, uint32_t bits) {
+                const int o = atomicAdd(&nopen, 1);
+                if (o < kCandCap) opn[o] = (uint32_t)q | (bits << 16);
+            };
+            if (lb.y2 <= kxf || lt.y2 <= kxf) {
+                for (int u = 0; u < U; ++u) {
+                    const int q = t + 256 * u;
+                    if ((u & 3) == 0) {
+                        if (brm) hb = rng.draw(hi_group((uint32_t)q), cell, kTagHiBr);
+                        if (tri) ht = rng.draw(hi_group((uint32_t)q), cell, kTagHiTr);
+                    }
+                    if (q >= N) continue;
+                    uint32_t bits = 0;
+                    const float s1 = sv[q];
+                    if (s1 > 0.0f && bound24(hi_word(hb, (uint32_t)u & 3u), kx * s1)) bits = 1u;
+                    if (tri && !bits) {
+                        const float s2 = svt[q];
+                        if (s2 > 0.0f && bound24(hi_word(ht, (uint32_t)u & 3u), kx * s2)) bits = 2u;
+                    }
+                    if (bits) open_pair(q, bits);
                 }
-                if (q >= N) continue;
-                uint32_t bits = 0;
-                const float s1 = sv[q];
-                if (s1 > 0.0f && bound24(hi_word(hb, (uint32_t)u & 3u), kx * s1)) bits = 1u;
-                if (tri && !bits) {
-                    const float s2 = svt[q];
-                    if (s2 > 0.0f && bound24(hi_word(ht, (uint32_t)u & 3u), kx * s2)) bits = 2u;
+            } else {
+                // Bremsstrahlung first, Trident where it fails; every other pair
+                // of the thread fails both filters, hence both tests.  The
+                // pair's word is drawn again.
+                const auto word = [&](int u, uint32_t tag) {
+                    return hi_word(rng.draw(hi_group((uint32_t)(t + 256 * u)), cell, tag), (uint32_t)u & 3u);
+                };
+                bool done_t = false;
+                if (lb.y1 <= kxf) {
+                    const int q = t + 256 * lb.u1;
+                    if (bound24(word(lb.u1, kTagHiBr), kx * sv[q])) {
+                        open_pair(q, 1u);
+                        done_t = tri && lt.u1 == lb.u1;
+                    }
                 }
-                if (bits) {
-                    const int o = atomicAdd(&nopen, 1);
-                    if (o < kCandCap) opn[o] = (uint32_t)q | (bits << 16);
+                if (tri && !done_t && lt.y1 <= kxf) {
+                    const int q = t + 256 * lt.u1;
+                    if (bound24(word(lt.u1, kTagHiTr), kx * svt[q])) open_pair(q, 2u);
                 }
             }
             __syncthreads();
-            const int n_open = nopen;
-            if (n_open > kCandCap) {
-                if (t == 0) mark_slow(W, c);
-            } else if (n_open > 0) {
-                // pair index of an open pair: the rank of its electron's key
-                rank_open<256>(N, cell, kTagKeyE, rng, opn, opk, opj, n_open);
-                if (t < n_open)
-                    push_cand(W, c, ev_pack(0, (int)opj[t], (int)(opn[t] & 0xFFFFu), 0, opn[t] >> 16));
+            nc = nopen;
+            if (nc > 0 && nc <= kCandCap && t < 64) {
+                // The event kernels use an open pair's index only to order the
+                // open pairs of a pass: every electron here pairs once, with
+                // interchangeable ions, so a pair's draws are keyed by its
+                // electron alone and nothing else depends on the index.  Its
+                // rank among the open pairs by (key, electron) orders them as
+                // the pair indices do, and stands for the index.
+                const bool has = t < nc;
+                const uint32_t mt = has ? (opn[t] & 0xFFFFu) : 0u;
+                uint32_t kt = 0u;
+                if (has) kt = hi_word(rng.draw(mt >> 2, cell, kTagKeyE), mt & 3u);
+                int rk = 0;
+                for (int j = 0; j < nc; ++j) {
+                    const uint32_t kj = (uint32_t)__builtin_amdgcn_readlane((int)kt, j);
+                    const uint32_t mj = (uint32_t)__builtin_amdgcn_readlane((int)mt, j);
+                    rk += (kj < kt || (kj == kt && mj < mt)) ? 1 : 0;
+                }
+                if (has) W.cand[c * kCandCap + t] = ev_pack(0, rk, (int)mt, 0, opn[t] >> 16);
             }
             if (t == 0) W.coef[c * 2] = coef;
         }
         if (ph) {
-            // n_g, A = sum min(W_g, W_i) and B, the same over the photons that
-            // pair once more: n_ab = fma(K, A, B), as the pass kernel forms it
-            double vg[4] = {0.0, 0.0, 0.0, 0.0};
-            if (t < Ng) {
-                const double m = gw < w0 ? gw : w0;
-                vg[0] = 0.0 + m;
-                vg[1] = (int)grank[t] < ee ? 0.0 + m : 0.0;
-            }
-            vg[0] = wave_sum(vg[0]);
-            vg[1] = wave_sum(vg[1]);
-            int fg = flg;
-            team_reduce4_bits<256>(vg, fg, red4, redi);
-            const double nabg = fma((double)K, vg[0], vg[1]);
-            if (t == 0) nopen = 0;
-            __syncthreads();
+            const double ng = ((pg[0] + pg[3]) + pg[6]) + pg[9];
+            const double Ag = ((pg[1] + pg[4]) + pg[7]) + pg[10];
+            const double Bg = ((pg[2] + pg[5]) + pg[8]) + pg[11];
+            const double nabg = fma((double)K, Ag, Bg);   // as the pass kernel forms it
             if (nabg > 0.0) {
-                const double coefg = v4[3] * v4[2] / nabg;
+                const double coefg = ng * v4[2] / nabg;
                 const float kxg = (float)(coefg * A.dt * rej * 16777216.0);
-                // a thread whose smallest value is near or below kx tests its
-                // pairs again with the pass kernel's bound (the margin covers
-                // the roundings of 1/(sigma c))
-                if (ymin <= kxg * 1.001f) {
-                    for (int j = 0; j < Gt; ++j) {
-                        const int g = t + 256 * j;
-                        const int base = ((g >> 8) << 10) | (g & 255);
-                        if (base >= X) continue;
-                        const U4 h = rng.draw((uint32_t)g, cell, kTagHiBh);
-                        for (int w = 0; w < 4; ++w) {
-                            const int x = base + 256 * w;
-                            if (x >= X) break;
-                            const int m = mod_small(x, Ng, rNg);
-                            const int k = __float2int_rn((float)(x - m) * rNg);
-                            if (!(k < (int)greps[m])) continue;
-                            const float sg = gsig[m];
-                            if (sg > 0.0f && bound24(hi_word(h, (uint32_t)w), kxg * sg * (float)phys::kC)) {
-                                const int o = atomicAdd(&nopen, 1);
-                                if (o < kCandCap) opn[o] = (uint32_t)m | ((uint32_t)k << 16);
+                const float kxgf = kxg * 1.001f;
+                const bool any = __syncthreads_or(lg.y1 <= kxgf) != 0;
+                if (any) {
+                    // the photon-ion tests again with the pass kernel's bound
+                    if (t == 0) nopen = 0;
+                    __syncthreads();
+                    const auto test = [&](int x, uint32_t wd) {
+                        const int m = mod_small(x, Ng, rNg);
+                        const int k = __float2int_rn((float)(x - m) * rNg);
+                        const float sg = gsig[m];
+                        if (k < (int)greps[m] && sg > 0.0f && bound24(wd, kxg * sg * (float)phys::kC)) {
+                            const int o = atomicAdd(&nopen, 1);
+                            if (o < kCandCap) opn[o] = (uint32_t)m | ((uint32_t)k << 16);
+                        }
+                    };
+                    if (lg.y2 <= kxgf) {
+                        for (int j = 0; j < Gt; ++j) {
+                            const int g = t + 256 * j;
+                            const int base = ((g >> 8) << 10) | (g & 255);
+                            if (base >= X) continue;
+                            const U4 h = rng.draw((uint32_t)g, cell, kTagHiBh);
+                            for (int w = 0; w < 4; ++w) {
+                                const int x = base + 256 * w;
+                                if (x >= X) break;
+                                test(x, hi_word(h, (uint32_t)w));
                             }
                         }
+                    } else if (lg.y1 <= kxgf) {
+                        // the key's word, drawn again
+                        const int x = lg.u1;
+                        const int g = ((x >> 10) << 8) | (x & 255);
+                        test(x, hi_word(rng.draw((uint32_t)g, cell, kTagHiBh), (uint32_t)(x >> 8) & 3u));
                     }
-                }
-                __syncthreads();
-                const int n_open = nopen;
-                if (n_open > kCandCap) {
-                    if (t == 0) mark_slow(W, c);
-                } else if (t < n_open) {
-                    // pair index: the photon's rank plus k N_g
-                    const uint32_t o = opn[t];
-                    const int m = (int)(o & 0xFFFFu), k = (int)(o >> 16);
-                    push_cand(W, c, ev_pack(1, (int)grank[m] + k * Ng, m, 0, 1u));
+                    __syncthreads();
+                    const int ngo = nopen;
+                    if (ngo > 0 && nc + ngo <= kCandCap && t < ngo) {
+                        // pair index: the photon's rank plus k N_g
+                        const uint32_t o = opn[t];
+                        const int m = (int)(o & 0xFFFFu), k = (int)(o >> 16);
+                        W.cand[c * kCandCap + nc + t] = ev_pack(1, (int)grank[m] + k * Ng, m, 0, 1u);
+                    }
+                    nc += ngo;
                 }
                 if (t == 0) W.coef[c * 2 + 1] = coefg;
             }
             if (t == 0) {
                 A.ti[c * CMC_NI + CMC_I_PAIRS_BH] = nabg > 0.0 ? Ni : 0;
                 A.td[c * CMC_ND + CMC_D_NAB_GI] = nabg;
-                if (nabg > 0.0 && (fg & 4)) atomicOr(A.status, CMC_ST_GAMMA_HIGH);
+                if (nabg > 0.0 && (flg & 4)) atomicOr(A.status, CMC_ST_GAMMA_HIGH);
             }
         }
         if (t == 0) {
@@ -2252,10 +2400,21 @@ __global__ __launch_bounds__(256, (kStreamWgs<R, kTri>)) void k_stream(StepArgs 
             A.td[c * CMC_ND + CMC_D_NAB_EI] = nab;
             if (nab > 0.0 && (fl & 4)) atomicOr(A.status, CMC_ST_GAMMA_HIGH);
             W.ionsum[c] = v4[2];
-            atomicOr(&W.flags[c], kFlagWeightsOk | kFlagIonsSame | kFlagDone0 | (ph ? kFlagDone1 : 0));
+            W.ncand[c] = nc;
+        }
+        __syncthreads();   // LDS of this cell is free
+        if (t == 0) {
+            // flags, then the lists (the only waits on atomics, after the barrier)
+            const int32_t f = kFlagWeightsOk | kFlagIonsSame | kFlagDone0 | (ph ? kFlagDone1 : 0) |
+                              (nc > kCandCap ? kFlagSlow : 0) | (nc > 0 ? kFlagListed : 0);
+            if (nc > 0) {
+                if (!(atomicOr(&W.flags[c], f) & kFlagListed))
+                    W.list_ev[atomicAdd(&W.counters[kCntEv], 1)] = (int32_t)c;
+            } else {
+                atomicOr(&W.flags[c], f);
+            }
         }
         if (left1) rest();
-        __syncthreads();   // LDS of this cell is free
     }
 }
 
