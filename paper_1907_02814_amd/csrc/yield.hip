@@ -41,6 +41,18 @@ __device__ __forceinline__ double one_minus_exp(double x) {
     return -expm1(-x);
 }
 
+// an electron record (momenta and weight)
+struct YRec { double x, y, z, w; };
+
+// A copy in registers of its own (an instruction the compiler cannot fold),
+// so that the registers a record arrived in may take the next load at once
+__device__ __forceinline__ double fresh(double v) {
+    double r;
+    asm("v_mov_b64 %0, %1" : "=v"(r) : "v"(v));
+    return r;
+}
+__device__ __forceinline__ YRec fresh(const YRec& r) { return YRec{fresh(r.x), fresh(r.y), fresh(r.z), fresh(r.w)}; }
+
 // 1/v in the form's precision: v holds an R value
 template <typename R>
 __device__ __forceinline__ double rcp_r(double v) {
@@ -96,29 +108,31 @@ __device__ __forceinline__ EPos<A> epos(const Axes& ax, A g, A gm1, bool& near) 
     const A tmin = (A)(grid::kTminEv / grid::kMec2Ev);
     if (f32 && fabs(gm1 - tmin) <= rt * tmin) near = true;
     if (!(gm1 > tmin)) return o;
-    const AxisDef* d;
-    A u;
-    int base;
+    // the segment's axis by value (selects of kernel arguments: a pointer
+    // chosen per lane would be read from memory, and each such read waits
+    // for every load in flight)
+    A u, u0, du;
+    int base, n;
     if (g <= (A)2) {
-        o.seg = kSegNR; d = &ax.nr; base = 0;
+        o.seg = kSegNR; u0 = (A)ax.nr.u0; du = (A)ax.nr.du; n = ax.nr.n; base = 0;
         u = Fast<A>::log(gm1);
     } else if (g <= (A)100) {
-        o.seg = kSegRel; d = &ax.rel; base = grid::kNR;
+        o.seg = kSegRel; u0 = (A)ax.rel.u0; du = (A)ax.rel.du; n = ax.rel.n; base = grid::kNR;
         u = Fast<A>::log(g);
     } else {
-        o.seg = kSegUR; d = &ax.ur; base = grid::kNR + grid::kRel;
+        o.seg = kSegUR; u0 = (A)ax.ur.u0; du = (A)ax.ur.du; n = ax.ur.n; base = grid::kNR + grid::kRel;
         u = g > (A)grid::kTop ? (A)log(grid::kTop) : Fast<A>::log(g);
     }
     if (f32 && (fabs(g - (A)2) <= rt * (A)2 || fabs(g - (A)100) <= rt * (A)100 ||
                 fabs(g - (A)grid::kTop) <= rt * (A)grid::kTop))
         near = true;
-    const A pos = Fast<A>::div(u - (A)d->u0, (A)d->du);
+    const A pos = Fast<A>::div(u - u0, du);
     int ig;
     if (pos <= (A)0) { ig = 0; o.w = (A)0; o.in = false; }
-    else if (pos >= (A)(d->n - 1)) { ig = d->n - 2; o.w = (A)1; o.in = false; }
+    else if (pos >= (A)(n - 1)) { ig = n - 2; o.w = (A)1; o.in = false; }
     else {
         ig = (int)pos;
-        if (ig > d->n - 2) ig = d->n - 2;
+        if (ig > n - 2) ig = n - 2;
         o.w = pos - (A)ig; o.in = true;
     }
     if (f32) {
@@ -292,9 +306,16 @@ __global__ __launch_bounds__(kThreads, sizeof(R) == 4 ? 4 : 3) void k_yield(YArg
                 for (int64_t j = j0 + threadIdx.x; j < j1; j += kThreads) A.yp[j] = 0.0;
             continue;
         }
-        int64_t j = j0 + threadIdx.x;
-        double nx = 0.0, ny = 0.0, nz = 0.0, nw = 0.0;
-        if (j < j1) { nx = A.px[j]; ny = A.py[j]; nz = A.pz[j]; nw = A.w[j]; }
+        // the first two records of each thread are in flight while thread 0
+        // computes the cell's screening state (reads clamped into the cell)
+        const int64_t j = j0 + threadIdx.x;
+        const bool any = j1 > j0;
+        const auto load = [&](int64_t k) {
+            const int64_t q = k < j1 ? k : j1 - 1;
+            return YRec{A.px[q], A.py[q], A.pz[q], A.w[q]};
+        };
+        YRec ra{}, rb{};
+        if (any) { ra = load(j); rb = load(j + kThreads); }
         if (threadIdx.x == 0) ct_s = cell_tab<R>(phys::screening(T.Z, Zs, ni, Te), T.ax);
         __syncthreads();
         {
@@ -303,25 +324,35 @@ __global__ __launch_bounds__(kThreads, sizeof(R) == 4 ? 4 : 3) void k_yield(YArg
         }
         __syncthreads();
         double acc = 0.0;
-        for (; j < j1; j += kThreads) {
-            const double qx = nx, qy = ny, qz = nz, w = nw;
-            if (j + kThreads < j1) {
-                nx = A.px[j + kThreads]; ny = A.py[j + kThreads]; nz = A.pz[j + kThreads]; nw = A.w[j + kThreads];
-            }
-            const R px = (R)qx, py = (R)qy, pz = (R)qz;
+        const auto eval = [&](int64_t k, const YRec& r) {
+            if (k >= j1) return;
+            const R px = (R)r.x, py = (R)r.y, pz = (R)r.z;
             const R p2 = px * px + py * py + pz * pz;
             const R g = Fast<R>::sqrt((R)1 + p2), gm1 = Fast<R>::div(p2, g + (R)1);
-            const EPos<R> e = electron_pos<R>(T.ax, g, gm1, qx, qy, qz);
+            const EPos<R> e = electron_pos<R>(T.ax, g, gm1, r.x, r.y, r.z);
             const BremsGrad<R> L = brems_grad<R>(e, sS, sK, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
             double y = 0.0;
             if (L.sig > 0.0) {
                 const double beta = (double)Fast<R>::div(Fast<R>::sqrt(p2), g);
                 const double x = ni * L.sig * beta * phys::kC * A.dt;
                 const double P = one_minus_exp(x);
-                y = w * P * (L.sk * rcp_r<R>(L.sig));
+                y = r.w * P * (L.sk * rcp_r<R>(L.sig));
             }
-            if (A.yp) A.yp[j] = y;
+            if (A.yp) A.yp[k] = y;
             acc += y;
+        };
+        // two records in flight, each in registers of its own: a record is
+        // copied out (fresh) before the load two ahead goes into its
+        // registers (moving a value still in flight waits for every load)
+        if (any) {
+            for (int64_t k = j; k < j1; k += 2 * kThreads) {
+                const YRec ca = fresh(ra);
+                ra = load(k + 2 * kThreads);
+                eval(k, ca);
+                const YRec cb = fresh(rb);
+                rb = load(k + 3 * kThreads);
+                eval(k + kThreads, cb);
+            }
         }
         const double s = ysum<kWaves>(acc, red);
         if (threadIdx.x == 0) A.Y[c] = s;
