@@ -1265,10 +1265,13 @@ __device__ __forceinline__ int mod_small(int j, int n, float rn) {
 
 // per-team LDS of the pass kernel
 constexpr int kSliceMax = 168;   // >= kSliceBrems, kSliceBH
-// the stream kernel: electrons per cell it takes at most, workgroups per CU
-// (the FP64 form and Trident need more registers)
+// the stream kernel: electrons per cell it takes at most, records in flight
+// per thread, workgroups per CU (measured on the foil cells: four with 128
+// registers beat five or six, which spill in the cell's prologue, and more
+// records in flight gained nothing)
 constexpr int kStreamCap = 4096;
-template <typename R, bool kTri> constexpr int kStreamWgs = sizeof(R) == 4 && !kTri ? 6 : 4;
+constexpr int kStreamDepth = 2;
+constexpr int kStreamWgs = 4;
 
 // The team's region holds the arrays of the rank sort or, in the direct
 // form of a cycled mobile species, the selection scratch (kSelBytes); the
@@ -2012,7 +2015,7 @@ __device__ __forceinline__ float kx_needed(uint32_t word, float s) {
 }
 
 template <typename R, bool kTri, bool kPh>
-__global__ __launch_bounds__(256, (kStreamWgs<R, kTri>)) void k_stream(StepArgs A, TabView<R> T, Work W, int scap,
+__global__ __launch_bounds__(256, kStreamWgs) void k_stream(StepArgs A, TabView<R> T, Work W, int scap,
                                                                      int from_list) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ R slice[kSliceMax];
@@ -2073,7 +2076,7 @@ __global__ __launch_bounds__(256, (kStreamWgs<R, kTri>)) void k_stream(StepArgs 
         const int Gt = ph ? (((X + 1023) >> 10) << 8) / 256 : 0;   // draw groups per thread
         const float rNg = ph ? 1.0f / (float)Ng : 0.0f;
         // Loads in the order their values are needed: the table slices (from
-        // L2) first, then the photons, then the first two electron records,
+        // L2) first, then the photons, then the first electron records,
         // which stay in flight through the staging and the photons' setup.
         if (brm)
             for (int i = t; i < kSliceBrems; i += 256) slice[i] = slice_node_brems<R>(T, ct, i);
@@ -2085,7 +2088,9 @@ __global__ __launch_bounds__(256, (kStreamWgs<R, kTri>)) void k_stream(StepArgs 
             gw = wo[t];
         }
         const double w0 = wion[0];
-        Rec r0 = load(0), r1 = load(1);
+        Rec rr[kStreamDepth];
+#pragma unroll
+        for (int d = 0; d < kStreamDepth; ++d) rr[d] = load(min(d, U - 1));
         if (ph && t < Ng) {
             const U4 r = rng.draw((uint32_t)t >> 2, cell, kTagKeyG);
             gkey[t] = hi_word(r, (uint32_t)t & 3u);
@@ -2198,20 +2203,20 @@ __global__ __launch_bounds__(256, (kStreamWgs<R, kTri>)) void k_stream(StepArgs 
             }
             if (ph && (u & 3) == 3 && (u >> 2) < Gt) group(u >> 2);
         };
-        // Two records in flight per thread, each in registers of its own: the
-        // walk takes two records a round, each copied out (fresh, once it has
-        // arrived) before the load of the record two ahead goes out into its
-        // registers.  A plain rotation (r0 = r1) would move a value still in
-        // flight, which waits for every load.  The last round's loads are
-        // clamped to the last record.
+        // kStreamDepth records in flight per thread, each in registers of its
+        // own: the walk takes kStreamDepth records a round, each copied out
+        // (fresh, once it has arrived) before the load of the record
+        // kStreamDepth ahead goes out into its registers.  A plain rotation
+        // (r0 = r1) would move a value still in flight, which waits for every
+        // load.  The last round's loads are clamped to the last record.
 #pragma unroll 1
-        for (int u = 0; u < U; u += 2) {
-            const Rec ca = fresh(r0);
-            r0 = load(min(u + 2, U - 1));
-            take(u, ca);
-            const Rec cb = fresh(r1);
-            r1 = load(min(u + 3, U - 1));
-            if (u + 1 < U) take(u + 1, cb);
+        for (int u0 = 0; u0 < U; u0 += kStreamDepth) {
+#pragma unroll
+            for (int d = 0; d < kStreamDepth; ++d) {
+                const Rec cur = fresh(rr[d]);
+                rr[d] = load(min(u0 + d + kStreamDepth, U - 1));
+                if (u0 + d < U) take(u0 + d, cur);
+            }
         }
         if (ph)
             for (int j = U >> 2; j < Gt; ++j) group(j);
