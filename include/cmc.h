@@ -132,7 +132,7 @@ typedef struct {
     uint64_t step;         /* step counter (keys the random numbers)          */
     uint32_t processes;    /* CMC_BREMS | CMC_BH | CMC_TRIDENT                */
     int32_t precision;     /* CMC_FP64 or CMC_FP32                            */
-    int32_t schedule;      /* 0 = automatic, see cmc_schedule_*               */
+    int32_t schedule;      /* 0 = automatic, see CMC_SCHED_*                  */
     int32_t max_per_cell;  /* upper bound of live electrons, photons and ions
                               per cell (<= CMC_MAX_PER_CELL); sizes the launch */
     double near_rel;       /* band |U - P| <= near_rel * P counted as near-threshold,
@@ -295,14 +295,22 @@ size_t cmc_noalloc_max_cells(void);
  *                   many ions, as in a foil's Bremsstrahlung -> Bethe-
  *                   Heitler chain;
  *  CMC_SCHED_AUTO   GROUP, WAVE (max_per_cell <= 1024) or HYBRID, QUEUE
- *                   and, with both passes on, SPLIT, whichever is fastest
- *                   on the first step of a
+ *                   and, with both passes on, SPLIT, each with and without
+ *                   the stream kernel, whichever is fastest on the first
+ *                   step of a
  *                   launch shape (device, n_cells, max_per_cell, processes,
  *                   precision): that first call times them and waits for
  *                   the timing; under stream capture an untimed shape uses
  *                   GROUP. */
 enum { CMC_SCHED_AUTO = 0, CMC_SCHED_CELL = 1, CMC_SCHED_GROUP = 2, CMC_SCHED_WAVE = 3, CMC_SCHED_HYBRID = 4,
        CMC_SCHED_QUEUE = 5, CMC_SCHED_SPLIT = 6 };
+/* Every schedule but CELL and WAVE first runs the stream kernel: one
+ * workgroup walks each cell whose ions are at rest and whose electrons
+ * each pair once (N_i <= N_e, 1024 < N_e <= 4096), reading every record
+ * once for both passes; the other cells take the schedule's teams.  OR-ing
+ * CMC_SCHED_NO_STREAM into the schedule leaves every cell to its teams (the
+ * same decisions and products). */
+#define CMC_SCHED_NO_STREAM 0x100
 
 /* ------------------------------------------------------------------ */
 /* Expected photon energy yield (deterministic): for every cell c,      */

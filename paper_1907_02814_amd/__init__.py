@@ -24,6 +24,7 @@ LIB_PATH = os.path.join(HERE, "libcmc.so")
 BREMS, BH, TRIDENT = 1, 2, 4
 FP64, FP32 = 0, 1
 SCHED_AUTO, SCHED_CELL, SCHED_GROUP, SCHED_WAVE, SCHED_HYBRID, SCHED_QUEUE, SCHED_SPLIT = 0, 1, 2, 3, 4, 5, 6
+SCHED_NO_STREAM = 0x100   # OR-ed into a schedule: no stream kernel
 SCREEN_REDUCED, SCREEN_TFD = 0, 1
 MAX_PER_CELL = 16384
 ST_OVERFLOW, ST_GAMMA_HIGH, ST_BAD_CELL, ST_BAD_WEIGHT, ST_TOO_LARGE, ST_BAD_OFFSETS = 1, 2, 4, 8, 16, 32

@@ -777,9 +777,9 @@ constexpr int kStagePh = 1024;   // photons the event kernel stages in LDS per c
 // (kFlagIonsSame: the ions share one weight), so that the photon-ion pass
 // reads neither the ions' nor the electrons' weights again; kFlagDone0,
 // kFlagDone1: the stream kernel has run the cell's electron-ion pass, its
-// photon-ion pass; kFlagRest: the cell is in list_rest
+// photon-ion pass
 enum : int32_t { kFlagSlow = 1, kFlagListed = 2, kFlagBig0 = 4, kFlagBig1 = 8, kFlagWeightsOk = 16, kFlagIonsSame = 32,
-                 kFlagDone0 = 64, kFlagDone1 = 128, kFlagRest = 256 };
+                 kFlagDone0 = 64, kFlagDone1 = 128 };
 enum : uint32_t { kEvBr = 1, kEvTrPending = 2, kEvTr = 4, kEvBh = 8 };
 
 struct CellState {
@@ -794,7 +794,6 @@ enum : int {
     kCntBig0 = 1,    // electron-ion passes deferred to the large-LDS launch (list_big[0])
     kCntBig1 = 2,    // photon-ion passes deferred (list_big[1])
     kCntWg = 3,      // listed cells the wavefront event kernel hands to the workgroup one (list_wg)
-    kCntRest = 4,    // cells the stream kernel leaves (wholly or in part) to the pass kernel (list_rest)
     kNumCnt = 8
 };
 
@@ -810,7 +809,7 @@ struct Work {
     int32_t* list_wg;                // listed cells that need the workgroup event kernel
     int32_t* list_big[2];            // per pass: cells whose pass needs more LDS than the first launch has
     int32_t* queue;                  // the cells in decreasing order of cost (batched schedule)
-    int32_t* list_rest;              // cells with a pass the stream kernel did not run
+    int32_t* list_rest;              // per item of the stream kernel's walk: its cell if a pass is left, else -1
     uint64_t* cand;                  // [n_cells][kCandCap] open pairs
 };
 
@@ -1976,7 +1975,7 @@ __device__ __forceinline__ void pass_cell(const StepArgs& A, const TabView<R>& T
 // count (no atomics per pair); the cell is listed for the event kernels
 // once, after the workgroup's last barrier.  Done passes are flagged
 // (kFlagDone0, kFlagDone1); cells of unequal ion weights, and all others,
-// are left to the pass kernel, listed in list_rest (a cell whose photon-ion
+// are left to the pass kernel, marked in list_rest (a cell whose photon-ion
 // pass is left, too).  One workgroup per cell, walking the cells in index
 // order or (from_list 2) the work queue.
 constexpr int kStreamPh = 256;   // photons per cell the stream kernel's photon-ion pass takes
@@ -2048,14 +2047,18 @@ __global__ __launch_bounds__(256, kStreamWgs) void k_stream(StepArgs A, TabView<
         const int icn = A.io.count ? A.io.count[c] : 0x7FFFFFFF;
         const int Ne = max(0, min(ecn, (int)(eo1 - e0))), Ng = max(0, min(gcn, (int)(go1 - g0)));
         const int Ni = max(0, min(icn, (int)(io1 - i0)));
-        // the cell to the pass kernel (one thread lists it, once a step)
-        const auto rest = [&]() {
-            if (t == 0 && !(atomicOr(&W.flags[c], kFlagRest) & kFlagRest))
-                W.list_rest[atomicAdd(&W.counters[kCntRest], 1)] = (int32_t)c;
+        // item's entry of list_rest: the cell, when a pass is left to the
+        // pass kernel, else -1 (the pass kernel walks the entries in the
+        // order of this walk: index order, or the work queue's)
+        const auto rest = [&](bool left) {
+            if (t == 0) W.list_rest[item] = left ? (int32_t)c : -1;
         };
-        if (cstat) continue;                     // invalid cell (flagged by k_cell_state)
+        if (cstat) {                             // invalid cell (flagged by k_cell_state)
+            rest(false);
+            continue;
+        }
         if (Ni == 0 || Ne < Ni || Ne <= 1024 || Ne > scap || Ne > A.maxn || Ng > A.maxn) {
-            rest();
+            rest(true);
             continue;
         }
         const int N = Ne, U = (N + 255) / 256;
@@ -2254,7 +2257,7 @@ __global__ __launch_bounds__(256, kStreamWgs) void k_stream(StepArgs A, TabView<
             fl |= flg & 1;
         }
         if (fl & 2) {                                // the ordered form, in the pass kernel
-            rest();
+            rest(true);
             __syncthreads();                         // rs is read by every thread
             continue;
         }
@@ -2264,7 +2267,7 @@ __global__ __launch_bounds__(256, kStreamWgs) void k_stream(StepArgs A, TabView<
                 atomicOr(A.status, CMC_ST_BAD_WEIGHT);
                 atomicOr(&W.flags[c], kFlagDone0 | (ph ? kFlagDone1 : 0));
             }
-            if (left1) rest();
+            rest(left1);
             __syncthreads();
             continue;
         }
@@ -2419,7 +2422,7 @@ __global__ __launch_bounds__(256, kStreamWgs) void k_stream(StepArgs A, TabView<
                 atomicOr(&W.flags[c], f);
             }
         }
-        if (left1) rest();
+        rest(left1);
     }
 }
 
@@ -2464,16 +2467,16 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
 
     const PassLds L{red4, redu, redi, opn[team], opk[team], opj[team], &nopen[team]};
     // from_list 0: every cell in index order; 1: the pass's deferred list;
-    // 3: the cells the stream kernel left;
+    // 3: the cells the stream kernel left, in the order of its walk;
     // 2: the work queue, the cells costliest first (workgroups are
     // dispatched in index order as compute units free up, so the largest
     // cells start first and the rest fill in behind them)
-    const int64_t n_items = from_list == 1 ? (int64_t)W.counters[kPass == 1 ? kCntBig1 : kCntBig0]
-                          : from_list == 3 ? (int64_t)W.counters[kCntRest] : A.n_cells;
+    const int64_t n_items = from_list == 1 ? (int64_t)W.counters[kPass == 1 ? kCntBig1 : kCntBig0] : A.n_cells;
     for (int64_t item = (int64_t)blockIdx.x * kTeams + team; item < n_items; item += (int64_t)gridDim.x * kTeams) {
         const int64_t c = from_list == 2 ? (int64_t)W.queue[item]
                         : from_list == 3 ? (int64_t)W.list_rest[item]
                         : from_list ? (int64_t)W.list_big[kPass == 1 ? 1 : 0][item] : item;
+        if (c < 0) continue;                     // done by the stream kernel
         PassCarry carry{0, 0.0};
         if constexpr (kPass != 1)
             pass_cell<R, kT, 0, kMov, false>(A, T, W, cap, filter, fcap, slow_cap, c, M, rng, rej, t, L, carry);
@@ -3442,8 +3445,19 @@ static bool launch_stream(const StepArgs& A, const cmc_tables_s* t, const Work& 
     return true;
 }
 
-static cmc_status launch_passes(const StepArgs& A, const cmc_tables_s* t, const Work& W, bool fp64, int shape,
+// A launch plan of the pair tests: the team shape, and whether the stream
+// kernel runs first
+struct Plan {
+    int team;
+    bool stream;
+};
+
+static cmc_status launch_passes(const StepArgs& A, const cmc_tables_s* t, const Work& W, bool fp64, Plan plan,
                                 hipStream_t st, PassTiming* pt = nullptr) {
+    const int shape = plan.team;
+    const auto launch_stream = [&](int from_list) {
+        return plan.stream && ::launch_stream(A, t, W, fp64, team_cap(256, A.maxn, fp64, 1), from_list, st, pt);
+    };
     const int big = team_cap(256, A.maxn, fp64, 1);
     const int main = std::min(big, team_cap(256, A.maxn, fp64, kMainWgs));
     const int small = team_cap(64, A.maxn, fp64);
@@ -3455,7 +3469,7 @@ static cmc_status launch_passes(const StepArgs& A, const cmc_tables_s* t, const 
         // one launch per pass (the fused wavefront kernel holds too many
         // registers for the occupancy the photon-ion pass needs)
         const int sc = std::min(big, kSplitCap);
-        const int fl = launch_stream(A, t, W, fp64, big, 0, st, pt) ? 3 : 0;
+        const int fl = launch_stream(0) ? 3 : 0;
         launch_team(A, t, W, fp64, 64, sc, 0, 0, big, fl, 256 * 64, st, pt, 1);
         launch_team(A, t, W, fp64, 64, sc, 0, 0, big, fl, 256 * 64, st, pt, 2);
         if (big > sc) launch_team(A, t, W, fp64, 256, big, 0, 0, big, 1, 1024, st, pt);
@@ -3465,11 +3479,11 @@ static cmc_status launch_passes(const StepArgs& A, const cmc_tables_s* t, const 
         // after the stream kernel, the cells it left (listed in about the
         // order it took them from the queue)
         hipLaunchKernelGGL(k_queue, dim3(1), dim3(kQThreads), 0, st, A, W);
-        const int fl = launch_stream(A, t, W, fp64, big, 2, st, pt) ? 3 : 2;
+        const int fl = launch_stream(2) ? 3 : 2;
         launch_team(A, t, W, fp64, 256, main, 0, 0, big, fl, (int64_t)1 << 20, st, pt);
         if (big > main) launch_team(A, t, W, fp64, 256, big, 0, 0, big, 1, 1024, st, pt);
     } else {
-        const int fl = launch_stream(A, t, W, fp64, big, 0, st, pt) ? 3 : 0;
+        const int fl = launch_stream(0) ? 3 : 0;
         if (shape == kHybrid) {
             launch_team(A, t, W, fp64, 64, small, 1, small, big, fl, 256 * 64, st, pt);
             launch_team(A, t, W, fp64, 256, main, 2, small, big, fl, 256 * 64, st, pt);
@@ -3483,38 +3497,44 @@ static cmc_status launch_passes(const StepArgs& A, const cmc_tables_s* t, const 
     return CMC_OK;
 }
 
-// Autotuner of the pass kernels' team shape: on the first step of a launch
-// shape (device, cells, max_per_cell, processes, precision) both shapes are
-// timed on that step's own cells (the pass kernels leave the particles
-// untouched; the cell state is cleared again afterwards) and the faster one
-// is kept for the process.  The host waits for the timing once per shape.
+// Autotuner of the pair-test launches: on the first step of a launch shape
+// (device, cells, max_per_cell, processes, precision, moving ions, stream
+// kernel allowed) each plan (team shape, with or without the stream kernel)
+// is timed on that step's own cells (the pass kernels leave the particles
+// untouched; the cell state is cleared before each plan and again
+// afterwards) and the fastest is kept for the process.  The host waits for
+// the timing once per launch shape.
 struct TuneKey {
     int dev;
     int64_t n_cells;
-    int maxn, proc, precision, moving;
+    int maxn, proc, precision, moving, no_stream;
     bool operator<(const TuneKey& o) const {
-        return std::tie(dev, n_cells, maxn, proc, precision, moving) <
-               std::tie(o.dev, o.n_cells, o.maxn, o.proc, o.precision, o.moving);
+        return std::tie(dev, n_cells, maxn, proc, precision, moving, no_stream) <
+               std::tie(o.dev, o.n_cells, o.maxn, o.proc, o.precision, o.moving, o.no_stream);
     }
 };
 static std::mutex g_tune_mu;
-static std::map<TuneKey, int> g_tune;
+static std::map<TuneKey, Plan> g_tune;
 
-static bool tune_lookup(const TuneKey& k, int& team) {
+static bool tune_lookup(const TuneKey& k, Plan& plan) {
     std::lock_guard<std::mutex> g(g_tune_mu);
     auto it = g_tune.find(k);
     if (it == g_tune.end()) return false;
-    team = it->second;
+    plan = it->second;
     return true;
 }
 
-static void tune_store(const TuneKey& k, int team) {
+static void tune_store(const TuneKey& k, Plan plan) {
     std::lock_guard<std::mutex> g(g_tune_mu);
-    g_tune[k] = team;
+    g_tune[k] = plan;
 }
 
+// reset() clears the cells' flags and counters (the cell-state launch)
+// before each plan is timed: flags one plan sets (passes done by the
+// stream kernel) would let another skip work.
+template <typename Reset>
 static cmc_status tune_passes(const StepArgs& A, const cmc_tables_s* t, const Work& W, bool fp64, hipStream_t st,
-                              int& best) {
+                              bool allow_stream, Plan& best, const Reset& reset) {
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) { set_error("cmc_collide_step: hipEventCreate failed"); return CMC_EDEVICE; }
     if (hipEventCreate(&e1) != hipSuccess) {
@@ -3523,23 +3543,38 @@ static cmc_status tune_passes(const StepArgs& A, const cmc_tables_s* t, const Wo
         return CMC_EDEVICE;
     }
     float best_ms = 0.0f;
-    best = 256;
     cmc_status rc = CMC_OK;
     const int other = A.maxn <= team_cap(64, A.maxn, fp64) ? 64 : kHybrid;
     const bool both = (A.proc & (CMC_BREMS | CMC_TRIDENT)) && (A.proc & CMC_BH);
-    for (int team : {256, other, kQueue, both ? kSplit : 256}) {
-        if (team == 256 && best_ms > 0.0f) continue;
-        if ((rc = launch_passes(A, t, W, fp64, team, st)) != CMC_OK) break;   // warm-up
+    // the stream kernel applies to ions at rest with an electron-ion process
+    const bool sk = allow_stream && !A.io.px && (A.proc & (CMC_BREMS | CMC_TRIDENT));
+    Plan plans[6];
+    int np = 0;
+    plans[np++] = Plan{256, sk};            // the reference: workgroup teams
+    if (sk) plans[np++] = Plan{256, false};
+    plans[np++] = Plan{other, sk && other != 64};
+    plans[np++] = Plan{kQueue, false};
+    if (sk) plans[np++] = Plan{kQueue, true};
+    if (both) plans[np++] = Plan{kSplit, sk};
+    best = plans[0];
+    for (int i = 0; i < np; ++i) {
+        const Plan p = plans[i];
+        reset();
+        if ((rc = launch_passes(A, t, W, fp64, p, st)) != CMC_OK) break;   // warm-up
         (void)hipEventRecord(e0, st);
-        for (int r = 0; r < 3 && rc == CMC_OK; ++r) rc = launch_passes(A, t, W, fp64, team, st);
+        for (int r = 0; r < 3 && rc == CMC_OK; ++r) rc = launch_passes(A, t, W, fp64, p, st);
         (void)hipEventRecord(e1, st);
         if (rc != CMC_OK) break;
         if (hipEventSynchronize(e1) != hipSuccess) { set_error("cmc_collide_step: timing failed"); rc = CMC_EDEVICE; break; }
         float ms = 0.0f;
         (void)hipEventElapsedTime(&ms, e0, e1);
-        // another shape must beat workgroup teams by 3% (timing noise of a
-        // few runs would otherwise pick a slower shape now and then)
-        if (team == 256 || ms < best_ms * (best == 256 ? 0.97f : 1.0f)) { best_ms = ms; best = team; }
+        // another plan must beat the reference by 3% (timing noise of a
+        // few runs would otherwise pick a slower plan now and then)
+        if (i == 0 || ms < best_ms * (i > 0 && best.team == plans[0].team && best.stream == plans[0].stream
+                                          ? 0.97f : 1.0f)) {
+            best_ms = ms;
+            best = p;
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -3547,7 +3582,7 @@ static cmc_status tune_passes(const StepArgs& A, const cmc_tables_s* t, const Wo
 }
 
 extern "C" size_t cmc_step_workspace_bytes(int64_t n_cells, int32_t schedule) {
-    if (n_cells <= 0 || schedule == CMC_SCHED_CELL) return 0;
+    if (n_cells <= 0 || (schedule & ~CMC_SCHED_NO_STREAM) == CMC_SCHED_CELL) return 0;
     return work_bytes(n_cells);
 }
 
@@ -3576,7 +3611,8 @@ static cmc_status collide_step_impl(const char* who, cmc_tables t, const cmc_cel
     CMC_REQUIRE((P->processes & ~7u) == 0, CMC_EINVAL, "%s: unknown process bits", who);
     CMC_REQUIRE(P->precision == CMC_FP64 || P->precision == CMC_FP32, CMC_EINVAL,
                 "%s: unknown precision %d", who, P->precision);
-    CMC_REQUIRE(P->schedule >= 0 && P->schedule <= 6, CMC_EINVAL, "%s: unknown schedule", who);
+    CMC_REQUIRE((P->schedule & ~CMC_SCHED_NO_STREAM) >= 0 && (P->schedule & ~CMC_SCHED_NO_STREAM) <= 6, CMC_EINVAL,
+                "%s: unknown schedule", who);
     CMC_REQUIRE(P->max_per_cell >= 1 && P->max_per_cell <= CMC_MAX_PER_CELL, CMC_ERANGE,
                 "%s: max_per_cell = %d outside [1, %d]", who, P->max_per_cell, CMC_MAX_PER_CELL);
     CMC_REQUIRE(P->near_rel >= 0.0 && P->near_rel <= 1.0, CMC_EINVAL, "%s: near_rel outside [0, 1]", who);
@@ -3602,7 +3638,7 @@ static cmc_status collide_step_impl(const char* who, cmc_tables t, const cmc_cel
     const size_t shm = smem_bytes(A.maxn);
     const int grid = grid_for(A.n_cells);
     const bool fp64 = P->precision == CMC_FP64;
-    if (P->schedule == CMC_SCHED_CELL) {
+    if ((P->schedule & ~CMC_SCHED_NO_STREAM) == CMC_SCHED_CELL) {
         // one sequential workgroup per cell for every cell
         A.list = nullptr; A.list_n = nullptr;
         A.step_dev = P->step_counter;
@@ -3630,17 +3666,19 @@ static cmc_status collide_step_impl(const char* who, cmc_tables t, const cmc_cel
                            0, st, A.Zs, A.ni, A.Te, A.n_cells, (double)t->Z, t->ax, W, A.ti, A.td, A.status,
                            P->step_counter, P->step, advance);
     };
-    int team = P->schedule == CMC_SCHED_WAVE ? 64
-             : P->schedule == CMC_SCHED_HYBRID ? kHybrid
-             : P->schedule == CMC_SCHED_QUEUE ? kQueue
-             : P->schedule == CMC_SCHED_SPLIT ? kSplit : 256;
-    bool tuned = P->schedule != CMC_SCHED_AUTO;
+    const int sched = P->schedule & ~CMC_SCHED_NO_STREAM;
+    const bool allow_stream = !(P->schedule & CMC_SCHED_NO_STREAM);
+    Plan plan{sched == CMC_SCHED_WAVE ? 64
+              : sched == CMC_SCHED_HYBRID ? kHybrid
+              : sched == CMC_SCHED_QUEUE ? kQueue
+              : sched == CMC_SCHED_SPLIT ? kSplit : 256, allow_stream};
+    bool tuned = sched != CMC_SCHED_AUTO;
     TuneKey key{};
     if (!tuned) {
         int dev = 0;
         (void)hipGetDevice(&dev);
-        key = TuneKey{dev, A.n_cells, A.maxn, (int)A.proc, P->precision, A.io.px ? 1 : 0};
-        tuned = tune_lookup(key, team);
+        key = TuneKey{dev, A.n_cells, A.maxn, (int)A.proc, P->precision, A.io.px ? 1 : 0, allow_stream ? 0 : 1};
+        tuned = tune_lookup(key, plan);
     }
     // the counter advances once, in the last cell-state launch of the step
     cell_state(tuned ? 1 : 0);
@@ -3649,17 +3687,17 @@ static cmc_status collide_step_impl(const char* who, cmc_tables t, const cmc_cel
         hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
         (void)hipStreamIsCapturing(st, &cap);
         if (cap == hipStreamCaptureStatusNone && may_time) {
-            cmc_status s2 = tune_passes(A, t, W, fp64, st, team);
+            cmc_status s2 = tune_passes(A, t, W, fp64, st, allow_stream, plan, [&]() { cell_state(0); });
             if (s2 != CMC_OK) return s2;
-            tune_store(key, team);
+            tune_store(key, plan);
         } else {
-            team = 256;         // no timing under graph capture: workgroup teams
+            plan = Plan{256, allow_stream};   // no timing under graph capture: workgroup teams
         }
         cell_state(1);          // the timing runs filled the cell lists
         CMC_CHECK_LAUNCH2(who, "k_cell_state");
     }
     PassTiming timing{static_cast<hipEvent_t>(P->pass_events[0]), static_cast<hipEvent_t>(P->pass_events[1]), true};
-    cmc_status s1 = launch_passes(A, t, W, fp64, team, st,
+    cmc_status s1 = launch_passes(A, t, W, fp64, plan, st,
                                   (P->pass_events[0] && P->pass_events[1]) ? &timing : nullptr);
     if (s1 != CMC_OK) return s1;
     // the listed cells: open pairs and events, or the sequential step (a

@@ -1,11 +1,12 @@
 """Parity at the benchmark sizes, in the launch configuration bench.py times
 (automatic schedule): cfg2 in full (4096 cells x (1024 photons + 1024 Au
-ions), FP32 form) against the oracle; foil-chain cells at their full size
-(4096 electrons + 4096 Au ions, all processes); cfg3 in full (16384 uneven
-cells, all processes) on the GPU against the oracle on a sample of its
-cells (the random numbers are keyed by the global cell index); the expected
-yield and its adjoint on cfg4 in full (1024 cells x 4096 electrons), both
-forms, against the oracle on every cell and electron."""
+ions), both forms) against the oracle; foil-chain cells at their full size
+(4096 electrons + 4096 Au ions, all processes); cfg5 in full and cfg3 in
+full (16384 uneven cells, all processes), both forms over three steps, on
+the GPU against the oracle on a sample of their cells (the random numbers
+are keyed by the global cell index); the expected yield and its adjoint on
+cfg4 in full (1024 cells x 4096 electrons), both forms, against the oracle
+on every cell and electron."""
 import numpy as np
 import pytest
 
@@ -82,27 +83,51 @@ def test_cfg5_full_size_sampled_cells(precision):
         torch.cuda.empty_cache()
 
 
-def test_cfg3_full_sampled_cells():
+@pytest.mark.parametrize("precision", [1, 0])
+def test_cfg3_full_sampled_cells(precision):
+    """cfg3 in full (16384 uneven cells, all processes), in the batched
+    schedule the benchmark uses for it (automatic: the work queue), three
+    steps: 256 seeded cells and the 8 largest against the oracle run on the
+    same cells with their global ids, after every step."""
     import torch
     import paper_1907_02814_amd as cmc
-    from gpu_parity import compare_sampled_cells, gpu_tables
+    from gpu_parity import compare_host_subsets, gpu_tables
     wl = W.cfg3()
     g = wl.copy().to_torch("cuda:0")
     st = cmc.StepState(gpu_tables(wl.Z), g.cells, g.electrons, g.photons, g.ions, g.new_el, g.new_po,
-                       dt=wl.dt, seed=1, processes=wl.processes, precision=cmc.FP32)
-    st.step(0)
-    torch.cuda.synchronize()
+                       dt=wl.dt, seed=1, processes=wl.processes, precision=precision)
     sample = np.sort(np.random.default_rng(5).choice(wl.n_cells, 256, replace=False))
-    # the largest cells too
     big = np.argsort(np.diff(wl.electrons["off"]) + np.diff(wl.ions["off"]))[-8:]
     sample = np.unique(np.concatenate([sample, big]))
-    ref = wl.subset(sample)
-    oti, otd, ost = O.collide_step(O.tables(wl.Z), ref.cells, ref.electrons, ref.photons, ref.ions,
-                                   ref.new_el, ref.new_po, wl.dt, 1, 0, wl.processes)
-    flips = compare_sampled_cells(g, st, ref, sample, oti, otd, 1e-5)
-    print(f"[parity] cfg3 full, {len(sample)} sampled cells: {flips} with a near-threshold decision")
-    assert flips <= 2
-    assert oti[:, 0:3].sum() > 1e5
+    ref = g.host_subset(sample)
+    rtol = 1e-12 if precision == cmc.FP64 else 1e-5
+    skip = np.zeros(len(sample), bool)
+    pairs = 0
+    for s in range(3):
+        st.step(s)
+        torch.cuda.synchronize()
+        oti, otd, ost = O.collide_step(O.tables(wl.Z), ref.cells, ref.electrons, ref.photons, ref.ions,
+                                       ref.new_el, ref.new_po, wl.dt, 1, s, wl.processes)
+        now = g.host_subset(sample)
+        skip, errs = compare_host_subsets(st.ti.cpu().numpy()[sample], st.td.cpu().numpy()[sample], now, ref,
+                                          oti, otd, rtol, skip)
+        pairs += int(oti[:, 0:3].sum())
+        print(f"[parity] cfg3 full, precision {precision}, step {s}: {int(skip.sum())} cell(s) left out "
+              f"(near threshold); " + ", ".join(f"{k} {v:.1e}" for k, v in errs.items()))
+    assert skip.sum() <= 4
+    assert pairs > 3e5
+
+
+def test_cfg2_full_size_fp64():
+    import paper_1907_02814_amd as cmc
+    from gpu_parity import Parity
+    wl = W.cfg2()
+    P = Parity(wl, precision=cmc.FP64)
+    for s in range(2):
+        P.step(s)
+    print(f"[parity] cfg2 full FP64: {P.flips} flip(s); " + ", ".join(f"{k} {v:.1e}" for k, v in P.errors.items()))
+    assert P.flips <= 2
+    assert P.state.ti.cpu().numpy()[:, 2].sum() > 4_000_000
 
 
 @pytest.mark.parametrize("precision,rtol", [(0, 1e-12), (1, 1e-5)])

@@ -55,7 +55,17 @@ def _snap(g, st):
     return out
 
 
+def _sched(name):
+    """SCHED_<name>; a trailing "-" adds CMC_SCHED_NO_STREAM (no stream kernel)"""
+    import paper_1907_02814_amd as cmc
+    if name.endswith("-"):
+        return getattr(cmc, "SCHED_" + name[:-1]) | cmc.SCHED_NO_STREAM
+    return getattr(cmc, "SCHED_" + name)
+
+
 @pytest.mark.parametrize("precision,other,hi,moving", [(0, "WAVE", 480, False), (1, "WAVE", 480, False),
+                                                       (0, "GROUP-", 3000, False), (1, "GROUP-", 3000, "weights"),
+                                                       (1, "QUEUE-", 3000, False),
                                                        (1, "HYBRID", 3000, False), (0, "HYBRID", 3000, True),
                                                        (1, "WAVE", 480, "weights"), (0, "QUEUE", 3000, False),
                                                        (1, "QUEUE", 3000, "weights"), (1, "QUEUE", 3000, True),
@@ -70,7 +80,7 @@ def test_team_shapes_bit_identical(precision, other, hi, moving):
     elif moving:
         W.moving_ions(wl, np.random.default_rng(23), 0.5)
     ga, sa = _state(wl, cmc.SCHED_GROUP, precision)
-    gb, sb = _state(wl, getattr(cmc, "SCHED_" + other), precision)
+    gb, sb = _state(wl, _sched(other), precision)
     for s in range(3):
         sa.step(s)
         sb.step(s)
@@ -102,13 +112,13 @@ def test_sequential_schedule_agrees(precision, moving):
     assert A["ti"][:, 3:6].sum() > 50
 
 
-@pytest.mark.parametrize("schedule", ["AUTO", "QUEUE", "SPLIT"])
+@pytest.mark.parametrize("schedule", ["AUTO", "QUEUE", "SPLIT", "QUEUE-"])
 def test_graph_replay_matches_eager_steps(schedule):
     """(the work queue is rebuilt and drained inside the captured step)"""
     import torch
     import paper_1907_02814_amd as cmc
     wl = W.cfg3(np.random.default_rng(23), n_cells=96, dt=2e-13, lo=1, hi=1200)
-    sched = getattr(cmc, "SCHED_" + schedule)
+    sched = _sched(schedule)
     ge, se = _state(wl, sched, cmc.FP32)
     gg, sg = _state(wl, sched, cmc.FP32)
     se.step(0)
@@ -152,10 +162,11 @@ def test_cycled_photons_bit_identical_across_team_shapes(precision, other):
 def test_foil_cells_bit_identical_across_schedules(precision):
     """Foil cells (4096 electrons + 4096 Au ions, the photons of earlier steps
     cycled against the ions): the stream kernel with workgroup teams, with
-    wavefront teams (SPLIT) and from the work queue give the same bits."""
+    wavefront teams (SPLIT) and from the work queue, and the same schedules
+    without it, give the same bits."""
     import paper_1907_02814_amd as cmc
     wl = W.cfg5(np.random.default_rng(61), n_cells=48, per_cell=4096, dt=4e-15, processes=7)
-    states = [_state(wl, getattr(cmc, "SCHED_" + s), precision) for s in ("GROUP", "SPLIT", "QUEUE")]
+    states = [_state(wl, _sched(s), precision) for s in ("GROUP", "SPLIT", "QUEUE", "GROUP-", "QUEUE-", "SPLIT-")]
     for s in range(4):
         snaps = []
         for g, st in states:
