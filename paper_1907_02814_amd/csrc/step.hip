@@ -23,6 +23,7 @@
 #include <mutex>
 #include <tuple>
 #include <type_traits>
+#include <utility>
 
 #include "common.hpp"
 #include "philox.hpp"
@@ -1265,12 +1266,14 @@ __device__ __forceinline__ int mod_small(int j, int n, float rn) {
 // per-team LDS of the pass kernel
 constexpr int kSliceMax = 168;   // >= kSliceBrems, kSliceBH
 // the stream kernel: electrons per cell it takes at most, records in flight
-// per thread, workgroups per CU (measured on the foil cells: four with 128
-// registers beat five or six, which spill in the cell's prologue, and more
-// records in flight gained nothing)
+// per thread, threads per cell, wavefronts per SIMD (the second launch
+// bound; measured on the foil cells: four with 128 registers beat five or
+// six, which spill in the cell's prologue, and more records in flight
+// gained nothing)
 constexpr int kStreamCap = 4096;
 constexpr int kStreamDepth = 2;
-constexpr int kStreamWgs = 4;
+constexpr int kStreamThreads = 256;
+constexpr int kStreamWaves = 4;
 
 // The team's region holds the arrays of the rank sort or, in the direct
 // form of a cycled mobile species, the selection scratch (kSelBytes); the
@@ -1980,6 +1983,12 @@ __device__ __forceinline__ void pass_cell(const StepArgs& A, const TabView<R>& T
 // order or (from_list 2) the work queue.
 constexpr int kStreamPh = 256;   // photons per cell the stream kernel's photon-ion pass takes
 
+// f(integral_constant<int, I>) for I = 0, 1, ... in order, unrolled
+template <int... I, typename F>
+__device__ __forceinline__ void unrolled(std::integer_sequence<int, I...>, F&& f) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+
 // An electron record of the stream kernel's walk, and the ion weight beside it
 struct Rec { double x, y, z, w, wi; };
 
@@ -2014,15 +2023,22 @@ __device__ __forceinline__ float kx_needed(uint32_t word, float s) {
 }
 
 template <typename R, bool kTri, bool kPh>
-__global__ __launch_bounds__(256, kStreamWgs) void k_stream(StepArgs A, TabView<R> T, Work W, int scap,
-                                                                     int from_list) {
+__global__ __launch_bounds__(kStreamThreads, kStreamWaves) void k_stream(StepArgs A, TabView<R> T, Work W, int scap,
+                                                                       int from_list) {
+    // Thread t stands for threads t + kST v, v < kV, of the 256-thread order
+    // the canonical sums are defined in (canon_part2): its records u with
+    // u mod kV = v are theirs, in the same order, and the partial sums of the
+    // slot v are kept apart, so every sum is the one a workgroup of 256
+    // threads forms.  Slot v of wavefront wv is the 256-thread order's
+    // wavefront wv + kW v.
+    constexpr int kST = kStreamThreads, kV = 256 / kST, kW = kST / 64;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ R slice[kSliceMax];
     __shared__ R slice_g[kPh ? kSliceMax : 1];
-    __shared__ double rs[kWaves][4];              // per wavefront: the canonical parts of n_e, n_ab, n_i, n_g
-    __shared__ int rsf[kWaves];                   // per wavefront: flag bits
-    __shared__ double pg[kPh ? kWaves * 3 : 1];   // per wavefront: the photons' n_g, A, B parts
-    __shared__ int pgf[kPh ? kWaves : 1];         // per wavefront: 1 bad photon weight, 4 above the tables
+    __shared__ double rs[4][4];                   // per wavefront of the 256 order: parts of n_e, n_ab, n_i
+    __shared__ int rsf[kW];                       // per wavefront: flag bits
+    __shared__ double pg[kPh ? 4 * 3 : 1];        // per wavefront of the 256 order: the photons' n_g, A, B parts
+    __shared__ int pgf[kPh ? kW : 1];             // per wavefront: 1 bad photon weight, 4 above the tables
     __shared__ uint32_t opn[kCandCap];
     __shared__ int nopen;
     // the photons of the cell: key, then rank; repetitions; sigma and 1/(sigma c)
@@ -2061,12 +2077,12 @@ __global__ __launch_bounds__(256, kStreamWgs) void k_stream(StepArgs A, TabView<
             rest(true);
             continue;
         }
-        const int N = Ne, U = (N + 255) / 256;
+        const int N = Ne, U = (N + kST - 1) / kST;
         const double* wm = A.el.w + e0;
         const double* wion = A.io.w + i0;
         const double* wo = A.ph.w + g0;
         const auto load = [&](int u) {
-            const int q = min(t + 256 * u, N - 1), qi = min(t + 256 * u, Ni - 1);
+            const int q = min(t + kST * u, N - 1), qi = min(t + kST * u, Ni - 1);
             return Rec{A.el.px[e0 + q], A.el.py[e0 + q], A.el.pz[e0 + q], wm[q], wion[qi]};
         };
         // the photon-ion pass here: photons cycled against the ions (the pair
@@ -2076,28 +2092,31 @@ __global__ __launch_bounds__(256, kStreamWgs) void k_stream(StepArgs A, TabView<
         const bool left1 = !ph && (A.proc & CMC_BH) && Ng > 0;      // a photon-ion pass for the pass kernel
         const int K = ph ? Ni / Ng : 0, ee = ph ? Ni - K * Ng : 0;
         const int X = K * Ng + (ee > 0 ? Ng : 0);
-        const int Gt = ph ? (((X + 1023) >> 10) << 8) / 256 : 0;   // draw groups per thread
+        const int Gt = ph ? (((X + 1023) >> 10) << 8) / kST : 0;   // draw groups per thread
         const float rNg = ph ? 1.0f / (float)Ng : 0.0f;
         // Loads in the order their values are needed: the table slices (from
         // L2) first, then the photons, then the first electron records,
         // which stay in flight through the staging and the photons' setup.
         if (brm)
-            for (int i = t; i < kSliceBrems; i += 256) slice[i] = slice_node_brems<R>(T, ct, i);
+            for (int i = t; i < kSliceBrems; i += kST) slice[i] = slice_node_brems<R>(T, ct, i);
         if (ph)
-            for (int i = t; i < kSliceBH; i += 256) slice_g[i] = slice_node_bh<R>(T, ct, i);
-        double gw = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;          // this thread's photon
-        if (ph && t < Ng) {
-            gx = A.ph.px[g0 + t]; gy = A.ph.py[g0 + t]; gz = A.ph.pz[g0 + t];
-            gw = wo[t];
+            for (int i = t; i < kSliceBH; i += kST) slice_g[i] = slice_node_bh<R>(T, ct, i);
+        double gw[kV], gx[kV], gy[kV], gz[kV];                  // this thread's photons m = t + kST v
+#pragma unroll
+        for (int v = 0; v < kV; ++v) {
+            const int m = t + kST * v;
+            gw[v] = 0.0; gx[v] = 0.0; gy[v] = 0.0; gz[v] = 0.0;
+            if (ph && m < Ng) {
+                gx[v] = A.ph.px[g0 + m]; gy[v] = A.ph.py[g0 + m]; gz[v] = A.ph.pz[g0 + m];
+                gw[v] = wo[m];
+            }
         }
         const double w0 = wion[0];
         Rec rr[kStreamDepth];
 #pragma unroll
         for (int d = 0; d < kStreamDepth; ++d) rr[d] = load(min(d, U - 1));
-        if (ph && t < Ng) {
-            const U4 r = rng.draw((uint32_t)t >> 2, cell, kTagKeyG);
-            gkey[t] = hi_word(r, (uint32_t)t & 3u);
-        }
+        if (ph)
+            for (int m = t; m < Ng; m += kST) gkey[m] = hi_word(rng.draw((uint32_t)m >> 2, cell, kTagKeyG), (uint32_t)m & 3u);
         if (t == 0) nopen = 0;
         __syncthreads();
         if (ph) {
@@ -2105,49 +2124,55 @@ __global__ __launch_bounds__(256, kStreamWgs) void k_stream(StepArgs A, TabView<
             // the canonical per-wavefront parts of n_g, A = sum min(W_g, W_i)
             // and B, the same over the photons that pair once more
             int flg = 0;
-            double pa = 0.0, pb = 0.0, pc = 0.0;
-            if (t < Ng) {
-                const uint32_t kt = gkey[t];
-                int rk = 0;
-                for (int j = 0; j < Ng; ++j) {
-                    const uint32_t kj = gkey[j];
-                    rk += (kj < kt || (kj == kt && j < t)) ? 1 : 0;
+#pragma unroll
+            for (int v = 0; v < kV; ++v) {
+                const int mt = t + kST * v;
+                double pa = 0.0, pb = 0.0, pc = 0.0;
+                if (mt < Ng) {
+                    const uint32_t kt = gkey[mt];
+                    int rk = 0;
+                    for (int j = 0; j < Ng; ++j) {
+                        const uint32_t kj = gkey[j];
+                        rk += (kj < kt || (kj == kt && j < mt)) ? 1 : 0;
+                    }
+                    grank[mt] = (uint16_t)rk;
+                    greps[mt] = (uint16_t)(K + (rk < ee ? 1 : 0));
+                    bool hi;
+                    const R sig = bh_sig_slice<R>(T, slice_g, photon_k<R>(gx[v], gy[v], gz[v]), hi);
+                    flg |= hi ? 4 : 0;
+                    gsig[mt] = (float)sig;
+                    ginv[mt] = sig > (R)0 ? 1.0f / ((float)sig * (float)phys::kC) : -1.0f;
+                    flg |= (!(gw[v] >= 0.0) || !isfinite(gw[v])) ? 1 : 0;
+                    const double m = gw[v] < w0 ? gw[v] : w0;
+                    pa = 0.0 + gw[v];
+                    pb = 0.0 + m;
+                    pc = rk < ee ? 0.0 + m : 0.0;
                 }
-                grank[t] = (uint16_t)rk;
-                greps[t] = (uint16_t)(K + (rk < ee ? 1 : 0));
-                bool hi;
-                const R sig = bh_sig_slice<R>(T, slice_g, photon_k<R>(gx, gy, gz), hi);
-                flg |= hi ? 4 : 0;
-                gsig[t] = (float)sig;
-                ginv[t] = sig > (R)0 ? 1.0f / ((float)sig * (float)phys::kC) : -1.0f;
-                flg |= (!(gw >= 0.0) || !isfinite(gw)) ? 1 : 0;
-                const double m = gw < w0 ? gw : w0;
-                pa = 0.0 + gw;
-                pb = 0.0 + m;
-                pc = rk < ee ? 0.0 + m : 0.0;
+                pa = wave_sum(pa);
+                pb = wave_sum(pb);
+                pc = wave_sum(pc);
+                if (lane == 0) {
+                    pg[(wv + kW * v) * 3] = pa;
+                    pg[(wv + kW * v) * 3 + 1] = pb;
+                    pg[(wv + kW * v) * 3 + 2] = pc;
+                }
             }
-            pa = wave_sum(pa);
-            pb = wave_sum(pb);
-            pc = wave_sum(pc);
             const int f1 = __ballot(flg & 1) != 0ull ? 1 : 0, f4 = __ballot(flg & 4) != 0ull ? 4 : 0;
-            if (lane == 0) {
-                pg[wv * 3] = pa;
-                pg[wv * 3 + 1] = pb;
-                pg[wv * 3 + 2] = pc;
-                pgf[wv] = f1 | f4;
-            }
+            if (lane == 0) pgf[wv] = f1 | f4;
             __syncthreads();
         }
-        double sa = 0.0, sb = 0.0, si = 0.0;     // n_e, n_ab and n_i: canonical per-thread parts
+        double sa[kV], sb[kV], si[kV];           // n_e, n_ab and n_i: canonical parts of the slots
+#pragma unroll
+        for (int v = 0; v < kV; ++v) { sa[v] = 0.0; sb[v] = 0.0; si[v] = 0.0; }
         int fl = 0;                              // 1 bad weight, 2 ions of unequal weight, 4 above the tables
         // the two smallest kx at which one of this thread's tests would pass
         // the bound, with the word and place of the smallest: Bremsstrahlung,
         // Trident, Bethe-Heitler
         Low lb, lt, lg;
-        U4 hb{0u, 0u, 0u, 0u}, ht{0u, 0u, 0u, 0u};
-        // draw group j of this thread's photon-ion tests: g = t + 256 j, keys base(g) + 256 w
+        U4 hb[kV], ht[kV];
+        // draw group j of this thread's photon-ion tests: g = t + kST j, keys base(g) + 256 w
         const auto group = [&](int j) {
-            const int g = t + 256 * j;
+            const int g = t + kST * j;
             const int base = ((g >> 8) << 10) | (g & 255);
             if (base >= X) return;
             const U4 h = rng.draw((uint32_t)g, cell, kTagHiBh);
@@ -2164,19 +2189,20 @@ __global__ __launch_bounds__(256, kStreamWgs) void k_stream(StepArgs A, TabView<
                 }
             }
         };
-        // record u of the walk (q = t + 256 u)
-        const auto take = [&](int u, const Rec& cur) {
-            const int q = t + 256 * u;
-            // pair q: U1's upper bits are word u & 3 of the draw
-            // hi_group(q) = (u >> 2) << 8 | t, one per four pairs
-            if ((u & 3) == 0) {
-                if (brm) hb = rng.draw(hi_group((uint32_t)q), cell, kTagHiBr);
-                if (tri) ht = rng.draw(hi_group((uint32_t)q), cell, kTagHiTr);
+        // record u of the walk (q = t + kST u), slot v = u mod kV
+        const auto take = [&](int u, const Rec& cur, auto vc) {
+            constexpr int v = decltype(vc)::value;
+            const int q = t + kST * u, vu = u / kV;
+            // pair q: U1's upper bits are word vu & 3 of the draw
+            // hi_group(q) = (vu >> 2) << 8 | (t + kST v), one per four pairs
+            if ((vu & 3) == 0) {
+                if (brm) hb[v] = rng.draw(hi_group((uint32_t)q), cell, kTagHiBr);
+                if (tri) ht[v] = rng.draw(hi_group((uint32_t)q), cell, kTagHiTr);
             }
             if (q < N) {
                 fl |= (!(cur.w >= 0.0) || !isfinite(cur.w)) ? 1 : 0;
-                sa += cur.w;
-                sb += cur.w < w0 ? cur.w : w0;
+                sa[v] += cur.w;
+                sb[v] += cur.w < w0 ? cur.w : w0;
                 const Elec<R> el = electron_p<R>(cur.x, cur.y, cur.z);
                 float s1 = -1.0f;
                 if (brm) {
@@ -2185,7 +2211,7 @@ __global__ __launch_bounds__(256, kStreamWgs) void k_stream(StepArgs A, TabView<
                     fl |= hi ? 4 : 0;
                     if (sig > (R)0) {
                         s1 = (float)sig * (float)el.vrel;
-                        lb.add(kx_needed(hi_word(hb, (uint32_t)u & 3u), s1), u);
+                        lb.add(kx_needed(hi_word(hb[v], (uint32_t)vu & 3u), s1), u);
                     }
                 }
                 sv[q] = s1;
@@ -2194,7 +2220,7 @@ __global__ __launch_bounds__(256, kStreamWgs) void k_stream(StepArgs A, TabView<
                     float s2 = -1.0f;
                     if (st > (R)0) {
                         s2 = (float)st * (float)el.vrel;
-                        lt.add(kx_needed(hi_word(ht, (uint32_t)u & 3u), s2), u);
+                        lt.add(kx_needed(hi_word(ht[v], (uint32_t)vu & 3u), s2), u);
                     }
                     svt[q] = s2;
                 }
@@ -2202,7 +2228,7 @@ __global__ __launch_bounds__(256, kStreamWgs) void k_stream(StepArgs A, TabView<
             if (q < Ni) {
                 fl |= (!(cur.wi >= 0.0) || !isfinite(cur.wi)) ? 1 : 0;
                 fl |= cur.wi != w0 ? 2 : 0;
-                si += cur.wi;
+                si[v] += cur.wi;
             }
             if (ph && (u & 3) == 3 && (u >> 2) < Gt) group(u >> 2);
         };
@@ -2212,48 +2238,49 @@ __global__ __launch_bounds__(256, kStreamWgs) void k_stream(StepArgs A, TabView<
         // kStreamDepth ahead goes out into its registers.  A plain rotation
         // (r0 = r1) would move a value still in flight, which waits for every
         // load.  The last round's loads are clamped to the last record.
+        static_assert(kStreamDepth % kV == 0, "a round of records covers whole slots");
 #pragma unroll 1
         for (int u0 = 0; u0 < U; u0 += kStreamDepth) {
-#pragma unroll
-            for (int d = 0; d < kStreamDepth; ++d) {
+            unrolled(std::make_integer_sequence<int, kStreamDepth>{}, [&](auto dc) {
+                constexpr int d = decltype(dc)::value;
                 const Rec cur = fresh(rr[d]);
                 rr[d] = load(min(u0 + d + kStreamDepth, U - 1));
-                if (u0 + d < U) take(u0 + d, cur);
-            }
+                if (u0 + d < U) take(u0 + d, cur, std::integral_constant<int, d % kV>{});
+            });
         }
         if (ph)
             for (int j = U >> 2; j < Gt; ++j) group(j);
         {
             // the team reduction: per-wavefront parts, one barrier (which also
             // publishes sv), the four parts added in order
-            double p3 = 0.0;
-            if (!ph) {
-                // the photons' weights are checked (their pass is left to the pass kernel)
-                int bad = 0;
-                p3 = canon_part<256>(Ng, [&](int q) { const double w = wo[q]; bad |= !(w >= 0.0) || !isfinite(w); return w; });
-                fl |= bad ? 1 : 0;
+            if (!ph)   // the photons' weights are checked (their pass is left to the pass kernel)
+                for (int q = t; q < Ng; q += kST) fl |= (!(wo[q] >= 0.0) || !isfinite(wo[q])) ? 1 : 0;
+#pragma unroll
+            for (int v = 0; v < kV; ++v) {
+                const double p0 = wave_sum(sa[v]), p1 = wave_sum(sb[v]), p2 = wave_sum(si[v]);
+                if (lane == 0) {
+                    rs[wv + kW * v][0] = p0;
+                    rs[wv + kW * v][1] = p1;
+                    rs[wv + kW * v][2] = p2;
+                }
             }
-            const double p0 = wave_sum(sa), p1 = wave_sum(sb), p2 = wave_sum(si);
             int wf = 0;
 #pragma unroll
             for (int b = 0; b < 3; ++b)
                 if (__ballot((fl >> b) & 1) != 0ull) wf |= 1 << b;
-            if (lane == 0) {
-                rs[wv][0] = p0;
-                rs[wv][1] = p1;
-                rs[wv][2] = p2;
-                rs[wv][3] = p3;
-                rsf[wv] = wf;
-            }
+            if (lane == 0) rsf[wv] = wf;
             __syncthreads();
         }
-        double v4[4];
+        double v4[3];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) v4[k] = ((rs[0][k] + rs[1][k]) + rs[2][k]) + rs[3][k];
-        fl = rsf[0] | rsf[1] | rsf[2] | rsf[3];
+        for (int k = 0; k < 3; ++k) v4[k] = ((rs[0][k] + rs[1][k]) + rs[2][k]) + rs[3][k];
+        fl = 0;
+#pragma unroll
+        for (int w = 0; w < kW; ++w) fl |= rsf[w];
         int flg = 0;
         if (ph) {
-            flg = pgf[0] | pgf[1] | pgf[2] | pgf[3];
+#pragma unroll
+            for (int w = 0; w < kW; ++w) flg |= pgf[w];
             fl |= flg & 1;
         }
         if (fl & 2) {                                // the ordered form, in the pass kernel
@@ -2284,19 +2311,20 @@ __global__ __launch_bounds__(256, kStreamWgs) void k_stream(StepArgs A, TabView<
                 if (o < kCandCap) opn[o] = (uint32_t)q | (bits << 16);
             };
             if (lb.y2 <= kxf || lt.y2 <= kxf) {
+                // each pair's word drawn on its own (this path is rare)
                 for (int u = 0; u < U; ++u) {
-                    const int q = t + 256 * u;
-                    if ((u & 3) == 0) {
-                        if (brm) hb = rng.draw(hi_group((uint32_t)q), cell, kTagHiBr);
-                        if (tri) ht = rng.draw(hi_group((uint32_t)q), cell, kTagHiTr);
-                    }
+                    const int q = t + kST * u;
                     if (q >= N) continue;
                     uint32_t bits = 0;
                     const float s1 = sv[q];
-                    if (s1 > 0.0f && bound24(hi_word(hb, (uint32_t)u & 3u), kx * s1)) bits = 1u;
+                    if (s1 > 0.0f &&
+                        bound24(hi_word(rng.draw(hi_group((uint32_t)q), cell, kTagHiBr), ((uint32_t)q >> 8) & 3u), kx * s1))
+                        bits = 1u;
                     if (tri && !bits) {
                         const float s2 = svt[q];
-                        if (s2 > 0.0f && bound24(hi_word(ht, (uint32_t)u & 3u), kx * s2)) bits = 2u;
+                        if (s2 > 0.0f &&
+                            bound24(hi_word(rng.draw(hi_group((uint32_t)q), cell, kTagHiTr), ((uint32_t)q >> 8) & 3u), kx * s2))
+                            bits = 2u;
                     }
                     if (bits) open_pair(q, bits);
                 }
@@ -2305,18 +2333,19 @@ __global__ __launch_bounds__(256, kStreamWgs) void k_stream(StepArgs A, TabView<
                 // of the thread fails both filters, hence both tests.  The
                 // pair's word is drawn again.
                 const auto word = [&](int u, uint32_t tag) {
-                    return hi_word(rng.draw(hi_group((uint32_t)(t + 256 * u)), cell, tag), (uint32_t)u & 3u);
+                    const uint32_t q = (uint32_t)(t + kST * u);
+                    return hi_word(rng.draw(hi_group(q), cell, tag), (q >> 8) & 3u);
                 };
                 bool done_t = false;
                 if (lb.y1 <= kxf) {
-                    const int q = t + 256 * lb.u1;
+                    const int q = t + kST * lb.u1;
                     if (bound24(word(lb.u1, kTagHiBr), kx * sv[q])) {
                         open_pair(q, 1u);
                         done_t = tri && lt.u1 == lb.u1;
                     }
                 }
                 if (tri && !done_t && lt.y1 <= kxf) {
-                    const int q = t + 256 * lt.u1;
+                    const int q = t + kST * lt.u1;
                     if (bound24(word(lt.u1, kTagHiTr), kx * svt[q])) open_pair(q, 2u);
                 }
             }
@@ -2368,7 +2397,7 @@ __global__ __launch_bounds__(256, kStreamWgs) void k_stream(StepArgs A, TabView<
                     };
                     if (lg.y2 <= kxgf) {
                         for (int j = 0; j < Gt; ++j) {
-                            const int g = t + 256 * j;
+                            const int g = t + kST * j;
                             const int base = ((g >> 8) << 10) | (g & 255);
                             if (base >= X) continue;
                             const U4 h = rng.draw((uint32_t)g, cell, kTagHiBh);
@@ -2426,6 +2455,7 @@ __global__ __launch_bounds__(256, kStreamWgs) void k_stream(StepArgs A, TabView<
     }
 }
 
+// One pass of pair tests over all cells from the particles as they are at
 // One pass of pair tests over all cells from the particles as they are at
 // the start of the step: kPass 0 electron-ion (Bremsstrahlung, then Trident
 // when Bremsstrahlung is not accepted), kPass 1 photon-ion (Bethe-Heitler),
@@ -3431,7 +3461,8 @@ static void launch_stream_r(const StepArgs& A, const TabView<R>& T, const Work& 
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(A.n_cells, cap_blocks));
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (pt) { e0 = pt->first ? pt->start : nullptr; e1 = pt->stop; pt->first = false; }
-    hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(256), (uint32_t)dshm, st, e0, e1, 0u, A, T, W, scap, from_list);
+    hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(kStreamThreads), (uint32_t)dshm, st, e0, e1, 0u, A, T, W, scap,
+                          from_list);
 }
 
 // true when it ran: the pass kernels then walk the cells it left (from_list 3)
