@@ -795,6 +795,7 @@ enum : int {
     kCntBig0 = 1,    // electron-ion passes deferred to the large-LDS launch (list_big[0])
     kCntBig1 = 2,    // photon-ion passes deferred (list_big[1])
     kCntWg = 3,      // listed cells the wavefront event kernel hands to the workgroup one (list_wg)
+    kCntRest = 4,    // cells the stream kernel leaves to the pass kernel (marked in list_rest)
     kNumCnt = 8
 };
 
@@ -2067,7 +2068,10 @@ __global__ __launch_bounds__(kStreamThreads, kStreamWaves) void k_stream(StepArg
         // pass kernel, else -1 (the pass kernel walks the entries in the
         // order of this walk: index order, or the work queue's)
         const auto rest = [&](bool left) {
-            if (t == 0) W.list_rest[item] = left ? (int32_t)c : -1;
+            if (t == 0) {
+                W.list_rest[item] = left ? (int32_t)c : -1;
+                if (left) atomicAdd(&W.counters[kCntRest], 1);
+            }
         };
         if (cstat) {                             // invalid cell (flagged by k_cell_state)
             rest(false);
@@ -2501,6 +2505,12 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
     // 2: the work queue, the cells costliest first (workgroups are
     // dispatched in index order as compute units free up, so the largest
     // cells start first and the rest fill in behind them)
+    // The walk of list_rest ends at once when the stream kernel left no
+    // cell.  (Folded into the choice of n_items below, as a nested
+    // conditional, this test made the compiler drop n_cells on the path where
+    // the count is not zero: the early return keeps the two apart.)
+    if (from_list == 3 && __hip_atomic_load(&W.counters[kCntRest], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+        return;
     const int64_t n_items = from_list == 1 ? (int64_t)W.counters[kPass == 1 ? kCntBig1 : kCntBig0] : A.n_cells;
     for (int64_t item = (int64_t)blockIdx.x * kTeams + team; item < n_items; item += (int64_t)gridDim.x * kTeams) {
         const int64_t c = from_list == 2 ? (int64_t)W.queue[item]
