@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "pair evaluations/sec + % HBM peak; FP32-batched vs FP64-plain at 1e-5 rel err"
 COUNTERS = {"cfg2": os.path.join(ROOT, "profiles", "k_pass_bh_cfg2_counters.txt"),
-            "cfg5": os.path.join(ROOT, "profiles", "k_pass_cfg5_counters.txt")}
+            "cfg5": os.path.join(ROOT, "profiles", "k_stream_cfg5_counters.txt")}
 CFG5_SAMPLE = 1024             # seeded cells of cfg5 the oracle runs (global cell ids)
 COPY_BYTES = 1 << 30
 HIP_EVENT_DISABLE_SYSTEM_FENCE = 0x20000000
