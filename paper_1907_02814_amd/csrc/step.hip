@@ -2023,6 +2023,54 @@ __device__ __forceinline__ float kx_needed(uint32_t word, float s) {
     return v == 0u ? 0.0f : (float)v * __builtin_amdgcn_rcpf(s);
 }
 
+// The FP64 form's filter of the electron-ion bound test, in FP32: an upper
+// bound of the Bremsstrahlung sigma that brems_sig_slice<double> gives for
+// the same electron.  The energy axes of the three segments as FP32 values
+// (start, reciprocal step, node count), selected by value per lane.
+struct SegAxes {
+    float u0[3], rdu[3];
+    int n[3];
+};
+
+__host__ __device__ inline SegAxes seg_axes(const Axes& ax) {
+    const AxisDef* a[3] = {&ax.nr, &ax.rel, &ax.ur};
+    SegAxes S;
+    for (int k = 0; k < 3; ++k) {
+        S.u0[k] = (float)a[k]->u0;
+        S.rdu[k] = (float)(1.0 / a[k]->du);
+        S.n[k] = a[k]->n;
+    }
+    return S;
+}
+
+// The bound: the largest slice node of the interval the FP32 energy falls
+// in and of its two neighbours.  The FP32 position along the axis differs
+// from the FP64 one by far less than a node spacing (about 1e-4 of one), so
+// the FP64 interval is among these three and its interpolated sigma is at
+// most the largest of their nodes (which the FP32 copy of the slice holds
+// rounded to nearest).  edge: the electron lies within 2^-10 (relative) of
+// the emission threshold, of a segment join (gamma 2 and 100) or of the top
+// of the tables, or its FP32 energy is not finite; there the two energies
+// may fall on different sides, and the pair is tested exactly.  sl: the
+// FP32 copy of the cell's slice (segments NR | rel | UR).
+__device__ __forceinline__ float brems_sig_bound(const SegAxes& X, const float* sl, float g, float g1m1,
+                                                 bool& edge) {
+    constexpr float kB = 1.0f / 1024.0f;
+    constexpr float tmin = (float)(grid::kTminEv / grid::kMec2Ev);
+    edge = !(g < (float)grid::kTop * (1.0f - kB)) || fabsf(g - 2.0f) <= 2.0f * kB ||
+           fabsf(g - 100.0f) <= 100.0f * kB || fabsf(g1m1 - tmin) <= tmin * kB;
+    if (edge || !(g1m1 > tmin)) return 0.0f;
+    const bool nr = g <= 2.0f, rel = g <= 100.0f;
+    const float u0 = nr ? X.u0[0] : rel ? X.u0[1] : X.u0[2];
+    const float rdu = nr ? X.rdu[0] : rel ? X.rdu[1] : X.rdu[2];
+    const int n = nr ? X.n[0] : rel ? X.n[1] : X.n[2];
+    const int off = nr ? 0 : rel ? grid::kNR : grid::kNR + grid::kRel;
+    const float pos = (Fast<float>::log(nr ? g1m1 : g) - u0) * rdu;
+    const int ig = pos <= 0.0f ? 0 : min((int)pos, n - 2);
+    const float* s = sl + off;
+    return fmaxf(fmaxf(s[max(ig - 1, 0)], s[ig]), fmaxf(s[ig + 1], s[min(ig + 2, n - 1)]));
+}
+
 template <typename R, bool kTri, bool kPh>
 __global__ __launch_bounds__(kStreamThreads, kStreamWaves) void k_stream(StepArgs A, TabView<R> T, Work W, int scap,
                                                                        int from_list) {
@@ -2033,8 +2081,13 @@ __global__ __launch_bounds__(kStreamThreads, kStreamWaves) void k_stream(StepArg
     // threads forms.  Slot v of wavefront wv is the 256-thread order's
     // wavefront wv + kW v.
     constexpr int kST = kStreamThreads, kV = 256 / kST, kW = kST / 64;
+    // FP64 form without Trident: the walk filters the bound tests with
+    // brems_sig_bound in FP32, and a pair that passes the filter is tested
+    // again from its FP64 sigma v, exactly as the pass kernel tests it
+    constexpr bool kLoose = std::is_same<R, double>::value && !kTri;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ R slice[kSliceMax];
+    __shared__ float slice_f[kLoose ? kSliceMax : 1];
     __shared__ R slice_g[kPh ? kSliceMax : 1];
     __shared__ double rs[4][4];                   // per wavefront of the 256 order: parts of n_e, n_ab, n_i
     __shared__ int rsf[kW];                       // per wavefront: flag bits
@@ -2053,6 +2106,7 @@ __global__ __launch_bounds__(kStreamThreads, kStreamWaves) void k_stream(StepArg
     const bool brm = (A.proc & CMC_BREMS) != 0;
     float* sv = reinterpret_cast<float*>(smem_raw);   // sigma v of electron q (< 0: no test)
     float* svt = sv + scap;                           // Trident's
+    const SegAxes X3 = seg_axes(T.ax);
     for (int64_t item = blockIdx.x; item < A.n_cells; item += gridDim.x) {
         const int64_t c = from_list == 2 ? (int64_t)W.queue[item] : item;
         const uint32_t cell = cell_word(A.cid, c);
@@ -2102,7 +2156,11 @@ __global__ __launch_bounds__(kStreamThreads, kStreamWaves) void k_stream(StepArg
         // L2) first, then the photons, then the first electron records,
         // which stay in flight through the staging and the photons' setup.
         if (brm)
-            for (int i = t; i < kSliceBrems; i += kST) slice[i] = slice_node_brems<R>(T, ct, i);
+            for (int i = t; i < kSliceBrems; i += kST) {
+                const R sn = slice_node_brems<R>(T, ct, i);
+                slice[i] = sn;
+                if constexpr (kLoose) slice_f[i] = (float)sn;
+            }
         if (ph)
             for (int i = t; i < kSliceBH; i += kST) slice_g[i] = slice_node_bh<R>(T, ct, i);
         double gw[kV], gx[kV], gy[kV], gz[kV];                  // this thread's photons m = t + kST v
@@ -2207,26 +2265,37 @@ __global__ __launch_bounds__(kStreamThreads, kStreamWaves) void k_stream(StepArg
                 fl |= (!(cur.w >= 0.0) || !isfinite(cur.w)) ? 1 : 0;
                 sa[v] += cur.w;
                 sb[v] += cur.w < w0 ? cur.w : w0;
-                const Elec<R> el = electron_p<R>(cur.x, cur.y, cur.z);
-                float s1 = -1.0f;
-                if (brm) {
-                    bool hi;
-                    const R sig = brems_sig_slice<R>(T, slice, el.g, el.gm1, hi);
-                    fl |= hi ? 4 : 0;
-                    if (sig > (R)0) {
-                        s1 = (float)sig * (float)el.vrel;
-                        lb.add(kx_needed(hi_word(hb[v], (uint32_t)vu & 3u), s1), u);
+                if constexpr (kLoose) {
+                    if (brm) {
+                        // an edge electron passes the filter (it is tested exactly)
+                        const Elec<float> ef = electron_p<float>(cur.x, cur.y, cur.z);
+                        bool edge;
+                        const float sup = brems_sig_bound(X3, slice_f, ef.g, ef.gm1, edge);
+                        if (edge || sup > 0.0f)
+                            lb.add(edge ? 0.0f : kx_needed(hi_word(hb[v], (uint32_t)vu & 3u), sup * (float)ef.vrel), u);
                     }
-                }
-                sv[q] = s1;
-                if (tri) {
-                    const R st = (R)phys::trident_sigma(T.Z, (double)el.g);
-                    float s2 = -1.0f;
-                    if (st > (R)0) {
-                        s2 = (float)st * (float)el.vrel;
-                        lt.add(kx_needed(hi_word(ht[v], (uint32_t)vu & 3u), s2), u);
+                } else {
+                    const Elec<R> el = electron_p<R>(cur.x, cur.y, cur.z);
+                    float s1 = -1.0f;
+                    if (brm) {
+                        bool hi;
+                        const R sig = brems_sig_slice<R>(T, slice, el.g, el.gm1, hi);
+                        fl |= hi ? 4 : 0;
+                        if (sig > (R)0) {
+                            s1 = (float)sig * (float)el.vrel;
+                            lb.add(kx_needed(hi_word(hb[v], (uint32_t)vu & 3u), s1), u);
+                        }
                     }
-                    svt[q] = s2;
+                    sv[q] = s1;
+                    if (tri) {
+                        const R st = (R)phys::trident_sigma(T.Z, (double)el.g);
+                        float s2 = -1.0f;
+                        if (st > (R)0) {
+                            s2 = (float)st * (float)el.vrel;
+                            lt.add(kx_needed(hi_word(ht[v], (uint32_t)vu & 3u), s2), u);
+                        }
+                        svt[q] = s2;
+                    }
                 }
             }
             if (q < Ni) {
@@ -2314,13 +2383,28 @@ __global__ __launch_bounds__(kStreamThreads, kStreamWaves) void k_stream(StepArg
                 const int o = atomicAdd(&nopen, 1);
                 if (o < kCandCap) opn[o] = (uint32_t)q | (bits << 16);
             };
+            // electron q's Bremsstrahlung sigma v as the pass kernel forms it
+            // (< 0: no test): from LDS, or (kLoose) from its FP64 momenta,
+            // which also decide whether it lies above the tables
+            const auto sig_v = [&](int q) -> float {
+                if constexpr (kLoose) {
+                    const int64_t ie = e0 + q;
+                    const Elec<R> el = electron_p<R>(A.el.px[ie], A.el.py[ie], A.el.pz[ie]);
+                    bool hi;
+                    const R sig = brems_sig_slice<R>(T, slice, el.g, el.gm1, hi);
+                    if (hi) atomicOr(A.status, CMC_ST_GAMMA_HIGH);
+                    return sig > (R)0 ? (float)sig * (float)el.vrel : -1.0f;
+                } else {
+                    return sv[q];
+                }
+            };
             if (lb.y2 <= kxf || lt.y2 <= kxf) {
                 // each pair's word drawn on its own (this path is rare)
                 for (int u = 0; u < U; ++u) {
                     const int q = t + kST * u;
                     if (q >= N) continue;
                     uint32_t bits = 0;
-                    const float s1 = sv[q];
+                    const float s1 = brm ? sig_v(q) : -1.0f;
                     if (s1 > 0.0f &&
                         bound24(hi_word(rng.draw(hi_group((uint32_t)q), cell, kTagHiBr), ((uint32_t)q >> 8) & 3u), kx * s1))
                         bits = 1u;
@@ -2343,7 +2427,8 @@ __global__ __launch_bounds__(kStreamThreads, kStreamWaves) void k_stream(StepArg
                 bool done_t = false;
                 if (lb.y1 <= kxf) {
                     const int q = t + kST * lb.u1;
-                    if (bound24(word(lb.u1, kTagHiBr), kx * sv[q])) {
+                    const float s1 = sig_v(q);
+                    if (s1 > 0.0f && bound24(word(lb.u1, kTagHiBr), kx * s1)) {
                         open_pair(q, 1u);
                         done_t = tri && lt.u1 == lb.u1;
                     }
