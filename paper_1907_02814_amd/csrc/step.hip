@@ -796,6 +796,7 @@ enum : int {
     kCntBig1 = 2,    // photon-ion passes deferred (list_big[1])
     kCntWg = 3,      // listed cells the wavefront event kernel hands to the workgroup one (list_wg)
     kCntRest = 4,    // cells the stream kernel leaves to the pass kernel (marked in list_rest)
+    kCntLane = 5,    // cells the stream kernel lists for the lane event kernel (list_lane)
     kNumCnt = 8
 };
 
@@ -812,6 +813,7 @@ struct Work {
     int32_t* list_big[2];            // per pass: cells whose pass needs more LDS than the first launch has
     int32_t* queue;                  // the cells in decreasing order of cost (batched schedule)
     int32_t* list_rest;              // per item of the stream kernel's walk: its cell if a pass is left, else -1
+    int32_t* list_lane;              // listed cells for the lane event kernel (k_events_lane)
     uint64_t* cand;                  // [n_cells][kCandCap] open pairs
 };
 
@@ -819,7 +821,7 @@ __host__ __device__ constexpr size_t align256(size_t b) { return (b + 255) / 256
 
 __host__ __device__ constexpr size_t work_bytes(int64_t n) {
     return align256(sizeof(CellState) * n) + align256(4 * n) + align256(4 * n) +
-           align256(16 * n) + align256(8 * n) + align256(8) + align256(4 * kNumCnt) + 6 * align256(4 * n) +
+           align256(16 * n) + align256(8 * n) + align256(8) + align256(4 * kNumCnt) + 7 * align256(4 * n) +
            align256(8 * (size_t)n * kCandCap);
 }
 
@@ -839,6 +841,7 @@ inline Work carve_work(void* base, int64_t n) {
     w.list_big[1] = reinterpret_cast<int32_t*>(p); p += align256(4 * n);
     w.queue = reinterpret_cast<int32_t*>(p); p += align256(4 * n);
     w.list_rest = reinterpret_cast<int32_t*>(p); p += align256(4 * n);
+    w.list_lane = reinterpret_cast<int32_t*>(p); p += align256(4 * n);
     w.cand = reinterpret_cast<uint64_t*>(p);
     return w;
 }
@@ -1983,6 +1986,7 @@ __device__ __forceinline__ void pass_cell(const StepArgs& A, const TabView<R>& T
 // pass is left, too).  One workgroup per cell, walking the cells in index
 // order or (from_list 2) the work queue.
 constexpr int kStreamPh = 256;   // photons per cell the stream kernel's photon-ion pass takes
+constexpr int kLaneCap = 4;      // open pairs per cell the lane event kernel takes
 
 // f(integral_constant<int, I>) for I = 0, 1, ... in order, unrolled
 template <int... I, typename F>
@@ -2461,6 +2465,7 @@ __global__ __launch_bounds__(kStreamThreads, kStreamWaves) void k_stream(StepArg
             }
             if (t == 0) W.coef[c * 2] = coef;
         }
+        const int nc_e = nc;                         // the electron-ion pairs among them
         if (ph) {
             const double ng = ((pg[0] + pg[3]) + pg[6]) + pg[9];
             const double Ag = ((pg[1] + pg[4]) + pg[7]) + pg[10];
@@ -2531,11 +2536,16 @@ __global__ __launch_bounds__(kStreamThreads, kStreamWaves) void k_stream(StepArg
         __syncthreads();   // LDS of this cell is free
         if (t == 0) {
             // flags, then the lists (the only waits on atomics, after the barrier)
+            // a cell whose open pairs are a few electron-ion pairs, with no
+            // photon-ion pass left and no Trident, goes to the lane kernel
             const int32_t f = kFlagWeightsOk | kFlagIonsSame | kFlagDone0 | (ph ? kFlagDone1 : 0) |
                               (nc > kCandCap ? kFlagSlow : 0) | (nc > 0 ? kFlagListed : 0);
             if (nc > 0) {
-                if (!(atomicOr(&W.flags[c], f) & kFlagListed))
-                    W.list_ev[atomicAdd(&W.counters[kCntEv], 1)] = (int32_t)c;
+                const bool by_lane = nc == nc_e && nc <= kLaneCap && !tri && !left1;
+                if (!(atomicOr(&W.flags[c], f) & kFlagListed)) {
+                    if (by_lane) W.list_lane[atomicAdd(&W.counters[kCntLane], 1)] = (int32_t)c;
+                    else W.list_ev[atomicAdd(&W.counters[kCntEv], 1)] = (int32_t)c;
+                }
             } else {
                 atomicOr(&W.flags[c], f);
             }
@@ -2701,39 +2711,23 @@ struct EvLane {
     bool last;     // no later event of its pass on the same particle
 };
 
-// A wavefront settles the open pairs of a listed cell with P (same
-// arithmetic as the pass kernels: lookups from the full tables give the
-// same values as the slices), after ordering them by (pass, pair index) in
-// rec (kCandCap records of LDS).  `reused` marks an open pair whose mobile
+// Settles one open pair (record `mine`, or none when !cand) with P: the
+// same arithmetic as the pass kernels (lookups from the full tables give
+// the same values as the slices).  `reused` marks an open pair whose mobile
 // particle is used by a later pair of its pass.
 template <typename R>
-__device__ __forceinline__ EvLane<R> ev_settle(const StepArgs& A, const TabView<R>& T, const TabView<double>& T64,
-                                               const Rng& rng, const EvCell<R>& E, uint64_t* rec, double rej) {
-    const int lane = threadIdx.x & 63;
-    const bool cand = lane < E.nc;
+__device__ __forceinline__ EvLane<R> ev_pair(const StepArgs& A, const TabView<R>& T, const TabView<double>& T64,
+                                             const Rng& rng, const EvCell<R>& E, uint64_t mine, bool cand,
+                                             double rej) {
     EvLane<R> L{};
-    L.pass = 2;
-    L.b = Ion{0.0, 0.0, 0.0, 1.0, false};
-    // ---- the open pairs in (pass, pair index) order, one per lane
-    {
-        const bool has = lane < E.nc;
-        const unsigned long long hb = __ballot(has);
-        const uint32_t key = has ? ev_key(E.raw) : 0xFFFFFFFFu;
-        int rank = 0;
-        for (unsigned long long m = hb; m; m &= m - 1ull)
-            rank += (uint32_t)__builtin_amdgcn_readlane((int)key, __ffsll((long long)m) - 1) < key;
-        if (has) rec[rank] = E.raw;
-        Team<64>::sync();
-    }
-    const uint64_t mine = cand ? rec[lane] : 0ull;
     L.pass = cand ? ev_pass(mine) : 2;
+    L.b = Ion{0.0, 0.0, 0.0, 1.0, false};
     L.j = ev_j(mine); L.mi = ev_m(mine); L.ii = ev_i(mine);
     // the pair's draws: keyed by its mobile particle and its repetition
     {
         const int nm = L.pass == 0 ? E.Ne : E.Ng0;
         L.dk = cand && nm > 0 ? (uint32_t)(L.mi + (L.j / nm) * nm) : 0u;
     }
-    // ---- settle them
     L.reused = false;
     L.last = true;
     if (cand) {
@@ -2782,6 +2776,29 @@ __device__ __forceinline__ EvLane<R> ev_settle(const StepArgs& A, const TabView<
         }
     }
     return L;
+}
+
+// A wavefront settles the open pairs of a listed cell (ev_pair), one per
+// lane in (pass, pair index) order, after ordering them in rec (kCandCap
+// records of LDS).
+template <typename R>
+__device__ __forceinline__ EvLane<R> ev_settle(const StepArgs& A, const TabView<R>& T, const TabView<double>& T64,
+                                               const Rng& rng, const EvCell<R>& E, uint64_t* rec, double rej) {
+    const int lane = threadIdx.x & 63;
+    const bool cand = lane < E.nc;
+    // ---- the open pairs in (pass, pair index) order, one per lane
+    {
+        const bool has = lane < E.nc;
+        const unsigned long long hb = __ballot(has);
+        const uint32_t key = has ? ev_key(E.raw) : 0xFFFFFFFFu;
+        int rank = 0;
+        for (unsigned long long m = hb; m; m &= m - 1ull)
+            rank += (uint32_t)__builtin_amdgcn_readlane((int)key, __ffsll((long long)m) - 1) < key;
+        if (has) rec[rank] = E.raw;
+        Team<64>::sync();
+    }
+    const uint64_t mine = cand ? rec[lane] : 0ull;
+    return ev_pair<R>(A, T, T64, rng, E, mine, cand, rej);
 }
 
 // The kinematics of each lane's event: the energies sampled from the FP64
@@ -3344,6 +3361,82 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
 }
 
 
+// One lane per listed cell: the cells the stream kernel lists whose open
+// pairs are at most kLaneCap electron-ion pairs (its electrons pair once,
+// so no event falls on an electron used by a later pair), with Trident
+// off: nearly every listed cell of the Bremsstrahlung workloads.  The lane
+// settles its cell's open pairs in pair order (ev_pair) and applies their
+// events one after the other (ev_kin, each lane inverting its own CDFs):
+// the values, product slots and tallies of the wavefront kernel, whose
+// lanes take the same pairs in the same order and add the tallies in pair
+// order.  Many cells are in flight at once where the wavefront kernel has
+// one per wavefront.  A cell that does not qualify is handed to list_ev.
+template <typename R>
+__global__ __launch_bounds__(kThreads, 2) void k_events_lane(StepArgs A, TabView<R> T, TabView<double> T64, Work W) {
+    const int n_items = W.counters[kCntLane];
+    const double rej = 2.0 * (1.0 + A.near_rel);
+    const Rng rng = step_rng(A);
+    for (int item = (int)(blockIdx.x * kThreads + threadIdx.x); item < n_items; item += (int)(gridDim.x * kThreads)) {
+        const int64_t c = W.list_lane[item];
+        const EvCell<R> E = ev_cell<R>(A, W, c, 0);
+        uint64_t r[kLaneCap];
+#pragma unroll
+        for (int i = 0; i < kLaneCap; ++i) r[i] = i < E.nc ? W.cand[c * kCandCap + i] : ~0ull;
+        bool hand = (E.flg & kFlagSlow) != 0 || E.ncr > kLaneCap || E.Ne < E.Ni || (A.proc & CMC_TRIDENT);
+#pragma unroll
+        for (int i = 0; i < kLaneCap; ++i) hand |= i < E.nc && ev_pass(r[i]) != 0;
+        if (hand) {
+            W.list_ev[atomicAdd(&W.counters[kCntEv], 1)] = (int32_t)c;
+            continue;
+        }
+        // pair order (an absent record sorts last)
+        const auto order = [&](int a, int b) {
+            const bool sw = ev_key(r[b]) < ev_key(r[a]);
+            const uint64_t lo = sw ? r[b] : r[a], hi = sw ? r[a] : r[b];
+            r[a] = lo; r[b] = hi;
+        };
+        static_assert(kLaneCap == 4, "a sorting network of four");
+        order(0, 1); order(2, 3); order(0, 2); order(1, 3); order(1, 2);
+        long long iv[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        double dv[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        int n_ph = 0;
+        for (int k = 0; k < E.nc; ++k) {
+            EvLane<R> L = ev_pair<R>(A, T, T64, rng, E, r[k], true, rej);
+            const EvKin K = ev_kin<R>(A, T, T64, rng, E, L, false);
+            Tally t = K.t;
+            t.near_br += L.near_br; t.near_tr += L.near_tr; t.near_bh += L.near_bh;
+            const int64_t par = E.e0 + L.mi;
+            if ((K.f_ph || K.f_tr) && L.last) { A.el.px[par] = L.px; A.el.py[par] = L.py; A.el.pz[par] = L.pz; }
+            if (K.f_ph) {
+                const int slot = E.Ng0 + n_ph;
+                if (slot < E.cap_ph) {
+                    const int64_t at = E.g0 + slot;
+                    A.ph.px[at] = K.kx; A.ph.py[at] = K.ky; A.ph.pz[at] = K.kz; A.ph.w[at] = L.Wm;
+                    if (A.ph.parent) A.ph.parent[at] = par;
+                } else t.drop_ph++;
+                ++n_ph;
+            }
+            iv[0] += t.ev_br != 0; iv[1] += t.ev_tr != 0; iv[2] += t.ev_bh != 0;
+            iv[3] += t.near_br != 0; iv[4] += t.near_tr != 0; iv[5] += t.near_bh != 0;
+            iv[6] += t.drop_ph != 0; iv[7] += t.drop_el != 0; iv[8] += t.drop_po != 0;
+            if (K.f_ph || K.f_tr || K.f_bh) {
+                dv[0] += t.E_br; dv[1] += t.E_tr; dv[2] += t.E_bh; dv[3] += t.dE_el; dv[4] += t.dE_ph;
+                dv[5] += t.W_br; dv[6] += t.W_tr; dv[7] += t.W_bh;
+            }
+        }
+        int64_t* ti = A.ti + c * CMC_NI;
+        ti[CMC_I_EV_BR] = iv[0]; ti[CMC_I_EV_TR] = iv[1]; ti[CMC_I_EV_BH] = iv[2];
+        ti[CMC_I_NEAR_BR] = iv[3]; ti[CMC_I_NEAR_TR] = iv[4]; ti[CMC_I_NEAR_BH] = iv[5];
+        ti[CMC_I_DROP_PH] = iv[6]; ti[CMC_I_DROP_EL] = iv[7]; ti[CMC_I_DROP_PO] = iv[8];
+        double* td = A.td + c * CMC_ND + CMC_D_E_BR;
+        for (int q = 0; q < 8; ++q) td[q] = dv[q];
+        if (A.ph.count) A.ph.count[c] = min(E.cap_ph, E.Ng0 + n_ph);
+        A.ne.count[c] = min(E.cap_ne, E.cnt_ne0);
+        A.np.count[c] = min(E.cap_np, E.cnt_np0);
+        if (iv[6] + iv[7] + iv[8]) atomicOr(A.status, CMC_ST_OVERFLOW);
+    }
+}
+
 // One wavefront per listed cell, four cells per workgroup, no workgroup
 // barrier and little LDS: a cell whose open pairs are all electron-ion
 // pairs, none of whose events falls on an electron used by a later pair,
@@ -3835,6 +3928,14 @@ static cmc_status collide_step_impl(const char* who, cmc_tables t, const cmc_cel
     const unsigned gev = (unsigned)std::min<int64_t>(A.n_cells, 512);
     const size_t shm_ev = std::max(shm, (size_t)kStagePh * 40);
     const int from_wave = (A.proc & (CMC_BREMS | CMC_TRIDENT)) ? 1 : 0;
+    if (from_wave && plan.stream && !(A.proc & CMC_TRIDENT)) {
+        // the cells the stream kernel listed for a lane each (any it hands
+        // back join list_ev before the wavefront kernel reads its length)
+        const unsigned gl = (unsigned)std::min<int64_t>((A.n_cells + kThreads - 1) / kThreads, 2048);
+        if (fp64) hipLaunchKernelGGL(k_events_lane<double>, dim3(gl), dim3(kThreads), 0, st, A, view64(t), view64(t), W);
+        else hipLaunchKernelGGL(k_events_lane<float>, dim3(gl), dim3(kThreads), 0, st, A, view32(t), view64(t), W);
+        CMC_CHECK_LAUNCH2(who, "k_events_lane");
+    }
     if (from_wave) {
         const unsigned gw = (unsigned)std::min<int64_t>((A.n_cells + kWaves - 1) / kWaves, 2048);
         if (fp64) hipLaunchKernelGGL(k_events_wave<double>, dim3(gw), dim3(kThreads), 0, st, A, view64(t), view64(t), W);

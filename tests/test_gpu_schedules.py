@@ -158,14 +158,16 @@ def test_cycled_photons_bit_identical_across_team_shapes(precision, other):
     assert A["ti"][:, 5].sum() > 20
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_foil_cells_bit_identical_across_schedules(precision):
+@pytest.mark.parametrize("precision,processes", [(0, 7), (1, 7), (0, 3), (1, 3)])
+def test_foil_cells_bit_identical_across_schedules(precision, processes):
     """Foil cells (4096 electrons + 4096 Au ions, the photons of earlier steps
     cycled against the ions): the stream kernel with workgroup teams, with
     wavefront teams (SPLIT) and from the work queue, and the same schedules
-    without it, give the same bits."""
+    without it, give the same bits.  Without Trident (processes 3) the cells
+    the stream kernel lists go to the lane event kernel, the others' to the
+    wavefront one."""
     import paper_1907_02814_amd as cmc
-    wl = W.cfg5(np.random.default_rng(61), n_cells=48, per_cell=4096, dt=4e-15, processes=7)
+    wl = W.cfg5(np.random.default_rng(61), n_cells=48, per_cell=4096, dt=4e-15, processes=processes)
     states = [_state(wl, _sched(s), precision) for s in ("GROUP", "SPLIT", "QUEUE", "GROUP-", "QUEUE-", "SPLIT-")]
     for s in range(4):
         snaps = []

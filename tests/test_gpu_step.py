@@ -219,15 +219,20 @@ def test_stream_kernel_cells(precision):
     assert I[:, 3].sum() > 100
 
 
-def test_stream_kernel_fp64_filter_edges():
-    """FP64 form, Bremsstrahlung and Bethe-Heitler (no Trident): the stream
-    kernel filters its bound tests in FP32 and tests the pairs that pass
-    from their FP64 sigma v.  Half the electrons sit 1e-9 to 1e-6 (relative)
-    from the emission threshold, the segment joins gamma = 2 and 100 and
-    the top of the tables, where FP32 energies may fall on the other side,
-    or above the top (the status bit of energies above the tables); the run
-    must match the oracle.  None sits on a boundary itself: there the last
-    bit of the FP64 energy (how its sum of squares is rounded) decides."""
+@pytest.mark.parametrize("precision", [0, 1])
+def test_stream_kernel_filter_edges(precision):
+    """Bremsstrahlung and Bethe-Heitler (no Trident), both forms: in the FP64
+    form the stream kernel filters its bound tests in FP32 and tests the
+    pairs that pass from their FP64 sigma v; the cells it lists go to the
+    lane event kernel.  FP64: half the electrons sit 1e-9 to 1e-6
+    (relative) from the emission threshold, the segment joins gamma = 2
+    and 100 and the top of the tables, where FP32 energies may fall on the
+    other side, or above the top (the status bit of energies above the
+    tables).  None sits on a boundary itself: there the last bit of the
+    FP64 energy (how its sum of squares is rounded) decides.  FP32: the
+    form itself looks up FP32 energies, which this close to a join take
+    the other segment's cross section, so only the electrons above the top
+    are added.  The run must match the oracle."""
     import paper_1907_02814_amd as cmc
     rng = np.random.default_rng(83)
     ne = np.array([1100, 1500, 2048, 2500, 1200, 1800])
@@ -238,15 +243,17 @@ def test_stream_kernel_fp64_filter_edges():
     tmin = 1e-3 / MEC2
     eps = np.array([-1e-6, -3e-8, -1e-9, 1e-9, 3e-8, 1e-6])
     edges = np.concatenate([2.0 * (1 + eps), 100.0 * (1 + eps), 1 + tmin * (1 + eps), 2e4 * (1 + eps), [3e4]])
+    if precision == cmc.FP32:
+        edges = np.array([3e4])
     e_g = 1 + np.exp(rng.uniform(math.log(1e-3), math.log(500.0), ne.sum())) / MEC2
     pick = rng.random(ne.sum()) < 0.5
     e_g[pick] = rng.choice(edges, int(pick.sum()))
     k = 2.0 + rng.exponential(5.0 / MEC2, ng.sum())
-    wl = W.assemble("stream-fp64-edges", 79, 1.5e-15, int(cmc.BREMS | cmc.BH), 1, rng.uniform(0.0, 79.0, n), n_i,
+    wl = W.assemble("stream-edges", 79, 1.5e-15, int(cmc.BREMS | cmc.BH), 1, rng.uniform(0.0, 79.0, n), n_i,
                     np.full(n, 100.0), e_g, np.repeat(n_i / ni, ne) * rng.lognormal(0.0, 1.0, ne.sum()), ne, k,
                     np.repeat(n_i / ni, ng) * rng.lognormal(0, 1, ng.sum()), ng, np.repeat(n_i / ni, ni), ni, rng,
                     photon_extra=np.full(n, 512), pair_cap=np.full(n, 128))
-    P = _run(wl, 3, precision=cmc.FP64, schedule=cmc.SCHED_GROUP)
+    P = _run(wl, 3, precision=precision, schedule=cmc.SCHED_GROUP)
     I = P.state.ti.cpu().numpy()
     assert I[:, 3].sum() > 20
     assert int(P.state.status.item()) & cmc.ST_GAMMA_HIGH
