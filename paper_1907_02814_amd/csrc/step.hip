@@ -2575,7 +2575,7 @@ __global__ __launch_bounds__(kStreamThreads, kStreamWaves) void k_stream(StepArg
 // that needs an order larger than cap is deferred to list_big[kPass],
 // which a launch with a larger cap walks (from_list = 1).  Cells above
 // slow_cap, the largest cap of the step, take the sequential step whole.
-template <typename R, int kT, int kPass, bool kMov>
+template <typename R, int kT, int kPass, bool kMov, bool kRest = false>
 __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, TabView<R> T, Work W, int cap, int filter, int fcap,
                                                                  int slow_cap, int from_list) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -2587,6 +2587,8 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
     __shared__ uint32_t opk[kTeams][kCandCap];    // their particles' keys
     __shared__ uint32_t opj[kTeams][kCandCap];    // their pair indices
     __shared__ int nopen[kTeams];
+    __shared__ int32_t rest_ent[kRest ? 256 : 1];             // per thread: its list_rest entry of the batch
+    __shared__ unsigned long long rest_mask[kRest ? 4 : 1];   // per wavefront: the entries >= 0
     const int team = kT == 64 ? (int)(threadIdx.x >> 6) : 0;
     const int t = Team<kT>::tid();
     const size_t tstride = (team_bytes(cap, (int)sizeof(R), kT) + 15) / 16 * 16;
@@ -2604,19 +2606,57 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
     // cell.  (Folded into the choice of n_items below, as a nested
     // conditional, this test made the compiler drop n_cells on the path where
     // the count is not zero: the early return keeps the two apart.)
-    if (from_list == 3 && __hip_atomic_load(&W.counters[kCntRest], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+    if ((kRest || from_list == 3) &&
+        __hip_atomic_load(&W.counters[kCntRest], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
         return;
-    const int64_t n_items = from_list == 1 ? (int64_t)W.counters[kPass == 1 ? kCntBig1 : kCntBig0] : A.n_cells;
-    for (int64_t item = (int64_t)blockIdx.x * kTeams + team; item < n_items; item += (int64_t)gridDim.x * kTeams) {
-        const int64_t c = from_list == 2 ? (int64_t)W.queue[item]
-                        : from_list == 3 ? (int64_t)W.list_rest[item]
-                        : from_list ? (int64_t)W.list_big[kPass == 1 ? 1 : 0][item] : item;
-        if (c < 0) continue;                     // done by the stream kernel
-        PassCarry carry{0, 0.0};
-        if constexpr (kPass != 1)
-            pass_cell<R, kT, 0, kMov, false>(A, T, W, cap, filter, fcap, slow_cap, c, M, rng, rej, t, L, carry);
-        if constexpr (kPass != 0)
-            pass_cell<R, kT, 1, kMov, kPass == 2>(A, T, W, cap, filter, fcap, slow_cap, c, M, rng, rej, t, L, carry);
+    if constexpr (kRest) {
+        // from_list 3 (its own instantiation, so that the other lists keep
+        // their plain loop): the team's items are item0 + k G (G teams in
+        // the grid, which holds only the teams that fit on the device at
+        // once); their list_rest entries are read kT at a time, one per
+        // thread, and the cells among them (entries >= 0: the cells the
+        // stream kernel left) run in item order
+        const int64_t G = (int64_t)gridDim.x * kTeams;
+        for (int64_t i0 = (int64_t)blockIdx.x * kTeams + team; i0 < A.n_cells; i0 += G * kT) {
+            const int64_t it = i0 + (int64_t)t * G;
+            const int32_t e = it < A.n_cells ? W.list_rest[it] : -1;
+            const unsigned long long mk = __ballot(e >= 0);
+            rest_ent[threadIdx.x] = e;
+            if ((t & 63) == 0) rest_mask[threadIdx.x >> 6] = mk;
+            Team<kT>::sync();
+            for (int w = 0; w < kT / 64; ++w) {
+                // the mask and the cell as wave-uniform values (scalar registers)
+                const int wave = kT == 64 ? team : w;
+                const unsigned long long mw = rest_mask[wave];
+                unsigned long long m =
+                    ((unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(mw >> 32)) << 32) |
+                    (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)mw);
+                for (; m; m &= m - 1ull) {
+                    const int64_t c = __builtin_amdgcn_readfirstlane(rest_ent[wave * 64 + __ffsll((long long)m) - 1]);
+                    PassCarry carry{0, 0.0};
+                    if constexpr (kPass != 1)
+                        pass_cell<R, kT, 0, kMov, false>(A, T, W, cap, filter, fcap, slow_cap, c, M, rng, rej, t, L,
+                                                         carry);
+                    if constexpr (kPass != 0)
+                        pass_cell<R, kT, 1, kMov, kPass == 2>(A, T, W, cap, filter, fcap, slow_cap, c, M, rng, rej, t,
+                                                              L, carry);
+                }
+            }
+            Team<kT>::sync();   // the entries are read before the next batch
+        }
+    } else {
+        const int64_t n_items = from_list == 1 ? (int64_t)W.counters[kPass == 1 ? kCntBig1 : kCntBig0] : A.n_cells;
+        for (int64_t item = (int64_t)blockIdx.x * kTeams + team; item < n_items; item += (int64_t)gridDim.x * kTeams) {
+            const int64_t c = from_list == 2 ? (int64_t)W.queue[item]
+                            : from_list == 3 ? (int64_t)W.list_rest[item]
+                            : from_list ? (int64_t)W.list_big[kPass == 1 ? 1 : 0][item] : item;
+            if (c < 0) continue;                     // done by the stream kernel
+            PassCarry carry{0, 0.0};
+            if constexpr (kPass != 1)
+                pass_cell<R, kT, 0, kMov, false>(A, T, W, cap, filter, fcap, slow_cap, c, M, rng, rej, t, L, carry);
+            if constexpr (kPass != 0)
+                pass_cell<R, kT, 1, kMov, kPass == 2>(A, T, W, cap, filter, fcap, slow_cap, c, M, rng, rej, t, L, carry);
+        }
     }
 }
 
@@ -3545,7 +3585,7 @@ constexpr size_t kLdsMax = 160 * 1024;
 static int team_cap(int team, int maxn, bool fp64, int wgs_per_cu = 1) {
     const int rb = fp64 ? 8 : 4;
     int cap = team == 64 ? std::min(maxn, kWaveCap) : maxn;
-    const size_t static_lds = 2560;
+    const size_t static_lds = team == 64 ? 4608 : 2560;   // at least the pass kernel's static LDS
     while (cap > 64 && (size_t)wgs_per_cu * ((size_t)(256 / team) * ((team_bytes(cap, rb, team) + 15) / 16 * 16) + static_lds) > kLdsMax)
         cap -= 64;
     return cap;
@@ -3558,6 +3598,21 @@ static void lds_attr(const void* fn, size_t bytes, hipStream_t st) {
     (void)hipStreamIsCapturing(st, &cap);
     if (cap == hipStreamCaptureStatusNone)
         (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+// compute units of the current device (queried once per device)
+static int device_cus() {
+    static std::mutex mu;
+    static std::map<int, int> cus;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cus.find(dev);
+    if (it != cus.end()) return it->second;
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    cus[dev] = n;
+    return n;
 }
 
 // Optional timing of the pair-test kernels of a step: the first launch
@@ -3581,20 +3636,32 @@ struct PassLaunch {
 template <typename R, int kT, bool kMov>
 static void launch_pass_m(const StepArgs& A, const TabView<R>& T, const Work& W, const PassLaunch& L,
                           hipStream_t st, PassTiming* pt) {
-    const auto launch = [&](auto kernel) {
+    // the list of the cells the stream kernel left (from_list 3, ions at
+    // rest) has an instantiation of its own
+    const auto launch = [&](auto plain, auto rest) {
+        const auto kernel = (!kMov && L.from_list == 3) ? rest : plain;
         lds_attr((const void*)kernel, L.dshm, st);
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (pt) { e0 = pt->first ? pt->start : nullptr; e1 = pt->stop; pt->first = false; }
-        hipExtLaunchKernelGGL(kernel, dim3(L.grid), dim3(256), (uint32_t)L.dshm, st, e0, e1, 0u, A, T, W, L.cap,
+        // The launch over the cells the stream kernel left holds only the
+        // workgroups that fit on the device at once: when it left none, each
+        // returns after one read of the count, in one round.
+        unsigned grid = L.grid;
+        if (!kMov && L.from_list == 3) {
+            int per_cu = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, L.dshm) == hipSuccess && per_cu > 0)
+                grid = (unsigned)std::min<int64_t>(grid, (int64_t)per_cu * device_cus());
+        }
+        hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(256), (uint32_t)L.dshm, st, e0, e1, 0u, A, T, W, L.cap,
                               L.filter, L.fcap, L.slow_cap, L.from_list);
     };
     const bool ei = (L.passes & 1) && (A.proc & (CMC_BREMS | CMC_TRIDENT)) != 0;
     const bool gi = (L.passes & 2) && (A.proc & CMC_BH) != 0;
     if (ei && gi && L.from_list != 1) {
-        launch(k_pass<R, kT, 2, kMov>);
+        launch(k_pass<R, kT, 2, kMov>, k_pass<R, kT, 2, kMov, !kMov>);
     } else {
-        if (ei) launch(k_pass<R, kT, 0, kMov>);
-        if (gi) launch(k_pass<R, kT, 1, kMov>);
+        if (ei) launch(k_pass<R, kT, 0, kMov>, k_pass<R, kT, 0, kMov, !kMov>);
+        if (gi) launch(k_pass<R, kT, 1, kMov>, k_pass<R, kT, 1, kMov, !kMov>);
     }
 }
 
