@@ -2465,7 +2465,6 @@ __global__ __launch_bounds__(kStreamThreads, kStreamWaves) void k_stream(StepArg
             }
             if (t == 0) W.coef[c * 2] = coef;
         }
-        const int nc_e = nc;                         // the electron-ion pairs among them
         if (ph) {
             const double ng = ((pg[0] + pg[3]) + pg[6]) + pg[9];
             const double Ag = ((pg[1] + pg[4]) + pg[7]) + pg[10];
@@ -2541,7 +2540,7 @@ __global__ __launch_bounds__(kStreamThreads, kStreamWaves) void k_stream(StepArg
             const int32_t f = kFlagWeightsOk | kFlagIonsSame | kFlagDone0 | (ph ? kFlagDone1 : 0) |
                               (nc > kCandCap ? kFlagSlow : 0) | (nc > 0 ? kFlagListed : 0);
             if (nc > 0) {
-                const bool by_lane = nc == nc_e && nc <= kLaneCap && !tri && !left1;
+                const bool by_lane = nc <= kLaneCap && !tri && !left1;
                 if (!(atomicOr(&W.flags[c], f) & kFlagListed)) {
                     if (by_lane) W.list_lane[atomicAdd(&W.counters[kCntLane], 1)] = (int32_t)c;
                     else W.list_ev[atomicAdd(&W.counters[kCntEv], 1)] = (int32_t)c;
@@ -3401,16 +3400,18 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
 }
 
 
-// One lane per listed cell: the cells the stream kernel lists whose open
-// pairs are at most kLaneCap electron-ion pairs (its electrons pair once,
-// so no event falls on an electron used by a later pair), with Trident
-// off: nearly every listed cell of the Bremsstrahlung workloads.  The lane
-// settles its cell's open pairs in pair order (ev_pair) and applies their
-// events one after the other (ev_kin, each lane inverting its own CDFs):
-// the values, product slots and tallies of the wavefront kernel, whose
-// lanes take the same pairs in the same order and add the tallies in pair
-// order.  Many cells are in flight at once where the wavefront kernel has
-// one per wavefront.  A cell that does not qualify is handed to list_ev.
+// One lane per listed cell: the cells the stream kernel lists with at most
+// kLaneCap open pairs, Trident off and both passes done by it (nearly
+// every listed cell of the Bremsstrahlung workloads).  Its electrons pair
+// once, so no event falls on an electron used by a later pair.  The lane
+// settles the photon-ion pairs first: a conversion hands the cell to
+// list_ev before anything is written (its converted photons need the
+// workgroup kernel).  Then it settles the electron-ion pairs in pair order
+// (ev_pair) and applies their events one after the other (ev_kin, each
+// lane inverting its own CDFs): the values, product slots and tallies of
+// the wavefront kernel, whose lanes take the same pairs in the same order
+// and add the tallies in pair order.  Many cells are in flight at once
+// where the wavefront kernel has one per wavefront.
 template <typename R>
 __global__ __launch_bounds__(kThreads, 2) void k_events_lane(StepArgs A, TabView<R> T, TabView<double> T64, Work W) {
     const int n_items = W.counters[kCntLane];
@@ -3423,8 +3424,14 @@ __global__ __launch_bounds__(kThreads, 2) void k_events_lane(StepArgs A, TabView
 #pragma unroll
         for (int i = 0; i < kLaneCap; ++i) r[i] = i < E.nc ? W.cand[c * kCandCap + i] : ~0ull;
         bool hand = (E.flg & kFlagSlow) != 0 || E.ncr > kLaneCap || E.Ne < E.Ni || (A.proc & CMC_TRIDENT);
-#pragma unroll
-        for (int i = 0; i < kLaneCap; ++i) hand |= i < E.nc && ev_pass(r[i]) != 0;
+        // the photon-ion pairs: their near-threshold tests, or a conversion
+        int near_bh = 0;
+        for (int k = 0; k < E.nc && !hand; ++k) {
+            if (ev_pass(r[k]) != 1) continue;
+            const EvLane<R> L = ev_pair<R>(A, T, T64, rng, E, r[k], true, rej);
+            hand = L.kind != 0u;
+            near_bh += L.near_bh != 0 ? 1 : 0;
+        }
         if (hand) {
             W.list_ev[atomicAdd(&W.counters[kCntEv], 1)] = (int32_t)c;
             continue;
@@ -3439,8 +3446,10 @@ __global__ __launch_bounds__(kThreads, 2) void k_events_lane(StepArgs A, TabView
         order(0, 1); order(2, 3); order(0, 2); order(1, 3); order(1, 2);
         long long iv[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
         double dv[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        iv[5] = near_bh;
         int n_ph = 0;
         for (int k = 0; k < E.nc; ++k) {
+            if (ev_pass(r[k]) != 0) continue;   // photon-ion pairs without an event: counted above
             EvLane<R> L = ev_pair<R>(A, T, T64, rng, E, r[k], true, rej);
             const EvKin K = ev_kin<R>(A, T, T64, rng, E, L, false);
             Tally t = K.t;
@@ -3615,6 +3624,15 @@ static int device_cus() {
     return n;
 }
 
+// at most `want` workgroups, and no more than the device holds at once
+// (kernel with `threads` threads and `dshm` bytes of dynamic LDS)
+static unsigned resident_grid(const void* kernel, int threads, size_t dshm, int64_t want) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, dshm) == hipSuccess && per_cu > 0)
+        want = std::min<int64_t>(want, (int64_t)per_cu * device_cus());
+    return (unsigned)std::max<int64_t>(1, want);
+}
+
 // Optional timing of the pair-test kernels of a step: the first launch
 // records `start` when it begins, every launch records `stop` when it ends
 // (the last one wins), timestamped by the launches themselves.
@@ -3646,12 +3664,8 @@ static void launch_pass_m(const StepArgs& A, const TabView<R>& T, const Work& W,
         // The launch over the cells the stream kernel left holds only the
         // workgroups that fit on the device at once: when it left none, each
         // returns after one read of the count, in one round.
-        unsigned grid = L.grid;
-        if (!kMov && L.from_list == 3) {
-            int per_cu = 0;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, L.dshm) == hipSuccess && per_cu > 0)
-                grid = (unsigned)std::min<int64_t>(grid, (int64_t)per_cu * device_cus());
-        }
+        const unsigned grid = (!kMov && L.from_list == 3) ? resident_grid((const void*)kernel, 256, L.dshm, L.grid)
+                                                          : L.grid;
         hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(256), (uint32_t)L.dshm, st, e0, e1, 0u, A, T, W, L.cap,
                               L.filter, L.fcap, L.slow_cap, L.from_list);
     };
@@ -3992,8 +4006,12 @@ static cmc_status collide_step_impl(const char* who, cmc_tables t, const cmc_cel
     // first settles and applies the cells that need no workgroup and hands
     // the others on; with Bethe-Heitler alone every listed cell needs the
     // workgroup kernel, which then walks the list itself.
-    const unsigned gev = (unsigned)std::min<int64_t>(A.n_cells, 512);
+    // The event kernels walk their lists with as many workgroups as the
+    // device holds at once (an empty or short list then costs one round)
     const size_t shm_ev = std::max(shm, (size_t)kStagePh * 40);
+    const void* kev = fp64 ? (const void*)k_events<double> : (const void*)k_events<float>;
+    lds_attr(kev, shm_ev, st);   // before the occupancy query, which sees the attribute
+    const unsigned gev = resident_grid(kev, kThreads, shm_ev, std::min<int64_t>(A.n_cells, 512));
     const int from_wave = (A.proc & (CMC_BREMS | CMC_TRIDENT)) ? 1 : 0;
     if (from_wave && plan.stream && !(A.proc & CMC_TRIDENT)) {
         // the cells the stream kernel listed for a lane each (any it hands
@@ -4004,20 +4022,16 @@ static cmc_status collide_step_impl(const char* who, cmc_tables t, const cmc_cel
         CMC_CHECK_LAUNCH2(who, "k_events_lane");
     }
     if (from_wave) {
-        const unsigned gw = (unsigned)std::min<int64_t>((A.n_cells + kWaves - 1) / kWaves, 2048);
+        const unsigned gw = resident_grid(fp64 ? (const void*)k_events_wave<double> : (const void*)k_events_wave<float>,
+                                          kThreads, 0, std::min<int64_t>((A.n_cells + kWaves - 1) / kWaves, 2048));
         if (fp64) hipLaunchKernelGGL(k_events_wave<double>, dim3(gw), dim3(kThreads), 0, st, A, view64(t), view64(t), W);
         else hipLaunchKernelGGL(k_events_wave<float>, dim3(gw), dim3(kThreads), 0, st, A, view32(t), view64(t), W);
         CMC_CHECK_LAUNCH2(who, "k_events_wave");
     }
-    if (fp64) {
-        lds_attr((const void*)k_events<double>, shm_ev, st);
-        hipLaunchKernelGGL(k_events<double>, dim3(gev), dim3(kThreads), shm_ev, st, A, view64(t), view64(t), W,
-                           from_wave);
-    } else {
-        lds_attr((const void*)k_events<float>, shm_ev, st);
-        hipLaunchKernelGGL(k_events<float>, dim3(gev), dim3(kThreads), shm_ev, st, A, view32(t), view64(t), W,
-                           from_wave);
-    }
+    if (fp64) hipLaunchKernelGGL(k_events<double>, dim3(gev), dim3(kThreads), shm_ev, st, A, view64(t), view64(t), W,
+                                 from_wave);
+    else hipLaunchKernelGGL(k_events<float>, dim3(gev), dim3(kThreads), shm_ev, st, A, view32(t), view64(t), W,
+                            from_wave);
     CMC_CHECK_LAUNCH2(who, "k_events");
     return CMC_OK;
 }
