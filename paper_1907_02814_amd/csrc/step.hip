@@ -1986,7 +1986,7 @@ __device__ __forceinline__ void pass_cell(const StepArgs& A, const TabView<R>& T
 // pass is left, too).  One workgroup per cell, walking the cells in index
 // order or (from_list 2) the work queue.
 constexpr int kStreamPh = 256;   // photons per cell the stream kernel's photon-ion pass takes
-constexpr int kLaneCap = 4;      // open pairs per cell the lane event kernel takes
+constexpr int kLaneCap = 8;      // open pairs per cell the lane event kernel takes
 
 // f(integral_constant<int, I>) for I = 0, 1, ... in order, unrolled
 template <int... I, typename F>
@@ -3414,21 +3414,29 @@ __global__ __launch_bounds__(kThreads) void k_events(StepArgs A, TabView<R> T, T
 // where the wavefront kernel has one per wavefront.
 template <typename R>
 __global__ __launch_bounds__(kThreads, 2) void k_events_lane(StepArgs A, TabView<R> T, TabView<double> T64, Work W) {
+    __shared__ uint64_t rec[kLaneCap][kThreads];   // per lane (column): its cell's open-pair records
     const int n_items = W.counters[kCntLane];
     const double rej = 2.0 * (1.0 + A.near_rel);
     const Rng rng = step_rng(A);
     for (int item = (int)(blockIdx.x * kThreads + threadIdx.x); item < n_items; item += (int)(gridDim.x * kThreads)) {
         const int64_t c = W.list_lane[item];
         const EvCell<R> E = ev_cell<R>(A, W, c, 0);
-        uint64_t r[kLaneCap];
-#pragma unroll
-        for (int i = 0; i < kLaneCap; ++i) r[i] = i < E.nc ? W.cand[c * kCandCap + i] : ~0ull;
         bool hand = (E.flg & kFlagSlow) != 0 || E.ncr > kLaneCap || E.Ne < E.Ni || (A.proc & CMC_TRIDENT);
+        const int nc = hand ? 0 : E.nc;
+        // the cell's records in pair order, (pass, j), in the lane's column
+        // of LDS (insertion sort: at most kLaneCap records)
+        for (int i = 0; i < nc; ++i) {
+            const uint64_t v = W.cand[c * kCandCap + i];
+            int j = i;
+            for (; j > 0 && ev_key(rec[j - 1][threadIdx.x]) > ev_key(v); --j) rec[j][threadIdx.x] = rec[j - 1][threadIdx.x];
+            rec[j][threadIdx.x] = v;
+        }
         // the photon-ion pairs: their near-threshold tests, or a conversion
         int near_bh = 0;
-        for (int k = 0; k < E.nc && !hand; ++k) {
-            if (ev_pass(r[k]) != 1) continue;
-            const EvLane<R> L = ev_pair<R>(A, T, T64, rng, E, r[k], true, rej);
+        for (int k = 0; k < nc && !hand; ++k) {
+            const uint64_t rk = rec[k][threadIdx.x];
+            if (ev_pass(rk) != 1) continue;
+            const EvLane<R> L = ev_pair<R>(A, T, T64, rng, E, rk, true, rej);
             hand = L.kind != 0u;
             near_bh += L.near_bh != 0 ? 1 : 0;
         }
@@ -3436,21 +3444,14 @@ __global__ __launch_bounds__(kThreads, 2) void k_events_lane(StepArgs A, TabView
             W.list_ev[atomicAdd(&W.counters[kCntEv], 1)] = (int32_t)c;
             continue;
         }
-        // pair order (an absent record sorts last)
-        const auto order = [&](int a, int b) {
-            const bool sw = ev_key(r[b]) < ev_key(r[a]);
-            const uint64_t lo = sw ? r[b] : r[a], hi = sw ? r[a] : r[b];
-            r[a] = lo; r[b] = hi;
-        };
-        static_assert(kLaneCap == 4, "a sorting network of four");
-        order(0, 1); order(2, 3); order(0, 2); order(1, 3); order(1, 2);
         long long iv[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
         double dv[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         iv[5] = near_bh;
         int n_ph = 0;
-        for (int k = 0; k < E.nc; ++k) {
-            if (ev_pass(r[k]) != 0) continue;   // photon-ion pairs without an event: counted above
-            EvLane<R> L = ev_pair<R>(A, T, T64, rng, E, r[k], true, rej);
+        for (int k = 0; k < nc; ++k) {
+            const uint64_t rk = rec[k][threadIdx.x];
+            if (ev_pass(rk) != 0) continue;   // photon-ion pairs without an event: counted above
+            EvLane<R> L = ev_pair<R>(A, T, T64, rng, E, rk, true, rej);
             const EvKin K = ev_kin<R>(A, T, T64, rng, E, L, false);
             Tally t = K.t;
             t.near_br += L.near_br; t.near_tr += L.near_tr; t.near_bh += L.near_bh;

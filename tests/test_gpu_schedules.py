@@ -178,3 +178,25 @@ def test_foil_cells_bit_identical_across_schedules(precision, processes):
             for k in snaps[0]:
                 assert np.array_equal(snaps[0][k], other[k]), (s, k)
     assert snaps[0]["ti"][:, 3].sum() > 1000 and snaps[0]["ti"][:, 2].sum() > 0
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_lane_event_kernel_bit_identical(precision):
+    """Foil cells (Bremsstrahlung and Bethe-Heitler) at a dt that opens zero
+    to about ten pairs per cell: the lane event kernel, which takes the cells
+    the stream kernel lists with up to eight open pairs, and the wavefront
+    event kernel (the same schedule without the stream kernel) give the same
+    bits over four steps."""
+    wl = W.cfg5(np.random.default_rng(67), n_cells=64, per_cell=4096, dt=1.5e-16, processes=3)
+    states = [_state(wl, _sched(s), precision) for s in ("GROUP", "GROUP-", "SPLIT")]
+    events = 0
+    for s in range(4):
+        snaps = []
+        for g, st in states:
+            st.step(s)
+            snaps.append(_snap(g, st))
+        for other in snaps[1:]:
+            for k in snaps[0]:
+                assert np.array_equal(snaps[0][k], other[k]), (s, k)
+        events += int(snaps[0]["ti"][:, 3].sum())
+    assert events > 100

@@ -259,6 +259,17 @@ def test_stream_kernel_filter_edges(precision):
     assert int(P.state.status.item()) & cmc.ST_GAMMA_HIGH
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_lane_event_kernel_against_the_oracle(precision):
+    """Foil cells, Bremsstrahlung and Bethe-Heitler, at a dt that opens zero
+    to about ten pairs per cell: the cells the stream kernel lists go to the
+    lane event kernel (up to eight open pairs) or the wavefront one."""
+    import paper_1907_02814_amd as cmc
+    wl = W.cfg5(np.random.default_rng(71), n_cells=32, per_cell=4096, dt=1.5e-16, processes=3)
+    P = _run(wl, 3, precision=precision, schedule=cmc.SCHED_GROUP)
+    assert P.state.ti.cpu().numpy()[:, 3].sum() > 20
+
+
 @pytest.mark.parametrize("schedule", ["GROUP", "SPLIT", "QUEUE"])
 def test_stream_kernel_bad_weights(schedule):
     import paper_1907_02814_amd as cmc
