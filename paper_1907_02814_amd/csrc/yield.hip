@@ -99,7 +99,7 @@ constexpr double kKnotTol = 1e-4;
 template <typename A>
 struct EPos { int seg, i0; A w; bool in; };
 
-template <typename A>
+template <typename A, bool kKnots = true>
 __device__ __forceinline__ EPos<A> epos(const Axes& ax, A g, A gm1, bool& near) {
     EPos<A> o{kSegNone, 0, (A)0, false};
     near = false;
@@ -135,7 +135,7 @@ __device__ __forceinline__ EPos<A> epos(const Axes& ax, A g, A gm1, bool& near) 
         if (ig > n - 2) ig = n - 2;
         o.w = pos - (A)ig; o.in = true;
     }
-    if (f32) {
+    if (f32 && kKnots) {
         const A fr = pos - floor(pos);
         if (fr < (A)kKnotTol || fr > (A)(1.0 - kKnotTol)) near = true;
     }
@@ -144,11 +144,14 @@ __device__ __forceinline__ EPos<A> epos(const Axes& ax, A g, A gm1, bool& near) 
 }
 
 // The position in the arithmetic of the form R; in FP32 it is taken again
-// from the FP64 energy (momenta as stored) when the FP32 one is near a knot
-template <typename R>
+// from the FP64 energy (momenta as stored) when the FP32 one is near a
+// segment join, the floor or the top, and (kKnots, for the slopes of the
+// adjoint) near a knot.  The forward needs no knots: the interpolant is
+// continuous there, so either interval gives its value.
+template <typename R, bool kKnots = true>
 __device__ __forceinline__ EPos<R> electron_pos(const Axes& ax, R g, R gm1, double qx, double qy, double qz) {
     bool near;
-    EPos<R> o = epos<R>(ax, g, gm1, near);
+    EPos<R> o = epos<R, kKnots>(ax, g, gm1, near);
     if constexpr (sizeof(R) == 4) {
         if (near) {
             const double p2 = qx * qx + qy * qy + qz * qz, gd = sqrt(1.0 + p2), gm1d = p2 / (gd + 1.0);
@@ -329,7 +332,7 @@ __global__ __launch_bounds__(kThreads, sizeof(R) == 4 ? 4 : 3) void k_yield(YArg
             const R px = (R)r.x, py = (R)r.y, pz = (R)r.z;
             const R p2 = px * px + py * py + pz * pz;
             const R g = Fast<R>::sqrt((R)1 + p2), gm1 = Fast<R>::div(p2, g + (R)1);
-            const EPos<R> e = electron_pos<R>(T.ax, g, gm1, r.x, r.y, r.z);
+            const EPos<R> e = electron_pos<R, false>(T.ax, g, gm1, r.x, r.y, r.z);
             const BremsGrad<R> L = brems_grad<R>(e, sS, sK, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
             double y = 0.0;
             if (L.sig > 0.0) {
