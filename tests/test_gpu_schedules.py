@@ -200,3 +200,21 @@ def test_lane_event_kernel_bit_identical(precision):
                 assert np.array_equal(snaps[0][k], other[k]), (s, k)
         events += int(snaps[0]["ti"][:, 3].sum())
     assert events > 100
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_lane_event_kernel_photon_pairs_bit_identical(precision):
+    """Cells with photon-ion pairs open (some converting): the lane event
+    kernel after the stream kernel, and the wavefront and workgroup event
+    kernels without it, give the same bits over four steps."""
+    from test_gpu_step import _bh_lane_cells
+    wl = _bh_lane_cells()
+    states = [_state(wl, _sched(s), precision) for s in ("GROUP", "GROUP-", "SPLIT")]
+    for s in range(4):
+        snaps = []
+        for g, st in states:
+            st.step(s)
+            snaps.append(_snap(g, st))
+        for other in snaps[1:]:
+            for k in snaps[0]:
+                assert np.array_equal(snaps[0][k], other[k]), (s, k)

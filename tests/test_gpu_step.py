@@ -270,6 +270,41 @@ def test_lane_event_kernel_against_the_oracle(precision):
     assert P.state.ti.cpu().numpy()[:, 3].sum() > 20
 
 
+def _bh_lane_cells(dt=5e-14, seed=91):
+    """Cells for the lane event kernel with photon-ion pairs open: electrons
+    below the emission threshold but for 0.2% of 0.1-1 MeV, photons of
+    20-200 MeV cycled against the ions (10-256 of them), Bremsstrahlung and
+    Bethe-Heitler.  At dt = 5e-14 s a few pairs open per cell; some cells
+    convert a photon (handed on by the lane kernel), others do not."""
+    import paper_1907_02814_amd as cmc
+    rng = np.random.default_rng(seed)
+    ne = np.array([1100, 1500, 2048, 1300, 1200, 1800, 1400, 1600])
+    ni = ne.copy()
+    ng = np.array([50, 120, 200, 256, 30, 90, 160, 10])
+    n = len(ne)
+    n_i = np.full(n, 5.9e28)
+    e_g = 1 + rng.uniform(0.1e-3, 0.9e-3, ne.sum()) / MEC2
+    hot = rng.random(ne.sum()) < 0.002
+    e_g[hot] = 1 + rng.uniform(0.1, 1.0, int(hot.sum())) / MEC2
+    k = np.exp(rng.uniform(math.log(20.0), math.log(200.0), ng.sum())) / MEC2
+    return W.assemble("bh-lane", 79, dt, int(cmc.BREMS | cmc.BH), 1, rng.uniform(1.0, 79.0, n), n_i,
+                      np.full(n, 100.0), e_g, np.repeat(n_i / ni, ne), ne, k,
+                      np.repeat(n_i / ni, ng) * rng.lognormal(0, 1, ng.sum()), ng, np.repeat(n_i / ni, ni), ni, rng,
+                      photon_extra=np.full(n, 64), pair_cap=np.full(n, 64))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_lane_event_kernel_photon_pairs(precision):
+    """The lane event kernel with photon-ion pairs among a cell's open
+    pairs: cells without a conversion are applied by the lane, a conversion
+    hands the cell on to the wavefront and workgroup kernels.  Against the
+    oracle over three steps."""
+    import paper_1907_02814_amd as cmc
+    P = _run(_bh_lane_cells(), 3, precision=precision, schedule=cmc.SCHED_GROUP)
+    I = P.state.ti.cpu().numpy()    # the last step's tallies
+    assert I[:, 5].sum() > 0 and I[:, 3].sum() > 0
+
+
 @pytest.mark.parametrize("schedule", ["GROUP", "SPLIT", "QUEUE"])
 def test_stream_kernel_bad_weights(schedule):
     import paper_1907_02814_amd as cmc
