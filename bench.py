@@ -137,12 +137,16 @@ def count_evals(make, precision, steps, warmup, schedule, seed=1):
 
 def run_gpu(make, precision, steps, warmup, schedule, seed=1, graph=False):
     """K timed steps of a fresh copy of the workload (make() builds it in
-    device memory), then K more whose pair-test launches stamp HIP events
-    (the kernel durations).  Each timed step writes its integer tallies to
-    a row of its own (the pass kernels count the pairs they test), so the
-    pair evaluations of the timed steps are summed afterwards, outside the
-    timed region.  graph: the timed steps are replays of one captured step
-    (its tallies in one buffer; the counts come from count_evals)."""
+    device memory) whose pair-test launches stamp HIP events on their stream
+    (the first launch at its start, a record after the last): the wall time
+    of the K steps gives the throughput, the events the kernel durations of
+    the same steps.  Each timed step writes its integer tallies to a row of
+    its own (the pass kernels count the pairs they test), so the pair
+    evaluations of the timed steps are summed afterwards, outside the timed
+    region.  graph: the timed steps are replays of one captured step (its
+    tallies in one buffer; the counts come from count_evals), and W + K
+    eager steps stamped after them give the kernel durations (of the last
+    K: after the host's pause the device runs its first steps slower)."""
     import torch
     import paper_1907_02814_amd as cmc
     g = make()
@@ -150,14 +154,15 @@ def run_gpu(make, precision, steps, warmup, schedule, seed=1, graph=False):
     st = cmc.StepState(tab, g.cells, g.electrons, g.photons, g.ions, g.new_el, g.new_po, dt=g.dt,
                        seed=seed, processes=g.processes, precision=precision, schedule=schedule)
     n = g.cells["Zstar"].numel()
-    rows = torch.zeros((steps, n, len(cmc.I_NAMES)), dtype=torch.int64, device="cuda:0")
     stream = torch.cuda.current_stream()
     H = HipEvents()
-    evs = H.create(2 * steps)
+    evs = H.create(2 * (warmup + steps))
     for s in range(warmup):
         st.step(s, stream)
     torch.cuda.synchronize()
-    # the K timed steps, as a user runs them
+    # the live photons before the first and after the last measured step
+    # (their mean over the steps, by linear growth, for the algorithmic bytes)
+    ng0 = int(g.photons["count"].sum().item())
     if graph:
         gr, counter = st.graph(warmup)
         torch.cuda.synchronize()
@@ -167,41 +172,36 @@ def run_gpu(make, precision, steps, warmup, schedule, seed=1, graph=False):
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         st.use_counter(None)
-        del gr, counter, rows
+        del gr, counter
         evals, events = None, None
+        ng0 = int(g.photons["count"].sum().item())
+        for i in range(warmup + steps):
+            st.step(warmup + steps + i, stream, events=(evs[2 * i], evs[2 * i + 1]))
+        torch.cuda.synchronize()
+        pass_ms = [H.elapsed_ms(evs[2 * i], evs[2 * i + 1]) for i in range(warmup, warmup + steps)]
     else:
+        rows = torch.zeros((steps, n, len(cmc.I_NAMES)), dtype=torch.int64, device="cuda:0")
         t0 = time.perf_counter()
         for i in range(steps):
             st.set_tallies(ti=rows[i])
-            st.step(warmup + i, stream)
+            st.step(warmup + i, stream, events=(evs[2 * i], evs[2 * i + 1]))
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         st.set_tallies(ti=None)
+        pass_ms = [H.elapsed_ms(evs[2 * i], evs[2 * i + 1]) for i in range(steps)]
         evals = int(rows[:, :, 0:3].sum().item())
         events = rows[:, :, 3:6].sum((0, 1)).tolist()
         del rows
-    # K more steps whose pair-test launches stamp HIP events at their start
-    # and end (on their stream): the kernel durations.  These steps are kept
-    # apart from the ones whose wall time gives the throughput.
-    # (the photons live before each of them, for its algorithmic bytes, are
-    # counted between the steps, outside the stamped kernels)
-    ng = torch.zeros(steps, dtype=torch.int64, device="cuda:0")
-    t1 = time.perf_counter()
-    for i in range(steps):
-        ng[i] = g.photons["count"].sum()
-        st.step(warmup + steps + i, stream, events=(evs[2 * i], evs[2 * i + 1]))
-    torch.cuda.synchronize()
-    wall_ev = time.perf_counter() - t1
-    pass_ms = [H.elapsed_ms(evs[2 * i], evs[2 * i + 1]) for i in range(steps)]
+    ng1 = int(g.photons["count"].sum().item())
     H.destroy(evs)
     status = int(st.status.item())
-    alg = algorithmic_bytes_dev(g, float(ng.double().mean().item()))
+    alg = algorithmic_bytes_dev(g, ng0 + (ng1 - ng0) * (steps - 1) / (2 * steps))
     step_b = alg + g.cells["Zstar"].numel() * (24 + 12 * 8 + 10 * 8)
     del st, g
     torch.cuda.empty_cache()
     if graph:
         evals, events = count_evals(make, precision, steps, warmup, schedule, seed)
-    return {"wall_s": wall, "wall_events_s": wall_ev, "pass_ms": pass_ms, "evals": evals, "status": status,
+    return {"wall_s": wall, "pass_ms": pass_ms, "evals": evals, "status": status,
             "events": events, "alg_bytes": alg, "step_bytes": step_b}
 
 
@@ -458,7 +458,6 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": kname, "kernel_ms": kavg, "alg_bytes_per_launch": alg},
         "step_hbm_frac": fp32["step_bytes"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-        "ms_per_step_with_kernel_events": fp32["wall_events_s"] * 1e3 / a.steps,
         "status": fp32["status"],
         "events_per_step": [e / a.steps for e in fp32["events"]],
     }

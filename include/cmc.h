@@ -138,9 +138,9 @@ typedef struct {
     double near_rel;       /* band |U - P| <= near_rel * P counted as near-threshold,
                               in [0, 1] (default 1e-6)                        */
     void* pass_events[2];  /* optional hipEvent_t pair (both or none), to time
-                              the pair-test kernels of the step: [0] takes the
-                              start of the first of them and [1] the end of the
-                              last, stamped by the launches themselves (no
+                              the pair-test kernels of the step: [0] is
+                              stamped by the first of them at its start, [1]
+                              recorded on the stream after the last (no
                               marker between kernels); ignored by
                               CMC_SCHED_CELL                                  */
     uint64_t* step_counter;/* optional device [1] (NULL: use `step`): the step

@@ -3635,8 +3635,8 @@ static unsigned resident_grid(const void* kernel, int threads, size_t dshm, int6
 }
 
 // Optional timing of the pair-test kernels of a step: the first launch
-// records `start` when it begins, every launch records `stop` when it ends
-// (the last one wins), timestamped by the launches themselves.
+// records `start` when it begins (timestamped by the launch itself), and
+// `stop` is recorded on the stream after the last launch.
 struct PassTiming {
     hipEvent_t start, stop;
     bool first;
@@ -3661,7 +3661,7 @@ static void launch_pass_m(const StepArgs& A, const TabView<R>& T, const Work& W,
         const auto kernel = (!kMov && L.from_list == 3) ? rest : plain;
         lds_attr((const void*)kernel, L.dshm, st);
         hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (pt) { e0 = pt->first ? pt->start : nullptr; e1 = pt->stop; pt->first = false; }
+        if (pt) { e0 = pt->first ? pt->start : nullptr; pt->first = false; }
         // The launch over the cells the stream kernel left holds only the
         // workgroups that fit on the device at once: when it left none, each
         // returns after one read of the count, in one round.
@@ -3730,7 +3730,7 @@ static void launch_stream_r(const StepArgs& A, const TabView<R>& T, const Work& 
     const int64_t cap_blocks = from_list == 2 ? ((int64_t)1 << 20) : 256 * 64;
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(A.n_cells, cap_blocks));
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (pt) { e0 = pt->first ? pt->start : nullptr; e1 = pt->stop; pt->first = false; }
+    if (pt) { e0 = pt->first ? pt->start : nullptr; pt->first = false; }
     hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(kStreamThreads), (uint32_t)dshm, st, e0, e1, 0u, A, T, W, scap,
                           from_list);
 }
@@ -3998,9 +3998,13 @@ static cmc_status collide_step_impl(const char* who, cmc_tables t, const cmc_cel
         CMC_CHECK_LAUNCH2(who, "k_cell_state");
     }
     PassTiming timing{static_cast<hipEvent_t>(P->pass_events[0]), static_cast<hipEvent_t>(P->pass_events[1]), true};
-    cmc_status s1 = launch_passes(A, t, W, fp64, plan, st,
-                                  (P->pass_events[0] && P->pass_events[1]) ? &timing : nullptr);
+    const bool timed = P->pass_events[0] && P->pass_events[1];
+    cmc_status s1 = launch_passes(A, t, W, fp64, plan, st, timed ? &timing : nullptr);
     if (s1 != CMC_OK) return s1;
+    if (timed && hipEventRecord(timing.stop, st) != hipSuccess) {
+        set_error("%s: hipEventRecord of pass_events[1] failed", who);
+        return CMC_EDEVICE;
+    }
     // the listed cells: open pairs and events, or the sequential step (a
     // short list: a small grid)
     // When electron-ion pairs can be open, a wavefront per listed cell
