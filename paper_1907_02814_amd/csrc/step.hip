@@ -2097,6 +2097,7 @@ __global__ __launch_bounds__(kStreamThreads, kStreamWaves) void k_stream(StepArg
     __shared__ int rsf[kW];                       // per wavefront: flag bits
     __shared__ double pg[kPh ? 4 * 3 : 1];        // per wavefront of the 256 order: the photons' n_g, A, B parts
     __shared__ int pgf[kPh ? kW : 1];             // per wavefront: 1 bad photon weight, 4 above the tables
+    __shared__ float pgm[kPh ? kW : 1];           // per wavefront: the smallest 1/(sigma c) of its photons
     __shared__ uint32_t opn[kCandCap];
     __shared__ int nopen;
     // the photons of the cell: key, then rank; repetitions; sigma and 1/(sigma c)
@@ -2190,6 +2191,7 @@ __global__ __launch_bounds__(kStreamThreads, kStreamWaves) void k_stream(StepArg
             // the canonical per-wavefront parts of n_g, A = sum min(W_g, W_i)
             // and B, the same over the photons that pair once more
             int flg = 0;
+            float imin = INFINITY;
 #pragma unroll
             for (int v = 0; v < kV; ++v) {
                 const int mt = t + kST * v;
@@ -2208,6 +2210,7 @@ __global__ __launch_bounds__(kStreamThreads, kStreamWaves) void k_stream(StepArg
                     flg |= hi ? 4 : 0;
                     gsig[mt] = (float)sig;
                     ginv[mt] = sig > (R)0 ? 1.0f / ((float)sig * (float)phys::kC) : -1.0f;
+                    if (sig > (R)0) imin = fminf(imin, ginv[mt]);
                     flg |= (!(gw[v] >= 0.0) || !isfinite(gw[v])) ? 1 : 0;
                     const double m = gw[v] < w0 ? gw[v] : w0;
                     pa = 0.0 + gw[v];
@@ -2224,9 +2227,19 @@ __global__ __launch_bounds__(kStreamThreads, kStreamWaves) void k_stream(StepArg
                 }
             }
             const int f1 = __ballot(flg & 1) != 0ull ? 1 : 0, f4 = __ballot(flg & 4) != 0ull ? 4 : 0;
-            if (lane == 0) pgf[wv] = f1 | f4;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) imin = fminf(imin, __shfl_xor(imin, o, 64));
+            if (lane == 0) { pgf[wv] = f1 | f4; pgm[wv] = imin; }
             __syncthreads();
         }
+        // the filter of the photon-ion tests bounds every test with the
+        // largest sigma of the cell's photons: v / (sigma_max c) is at most
+        // the test's own v / (sigma c), so no test that passes is missed
+        // (the exact tests follow for a thread whose bound passes)
+        float ginv_min = INFINITY;
+        if (ph)
+#pragma unroll
+            for (int w = 0; w < kW; ++w) ginv_min = fminf(ginv_min, pgm[w]);
         double sa[kV], sb[kV], si[kV];           // n_e, n_ab and n_i: canonical parts of the slots
 #pragma unroll
         for (int v = 0; v < kV; ++v) { sa[v] = 0.0; sb[v] = 0.0; si[v] = 0.0; }
@@ -2246,13 +2259,8 @@ __global__ __launch_bounds__(kStreamThreads, kStreamWaves) void k_stream(StepArg
             for (int w = 0; w < 4; ++w) {
                 const int x = base + 256 * w;
                 if (x >= X) break;
-                const int m = mod_small(x, Ng, rNg);
-                const int k = __float2int_rn((float)(x - m) * rNg);
-                const float inv = ginv[m];
-                if (k < (int)greps[m] && inv > 0.0f) {
-                    const uint32_t v = hi_word(h, (uint32_t)w) >> 8;
-                    lg.add(v == 0u ? 0.0f : (float)v * inv, x);
-                }
+                const uint32_t v = hi_word(h, (uint32_t)w) >> 8;
+                lg.add(v == 0u ? 0.0f : (float)v * ginv_min, x);
             }
         };
         // record u of the walk (q = t + kST u), slot v = u mod kV
