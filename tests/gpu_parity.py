@@ -30,6 +30,21 @@ def gpu_tables(Z):
     return cmc.build_tables(Z)
 
 
+def tally_scale(otd):
+    """Scale of each FP64 tally of each cell for its relative error: the
+    tally itself for n_ab, the event energies E_br, E_tr, E_bh and the
+    weights, sums of terms of one sign.  The energy changes dE_el and
+    dE_ph can mix signs (with moving ions a lab-frame change may be a
+    gain), so they are judged against the cell's energy throughput, the
+    sum of the magnitudes of its energy tallies (the oracle does not report
+    their terms)."""
+    sc = np.abs(otd).astype(np.float64)
+    pooled = np.abs(otd[:, 2:5]).sum(1) + np.abs(otd[:, 5:7]).sum(1)
+    for q in (5, 6):
+        sc[:, q] = np.maximum(sc[:, q], pooled)
+    return sc
+
+
 def _vec_rel(ax, ay, az, bx, by, bz):
     """|a - b|/|b| per particle (0 where both vanish)."""
     da = np.sqrt((ax - bx) ** 2 + (ay - by) ** 2 + (az - bz) ** 2)
@@ -117,11 +132,11 @@ class Parity:
             if G.get("parent") is not None and Rr.get("parent") is not None:
                 wrong |= live & (G["parent"].cpu().numpy() != Rr["parent"])
             flag(np.bincount(cells[wrong], minlength=n) > 0, name)
-        # FP64 tallies
-        scale = np.abs(otd[:, 2:5]).sum(1) + np.abs(otd[:, 5:7]).sum(1)
+        # FP64 tallies (scales: tally_scale)
+        S = tally_scale(otd)
         for q in range(otd.shape[1]):
             ref = otd[:, q]
-            sc = np.maximum(np.abs(ref), scale if q in (2, 3, 4, 5, 6) else np.abs(ref))
+            sc = S[:, q]
             errq = np.abs(td[:, q] - ref) / np.maximum(sc, 1e-300)
             self._note("tally " + D_NAMES[q], errq[keep])
             flag(errq > rtol, "tally " + D_NAMES[q])
@@ -161,9 +176,7 @@ def compare_sampled_cells(g, st, ref, sample, oti, otd, rtol):
     if not np.array_equal(ti[keep], oti[keep]):
         c = int(np.flatnonzero(np.any(ti != oti, axis=1) & keep)[0])
         raise AssertionError(f"integer tallies of cell {sample[c]}: {ti[c].tolist()} vs {oti[c].tolist()}")
-    scale = np.abs(otd[:, 2:5]).sum(1, keepdims=True) + np.abs(otd[:, 5:7]).sum(1, keepdims=True)
-    sc = np.maximum(np.maximum(np.abs(otd), scale), 1e-300)
-    err = np.abs(td - otd) / sc
+    err = np.abs(td - otd) / np.maximum(tally_scale(otd), 1e-300)
     if keep.any() and err[keep].max() > rtol:
         raise AssertionError(f"FP tallies differ by {err[keep].max():.3g}")
     for name in ("electrons", "photons", "new_el", "new_po"):
@@ -207,9 +220,7 @@ def compare_host_subsets(ti, td, now, ref, oti, otd, rtol, skip_cells=None):
     if bad.any():
         c = int(np.flatnonzero(bad)[0])
         raise AssertionError(f"integer tallies of cell {c}: {ti[c].tolist()} vs {oti[c].tolist()}")
-    scale = np.abs(otd[:, 2:5]).sum(1, keepdims=True) + np.abs(otd[:, 5:7]).sum(1, keepdims=True)
-    sc = np.maximum(np.maximum(np.abs(otd), scale), 1e-300)
-    err = np.abs(td - otd) / sc
+    err = np.abs(td - otd) / np.maximum(tally_scale(otd), 1e-300)
     errs["tallies"] = float(err[keep].max()) if keep.any() else 0.0
     if errs["tallies"] > rtol:
         raise AssertionError(f"FP tallies differ by {errs['tallies']:.3g}")
