@@ -22,7 +22,8 @@
  *    the default stream) and return without synchronising.
  *  - Argument errors found on the host return CMC_EINVAL (or CMC_ERANGE)
  *    synchronously, enqueue nothing and set the thread-local message of
- *    cmc_last_error().  Errors found on the device (bad cell parameters,
+ *    cmc_last_error().  Among them: a device array whose address is not a
+ *    multiple of its element size (8 for double and int64, 4 for int32).  Errors found on the device (bad cell parameters,
  *    bad weights, energies above the tables, full product buffers, cells
  *    larger than the launch allows) never abort the launch: they set bits
  *    of the sticky status word (CMC_ST_*) and are counted in the tallies.
@@ -39,7 +40,8 @@ extern "C" {
 
 typedef enum {
     CMC_OK = 0,
-    CMC_EINVAL = 1,    /* bad argument (null pointer, size, flag)           */
+    CMC_EINVAL = 1,    /* bad argument (null or misaligned pointer, size,   */
+                       /* flag)                                             */
     CMC_ERANGE = 2,    /* argument outside the supported range              */
     CMC_EDEVICE = 3,   /* HIP runtime error (launch, copy, memory)          */
     CMC_ENOMEM = 4     /* device allocation failed (cmc_build_tables only)  */

@@ -54,3 +54,12 @@ inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s);
     do {                                                                         \
         if (!(cond)) { cmc::set_error(__VA_ARGS__); return code; }               \
     } while (0)
+
+namespace cmc {
+// NULL, or aligned to the element type the library reads there (the host
+// check of a device array pointer; nothing is dereferenced)
+template <typename T>
+inline bool aligned_to(const void* p) {
+    return (reinterpret_cast<uintptr_t>(p) % alignof(T)) == 0;
+}
+}  // namespace cmc

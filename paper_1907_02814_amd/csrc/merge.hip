@@ -130,6 +130,11 @@ static cmc_status check_pair(const char* who, const cmc_species* d, const cmc_sp
     const bool dm = d->px && d->py && d->pz, sm = s->px && s->py && s->pz;
     CMC_REQUIRE(dm == sm && (dm || (!d->px && !d->py && !d->pz && !s->px && !s->py && !s->pz)), CMC_EINVAL,
                 "%s: px, py, pz must be set on both species or on neither", who);
+    for (const cmc_species* x : {d, s})
+        CMC_REQUIRE(aligned_to<int64_t>(x->off) && aligned_to<int32_t>(x->count) && aligned_to<double>(x->px) &&
+                        aligned_to<double>(x->py) && aligned_to<double>(x->pz) && aligned_to<double>(x->w) &&
+                        aligned_to<int64_t>(x->parent),
+                    CMC_EINVAL, "%s: an array is not aligned to its element type", who);
     return CMC_OK;
 }
 
@@ -153,6 +158,8 @@ extern "C" cmc_status cmc_rebin_offsets(int64_t n_cells, const cmc_species* src,
     CMC_REQUIRE(n_cells >= 0, CMC_EINVAL, "%s: n_cells < 0", who);
     CMC_REQUIRE(headroom >= 0, CMC_EINVAL, "%s: headroom < 0", who);
     CMC_REQUIRE(src && src->off && off_new, CMC_EINVAL, "%s: NULL argument", who);
+    CMC_REQUIRE(aligned_to<int64_t>(src->off) && aligned_to<int32_t>(src->count) && aligned_to<int64_t>(off_new),
+                CMC_EINVAL, "%s: an array is not aligned to its element type", who);
     hipLaunchKernelGGL(k_rebin_offsets, dim3(1), dim3(kScanThreads), 0, as_stream(stream), src->off, src->count,
                        n_cells, headroom, off_new);
     CMC_CHECK_LAUNCH(who);

@@ -211,6 +211,10 @@ extern "C" cmc_status cmc_screening_functions(cmc_tables t, int32_t form, int64_
     CMC_REQUIRE(n >= 0, CMC_EINVAL, "cmc_screening_functions: n < 0");
     if (n == 0) return CMC_OK;
     CMC_REQUIRE(Zstar && n_i && T_e && delta && I1 && I2, CMC_EINVAL, "cmc_screening_functions: NULL array");
+    CMC_REQUIRE(aligned_to<double>(Zstar) && aligned_to<double>(n_i) && aligned_to<double>(T_e) &&
+                    aligned_to<double>(delta) && aligned_to<double>(I1) && aligned_to<double>(I2) &&
+                    aligned_to<int32_t>(status),
+                CMC_EINVAL, "cmc_screening_functions: an array is not aligned to its element type");
     SArgs A{};
     A.Zs = Zstar; A.ni = n_i; A.Te = T_e; A.x = delta; A.o1 = I1; A.o2 = I2; A.status = status; A.n = n;
     A.Z = (double)t->Z; A.fc = t->fc; A.form = form;
@@ -231,6 +235,10 @@ extern "C" cmc_status cmc_cross_sections(cmc_tables t, int32_t process, int32_t 
     CMC_REQUIRE(n >= 0, CMC_EINVAL, "cmc_cross_sections: n < 0");
     if (n == 0) return CMC_OK;
     CMC_REQUIRE(Zstar && n_i && T_e && e1 && x && out, CMC_EINVAL, "cmc_cross_sections: NULL array");
+    CMC_REQUIRE(aligned_to<double>(Zstar) && aligned_to<double>(n_i) && aligned_to<double>(T_e) &&
+                    aligned_to<double>(e1) && aligned_to<double>(x) && aligned_to<double>(out) &&
+                    aligned_to<int32_t>(status),
+                CMC_EINVAL, "cmc_cross_sections: an array is not aligned to its element type");
     SArgs A{};
     A.Zs = Zstar; A.ni = n_i; A.Te = T_e; A.e1 = e1; A.x = x; A.o1 = out; A.status = status; A.n = n;
     A.Z = (double)t->Z; A.fc = t->fc; A.form = form; A.process = process;

@@ -3901,6 +3901,10 @@ static cmc_status set_species(SpeciesDev& d, const cmc_species* s, const char* n
     CMC_REQUIRE(!need_count || s->count, CMC_EINVAL, "cmc_collide_step: %s: count is required", name);
     CMC_REQUIRE(!need_mom || (s->px && s->py && s->pz), CMC_EINVAL,
                 "cmc_collide_step: %s: px, py, pz are required", name);
+    CMC_REQUIRE(aligned_to<int64_t>(s->off) && aligned_to<int32_t>(s->count) && aligned_to<double>(s->px) &&
+                    aligned_to<double>(s->py) && aligned_to<double>(s->pz) && aligned_to<double>(s->w) &&
+                    aligned_to<int64_t>(s->parent),
+                CMC_EINVAL, "cmc_collide_step: %s: an array is not aligned to its element type", name);
     d.off = s->off; d.count = s->count; d.px = s->px; d.py = s->py; d.pz = s->pz; d.w = s->w;
     d.parent = s->parent;
     return CMC_OK;
@@ -3916,6 +3920,11 @@ static cmc_status collide_step_impl(const char* who, cmc_tables t, const cmc_cel
     CMC_REQUIRE(cells->n_cells >= 0 && cells->Zstar && cells->n_i && cells->T_e, CMC_EINVAL,
                 "%s: cells incomplete", who);
     CMC_REQUIRE(tal->ti && tal->td && tal->status, CMC_EINVAL, "%s: tallies incomplete", who);
+    CMC_REQUIRE(aligned_to<double>(cells->Zstar) && aligned_to<double>(cells->n_i) && aligned_to<double>(cells->T_e) &&
+                    aligned_to<int64_t>(cells->cell_id) && aligned_to<int64_t>(tal->ti) && aligned_to<double>(tal->td) &&
+                    aligned_to<int32_t>(tal->status) && aligned_to<uint64_t>(P->step_counter) &&
+                    aligned_to<uint64_t>(workspace),
+                CMC_EINVAL, "%s: a cell, tally, counter or workspace array is not aligned to its element type", who);
     CMC_REQUIRE(P->dt > 0.0, CMC_EINVAL, "%s: dt must be > 0", who);
     CMC_REQUIRE((P->processes & ~7u) == 0, CMC_EINVAL, "%s: unknown process bits", who);
     CMC_REQUIRE(P->precision == CMC_FP64 || P->precision == CMC_FP32, CMC_EINVAL,
@@ -4120,6 +4129,11 @@ extern "C" cmc_status cmc_pair_cells(int64_t n_cells, const int64_t* cell_id, co
                                      void* stream) {
     CMC_REQUIRE(n_cells >= 0, CMC_EINVAL, "cmc_pair_cells: n_cells < 0");
     CMC_REQUIRE(a_off && b_off && wa && wb && pair_off && pa && pb, CMC_EINVAL, "cmc_pair_cells: NULL argument");
+    CMC_REQUIRE(aligned_to<int64_t>(cell_id) && aligned_to<int64_t>(a_off) && aligned_to<int64_t>(b_off) &&
+                    aligned_to<int32_t>(a_cnt) && aligned_to<int32_t>(b_cnt) && aligned_to<double>(wa) &&
+                    aligned_to<double>(wb) && aligned_to<int64_t>(pair_off) && aligned_to<int32_t>(pa) &&
+                    aligned_to<int32_t>(pb) && aligned_to<double>(n_ab),
+                CMC_EINVAL, "cmc_pair_cells: an array is not aligned to its element type");
     CMC_REQUIRE(pass == 1 || pass == 2, CMC_EINVAL, "cmc_pair_cells: pass must be 1 or 2");
     if (n_cells == 0) return CMC_OK;
     PairArgs A{};

@@ -498,6 +498,10 @@ static cmc_status yield_common(cmc_tables t, int64_t n_cells, const double* Zs, 
     // with no cell nothing is read or written: the arrays may be NULL
     CMC_REQUIRE(n_cells == 0 || (Zs && ne && Te && off), CMC_EINVAL, "%s: NULL cell array", who);
     CMC_REQUIRE(n_cells == 0 || n_part == 0 || (px && py && pz && w), CMC_EINVAL, "%s: NULL particle array", who);
+    CMC_REQUIRE(aligned_to<double>(Zs) && aligned_to<double>(ne) && aligned_to<double>(Te) &&
+                    aligned_to<int64_t>(off) && aligned_to<double>(px) && aligned_to<double>(py) &&
+                    aligned_to<double>(pz) && aligned_to<double>(w),
+                CMC_EINVAL, "%s: an input array is not aligned to its element type", who);
     return CMC_OK;
 }
 
@@ -511,6 +515,8 @@ extern "C" cmc_status cmc_expected_yield(cmc_tables t, int64_t n_cells, const do
     if (s != CMC_OK) return s;
     if (n_cells == 0) return CMC_OK;
     CMC_REQUIRE(Y, CMC_EINVAL, "cmc_expected_yield: Y is NULL");
+    CMC_REQUIRE(aligned_to<double>(Y) && aligned_to<double>(y_part) && aligned_to<int32_t>(status), CMC_EINVAL,
+                "cmc_expected_yield: an output array is not aligned to its element type");
     YArgs A{};
     A.Zs = Zstar; A.ne = n_e; A.Te = T_e; A.off = off; A.px = px; A.py = py; A.pz = pz; A.w = w;
     A.Y = Y; A.yp = y_part; A.status = status; A.n_cells = n_cells; A.n_part = n_part; A.dt = dt;
@@ -537,6 +543,10 @@ extern "C" cmc_status cmc_expected_yield_backward(cmc_tables t, int64_t n_cells,
     if (n_cells == 0) return CMC_OK;
     CMC_REQUIRE(gY && gZstar && gn_e && gT_e, CMC_EINVAL, "cmc_expected_yield_backward: NULL output");
     CMC_REQUIRE(n_part == 0 || (gpx && gpy && gpz), CMC_EINVAL, "cmc_expected_yield_backward: NULL output");
+    CMC_REQUIRE(aligned_to<double>(gY) && aligned_to<double>(gpx) && aligned_to<double>(gpy) &&
+                    aligned_to<double>(gpz) && aligned_to<double>(gw) && aligned_to<double>(gZstar) &&
+                    aligned_to<double>(gn_e) && aligned_to<double>(gT_e) && aligned_to<int32_t>(status),
+                CMC_EINVAL, "cmc_expected_yield_backward: an array is not aligned to its element type");
     YArgs A{};
     A.Zs = Zstar; A.ne = n_e; A.Te = T_e; A.off = off; A.px = px; A.py = py; A.pz = pz; A.w = w;
     A.gY = gY; A.gpx = gpx; A.gpy = gpy; A.gpz = gpz; A.gw = gw; A.gZs = gZstar; A.gne = gn_e;

@@ -176,3 +176,41 @@ def test_screening_calls_check_arguments_without_gpu():
     assert L.cmc_cross_sections(t, cmc.BH, 5, 0, *([None] * 8)) == 1
     assert L.cmc_cross_sections(t, cmc.BREMS, 1, 0, *([None] * 8)) == 0
     assert L.cmc_cross_sections(t, cmc.BREMS, 1, 2, *([None] * 8)) == 1
+
+
+def test_misaligned_arrays_are_refused_on_the_host():
+    """A device array pointer that is not aligned to its element type is
+    refused before anything is launched (the pointers here are placeholders,
+    never dereferenced; each call also lacks what a launch would need, so
+    nothing could run if a check were missing)."""
+    import paper_1907_02814_amd as cmc
+    L = cmc.get_lib()
+    ok8, odd = C.c_void_p(1 << 20), C.c_void_p((1 << 20) + 4)
+    t = C.c_void_p(1)
+    # collide_step: a cell array, then a species array (workspace NULL)
+    cells = cmc._Cells(2, odd, ok8, ok8, None)
+    tal = cmc._Tallies(ok8, ok8, ok8)
+    P = cmc._StepParams()
+    P.dt, P.processes, P.precision, P.schedule, P.max_per_cell, P.near_rel = 1e-16, 1, 0, 2, 64, 1e-6
+    sp = cmc._Species(ok8, ok8, ok8, ok8, ok8, ok8, None)
+    args = [C.byref(sp)] * 5
+    assert L.cmc_collide_step(t, C.byref(cells), *args, C.byref(P), C.byref(tal), None, 0, None) == 1
+    assert b"aligned" in L.cmc_last_error()
+    cells = cmc._Cells(2, ok8, ok8, ok8, None)
+    bad = cmc._Species(ok8, ok8, odd, ok8, ok8, ok8, None)
+    assert L.cmc_collide_step(t, C.byref(cells), C.byref(bad), *args[1:], C.byref(P), C.byref(tal), None, 0,
+                              None) == 1
+    assert b"aligned" in L.cmc_last_error() and b"electrons" in L.cmc_last_error()
+    bad = cmc._Species(ok8, C.c_void_p((1 << 20) + 2), ok8, ok8, ok8, ok8, None)   # count: int32
+    assert L.cmc_collide_step(t, C.byref(cells), args[0], C.byref(bad), *args[2:], C.byref(P), C.byref(tal), None,
+                              0, None) == 1
+    assert b"aligned" in L.cmc_last_error() and b"photons" in L.cmc_last_error()
+    # expected yield: the offsets (Y NULL)
+    assert L.cmc_expected_yield(t, 2, ok8, ok8, ok8, odd, 4, ok8, ok8, ok8, ok8, 1e-16, 0, None, None, None,
+                                None) == 1
+    assert b"aligned" in L.cmc_last_error()
+    # pair_cells: a pair array (int32) at an odd address (no stream, no tables: a
+    # missing check would reach the launch, which fails without a GPU)
+    odd2 = C.c_void_p((1 << 20) + 2)
+    assert L.cmc_pair_cells(1, None, ok8, None, ok8, None, ok8, ok8, 1, 0, 1, ok8, odd2, ok8, None, None) == 1
+    assert b"aligned" in L.cmc_last_error()
