@@ -288,10 +288,11 @@ YIELD_WORKLOAD = ("cfg4: expected yield and its adjoint, 1024 cells x 4096 elect
 def yield_bytes(n_cells, n_el):
     """Algorithmic bytes of one call: forward reads px, py, pz, w (32 B per
     electron) and the cell parameters (24 B), writes Y (8 B per cell); the
-    adjoint also reads gY and writes gpx, gpy, gpz, gw (32 B per electron)
-    and three cell gradients."""
+    adjoint reads the same and gY and writes gpx, gpy, gpz (24 B per
+    electron) and three cell gradients.  (It is timed without the optional
+    gradient with respect to the weights.)"""
     fwd = 32 * n_el + 32 * n_cells
-    bwd = 64 * n_el + 56 * n_cells
+    bwd = 56 * n_el + 56 * n_cells
     return fwd, bwd
 
 
@@ -316,7 +317,8 @@ def run_yield(calls=20, seed_cells=64, cpu=True):
     for name, prec in (("fp32", cmc.FP32), ("fp64", cmc.FP64)):
         row = {}
         for kind, fn, nbytes in (("forward", lambda: cmc.expected_yield(tab, *args, precision=prec), fwd_b),
-                                 ("adjoint", lambda: cmc.expected_yield_backward(tab, *args, gY, precision=prec), bwd_b)):
+                                 ("adjoint", lambda: cmc.expected_yield_backward(tab, *args, gY, precision=prec,
+                                                                                 weight_grad=False), bwd_b)):
             for _ in range(3):
                 fn()
             torch.cuda.synchronize()

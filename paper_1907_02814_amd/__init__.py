@@ -391,19 +391,21 @@ def expected_yield(tables: Tables, Zstar, n_e, T_e, off, px, py, pz, w, dt, prec
 
 
 def expected_yield_backward(tables: Tables, Zstar, n_e, T_e, off, px, py, pz, w, dt, gY,
-                            precision=FP64, stream=None, status=None):
+                            precision=FP64, stream=None, status=None, weight_grad=True):
+    """The adjoint of expected_yield (cmc_expected_yield_backward): a dict of
+    gpx, gpy, gpz, gZstar, gn_e, gT_e and, with weight_grad, gw."""
     import torch
     n = Zstar.numel()
     _lengths(cells=(n, n_e, T_e, gY), off=(n + 1, off), electrons=(px.numel(), py, pz, w), status=(1, status))
     _check_offsets(off, px.numel())
-    out = {k: torch.empty_like(px) for k in ("gpx", "gpy", "gpz", "gw")}
+    out = {k: torch.empty_like(px) for k in (("gpx", "gpy", "gpz", "gw") if weight_grad else ("gpx", "gpy", "gpz"))}
     out.update({k: torch.empty_like(Zstar) for k in ("gZstar", "gn_e", "gT_e")})
     f8 = "float64"
     _check(get_lib().cmc_expected_yield_backward(
         tables.handle, Zstar.numel(), _ptr(Zstar, f8), _ptr(n_e, f8), _ptr(T_e, f8), _ptr(off, "int64"),
         px.numel(), _ptr(px, f8), _ptr(py, f8), _ptr(pz, f8), _ptr(w, f8), float(dt), int(precision),
         _ptr(gY.contiguous(), f8),
-        _ptr(out["gpx"]), _ptr(out["gpy"]), _ptr(out["gpz"]), _ptr(out["gw"]), _ptr(out["gZstar"]),
+        _ptr(out["gpx"]), _ptr(out["gpy"]), _ptr(out["gpz"]), _ptr(out.get("gw")), _ptr(out["gZstar"]),
         _ptr(out["gn_e"]), _ptr(out["gT_e"]), _ptr(status, "int32"), _stream(stream)),
         "cmc_expected_yield_backward")
     return out
@@ -498,8 +500,8 @@ def _autograd_function():
         def backward(ctx, gY):
             px, py, pz, w, Zstar, n_e, T_e, off = ctx.saved_tensors
             g = expected_yield_backward(ctx.tables, Zstar, n_e, T_e, off, px, py, pz, w, ctx.dt,
-                                        gY.to(torch.float64), ctx.precision)
-            return (g["gpx"], g["gpy"], g["gpz"], g["gw"], g["gZstar"], g["gn_e"], g["gT_e"],
+                                        gY.to(torch.float64), ctx.precision, weight_grad=ctx.needs_input_grad[3])
+            return (g["gpx"], g["gpy"], g["gpz"], g.get("gw"), g["gZstar"], g["gn_e"], g["gT_e"],
                     None, None, None, None)
 
     return ExpectedYield

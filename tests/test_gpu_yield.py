@@ -81,6 +81,25 @@ def test_backward_matches_oracle(precision, rtol):
     check_adjoint(G, Go, rtol, f"small, precision {precision}")
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_backward_without_the_weight_gradient(precision):
+    """The adjoint asked for no gradient with respect to the weights (gw
+    NULL, as timed in the benchmark) gives the other gradients bit for bit."""
+    import torch
+    import paper_1907_02814_amd as cmc
+    from gpu_parity import gpu_tables
+    y = _inputs()
+    g = _dev(y)
+    gY = _dev({"a": np.linspace(0.5, 2.0, len(y["Zstar"]))})["a"]
+    args = (gpu_tables(29), g["Zstar"], g["n_e"], g["T_e"], g["off"], g["px"], g["py"], g["pz"], g["w"], y["dt"], gY)
+    A = cmc.expected_yield_backward(*args, precision)
+    B = cmc.expected_yield_backward(*args, precision, weight_grad=False)
+    torch.cuda.synchronize()
+    assert "gw" in A and "gw" not in B
+    for k in B:
+        assert torch.equal(A[k], B[k]), k
+
+
 def _fd_inputs():
     """Cells of cfg4's distributions whose screening takes both Debye
     branches (L_D from the temperature, and L_D clamped to r_i), with a few
