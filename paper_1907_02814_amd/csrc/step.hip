@@ -2676,8 +2676,9 @@ __global__ __launch_bounds__(256, kT == 256 ? 6 : 1) void k_pass(StepArgs A, Tab
 constexpr int kQBuckets = 128;
 constexpr int kQThreads = 1024;
 
-__device__ __forceinline__ int queue_bucket(const StepArgs& A, int64_t c) {
-    const int Ne = live(A.el, c), Ng = live(A.ph, c), Ni = live(A.io, c);
+// Cost bucket of a cell with Ne, Ng, Ni live particles: a quarter octave
+// of 64 + the pairs of its two passes
+__device__ __forceinline__ int queue_bucket(const StepArgs& A, int Ne, int Ng, int Ni) {
     const bool ei = (A.proc & (CMC_BREMS | CMC_TRIDENT)) && Ne > 0 && Ni > 0;
     const bool gi = (A.proc & CMC_BH) && Ng > 0 && Ni > 0;
     const uint32_t cost = 64u + (ei ? (uint32_t)max(Ne, Ni) : 0u) + (gi ? (uint32_t)max(Ng, Ni) : 0u);
@@ -2685,13 +2686,59 @@ __device__ __forceinline__ int queue_bucket(const StepArgs& A, int64_t c) {
     return min(kQBuckets - 1, 4 * b + (int)((cost >> (b - 2)) & 3u));
 }
 
+// The live counts of one species in kQCells cells (c[u], all valid), every
+// load issued before the first is used.  Without live counts the words
+// read in their place are the offsets' own (in bounds: the offsets hold
+// 2 (n_cells + 1) words) and are not used, so that no branch separates
+// the loads.
+constexpr int kQCells = 4;
+__device__ __forceinline__ void queue_live(const SpeciesDev& S, const int64_t (&c)[kQCells], int (&n)[kQCells]) {
+    const bool has = S.count != nullptr;
+    const int32_t* cnt = has ? S.count : reinterpret_cast<const int32_t*>(S.off);
+    int64_t lo[kQCells], hi[kQCells];
+#pragma unroll
+    for (int u = 0; u < kQCells; ++u) { lo[u] = S.off[c[u]]; hi[u] = S.off[c[u] + 1]; n[u] = cnt[c[u]]; }
+#pragma unroll
+    for (int u = 0; u < kQCells; ++u) {
+        const int cap = (int)(hi[u] - lo[u]);
+        n[u] = !has ? cap : n[u] < 0 ? 0 : (n[u] > cap ? cap : n[u]);
+    }
+}
+
+// The buckets of the kQCells cells c0, c0 + kQThreads, ... of a thread (-1
+// past the end), their loads issued together (read one cell at a time,
+// each load waited for before the next, the launch was a chain of memory
+// latencies).  Positions past the end read the last cell.
+__device__ __forceinline__ void queue_buckets(const StepArgs& A, int64_t c0, int (&b)[kQCells]) {
+    int64_t c[kQCells];
+#pragma unroll
+    for (int u = 0; u < kQCells; ++u) {
+        const int64_t cu = c0 + (int64_t)u * kQThreads;
+        c[u] = cu < A.n_cells ? cu : A.n_cells - 1;
+    }
+    int ne[kQCells], ng[kQCells], ni[kQCells];
+    queue_live(A.el, c, ne);
+    queue_live(A.ph, c, ng);
+    queue_live(A.io, c, ni);
+#pragma unroll
+    for (int u = 0; u < kQCells; ++u)
+        b[u] = c0 + (int64_t)u * kQThreads < A.n_cells ? queue_bucket(A, ne[u], ng[u], ni[u]) : -1;
+}
+
 __global__ __launch_bounds__(kQThreads) void k_queue(StepArgs A, Work W) {
     __shared__ int hist[kQBuckets];
     __shared__ int base[kQBuckets];
     const int t = threadIdx.x;
+    constexpr int64_t kStride = (int64_t)kQThreads * kQCells;
     for (int b = t; b < kQBuckets; b += kQThreads) hist[b] = 0;
     __syncthreads();
-    for (int64_t c = t; c < A.n_cells; c += kQThreads) atomicAdd(&hist[queue_bucket(A, c)], 1);
+    for (int64_t c0 = t; c0 < A.n_cells; c0 += kStride) {
+        int b[kQCells];
+        queue_buckets(A, c0, b);
+#pragma unroll
+        for (int u = 0; u < kQCells; ++u)
+            if (b[u] >= 0) atomicAdd(&hist[b[u]], 1);
+    }
     __syncthreads();
     if (t < kQBuckets) {
         int s = 0;
@@ -2699,7 +2746,13 @@ __global__ __launch_bounds__(kQThreads) void k_queue(StepArgs A, Work W) {
         base[t] = s;
     }
     __syncthreads();
-    for (int64_t c = t; c < A.n_cells; c += kQThreads) W.queue[atomicAdd(&base[queue_bucket(A, c)], 1)] = (int32_t)c;
+    for (int64_t c0 = t; c0 < A.n_cells; c0 += kStride) {
+        int b[kQCells];
+        queue_buckets(A, c0, b);
+#pragma unroll
+        for (int u = 0; u < kQCells; ++u)
+            if (b[u] >= 0) W.queue[atomicAdd(&base[b[u]], 1)] = (int32_t)(c0 + (int64_t)u * kQThreads);
+    }
 }
 
 // The values an event kernel reads for a listed cell, in one round of
